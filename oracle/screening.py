@@ -1,0 +1,214 @@
+"""The paper's method step by step in FP64 -- TEST INFRASTRUCTURE.
+
+Algorithm 1 (FastL1) with Algorithm 2 (SwitchDictionary), a FISTA update, and
+the stable GAP Safe sphere test (Table I, last row), written from Sections
+III and IV in the paper's order and notation.  It is the per-iteration
+reference the GPU trace is compared with.  Parity status: pinned (Lemma 2,
+Theorem 1, the eps = 0 reduction to GAP Safe, nested preserved sets, zero
+unsafe rejections against ``oracle.lasso.solve``); the switching quantities
+gamma_t and K_t have no printed values in the paper and are pinned only by
+their invariants (0 <= gamma_t <= 1, K_t <= |A_t|).
+
+Readings of points the paper leaves open (each stated where it is used):
+  * FISTA is only cited; the update is Beck & Teboulle's with constant step
+    1/L_i, L_i = ||A~^i||_2^2, and its momentum restarts on a dictionary switch.
+  * Screening uses the prox output x_t and rho~_t = y - A~ x_t (Section III-C).
+    The gradient at the extrapolated point is obtained by linearity from the
+    two correlation vectors A~^T rho~_t and A~^T rho~_{t-1}.
+  * The maxima defining alpha'_t, and the error scale of Theorem 1 with
+    r = 1 (E = max_j eps_j, the largest column error), run over the preserved
+    set A_t, as Algorithm 1 restricts the dictionary to A_t before each update.
+  * An atom is rejected when its test value is below 1 - margin.
+  * K_t uses the conventional sphere test on the approximate atoms with the
+    same sphere (theta'_t, R'_t).
+  * The stop test is the conventional duality gap once A~ = A (Section IV).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .lasso import soft_threshold
+
+
+def sphere_test(at_c, radius, a_norm):
+    """mu(a|B(c,R)) = |a^T c| + R ||a||_2 (closed form of Section II-B, p = 2)."""
+    return np.abs(at_c) + radius * a_norm
+
+
+def stable_sphere_test(at_c, eps, c_norm, radius, a_norm):
+    """mu(S'|B(c,R)) = |a~^T c| + eps ||c||_2 + R a for the norm-restricted zone
+    (Section III-B, Lemma 1, q = p = 2)."""
+    return np.abs(at_c) + eps * c_norm + radius * a_norm
+
+
+def stable_dual_scaling(corr, eps, z_norm):
+    """max(1, max_j (|a~_j^T z| + eps_j ||z||_2)): the divisor of the stable dual
+    scaling Theta'(z|A~, eps) (Section III-C, Lemma 2)."""
+    m = float(np.max(np.abs(corr) + eps * z_norm, initial=0.0))
+    return max(1.0, m)
+
+
+def clip_scale(s0, m):
+    """[s0]_{-1/m}^{1/m} (no clipping when m = 0)."""
+    if m <= 0.0:
+        return s0
+    return min(max(s0, -1.0 / m), 1.0 / m)
+
+
+def dual_value_along(s, lam, y_dot_z, z_sq, y_sq):
+    """D(s z) = 1/2||y||^2 - lam^2/2 ||s z - y/lam||^2 written with the scalars
+    y^T z and ||z||^2 (Section II, dual problem)."""
+    return lam * s * y_dot_z - 0.5 * lam * lam * s * s * z_sq
+
+
+def stable_gap_radius(gap_tilde_A, res_norm, E, x_l1, lam):
+    """R' = sqrt(2 G(x, theta|A~) + 2 delta(x)) / lam with
+    delta(x) = ||y - A~x|| E ||x||_1 + E^2 ||x||_1^2 / 2 (Theorem 1, r = 1)."""
+    delta = res_norm * E * x_l1 + 0.5 * E * E * x_l1 * x_l1
+    return np.sqrt(2.0 * max(gap_tilde_A, 0.0) + 2.0 * delta) / lam, delta
+
+
+def stable_lambda_max(At, eps, y):
+    """lambda'_max = max_j (|a~_j^T y| + eps_j ||y||_2) >= lambda_max (Section III-C,
+    stable static sphere)."""
+    return float(np.max(np.abs(At.T @ y) + eps * np.linalg.norm(y)))
+
+
+def switch_dictionary(i, I, gamma, Gamma, K_t, rc_i, K):
+    """Algorithm 2: speed criterion (K_t <= RC(A~^i) K) jumps to A; otherwise the
+    convergence criterion (gamma_t <= Gamma) moves to the next approximation."""
+    if i >= I:
+        return I
+    if K_t <= rc_i * K:
+        return I
+    if gamma <= Gamma:
+        return i + 1
+    return i
+
+
+@dataclass
+class TraceRow:
+    t: int
+    stage: int
+    n_active: int          # |A_t| before the test
+    n_keep: int            # |A_{t+1}|
+    K_t: int
+    G_stable: float        # G(x_t, theta'_t | A~)
+    G_conv: float          # G(x_t, theta~_t | A~)
+    delta: float
+    R_stable: float
+    gamma: float
+    x_l1: float
+    P: float
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    gap: float             # conventional gap with A at the returned x
+    gap_cert: float        # G' + delta at the returned x
+    screened: np.ndarray   # bool (K,), True = rejected
+    iters: int
+    stage: int
+    converged: bool
+    trace: list = field(default_factory=list)
+
+
+def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12,
+            eps_scale=1.0, keep_trace=True):
+    """Algorithm 1 (FastL1) with FISTA and the stable GAP Safe test.
+
+    stages     list of (At, eps, L): At is the (N, K) FP64 matrix of the i-th
+               approximation (the last one is A, with eps = 0), eps its per-atom
+               l2 error bounds and L its Lipschitz constant.
+    atom_norm  ||a_j||_2 of the exact atoms (the restricted zone of Lemma 1).
+    rc         relative complexity RC(A~^i) of each stage (Section IV-B).
+    eps_scale  multiplies every eps (a value below 1 plants an unsafe bound; the
+               tests use it to show that the safety check can fail).
+    """
+    I = len(stages) - 1
+    N, K = stages[0][0].shape
+    y = np.asarray(y, dtype=np.float64)
+    y_sq = float(y @ y)
+    x = np.zeros(K)
+    x_prev = np.zeros(K)
+    g_prev = np.zeros(K)
+    active = np.ones(K, dtype=bool)
+    i = 0
+    tau = 1.0
+    k_since = 0
+    trace = []
+    At, eps, L = stages[0]
+    at_norms = [np.linalg.norm(s[0], axis=0) for s in stages]
+    res = None
+    for t in range(max_iter + 1):
+        At, eps, L = stages[i]
+        eps = eps * eps_scale
+        act = np.flatnonzero(active)
+        # ---- products on the preserved set (restriction step of Algorithm 1)
+        rho = y - At[:, act] @ x[act]
+        g = np.zeros(K)
+        g[act] = At[:, act].T @ rho
+        # ---- stable dual point theta'_t and conventional theta~_t (Section III-C, IV-A)
+        r_sq = float(rho @ rho)
+        r_norm = np.sqrt(r_sq)
+        y_rho = float(y @ rho)
+        s0 = y_rho / (lam * r_sq) if r_sq > 0 else 0.0
+        m_stable = float(np.max(np.abs(g[act]) + eps[act] * r_norm, initial=0.0))
+        m_conv = float(np.max(np.abs(g[act]), initial=0.0))
+        s_stable = clip_scale(s0, m_stable)
+        s_conv = clip_scale(s0, m_conv)
+        x_l1 = float(np.sum(np.abs(x)))
+        P = 0.5 * r_sq + lam * x_l1
+        G_stable = P - dual_value_along(s_stable, lam, y_rho, r_sq, y_sq)
+        G_conv = P - dual_value_along(s_conv, lam, y_rho, r_sq, y_sq)
+        E = float(np.max(eps[act], initial=0.0))
+        R_stable, delta = stable_gap_radius(G_stable, r_norm, E, x_l1, lam)
+        gamma = G_conv / G_stable if G_stable > 0 else 1.0
+        # ---- stopping criterion: conventional gap once A~ = A (Section IV)
+        if i == I and G_conv < tol:
+            res = Result(x=x.copy(), gap=G_conv, gap_cert=G_stable + delta, screened=~active,
+                         iters=t, stage=i, converged=True, trace=trace)
+            break
+        if t == max_iter:
+            res = Result(x=x.copy(), gap=G_conv, gap_cert=G_stable + delta, screened=~active,
+                         iters=t, stage=i, converged=False, trace=trace)
+            break
+        # ---- update of the preserved coefficients (FISTA step)
+        if k_since == 0:
+            beta = 0.0
+        else:
+            tau_next = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * tau * tau))
+            beta = (tau - 1.0) / tau_next
+            tau = tau_next
+        k_since += 1
+        z = x + beta * (x - x_prev)
+        h = (1.0 + beta) * g - beta * g_prev
+        x_new = np.zeros(K)
+        x_new[act] = soft_threshold(z[act] + h[act] / L, lam / L)
+        # ---- dynamic screening with the stable GAP Safe sphere (Table I)
+        c_norm = abs(s_stable) * r_norm                       # ||theta'_t||_2
+        mu = stable_sphere_test(s_stable * g, eps, c_norm, R_stable, atom_norm)
+        keep = active & (mu >= 1.0 - margin)
+        # ---- look-ahead estimate K_t (Section IV-C)
+        mu_conv = sphere_test(s_stable * g, R_stable, at_norms[i])
+        K_t = int(np.count_nonzero(active & (mu_conv >= 1.0)))
+        x_new[~keep] = 0.0
+        x[~keep] = 0.0
+        if keep_trace:
+            trace.append(TraceRow(t=t, stage=i, n_active=int(act.size), n_keep=int(keep.sum()), K_t=K_t,
+                                  G_stable=G_stable, G_conv=G_conv, delta=delta, R_stable=float(R_stable),
+                                  gamma=gamma, x_l1=x_l1, P=P))
+        # ---- switching criterion (Algorithm 2)
+        i_next = switch_dictionary(i, I, gamma, Gamma, K_t, rc[i], K)
+        if i_next != i:
+            k_since = 0
+            tau = 1.0
+        x_prev = x
+        x = x_new
+        g_prev = g
+        active = keep
+        i = i_next
+    return res

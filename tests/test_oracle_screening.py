@@ -1,0 +1,235 @@
+"""Pins of the FP64 method reference (Algorithms 1-2, stable GAP Safe) against
+the paper's lemmas and theorem, its printed table values, and the exact Lasso
+solution (no GPU)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle.lasso as ol
+import oracle.screening as osc
+import synth
+from synth import workloads as sw
+
+
+def _stages(p):
+    return [(s.values(), s.eps, s.L) for s in p.stages]
+
+
+def _approx(rng, A, level):
+    """An approximation A~ = A - E with known per-atom bounds eps_j >= ||e_j||."""
+    E = level * rng.standard_normal(A.shape) / np.sqrt(A.shape[0])
+    At = A - E
+    eps = np.linalg.norm(E, axis=0) * (1 + 1e-12)
+    return At, eps
+
+
+def test_sphere_test_closed_form_is_the_supremum():
+    # Appendix A: sup_{theta in B(c,R)} |a^T theta| = |a^T c| + R ||a||_2, attained
+    # at c +- R a/||a|| and never exceeded by sampled points.
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        a, c = rng.standard_normal(12), rng.standard_normal(12)
+        R = rng.random() * 2
+        mu = osc.sphere_test(a @ c, R, np.linalg.norm(a))
+        u = rng.standard_normal((2000, 12))
+        u *= (rng.random((2000, 1)) ** (1 / 12)) / np.linalg.norm(u, axis=1, keepdims=True)
+        assert np.max(np.abs((c + R * u) @ a)) <= mu + 1e-12
+        best = c + np.sign(a @ c) * R * a / np.linalg.norm(a)
+        assert abs(abs(a @ best) - mu) < 1e-12
+
+
+def test_stable_zone_test_bounds_every_atom_of_the_zone():
+    # Lemma 1: for every a in B(a~, eps) with ||a|| = alpha and theta in B(c, R),
+    # |a^T theta| <= |a~^T c| + eps ||c|| + R alpha.
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        at, c = rng.standard_normal(10), rng.standard_normal(10)
+        eps, R = rng.random() * 0.5, rng.random()
+        e = rng.standard_normal(10)
+        e *= eps * rng.random() / np.linalg.norm(e)
+        a = at + e
+        alpha = np.linalg.norm(a)
+        bound = osc.stable_sphere_test(at @ c, eps, np.linalg.norm(c), R, alpha)
+        u = rng.standard_normal((1000, 10))
+        u *= (rng.random((1000, 1)) ** 0.1) / np.linalg.norm(u, axis=1, keepdims=True)
+        assert np.max(np.abs((c + R * u) @ a)) <= bound + 1e-12
+
+
+@pytest.mark.parametrize("level", [0.01, 0.3, 1.0])
+def test_lemma2_stable_dual_scaling_is_feasible_for_both_dictionaries(level):
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((30, 80))
+    A /= np.linalg.norm(A, axis=0)
+    At, eps = _approx(rng, A, level)
+    for _ in range(100):
+        z = rng.standard_normal(30)
+        theta = z / osc.stable_dual_scaling(At.T @ z, eps, np.linalg.norm(z))
+        assert np.max(np.abs(A.T @ theta)) <= 1 + 1e-12
+        assert np.max(np.abs(At.T @ theta)) <= 1 + 1e-12
+    # eps = 0 recovers the conventional scaling Theta(z|A)
+    z = rng.standard_normal(30)
+    np.testing.assert_allclose(z / osc.stable_dual_scaling(A.T @ z, 0 * eps, np.linalg.norm(z)),
+                               z / max(1, np.max(np.abs(A.T @ z))), rtol=1e-15)
+
+
+@pytest.mark.parametrize("level", [0.02, 0.2])
+def test_theorem1_stable_gap_sphere_contains_the_dual_solution(level):
+    rng = np.random.default_rng(3)
+    N, K = 25, 60
+    A = rng.standard_normal((N, K))
+    A /= np.linalg.norm(A, axis=0)
+    At, eps = _approx(rng, A, level)
+    y = A @ (rng.standard_normal(K) * (rng.random(K) < 0.1)) + 0.1 * rng.standard_normal(N)
+    for frac in (0.1, 0.5, 0.9):
+        lam = frac * ol.lambda_max(A, y)
+        theta_star = ol.solve(A, y, lam)["theta"]
+        for _ in range(60):
+            x = rng.standard_normal(K) * (rng.random(K) < 0.2)
+            rho = y - At @ x
+            r2 = rho @ rho
+            s0 = (y @ rho) / (lam * r2)
+            s = osc.clip_scale(s0, np.max(np.abs(At.T @ rho) + eps * np.sqrt(r2)))
+            P = 0.5 * r2 + lam * np.abs(x).sum()
+            G = P - osc.dual_value_along(s, lam, y @ rho, r2, y @ y)
+            R, _ = osc.stable_gap_radius(G, np.sqrt(r2), eps.max(), np.abs(x).sum(), lam)
+            assert np.linalg.norm(theta_star - s * rho) <= R * (1 + 1e-12) + 1e-12
+
+
+def test_stable_lambda_max_upper_bounds_lambda_max():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((20, 50))
+    A /= np.linalg.norm(A, axis=0)
+    for level in (0.0, 0.05, 0.5):
+        At, eps = _approx(rng, A, level) if level else (A, np.zeros(50))
+        y = rng.standard_normal(20)
+        lm = osc.stable_lambda_max(At, eps, y)
+        assert lm >= ol.lambda_max(A, y) - 1e-12
+        if level == 0.0:
+            assert lm == pytest.approx(ol.lambda_max(A, y), rel=1e-15)
+
+
+def test_switch_dictionary_truth_table():
+    # Algorithm 2: speed first (to I), then convergence (to i+1), else stay; I absorbs.
+    I, K = 4, 1000
+    assert osc.switch_dictionary(0, I, 0.9, 0.5, 100, 0.15, K) == I       # 100 <= 150
+    assert osc.switch_dictionary(0, I, 0.1, 0.5, 100, 0.15, K) == I       # speed beats convergence
+    assert osc.switch_dictionary(1, I, 0.4, 0.5, 900, 0.30, K) == 2
+    assert osc.switch_dictionary(1, I, 0.5, 0.5, 900, 0.30, K) == 2       # gamma <= Gamma
+    assert osc.switch_dictionary(1, I, 0.6, 0.5, 900, 0.30, K) == 1
+    assert osc.switch_dictionary(I, I, 0.0, 0.5, 0, 1.0, K) == I
+
+
+def test_theoretical_relative_complexity_matches_table_iv():
+    # Table IV, theoretical row: RC = n_kron (1/sqrt(N) + 1/sqrt(K)) at N=2500, K=10000.
+    rows = [l.split() for l in open(__file__.replace("test_oracle_screening.py", "golden/rc_table.txt"))
+            if l.strip() and not l.startswith("#")]
+    for n_kron, rc in rows:
+        assert sw.kron_rc(int(n_kron), 50, 100) == pytest.approx(float(rc), abs=1e-12)
+
+
+def _check_method(p, b=0, Gamma=0.5, tol=1e-10, **kw):
+    y, lam = p.Y[b], float(p.lam[b])
+    sol = ol.solve(p.A, y, lam, L=p.stages[-1].L)
+    res = osc.fast_l1(_stages(p), p.atom_norm, y, lam, [s.rc_theory for s in p.stages],
+                      Gamma=Gamma, tol=tol, **kw)
+    return sol, res
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: synth.config1(),
+    lambda: synth.config1(realization=1, lam_frac=0.2),
+    lambda: synth.config1(realization=2, lam_frac=0.8),
+    lambda: synth.config2(n=(16, 32), lam_frac=0.3),
+    lambda: synth.config3(N=256, K=1024),
+    lambda: synth.config4(batch=1, n=(16, 32)),
+])
+def test_method_is_safe_and_reaches_the_lasso_solution(maker):
+    p = maker()
+    sol, res = _check_method(p)
+    assert res.converged
+    xs = sol["x"]
+    # zero unsafe rejections: no screened atom in the support of x*
+    assert not np.any(res.screened & (xs != 0))
+    # relative objective error and distance to x*
+    P = ol.primal(p.A, p.Y[0], float(p.lam[0]), res.x)
+    assert (P - sol["P"]) / sol["P"] <= 1e-7
+    assert np.linalg.norm(res.x - xs) <= 1e-4 * np.linalg.norm(xs)
+    # nested preserved sets, 0 <= gamma <= 1, K_t <= |A_t|
+    na = [r.n_active for r in res.trace]
+    assert all(a >= b for a, b in zip(na, na[1:]))
+    for r in res.trace:
+        assert -1e-12 <= r.gamma <= 1 + 1e-9
+        assert r.K_t <= r.n_active
+        assert r.n_keep <= r.n_active
+    # stages only move forward and end on A
+    st = [r.stage for r in res.trace]
+    assert all(a <= b for a, b in zip(st, st[1:])) and res.stage == len(p.stages) - 1
+
+
+def test_eps_zero_reduces_to_gap_safe():
+    # With the single exact stage the stable test is GAP Safe (Table I): gamma = 1,
+    # delta = 0 and R' = sqrt(2 G)/lam with the conventional gap.
+    p = synth.config1()
+    sol, res = _check_method(p)
+    ex = [p.stages[-1]]
+    y, lam = p.Y[0], float(p.lam[0])
+    r2 = osc.fast_l1([(s.values(), s.eps, s.L) for s in ex], p.atom_norm, y, lam, [1.0], tol=1e-10)
+    for r in r2.trace:
+        assert r.gamma == 1.0 and r.delta == 0.0
+        assert r.R_stable == pytest.approx(np.sqrt(2 * max(r.G_conv, 0)) / lam, rel=1e-14)
+    assert np.linalg.norm(r2.x - sol["x"]) <= 1e-6 * np.linalg.norm(sol["x"])
+    assert not np.any(r2.screened & (sol["x"] != 0))
+
+
+def test_planted_unsafe_bounds_are_caught():
+    # Shrinking every eps (a mistake planted in the oracle, on the CPU) makes the
+    # stable test unsafe; the safety check must notice on at least one case.
+    caught = 0
+    for real, frac in itertools.product(range(3), (0.2, 0.5)):
+        p = synth.config1(realization=real, lam_frac=frac)
+        sol, res = _check_method(p, eps_scale=0.0, Gamma=0.01)
+        unsafe = np.any(res.screened & (sol["x"] != 0))
+        wrong = np.linalg.norm(res.x - sol["x"]) > 1e-4 * np.linalg.norm(sol["x"])
+        caught += bool(unsafe or wrong)
+    assert caught > 0
+
+
+def test_nkp_svd_recovers_exact_kronecker_sums():
+    # Eckart-Young on the rearranged matrix: an exact R-term Kronecker sum is
+    # recovered, and the truncation error equals the tail singular values.
+    rng = np.random.default_rng(9)
+    n1, k1, n2, k2, R = 4, 6, 5, 3, 3
+    B = rng.standard_normal((R, n1, k1))
+    C = rng.standard_normal((R, n2, k2))
+    A = sum(np.kron(B[r], C[r]) for r in range(R))
+    Bh, Ch, s = sw.nkp_factors(A, n1, k1, n2, k2, R)
+    np.testing.assert_allclose(sum(np.kron(Bh[r], Ch[r]) for r in range(R)), A, atol=1e-12)
+    A2 = A + 0.1 * rng.standard_normal(A.shape)
+    for Rt in (1, 2, 3):
+        Bh, Ch, _ = sw.nkp_factors(A2, n1, k1, n2, k2, Rt)
+        At = sum(np.kron(Bh[r], Ch[r]) for r in range(Rt))
+        sv = np.linalg.svd(sw._rearrange(A2, n1, k1, n2, k2), compute_uv=False)
+        assert np.sum((A2 - At) ** 2) == pytest.approx(np.sum(sv[Rt:] ** 2), rel=1e-10)
+
+
+def test_quantizers_match_library_rounding():
+    torch = pytest.importorskip("torch")
+    v = np.random.default_rng(0).standard_normal(200000).astype(np.float32) * 60
+    v = np.concatenate([v, np.float32([0, -0.0, 448, -448, 2 ** -9, 2 ** -10, 3 * 2 ** -11])])
+    q = synth.fp8_e4m3_decode(synth.fp8_e4m3_round(v))
+    qt = torch.from_numpy(np.clip(v, -448, 448)).to(torch.float8_e4m3fn).double().numpy()
+    assert np.array_equal(q, qt)
+    b = synth.bf16_decode(synth.bf16_round(v))
+    assert np.array_equal(b, torch.from_numpy(v).to(torch.bfloat16).double().numpy())
+
+
+def test_stage_error_bounds_are_exact_column_errors():
+    p = synth.config3(N=256, K=1024)
+    for st in p.stages[:-1]:
+        err = np.linalg.norm(p.A - st.values(), axis=0)
+        assert np.all(st.eps >= err) and np.all(st.eps <= err * (1 + 1e-9) + 1e-12)
+    q = synth.config4(batch=1, n=(16, 32))
+    for st in q.stages[:-1]:
+        err = np.linalg.norm(q.A - st.values(), axis=0)
+        assert np.all(st.eps >= err)
