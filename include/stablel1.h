@@ -1,0 +1,216 @@
+/*
+ * stablel1 -- Lasso solver with stable safe screening over a sequence of fast
+ * approximate dictionaries, for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section I-A, the Lasso): given a dictionary A in R^{N x K}, a signal
+ * y in R^N and lambda > 0, find x* = argmin_x 1/2 ||A x - y||^2 + lambda ||x||_1.
+ *
+ * Method (Algorithm 1, FastL1, with Algorithm 2, SwitchDictionary): FISTA
+ * iterations run on a sequence A~^0, ..., A~^I = A of approximations whose atoms
+ * are known up to l2 error bounds ||a~_j - a_j||_2 <= eps_j (Section III-B).  Each
+ * iteration applies the stable GAP Safe sphere test (Table I, last row; Theorem 1)
+ * so that rejected atoms are provably inactive for the ORIGINAL problem, and
+ * switches to a finer approximation on duality-gap saturation (Section IV-A) or
+ * straight to A when the preserved set is small enough (Sections IV-B, IV-C).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer (memory of the current HIP device)
+ *     unless its description says "host".
+ *   - Dense matrices are column-major: atom j occupies A[j*N .. j*N+N-1].
+ *   - Kronecker atoms: atom j = j1*k2 + j2, row i = i1*n2 + i2 and
+ *     (B kron C)[i, j] = B[i1, j1] * C[i2, j2]; term r of B is column-major
+ *     n1 x k1 at B + r*n1*k1 (element (i1, j1) at j1*n1 + i1), same for C.
+ *   - BF16 arrays hold bfloat16 bit patterns (uint16); FP8 arrays hold OCP FP8
+ *     E4M3FN codes (uint8, largest finite value 448).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Return value: 0 = SL1_OK, > 0 = warning (outputs valid), < 0 = error
+ *     (outputs untouched or undefined).  Argument checks are synchronous on the
+ *     host; errors met on the device are reported through the return value of
+ *     the call that waits for them (sl1_solve, sl1_lambda_max, sl1_grad).
+ *   - Implementation limits (SL1_ELIMIT): N % 4 == 0; N <= 16384; Kronecker
+ *     factor sizes n1, k1, n2, k2 multiples of 16; at most SL1_MAX_STAGES stages.
+ */
+#ifndef STABLEL1_H
+#define STABLEL1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SL1_MAX_STAGES 8
+#define SL1_TRACE_FIELDS 12
+
+enum sl1_status_code {
+    SL1_OK = 0,
+    SL1_MAXITER = 1,      /* warning: a signal stopped at max_iter; its gap may exceed tol */
+    SL1_EINVAL = -1,      /* bad value: lambda <= 0, non-finite input, eps < 0, NULL pointer, ... */
+    SL1_ESHAPE = -2,      /* inconsistent sizes between dictionaries or arguments */
+    SL1_EDTYPE = -3,      /* unsupported storage / working precision combination */
+    SL1_EHIP = -4,        /* a HIP runtime call failed */
+    SL1_ENOMEM = -5,      /* device or host allocation failed */
+    SL1_ESINGULAR = -6,   /* singular Gram matrix on the support (sl1_grad) */
+    SL1_ELIMIT = -7       /* outside a documented implementation limit */
+};
+
+enum sl1_dtype {
+    SL1_F64 = 0,
+    SL1_F32 = 1,
+    SL1_BF16 = 2,
+    SL1_FP8_E4M3 = 3
+};
+
+/* Immutable dictionary handle (one stage of the sequence). */
+typedef struct sl1_dict_s* sl1_dict;
+
+/*
+ * sl1_dict_dense -- a dense stage A~ (or the exact A).
+ *   dtype      storage type: SL1_F64, SL1_F32, SL1_BF16 or SL1_FP8_E4M3.
+ *   N, K       rows (signal length) and atoms.
+ *   A          N x K column-major storage, device.  BORROWED: the caller keeps it
+ *              alive and unchanged until sl1_dict_free.
+ *   col_scale  optional (may be NULL) K floats, device: atom j is
+ *              col_scale[j] * decode(A[:, j]).  Copied.
+ *   eps        K doubles, device: bounds eps_j >= ||a~_j - a_j||_2 against the
+ *              exact dictionary (Section III-B; all zero for the exact A).  Copied.
+ *              The library adds to each eps_j a bound on its own rounding in the
+ *              products with this stage, so the test stays safe (Lemma 1, Lemma 2,
+ *              Theorem 1 hold with the enlarged bounds).
+ * Errors: SL1_EINVAL (NULL A/eps, N or K < 1), SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP, SL1_ENOMEM.
+ */
+int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A,
+                   const float* col_scale, const double* eps, void* stream);
+
+/*
+ * sl1_dict_kron -- a structured stage A~ = sum_{r<R} B_r kron C_r (the SuKro model
+ * of Section V-A), N = n1*n2, K = k1*k2.
+ *   dtype      SL1_F64, SL1_F32 or SL1_BF16 (factor storage).
+ *   B, C       R*n1*k1 and R*n2*k2 elements, device, layout in the header comment.
+ *              Copied (the factors are small).
+ *   eps        K doubles, device, as for sl1_dict_dense.  Copied.
+ * Errors: SL1_EINVAL, SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP, SL1_ENOMEM.
+ */
+int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k2,
+                  const void* B, const void* C, const double* eps, void* stream);
+
+/* Releases a handle; NULL is accepted and ignored. */
+int sl1_dict_free(sl1_dict d);
+
+/*
+ * sl1_dict_info -- host outputs (any may be NULL): sizes, the largest bound
+ * max_j eps_j as given, and the relative-complexity model of the stage
+ * (1 for dense full precision, bytes per element / 4 for BF16 and FP8 storage,
+ * R (1/n1 + 1/k2) for Kronecker sums; Section IV-B and Table IV).
+ */
+int sl1_dict_info(sl1_dict d, int64_t* N, int64_t* K, double* eps_max, double* rc_model);
+
+/* Solver options (sl1_opts_default fills the defaults given in brackets). */
+typedef struct {
+    double Gamma;        /* [0.5] gap-ratio switching threshold (Section IV-A; Section V-C) */
+    double tol;          /* [1e-6] stop once on A with conventional duality gap < tol */
+    double margin;       /* [1e-12] reject atom j iff its test value < 1 - margin */
+    int32_t max_iter;    /* [100000] iteration cap per signal */
+    int32_t work_dtype;  /* [SL1_F32] type of y, x and iterate vectors: SL1_F64 or SL1_F32 */
+    int32_t chunk;       /* [16] iterations enqueued between two convergence polls */
+    int32_t flags;       /* [0] SL1_FLAG_* */
+    double* trace;       /* [NULL] optional device buffer, batch x trace_cap x SL1_TRACE_FIELDS
+                            doubles: per iteration t, stage, |A_t|, |A_t+1|, K_t, G(x,theta'|A~),
+                            G(x,theta~|A~), delta, R', gamma, ||x_t||_1, P(x_t|A~) */
+    int32_t trace_cap;   /* [0] rows per signal in `trace` */
+    int32_t reserved;
+} sl1_opts;
+
+#define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */
+
+int sl1_opts_default(sl1_opts* o);
+
+/*
+ * sl1_solve -- Algorithm 1 on a batch of independent signals sharing the
+ * dictionary sequence seq[0..n_stages-1]; seq[n_stages-1] must be the exact A
+ * (eps = 0; Algorithm 1 input).  Stages must share N and K.
+ *   L          host, n_stages doubles: step-size constants L_i >= ||A~^i||_2^2.
+ *   rc         host, n_stages doubles: relative complexities RC(A~^i) used by the
+ *              speed criterion (Section IV-B); rc[n_stages-1] is ignored.
+ *   atom_norm  K doubles: ||a_j||_2 of the exact atoms (restricted zone, Lemma 1).
+ *   batch      number of signals (>= 1).
+ *   y          batch x N in opt->work_dtype (signal b at y + b*N).
+ *   lambda     batch doubles, each > 0.
+ *   x          out, batch x K in opt->work_dtype: the solution, zero on screened atoms.
+ *   gap        out, batch doubles: conventional duality gap G(x, theta|A) at x.
+ *   gap_cert   out (may be NULL), batch doubles: G(x, theta'|A~) + delta(x) at x, an
+ *              upper bound of the gap of the exact problem (Theorem 1).
+ *   screened   out (may be NULL), batch x K bytes: 1 = atom rejected by the test.
+ *   iters      out (may be NULL), batch int32: iterations performed.
+ *   stage      out (may be NULL), batch int32: index of the final stage.
+ * The call orders itself after prior work on `stream`, polls convergence and
+ * returns once every signal has converged or reached max_iter; the outputs are
+ * then complete.  Concurrent calls with identical shapes on one device are
+ * serialised internally.
+ * Returns SL1_OK, SL1_MAXITER, SL1_EINVAL (bad lambda / non-finite y detected on
+ * the device), SL1_ESHAPE, SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP or SL1_ENOMEM.
+ */
+int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc,
+              const double* atom_norm, int64_t batch, const void* y, const double* lambda,
+              const sl1_opts* opt, void* x, double* gap, double* gap_cert, uint8_t* screened,
+              int32_t* iters, int32_t* stage, void* stream);
+
+/*
+ * sl1_lambda_max -- out[b] = max_j (|a~_j^T y_b| + eps_j ||y_b||_2), the stable
+ * lambda'_max of Section III-C (equal to lambda_max = ||A^T y_b||_inf when eps = 0).
+ *   y    batch x N in work_dtype;  out  batch doubles.  Synchronous.
+ */
+int sl1_lambda_max(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out,
+                   void* stream);
+
+/*
+ * sl1_dict_adjoint -- out[b*K + j] = a~_j^T z_b for every atom j, computed by the
+ * solver's own correlation kernel for this stage (the adjoint product of
+ * Algorithm 1's update, A~^T rho~).  z_b is y_b as the solver stores it: y_b
+ * itself, or its BF16 rounding for BF16 Kronecker stages (written to z_used,
+ * batch x N in work_dtype, when z_used is not NULL).
+ *   y    batch x N in work_dtype;  out  batch x K doubles.  Synchronous.
+ */
+int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out,
+                     void* z_used, void* stream);
+
+/*
+ * sl1_grad -- implicit adjoint of the Lasso solution map on the support
+ * S_b = {j : x_b[j] != 0}: from the optimality conditions (Section II),
+ * A_S^T A_S x_S = A_S^T y - lambda sign(x_S), so for a loss L(x*):
+ *   dL/dy      = A_S (A_S^T A_S)^{-1} (dL/dx)_S
+ *   dL/dlambda = -sign(x_S)^T (A_S^T A_S)^{-1} (dL/dx)_S
+ *   A          the exact dictionary (dense stage).
+ *   x, dx      batch x K in work_dtype (solution and incoming gradient).
+ *   dy         out, batch x N in work_dtype;  dlambda  out, batch doubles.
+ * Returns SL1_ESINGULAR if a support Gram matrix is not positive definite,
+ * SL1_ELIMIT if a support exceeds 1024 atoms or N.  Synchronous.
+ */
+int sl1_grad(sl1_dict A, int64_t batch, const void* x, const void* y, const double* lambda,
+             const void* dx, void* dy, double* dlambda, int work_dtype, void* stream);
+
+/*
+ * sl1_measure_rc -- measured relative complexity of each stage: the device
+ * time of one iteration's products with seq[i] divided by that of the last
+ * stage with every atom preserved (Section IV-B, Section V-A measures RC
+ * instead of using the model).  rc_out: host, n_stages doubles.  Synchronous.
+ */
+int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dtype,
+                   double* rc_out, void* stream);
+
+/*
+ * sl1_last_solve_clock -- device wall-clock stamps of the most recent
+ * sl1_solve with these shapes on the current device: out[2b] = start of signal
+ * b, out[2b+1] = iteration at which its gap first fell below tol (0 if never).
+ * out: host, 2*batch int64; rate_khz: host, clock rate.  For time-to-gap.
+ */
+int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, int work_dtype, long long* out,
+                         double* rate_khz);
+
+const char* sl1_status_str(int status);
+const char* sl1_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STABLEL1_H */

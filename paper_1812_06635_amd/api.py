@@ -1,0 +1,246 @@
+"""Python binding of the stablel1 C ABI.
+
+Argument marshalling only: tensors are passed by device pointer with the
+current torch stream; every step of the solver runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DTYPES = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16, "fp8": L.FP8_E4M3}
+_STORAGE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8}
+_WORK = {"f64": torch.float64, "f32": torch.float32}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(t, dtype=None, what="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+class Dict:
+    """One dictionary stage (handle owned by the library).  A dense stage
+    borrows its matrix: the tensor is kept referenced by this object."""
+
+    def __init__(self, handle, keep, N, K, kind, dtype):
+        self._h = handle
+        self._keep = keep
+        self.N, self.K, self.kind, self.dtype = N, K, kind, dtype
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("dictionary handle already freed")
+        return self._h
+
+    @classmethod
+    def dense(cls, A, eps, dtype, scale=None):
+        """A: (K, N) device tensor, atom-major (= column-major N x K), storage
+        dtype float64 / float32 / int16 (bf16 bits) / uint8 (fp8 E4M3 codes)."""
+        _dev(A, _STORAGE[dtype], "A")
+        _dev(eps, torch.float64, "eps")
+        if scale is not None:
+            _dev(scale, torch.float32, "scale")
+        K, N = A.shape
+        h = L.c_dict()
+        L.check(L.load().sl1_dict_dense(ctypes.byref(h), DTYPES[dtype], N, K, _ptr(A), _ptr(scale), _ptr(eps),
+                                        _stream()), "sl1_dict_dense")
+        return cls(h, (A, scale), N, K, "dense", dtype)
+
+    @classmethod
+    def kron(cls, B, C, eps, dtype):
+        """B: (R, k1, n1), C: (R, k2, n2) device tensors (each term column-major)."""
+        _dev(B, _STORAGE[dtype], "B")
+        _dev(C, _STORAGE[dtype], "C")
+        _dev(eps, torch.float64, "eps")
+        R, k1, n1 = B.shape
+        R2, k2, n2 = C.shape
+        if R2 != R:
+            raise ValueError("B and C must have the same number of terms")
+        h = L.c_dict()
+        L.check(L.load().sl1_dict_kron(ctypes.byref(h), DTYPES[dtype], R, n1, k1, n2, k2, _ptr(B), _ptr(C),
+                                       _ptr(eps), _stream()), "sl1_dict_kron")
+        return cls(h, None, n1 * n2, k1 * k2, "kron", dtype)
+
+    def info(self):
+        N, K = L.c_i64(), L.c_i64()
+        em, rc = L.c_d(), L.c_d()
+        L.check(L.load().sl1_dict_info(self.handle, ctypes.byref(N), ctypes.byref(K), ctypes.byref(em),
+                                       ctypes.byref(rc)), "sl1_dict_info")
+        return dict(N=N.value, K=K.value, eps_max=em.value, rc_model=rc.value)
+
+    def free(self):
+        if self._h is not None:
+            L.load().sl1_dict_free(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def upload_stage(stage, device="cuda"):
+    """Device copy of a host stage description with attributes kind, dtype,
+    data/scale (dense) or B/C (kron), eps (numpy arrays)."""
+    eps = torch.from_numpy(np.ascontiguousarray(stage.eps, dtype=np.float64)).to(device)
+    if stage.kind == "dense":
+        arr = stage.data.view(np.int16) if stage.dtype == "bf16" else stage.data
+        A = torch.from_numpy(np.ascontiguousarray(arr)).to(device)
+        sc = None if stage.scale is None else torch.from_numpy(np.ascontiguousarray(stage.scale)).to(device)
+        return Dict.dense(A, eps, stage.dtype, sc)
+    conv = (lambda a: a.view(np.int16)) if stage.dtype == "bf16" else (lambda a: a)
+    B = torch.from_numpy(np.ascontiguousarray(conv(stage.B))).to(device)
+    C = torch.from_numpy(np.ascontiguousarray(conv(stage.C))).to(device)
+    return Dict.kron(B, C, eps, stage.dtype)
+
+
+def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
+          trace_cap=0, use_graph=True, check=True):
+    """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
+    Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage,
+    the status code, and the trace (batch, trace_cap, 12) when requested."""
+    work = "f64" if y.dtype == torch.float64 else "f32"
+    _dev(y, _WORK[work], "y")
+    _dev(lam, torch.float64, "lam")
+    _dev(atom_norm, torch.float64, "atom_norm")
+    if y.dim() == 1:
+        y = y.unsqueeze(0)
+    batch, N = y.shape
+    K = stages[0].K
+    dev = y.device
+    n = len(stages)
+    arr = (L.c_dict * n)(*[s.handle for s in stages])
+    Ls = (L.c_d * n)(*[float(v) for v in L_])
+    rcs = (L.c_d * n)(*[float(v) for v in rc])
+    opts = L.Opts()
+    L.load().sl1_opts_default(ctypes.byref(opts))
+    opts.Gamma, opts.tol, opts.margin = Gamma, tol, margin
+    opts.max_iter, opts.chunk = max_iter, chunk
+    opts.work_dtype = L.F64 if work == "f64" else L.F32
+    opts.flags = 0 if use_graph else L.FLAG_NO_GRAPH
+    trace = None
+    if trace_cap > 0:
+        trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)
+        opts.trace = trace.data_ptr()
+        opts.trace_cap = trace_cap
+    x = torch.empty((batch, K), dtype=y.dtype, device=dev)
+    gap = torch.empty(batch, dtype=torch.float64, device=dev)
+    gap_cert = torch.empty(batch, dtype=torch.float64, device=dev)
+    screened = torch.empty((batch, K), dtype=torch.uint8, device=dev)
+    iters = torch.empty(batch, dtype=torch.int32, device=dev)
+    stage = torch.empty(batch, dtype=torch.int32, device=dev)
+    code = L.load().sl1_solve(arr, n, Ls, rcs, _ptr(atom_norm), batch, _ptr(y), _ptr(lam), ctypes.byref(opts),
+                              _ptr(x), _ptr(gap), _ptr(gap_cert), _ptr(screened), _ptr(iters), _ptr(stage),
+                              _stream())
+    if check:
+        L.check(code, "sl1_solve")
+    out = dict(x=x, gap=gap, gap_cert=gap_cert, screened=screened, iters=iters, stage=stage, status=code)
+    if trace is not None:
+        out["trace"] = trace
+    return out
+
+
+def lambda_max(d, y):
+    """Stable lambda'_max of stage d for each signal (Section III-C)."""
+    if y.dim() == 1:
+        y = y.unsqueeze(0)
+    work = L.F64 if y.dtype == torch.float64 else L.F32
+    _dev(y, None, "y")
+    out = torch.empty(y.shape[0], dtype=torch.float64, device=y.device)
+    L.check(L.load().sl1_lambda_max(d.handle, y.shape[0], _ptr(y), work, _ptr(out), _stream()), "sl1_lambda_max")
+    return out
+
+
+def adjoint(d, y):
+    """(A~^T z, z) for each signal, with z = y as the solver stores it."""
+    if y.dim() == 1:
+        y = y.unsqueeze(0)
+    work = L.F64 if y.dtype == torch.float64 else L.F32
+    _dev(y, None, "y")
+    out = torch.empty((y.shape[0], d.K), dtype=torch.float64, device=y.device)
+    z = torch.empty_like(y)
+    L.check(L.load().sl1_dict_adjoint(d.handle, y.shape[0], _ptr(y), work, _ptr(out), _ptr(z), _stream()),
+            "sl1_dict_adjoint")
+    return out, z
+
+
+def measure_rc(stages, batch=1, work="f32"):
+    n = len(stages)
+    arr = (L.c_dict * n)(*[s.handle for s in stages])
+    out = (L.c_d * n)()
+    L.check(L.load().sl1_measure_rc(arr, n, batch, L.F64 if work == "f64" else L.F32, out, _stream()),
+            "sl1_measure_rc")
+    return [out[i] for i in range(n)]
+
+
+def last_solve_clock(batch, N, K, work="f32"):
+    """(start, converged) device clock stamps in seconds of the last solve of this shape."""
+    buf = (ctypes.c_longlong * (2 * batch))()
+    rate = L.c_d()
+    L.check(L.load().sl1_last_solve_clock(batch, N, K, L.F64 if work == "f64" else L.F32, buf,
+                                          ctypes.byref(rate)), "sl1_last_solve_clock")
+    a = np.frombuffer(buf, dtype=np.int64).reshape(batch, 2).astype(np.float64)
+    return a / (rate.value * 1e3)
+
+
+def grad(A, x, y, lam, dx):
+    """Implicit adjoint on the support of x: returns (dL/dy, dL/dlambda)."""
+    if x.dim() == 1:
+        x, y, dx = x.unsqueeze(0), y.unsqueeze(0), dx.unsqueeze(0)
+    work = L.F64 if x.dtype == torch.float64 else L.F32
+    _dev(x, None, "x")
+    _dev(dx, x.dtype, "dx")
+    _dev(y, x.dtype, "y")
+    _dev(lam, torch.float64, "lam")
+    dy = torch.empty_like(y)
+    dlam = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    L.check(L.load().sl1_grad(A.handle, x.shape[0], _ptr(x), _ptr(y), _ptr(lam), _ptr(dx), _ptr(dy), _ptr(dlam),
+                              work, _stream()), "sl1_grad", allow_warn=False)
+    return dy, dlam
+
+
+class LassoFunction(torch.autograd.Function):
+    """x* = Lasso(y, lambda) through Algorithm 1; backward by the implicit
+    adjoint on the final support (the exact dictionary is stages[-1])."""
+
+    @staticmethod
+    def forward(ctx, y, lam, stages, L_, rc, atom_norm, opts):
+        out = solve(stages, L_, rc, atom_norm, y.detach().contiguous(), lam.detach().contiguous(), **(opts or {}))
+        x = out["x"]
+        ctx.stages = stages
+        ctx.save_for_backward(x, y.detach(), lam.detach())
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        x, y, lam = ctx.saved_tensors
+        dy, dlam = grad(ctx.stages[-1], x, y if y.dim() == 2 else y.unsqueeze(0), lam,
+                        gx.contiguous().to(x.dtype))
+        if y.dim() == 1:
+            dy = dy[0]
+        return dy, dlam.reshape(lam.shape), None, None, None, None, None
+
+
+def lasso(y, lam, stages, L_, rc, atom_norm, **opts):
+    """Differentiable solution map (see LassoFunction)."""
+    return LassoFunction.apply(y, lam, stages, L_, rc, atom_norm, opts)

@@ -1,0 +1,813 @@
+// C ABI of the stablel1 library: dictionary handles, workspaces, the solve
+// driver (iteration chunks replayed from a captured hipGraph, convergence polled
+// between chunks), lambda'_max and relative-complexity measurement.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "sl1_internal.hpp"
+
+namespace sl1 {
+hipError_t launch_init(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
+hipError_t launch_iter(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
+hipError_t launch_fwd_adj(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
+hipError_t launch_adj_only(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
+hipError_t launch_finalize(const SolveParams*, const LaunchCfg&, bool, void*, double*, double*, uint8_t*, int32_t*,
+                           int32_t*, int32_t*, hipStream_t);
+hipError_t launch_lambda_out(const SolveParams*, int, double*, int32_t*, hipStream_t);
+hipError_t launch_time_out(const SolveParams*, int, long long*, hipStream_t);
+hipError_t launch_adjoint_out(const SolveParams*, int, int, int, bool, double*, void*, hipStream_t);
+hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
+                              int*, hipStream_t);
+hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
+}  // namespace sl1
+
+using namespace sl1;
+
+struct sl1_dict_s {
+    int kind = 0, dtype = 0, device = 0;
+    int64_t N = 0, K = 0;
+    int R = 0, n1 = 0, k1 = 0, n2 = 0, k2 = 0, vec = 4;
+    const void* A = nullptr;   // borrowed (dense)
+    float* scale = nullptr;    // owned
+    void* B = nullptr;         // owned (kron)
+    void* C = nullptr;         // owned (kron)
+    double* eps_eff = nullptr; // owned
+    double* at_norm = nullptr; // owned
+    double eps_max_in = 0.0, eps_max_eff = 0.0, at_norm_max = 0.0, rc_model = 1.0;
+};
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) return SL1_EHIP;       \
+    } while (0)
+
+namespace {
+
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24
+
+size_t dtype_size(int dt) {
+    switch (dt) {
+        case SL1_F64: return 8;
+        case SL1_F32: return 4;
+        case SL1_BF16: return 2;
+        case SL1_FP8_E4M3: return 1;
+    }
+    return 0;
+}
+
+double bf16_host(uint16_t b) {
+    uint32_t u = ((uint32_t)b) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+// Bound on |computed - exact| of both products with a stage, per unit
+// ||abs-atom||_2 ||vector||_2 (standard gamma_n = n u accumulation bounds, doubled
+// to cover any order or internal precision of the matrix-core accumulation).
+double rounding_allowance(const sl1_dict_s& d) {
+    const double N = (double)d.N, K = (double)d.K;
+    if (d.kind == kDense) return 2.0 * (N + K + 32.0) * kU64;
+    const double n1 = d.n1, n2 = d.n2, R = d.R;
+    if (d.dtype == SL1_F64) return 2.0 * (n2 + R * n1 + R + K + 32.0) * kU64;
+    if (d.dtype == SL1_F32) return 2.0 * (n2 + R * n1 + R + 10.0) * kU32 + 2.0 * (K + 24.0) * kU64;
+    // BF16: exact first product inputs, FP32 accumulation, hi/lo split of the
+    // intermediate (residual <= 2^-18, counted as 2^-16)
+    return 2.0 * (n2 + 2.0 * R * n1 + R + 10.0) * kU32 + 1.52587890625e-05 + 2.0 * (K + 24.0) * kU64;
+}
+
+struct Workspace {
+    int device = 0, batch = 0, N = 0, K = 0;
+    bool f64 = false;
+    int nseg_max = 0, nrc = 0, nadj_max = 0;
+    void* mem = nullptr;
+    SolveParams* dP = nullptr;
+    SolveParams* hP = nullptr;   // pinned
+    int* d_active = nullptr;
+    int* h_active = nullptr;     // pinned
+    int32_t* d_status = nullptr;
+    long long* d_times = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+    LaunchCfg graph_cfg{};
+    std::mutex mu;
+    ~Workspace() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (mem) (void)hipFree(mem);
+        if (hP) (void)hipHostFree(hP);
+        if (h_active) (void)hipHostFree(h_active);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+std::mutex g_ws_mu;
+std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Workspace>> g_ws;
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_workspace(Workspace& w) {
+    const size_t ws = w.f64 ? 8 : 4;
+    const size_t B = w.batch, K = w.K, N = w.N;
+    w.nseg_max = (w.K + kSeg - 1) / kSeg;
+    w.nrc = (w.N + kFwdRows - 1) / kFwdRows;
+    w.nadj_max = std::max(1, (w.K + kAdjAtoms - 1) / kAdjAtoms);
+    const size_t np = w.nseg_max + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return o; };
+    const size_t o_state = take(B * sizeof(SigState));
+    const size_t o_x = take(B * 2 * K * ws);
+    const size_t o_g = take(B * 2 * K * 8);
+    const size_t o_mask = take(B * K);
+    const size_t o_act = take(B * 2 * K * 4);
+    const size_t o_nz = take(B * 2 * K * 4);
+    const size_t o_ap = take(B * 2 * np * 4);
+    const size_t o_zp = take(B * 2 * np * 4);
+    const size_t o_z = take(B * N * ws);
+    const size_t o_fp = take(B * kFwdSplits * N * 8);
+    const size_t o_rp = take(B * w.nrc * 3 * 8);
+    const size_t o_adp = take(B * w.nadj_max * 3 * 8);
+    const size_t o_up = take(B * w.nseg_max * 4 * 8);
+    const size_t o_ctr = take(B * (w.nrc + 3) * 4);
+    const size_t o_act_sig = take(64);
+    const size_t o_status = take(B * 4);
+    const size_t o_times = take(B * 16);
+    const size_t o_params = take(sizeof(SolveParams));
+    if (hipMalloc(&w.mem, off) != hipSuccess) return SL1_ENOMEM;
+    char* m = (char*)w.mem;
+    if (hipHostMalloc((void**)&w.hP, sizeof(SolveParams), hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
+    if (hipHostMalloc((void**)&w.h_active, 64, hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
+    std::memset(w.hP, 0, sizeof(SolveParams));
+    SolveParams& p = *w.hP;
+    p.state = (SigState*)(m + o_state);
+    p.x = m + o_x;
+    p.g = (double*)(m + o_g);
+    p.mask = (uint8_t*)(m + o_mask);
+    p.act = (int*)(m + o_act);
+    p.nz = (int*)(m + o_nz);
+    p.act_pre = (int*)(m + o_ap);
+    p.nz_pre = (int*)(m + o_zp);
+    p.z = m + o_z;
+    p.fwd_part = (double*)(m + o_fp);
+    p.res_part = (double*)(m + o_rp);
+    p.adj_part = (double*)(m + o_adp);
+    p.upd_part = (double*)(m + o_up);
+    p.counters = (unsigned*)(m + o_ctr);
+    p.active_signals = (int*)(m + o_act_sig);
+    p.nseg_max = w.nseg_max;
+    p.nrc = w.nrc;
+    p.nadj_max = w.nadj_max;
+    w.d_active = p.active_signals;
+    w.d_status = (int32_t*)(m + o_status);
+    w.d_times = (long long*)(m + o_times);
+    w.dP = (SolveParams*)(m + o_params);
+    if (hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreateWithFlags(&w.ev_in, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreateWithFlags(&w.ev_out, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreate(&w.ev_a) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreate(&w.ev_b) != hipSuccess) return SL1_EHIP;
+    if (hipMemsetAsync(w.mem, 0, off, w.stream) != hipSuccess) return SL1_EHIP;
+    if (hipStreamSynchronize(w.stream) != hipSuccess) return SL1_EHIP;
+    return SL1_OK;
+}
+
+int get_workspace(int device, int batch, int N, int K, bool f64, Workspace** out) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto key = std::make_tuple(device, batch, N, K, (int)f64);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = it->second.get();
+        return SL1_OK;
+    }
+    // keep the cache small: drop idle workspaces of other shapes on this device
+    for (auto i = g_ws.begin(); i != g_ws.end();) {
+        if (std::get<0>(i->first) == device && g_ws.size() >= 4) i = g_ws.erase(i);
+        else ++i;
+    }
+    auto w = std::make_unique<Workspace>();
+    w->device = device;
+    w->batch = batch;
+    w->N = N;
+    w->K = K;
+    w->f64 = f64;
+    int st = make_workspace(*w);
+    if (st != SL1_OK) return st;
+    *out = w.get();
+    g_ws[key] = std::move(w);
+    return SL1_OK;
+}
+
+void fill_stage(StageDesc& s, const sl1_dict_s& d, double L, double rc) {
+    std::memset(&s, 0, sizeof(s));
+    s.kind = d.kind;
+    s.dtype = d.dtype;
+    s.R = d.R;
+    s.n1 = d.n1;
+    s.k1 = d.k1;
+    s.n2 = d.n2;
+    s.k2 = d.k2;
+    s.vec = d.vec;
+    s.A = d.A;
+    s.scale = d.scale;
+    s.B = d.B;
+    s.C = d.C;
+    s.eps = d.eps_eff;
+    s.at_norm = d.at_norm;
+    s.L = L;
+    s.invL = 1.0 / L;
+    s.rc = rc;
+    s.at_norm_max = d.at_norm_max;
+    s.eps_max = d.eps_max_eff;
+}
+
+LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
+    LaunchCfg c{};
+    c.batch = w.batch;
+    c.nseg_max = w.nseg_max;
+    c.nrc = w.nrc;
+    c.nadj_max = w.nadj_max;
+    const size_t ws = w.f64 ? 8 : 4;
+    const size_t pre = ((size_t)(w.nseg_max + 1) * 4 + 15) & ~(size_t)15;
+    c.lds_fwd = pre + kBlock * 4 + 16 + kBlock * 8;
+    c.lds_upd = pre;
+    size_t extra = 0;
+    for (int i = 0; i < p.n_stages; ++i) {
+        const StageDesc& s = p.st[i];
+        if (s.kind != kKron) continue;
+        size_t need;
+        if (s.dtype == SL1_F64) need = 4 * 16 * (size_t)p.n1_max * 8 + 4 * 16 * 64 * 8;
+        else need = 4 * 16 * 64 * 4 + 4 * 16 * (size_t)p.n1_max * 4;
+        extra = std::max(extra, need);
+    }
+    c.lds_adj = (((size_t)w.N * ws + 15) & ~(size_t)15) + pre + extra;
+    return c;
+}
+
+bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
+    return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
+           a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj && a.lds_upd == b.lds_upd;
+}
+
+int check_lds(const LaunchCfg& c) {
+    const size_t lim = 160 * 1024;
+    if (c.lds_adj > lim || c.lds_fwd > lim) return SL1_ELIMIT;
+    return SL1_OK;
+}
+
+int current_device(int* dev) {
+    return hipGetDevice(dev) == hipSuccess ? SL1_OK : SL1_EHIP;
+}
+
+// Common validation of a stage sequence; fills the host params.
+int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc, int work_dtype, SolveParams& p) {
+    if (!seq || n_stages < 1) return SL1_EINVAL;
+    if (n_stages > SL1_MAX_STAGES) return SL1_ELIMIT;
+    if (work_dtype != SL1_F64 && work_dtype != SL1_F32) return SL1_EDTYPE;
+    const sl1_dict_s* d0 = seq[0];
+    if (!d0) return SL1_EINVAL;
+    int n1_max = 0;
+    for (int i = 0; i < n_stages; ++i) {
+        const sl1_dict_s* d = seq[i];
+        if (!d) return SL1_EINVAL;
+        if (d->N != d0->N || d->K != d0->K || d->device != d0->device) return SL1_ESHAPE;
+        if (work_dtype == SL1_F64 && d->dtype != SL1_F64) return SL1_EDTYPE;
+        if (work_dtype == SL1_F32 && d->dtype == SL1_F64) return SL1_EDTYPE;
+        const double Li = L ? L[i] : 0.0;
+        if (!(Li > 0.0) || !std::isfinite(Li)) return SL1_EINVAL;
+        const double rci = rc ? rc[i] : d->rc_model;
+        if (!std::isfinite(rci)) return SL1_EINVAL;
+        fill_stage(p.st[i], *d, Li, rci);
+        if (d->kind == kKron) n1_max = std::max(n1_max, d->n1);
+    }
+    p.n_stages = n_stages;
+    p.N = (int)d0->N;
+    p.K = (int)d0->K;
+    p.work_f64 = work_dtype == SL1_F64;
+    p.n1_max = n1_max;
+    return SL1_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sl1_version(void) { return "stablel1 0.1.0 (gfx950)"; }
+
+const char* sl1_status_str(int s) {
+    switch (s) {
+        case SL1_OK: return "ok";
+        case SL1_MAXITER: return "iteration cap reached before the duality-gap tolerance";
+        case SL1_EINVAL: return "invalid argument value";
+        case SL1_ESHAPE: return "inconsistent sizes";
+        case SL1_EDTYPE: return "unsupported data type combination";
+        case SL1_EHIP: return "HIP runtime error";
+        case SL1_ENOMEM: return "allocation failed";
+        case SL1_ESINGULAR: return "singular support Gram matrix";
+        case SL1_ELIMIT: return "outside an implementation limit";
+    }
+    return "unknown status";
+}
+
+int sl1_opts_default(sl1_opts* o) {
+    if (!o) return SL1_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->Gamma = 0.5;
+    o->tol = 1e-6;
+    o->margin = 1e-12;
+    o->max_iter = 100000;
+    o->work_dtype = SL1_F32;
+    o->chunk = 16;
+    o->flags = 0;
+    o->trace = nullptr;
+    o->trace_cap = 0;
+    return SL1_OK;
+}
+
+int sl1_dict_free(sl1_dict d) {
+    if (!d) return SL1_OK;
+    if (d->scale) (void)hipFree(d->scale);
+    if (d->B) (void)hipFree(d->B);
+    if (d->C) (void)hipFree(d->C);
+    if (d->eps_eff) (void)hipFree(d->eps_eff);
+    if (d->at_norm) (void)hipFree(d->at_norm);
+    delete d;
+    return SL1_OK;
+}
+
+int sl1_dict_info(sl1_dict d, int64_t* N, int64_t* K, double* eps_max, double* rc_model) {
+    if (!d) return SL1_EINVAL;
+    if (N) *N = d->N;
+    if (K) *K = d->K;
+    if (eps_max) *eps_max = d->eps_max_in;
+    if (rc_model) *rc_model = d->rc_model;
+    return SL1_OK;
+}
+
+static int finish_dict_host_eps(sl1_dict_s* d, const double* eps, hipStream_t s) {
+    std::vector<double> h(d->K);
+    HIP_TRY(hipMemcpyAsync(h.data(), eps, d->K * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double m = 0.0;
+    for (double e : h) {
+        if (!(e >= 0.0) || !std::isfinite(e)) return SL1_EINVAL;
+        m = std::max(m, e);
+    }
+    d->eps_max_in = m;
+    return SL1_OK;
+}
+
+int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A, const float* col_scale,
+                   const double* eps, void* stream) {
+    if (!out || !A || !eps || N < 1 || K < 1) return SL1_EINVAL;
+    *out = nullptr;
+    if (dtype_size(dtype) == 0) return SL1_EDTYPE;
+    if (N % 4 != 0 || N > kMaxN || K > (int64_t)1 << 30) return SL1_ELIMIT;
+    hipStream_t s = (hipStream_t)stream;
+    auto d = std::make_unique<sl1_dict_s>();
+    HIP_TRY(hipGetDevice(&d->device));
+    d->kind = kDense;
+    d->dtype = dtype;
+    d->N = N;
+    d->K = K;
+    d->A = A;
+    if (dtype == SL1_F64 || dtype == SL1_F32) d->vec = 4;
+    else if (dtype == SL1_BF16) d->vec = (N % 8 == 0) ? 8 : 4;
+    else d->vec = (N % 16 == 0) ? 16 : 4;
+    int st = finish_dict_host_eps(d.get(), eps, s);
+    if (st != SL1_OK) return st;
+    if (col_scale) {
+        if (hipMalloc(&d->scale, K * sizeof(float)) != hipSuccess) return SL1_ENOMEM;
+        HIP_TRY(hipMemcpyAsync(d->scale, col_scale, K * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    if (hipMalloc(&d->eps_eff, K * 8) != hipSuccess || hipMalloc(&d->at_norm, K * 8) != hipSuccess) {
+        sl1_dict_free(d.release());
+        return SL1_ENOMEM;
+    }
+    int* bad = nullptr;
+    if (hipMalloc(&bad, 4) != hipSuccess) return SL1_ENOMEM;
+    HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
+    const double kappa = rounding_allowance(*d);
+    HIP_TRY(launch_dense_norms(dtype, A, d->scale, (int)N, (int)K, eps, kappa, d->at_norm, d->eps_eff, bad, s));
+    int hbad = 0;
+    std::vector<double> an(K), ee(K);
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(an.data(), d->at_norm, K * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ee.data(), d->eps_eff, K * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(bad);
+    if (hbad) {
+        sl1_dict_free(d.release());
+        return SL1_EINVAL;
+    }
+    d->at_norm_max = *std::max_element(an.begin(), an.end());
+    d->eps_max_eff = *std::max_element(ee.begin(), ee.end());
+    d->rc_model = dtype == SL1_BF16 ? 0.5 : (dtype == SL1_FP8_E4M3 ? 0.25 : 1.0);
+    *out = d.release();
+    return SL1_OK;
+}
+
+int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k2, const void* B, const void* C,
+                  const double* eps, void* stream) {
+    if (!out || !B || !C || !eps || R < 1 || n1 < 1 || k1 < 1 || n2 < 1 || k2 < 1) return SL1_EINVAL;
+    *out = nullptr;
+    if (dtype != SL1_F64 && dtype != SL1_F32 && dtype != SL1_BF16) return SL1_EDTYPE;
+    if (n1 % 16 || k1 % 16 || n2 % 16 || k2 % 16) return SL1_ELIMIT;
+    const int64_t N = (int64_t)n1 * n2, K = (int64_t)k1 * k2;
+    if (N > kMaxN || n1 > (dtype == SL1_F64 ? 128 : 256) || K > (int64_t)1 << 30) return SL1_ELIMIT;
+    hipStream_t s = (hipStream_t)stream;
+    auto d = std::make_unique<sl1_dict_s>();
+    HIP_TRY(hipGetDevice(&d->device));
+    d->kind = kKron;
+    d->dtype = dtype;
+    d->N = N;
+    d->K = K;
+    d->R = R;
+    d->n1 = n1;
+    d->k1 = k1;
+    d->n2 = n2;
+    d->k2 = k2;
+    int st = finish_dict_host_eps(d.get(), eps, s);
+    if (st != SL1_OK) return st;
+    const size_t es = dtype_size(dtype);
+    const size_t nb = (size_t)R * n1 * k1, nc = (size_t)R * n2 * k2;
+    if (hipMalloc(&d->B, nb * es) != hipSuccess || hipMalloc(&d->C, nc * es) != hipSuccess ||
+        hipMalloc(&d->eps_eff, K * 8) != hipSuccess || hipMalloc(&d->at_norm, K * 8) != hipSuccess) {
+        sl1_dict_free(d.release());
+        return SL1_ENOMEM;
+    }
+    HIP_TRY(hipMemcpyAsync(d->B, B, nb * es, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d->C, C, nc * es, hipMemcpyDeviceToDevice, s));
+    // host copies of the factors: atom norms from per-column Gram matrices
+    std::vector<unsigned char> hb(nb * es), hc(nc * es);
+    HIP_TRY(hipMemcpyAsync(hb.data(), B, nb * es, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hc.data(), C, nc * es, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    auto val = [&](const std::vector<unsigned char>& v, size_t i) -> double {
+        if (dtype == SL1_F64) return ((const double*)v.data())[i];
+        if (dtype == SL1_F32) return (double)((const float*)v.data())[i];
+        return bf16_host(((const uint16_t*)v.data())[i]);
+    };
+    // GB[j1][r][r'] = sum_i1 B_r[i1,j1] B_r'[i1,j1] (signed and absolute)
+    std::vector<double> GB((size_t)k1 * R * R), GBa((size_t)k1 * R * R), GC((size_t)k2 * R * R), GCa((size_t)k2 * R * R);
+    for (int j1 = 0; j1 < k1; ++j1)
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < R; ++q) {
+                double s1 = 0, s2 = 0;
+                for (int i1 = 0; i1 < n1; ++i1) {
+                    const double a = val(hb, ((size_t)r * k1 + j1) * n1 + i1), b = val(hb, ((size_t)q * k1 + j1) * n1 + i1);
+                    s1 += a * b;
+                    s2 += std::fabs(a) * std::fabs(b);
+                }
+                GB[((size_t)j1 * R + r) * R + q] = s1;
+                GBa[((size_t)j1 * R + r) * R + q] = s2;
+            }
+    for (int j2 = 0; j2 < k2; ++j2)
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < R; ++q) {
+                double s1 = 0, s2 = 0;
+                for (int i2 = 0; i2 < n2; ++i2) {
+                    const double a = val(hc, ((size_t)r * k2 + j2) * n2 + i2), b = val(hc, ((size_t)q * k2 + j2) * n2 + i2);
+                    s1 += a * b;
+                    s2 += std::fabs(a) * std::fabs(b);
+                }
+                GC[((size_t)j2 * R + r) * R + q] = s1;
+                GCa[((size_t)j2 * R + r) * R + q] = s2;
+            }
+    std::vector<double> an(K), ab(K);
+    for (int j1 = 0; j1 < k1; ++j1)
+        for (int j2 = 0; j2 < k2; ++j2) {
+            double s1 = 0, s2 = 0;
+            for (int r = 0; r < R; ++r)
+                for (int q = 0; q < R; ++q) {
+                    s1 += GB[((size_t)j1 * R + r) * R + q] * GC[((size_t)j2 * R + r) * R + q];
+                    s2 += GBa[((size_t)j1 * R + r) * R + q] * GCa[((size_t)j2 * R + r) * R + q];
+                }
+            an[(size_t)j1 * k2 + j2] = std::sqrt(std::max(s1, 0.0));
+            ab[(size_t)j1 * k2 + j2] = std::sqrt(std::max(s2, 0.0)) * (1.0 + 1e-12);
+        }
+    double* d_ab = nullptr;
+    int* bad = nullptr;
+    if (hipMalloc(&d_ab, K * 8) != hipSuccess || hipMalloc(&bad, 4) != hipSuccess) return SL1_ENOMEM;
+    HIP_TRY(hipMemcpyAsync(d->at_norm, an.data(), K * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ab, ab.data(), K * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
+    const double kappa = rounding_allowance(*d);
+    HIP_TRY(launch_eps_fold(eps, d_ab, kappa, (int)K, d->eps_eff, bad, s));
+    std::vector<double> ee(K);
+    int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(ee.data(), d->eps_eff, K * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(d_ab);
+    (void)hipFree(bad);
+    if (hbad) {
+        sl1_dict_free(d.release());
+        return SL1_EINVAL;
+    }
+    d->at_norm_max = *std::max_element(an.begin(), an.end());
+    d->eps_max_eff = *std::max_element(ee.begin(), ee.end());
+    d->rc_model = R * (1.0 / n1 + 1.0 / k2);
+    *out = d.release();
+    return SL1_OK;
+}
+
+int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc, const double* atom_norm,
+              int64_t batch, const void* y, const double* lambda, const sl1_opts* opt, void* x, double* gap,
+              double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage, void* stream) {
+    sl1_opts o;
+    if (opt) o = *opt;
+    else sl1_opts_default(&o);
+    if (!atom_norm || !y || !lambda || !x || !gap || batch < 1) return SL1_EINVAL;
+    if (batch > (1 << 20)) return SL1_ELIMIT;
+    if (o.max_iter < 0 || !(o.tol >= 0.0) || !std::isfinite(o.Gamma) || !(o.margin >= 0.0)) return SL1_EINVAL;
+    if (o.trace && o.trace_cap < 0) return SL1_EINVAL;
+    SolveParams tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    int st = prepare(seq, n_stages, L, rc, o.work_dtype, tmp);
+    if (st != SL1_OK) return st;
+    if (seq[n_stages - 1]->eps_max_in != 0.0) return SL1_EINVAL;   // the last stage must be A
+    int dev = 0;
+    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
+    if (dev != seq[0]->device) return SL1_EINVAL;
+    Workspace* w = nullptr;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, tmp.work_f64 != 0, &w);
+    if (st != SL1_OK) return st;
+    std::lock_guard<std::mutex> lk(w->mu);
+    SolveParams& p = *w->hP;
+    std::memcpy(p.st, tmp.st, sizeof(tmp.st));
+    p.n_stages = tmp.n_stages;
+    p.N = tmp.N;
+    p.K = tmp.K;
+    p.batch = (int)batch;
+    p.work_f64 = tmp.work_f64;
+    p.n1_max = tmp.n1_max;
+    p.max_iter = o.max_iter;
+    p.trace = o.trace;
+    p.trace_cap = o.trace ? o.trace_cap : 0;
+    p.lambda_only = 0;
+    p.Gamma = o.Gamma;
+    p.tol = o.tol;
+    p.margin = o.margin;
+    p.atom_norm = atom_norm;
+    p.y = y;
+    p.lam = lambda;
+    LaunchCfg cfg = launch_cfg(*w, p);
+    st = check_lds(cfg);
+    if (st != SL1_OK) return st;
+    const bool f64 = p.work_f64 != 0;
+    hipStream_t us = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(w->ev_in, us));
+    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+    HIP_TRY(launch_init(w->dP, cfg, f64, w->stream));
+    const int chunk = o.chunk > 0 ? o.chunk : 16;
+    const bool use_graph = !(o.flags & SL1_FLAG_NO_GRAPH);
+    if (use_graph && (!w->graph || w->graph_chunk != chunk || !cfg_equal(cfg, w->graph_cfg))) {
+        if (w->graph) {
+            HIP_TRY(hipGraphExecDestroy(w->graph));
+            w->graph = nullptr;
+        }
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        hipStream_t cs;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < chunk; ++k) {
+            if (launch_iter(w->dP, cfg, f64, cs) != hipSuccess) {
+                (void)hipStreamEndCapture(cs, &g);
+                (void)hipStreamDestroy(cs);
+                return SL1_EHIP;
+            }
+        }
+        HIP_TRY(hipStreamEndCapture(cs, &g));
+        HIP_TRY(hipStreamDestroy(cs));
+        hipError_t e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            w->graph = nullptr;
+            return SL1_EHIP;
+        }
+        w->graph_chunk = chunk;
+        w->graph_cfg = cfg;
+    }
+    long long launched = 0;
+    const long long cap = (long long)o.max_iter + 2LL * chunk + 4;
+    for (;;) {
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(w->graph, w->stream));
+        } else {
+            for (int k = 0; k < chunk; ++k) HIP_TRY(launch_iter(w->dP, cfg, f64, w->stream));
+        }
+        launched += chunk;
+        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        if (*w->h_active <= 0 || launched > cap) break;
+    }
+    HIP_TRY(launch_finalize(w->dP, cfg, f64, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
+    std::vector<int32_t> hs(batch);
+    HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
+    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
+    int result = SL1_OK;
+    for (int32_t v : hs) {
+        if (v < 0) return v;
+        if (v == SL1_MAXITER) result = SL1_MAXITER;
+    }
+    if (*w->h_active > 0) result = SL1_MAXITER;
+    return result;
+}
+
+static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* lam_out, double* g_out,
+                       void* z_out, void* stream) {
+    if (!d || !y || batch < 1) return SL1_EINVAL;
+    sl1_dict seq[1] = {d};
+    double L = 1.0;
+    SolveParams tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    int st = prepare(seq, 1, &L, nullptr, work_dtype, tmp);
+    if (st != SL1_OK) return st;
+    int dev = 0;
+    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
+    if (dev != d->device) return SL1_EINVAL;
+    Workspace* w = nullptr;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, tmp.work_f64 != 0, &w);
+    if (st != SL1_OK) return st;
+    std::lock_guard<std::mutex> lk(w->mu);
+    SolveParams& p = *w->hP;
+    std::memcpy(p.st, tmp.st, sizeof(tmp.st));
+    p.n_stages = 1;
+    p.N = tmp.N;
+    p.K = tmp.K;
+    p.batch = (int)batch;
+    p.work_f64 = tmp.work_f64;
+    p.n1_max = tmp.n1_max;
+    p.max_iter = 0;
+    p.trace = nullptr;
+    p.trace_cap = 0;
+    p.lambda_only = 1;
+    p.Gamma = 0.5;
+    p.tol = 0.0;
+    p.margin = 0.0;
+    p.atom_norm = d->at_norm;
+    p.y = y;
+    p.lam = nullptr;
+    LaunchCfg cfg = launch_cfg(*w, p);
+    st = check_lds(cfg);
+    if (st != SL1_OK) return st;
+    const bool f64 = p.work_f64 != 0;
+    hipStream_t us = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(w->ev_in, us));
+    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+    HIP_TRY(launch_init(w->dP, cfg, f64, w->stream));
+    HIP_TRY(launch_fwd_adj(w->dP, cfg, f64, w->stream));
+    // the per-signal status always comes back; lambda'_max lands in scratch when not asked for
+    double* lam_dst = lam_out ? lam_out : (double*)w->d_times;
+    HIP_TRY(launch_lambda_out(w->dP, (int)batch, lam_dst, w->d_status, w->stream));
+    if (g_out) HIP_TRY(launch_adjoint_out(w->dP, (int)batch, tmp.K, tmp.N, f64, g_out, z_out, w->stream));
+    std::vector<int32_t> hs(batch);
+    HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
+    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
+    for (int32_t v : hs)
+        if (v < 0) return v;
+    return SL1_OK;
+}
+
+int sl1_lambda_max(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out, void* stream) {
+    if (!out) return SL1_EINVAL;
+    return lambda_pass(d, batch, y, work_dtype, out, nullptr, nullptr, stream);
+}
+
+int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out, void* z_used,
+                     void* stream) {
+    if (!out) return SL1_EINVAL;
+    return lambda_pass(d, batch, y, work_dtype, nullptr, out, z_used, stream);
+}
+
+int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dtype, double* rc_out, void* stream) {
+    if (!seq || n_stages < 1 || !rc_out || batch < 1) return SL1_EINVAL;
+    std::vector<double> Ls(n_stages, 1.0);
+    SolveParams tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    int st = prepare(seq, n_stages, Ls.data(), nullptr, work_dtype, tmp);
+    if (st != SL1_OK) return st;
+    int dev = 0;
+    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
+    Workspace* w = nullptr;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, tmp.work_f64 != 0, &w);
+    if (st != SL1_OK) return st;
+    std::lock_guard<std::mutex> lk(w->mu);
+    // synthetic signals: y = 1 (any direction works, the cost does not depend on it)
+    void* ybuf = nullptr;
+    const size_t ws = tmp.work_f64 ? 8 : 4;
+    if (hipMalloc(&ybuf, (size_t)batch * tmp.N * ws) != hipSuccess) return SL1_ENOMEM;
+    std::vector<unsigned char> hy((size_t)batch * tmp.N * ws);
+    for (size_t i = 0; i < (size_t)batch * tmp.N; ++i) {
+        if (ws == 8) ((double*)hy.data())[i] = 1.0;
+        else ((float*)hy.data())[i] = 1.0f;
+    }
+    std::vector<double> times(n_stages, 0.0);
+    hipStream_t us = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(w->ev_in, us));
+    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    HIP_TRY(hipMemcpyAsync(ybuf, hy.data(), hy.size(), hipMemcpyHostToDevice, w->stream));
+    const int reps = 20;
+    for (int i = 0; i < n_stages; ++i) {
+        SolveParams& p = *w->hP;
+        std::memcpy(p.st, tmp.st, sizeof(tmp.st));
+        p.st[0] = tmp.st[i];
+        p.n_stages = 1;
+        p.N = tmp.N;
+        p.K = tmp.K;
+        p.batch = (int)batch;
+        p.work_f64 = tmp.work_f64;
+        p.n1_max = tmp.n1_max;
+        p.max_iter = 0;
+        p.trace = nullptr;
+        p.trace_cap = 0;
+        p.lambda_only = 1;
+        p.tol = 0.0;
+        p.margin = 0.0;
+        p.atom_norm = tmp.st[i].at_norm;
+        p.y = ybuf;
+        p.lam = nullptr;
+        LaunchCfg cfg = launch_cfg(*w, p);
+        if ((st = check_lds(cfg)) != SL1_OK) { (void)hipFree(ybuf); return st; }
+        const bool f64 = p.work_f64 != 0;
+        HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+        HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+        HIP_TRY(launch_init(w->dP, cfg, f64, w->stream));
+        HIP_TRY(launch_fwd_adj(w->dP, cfg, f64, w->stream));
+        for (int k = 0; k < 3; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, f64, w->stream));
+        HIP_TRY(hipEventRecord(w->ev_a, w->stream));
+        for (int k = 0; k < reps; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, f64, w->stream));
+        HIP_TRY(hipEventRecord(w->ev_b, w->stream));
+        HIP_TRY(hipEventSynchronize(w->ev_b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
+        times[i] = ms / reps;
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    (void)hipFree(ybuf);
+    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
+    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
+    const double ref = times[n_stages - 1];
+    for (int i = 0; i < n_stages; ++i) rc_out[i] = ref > 0 ? times[i] / ref : 1.0;
+    return SL1_OK;
+}
+
+// Device clock stamps (start, convergence) of each signal of the last solve of
+// this shape, for time-to-gap measurements; out: host, 2*batch int64, and the
+// clock rate in kHz.
+int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, int work_dtype, long long* out, double* rate_khz) {
+    int dev = 0;
+    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
+    Workspace* w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K, (int)(work_dtype == SL1_F64)));
+        if (it == g_ws.end()) return SL1_EINVAL;
+        w = it->second.get();
+    }
+    std::lock_guard<std::mutex> lk(w->mu);
+    HIP_TRY(launch_time_out(w->dP, (int)batch, w->d_times, w->stream));
+    HIP_TRY(hipMemcpyAsync(out, w->d_times, batch * 16, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *rate_khz = khz;
+    return SL1_OK;
+}
+
+__attribute__((visibility("hidden"))) int sl1_grad_impl_dense_info(sl1_dict_s* d, int* kind, int* dtype, int64_t* N, int64_t* K, const void** A,
+                             const float** scale) {
+    if (!d) return SL1_EINVAL;
+    *kind = d->kind;
+    *dtype = d->dtype;
+    *N = d->N;
+    *K = d->K;
+    *A = d->A;
+    *scale = d->scale;
+    return SL1_OK;
+}
+
+}  // extern "C"

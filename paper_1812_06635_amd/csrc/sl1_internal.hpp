@@ -1,0 +1,127 @@
+// Internal device-side definitions shared by the stablel1 kernels and the host
+// orchestration.  CDNA4 (gfx950): wave64, 256 threads per block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/stablel1.h"
+
+namespace sl1 {
+
+constexpr int kBlock = 256;         // threads per block (4 waves)
+constexpr int kWave = 64;
+constexpr int kSeg = 256;           // atoms per segment of a compacted list (one update block)
+constexpr int kAdjAtoms = 64;       // atoms per dense-adjoint block (16 per wave)
+constexpr int kFwdRows = 1024;      // rows per forward block (4 per thread)
+constexpr int kFwdSplits = 16;      // most column splits of the forward gather
+constexpr int kFwdMinPerSplit = 16; // fewest nonzeros per split
+constexpr int kKronColTile = 64;    // atoms (j1) per Kronecker-adjoint block (16 per wave)
+constexpr int kMaxN = 16384;
+
+enum Kind { kDense = 0, kKron = 1 };
+
+struct StageDesc {
+    int kind, dtype;
+    int R, n1, k1, n2, k2;
+    int vec;                  // dense: elements per lane per load (4, 8 or 16)
+    const void* A;            // dense storage
+    const float* scale;       // dense per-column scale or nullptr
+    const void* B;            // kron factors (device copies)
+    const void* C;
+    const double* eps;        // eps_j enlarged by the library's rounding bound
+    const double* at_norm;    // ||a~_j||_2 (look-ahead estimate K_t)
+    double L, invL, rc;
+    double at_norm_max, eps_max;
+};
+
+// Per-signal control and scalar state.  Written by the "last block" of a
+// kernel (after every other block of the signal has finished) or by the
+// initialisation kernel; read at kernel start.
+struct SigState {
+    int stage, iter, done, status;
+    int ksince, par;          // iterations since (re)start; parity of the current buffers
+    int n_act, n_nz;          // |A_t| and ||x_t||_0 (sizes of the current compacted lists)
+    int nseg_act, nseg_nz;    // segments of the current lists
+    int conv, Kt;
+    int n_keep, pad0;
+    double lam;
+    double tau, tau_next, beta;
+    double l1;                // ||x_t||_1
+    double r2, zz, yz;        // ||y - A~x||^2, ||z||^2, y^T z with z the stored residual
+    double mp, mt, E;         // max(|g|+eps||z||), max|g|, max eps over A_t
+    double sp, st;            // s' and s~: theta' = s' z, theta~ = s~ z
+    double P, Gp, Gt, delta, Rp, gamma;
+    double c1, c2;            // |s'| and |s'| ||z||: test coefficients
+    long long t0, tconv;      // wall-clock stamps (start, convergence)
+};
+
+struct SolveParams {
+    int n_stages, N, K, batch;
+    int max_iter, trace_cap, work_f64, lambda_only;
+    double Gamma, tol, margin;
+    StageDesc st[SL1_MAX_STAGES];
+    const double* atom_norm;
+    const void* y;            // batch x N (work type)
+    const double* lam;        // batch
+    double* trace;
+    // workspace (per signal b, arrays at base + b * stride)
+    SigState* state;
+    void* x;                  // [batch][2][K] work type
+    double* g;                // [batch][2][K]
+    uint8_t* mask;            // [batch][K]
+    int* act;                 // [batch][2][K]
+    int* nz;                  // [batch][2][K]
+    int* act_pre;             // [batch][2][nseg_max+1]
+    int* nz_pre;              // [batch][2][nseg_max+1]
+    void* z;                  // [batch][N] work type
+    double* fwd_part;         // [batch][kFwdSplits][N]
+    double* res_part;         // [batch][nrc][3]
+    double* adj_part;         // [batch][nadj_max][3]
+    double* upd_part;         // [batch][nseg_max][4]
+    unsigned* counters;       // [batch][nrc + 3]
+    int* active_signals;      // one int: signals not yet done
+    int nseg_max, nrc, nadj_max, n1_max;
+};
+
+struct LaunchCfg {
+    int batch, nseg_max, nrc, nadj_max;
+    size_t lds_fwd, lds_adj, lds_upd;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// bfloat16 bits -> float (exact)
+__device__ __forceinline__ float bf16_to_f(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Index i of a segmented compacted list: pre[] (in LDS) holds nseg+1 prefix counts.
+__device__ __forceinline__ int seg_find(const int* pre, int nseg, int i) {
+    int lo = 0, hi = nseg;   // invariant pre[lo] <= i < pre[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int list_get(const int* idx, const int* pre, int nseg, int i) {
+    int s = seg_find(pre, nseg, i);
+    return idx[s * kSeg + (i - pre[s])];
+}
+
+}  // namespace sl1

@@ -1,0 +1,76 @@
+"""The C-ABI library builds, loads and exports every entry point declared in
+include/stablel1.h (no compute call: these run without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stablel1.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl1_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1812_06635_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_expected_entry_points():
+    names = _declared()
+    for n in ["sl1_dict_dense", "sl1_dict_kron", "sl1_dict_free", "sl1_solve", "sl1_lambda_max", "sl1_grad",
+              "sl1_measure_rc", "sl1_status_str", "sl1_version", "sl1_opts_default"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1812_06635_amd.build import lib_path
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path()], capture_output=True, text=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    for n in _declared():
+        assert n in exported, n
+        assert hasattr(lib, n)
+    # nothing but the C ABI is exported
+    assert all(e.startswith("sl1_") for e in exported)
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1812_06635_amd import _lib
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert bound == set(_declared())
+
+
+def test_host_only_calls(lib):
+    from paper_1812_06635_amd import _lib
+    assert lib.sl1_version().decode().startswith("stablel1")
+    assert lib.sl1_status_str(0).decode() == "ok"
+    assert "singular" in lib.sl1_status_str(-6).decode()
+    o = _lib.Opts()
+    assert ctypes.sizeof(o) == 56
+    assert lib.sl1_opts_default(ctypes.byref(o)) == 0
+    assert (o.Gamma, o.tol, o.max_iter, o.chunk, o.work_dtype) == (0.5, 1e-6, 100000, 16, _lib.F32)
+    assert lib.sl1_opts_default(None) == _lib.EINVAL
+    assert lib.sl1_dict_free(None) == 0
+
+
+def test_argument_validation_without_device(lib):
+    from paper_1812_06635_amd import _lib
+    h = _lib.c_dict()
+    # NULL pointers and bad sizes are refused on the host before any HIP call
+    assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 256, 1024, None, None, None, None) == _lib.EINVAL
+    assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 0, 16, 16, 16, 16, None, None, None, None) == _lib.EINVAL
+    assert lib.sl1_dict_kron(ctypes.byref(h), 7, 1, 16, 16, 16, 16, 1, 1, 1, None) == _lib.EDTYPE
+    assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 1, 15, 16, 16, 16, 1, 1, 1, None) == _lib.ELIMIT
+    assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 258, 16, 1, None, 1, None) == _lib.ELIMIT
+    assert lib.sl1_dict_dense(ctypes.byref(h), 9, 256, 16, 1, None, 1, None) == _lib.EDTYPE
+    assert lib.sl1_solve(None, 1, None, None, None, 1, None, None, None, None, None, None, None, None, None,
+                         None) == _lib.EINVAL
+    assert lib.sl1_lambda_max(None, 1, None, 1, None, None) == _lib.EINVAL
+    assert lib.sl1_grad(None, 1, None, None, None, None, None, None, 1, None) == _lib.EINVAL

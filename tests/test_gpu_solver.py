@@ -1,0 +1,295 @@
+"""GPU parity of the HIP solver against the FP64 oracle (run with -m gpu).
+
+Every call goes through the C ABI (via the ctypes binding).  Inputs come from
+the seeded generators in ``synth``; expected values come from ``oracle`` only.
+"""
+import numpy as np
+import pytest
+
+import oracle.lasso as ol
+import oracle.screening as osc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sl1():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1812_06635_amd as m
+    m.load_library()
+    return m
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _run(sl1, p, tol, stages=None, **kw):
+    import torch
+    ups = [sl1.upload_stage(s) for s in (stages or p.stages)]
+    st = stages or p.stages
+    wt = torch.float64 if p.work == "f64" else torch.float32
+    out = sl1.solve(ups, [s.L for s in st], [s.rc_theory for s in st], _t(p.atom_norm), _t(p.Y, wt), _t(p.lam),
+                    tol=tol, **kw)
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+    return res
+
+
+# ---------------------------------------------------------------------------
+# kernel-level parity: every adjoint variant, atom by atom
+# ---------------------------------------------------------------------------
+ADJ_CASES = [
+    ("C1 kron f64 + dense f64", lambda: synth.config1(), 1e-12),
+    ("C2-small kron f32", lambda: synth.config2(n=(16, 32)), 2e-5),
+    ("C3-small dense fp8/bf16/f32", lambda: synth.config3(N=256, K=1024), 1e-12),
+    ("C3 ragged N=2500", lambda: synth.config3(N=2500, K=600, s=20), 1e-12),
+    ("C4-small kron bf16", lambda: synth.config4(batch=3, n=(16, 32)), 3e-5),
+    ("kron f32 n=(32,64) R=4", lambda: synth.config2(n=(32, 64), R_A=4, Rs=(1, 4)), 2e-5),
+]
+
+
+@pytest.mark.parametrize("name,maker,rtol", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+def test_adjoint_kernels_match_oracle_products(sl1, name, maker, rtol):
+    import torch
+    p = maker()
+    wt = torch.float64 if p.work == "f64" else torch.float32
+    for k, st in enumerate(p.stages):
+        _say(f"adjoint {name} stage {k} {st.label}")
+        d = sl1.upload_stage(st)
+        g, z = sl1.adjoint(d, _t(p.Y, wt))
+        g, z = g.cpu().numpy(), z.cpu().numpy().astype(np.float64)
+        At = st.values()
+        ref = z @ At                                   # a~_j^T z in FP64
+        if st.kind == "kron":                          # accumulation scale: sum_r |b_r| kron |c_r|
+            Bv, Cv = st.factor_values()
+            Aabs = synth.workloads._kron_sum(np.abs(Bv), np.abs(Cv))
+        else:
+            Aabs = np.abs(At)
+        scale = np.abs(z) @ Aabs + 1e-300
+        err = np.abs(g - ref) / scale
+        assert np.max(err) <= rtol, (name, k, float(np.max(err)))
+        # z is y itself except for BF16 Kronecker stages (rounded to BF16)
+        if st.kind == "kron" and st.dtype == "bf16":
+            assert np.all(np.abs(z - p.Y) <= 2.0 ** -8 * np.abs(p.Y))
+        else:
+            assert np.array_equal(z, p.Y)
+        # lambda'_max is an upper bound of the exact quantity and tight
+        lm = sl1.lambda_max(d, _t(p.Y, wt)).cpu().numpy()
+        for b in range(p.batch):
+            exact = osc.stable_lambda_max(At, st.eps, p.Y[b])
+            assert lm[b] >= exact * (1 - 1e-12)
+            assert lm[b] <= exact * (1 + max(rtol * 10, 2 ** -5 if st.dtype == "bf16" and st.kind == "kron" else 0))
+        d.free()
+
+
+# ---------------------------------------------------------------------------
+# the method: per-iteration trace against the FP64 method reference (C1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("real,frac", [(0, 0.5), (1, 0.2), (2, 0.8)])
+def test_fp64_trace_matches_method_reference(sl1, real, frac):
+    _say(f"trace C1 real={real} frac={frac}")
+    p = synth.config1(realization=real, lam_frac=frac)
+    out = _run(sl1, p, tol=1e-10, trace_cap=5000)
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
+                      [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10)
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0
+    assert n == ref.iters
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]              # stage sequence
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]           # |A_t|
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]             # |A_t+1|
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]                # K_t
+    Gc = np.array([r.G_conv for r in ref.trace])
+    np.testing.assert_allclose(tr[:, 6], Gc, rtol=1e-7, atol=1e-12)
+    np.testing.assert_allclose(tr[:, 9], [r.gamma for r in ref.trace], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(out["x"][0], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
+    # and the Lasso solution itself
+    sol = ol.solve(p.A, p.Y[0], float(p.lam[0]), L=p.stages[-1].L)
+    x = out["x"][0]
+    assert not np.any((out["screened"][0] == 1) & (sol["x"] != 0))
+    assert (ol.primal(p.A, p.Y[0], float(p.lam[0]), x) - sol["P"]) / sol["P"] <= 1e-7
+    assert np.linalg.norm(x - sol["x"]) <= 1e-4 * np.linalg.norm(sol["x"])
+    assert out["gap"][0] < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the method in FP32 (with FP64 gap and test) at oracle-friendly sizes
+# ---------------------------------------------------------------------------
+def _check_solution(p, out, b, obj_tol=1e-5, x_tol=1e-4):
+    y, lam = p.Y[b], float(p.lam[b])
+    sol = ol.solve(p.A, y, lam, L=p.stages[-1].L)
+    x = out["x"][b].astype(np.float64)
+    unsafe = int(np.sum((out["screened"][b] == 1) & (sol["x"] != 0)))
+    rel_obj = (ol.primal(p.A, y, lam, x) - sol["P"]) / sol["P"]
+    rel_x = np.linalg.norm(x - sol["x"]) / max(np.linalg.norm(sol["x"]), 1e-300)
+    assert unsafe == 0, f"signal {b}: {unsafe} unsafe rejections"
+    assert rel_obj <= obj_tol, f"signal {b}: objective error {rel_obj:.3e}"
+    if np.linalg.norm(sol["x"]) > 0:
+        assert rel_x <= x_tol, f"signal {b}: x error {rel_x:.3e}"
+    else:
+        assert np.all(x == 0)
+    return rel_obj, rel_x
+
+
+@pytest.mark.parametrize("frac", [0.3, 0.5, 0.8])
+def test_fp32_kronecker_method(sl1, frac):
+    _say(f"C2-small f32 kron frac={frac}")
+    p = synth.config2(n=(16, 32), lam_frac=frac)
+    out = _run(sl1, p, tol=1e-7)
+    assert out["status"] == 0 and out["stage"][0] == len(p.stages) - 1
+    _check_solution(p, out, 0)
+
+
+def test_low_precision_dense_method(sl1):
+    _say("C3-small fp8/bf16/f32 dense")
+    p = synth.config3(N=256, K=1024, s=20, batch=4)
+    out = _run(sl1, p, tol=1e-8)
+    assert out["status"] == 0
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+def test_low_precision_dense_ragged(sl1):
+    _say("C3 ragged N=2500 K=600")
+    p = synth.config3(N=2500, K=600, s=20, batch=2)
+    out = _run(sl1, p, tol=1e-8)
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+def test_batched_bf16_kronecker_method(sl1):
+    _say("C4-small batch 24 bf16 kron")
+    p = synth.config4(batch=24, n=(16, 32))
+    out = _run(sl1, p, tol=1e-7)
+    assert out["status"] == 0
+    assert len(set(out["iters"].tolist())) > 1           # uneven convergence inside one launch
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+# ---------------------------------------------------------------------------
+# edge cases and error paths
+# ---------------------------------------------------------------------------
+def test_lambda_above_lambda_max_returns_zero(sl1):
+    _say("lambda >= lambda_max")
+    p = synth.config1()
+    p.lam = p.lam_max * 1.01
+    out = _run(sl1, p, tol=1e-12)
+    assert out["status"] == 0
+    assert np.all(out["x"] == 0) and out["gap"][0] <= 1e-12
+    assert np.all(out["screened"][0] == 1)
+
+
+def test_max_iter_zero_and_cap(sl1):
+    _say("max_iter 0 and 5")
+    p = synth.config1()
+    out = _run(sl1, p, tol=1e-12, max_iter=0, check=False)
+    assert out["status"] == 1 and out["iters"][0] == 0 and np.all(out["x"] == 0)
+    out = _run(sl1, p, tol=1e-14, max_iter=5, check=False)
+    assert out["status"] == 1 and out["iters"][0] == 5
+
+
+def test_invalid_lambda_is_reported(sl1):
+    _say("invalid lambda")
+    from paper_1812_06635_amd._lib import Stablel1Error
+    p = synth.config1()
+    p.lam = np.array([-1.0])
+    with pytest.raises(Stablel1Error):
+        _run(sl1, p, tol=1e-8)
+    p.lam = np.array([np.nan])
+    with pytest.raises(Stablel1Error):
+        _run(sl1, p, tol=1e-8)
+
+
+def test_graph_replay_equals_direct_launches(sl1):
+    _say("graph vs direct")
+    p = synth.config4(batch=6, n=(16, 32))
+    a = _run(sl1, p, tol=1e-7, use_graph=True)
+    b = _run(sl1, p, tol=1e-7, use_graph=False, chunk=5)
+    np.testing.assert_array_equal(a["x"], b["x"])
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    np.testing.assert_array_equal(a["screened"], b["screened"])
+
+
+def test_exact_only_sequence_is_gap_safe(sl1):
+    # one stage (the exact A): the stable test is GAP Safe, gamma = 1
+    _say("exact-only sequence")
+    p = synth.config1()
+    st = [p.stages[-1]]
+    out = _run(sl1, p, tol=1e-10, stages=st, trace_cap=3000)
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in st], p.atom_norm, p.Y[0], float(p.lam[0]), [1.0],
+                      tol=1e-10)
+    n = int(out["iters"][0])
+    assert n == ref.iters
+    assert [int(v) for v in out["trace"][0][:n, 2]] == [r.n_active for r in ref.trace]
+    np.testing.assert_allclose(out["trace"][0][:n, 9], 1.0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# implicit adjoint
+# ---------------------------------------------------------------------------
+def test_implicit_adjoint_matches_finite_differences(sl1):
+    import torch
+    _say("grad vs FD")
+    p = synth.config5(batch=3, n=(16, 32), R_A=8, Rs=(4, 8))
+    out = _run(sl1, p, tol=1e-8)
+    x = out["x"].astype(np.float64)
+    A = p.A
+    exact = sl1.upload_stage(p.stages[-1])
+    dx = 2.0 * (x - p.X0)
+    dy, dlam = sl1.grad(exact, _t(out["x"]), _t(p.Y, torch.float32), _t(p.lam), _t(dx, torch.float32))
+    dy, dlam = dy.cpu().numpy().astype(np.float64), dlam.cpu().numpy()
+    rng = np.random.default_rng(5)
+    for b in range(p.batch):
+        y, lam = p.Y[b], float(p.lam[b])
+
+        def loss(yy, ll):
+            s = ol.solve(A, yy, ll, L=p.stages[-1].L, tol=1e-15)
+            return float(np.sum((s["x"] - p.X0[b]) ** 2)), s
+
+        _, s0 = loss(y, lam)
+        assert s0["margin"] > 1e-4
+        # closed form on the oracle support (FP64)
+        S = s0["support"]
+        G = A[:, S].T @ A[:, S]
+        v = 2 * (s0["x"] - p.X0[b])[S]
+        w = np.linalg.solve(G, v)
+        g_ref = A[:, S] @ w
+        l_ref = -np.sign(s0["x"][S]) @ w
+        assert np.linalg.norm(dy[b] - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+        assert abs(dlam[b] - l_ref) <= 1e-4 * abs(l_ref) + 1e-8
+        # central differences, h = 1e-6
+        u = rng.standard_normal(len(y))
+        u /= np.linalg.norm(u)
+        h = 1e-6
+        fd = (loss(y + h * u, lam)[0] - loss(y - h * u, lam)[0]) / (2 * h)
+        assert abs(fd - dy[b] @ u) <= 1e-4 * max(1.0, abs(fd))
+        fdl = (loss(y, lam + h)[0] - loss(y, lam - h)[0]) / (2 * h)
+        assert abs(fdl - dlam[b]) <= 1e-4 * max(1.0, abs(fdl))
+
+
+def test_autograd_function_backward(sl1):
+    import torch
+    _say("autograd")
+    p = synth.config5(batch=2, n=(16, 32), R_A=8, Rs=(8,))
+    ups = [sl1.upload_stage(s) for s in p.stages]
+    y = _t(p.Y, torch.float32).requires_grad_(True)
+    lam = _t(p.lam).requires_grad_(True)
+    x = sl1.lasso(y, lam, ups, [s.L for s in p.stages], [s.rc_theory for s in p.stages], _t(p.atom_norm),
+                  tol=1e-8)
+    loss = ((x.double() - _t(p.X0)) ** 2).sum()
+    loss.backward()
+    assert y.grad is not None and lam.grad is not None
+    assert torch.isfinite(y.grad).all() and torch.isfinite(lam.grad).all()
