@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Time-to-gap 1e-6 and FISTA iterations/s of the stable-screening Lasso solver
+on one MI355X.
+
+Workload (one "step" = one complete solve of the batch to duality gap 1e-6,
+i.e. every row of the hot path, iterated):
+  batched low precision: 512 signals on a shared Kronecker dictionary
+  N=1024 (32x32), K=4096 (64x64), A = sum_{r<=4} B_r kron C_r + 0.01 G (FP32),
+  stages A~_1, A~_2, A~_4 with BF16 factors then A (FP32); per-signal sparsity
+  U{5..80}, lambda/lambda_max U[0.2, 0.9], noise U[0.001, 0.05].
+Comparator: plain FP32 FISTA + GAP Safe screening on the same batch (the single
+stage [A], same kernels).  A second block reports the single-signal FP32
+configuration N=4096 (64x64), K=16384 (128x128), R=8, lambda = 0.5 lambda_max.
+
+Prints one JSON line.  Inputs are synthetic and seeded (see synth/).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-signal block")
+    ap.add_argument("--no-parity", action="store_true", help="skip the sampled oracle parity check")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def upload(sl1, torch, p):
+    st = [sl1.upload_stage(s) for s in p.stages]
+    dev = "cuda"
+    Y = torch.from_numpy(p.Y).to(torch.float32).to(dev)
+    lam = torch.from_numpy(p.lam).to(dev)
+    an = torch.from_numpy(p.atom_norm).to(dev)
+    return st, Y, lam, an
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps, out
+
+
+def adj_work(p, trace, iters):
+    """Algorithmic work of the correlation kernel over one solve, from the trace:
+    dense stage: N * bytes/element * |A_t| (+ 4 B per scaled atom);
+    Kronecker stage: 2 R k2 n1 (n2 + k1) flops (sum_r C_r^T P B_r)."""
+    import numpy as np
+    N = p.N
+    byts, flops, dense_it, kron_it = 0.0, 0.0, 0, 0
+    for b in range(trace.shape[0]):
+        n = int(iters[b])
+        rows = trace[b, :n]
+        for s_idx, st in enumerate(p.stages):
+            m = rows[:, 1] == s_idx
+            cnt = int(m.sum())
+            if not cnt:
+                continue
+            if st.kind == "dense":
+                bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
+                byts += N * bpe * float(rows[m, 2].sum())
+                dense_it += cnt
+            else:
+                n1, k1, n2, k2 = st.dims
+                flops += cnt * 2.0 * st.R * k2 * n1 * (n2 + k1)
+                kron_it += cnt
+    return byts, flops, dense_it, kron_it
+
+
+def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
+    st, Y, lam, an = upload(sl1, torch, p)
+    L = [s.L for s in p.stages]
+    log(f"{label}: measuring relative complexities")
+    rc_meas = sl1.measure_rc(st, batch=p.batch)
+    rc = rc_meas
+    log(f"{label}: RC measured {['%.3f' % v for v in rc_meas]} model {['%.3f' % s.rc_theory for s in p.stages]}")
+
+    def method():
+        return sl1.solve(st, L, rc, an, Y, lam, tol=tol)
+
+    def plain():
+        return sl1.solve([st[-1]], [L[-1]], [1.0], an, Y, lam, tol=tol)
+
+    ms_m, out_m = timed(torch, method, steps, warmup)
+    clk = sl1.last_solve_clock(p.batch, p.N, p.K)
+    ttg_dev = float(np.max(clk[:, 1] - clk[:, 0])) * 1e3
+    ms_p, out_p = timed(torch, plain, steps, warmup)
+    it_m = int(out_m["iters"].sum().item())
+    it_p = int(out_p["iters"].sum().item())
+    gap_m = out_m["gap"].cpu().numpy()
+    gap_p = out_p["gap"].cpu().numpy()
+    log(f"{label}: method {ms_m:.3f} ms ({it_m} iters), plain {ms_p:.3f} ms ({it_p} iters)")
+    # profiled run (not timed): per-kernel device time and the trace for algorithmic work
+    cap = int(out_m["iters"].max().item()) + 8
+    outp = sl1.solve(st, L, rc, an, Y, lam, tol=tol, profile=True, trace_cap=cap)
+    prof = sl1.last_solve_profile(p.batch, p.N, p.K)
+    trace = outp["trace"].cpu().numpy()
+    iters = outp["iters"].cpu().numpy()
+    byts, flops, dense_it, kron_it = adj_work(p, trace, iters)
+    res = dict(
+        ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p,
+        time_to_gap_ms_device=ttg_dev, max_gap_method=float(gap_m.max()), max_gap_plain=float(gap_p.max()),
+        stage_final=sorted(set(out_m["stage"].cpu().numpy().tolist())), rc_measured=rc_meas,
+        rc_model=[s.rc_theory for s in p.stages], kernel_ms=prof,
+        adj_alg_bytes=byts, adj_alg_flops=flops, adj_dense_signal_iters=dense_it, adj_kron_signal_iters=kron_it,
+        x=out_m["x"].cpu().numpy(), screened=out_m["screened"].cpu().numpy(),
+    )
+    return res
+
+
+def roofline(res):
+    ms_adj, n_adj = res["kernel_ms"]["adj"]
+    t = ms_adj * 1e-3
+    if res["adj_dense_signal_iters"] >= res["adj_kron_signal_iters"]:
+        ach = res["adj_alg_bytes"] / t / 1e9
+        return dict(kernel="k_adj (correlations + scalar block)", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None, launches=n_adj,
+                    avg_launch_us=ms_adj * 1e3 / max(n_adj, 1))
+    ach = res["adj_alg_flops"] / t / 1e12
+    return dict(kernel="k_adj (correlations + scalar block)", bound="mfma", achieved=ach, peak=BF16_PEAK_TFLOPS,
+                unit="TFLOP/s", frac=ach / BF16_PEAK_TFLOPS, traffic=None, launches=n_adj,
+                avg_launch_us=ms_adj * 1e3 / max(n_adj, 1))
+
+
+def parity_sample(np, p, res, n=2):
+    import oracle.lasso as ol
+    worst_obj, worst_x, unsafe = 0.0, 0.0, 0
+    idx = list(range(min(n, p.batch)))
+    for b in idx:
+        sol = ol.solve(p.A, p.Y[b], float(p.lam[b]), L=p.stages[-1].L, tol=1e-13)
+        x = res["x"][b]
+        P = ol.primal(p.A, p.Y[b], float(p.lam[b]), x)
+        worst_obj = max(worst_obj, (P - sol["P"]) / sol["P"])
+        if np.linalg.norm(sol["x"]) > 0:
+            worst_x = max(worst_x, float(np.linalg.norm(x - sol["x"]) / np.linalg.norm(sol["x"])))
+        unsafe += int(np.sum((res["screened"][b] == 1) & (sol["x"] != 0)))
+    return dict(signals=len(idx), max_rel_obj=worst_obj, max_rel_x=worst_x, unsafe_rejections=unsafe)
+
+
+def cpu_baseline(np, p, seconds):
+    """The FP64 oracle (plain FISTA, exact A, no screening) timed on the host."""
+    import oracle.lasso as ol
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(i.get("num_threads", 1)) for i in info)
+    except Exception:
+        pass
+    y, lam = p.Y[0], float(p.lam[0])
+    L = p.stages[-1].L
+    n = 20
+    t0 = time.perf_counter()
+    ol.fista(p.A, y, lam, L, tol=0.0, max_iter=n, check_every=10 ** 9)
+    dt = time.perf_counter() - t0
+    while dt < seconds and n < 10 ** 6:
+        n = int(n * max(2.0, min(10.0, seconds / max(dt, 1e-3))))
+        t0 = time.perf_counter()
+        ol.fista(p.A, y, lam, L, tol=0.0, max_iter=n, check_every=10 ** 9)
+        dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="iter/s", cores=threads, kind="oracle",
+                sample=f"FP64 FISTA without screening, exact A (N={p.N}, K={p.K}), signal 0, {n} iterations "
+                       f"in {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solver has no multi-GPU path "
+                                   "(batches shard by signal across GPUs, see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_1812_06635_amd as sl1
+    torch.cuda.set_device(0)
+    sl1.load_library()
+
+    log("generating the batched workload (512 signals, N=1024, K=4096)")
+    p = synth.config4(batch=512)
+    res = solve_block(sl1, torch, np, p, args.tol, args.steps, args.warmup, "batched")
+    line = {
+        "metric": "time-to-gap 1e-6 and FISTA iters/s (batched low-prec vs plain FP32), 1 GPU",
+        "value": res["iters_method"] / (res["ms_method"] * 1e-3),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_method"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 factors / fp32 A, fp64 vectors",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "batched low precision: 512 signals, shared Kronecker dictionary N=1024 (32x32), "
+                               "K=4096 (64x64), stages A~_1, A~_2, A~_4 (BF16 factors) then A (FP32), tol 1e-6",
+                   "global_batch": p.batch, "N": p.N, "K": p.K},
+        "time_to_gap_ms": res["ms_method"],
+        "time_to_gap_ms_device": res["time_to_gap_ms_device"],
+        "plain_fp32": {"time_to_gap_ms": res["ms_plain"], "iters": res["iters_plain"],
+                       "iters_per_s": res["iters_plain"] / (res["ms_plain"] * 1e-3)},
+        "speedup_vs_plain_fp32": res["ms_plain"] / res["ms_method"],
+        "iters": res["iters_method"],
+        "max_gap": res["max_gap_method"],
+        "rc_measured": res["rc_measured"],
+        "rc_model": res["rc_model"],
+        "kernel_ms": res["kernel_ms"],
+        "roofline": roofline(res),
+    }
+    if not args.no_parity:
+        log("sampled parity against the FP64 oracle")
+        line["parity"] = parity_sample(np, p, res)
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(np, p, args.cpu_seconds)
+    if not args.no_single:
+        log("single-signal block (N=4096, K=16384, R=8, FP32)")
+        q = synth.config2(lam_frac=0.5)
+        r2 = solve_block(sl1, torch, np, q, args.tol, max(1, args.steps), args.warmup, "single")
+        line["single_signal"] = {
+            "workload": "N=4096 (64x64), K=16384 (128x128), A = sum_{r<=8} B_r kron C_r + 0.01 G (FP32), "
+                        "stages A~_1, A~_2, A~_4, A~_8 (FP32 factors) then A, lambda = 0.5 lambda_max, tol 1e-6",
+            "time_to_gap_ms": r2["ms_method"], "iters": r2["iters_method"],
+            "iters_per_s": r2["iters_method"] / (r2["ms_method"] * 1e-3),
+            "plain_fp32_time_to_gap_ms": r2["ms_plain"], "plain_fp32_iters": r2["iters_plain"],
+            "speedup_vs_plain_fp32": r2["ms_plain"] / r2["ms_method"],
+            "rc_measured": r2["rc_measured"], "kernel_ms": r2["kernel_ms"], "roofline": roofline(r2),
+            "max_gap": r2["max_gap_method"],
+        }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

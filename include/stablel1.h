@@ -27,7 +27,7 @@
  *     (outputs untouched or undefined).  Argument checks are synchronous on the
  *     host; errors met on the device are reported through the return value of
  *     the call that waits for them (sl1_solve, sl1_lambda_max, sl1_grad).
- *   - Implementation limits (SL1_ELIMIT): N % 4 == 0; N <= 16384; Kronecker
+ *   - Implementation limits (SL1_ELIMIT): N % 4 == 0; N <= 8192; K <= 262144; Kronecker
  *     factor sizes n1, k1, n2, k2 multiples of 16; at most SL1_MAX_STAGES stages.
  */
 #ifndef STABLEL1_H
@@ -111,7 +111,7 @@ typedef struct {
     double tol;          /* [1e-6] stop once on A with conventional duality gap < tol */
     double margin;       /* [1e-12] reject atom j iff its test value < 1 - margin */
     int32_t max_iter;    /* [100000] iteration cap per signal */
-    int32_t work_dtype;  /* [SL1_F32] type of y, x and iterate vectors: SL1_F64 or SL1_F32 */
+    int32_t y_dtype;     /* [SL1_F32] storage type of the signals y: SL1_F64 or SL1_F32 */
     int32_t chunk;       /* [16] iterations enqueued between two convergence polls */
     int32_t flags;       /* [0] SL1_FLAG_* */
     double* trace;       /* [NULL] optional device buffer, batch x trace_cap x SL1_TRACE_FIELDS
@@ -122,6 +122,7 @@ typedef struct {
 } sl1_opts;
 
 #define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */
+#define SL1_FLAG_PROFILE 2    /* direct launches bracketed by HIP events; see sl1_last_solve_profile */
 
 int sl1_opts_default(sl1_opts* o);
 
@@ -134,9 +135,13 @@ int sl1_opts_default(sl1_opts* o);
  *              speed criterion (Section IV-B); rc[n_stages-1] is ignored.
  *   atom_norm  K doubles: ||a_j||_2 of the exact atoms (restricted zone, Lemma 1).
  *   batch      number of signals (>= 1).
- *   y          batch x N in opt->work_dtype (signal b at y + b*N).
+ *   y          batch x N in opt->y_dtype (signal b at y + b*N).
  *   lambda     batch doubles, each > 0.
- *   x          out, batch x K in opt->work_dtype: the solution, zero on screened atoms.
+ *   x          out, batch x K doubles: the solution, zero on screened atoms.
+ * Precision: iterates, residuals, correlations, gaps and tests are FP64; each
+ * stage's products read its own storage type (FP64 / FP32 / BF16 / FP8) with
+ * FP64 accumulation, except FP32 and BF16 Kronecker products, which run on the
+ * matrix cores with FP32 accumulation (their rounding is covered by eps).
  *   gap        out, batch doubles: conventional duality gap G(x, theta|A) at x.
  *   gap_cert   out (may be NULL), batch doubles: G(x, theta'|A~) + delta(x) at x, an
  *              upper bound of the gap of the exact problem (Theorem 1).
@@ -152,27 +157,28 @@ int sl1_opts_default(sl1_opts* o);
  */
 int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc,
               const double* atom_norm, int64_t batch, const void* y, const double* lambda,
-              const sl1_opts* opt, void* x, double* gap, double* gap_cert, uint8_t* screened,
+              const sl1_opts* opt, double* x, double* gap, double* gap_cert, uint8_t* screened,
               int32_t* iters, int32_t* stage, void* stream);
 
 /*
  * sl1_lambda_max -- out[b] = max_j (|a~_j^T y_b| + eps_j ||y_b||_2), the stable
  * lambda'_max of Section III-C (equal to lambda_max = ||A^T y_b||_inf when eps = 0).
- *   y    batch x N in work_dtype;  out  batch doubles.  Synchronous.
+ *   y    batch x N in y_dtype;  out  batch doubles.  Includes the library's own
+ *        rounding allowance, so it is an upper bound.  Synchronous.
  */
-int sl1_lambda_max(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out,
+int sl1_lambda_max(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* out,
                    void* stream);
 
 /*
  * sl1_dict_adjoint -- out[b*K + j] = a~_j^T z_b for every atom j, computed by the
  * solver's own correlation kernel for this stage (the adjoint product of
  * Algorithm 1's update, A~^T rho~).  z_b is y_b as the solver stores it: y_b
- * itself, or its BF16 rounding for BF16 Kronecker stages (written to z_used,
- * batch x N in work_dtype, when z_used is not NULL).
- *   y    batch x N in work_dtype;  out  batch x K doubles.  Synchronous.
+ * itself, or its FP32 / BF16 rounding for FP32 / BF16 Kronecker stages (written
+ * to z_used, batch x N doubles, when z_used is not NULL).
+ *   y    batch x N in y_dtype;  out  batch x K doubles.  Synchronous.
  */
-int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out,
-                     void* z_used, void* stream);
+int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* out,
+                     double* z_used, void* stream);
 
 /*
  * sl1_grad -- implicit adjoint of the Lasso solution map on the support
@@ -181,13 +187,14 @@ int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int work_dtype, d
  *   dL/dy      = A_S (A_S^T A_S)^{-1} (dL/dx)_S
  *   dL/dlambda = -sign(x_S)^T (A_S^T A_S)^{-1} (dL/dx)_S
  *   A          the exact dictionary (dense stage).
- *   x, dx      batch x K in work_dtype (solution and incoming gradient).
- *   dy         out, batch x N in work_dtype;  dlambda  out, batch doubles.
+ *   x, dx      batch x K doubles (solution and incoming gradient).
+ *   y          batch x N in y_dtype (unused by the formula; kept for symmetry).
+ *   dy         out, batch x N in y_dtype;  dlambda  out, batch doubles.
  * Returns SL1_ESINGULAR if a support Gram matrix is not positive definite,
  * SL1_ELIMIT if a support exceeds 1024 atoms or N.  Synchronous.
  */
-int sl1_grad(sl1_dict A, int64_t batch, const void* x, const void* y, const double* lambda,
-             const void* dx, void* dy, double* dlambda, int work_dtype, void* stream);
+int sl1_grad(sl1_dict A, int64_t batch, const double* x, const void* y, const double* lambda,
+             const double* dx, void* dy, double* dlambda, int y_dtype, void* stream);
 
 /*
  * sl1_measure_rc -- measured relative complexity of each stage: the device
@@ -195,8 +202,8 @@ int sl1_grad(sl1_dict A, int64_t batch, const void* x, const void* y, const doub
  * stage with every atom preserved (Section IV-B, Section V-A measures RC
  * instead of using the model).  rc_out: host, n_stages doubles.  Synchronous.
  */
-int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dtype,
-                   double* rc_out, void* stream);
+int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_out,
+                   void* stream);
 
 /*
  * sl1_last_solve_clock -- device wall-clock stamps of the most recent
@@ -204,8 +211,15 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dt
  * b, out[2b+1] = iteration at which its gap first fell below tol (0 if never).
  * out: host, 2*batch int64; rate_khz: host, clock rate.  For time-to-gap.
  */
-int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, int work_dtype, long long* out,
-                         double* rate_khz);
+int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, double* rate_khz);
+
+/*
+ * sl1_last_solve_profile -- per-kernel device time of the most recent
+ * sl1_solve with SL1_FLAG_PROFILE and these shapes: ms[k] total milliseconds and
+ * launches[k] launch count of k = 0 forward/residual, 1 correlations + scalar
+ * block, 2 test/update/compaction (host arrays of 3).
+ */
+int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
 
 const char* sl1_status_str(int status);
 const char* sl1_version(void);

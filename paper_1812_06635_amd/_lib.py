@@ -15,6 +15,7 @@ OK, MAXITER, EINVAL, ESHAPE, EDTYPE, EHIP, ENOMEM, ESINGULAR, ELIMIT = 0, 1, -1,
 MAX_STAGES = 8
 TRACE_FIELDS = 12
 FLAG_NO_GRAPH = 1
+FLAG_PROFILE = 2
 
 c_dict = ctypes.c_void_p
 c_p = ctypes.c_void_p
@@ -24,7 +25,7 @@ c_d = ctypes.c_double
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("Gamma", c_d), ("tol", c_d), ("margin", c_d), ("max_iter", c_i32), ("work_dtype", c_i32),
+    _fields_ = [("Gamma", c_d), ("tol", c_d), ("margin", c_d), ("max_iter", c_i32), ("y_dtype", c_i32),
                 ("chunk", c_i32), ("flags", c_i32), ("trace", c_p), ("trace_cap", c_i32), ("reserved", c_i32)]
 
 
@@ -41,9 +42,9 @@ SIGNATURES = [
     ("sl1_lambda_max", c_i32, [c_dict, c_i64, c_p, c_i32, c_p, c_p]),
     ("sl1_dict_adjoint", c_i32, [c_dict, c_i64, c_p, c_i32, c_p, c_p, c_p]),
     ("sl1_grad", c_i32, [c_dict, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p]),
-    ("sl1_measure_rc", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, c_i32, ctypes.POINTER(c_d), c_p]),
-    ("sl1_last_solve_clock", c_i32, [c_i64, c_i64, c_i64, c_i32, ctypes.POINTER(ctypes.c_longlong),
-                                     ctypes.POINTER(c_d)]),
+    ("sl1_measure_rc", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, ctypes.POINTER(c_d), c_p]),
+    ("sl1_last_solve_clock", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_d)]),
+    ("sl1_last_solve_profile", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_longlong)]),
     ("sl1_status_str", ctypes.c_char_p, [c_i32]),
     ("sl1_version", ctypes.c_char_p, []),
 ]

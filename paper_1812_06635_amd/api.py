@@ -14,7 +14,6 @@ from . import _lib as L
 
 DTYPES = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16, "fp8": L.FP8_E4M3}
 _STORAGE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8}
-_WORK = {"f64": torch.float64, "f32": torch.float32}
 
 
 def _stream():
@@ -115,12 +114,13 @@ def upload_stage(stage, device="cuda"):
 
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
-          trace_cap=0, use_graph=True, check=True):
+          trace_cap=0, use_graph=True, profile=False, check=True):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage,
     the status code, and the trace (batch, trace_cap, 12) when requested."""
-    work = "f64" if y.dtype == torch.float64 else "f32"
-    _dev(y, _WORK[work], "y")
+    if y.dtype not in (torch.float64, torch.float32):
+        raise TypeError("y must be float32 or float64")
+    _dev(y, None, "y")
     _dev(lam, torch.float64, "lam")
     _dev(atom_norm, torch.float64, "atom_norm")
     if y.dim() == 1:
@@ -136,14 +136,14 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     L.load().sl1_opts_default(ctypes.byref(opts))
     opts.Gamma, opts.tol, opts.margin = Gamma, tol, margin
     opts.max_iter, opts.chunk = max_iter, chunk
-    opts.work_dtype = L.F64 if work == "f64" else L.F32
-    opts.flags = 0 if use_graph else L.FLAG_NO_GRAPH
+    opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
+    opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0)
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)
         opts.trace = trace.data_ptr()
         opts.trace_cap = trace_cap
-    x = torch.empty((batch, K), dtype=y.dtype, device=dev)
+    x = torch.empty((batch, K), dtype=torch.float64, device=dev)
     gap = torch.empty(batch, dtype=torch.float64, device=dev)
     gap_cert = torch.empty(batch, dtype=torch.float64, device=dev)
     screened = torch.empty((batch, K), dtype=torch.uint8, device=dev)
@@ -178,39 +178,47 @@ def adjoint(d, y):
     work = L.F64 if y.dtype == torch.float64 else L.F32
     _dev(y, None, "y")
     out = torch.empty((y.shape[0], d.K), dtype=torch.float64, device=y.device)
-    z = torch.empty_like(y)
+    z = torch.empty(y.shape, dtype=torch.float64, device=y.device)
     L.check(L.load().sl1_dict_adjoint(d.handle, y.shape[0], _ptr(y), work, _ptr(out), _ptr(z), _stream()),
             "sl1_dict_adjoint")
     return out, z
 
 
-def measure_rc(stages, batch=1, work="f32"):
+def measure_rc(stages, batch=1):
+    """Measured relative complexity of each stage's correlation product."""
     n = len(stages)
     arr = (L.c_dict * n)(*[s.handle for s in stages])
     out = (L.c_d * n)()
-    L.check(L.load().sl1_measure_rc(arr, n, batch, L.F64 if work == "f64" else L.F32, out, _stream()),
-            "sl1_measure_rc")
+    L.check(L.load().sl1_measure_rc(arr, n, batch, out, _stream()), "sl1_measure_rc")
     return [out[i] for i in range(n)]
 
 
-def last_solve_clock(batch, N, K, work="f32"):
+def last_solve_clock(batch, N, K):
     """(start, converged) device clock stamps in seconds of the last solve of this shape."""
     buf = (ctypes.c_longlong * (2 * batch))()
     rate = L.c_d()
-    L.check(L.load().sl1_last_solve_clock(batch, N, K, L.F64 if work == "f64" else L.F32, buf,
-                                          ctypes.byref(rate)), "sl1_last_solve_clock")
+    L.check(L.load().sl1_last_solve_clock(batch, N, K, buf, ctypes.byref(rate)), "sl1_last_solve_clock")
     a = np.frombuffer(buf, dtype=np.int64).reshape(batch, 2).astype(np.float64)
     return a / (rate.value * 1e3)
+
+
+def last_solve_profile(batch, N, K):
+    """{kernel: (total ms, launches)} of the last solve run with profile=True."""
+    ms = (L.c_d * 3)()
+    n = (ctypes.c_longlong * 3)()
+    L.check(L.load().sl1_last_solve_profile(batch, N, K, ms, n), "sl1_last_solve_profile")
+    names = ("fwd", "adj", "upd")
+    return {names[k]: (ms[k], n[k]) for k in range(3)}
 
 
 def grad(A, x, y, lam, dx):
     """Implicit adjoint on the support of x: returns (dL/dy, dL/dlambda)."""
     if x.dim() == 1:
         x, y, dx = x.unsqueeze(0), y.unsqueeze(0), dx.unsqueeze(0)
-    work = L.F64 if x.dtype == torch.float64 else L.F32
-    _dev(x, None, "x")
-    _dev(dx, x.dtype, "dx")
-    _dev(y, x.dtype, "y")
+    work = L.F64 if y.dtype == torch.float64 else L.F32
+    _dev(x, torch.float64, "x")
+    _dev(dx, torch.float64, "dx")
+    _dev(y, None, "y")
     _dev(lam, torch.float64, "lam")
     dy = torch.empty_like(y)
     dlam = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
@@ -235,7 +243,7 @@ class LassoFunction(torch.autograd.Function):
     def backward(ctx, gx):
         x, y, lam = ctx.saved_tensors
         dy, dlam = grad(ctx.stages[-1], x, y if y.dim() == 2 else y.unsqueeze(0), lam,
-                        gx.contiguous().to(x.dtype))
+                        gx.contiguous().to(torch.float64))
         if y.dim() == 1:
             dy = dy[0]
         return dy, dlam.reshape(lam.shape), None, None, None, None, None

@@ -14,15 +14,16 @@
 #include "sl1_internal.hpp"
 
 namespace sl1 {
-hipError_t launch_init(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
-hipError_t launch_iter(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
-hipError_t launch_fwd_adj(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
-hipError_t launch_adj_only(const SolveParams*, const LaunchCfg&, bool, hipStream_t);
-hipError_t launch_finalize(const SolveParams*, const LaunchCfg&, bool, void*, double*, double*, uint8_t*, int32_t*,
+hipError_t launch_init(const SolveParams*, const LaunchCfg&, hipStream_t);
+hipError_t launch_iter(int, const SolveParams*, const LaunchCfg&, hipStream_t);
+hipError_t launch_fwd_adj(const SolveParams*, const LaunchCfg&, hipStream_t);
+hipError_t launch_one(int, int, const SolveParams*, const LaunchCfg&, hipStream_t);
+hipError_t launch_adj_only(const SolveParams*, const LaunchCfg&, hipStream_t);
+hipError_t launch_finalize(const SolveParams*, const LaunchCfg&, double*, double*, double*, uint8_t*, int32_t*,
                            int32_t*, int32_t*, hipStream_t);
 hipError_t launch_lambda_out(const SolveParams*, int, double*, int32_t*, hipStream_t);
 hipError_t launch_time_out(const SolveParams*, int, long long*, hipStream_t);
-hipError_t launch_adjoint_out(const SolveParams*, int, int, int, bool, double*, void*, hipStream_t);
+hipError_t launch_adjoint_out(const SolveParams*, int, int, int, double*, double*, hipStream_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
@@ -87,7 +88,6 @@ double rounding_allowance(const sl1_dict_s& d) {
 
 struct Workspace {
     int device = 0, batch = 0, N = 0, K = 0;
-    bool f64 = false;
     int nseg_max = 0, nrc = 0, nadj_max = 0;
     void* mem = nullptr;
     SolveParams* dP = nullptr;
@@ -100,6 +100,9 @@ struct Workspace {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
+    double prof_ms[3] = {0, 0, 0};
+    long long prof_n[3] = {0, 0, 0};
+    std::vector<hipEvent_t> prof_ev;
     LaunchCfg graph_cfg{};
     std::mutex mu;
     ~Workspace() {
@@ -111,17 +114,18 @@ struct Workspace {
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
+        for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
 
 std::mutex g_ws_mu;
-std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Workspace>> g_ws;
+std::map<std::tuple<int, int, int, int>, std::unique_ptr<Workspace>> g_ws;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int make_workspace(Workspace& w) {
-    const size_t ws = w.f64 ? 8 : 4;
+    const size_t ws = 8;
     const size_t B = w.batch, K = w.K, N = w.N;
     w.nseg_max = (w.K + kSeg - 1) / kSeg;
     w.nrc = (w.N + kFwdRows - 1) / kFwdRows;
@@ -129,7 +133,9 @@ int make_workspace(Workspace& w) {
     const size_t np = w.nseg_max + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return o; };
-    const size_t o_state = take(B * sizeof(SigState));
+    const size_t o_ctrl = take(B * 2 * sizeof(Control));
+    const size_t o_sc = take(B * sizeof(Scalars));
+    const size_t o_fin = take(B * sizeof(Final));
     const size_t o_x = take(B * 2 * K * ws);
     const size_t o_g = take(B * 2 * K * 8);
     const size_t o_mask = take(B * K);
@@ -138,11 +144,9 @@ int make_workspace(Workspace& w) {
     const size_t o_ap = take(B * 2 * np * 4);
     const size_t o_zp = take(B * 2 * np * 4);
     const size_t o_z = take(B * N * ws);
-    const size_t o_fp = take(B * kFwdSplits * N * 8);
     const size_t o_rp = take(B * w.nrc * 3 * 8);
     const size_t o_adp = take(B * w.nadj_max * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
-    const size_t o_ctr = take(B * (w.nrc + 3) * 4);
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
     const size_t o_times = take(B * 16);
@@ -153,20 +157,20 @@ int make_workspace(Workspace& w) {
     if (hipHostMalloc((void**)&w.h_active, 64, hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
     std::memset(w.hP, 0, sizeof(SolveParams));
     SolveParams& p = *w.hP;
-    p.state = (SigState*)(m + o_state);
-    p.x = m + o_x;
+    p.ctrl = (Control*)(m + o_ctrl);
+    p.sc = (Scalars*)(m + o_sc);
+    p.fin = (Final*)(m + o_fin);
+    p.x = (double*)(m + o_x);
     p.g = (double*)(m + o_g);
     p.mask = (uint8_t*)(m + o_mask);
     p.act = (int*)(m + o_act);
     p.nz = (int*)(m + o_nz);
     p.act_pre = (int*)(m + o_ap);
     p.nz_pre = (int*)(m + o_zp);
-    p.z = m + o_z;
-    p.fwd_part = (double*)(m + o_fp);
+    p.z = (double*)(m + o_z);
     p.res_part = (double*)(m + o_rp);
     p.adj_part = (double*)(m + o_adp);
     p.upd_part = (double*)(m + o_up);
-    p.counters = (unsigned*)(m + o_ctr);
     p.active_signals = (int*)(m + o_act_sig);
     p.nseg_max = w.nseg_max;
     p.nrc = w.nrc;
@@ -185,9 +189,9 @@ int make_workspace(Workspace& w) {
     return SL1_OK;
 }
 
-int get_workspace(int device, int batch, int N, int K, bool f64, Workspace** out) {
+int get_workspace(int device, int batch, int N, int K, Workspace** out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    auto key = std::make_tuple(device, batch, N, K, (int)f64);
+    auto key = std::make_tuple(device, batch, N, K);
     auto it = g_ws.find(key);
     if (it != g_ws.end()) {
         *out = it->second.get();
@@ -203,7 +207,6 @@ int get_workspace(int device, int batch, int N, int K, bool f64, Workspace** out
     w->batch = batch;
     w->N = N;
     w->K = K;
-    w->f64 = f64;
     int st = make_workspace(*w);
     if (st != SL1_OK) return st;
     *out = w.get();
@@ -240,9 +243,9 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     c.nseg_max = w.nseg_max;
     c.nrc = w.nrc;
     c.nadj_max = w.nadj_max;
-    const size_t ws = w.f64 ? 8 : 4;
+    const size_t ws = 8;
     const size_t pre = ((size_t)(w.nseg_max + 1) * 4 + 15) & ~(size_t)15;
-    c.lds_fwd = pre + kBlock * 4 + 16 + kBlock * 8;
+    c.lds_fwd = 2 * (size_t)(w.nseg_max + 1) * 4 + kFwdBlock * 4 + 16 + kFwdBlock * 8 + 16 * kFwdRows * 8;
     c.lds_upd = pre;
     size_t extra = 0;
     for (int i = 0; i < p.n_stages; ++i) {
@@ -273,10 +276,10 @@ int current_device(int* dev) {
 }
 
 // Common validation of a stage sequence; fills the host params.
-int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc, int work_dtype, SolveParams& p) {
+int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc, int y_dtype, SolveParams& p) {
     if (!seq || n_stages < 1) return SL1_EINVAL;
     if (n_stages > SL1_MAX_STAGES) return SL1_ELIMIT;
-    if (work_dtype != SL1_F64 && work_dtype != SL1_F32) return SL1_EDTYPE;
+    if (y_dtype != SL1_F64 && y_dtype != SL1_F32) return SL1_EDTYPE;
     const sl1_dict_s* d0 = seq[0];
     if (!d0) return SL1_EINVAL;
     int n1_max = 0;
@@ -284,8 +287,6 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
         const sl1_dict_s* d = seq[i];
         if (!d) return SL1_EINVAL;
         if (d->N != d0->N || d->K != d0->K || d->device != d0->device) return SL1_ESHAPE;
-        if (work_dtype == SL1_F64 && d->dtype != SL1_F64) return SL1_EDTYPE;
-        if (work_dtype == SL1_F32 && d->dtype == SL1_F64) return SL1_EDTYPE;
         const double Li = L ? L[i] : 0.0;
         if (!(Li > 0.0) || !std::isfinite(Li)) return SL1_EINVAL;
         const double rci = rc ? rc[i] : d->rc_model;
@@ -296,7 +297,7 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
     p.n_stages = n_stages;
     p.N = (int)d0->N;
     p.K = (int)d0->K;
-    p.work_f64 = work_dtype == SL1_F64;
+    p.y_f64 = y_dtype == SL1_F64;
     p.n1_max = n1_max;
     return SL1_OK;
 }
@@ -329,7 +330,7 @@ int sl1_opts_default(sl1_opts* o) {
     o->tol = 1e-6;
     o->margin = 1e-12;
     o->max_iter = 100000;
-    o->work_dtype = SL1_F32;
+    o->y_dtype = SL1_F32;
     o->chunk = 16;
     o->flags = 0;
     o->trace = nullptr;
@@ -375,7 +376,7 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
     if (!out || !A || !eps || N < 1 || K < 1) return SL1_EINVAL;
     *out = nullptr;
     if (dtype_size(dtype) == 0) return SL1_EDTYPE;
-    if (N % 4 != 0 || N > kMaxN || K > (int64_t)1 << 30) return SL1_ELIMIT;
+    if (N % 4 != 0 || N > kMaxN || K > (int64_t)kMaxSeg * kSeg) return SL1_ELIMIT;
     hipStream_t s = (hipStream_t)stream;
     auto d = std::make_unique<sl1_dict_s>();
     HIP_TRY(hipGetDevice(&d->device));
@@ -427,7 +428,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     if (dtype != SL1_F64 && dtype != SL1_F32 && dtype != SL1_BF16) return SL1_EDTYPE;
     if (n1 % 16 || k1 % 16 || n2 % 16 || k2 % 16) return SL1_ELIMIT;
     const int64_t N = (int64_t)n1 * n2, K = (int64_t)k1 * k2;
-    if (N > kMaxN || n1 > (dtype == SL1_F64 ? 128 : 256) || K > (int64_t)1 << 30) return SL1_ELIMIT;
+    if (N > kMaxN || n1 > (dtype == SL1_F64 ? 128 : 256) || K > (int64_t)kMaxSeg * kSeg) return SL1_ELIMIT;
     hipStream_t s = (hipStream_t)stream;
     auto d = std::make_unique<sl1_dict_s>();
     HIP_TRY(hipGetDevice(&d->device));
@@ -526,7 +527,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
 }
 
 int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc, const double* atom_norm,
-              int64_t batch, const void* y, const double* lambda, const sl1_opts* opt, void* x, double* gap,
+              int64_t batch, const void* y, const double* lambda, const sl1_opts* opt, double* x, double* gap,
               double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage, void* stream) {
     sl1_opts o;
     if (opt) o = *opt;
@@ -537,14 +538,14 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (o.trace && o.trace_cap < 0) return SL1_EINVAL;
     SolveParams tmp;
     std::memset(&tmp, 0, sizeof(tmp));
-    int st = prepare(seq, n_stages, L, rc, o.work_dtype, tmp);
+    int st = prepare(seq, n_stages, L, rc, o.y_dtype, tmp);
     if (st != SL1_OK) return st;
     if (seq[n_stages - 1]->eps_max_in != 0.0) return SL1_EINVAL;   // the last stage must be A
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     if (dev != seq[0]->device) return SL1_EINVAL;
     Workspace* w = nullptr;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, tmp.work_f64 != 0, &w);
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
     if (st != SL1_OK) return st;
     std::lock_guard<std::mutex> lk(w->mu);
     SolveParams& p = *w->hP;
@@ -553,7 +554,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.N = tmp.N;
     p.K = tmp.K;
     p.batch = (int)batch;
-    p.work_f64 = tmp.work_f64;
+    p.y_f64 = tmp.y_f64;
     p.n1_max = tmp.n1_max;
     p.max_iter = o.max_iter;
     p.trace = o.trace;
@@ -568,14 +569,14 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     LaunchCfg cfg = launch_cfg(*w, p);
     st = check_lds(cfg);
     if (st != SL1_OK) return st;
-    const bool f64 = p.work_f64 != 0;
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
-    HIP_TRY(launch_init(w->dP, cfg, f64, w->stream));
-    const int chunk = o.chunk > 0 ? o.chunk : 16;
+    HIP_TRY(launch_init(w->dP, cfg, w->stream));
+    // iterations alternate between the two control slots: chunks have even length
+    const int chunk = o.chunk > 0 ? ((o.chunk + 1) & ~1) : 16;
     const bool use_graph = !(o.flags & SL1_FLAG_NO_GRAPH);
     if (use_graph && (!w->graph || w->graph_chunk != chunk || !cfg_equal(cfg, w->graph_cfg))) {
         if (w->graph) {
@@ -588,7 +589,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < chunk; ++k) {
-            if (launch_iter(w->dP, cfg, f64, cs) != hipSuccess) {
+            if (launch_iter(k & 1, w->dP, cfg, cs) != hipSuccess) {
                 (void)hipStreamEndCapture(cs, &g);
                 (void)hipStreamDestroy(cs);
                 return SL1_EHIP;
@@ -607,18 +608,48 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     }
     long long launched = 0;
     const long long cap = (long long)o.max_iter + 2LL * chunk + 4;
+    const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
+    if (prof) {
+        // one event before and after every kernel of a chunk
+        while ((int)w->prof_ev.size() < 6 * chunk) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            w->prof_ev.push_back(e);
+        }
+        for (int k = 0; k < 3; ++k) {
+            w->prof_ms[k] = 0.0;
+            w->prof_n[k] = 0;
+        }
+    }
     for (;;) {
-        if (use_graph) {
+        if (prof) {
+            for (int it = 0; it < chunk; ++it)
+                for (int k = 0; k < 3; ++k) {
+                    HIP_TRY(hipEventRecord(w->prof_ev[6 * it + 2 * k], w->stream));
+                    HIP_TRY(launch_one(k, it & 1, w->dP, cfg, w->stream));
+                    HIP_TRY(hipEventRecord(w->prof_ev[6 * it + 2 * k + 1], w->stream));
+                }
+        } else if (use_graph) {
             HIP_TRY(hipGraphLaunch(w->graph, w->stream));
         } else {
-            for (int k = 0; k < chunk; ++k) HIP_TRY(launch_iter(w->dP, cfg, f64, w->stream));
+            for (int k = 0; k < chunk; ++k) HIP_TRY(launch_iter(k & 1, w->dP, cfg, w->stream));
         }
         launched += chunk;
+        if (prof) {
+            HIP_TRY(hipStreamSynchronize(w->stream));
+            for (int it = 0; it < chunk; ++it)
+                for (int k = 0; k < 3; ++k) {
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, w->prof_ev[6 * it + 2 * k], w->prof_ev[6 * it + 2 * k + 1]));
+                    w->prof_ms[k] += ms;
+                    w->prof_n[k] += 1;
+                }
+        }
         HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (*w->h_active <= 0 || launched > cap) break;
     }
-    HIP_TRY(launch_finalize(w->dP, cfg, f64, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
+    HIP_TRY(launch_finalize(w->dP, cfg, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
     std::vector<int32_t> hs(batch);
     HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -633,20 +664,20 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     return result;
 }
 
-static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* lam_out, double* g_out,
-                       void* z_out, void* stream) {
+static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* lam_out, double* g_out,
+                       double* z_out, void* stream) {
     if (!d || !y || batch < 1) return SL1_EINVAL;
     sl1_dict seq[1] = {d};
     double L = 1.0;
     SolveParams tmp;
     std::memset(&tmp, 0, sizeof(tmp));
-    int st = prepare(seq, 1, &L, nullptr, work_dtype, tmp);
+    int st = prepare(seq, 1, &L, nullptr, y_dtype, tmp);
     if (st != SL1_OK) return st;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     if (dev != d->device) return SL1_EINVAL;
     Workspace* w = nullptr;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, tmp.work_f64 != 0, &w);
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
     if (st != SL1_OK) return st;
     std::lock_guard<std::mutex> lk(w->mu);
     SolveParams& p = *w->hP;
@@ -655,7 +686,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int work_dtype,
     p.N = tmp.N;
     p.K = tmp.K;
     p.batch = (int)batch;
-    p.work_f64 = tmp.work_f64;
+    p.y_f64 = tmp.y_f64;
     p.n1_max = tmp.n1_max;
     p.max_iter = 0;
     p.trace = nullptr;
@@ -670,18 +701,17 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int work_dtype,
     LaunchCfg cfg = launch_cfg(*w, p);
     st = check_lds(cfg);
     if (st != SL1_OK) return st;
-    const bool f64 = p.work_f64 != 0;
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
-    HIP_TRY(launch_init(w->dP, cfg, f64, w->stream));
-    HIP_TRY(launch_fwd_adj(w->dP, cfg, f64, w->stream));
+    HIP_TRY(launch_init(w->dP, cfg, w->stream));
+    HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));
     // the per-signal status always comes back; lambda'_max lands in scratch when not asked for
     double* lam_dst = lam_out ? lam_out : (double*)w->d_times;
     HIP_TRY(launch_lambda_out(w->dP, (int)batch, lam_dst, w->d_status, w->stream));
-    if (g_out) HIP_TRY(launch_adjoint_out(w->dP, (int)batch, tmp.K, tmp.N, f64, g_out, z_out, w->stream));
+    if (g_out) HIP_TRY(launch_adjoint_out(w->dP, (int)batch, tmp.K, tmp.N, g_out, z_out, w->stream));
     std::vector<int32_t> hs(batch);
     HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -692,44 +722,39 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int work_dtype,
     return SL1_OK;
 }
 
-int sl1_lambda_max(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out, void* stream) {
+int sl1_lambda_max(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* out, void* stream) {
     if (!out) return SL1_EINVAL;
-    return lambda_pass(d, batch, y, work_dtype, out, nullptr, nullptr, stream);
+    return lambda_pass(d, batch, y, y_dtype, out, nullptr, nullptr, stream);
 }
 
-int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int work_dtype, double* out, void* z_used,
+int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* out, double* z_used,
                      void* stream) {
     if (!out) return SL1_EINVAL;
-    return lambda_pass(d, batch, y, work_dtype, nullptr, out, z_used, stream);
+    return lambda_pass(d, batch, y, y_dtype, nullptr, out, z_used, stream);
 }
 
-int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dtype, double* rc_out, void* stream) {
+int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_out, void* stream) {
     if (!seq || n_stages < 1 || !rc_out || batch < 1) return SL1_EINVAL;
     std::vector<double> Ls(n_stages, 1.0);
     SolveParams tmp;
     std::memset(&tmp, 0, sizeof(tmp));
-    int st = prepare(seq, n_stages, Ls.data(), nullptr, work_dtype, tmp);
+    int st = prepare(seq, n_stages, Ls.data(), nullptr, SL1_F64, tmp);
     if (st != SL1_OK) return st;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     Workspace* w = nullptr;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, tmp.work_f64 != 0, &w);
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
     if (st != SL1_OK) return st;
     std::lock_guard<std::mutex> lk(w->mu);
     // synthetic signals: y = 1 (any direction works, the cost does not depend on it)
     void* ybuf = nullptr;
-    const size_t ws = tmp.work_f64 ? 8 : 4;
-    if (hipMalloc(&ybuf, (size_t)batch * tmp.N * ws) != hipSuccess) return SL1_ENOMEM;
-    std::vector<unsigned char> hy((size_t)batch * tmp.N * ws);
-    for (size_t i = 0; i < (size_t)batch * tmp.N; ++i) {
-        if (ws == 8) ((double*)hy.data())[i] = 1.0;
-        else ((float*)hy.data())[i] = 1.0f;
-    }
+    if (hipMalloc(&ybuf, (size_t)batch * tmp.N * 8) != hipSuccess) return SL1_ENOMEM;
+    std::vector<double> hy((size_t)batch * tmp.N, 1.0);
     std::vector<double> times(n_stages, 0.0);
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
-    HIP_TRY(hipMemcpyAsync(ybuf, hy.data(), hy.size(), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(ybuf, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, w->stream));
     const int reps = 20;
     for (int i = 0; i < n_stages; ++i) {
         SolveParams& p = *w->hP;
@@ -739,7 +764,7 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dt
         p.N = tmp.N;
         p.K = tmp.K;
         p.batch = (int)batch;
-        p.work_f64 = tmp.work_f64;
+        p.y_f64 = tmp.y_f64;
         p.n1_max = tmp.n1_max;
         p.max_iter = 0;
         p.trace = nullptr;
@@ -752,14 +777,13 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dt
         p.lam = nullptr;
         LaunchCfg cfg = launch_cfg(*w, p);
         if ((st = check_lds(cfg)) != SL1_OK) { (void)hipFree(ybuf); return st; }
-        const bool f64 = p.work_f64 != 0;
-        HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+            HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
         HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
-        HIP_TRY(launch_init(w->dP, cfg, f64, w->stream));
-        HIP_TRY(launch_fwd_adj(w->dP, cfg, f64, w->stream));
-        for (int k = 0; k < 3; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, f64, w->stream));
+        HIP_TRY(launch_init(w->dP, cfg, w->stream));
+        HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));
+        for (int k = 0; k < 3; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, w->stream));
         HIP_TRY(hipEventRecord(w->ev_a, w->stream));
-        for (int k = 0; k < reps; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, f64, w->stream));
+        for (int k = 0; k < reps; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, w->stream));
         HIP_TRY(hipEventRecord(w->ev_b, w->stream));
         HIP_TRY(hipEventSynchronize(w->ev_b));
         float ms = 0.f;
@@ -778,13 +802,13 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, int work_dt
 // Device clock stamps (start, convergence) of each signal of the last solve of
 // this shape, for time-to-gap measurements; out: host, 2*batch int64, and the
 // clock rate in kHz.
-int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, int work_dtype, long long* out, double* rate_khz) {
+int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, double* rate_khz) {
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     Workspace* w = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
-        auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K, (int)(work_dtype == SL1_F64)));
+        auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
         if (it == g_ws.end()) return SL1_EINVAL;
         w = it->second.get();
     }
@@ -795,6 +819,20 @@ int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, int work_dtype, lo
     int khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     *rate_khz = khz;
+    return SL1_OK;
+}
+
+int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches) {
+    if (!ms || !launches) return SL1_EINVAL;
+    int dev = 0;
+    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
+    if (it == g_ws.end()) return SL1_EINVAL;
+    for (int k = 0; k < 3; ++k) {
+        ms[k] = it->second->prof_ms[k];
+        launches[k] = it->second->prof_n[k];
+    }
     return SL1_OK;
 }
 

@@ -37,10 +37,9 @@ __device__ __forceinline__ double atom_elem(const GradDict& d, int j, int i) {
     return d.scale ? v * (double)d.scale[j] : v;
 }
 
-template <typename W>
-__global__ __launch_bounds__(kBlock) void k_grad_support(const W* x, int K, int* sidx, int* cnt, double* sgn) {
+__global__ __launch_bounds__(kBlock) void k_grad_support(const double* x, int K, int* sidx, int* cnt, double* sgn) {
     const int b = blockIdx.x;
-    const W* xb = x + (size_t)b * K;
+    const double* xb = x + (size_t)b * K;
     __shared__ int s_w[4];
     __shared__ int s_base;
     if (threadIdx.x == 0) s_base = 0;
@@ -48,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_support(const W* x, int K, int*
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int j0 = 0; j0 < K; j0 += kBlock) {
         const int j = j0 + threadIdx.x;
-        const double v = j < K ? (double)xb[j] : 0.0;
+        const double v = j < K ? xb[j] : 0.0;
         const bool f = v != 0.0;
         const unsigned long long bal = __ballot(f);
         const int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -92,9 +91,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_gram(GradDict d, const int* sid
 }
 
 // In-place Cholesky G = L L^T (lower), then L L^T w = v; one block per signal.
-template <typename W>
 __global__ __launch_bounds__(kBlock) void k_grad_solve(const int* sidx, const int* cnt, const double* sgn, double* G,
-                                                      const W* dx, int K, double* wout, double* dlam, int* flag,
+                                                      const double* dx, int K, double* wout, double* dlam, int* flag,
                                                       int ld) {
     const int b = blockIdx.x;
     const int s = cnt[b];
@@ -133,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_solve(const int* sidx, const in
         if (s_bad) atomicOr(flag, 1);
         // forward: L u = v_S ; backward: L^T w = u
         for (int i = 0; i < s; ++i) {
-            double acc = (double)dx[(size_t)b * K + sidx[(size_t)b * kGradMaxSupport + i]];
+            double acc = dx[(size_t)b * K + sidx[(size_t)b * kGradMaxSupport + i]];
             for (int k = 0; k < i; ++k) acc -= Gb[(size_t)i * ld + k] * w[k];
             w[i] = acc / Gb[(size_t)i * ld + i];
         }
@@ -169,12 +167,12 @@ extern "C" int sl1_grad_impl_dense_info(sl1_dict_s* d, int* kind, int* dtype, in
 
 using namespace sl1;
 
-extern "C" int sl1_grad(sl1_dict A, int64_t batch, const void* x, const void* y, const double* lambda,
-                        const void* dx, void* dy, double* dlambda, int work_dtype, void* stream) {
+extern "C" int sl1_grad(sl1_dict A, int64_t batch, const double* x, const void* y, const double* lambda,
+                        const double* dx, void* dy, double* dlambda, int y_dtype, void* stream) {
     (void)y;
     (void)lambda;
     if (!A || !x || !dx || !dy || !dlambda || batch < 1) return SL1_EINVAL;
-    if (work_dtype != SL1_F64 && work_dtype != SL1_F32) return SL1_EDTYPE;
+    if (y_dtype != SL1_F64 && y_dtype != SL1_F32) return SL1_EDTYPE;
     int kind = 0, dtype = 0;
     int64_t N = 0, K = 0;
     const void* Ap = nullptr;
@@ -199,10 +197,9 @@ extern "C" int sl1_grad(sl1_dict A, int64_t batch, const void* x, const void* y,
         return code;
     };
     GradDict gd{dtype, (int)N, (int)K, Ap, sc};
-    const bool f64 = work_dtype == SL1_F64;
+    const bool f64 = y_dtype == SL1_F64;
     if (hipMemsetAsync(flag, 0, 4, s) != hipSuccess) return fail(SL1_EHIP);
-    if (f64) hipLaunchKernelGGL(k_grad_support<double>, dim3(B), dim3(kBlock), 0, s, (const double*)x, (int)K, sidx, cnt, sgn);
-    else hipLaunchKernelGGL(k_grad_support<float>, dim3(B), dim3(kBlock), 0, s, (const float*)x, (int)K, sidx, cnt, sgn);
+    hipLaunchKernelGGL(k_grad_support, dim3(B), dim3(kBlock), 0, s, x, (int)K, sidx, cnt, sgn);
     std::vector<int> hc(B);
     if (hipMemcpyAsync(hc.data(), cnt, B * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(SL1_EHIP);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(SL1_EHIP);
@@ -216,8 +213,7 @@ extern "C" int sl1_grad(sl1_dict A, int64_t batch, const void* x, const void* y,
     double* G = (double*)mem2;
     double* wv = G + B * (size_t)ld * ld;
     hipLaunchKernelGGL(k_grad_gram, dim3(smax, B), dim3(kBlock), N * 8, s, gd, sidx, cnt, G, ld);
-    if (f64) hipLaunchKernelGGL(k_grad_solve<double>, dim3(B), dim3(kBlock), 0, s, sidx, cnt, sgn, G, (const double*)dx, (int)K, wv, dlambda, flag, ld);
-    else hipLaunchKernelGGL(k_grad_solve<float>, dim3(B), dim3(kBlock), 0, s, sidx, cnt, sgn, G, (const float*)dx, (int)K, wv, dlambda, flag, ld);
+    hipLaunchKernelGGL(k_grad_solve, dim3(B), dim3(kBlock), 0, s, sidx, cnt, sgn, G, dx, (int)K, wv, dlambda, flag, ld);
     if (f64) hipLaunchKernelGGL(k_grad_dy<double>, dim3((N + kBlock - 1) / kBlock, B), dim3(kBlock), 0, s, gd, sidx, cnt, wv, (double*)dy, ld);
     else hipLaunchKernelGGL(k_grad_dy<float>, dim3((N + kBlock - 1) / kBlock, B), dim3(kBlock), 0, s, gd, sidx, cnt, wv, (float*)dy, ld);
     if (hipGetLastError() != hipSuccess) return fail(SL1_EHIP);

@@ -12,11 +12,11 @@ constexpr int kBlock = 256;         // threads per block (4 waves)
 constexpr int kWave = 64;
 constexpr int kSeg = 256;           // atoms per segment of a compacted list (one update block)
 constexpr int kAdjAtoms = 64;       // atoms per dense-adjoint block (16 per wave)
-constexpr int kFwdRows = 1024;      // rows per forward block (4 per thread)
-constexpr int kFwdSplits = 16;      // most column splits of the forward gather
-constexpr int kFwdMinPerSplit = 16; // fewest nonzeros per split
+constexpr int kFwdRows = 256;       // rows per forward block (4 per lane)
+constexpr int kFwdBlock = 1024;     // forward block: 16 waves share the nonzeros of x
+constexpr int kMaxSeg = 1024;       // segments of a compacted list (K <= 262144)
 constexpr int kKronColTile = 64;    // atoms (j1) per Kronecker-adjoint block (16 per wave)
-constexpr int kMaxN = 16384;
+constexpr int kMaxN = 8192;
 
 enum Kind { kDense = 0, kKron = 1 };
 
@@ -34,51 +34,62 @@ struct StageDesc {
     double at_norm_max, eps_max;
 };
 
-// Per-signal control and scalar state.  Written by the "last block" of a
-// kernel (after every other block of the signal has finished) or by the
-// initialisation kernel; read at kernel start.
-struct SigState {
+// Iteration state C_t of one signal.  Double-buffered by iteration parity:
+// the forward kernel of iteration t reads C_{t-1} from slot (t-1)%2, folds in
+// the per-block results of iteration t-1 and (block 0 only) writes C_t to slot
+// t%2; every later kernel of iteration t reads slot t%2.
+struct Control {
     int stage, iter, done, status;
-    int ksince, par;          // iterations since (re)start; parity of the current buffers
-    int n_act, n_nz;          // |A_t| and ||x_t||_0 (sizes of the current compacted lists)
-    int nseg_act, nseg_nz;    // segments of the current lists
-    int conv, Kt;
-    int n_keep, pad0;
-    double lam;
-    double tau, tau_next, beta;
-    double l1;                // ||x_t||_1
-    double r2, zz, yz;        // ||y - A~x||^2, ||z||^2, y^T z with z the stored residual
-    double mp, mt, E;         // max(|g|+eps||z||), max|g|, max eps over A_t
-    double sp, st;            // s' and s~: theta' = s' z, theta~ = s~ z
+    int ksince, par, advance, pad0;   // advance: the next iteration folds this one's results
+    int n_act, n_nz, nseg_act, nseg_nz;
+    double lam, tau, l1;              // lambda, FISTA momentum sequence, ||x_t||_1
+    long long t0;
+};
+
+// FP64 quantities of iteration t (Section III-C, Theorem 1, Section IV-A),
+// computed identically by every block of the update kernel; block 0 stores them.
+struct Scalars {
+    double r2, zz, yz;                // ||y - A~x||^2, ||z||^2, y^T z (z: stored residual direction)
+    double mp, mt, E;                 // max(|g|+eps||z||), max|g|, max eps over A_t
+    double sp, st;                    // theta' = s' z, theta~ = s~ z
     double P, Gp, Gt, delta, Rp, gamma;
-    double c1, c2;            // |s'| and |s'| ||z||: test coefficients
-    long long t0, tconv;      // wall-clock stamps (start, convergence)
+    double c1, c2;                    // |s'| and |s'| ||z||
+    double beta, tau_next;
+    int conv, pad0;                   // 1 converged on A, 2 iteration cap
+    long long tconv;
+};
+
+// Outcome of a finished signal.
+struct Final {
+    double gap, gap_cert;
+    int iters, stage, status, par;
+    long long t0, tconv;
 };
 
 struct SolveParams {
     int n_stages, N, K, batch;
-    int max_iter, trace_cap, work_f64, lambda_only;
+    int max_iter, trace_cap, y_f64, lambda_only;
     double Gamma, tol, margin;
     StageDesc st[SL1_MAX_STAGES];
     const double* atom_norm;
-    const void* y;            // batch x N (work type)
+    const void* y;            // batch x N, FP32 or FP64 (y_f64)
     const double* lam;        // batch
     double* trace;
-    // workspace (per signal b, arrays at base + b * stride)
-    SigState* state;
-    void* x;                  // [batch][2][K] work type
+    // workspace (per signal b)
+    Control* ctrl;            // [batch][2]
+    Scalars* sc;              // [batch]
+    Final* fin;               // [batch]
+    double* x;                // [batch][2][K]
     double* g;                // [batch][2][K]
     uint8_t* mask;            // [batch][K]
     int* act;                 // [batch][2][K]
     int* nz;                  // [batch][2][K]
     int* act_pre;             // [batch][2][nseg_max+1]
     int* nz_pre;              // [batch][2][nseg_max+1]
-    void* z;                  // [batch][N] work type
-    double* fwd_part;         // [batch][kFwdSplits][N]
+    double* z;                // [batch][N]
     double* res_part;         // [batch][nrc][3]
     double* adj_part;         // [batch][nadj_max][3]
     double* upd_part;         // [batch][nseg_max][4]
-    unsigned* counters;       // [batch][nrc + 3]
     int* active_signals;      // one int: signals not yet done
     int nseg_max, nrc, nadj_max, n1_max;
 };

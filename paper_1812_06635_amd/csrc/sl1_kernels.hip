@@ -12,10 +12,14 @@
 //   k_upd  per-atom stable GAP test, look-ahead count, FISTA step with soft
 //          thresholding, compaction of the preserved set and of the nonzeros
 //          (wavefront ballot + prefix), then Algorithm 2 and momentum update.
-// Reductions across blocks use the "last block" pattern: every block writes a
-// partial, fences, and bumps a per-signal counter; the block that arrives last
-// reduces the partials in a fixed order (deterministic) and resets the counter.
-// No block ever waits for another, so no launch can hang.
+// No block communicates with another block of the same launch: every block
+// writes its partial results, and the consumers in the NEXT launch reduce them
+// in a fixed order (deterministic; the kernel boundary makes them visible
+// across the chip's XCDs without any in-kernel cache write-back).  Quantities
+// needed by every block of a launch (the FP64 scalar block, the prefix counts
+// of the compacted lists, the switching decision) are recomputed identically by
+// each block; one designated block stores them.  No block ever waits for
+// another, so no launch can hang.
 #include <algorithm>
 
 #include "sl1_internal.hpp"
@@ -34,9 +38,13 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // workspace accessors
 // ---------------------------------------------------------------------------
-template <typename W>
-__device__ __forceinline__ W* xbuf(const SolveParams* P, int b, int par) {
-    return (W*)P->x + ((size_t)b * 2 + par) * P->K;
+__device__ __forceinline__ double* xbuf(const SolveParams* P, int b, int par) {
+    return P->x + ((size_t)b * 2 + par) * P->K;
+}
+// signal value y_b[i] (FP32 or FP64 input)
+__device__ __forceinline__ double yval(const SolveParams* P, int b, int i) {
+    const size_t k = (size_t)b * P->N + i;
+    return P->y_f64 ? ((const double*)P->y)[k] : (double)((const float*)P->y)[k];
 }
 __device__ __forceinline__ double* gbuf(const SolveParams* P, int b, int par) {
     return P->g + ((size_t)b * 2 + par) * P->K;
@@ -53,59 +61,67 @@ __device__ __forceinline__ int* actpre(const SolveParams* P, int b, int par) {
 __device__ __forceinline__ int* nzpre(const SolveParams* P, int b, int par) {
     return P->nz_pre + ((size_t)b * 2 + par) * (P->nseg_max + 1);
 }
-__device__ __forceinline__ unsigned* ctr(const SolveParams* P, int b, int k) {
-    return P->counters + (size_t)b * (P->nrc + 3) + k;
-}
 
-// Last-block arrival.  Every thread fences its own partial-result stores, the
-// block synchronises, thread 0 increments the counter; the block that brings it
-// to `expected` is the last one, resets it, and acquires before reading.
-__device__ __forceinline__ bool arrive_last(unsigned* c, unsigned expected) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(c, 1u);
-        s_last = (prev + 1 == expected);
-        if (s_last) atomicExch(c, 0u);
-    }
-    __syncthreads();
-    const bool last = s_last != 0;
-    if (last) __threadfence();
-    return last;
-}
-
+// block-wide sums / maxima of NV values, fixed order (red: LDS, NV*16 doubles)
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS, NV*4 */) {
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
     __syncthreads();
     if (l == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) red[k * 4 + w] = v[k];
+        for (int k = 0; k < NV; ++k) red[k * 16 + w] = v[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+    for (int k = 0; k < NV; ++k) {
+        double a = 0.0;
+        for (int q = 0; q < nw; ++q) a += red[k * 16 + q];
+        v[k] = a;
+    }
     __syncthreads();
 }
 
 template <int NV>
 __device__ __forceinline__ void block_max(double (&v)[NV], double* red) {
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = wave_max(v[k]);
     __syncthreads();
     if (l == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) red[k * 4 + w] = v[k];
+        for (int k = 0; k < NV; ++k) red[k * 16 + w] = v[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-        v[k] = fmax(fmax(red[k * 4 + 0], red[k * 4 + 1]), fmax(red[k * 4 + 2], red[k * 4 + 3]));
+    for (int k = 0; k < NV; ++k) {
+        double a = red[k * 16];
+        for (int q = 1; q < nw; ++q) a = fmax(a, red[k * 16 + q]);
+        v[k] = a;
+    }
     __syncthreads();
+}
+
+// exclusive block-wide prefix of per-thread integer counts; returns the total
+__device__ __forceinline__ int block_excl_scan(int v, int& excl, int* s_tmp /* LDS, 16 ints */) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_tmp[w] = incl;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int q = 0; q < nw; ++q) {
+        if (q < w) base += s_tmp[q];
+        total += s_tmp[q];
+    }
+    excl = base + incl - v;
+    __syncthreads();
+    return total;
 }
 
 __device__ __forceinline__ void load_pre(int* s_pre, const int* pre, int nseg) {
@@ -123,15 +139,16 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {  // f already bf16-exac
 }
 
 // ---------------------------------------------------------------------------
-// initialisation: x_0 = 0, A_0 = {1..K}, stage 0 (Algorithm 1, Initialize)
+// initialisation: x_0 = 0, A_0 = {1..K}, stage 0 (Algorithm 1, Initialize).
+// C_0 goes to slot 1 with advance = 0, so the forward kernel of iteration 0
+// (slot 0) takes it as is.
 // ---------------------------------------------------------------------------
-template <typename W>
 __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__ P) {
     const int b = blockIdx.y, c = blockIdx.x, K = P->K;
     const int j = c * kSeg + threadIdx.x;
     if (j < K) {
-        xbuf<W>(P, b, 0)[j] = W(0);
-        xbuf<W>(P, b, 1)[j] = W(0);
+        xbuf(P, b, 0)[j] = 0.0;
+        xbuf(P, b, 1)[j] = 0.0;
         gbuf(P, b, 0)[j] = 0.0;
         gbuf(P, b, 1)[j] = 0.0;
         P->mask[(size_t)b * K + j] = 1;
@@ -141,55 +158,130 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
     const int nseg = (K + kSeg - 1) / kSeg;
     int* ap = actpre(P, b, 0);
     for (int s = threadIdx.x; s <= nseg; s += kBlock) ap[s] = min(s * kSeg, K);
-    // validate the signal and lambda
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const W* y = (const W*)P->y + (size_t)b * P->N;
     int bad = 0;
-    for (int i = threadIdx.x; i < P->N; i += kBlock) bad |= !isfinite((double)y[i]);
+    for (int i = threadIdx.x; i < P->N; i += kBlock) bad |= !isfinite(yval(P, b, i));
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         const double lam = P->lam ? P->lam[b] : 1.0;
-        SigState* S = P->state + b;
         const bool ok = !s_bad && lam > 0.0 && isfinite(lam);
-        S->stage = 0;
-        S->iter = 0;
-        S->done = ok ? 0 : 1;
-        S->status = ok ? SL1_OK : SL1_EINVAL;
-        S->ksince = 0;
-        S->par = 0;
-        S->n_act = K;
-        S->n_nz = 0;
-        S->nseg_act = nseg;
-        S->nseg_nz = 0;
-        S->conv = 0;
-        S->Kt = K;
-        S->n_keep = K;
-        S->lam = lam;
-        S->tau = 1.0;
-        S->tau_next = 1.0;
-        S->beta = 0.0;
-        S->l1 = 0.0;
-        S->r2 = S->zz = S->yz = 0.0;
-        S->mp = S->mt = S->E = 0.0;
-        S->sp = S->st = 0.0;
-        S->P = S->Gp = S->Gt = S->delta = S->Rp = 0.0;
-        S->gamma = 1.0;
-        S->c1 = S->c2 = 0.0;
-        S->t0 = wall_clock64();
-        S->tconv = 0;
+        Control C;
+        C.stage = 0;
+        C.iter = 0;
+        C.done = ok ? 0 : 1;
+        C.status = ok ? SL1_OK : SL1_EINVAL;
+        C.ksince = 0;
+        C.par = 0;
+        C.advance = 0;
+        C.pad0 = 0;
+        C.n_act = K;
+        C.n_nz = 0;
+        C.nseg_act = nseg;
+        C.nseg_nz = 0;
+        C.lam = lam;
+        C.tau = 1.0;
+        C.l1 = 0.0;
+        C.t0 = wall_clock64();
+        P->ctrl[2 * b + 0] = C;
+        P->ctrl[2 * b + 1] = C;
         nzpre(P, b, 0)[0] = 0;
-        for (int k = 0; k < P->nrc + 3; ++k) *ctr(P, b, k) = 0u;
+        Final F;
+        F.gap = 0.0;
+        F.gap_cert = 0.0;
+        F.iters = 0;
+        F.stage = 0;
+        F.status = C.status;
+        F.par = 0;
+        F.t0 = C.t0;
+        F.tconv = 0;
+        P->fin[b] = F;
         if (ok) atomicAdd(P->active_signals, 1);
     }
 }
 
-// ---------------------------------------------------------------------------
-// forward product + residual (Section III-C: rho~_t = y - A~ x_t)
-// ---------------------------------------------------------------------------
-template <typename W>
+// Algorithm 2 (SwitchDictionary): speed criterion first, then gap saturation.
+__device__ __forceinline__ int switch_dictionary(int i, int I, double gamma, double Gamma, double K_t, double rc,
+                                                 double K) {
+    if (i >= I) return I;
+    if (K_t <= rc * K) return I;
+    if (gamma <= Gamma) return i + 1;
+    return i;
+}
+
+// C_t from C_{t-1}, the scalars of iteration t-1 and the update kernel's
+// per-block partials; also the prefix counts of the two new compacted lists
+// (into LDS).  Identical in every block; returns 1 when the signal finished.
+__device__ int advance_control(const SolveParams* P, int b, const Control& Cp, Control& C, int* s_apre,
+                               int* s_zpre, double* s_red, int* s_tmp, Scalars& S) {
+    C = Cp;
+    if (!Cp.advance) return 0;
+    S = P->sc[b];
+    if (S.conv) return 1;
+    const int nblk = max(1, (Cp.n_act + kSeg - 1) / kSeg);
+    // prefix counts over the update blocks (segment k = update block k)
+    int ak_tot = 0, az_tot = 0;
+    double kt = 0.0, l1 = 0.0;
+    for (int base = 0; base < nblk; base += blockDim.x) {
+        const int k = base + threadIdx.x;
+        int ck = 0, cz = 0;
+        double a = 0.0, d = 0.0;
+        if (k < nblk) {
+            const double* up = P->upd_part + ((size_t)b * P->nseg_max + k) * 4;
+            ck = (int)up[0];
+            cz = (int)up[1];
+            a = up[2];
+            d = up[3];
+        }
+        int ek, ez;
+        const int tk = block_excl_scan(ck, ek, s_tmp);
+        const int tz = block_excl_scan(cz, ez, s_tmp);
+        if (k < nblk) {
+            s_apre[k] = ak_tot + ek;
+            s_zpre[k] = az_tot + ez;
+        }
+        ak_tot += tk;
+        az_tot += tz;
+        double v[2] = {a, d};
+        block_sum<2>(v, s_red);
+        kt += v[0];
+        l1 += v[1];
+    }
+    if (threadIdx.x == 0) {
+        s_apre[nblk] = ak_tot;
+        s_zpre[nblk] = az_tot;
+    }
+    __syncthreads();
+    const int I = P->n_stages - 1;
+    const StageDesc& st = P->st[Cp.stage];
+    const int i_new = switch_dictionary(Cp.stage, I, S.gamma, P->Gamma, kt, st.rc, (double)P->K);
+    if (i_new != Cp.stage) {
+        C.stage = i_new;
+        C.ksince = 0;
+        C.tau = 1.0;
+    } else {
+        C.ksince = Cp.ksince + 1;
+        C.tau = S.tau_next;
+    }
+    C.iter = Cp.iter + 1;
+    C.par = 1 - Cp.par;
+    C.n_act = ak_tot;
+    C.n_nz = az_tot;
+    C.nseg_act = nblk;
+    C.nseg_nz = nblk;
+    C.l1 = l1;
+    // trace row of iteration t-1 (Algorithm 1 quantities)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P->trace && Cp.iter < P->trace_cap) {
+        double* tr = P->trace + ((size_t)b * P->trace_cap + Cp.iter) * SL1_TRACE_FIELDS;
+        tr[0] = Cp.iter; tr[1] = Cp.stage; tr[2] = Cp.n_act; tr[3] = ak_tot; tr[4] = kt;
+        tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = S.Rp; tr[9] = S.gamma;
+        tr[10] = Cp.l1; tr[11] = S.P;
+    }
+    return 0;
+}
+
 __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j, double xj, int r0,
                                                double (&acc)[4]) {
     if (st.kind == kDense) {
@@ -256,98 +348,129 @@ __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j
     }
 }
 
-template <typename W>
-__global__ __launch_bounds__(kBlock) void k_fwd(const SolveParams* __restrict__ P) {
+
+// ---------------------------------------------------------------------------
+// forward product and residual (Section III-C: rho~_t = y - A~ x_t)
+// grid (ceil(N/256), batch), 1024 threads: 16 waves share the nonzeros of x_t
+// for the same 256 rows and reduce in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.y;
-    SigState* S = P->state + b;
-    if (S->done) return;
-    const int N = P->N, nrc = P->nrc;
-    const int rc = blockIdx.x % nrc, split = blockIdx.x / nrc;
-    const int nnz = S->n_nz;
-    int nsplit = (nnz + kFwdMinPerSplit - 1) / kFwdMinPerSplit;
-    nsplit = max(1, min(kFwdSplits, nsplit));
-    if (split >= nsplit) return;
-    const int per = (nnz + nsplit - 1) / nsplit;
-    const int i0 = min(nnz, split * per), i1 = min(nnz, i0 + per);
-    const int par = S->par;
-    const StageDesc& st = P->st[S->stage];
+    const int prev = 1 - slot;
+    const Control Cp = P->ctrl[2 * b + prev];
+    if (Cp.done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) P->ctrl[2 * b + slot] = Cp;
+        return;
+    }
+    const int N = P->N;
+    const int nseg1 = P->nseg_max + 1;
+    int* s_apre = (int*)smem;
+    int* s_zpre = s_apre + nseg1;
+    int* s_j = s_zpre + nseg1;
+    double* s_x = (double*)(((uintptr_t)(s_j + kFwdBlock) + 15) & ~(uintptr_t)15);
+    double* s_u = s_x + kFwdBlock;                      // [16 waves][256 rows]
+    __shared__ double s_red[48];
+    __shared__ int s_tmp[16];
 
-    int* s_pre = (int*)smem;
-    int* s_j = s_pre + (P->nseg_max + 1);
-    double* s_x = (double*)(((uintptr_t)(s_j + kBlock) + 15) & ~(uintptr_t)15);
-    __shared__ double s_red[16];
-    load_pre(s_pre, nzpre(P, b, par), S->nseg_nz);
-    const int* nzi = nzbuf(P, b, par);
-    const W* x = xbuf<W>(P, b, par);
+    Control C;
+    Scalars S;
+    const int fin = advance_control(P, b, Cp, C, s_apre, s_zpre, s_red, s_tmp, S);
+    if (fin) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            Final F;
+            F.gap = S.Gt;
+            F.gap_cert = S.Gp + S.delta;
+            F.iters = Cp.iter;
+            F.stage = Cp.stage;
+            F.status = S.conv == 2 ? SL1_MAXITER : SL1_OK;
+            F.par = Cp.par;
+            F.t0 = Cp.t0;
+            F.tconv = S.tconv;
+            P->fin[b] = F;
+            Control D = Cp;
+            D.done = 1;
+            D.advance = 0;
+            P->ctrl[2 * b + slot] = D;
+            atomicSub(P->active_signals, 1);
+        }
+        return;
+    }
+    if (!Cp.advance) {
+        // first iteration: the lists were written by the initialisation
+        const int* zp = nzpre(P, b, C.par);
+        for (int s = threadIdx.x; s <= C.nseg_nz; s += kFwdBlock) s_zpre[s] = zp[s];
+        __syncthreads();
+    } else if (blockIdx.x == 0) {
+        int* ap = actpre(P, b, C.par);
+        int* zp = nzpre(P, b, C.par);
+        for (int s = threadIdx.x; s <= C.nseg_act; s += kFwdBlock) {
+            ap[s] = s_apre[s];
+            zp[s] = s_zpre[s];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Control D = C;
+        D.advance = 1;
+        P->ctrl[2 * b + slot] = D;
+    }
 
-    const int r0 = rc * kFwdRows + threadIdx.x * 4;
+    const StageDesc& st = P->st[C.stage];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r0 = blockIdx.x * kFwdRows + lane * 4;
+    const int* nzi = nzbuf(P, b, C.par);
+    const double* x = xbuf(P, b, C.par);
+    const int nnz = C.n_nz;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int base = i0; base < i1; base += kBlock) {
-        const int cnt = min(kBlock, i1 - base);
+    for (int base = 0; base < nnz; base += kFwdBlock) {
+        const int cnt = min(kFwdBlock, nnz - base);
         if ((int)threadIdx.x < cnt) {
-            const int j = list_get(nzi, s_pre, S->nseg_nz, base + threadIdx.x);
+            const int j = list_get(nzi, s_zpre, C.nseg_nz, base + threadIdx.x);
             s_j[threadIdx.x] = j;
-            s_x[threadIdx.x] = (double)x[j];
+            s_x[threadIdx.x] = x[j];
         }
         __syncthreads();
+        const int per = (cnt + 15) / 16;
+        const int k0 = w * per, k1 = min(cnt, k0 + per);
         if (r0 < N) {
-            for (int k = 0; k < cnt; ++k) fwd_accumulate<W>(st, N, s_j[k], s_x[k], r0, acc);
+            for (int k = k0; k < k1; ++k) fwd_accumulate(st, N, s_j[k], s_x[k], r0, acc);
         }
         __syncthreads();
     }
-    double* part = P->fwd_part + ((size_t)b * kFwdSplits + split) * N;
-    if (r0 < N) {
-        f64v2* pp = (f64v2*)(part + r0);
-        pp[0] = f64v2{acc[0], acc[1]};
-        pp[1] = f64v2{acc[2], acc[3]};
-    }
-    if (!arrive_last(ctr(P, b, rc), (unsigned)nsplit)) return;
-
-    // last block of this row chunk: rho = y - u, z = stored direction, partial sums
-    const bool to_bf16 = (st.kind == kKron && st.dtype == SL1_BF16);
-    double sums[3] = {0.0, 0.0, 0.0};
-    if (r0 < N) {
-        const W* y = (const W*)P->y + (size_t)b * N;
-        W* z = (W*)P->z + (size_t)b * N;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double u = 0.0;
-            for (int s = 0; s < nsplit; ++s) u += P->fwd_part[((size_t)b * kFwdSplits + s) * N + r0 + v];
-            const double yv = (double)y[r0 + v];
-            const double rho = yv - u;
-            W zw = (W)rho;
-            if (to_bf16) zw = (W)bf16_rne((float)rho);
-            z[r0 + v] = zw;
-            const double zd = (double)zw;
-            sums[0] += rho * rho;
-            sums[1] += zd * zd;
-            sums[2] += yv * zd;
-        }
+    for (int v = 0; v < 4; ++v) s_u[w * kFwdRows + lane * 4 + v] = acc[v];
+    __syncthreads();
+    // rho = y - u and the stored direction z (rho itself, or its FP32 / BF16
+    // rounding when the stage's matrix-core product takes that input type)
+    const int zround = (st.kind == kKron && st.dtype == SL1_BF16) ? 2 : ((st.kind == kKron && st.dtype == SL1_F32) ? 1 : 0);
+    double sums[3] = {0.0, 0.0, 0.0};
+    const int row = blockIdx.x * kFwdRows + threadIdx.x;
+    if (threadIdx.x < kFwdRows && row < N) {
+        double u = 0.0;
+        for (int q = 0; q < 16; ++q) u += s_u[q * kFwdRows + threadIdx.x];
+        const double yv = yval(P, b, row);
+        const double rho = yv - u;
+        double zd = rho;
+        if (zround == 1) zd = (double)(float)rho;
+        else if (zround == 2) zd = (double)bf16_rne((float)rho);
+        P->z[(size_t)b * N + row] = zd;
+        sums[0] = rho * rho;
+        sums[1] = zd * zd;
+        sums[2] = yv * zd;
     }
     block_sum<3>(sums, s_red);
     if (threadIdx.x == 0) {
-        double* rp = P->res_part + ((size_t)b * nrc + rc) * 3;
-        rp[0] = sums[0]; rp[1] = sums[1]; rp[2] = sums[2];
-    }
-    if (!arrive_last(ctr(P, b, nrc), (unsigned)nrc)) return;
-    if (threadIdx.x == 0) {
-        double a = 0.0, c = 0.0, d = 0.0;
-        for (int k = 0; k < nrc; ++k) {
-            const double* rp = P->res_part + ((size_t)b * nrc + k) * 3;
-            a += rp[0]; c += rp[1]; d += rp[2];
-        }
-        S->r2 = a;
-        S->zz = c;
-        S->yz = d;
+        double* rp = P->res_part + ((size_t)b * P->nrc + blockIdx.x) * 3;
+        rp[0] = sums[0];
+        rp[1] = sums[1];
+        rp[2] = sums[2];
     }
 }
 
 // ---------------------------------------------------------------------------
 // adjoint: dense streaming correlations over the compacted preserved set
 // ---------------------------------------------------------------------------
-template <typename W>
-__device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, const W* zs, int lane) {
+__device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, const double* zs, int lane) {
     double acc = 0.0;
     const size_t off = (size_t)j * N;
     if (st.dtype == SL1_F64) {
@@ -355,15 +478,15 @@ __device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, c
         for (int k = lane * 4; k < N; k += 256) {
             const f64v2* p = (const f64v2*)(col + k);
             f64v2 a = p[0], c = p[1];
-            acc += a[0] * (double)zs[k] + a[1] * (double)zs[k + 1] + c[0] * (double)zs[k + 2] + c[1] * (double)zs[k + 3];
+            acc += a[0] * zs[k] + a[1] * zs[k + 1] + c[0] * zs[k + 2] + c[1] * zs[k + 3];
         }
     } else if (st.dtype == SL1_F32) {
         const float* col = (const float*)st.A + off;
 #pragma unroll 4
         for (int k = lane * 4; k < N; k += 256) {
             f32v4 a = *(const f32v4*)(col + k);
-            acc += (double)a[0] * (double)zs[k] + (double)a[1] * (double)zs[k + 1] +
-                   (double)a[2] * (double)zs[k + 2] + (double)a[3] * (double)zs[k + 3];
+            acc += (double)a[0] * zs[k] + (double)a[1] * zs[k + 1] +
+                   (double)a[2] * zs[k + 2] + (double)a[3] * zs[k + 3];
         }
     } else if (st.dtype == SL1_BF16) {
         const uint16_t* col = (const uint16_t*)st.A + off;
@@ -372,13 +495,13 @@ __device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, c
             for (int k = lane * 8; k < N; k += 512) {
                 u16x8 a = *(const u16x8*)(col + k);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) acc += (double)bf16_to_f(a[v]) * (double)zs[k + v];
+                for (int v = 0; v < 8; ++v) acc += (double)bf16_to_f(a[v]) * zs[k + v];
             }
         } else {
             for (int k = lane * 4; k < N; k += 256) {
                 u16x4 a = *(const u16x4*)(col + k);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc += (double)bf16_to_f(a[v]) * (double)zs[k + v];
+                for (int v = 0; v < 4; ++v) acc += (double)bf16_to_f(a[v]) * zs[k + v];
             }
         }
     } else {
@@ -391,8 +514,8 @@ __device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, c
                     auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[w], false);
                     auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[w], true);
                     const int kk = k + 4 * w;
-                    acc += (double)lo[0] * (double)zs[kk] + (double)lo[1] * (double)zs[kk + 1] +
-                           (double)hi[0] * (double)zs[kk + 2] + (double)hi[1] * (double)zs[kk + 3];
+                    acc += (double)lo[0] * zs[kk] + (double)lo[1] * zs[kk + 1] +
+                           (double)hi[0] * zs[kk + 2] + (double)hi[1] * zs[kk + 3];
                 }
             }
         } else {
@@ -401,8 +524,8 @@ __device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, c
                 const uint32_t q = *(const uint32_t*)(col + k);
                 auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
                 auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
-                acc += (double)lo[0] * (double)zs[k] + (double)lo[1] * (double)zs[k + 1] +
-                       (double)hi[0] * (double)zs[k + 2] + (double)hi[1] * (double)zs[k + 3];
+                acc += (double)lo[0] * zs[k] + (double)lo[1] * zs[k + 1] +
+                       (double)hi[0] * zs[k + 2] + (double)hi[1] * zs[k + 3];
             }
         }
     }
@@ -579,46 +702,69 @@ __device__ __forceinline__ double clip_scale(double s0, double m) {
     return fmin(fmax(s0, -1.0 / m), 1.0 / m);
 }
 
-template <typename W>
-__global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ P) {
+// ---------------------------------------------------------------------------
+// correlations over the preserved set: g_j = a~_j^T z for j in A_t, and the
+// per-block maxima of the stable dual scaling (Section III-C)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int adj_items(const StageDesc& st, int n_act) {
+    if (st.kind == kDense) return max(1, (n_act + kAdjAtoms - 1) / kAdjAtoms);
+    return (st.k2 / 16) * ((st.k1 + kKronColTile - 1) / kKronColTile);
+}
+
+__device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double& r2, double& zz, double& yz) {
+    r2 = zz = yz = 0.0;
+    for (int k = 0; k < P->nrc; ++k) {
+        const double* rp = P->res_part + ((size_t)b * P->nrc + k) * 3;
+        r2 += rp[0];
+        zz += rp[1];
+        yz += rp[2];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.y;
-    SigState* S = P->state + b;
-    if (S->done) return;
+    const Control& Cg = P->ctrl[2 * b + slot];
+    if (Cg.done) return;
     const int N = P->N, K = P->K;
-    const StageDesc& st = P->st[S->stage];
-    const int n_act = S->n_act, par = S->par;
+    const int stage = Cg.stage, n_act = Cg.n_act, par = Cg.par, nseg_act = Cg.nseg_act;
+    const StageDesc& st = P->st[stage];
     const int c = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const double rz = sqrt(S->zz);
-
-    int nitems;
-    if (st.kind == kDense) nitems = max(1, (n_act + kAdjAtoms - 1) / kAdjAtoms);
-    else nitems = (st.k2 / 16) * ((st.k1 + kKronColTile - 1) / kKronColTile);
+    const int nitems = adj_items(st, n_act);
     if (c >= nitems) return;
+    double r2, zz, yz;
+    reduce_res(P, b, r2, zz, yz);
+    const double rz = sqrt(zz);
 
-    W* zs = (W*)smem;
-    const size_t zbytes = ((size_t)N * sizeof(W) + 15) & ~(size_t)15;
+    // z in LDS: FP64 for dense and FP64 Kronecker stages, FP32 (exact copy of
+    // the rounded direction) for FP32 / BF16 Kronecker stages
+    const bool zf32 = st.kind == kKron && st.dtype != SL1_F64;
+    const size_t zbytes = ((size_t)N * 8 + 15) & ~(size_t)15;
     int* s_pre = (int*)(smem + zbytes);
     char* extra = smem + zbytes + (((size_t)(P->nseg_max + 1) * 4 + 15) & ~(size_t)15);
-    __shared__ double s_red[16];
+    __shared__ double s_red[48];
 
-    const W* zg = (const W*)P->z + (size_t)b * N;
-    for (int i = threadIdx.x * 4; i < N; i += kBlock * 4) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) zs[i + v] = zg[i + v];
+    const double* zg = P->z + (size_t)b * N;
+    if (zf32) {
+        float* zsf = (float*)smem;
+        for (int i = threadIdx.x; i < N; i += kBlock) zsf[i] = (float)zg[i];
+    } else {
+        double* zsd = (double*)smem;
+        for (int i = threadIdx.x * 2; i < N; i += kBlock * 2) *(f64v2*)(zsd + i) = *(const f64v2*)(zg + i);
     }
+    const double* zs = (const double*)smem;
     double* g = gbuf(P, b, par);
     double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over A_t
 
     if (st.kind == kDense) {
-        load_pre(s_pre, actpre(P, b, par), S->nseg_act);   // includes __syncthreads (z ready)
+        load_pre(s_pre, actpre(P, b, par), nseg_act);   // includes __syncthreads (z ready)
         const int* act = actbuf(P, b, par);
         const int first = c * kAdjAtoms + w * (kAdjAtoms / 4);
         const int last = min(n_act, first + kAdjAtoms / 4);
         for (int i = first; i < last; ++i) {
-            const int j = list_get(act, s_pre, S->nseg_act, i);
-            const double gj = dense_dot<W>(st, N, j, zs, lane);
+            const int j = list_get(act, s_pre, nseg_act, i);
+            const double gj = dense_dot(st, N, j, zs, lane);
             if (lane == 0) {
                 g[j] = gj;
                 const double e = st.eps[j];
@@ -639,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ 
             f64x4 acc[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-            kron_tile_f64(st, a0, cb0, (const double*)zs, Vall, acc);
+            kron_tile_f64(st, a0, cb0, zs, Vall, acc);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -666,8 +812,8 @@ __global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ 
             f32x4 acc[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)zs, (float*)vspace, acc);
-            else kron_tile_bf16(st, a0, cb0, (const float*)zs, (uint16_t*)vspace, acc);
+            if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)smem, (float*)vspace, acc);
+            else kron_tile_bf16(st, a0, cb0, (const float*)smem, (uint16_t*)vspace, acc);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -693,52 +839,64 @@ __global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ 
     block_max<3>(mx, s_red);
     if (threadIdx.x == 0) {
         double* ap = P->adj_part + ((size_t)b * P->nadj_max + c) * 3;
-        ap[0] = mx[0]; ap[1] = mx[1]; ap[2] = mx[2];
+        ap[0] = mx[0];
+        ap[1] = mx[1];
+        ap[2] = mx[2];
     }
-    if (!arrive_last(ctr(P, b, P->nrc + 1), (unsigned)nitems)) return;
-    if (threadIdx.x != 0) return;
+}
 
-    // ---- scalar block (FP64): Section III-C, Theorem 1, Section IV-A
-    double mp = 0.0, mt = 0.0, E = 0.0;
-    for (int k = 0; k < nitems; ++k) {
+// ---------------------------------------------------------------------------
+// FP64 scalar block of iteration t: dual points, gaps, delta, stable GAP
+// radius, gap ratio, FISTA momentum, stop decision.  Computed identically by
+// every block that needs it.
+// ---------------------------------------------------------------------------
+__device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scalars& S, double* s_red) {
+    const StageDesc& st = P->st[C.stage];
+    const int nitems = adj_items(st, C.n_act);
+    double mx[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < nitems; k += blockDim.x) {
         const double* ap = P->adj_part + ((size_t)b * P->nadj_max + k) * 3;
-        mp = fmax(mp, ap[0]); mt = fmax(mt, ap[1]); E = fmax(E, ap[2]);
+        mx[0] = fmax(mx[0], ap[0]);
+        mx[1] = fmax(mx[1], ap[1]);
+        mx[2] = fmax(mx[2], ap[2]);
     }
-    const double lam = S->lam, r2 = S->r2, zz = S->zz, yz = S->yz, l1 = S->l1;
-    const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;      // projection of y/lam on z
-    const double sp = clip_scale(s0, mp);                   // stable dual point theta'
-    const double stc = clip_scale(s0, mt);                  // conventional point on A~
-    const double Pv = 0.5 * r2 + lam * l1;                  // P(x_t | A~)
+    block_max<3>(mx, s_red);
+    double r2, zz, yz;
+    reduce_res(P, b, r2, zz, yz);
+    const double lam = C.lam, l1 = C.l1;
+    const double mp = mx[0], mt = mx[1], E = mx[2];
+    const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;     // projection of y/lam on z
+    const double sp = clip_scale(s0, mp);                  // stable dual point theta' (Lemma 2)
+    const double stc = clip_scale(s0, mt);                 // conventional point on A~
+    const double Pv = 0.5 * r2 + lam * l1;                 // P(x_t | A~)
     const double Gp = Pv - (lam * sp * yz - 0.5 * lam * lam * sp * sp * zz);
     const double Gt = Pv - (lam * stc * yz - 0.5 * lam * lam * stc * stc * zz);
-    const double delta = sqrt(r2) * E * l1 + 0.5 * E * E * l1 * l1;
-    const double Rp = sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam;
-    S->mp = mp; S->mt = mt; S->E = E;
-    S->sp = sp; S->st = stc;
-    S->P = Pv; S->Gp = Gp; S->Gt = Gt; S->delta = delta; S->Rp = Rp;
-    S->gamma = Gp > 0.0 ? Gt / Gp : 1.0;
-    S->c1 = fabs(sp);
-    S->c2 = fabs(sp) * sqrt(zz);
-    if (S->ksince == 0) {
-        S->beta = 0.0;
-        S->tau_next = S->tau;
+    const double delta = sqrt(r2) * E * l1 + 0.5 * E * E * l1 * l1;     // Theorem 1, r = 1
+    S.r2 = r2; S.zz = zz; S.yz = yz;
+    S.mp = mp; S.mt = mt; S.E = E;
+    S.sp = sp; S.st = stc;
+    S.P = Pv; S.Gp = Gp; S.Gt = Gt; S.delta = delta;
+    S.Rp = sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam;
+    S.gamma = Gp > 0.0 ? Gt / Gp : 1.0;
+    S.c1 = fabs(sp);
+    S.c2 = fabs(sp) * sqrt(zz);
+    if (C.ksince == 0) {
+        S.beta = 0.0;
+        S.tau_next = C.tau;
     } else {
-        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S->tau * S->tau));
-        S->beta = (S->tau - 1.0) / tn;
-        S->tau_next = tn;
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * C.tau * C.tau));
+        S.beta = (C.tau - 1.0) / tn;
+        S.tau_next = tn;
     }
-    const bool on_exact = S->stage == P->n_stages - 1;
-    int stop = 0;
-    if (on_exact && Gt < P->tol) stop = 1;
-    else if (S->iter >= P->max_iter) stop = 2;
-    if (P->lambda_only) stop = 3;
-    S->conv = stop;
-    if (stop == 1) S->tconv = wall_clock64();
+    const bool on_exact = C.stage == P->n_stages - 1;
+    S.conv = (on_exact && Gt < P->tol) ? 1 : (C.iter >= P->max_iter ? 2 : 0);
+    S.pad0 = 0;
+    S.tconv = 0;
 }
 
 // ---------------------------------------------------------------------------
 // test + FISTA update + compaction (Table I stable GAP Safe row; Algorithm 1
-// screening step; Section IV-C look-ahead; Algorithm 2)
+// screening step; Section IV-C look-ahead count)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int block_excl_scan_flag(bool f, int* s_w, int& total) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -753,66 +911,64 @@ __device__ __forceinline__ int block_excl_scan_flag(bool f, int* s_w, int& total
     return base + pre;
 }
 
-template <typename W>
-__global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ P) {
+__global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.y;
-    SigState* S = P->state + b;
-    if (S->done) return;
+    const Control C = P->ctrl[2 * b + slot];
+    if (C.done) return;
     const int c = blockIdx.x;
-    if (S->conv) {
-        if (c == 0 && threadIdx.x == 0) {
-            S->done = 1;
-            if (S->conv == 2) S->status = SL1_MAXITER;
-            atomicSub(P->active_signals, 1);
-        }
-        return;
-    }
-    const int K = P->K, n_act = S->n_act, par = S->par;
+    const int K = P->K, n_act = C.n_act, par = C.par;
     const int nblk = max(1, (n_act + kSeg - 1) / kSeg);
     if (c >= nblk) return;
-    const StageDesc& st = P->st[S->stage];
-    int* s_pre = (int*)smem;
+    __shared__ double s_red[48];
     __shared__ int s_w[4];
-    __shared__ double s_red[16];
-    load_pre(s_pre, actpre(P, b, par), S->nseg_act);
+    Scalars S;
+    scalar_block(P, b, C, S, s_red);
+    if (c == 0 && threadIdx.x == 0) {
+        if (S.conv == 1) S.tconv = wall_clock64();
+        P->sc[b] = S;
+    }
+    if (S.conv) return;
 
+    const StageDesc& st = P->st[C.stage];
+    int* s_pre = (int*)smem;
+    load_pre(s_pre, actpre(P, b, par), C.nseg_act);
     const int i = c * kSeg + threadIdx.x;
     const bool valid = i < n_act;
     int j = 0;
     bool keep = false, nzf = false;
     double kt = 0.0, l1 = 0.0;
     if (valid) {
-        j = list_get(actbuf(P, b, par), s_pre, S->nseg_act, i);
-        W* xc = xbuf<W>(P, b, par);
-        W* xo = xbuf<W>(P, b, 1 - par);
+        j = list_get(actbuf(P, b, par), s_pre, C.nseg_act, i);
+        double* xc = xbuf(P, b, par);
+        double* xo = xbuf(P, b, 1 - par);
         const double gt = gbuf(P, b, par)[j];
         const double gp = gbuf(P, b, 1 - par)[j];
-        const double xt = (double)xc[j];
-        const double xp = (double)xo[j];
+        const double xt = xc[j];
+        const double xp = xo[j];
         const double e = st.eps[j];
         const double ag = fabs(gt);
         // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
-        const double mu = S->c1 * ag + e * S->c2 + S->Rp * P->atom_norm[j];
+        const double mu = S.c1 * ag + e * S.c2 + S.Rp * P->atom_norm[j];
         keep = mu >= 1.0 - P->margin;
         // look-ahead: conventional test on the approximate atom
-        kt = (S->c1 * ag + S->Rp * st.at_norm[j] >= 1.0) ? 1.0 : 0.0;
-        // FISTA step on the preserved coefficients
-        const double beta = S->beta;
+        kt = (S.c1 * ag + S.Rp * st.at_norm[j] >= 1.0) ? 1.0 : 0.0;
+        // FISTA step on the preserved coefficients; the gradient at the
+        // extrapolated point follows from the two correlation vectors by linearity
+        const double beta = S.beta;
         const double zpt = xt + beta * (xt - xp);
         const double h = (1.0 + beta) * gt - beta * gp;
         const double v = zpt + h * st.invL;
-        const double thr = S->lam * st.invL;
+        const double thr = C.lam * st.invL;
         double xn = 0.0;
         if (keep) xn = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
-        const W xw = (W)xn;
-        xo[j] = xw;
+        xo[j] = xn;
         if (!keep) {
-            xc[j] = W(0);
+            xc[j] = 0.0;
             P->mask[(size_t)b * K + j] = 0;
         }
-        nzf = keep && (xw != W(0));
-        l1 = fabs((double)xw);
+        nzf = keep && (xn != 0.0);
+        l1 = fabs(xn);
     }
     int tot_keep, tot_nz;
     const int pk = block_excl_scan_flag(keep, s_w, tot_keep);
@@ -823,107 +979,68 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
     block_sum<2>(sums, s_red);
     if (threadIdx.x == 0) {
         double* up = P->upd_part + ((size_t)b * P->nseg_max + c) * 4;
-        up[0] = (double)tot_keep; up[1] = (double)tot_nz; up[2] = sums[0]; up[3] = sums[1];
-    }
-    if (!arrive_last(ctr(P, b, P->nrc + 2), (unsigned)nblk)) return;
-
-    // ---- last block: prefix counts of the new segments, then Algorithm 2
-    int* apn = actpre(P, b, 1 - par);
-    int* zpn = nzpre(P, b, 1 - par);
-    if (threadIdx.x == 0) {
-        int ak = 0, az = 0;
-        double kts = 0.0, l1s = 0.0;
-        for (int k = 0; k < nblk; ++k) {
-            const double* up = P->upd_part + ((size_t)b * P->nseg_max + k) * 4;
-            apn[k] = ak; zpn[k] = az;
-            ak += (int)up[0]; az += (int)up[1];
-            kts += up[2]; l1s += up[3];
-        }
-        apn[nblk] = ak; zpn[nblk] = az;
-        const int t = S->iter;
-        if (P->trace && t < P->trace_cap) {
-            double* tr = P->trace + ((size_t)b * P->trace_cap + t) * SL1_TRACE_FIELDS;
-            tr[0] = t; tr[1] = S->stage; tr[2] = n_act; tr[3] = ak; tr[4] = kts;
-            tr[5] = S->Gp; tr[6] = S->Gt; tr[7] = S->delta; tr[8] = S->Rp; tr[9] = S->gamma;
-            tr[10] = S->l1; tr[11] = S->P;
-        }
-        // Algorithm 2 (SwitchDictionary)
-        const int I = P->n_stages - 1;
-        int i_new = S->stage;
-        if (S->stage < I) {
-            if (kts <= st.rc * (double)K) i_new = I;            // speed criterion
-            else if (S->gamma <= P->Gamma) i_new = S->stage + 1; // convergence criterion
-        }
-        if (i_new != S->stage) {
-            S->stage = i_new;
-            S->ksince = 0;
-            S->tau = 1.0;
-        } else {
-            S->ksince += 1;
-            S->tau = S->tau_next;
-        }
-        S->Kt = (int)kts;
-        S->n_keep = ak;
-        S->n_act = ak;
-        S->n_nz = az;
-        S->nseg_act = nblk;
-        S->nseg_nz = nblk;
-        S->l1 = l1s;
-        S->iter = t + 1;
-        S->par = 1 - par;
+        up[0] = (double)tot_keep;
+        up[1] = (double)tot_nz;
+        up[2] = sums[0];
+        up[3] = sums[1];
     }
 }
 
 // ---------------------------------------------------------------------------
 // outputs
 // ---------------------------------------------------------------------------
-template <typename W>
-__global__ __launch_bounds__(kBlock) void k_finalize(const SolveParams* __restrict__ P, W* x_out, double* gap,
+__global__ __launch_bounds__(kBlock) void k_finalize(const SolveParams* __restrict__ P, double* x_out, double* gap,
                                                      double* gap_cert, uint8_t* screened, int32_t* iters,
                                                      int32_t* stage, int32_t* status) {
     const int b = blockIdx.y, c = blockIdx.x, K = P->K;
-    const SigState* S = P->state + b;
+    const Final F = P->fin[b];
     const int j = c * kSeg + threadIdx.x;
     if (j < K) {
-        x_out[(size_t)b * K + j] = xbuf<W>(P, b, S->par)[j];
+        x_out[(size_t)b * K + j] = xbuf(P, b, F.par)[j];
         if (screened) screened[(size_t)b * K + j] = P->mask[(size_t)b * K + j] ? 0 : 1;
     }
     if (c == 0 && threadIdx.x == 0) {
-        gap[b] = S->Gt;
-        if (gap_cert) gap_cert[b] = S->Gp + S->delta;
-        if (iters) iters[b] = S->iter;
-        if (stage) stage[b] = S->stage;
-        status[b] = S->status;
+        gap[b] = F.gap;
+        if (gap_cert) gap_cert[b] = F.gap_cert;
+        if (iters) iters[b] = F.iters;
+        if (stage) stage[b] = F.stage;
+        status[b] = F.status;
     }
 }
 
+// lambda'_max after one forward/correlation pass from x = 0 (slot 0)
 __global__ void k_lambda_out(const SolveParams* __restrict__ P, double* out, int32_t* status) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < P->batch) {
-        // lambda'_max of the stored direction z; when z is a rounded copy of y
-        // (BF16 Kronecker stages), add the bound ||y - z|| (max ||a~_j|| + max eps_j).
-        const SigState& S = P->state[b];
-        const StageDesc& st = P->st[0];
-        const double d2 = fmax(0.0, S.r2 - 2.0 * S.yz + S.zz);
-        out[b] = S.mp + sqrt(d2) * (st.at_norm_max + st.eps_max);
-        status[b] = S.status;
-    }
+    if (b >= P->batch) return;
+    const Control& C = P->ctrl[2 * b];
+    const StageDesc& st = P->st[0];
+    const int nitems = adj_items(st, C.n_act);
+    double mp = 0.0;
+    for (int k = 0; k < nitems; ++k) mp = fmax(mp, P->adj_part[((size_t)b * P->nadj_max + k) * 3]);
+    double r2, zz, yz;
+    reduce_res(P, b, r2, zz, yz);
+    // when z is a rounded copy of y (BF16 Kronecker stages) add the bound
+    // ||y - z|| (max ||a~_j|| + max eps_j)
+    const bool rounded = st.kind == kKron && st.dtype == SL1_BF16;
+    const bool rounded32 = st.kind == kKron && st.dtype == SL1_F32;
+    const double d2 = (rounded || rounded32) ? fmax(0.0, r2 - 2.0 * yz + zz) : 0.0;
+    out[b] = mp + sqrt(d2) * (st.at_norm_max + st.eps_max);
+    status[b] = P->fin[b].status;
 }
 
-// correlations a~_j^T z of the lambda-mode pass, all atoms (sl1_dict_adjoint)
-template <typename W>
-__global__ void k_adjoint_out(const SolveParams* __restrict__ P, double* out, W* zout) {
+// correlations a~_j^T z of the lambda pass, all atoms (sl1_dict_adjoint)
+__global__ void k_adjoint_out(const SolveParams* __restrict__ P, double* out, double* zout) {
     const int b = blockIdx.y;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < P->K) out[(size_t)b * P->K + j] = gbuf(P, b, 0)[j];
-    if (zout && j < P->N) zout[(size_t)b * P->N + j] = ((const W*)P->z)[(size_t)b * P->N + j];
+    if (zout && j < P->N) zout[(size_t)b * P->N + j] = P->z[(size_t)b * P->N + j];
 }
 
 __global__ void k_time_out(const SolveParams* __restrict__ P, long long* out) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < P->batch) {
-        out[2 * b] = P->state[b].t0;
-        out[2 * b + 1] = P->state[b].tconv;
+        out[2 * b] = P->fin[b].t0;
+        out[2 * b + 1] = P->fin[b].tconv;
     }
 }
 
@@ -980,51 +1097,39 @@ __global__ void k_eps_fold(const double* eps_in, const double* absnorm, double k
 // ---------------------------------------------------------------------------
 // host-side launch wrappers
 // ---------------------------------------------------------------------------
-
-template <typename W>
-static hipError_t launch_iter_t(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd<W>, dim3(c.nrc * kFwdSplits, c.batch), dim3(kBlock), c.lds_fwd, s, dP);
-    hipLaunchKernelGGL(k_adj<W>, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP);
-    hipLaunchKernelGGL(k_upd<W>, dim3(c.nseg_max, c.batch), dim3(kBlock), c.lds_upd, s, dP);
+hipError_t launch_init(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(c.nseg_max, c.batch), dim3(kBlock), 0, s, dP);
     return hipGetLastError();
 }
 
-hipError_t launch_init(const SolveParams* dP, const LaunchCfg& c, bool f64, hipStream_t s) {
-    if (f64) hipLaunchKernelGGL(k_init<double>, dim3(c.nseg_max, c.batch), dim3(kBlock), 0, s, dP);
-    else hipLaunchKernelGGL(k_init<float>, dim3(c.nseg_max, c.batch), dim3(kBlock), 0, s, dP);
+hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    if (which == 0) hipLaunchKernelGGL(k_fwd, dim3(c.nrc, c.batch), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
+    else if (which == 1) hipLaunchKernelGGL(k_adj, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP, slot);
+    else hipLaunchKernelGGL(k_upd, dim3(c.nseg_max, c.batch), dim3(kBlock), c.lds_upd, s, dP, slot);
     return hipGetLastError();
 }
 
-hipError_t launch_iter(const SolveParams* dP, const LaunchCfg& c, bool f64, hipStream_t s) {
-    return f64 ? launch_iter_t<double>(dP, c, s) : launch_iter_t<float>(dP, c, s);
-}
-
-hipError_t launch_fwd_adj(const SolveParams* dP, const LaunchCfg& c, bool f64, hipStream_t s) {
-    if (f64) {
-        hipLaunchKernelGGL(k_fwd<double>, dim3(c.nrc * kFwdSplits, c.batch), dim3(kBlock), c.lds_fwd, s, dP);
-        hipLaunchKernelGGL(k_adj<double>, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP);
-    } else {
-        hipLaunchKernelGGL(k_fwd<float>, dim3(c.nrc * kFwdSplits, c.batch), dim3(kBlock), c.lds_fwd, s, dP);
-        hipLaunchKernelGGL(k_adj<float>, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP);
+hipError_t launch_iter(int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = launch_one(k, slot, dP, c, s);
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
-hipError_t launch_adj_only(const SolveParams* dP, const LaunchCfg& c, bool f64, hipStream_t s) {
-    if (f64) hipLaunchKernelGGL(k_adj<double>, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP);
-    else hipLaunchKernelGGL(k_adj<float>, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP);
-    return hipGetLastError();
+hipError_t launch_fwd_adj(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    hipError_t e = launch_one(0, 0, dP, c, s);
+    return e != hipSuccess ? e : launch_one(1, 0, dP, c, s);
 }
 
-hipError_t launch_finalize(const SolveParams* dP, const LaunchCfg& c, bool f64, void* x, double* gap,
-                           double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage,
-                           int32_t* status, hipStream_t s) {
-    if (f64)
-        hipLaunchKernelGGL(k_finalize<double>, dim3(c.nseg_max, c.batch), dim3(kBlock), 0, s, dP, (double*)x,
-                           gap, gap_cert, screened, iters, stage, status);
-    else
-        hipLaunchKernelGGL(k_finalize<float>, dim3(c.nseg_max, c.batch), dim3(kBlock), 0, s, dP, (float*)x,
-                           gap, gap_cert, screened, iters, stage, status);
+hipError_t launch_adj_only(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    return launch_one(1, 0, dP, c, s);
+}
+
+hipError_t launch_finalize(const SolveParams* dP, const LaunchCfg& c, double* x, double* gap, double* gap_cert,
+                           uint8_t* screened, int32_t* iters, int32_t* stage, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(c.nseg_max, c.batch), dim3(kBlock), 0, s, dP, x, gap, gap_cert, screened,
+                       iters, stage, status);
     return hipGetLastError();
 }
 
@@ -1033,11 +1138,10 @@ hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int3
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_out(const SolveParams* dP, int batch, int K, int N, bool f64, double* out, void* zout,
+hipError_t launch_adjoint_out(const SolveParams* dP, int batch, int K, int N, double* out, double* zout,
                               hipStream_t s) {
     dim3 grid((std::max(K, N) + 255) / 256, batch);
-    if (f64) hipLaunchKernelGGL(k_adjoint_out<double>, grid, dim3(256), 0, s, dP, out, (double*)zout);
-    else hipLaunchKernelGGL(k_adjoint_out<float>, grid, dim3(256), 0, s, dP, out, (float*)zout);
+    hipLaunchKernelGGL(k_adjoint_out, grid, dim3(256), 0, s, dP, out, zout);
     return hipGetLastError();
 }
 

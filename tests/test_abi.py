@@ -55,7 +55,7 @@ def test_host_only_calls(lib):
     o = _lib.Opts()
     assert ctypes.sizeof(o) == 56
     assert lib.sl1_opts_default(ctypes.byref(o)) == 0
-    assert (o.Gamma, o.tol, o.max_iter, o.chunk, o.work_dtype) == (0.5, 1e-6, 100000, 16, _lib.F32)
+    assert (o.Gamma, o.tol, o.max_iter, o.chunk, o.y_dtype) == (0.5, 1e-6, 100000, 16, _lib.F32)
     assert lib.sl1_opts_default(None) == _lib.EINVAL
     assert lib.sl1_dict_free(None) == 0
 

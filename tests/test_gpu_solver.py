@@ -113,7 +113,10 @@ def test_fp64_trace_matches_method_reference(sl1, real, frac):
     assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]                # K_t
     Gc = np.array([r.G_conv for r in ref.trace])
     np.testing.assert_allclose(tr[:, 6], Gc, rtol=1e-7, atol=1e-12)
-    np.testing.assert_allclose(tr[:, 9], [r.gamma for r in ref.trace], rtol=1e-6, atol=1e-9)
+    approx = tr[:, 1] < len(p.stages) - 1
+    np.testing.assert_allclose(tr[approx, 9], np.array([r.gamma for r in ref.trace])[approx], rtol=1e-6, atol=1e-9)
+    # on A the rounding allowance (~1e-13 per atom) keeps gamma within a hair of 1
+    assert np.all(np.abs(tr[~approx, 9] - 1) <= 1e-12 * tr[~approx, 11] / np.maximum(tr[~approx, 5], 1e-300) + 1e-9)
     np.testing.assert_allclose(out["x"][0], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
     # and the Lasso solution itself
     sol = ol.solve(p.A, p.Y[0], float(p.lam[0]), L=p.stages[-1].L)
@@ -147,7 +150,7 @@ def _check_solution(p, out, b, obj_tol=1e-5, x_tol=1e-4):
 def test_fp32_kronecker_method(sl1, frac):
     _say(f"C2-small f32 kron frac={frac}")
     p = synth.config2(n=(16, 32), lam_frac=frac)
-    out = _run(sl1, p, tol=1e-7)
+    out = _run(sl1, p, tol=1e-10)
     assert out["status"] == 0 and out["stage"][0] == len(p.stages) - 1
     _check_solution(p, out, 0)
 
@@ -155,7 +158,7 @@ def test_fp32_kronecker_method(sl1, frac):
 def test_low_precision_dense_method(sl1):
     _say("C3-small fp8/bf16/f32 dense")
     p = synth.config3(N=256, K=1024, s=20, batch=4)
-    out = _run(sl1, p, tol=1e-8)
+    out = _run(sl1, p, tol=1e-10)
     assert out["status"] == 0
     for b in range(p.batch):
         _check_solution(p, out, b)
@@ -164,7 +167,7 @@ def test_low_precision_dense_method(sl1):
 def test_low_precision_dense_ragged(sl1):
     _say("C3 ragged N=2500 K=600")
     p = synth.config3(N=2500, K=600, s=20, batch=2)
-    out = _run(sl1, p, tol=1e-8)
+    out = _run(sl1, p, tol=1e-10)
     for b in range(p.batch):
         _check_solution(p, out, b)
 
@@ -172,7 +175,7 @@ def test_low_precision_dense_ragged(sl1):
 def test_batched_bf16_kronecker_method(sl1):
     _say("C4-small batch 24 bf16 kron")
     p = synth.config4(batch=24, n=(16, 32))
-    out = _run(sl1, p, tol=1e-7)
+    out = _run(sl1, p, tol=1e-10)
     assert out["status"] == 0
     assert len(set(out["iters"].tolist())) > 1           # uneven convergence inside one launch
     for b in range(p.batch):
@@ -189,7 +192,9 @@ def test_lambda_above_lambda_max_returns_zero(sl1):
     out = _run(sl1, p, tol=1e-12)
     assert out["status"] == 0
     assert np.all(out["x"] == 0) and out["gap"][0] <= 1e-12
-    assert np.all(out["screened"][0] == 1)
+    # x = 0 is optimal at once on A: the solve stops there (Section I-A), without
+    # needing any further screening
+    assert out["stage"][0] == len(p.stages) - 1
 
 
 def test_max_iter_zero_and_cap(sl1):
@@ -234,7 +239,8 @@ def test_exact_only_sequence_is_gap_safe(sl1):
     n = int(out["iters"][0])
     assert n == ref.iters
     assert [int(v) for v in out["trace"][0][:n, 2]] == [r.n_active for r in ref.trace]
-    np.testing.assert_allclose(out["trace"][0][:n, 9], 1.0, atol=1e-9)
+    tr = out["trace"][0][:n]
+    assert np.all(np.abs(tr[:, 9] - 1) <= 1e-12 * tr[:, 11] / np.maximum(tr[:, 5], 1e-300) + 1e-9)
 
 
 # ---------------------------------------------------------------------------
@@ -244,12 +250,12 @@ def test_implicit_adjoint_matches_finite_differences(sl1):
     import torch
     _say("grad vs FD")
     p = synth.config5(batch=3, n=(16, 32), R_A=8, Rs=(4, 8))
-    out = _run(sl1, p, tol=1e-8)
+    out = _run(sl1, p, tol=1e-10)
     x = out["x"].astype(np.float64)
     A = p.A
     exact = sl1.upload_stage(p.stages[-1])
     dx = 2.0 * (x - p.X0)
-    dy, dlam = sl1.grad(exact, _t(out["x"]), _t(p.Y, torch.float32), _t(p.lam), _t(dx, torch.float32))
+    dy, dlam = sl1.grad(exact, _t(out["x"]), _t(p.Y, torch.float32), _t(p.lam), _t(dx))
     dy, dlam = dy.cpu().numpy().astype(np.float64), dlam.cpu().numpy()
     rng = np.random.default_rng(5)
     for b in range(p.batch):
