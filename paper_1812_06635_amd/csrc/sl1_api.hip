@@ -129,7 +129,7 @@ int make_workspace(Workspace& w) {
     const size_t B = w.batch, K = w.K, N = w.N;
     w.nseg_max = (w.K + kSeg - 1) / kSeg;
     w.nrc = (w.N + kFwdRows - 1) / kFwdRows;
-    w.nadj_max = std::max(1, (w.K + kAdjAtoms - 1) / kAdjAtoms);
+    w.nadj_max = std::max(1, (w.K + 3) / 4);   // dense correlation items hold >= 4 atoms
     const size_t np = w.nseg_max + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return o; };
@@ -147,6 +147,7 @@ int make_workspace(Workspace& w) {
     const size_t o_rp = take(B * w.nrc * 3 * 8);
     const size_t o_adp = take(B * w.nadj_max * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
+    const size_t o_cnt = take(B * 4 * 4);
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
     const size_t o_times = take(B * 16);
@@ -171,6 +172,9 @@ int make_workspace(Workspace& w) {
     p.res_part = (double*)(m + o_rp);
     p.adj_part = (double*)(m + o_adp);
     p.upd_part = (double*)(m + o_up);
+    p.cnt_fwd = (int*)(m + o_cnt);
+    p.cnt_adj = p.cnt_fwd + 2 * B;
+    p.cnt_upd = p.cnt_adj + B;
     p.active_signals = (int*)(m + o_act_sig);
     p.nseg_max = w.nseg_max;
     p.nrc = w.nrc;
@@ -244,9 +248,14 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     c.nrc = w.nrc;
     c.nadj_max = w.nadj_max;
     const size_t ws = 8;
-    const size_t pre = ((size_t)(w.nseg_max + 1) * 4 + 15) & ~(size_t)15;
-    c.lds_fwd = 2 * (size_t)(w.nseg_max + 1) * 4 + kFwdBlock * 4 + 16 + kFwdBlock * 8 + 16 * kFwdRows * 8;
-    c.lds_upd = pre;
+    const size_t nseg1 = (size_t)w.nseg_max + 1, nb1 = (size_t)w.batch + 1;
+    c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + kFwdWaves * kFwdRows * 8;
+    c.lds_upd = 4 * (nseg1 + nb1);
+    const size_t pre = (4 * (nseg1 + nb1) + 15) & ~(size_t)15;
+    // persistent grids: enough blocks to fill the chip, never more than the work
+    c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
+    c.g_adj = (int)std::min<long long>((long long)w.batch * w.nadj_max, 2048);
+    c.g_upd = (int)std::min<long long>((long long)w.batch * w.nseg_max, 1024);
     size_t extra = 0;
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
@@ -262,7 +271,8 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
 
 bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
-           a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj && a.lds_upd == b.lds_upd;
+           a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_upd == b.g_upd && a.lds_fwd == b.lds_fwd &&
+           a.lds_adj == b.lds_adj && a.lds_upd == b.lds_upd;
 }
 
 int check_lds(const LaunchCfg& c) {
@@ -533,7 +543,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (opt) o = *opt;
     else sl1_opts_default(&o);
     if (!atom_norm || !y || !lambda || !x || !gap || batch < 1) return SL1_EINVAL;
-    if (batch > (1 << 20)) return SL1_ELIMIT;
+    if (batch > kMaxBatch) return SL1_ELIMIT;
     if (o.max_iter < 0 || !(o.tol >= 0.0) || !std::isfinite(o.Gamma) || !(o.margin >= 0.0)) return SL1_EINVAL;
     if (o.trace && o.trace_cap < 0) return SL1_EINVAL;
     SolveParams tmp;
@@ -667,6 +677,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
 static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* lam_out, double* g_out,
                        double* z_out, void* stream) {
     if (!d || !y || batch < 1) return SL1_EINVAL;
+    if (batch > kMaxBatch) return SL1_ELIMIT;
     sl1_dict seq[1] = {d};
     double L = 1.0;
     SolveParams tmp;
@@ -735,6 +746,7 @@ int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int y_dtype, doub
 
 int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_out, void* stream) {
     if (!seq || n_stages < 1 || !rc_out || batch < 1) return SL1_EINVAL;
+    if (batch > kMaxBatch) return SL1_ELIMIT;
     std::vector<double> Ls(n_stages, 1.0);
     SolveParams tmp;
     std::memset(&tmp, 0, sizeof(tmp));

@@ -11,9 +11,9 @@ namespace sl1 {
 constexpr int kBlock = 256;         // threads per block (4 waves)
 constexpr int kWave = 64;
 constexpr int kSeg = 256;           // atoms per segment of a compacted list (one update block)
-constexpr int kAdjAtoms = 64;       // atoms per dense-adjoint block (16 per wave)
 constexpr int kFwdRows = 256;       // rows per forward block (4 per lane)
-constexpr int kFwdBlock = 1024;     // forward block: 16 waves share the nonzeros of x
+constexpr int kFwdBlock = 512;      // forward block: 8 waves share the nonzeros of x
+constexpr int kFwdWaves = kFwdBlock / 64;
 constexpr int kMaxSeg = 1024;       // segments of a compacted list (K <= 262144)
 constexpr int kKronColTile = 64;    // atoms (j1) per Kronecker-adjoint block (16 per wave)
 constexpr int kMaxN = 8192;
@@ -90,14 +90,20 @@ struct SolveParams {
     double* res_part;         // [batch][nrc][3]
     double* adj_part;         // [batch][nadj_max][3]
     double* upd_part;         // [batch][nseg_max][4]
+    int* cnt_fwd;             // [2][batch] work items of the forward launch of the iteration with parity s
+    int* cnt_adj;             // [batch] work items of the correlation launch (current iteration)
+    int* cnt_upd;             // [batch] work items of the update launch (current iteration)
     int* active_signals;      // one int: signals not yet done
     int nseg_max, nrc, nadj_max, n1_max;
 };
 
 struct LaunchCfg {
     int batch, nseg_max, nrc, nadj_max;
+    int g_fwd, g_adj, g_upd;          // persistent grid sizes (blocks)
     size_t lds_fwd, lds_adj, lds_upd;
 };
+
+constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

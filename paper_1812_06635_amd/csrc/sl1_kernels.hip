@@ -139,9 +139,39 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {  // f already bf16-exac
 }
 
 // ---------------------------------------------------------------------------
+// work map: every launch covers the flattened list of (signal, item) pairs
+// of the live signals; the per-signal item counts were written by the previous
+// launch.  Each block scans the counts in LDS and takes a contiguous range of
+// the list, so no block is launched without work.
+// ---------------------------------------------------------------------------
+__device__ int build_work_map(const int* cnt, int batch, int* s_pre, int* s_tmp) {
+    int run = 0;
+    for (int base = 0; base < batch; base += blockDim.x) {
+        const int b = base + threadIdx.x;
+        const int v = b < batch ? cnt[b] : 0;
+        int ex;
+        const int tot = block_excl_scan(v, ex, s_tmp);
+        if (b < batch) s_pre[b] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) s_pre[batch] = run;
+    __syncthreads();
+    return run;
+}
+
+__device__ __forceinline__ int find_signal(const int* s_pre, int batch, int g) {
+    int lo = 0, hi = batch;      // s_pre[lo] <= g < s_pre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
 // initialisation: x_0 = 0, A_0 = {1..K}, stage 0 (Algorithm 1, Initialize).
-// C_0 goes to slot 1 with advance = 0, so the forward kernel of iteration 0
-// (slot 0) takes it as is.
+// C_0 goes to both control slots with advance = 0, so the forward launch of
+// iteration 0 (slot 0) takes it as is.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__ P) {
     const int b = blockIdx.y, c = blockIdx.x, K = P->K;
@@ -198,6 +228,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         F.t0 = C.t0;
         F.tconv = 0;
         P->fin[b] = F;
+        P->cnt_fwd[b] = ok ? P->nrc : 0;                 // slot 0
+        P->cnt_fwd[P->batch + b] = 0;                    // slot 1
+        P->cnt_adj[b] = 0;
+        P->cnt_upd[b] = 0;
         if (ok) atomicAdd(P->active_signals, 1);
     }
 }
@@ -211,17 +245,27 @@ __device__ __forceinline__ int switch_dictionary(int i, int I, double gamma, dou
     return i;
 }
 
-// C_t from C_{t-1}, the scalars of iteration t-1 and the update kernel's
+// dense correlation items: atoms per wave so that a wave keeps ~16 loads in flight
+__device__ __forceinline__ int dense_apw(int N) { return N <= 1024 ? 4 : (N <= 2048 ? 2 : 1); }
+
+__device__ __forceinline__ int adj_items(const StageDesc& st, int n_act, int N) {
+    if (st.kind == kDense) {
+        const int per = 4 * dense_apw(N);
+        return max(1, (n_act + per - 1) / per);
+    }
+    return (st.k2 / 16) * ((st.k1 + kKronColTile - 1) / kKronColTile);
+}
+
+// C_t from C_{t-1}, the scalars of iteration t-1 and the update launch's
 // per-block partials; also the prefix counts of the two new compacted lists
 // (into LDS).  Identical in every block; returns 1 when the signal finished.
 __device__ int advance_control(const SolveParams* P, int b, const Control& Cp, Control& C, int* s_apre,
-                               int* s_zpre, double* s_red, int* s_tmp, Scalars& S) {
+                               int* s_zpre, double* s_red, int* s_tmp, Scalars& S, double& kt_out) {
     C = Cp;
     if (!Cp.advance) return 0;
     S = P->sc[b];
     if (S.conv) return 1;
     const int nblk = max(1, (Cp.n_act + kSeg - 1) / kSeg);
-    // prefix counts over the update blocks (segment k = update block k)
     int ak_tot = 0, az_tot = 0;
     double kt = 0.0, l1 = 0.0;
     for (int base = 0; base < nblk; base += blockDim.x) {
@@ -272,16 +316,13 @@ __device__ int advance_control(const SolveParams* P, int b, const Control& Cp, C
     C.nseg_act = nblk;
     C.nseg_nz = nblk;
     C.l1 = l1;
-    // trace row of iteration t-1 (Algorithm 1 quantities)
-    if (blockIdx.x == 0 && threadIdx.x == 0 && P->trace && Cp.iter < P->trace_cap) {
-        double* tr = P->trace + ((size_t)b * P->trace_cap + Cp.iter) * SL1_TRACE_FIELDS;
-        tr[0] = Cp.iter; tr[1] = Cp.stage; tr[2] = Cp.n_act; tr[3] = ak_tot; tr[4] = kt;
-        tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = S.Rp; tr[9] = S.gamma;
-        tr[10] = Cp.l1; tr[11] = S.P;
-    }
+    kt_out = kt;
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// forward product: one nonzero of x_t (4 rows per lane)
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j, double xj, int r0,
                                                double (&acc)[4]) {
     if (st.kind == kDense) {
@@ -351,187 +392,156 @@ __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j
 
 // ---------------------------------------------------------------------------
 // forward product and residual (Section III-C: rho~_t = y - A~ x_t)
-// grid (ceil(N/256), batch), 1024 threads: 16 waves share the nonzeros of x_t
-// for the same 256 rows and reduce in LDS.
+// items: row chunks of 256 rows; the 8 waves of a block share the nonzeros of
+// x_t for the same rows and reduce in LDS.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
-    const int b = blockIdx.y;
     const int prev = 1 - slot;
-    const Control Cp = P->ctrl[2 * b + prev];
-    if (Cp.done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) P->ctrl[2 * b + slot] = Cp;
-        return;
-    }
-    const int N = P->N;
+    const int N = P->N, batch = P->batch;
     const int nseg1 = P->nseg_max + 1;
     int* s_apre = (int*)smem;
     int* s_zpre = s_apre + nseg1;
     int* s_j = s_zpre + nseg1;
-    double* s_x = (double*)(((uintptr_t)(s_j + kFwdBlock) + 15) & ~(uintptr_t)15);
-    double* s_u = s_x + kFwdBlock;                      // [16 waves][256 rows]
+    int* s_wpre = s_j + kFwdBlock;                      // work map (batch + 1)
+    double* s_x = (double*)(((uintptr_t)(s_wpre + batch + 1) + 15) & ~(uintptr_t)15);
+    double* s_u = s_x + kFwdBlock;                      // [kFwdWaves][256 rows]
     __shared__ double s_red[48];
     __shared__ int s_tmp[16];
 
-    Control C;
-    Scalars S;
-    const int fin = advance_control(P, b, Cp, C, s_apre, s_zpre, s_red, s_tmp, S);
-    if (fin) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            Final F;
-            F.gap = S.Gt;
-            F.gap_cert = S.Gp + S.delta;
-            F.iters = Cp.iter;
-            F.stage = Cp.stage;
-            F.status = S.conv == 2 ? SL1_MAXITER : SL1_OK;
-            F.par = Cp.par;
-            F.t0 = Cp.t0;
-            F.tconv = S.tconv;
-            P->fin[b] = F;
-            Control D = Cp;
-            D.done = 1;
-            D.advance = 0;
-            P->ctrl[2 * b + slot] = D;
-            atomicSub(P->active_signals, 1);
-        }
-        return;
+    const int* cnt_cur = P->cnt_fwd + (size_t)slot * batch;
+    const int total = build_work_map(cnt_cur, batch, s_wpre, s_tmp);
+    // a signal without work in this slot is finished: clear its count in the
+    // other slot too, so no later forward launch visits it (the other slot is
+    // read only by the next forward launch; live signals have work here)
+    if (blockIdx.x == 0) {
+        for (int b = threadIdx.x; b < batch; b += blockDim.x)
+            if (s_wpre[b + 1] == s_wpre[b]) P->cnt_fwd[(size_t)prev * batch + b] = 0;
     }
-    if (!Cp.advance) {
-        // first iteration: the lists were written by the initialisation
-        const int* zp = nzpre(P, b, C.par);
-        for (int s = threadIdx.x; s <= C.nseg_nz; s += kFwdBlock) s_zpre[s] = zp[s];
-        __syncthreads();
-    } else if (blockIdx.x == 0) {
-        int* ap = actpre(P, b, C.par);
-        int* zp = nzpre(P, b, C.par);
-        for (int s = threadIdx.x; s <= C.nseg_act; s += kFwdBlock) {
-            ap[s] = s_apre[s];
-            zp[s] = s_zpre[s];
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        Control D = C;
-        D.advance = 1;
-        P->ctrl[2 * b + slot] = D;
-    }
-
-    const StageDesc& st = P->st[C.stage];
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r0 = blockIdx.x * kFwdRows + lane * 4;
-    const int* nzi = nzbuf(P, b, C.par);
-    const double* x = xbuf(P, b, C.par);
-    const int nnz = C.n_nz;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int base = 0; base < nnz; base += kFwdBlock) {
-        const int cnt = min(kFwdBlock, nnz - base);
-        if ((int)threadIdx.x < cnt) {
-            const int j = list_get(nzi, s_zpre, C.nseg_nz, base + threadIdx.x);
-            s_j[threadIdx.x] = j;
-            s_x[threadIdx.x] = x[j];
-        }
-        __syncthreads();
-        const int per = (cnt + 15) / 16;
-        const int k0 = w * per, k1 = min(cnt, k0 + per);
-        if (r0 < N) {
-            for (int k = k0; k < k1; ++k) fwd_accumulate(st, N, s_j[k], s_x[k], r0, acc);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) s_u[w * kFwdRows + lane * 4 + v] = acc[v];
-    __syncthreads();
-    // rho = y - u and the stored direction z (rho itself, or its FP32 / BF16
-    // rounding when the stage's matrix-core product takes that input type)
-    const int zround = (st.kind == kKron && st.dtype == SL1_BF16) ? 2 : ((st.kind == kKron && st.dtype == SL1_F32) ? 1 : 0);
-    double sums[3] = {0.0, 0.0, 0.0};
-    const int row = blockIdx.x * kFwdRows + threadIdx.x;
-    if (threadIdx.x < kFwdRows && row < N) {
-        double u = 0.0;
-        for (int q = 0; q < 16; ++q) u += s_u[q * kFwdRows + threadIdx.x];
-        const double yv = yval(P, b, row);
-        const double rho = yv - u;
-        double zd = rho;
-        if (zround == 1) zd = (double)(float)rho;
-        else if (zround == 2) zd = (double)bf16_rne((float)rho);
-        P->z[(size_t)b * N + row] = zd;
-        sums[0] = rho * rho;
-        sums[1] = zd * zd;
-        sums[2] = yv * zd;
-    }
-    block_sum<3>(sums, s_red);
-    if (threadIdx.x == 0) {
-        double* rp = P->res_part + ((size_t)b * P->nrc + blockIdx.x) * 3;
-        rp[0] = sums[0];
-        rp[1] = sums[1];
-        rp[2] = sums[2];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// adjoint: dense streaming correlations over the compacted preserved set
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double dense_dot(const StageDesc& st, int N, int j, const double* zs, int lane) {
-    double acc = 0.0;
-    const size_t off = (size_t)j * N;
-    if (st.dtype == SL1_F64) {
-        const double* col = (const double*)st.A + off;
-        for (int k = lane * 4; k < N; k += 256) {
-            const f64v2* p = (const f64v2*)(col + k);
-            f64v2 a = p[0], c = p[1];
-            acc += a[0] * zs[k] + a[1] * zs[k + 1] + c[0] * zs[k + 2] + c[1] * zs[k + 3];
-        }
-    } else if (st.dtype == SL1_F32) {
-        const float* col = (const float*)st.A + off;
-#pragma unroll 4
-        for (int k = lane * 4; k < N; k += 256) {
-            f32v4 a = *(const f32v4*)(col + k);
-            acc += (double)a[0] * zs[k] + (double)a[1] * zs[k + 1] +
-                   (double)a[2] * zs[k + 2] + (double)a[3] * zs[k + 3];
-        }
-    } else if (st.dtype == SL1_BF16) {
-        const uint16_t* col = (const uint16_t*)st.A + off;
-        if (st.vec == 8) {
-#pragma unroll 2
-            for (int k = lane * 8; k < N; k += 512) {
-                u16x8 a = *(const u16x8*)(col + k);
-#pragma unroll
-                for (int v = 0; v < 8; ++v) acc += (double)bf16_to_f(a[v]) * zs[k + v];
+    int cur_b = -1, finished = 0;
+    Control C;
+    for (int g = g0; g < g1; ++g) {
+        const int b = find_signal(s_wpre, batch, g);
+        const int item = g - s_wpre[b];
+        if (b != cur_b) {
+            cur_b = b;
+            const Control Cp = P->ctrl[2 * b + prev];
+            if (Cp.done) {           // finished in an earlier launch: nothing to do
+                finished = 1;
+                continue;
             }
-        } else {
-            for (int k = lane * 4; k < N; k += 256) {
-                u16x4 a = *(const u16x4*)(col + k);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc += (double)bf16_to_f(a[v]) * zs[k + v];
-            }
-        }
-    } else {
-        const uint8_t* col = (const uint8_t*)st.A + off;
-        if (st.vec == 16) {
-            for (int k = lane * 16; k < N; k += 1024) {
-                u32x4 q = *(const u32x4*)(col + k);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[w], false);
-                    auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q[w], true);
-                    const int kk = k + 4 * w;
-                    acc += (double)lo[0] * zs[kk] + (double)lo[1] * zs[kk + 1] +
-                           (double)hi[0] * zs[kk + 2] + (double)hi[1] * zs[kk + 3];
+            Scalars S;
+            double kt = 0.0;
+            finished = advance_control(P, b, Cp, C, s_apre, s_zpre, s_red, s_tmp, S, kt);
+            if (finished) {
+                if (item == 0 && threadIdx.x == 0) {
+                    Final F;
+                    F.gap = S.Gt;
+                    F.gap_cert = S.Gp + S.delta;
+                    F.iters = Cp.iter;
+                    F.stage = Cp.stage;
+                    F.status = S.conv == 2 ? SL1_MAXITER : SL1_OK;
+                    F.par = Cp.par;
+                    F.t0 = Cp.t0;
+                    F.tconv = S.tconv;
+                    P->fin[b] = F;
+                    Control D = Cp;
+                    D.done = 1;
+                    D.advance = 0;
+                    P->ctrl[2 * b + slot] = D;
+                    P->ctrl[2 * b + prev] = D;   // other blocks read Cp here: done or not, they write nothing
+                    P->cnt_adj[b] = 0;
+                    P->cnt_upd[b] = 0;
+                    P->cnt_fwd[(size_t)prev * batch + b] = 0;
+                    atomicSub(P->active_signals, 1);
+                }
+            } else {
+                if (!Cp.advance) {
+                    const int* zp = nzpre(P, b, C.par);
+                    for (int s = threadIdx.x; s <= C.nseg_nz; s += kFwdBlock) s_zpre[s] = zp[s];
+                    __syncthreads();
+                }
+                if (item == 0) {
+                    if (Cp.advance) {
+                        int* ap = actpre(P, b, C.par);
+                        int* zp = nzpre(P, b, C.par);
+                        for (int s = threadIdx.x; s <= C.nseg_act; s += kFwdBlock) {
+                            ap[s] = s_apre[s];
+                            zp[s] = s_zpre[s];
+                        }
+                    }
+                    if (threadIdx.x == 0) {
+                        Control D = C;
+                        D.advance = 1;
+                        P->ctrl[2 * b + slot] = D;
+                        P->cnt_adj[b] = adj_items(P->st[C.stage], C.n_act, N);
+                        P->cnt_upd[b] = max(1, (C.n_act + kSeg - 1) / kSeg);
+                        if (Cp.advance && P->trace && Cp.iter < P->trace_cap) {
+                            double* tr = P->trace + ((size_t)b * P->trace_cap + Cp.iter) * SL1_TRACE_FIELDS;
+                            tr[0] = Cp.iter; tr[1] = Cp.stage; tr[2] = Cp.n_act; tr[3] = C.n_act;
+                            tr[4] = kt;
+                            tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = S.Rp; tr[9] = S.gamma;
+                            tr[10] = Cp.l1; tr[11] = S.P;
+                        }
+                    }
                 }
             }
-        } else {
-#pragma unroll 2
-            for (int k = lane * 4; k < N; k += 256) {
-                const uint32_t q = *(const uint32_t*)(col + k);
-                auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
-                auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
-                acc += (double)lo[0] * zs[k] + (double)lo[1] * zs[k + 1] +
-                       (double)hi[0] * zs[k + 2] + (double)hi[1] * zs[k + 3];
+        }
+        if (finished) continue;
+
+        const StageDesc& st = P->st[C.stage];
+        const int r0 = item * kFwdRows + lane * 4;
+        const int* nzi = nzbuf(P, b, C.par);
+        const double* x = xbuf(P, b, C.par);
+        const int nnz = C.n_nz;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int base = 0; base < nnz; base += kFwdBlock) {
+            const int cnt = min(kFwdBlock, nnz - base);
+            if ((int)threadIdx.x < cnt) {
+                const int j = list_get(nzi, s_zpre, C.nseg_nz, base + threadIdx.x);
+                s_j[threadIdx.x] = j;
+                s_x[threadIdx.x] = x[j];
             }
+            __syncthreads();
+            const int pw = (cnt + kFwdWaves - 1) / kFwdWaves;
+            const int k0 = w * pw, k1 = min(cnt, k0 + pw);
+            if (r0 < N) {
+                for (int k = k0; k < k1; ++k) fwd_accumulate(st, N, s_j[k], s_x[k], r0, acc);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s_u[w * kFwdRows + lane * 4 + v] = acc[v];
+        __syncthreads();
+        // rho = y - u and the stored direction z (rho itself, or its FP32 / BF16
+        // rounding when the stage's matrix-core product takes that input type)
+        const int zround = (st.kind == kKron && st.dtype == SL1_BF16) ? 2 : ((st.kind == kKron && st.dtype == SL1_F32) ? 1 : 0);
+        double sums[3] = {0.0, 0.0, 0.0};
+        const int row = item * kFwdRows + threadIdx.x;
+        if (threadIdx.x < kFwdRows && row < N) {
+            double u = 0.0;
+            for (int q = 0; q < kFwdWaves; ++q) u += s_u[q * kFwdRows + threadIdx.x];
+            const double yv = yval(P, b, row);
+            const double rho = yv - u;
+            double zd = rho;
+            if (zround == 1) zd = (double)(float)rho;
+            else if (zround == 2) zd = (double)bf16_rne((float)rho);
+            P->z[(size_t)b * N + row] = zd;
+            sums[0] = rho * rho;
+            sums[1] = zd * zd;
+            sums[2] = yv * zd;
+        }
+        block_sum<3>(sums, s_red);
+        if (threadIdx.x == 0) {
+            double* rp = P->res_part + ((size_t)b * P->nrc + item) * 3;
+            rp[0] = sums[0];
+            rp[1] = sums[1];
+            rp[2] = sums[2];
         }
     }
-    acc = wave_sum(acc);
-    if (st.scale) acc *= (double)st.scale[j];
-    return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -703,145 +713,237 @@ __device__ __forceinline__ double clip_scale(double s0, double m) {
 }
 
 // ---------------------------------------------------------------------------
-// correlations over the preserved set: g_j = a~_j^T z for j in A_t, and the
-// per-block maxima of the stable dual scaling (Section III-C)
+// dense correlations: NA atoms per wave streamed together (their loads are in
+// flight at once), FP64 accumulation of the decoded storage values
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int adj_items(const StageDesc& st, int n_act) {
-    if (st.kind == kDense) return max(1, (n_act + kAdjAtoms - 1) / kAdjAtoms);
-    return (st.k2 / 16) * ((st.k1 + kKronColTile - 1) / kKronColTile);
-}
-
-__device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double& r2, double& zz, double& yz) {
-    r2 = zz = yz = 0.0;
-    for (int k = 0; k < P->nrc; ++k) {
-        const double* rp = P->res_part + ((size_t)b * P->nrc + k) * 3;
-        r2 += rp[0];
-        zz += rp[1];
-        yz += rp[2];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ P, int slot) {
-    extern __shared__ __align__(16) char smem[];
-    const int b = blockIdx.y;
-    const Control& Cg = P->ctrl[2 * b + slot];
-    if (Cg.done) return;
-    const int N = P->N, K = P->K;
-    const int stage = Cg.stage, n_act = Cg.n_act, par = Cg.par, nseg_act = Cg.nseg_act;
-    const StageDesc& st = P->st[stage];
-    const int c = blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nitems = adj_items(st, n_act);
-    if (c >= nitems) return;
-    double r2, zz, yz;
-    reduce_res(P, b, r2, zz, yz);
-    const double rz = sqrt(zz);
-
-    // z in LDS: FP64 for dense and FP64 Kronecker stages, FP32 (exact copy of
-    // the rounded direction) for FP32 / BF16 Kronecker stages
-    const bool zf32 = st.kind == kKron && st.dtype != SL1_F64;
-    const size_t zbytes = ((size_t)N * 8 + 15) & ~(size_t)15;
-    int* s_pre = (int*)(smem + zbytes);
-    char* extra = smem + zbytes + (((size_t)(P->nseg_max + 1) * 4 + 15) & ~(size_t)15);
-    __shared__ double s_red[48];
-
-    const double* zg = P->z + (size_t)b * N;
-    if (zf32) {
-        float* zsf = (float*)smem;
-        for (int i = threadIdx.x; i < N; i += kBlock) zsf[i] = (float)zg[i];
+template <int DT>
+__device__ __forceinline__ void load4(const void* A, size_t idx, double (&v)[4]) {
+    if constexpr (DT == SL1_F64) {
+        const f64v2* p = (const f64v2*)((const double*)A + idx);
+        const f64v2 a = p[0], c = p[1];
+        v[0] = a[0]; v[1] = a[1]; v[2] = c[0]; v[3] = c[1];
+    } else if constexpr (DT == SL1_F32) {
+        const f32v4 a = *(const f32v4*)((const float*)A + idx);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+    } else if constexpr (DT == SL1_BF16) {
+        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
+        v[0] = bf16_to_f(a[0]); v[1] = bf16_to_f(a[1]); v[2] = bf16_to_f(a[2]); v[3] = bf16_to_f(a[3]);
     } else {
-        double* zsd = (double*)smem;
-        for (int i = threadIdx.x * 2; i < N; i += kBlock * 2) *(f64v2*)(zsd + i) = *(const f64v2*)(zg + i);
+        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+        v[0] = lo[0]; v[1] = lo[1]; v[2] = hi[0]; v[3] = hi[1];
     }
-    const double* zs = (const double*)smem;
-    double* g = gbuf(P, b, par);
-    double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over A_t
+}
 
-    if (st.kind == kDense) {
-        load_pre(s_pre, actpre(P, b, par), nseg_act);   // includes __syncthreads (z ready)
-        const int* act = actbuf(P, b, par);
-        const int first = c * kAdjAtoms + w * (kAdjAtoms / 4);
-        const int last = min(n_act, first + kAdjAtoms / 4);
-        for (int i = first; i < last; ++i) {
-            const int j = list_get(act, s_pre, nseg_act, i);
-            const double gj = dense_dot(st, N, j, zs, lane);
-            if (lane == 0) {
-                g[j] = gj;
+template <int DT, int NA>
+__device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const int (&js)[NA], const double* zs,
+                                             int lane, double (&out)[NA]) {
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    for (int k = lane * 4; k < N; k += 256) {
+        double a[NA][4];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) load4<DT>(st.A, (size_t)js[q] * N + k, a[q]);
+        const double z0 = zs[k], z1 = zs[k + 1], z2 = zs[k + 2], z3 = zs[k + 3];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) acc[q] += a[q][0] * z0 + a[q][1] * z1 + a[q][2] * z2 + a[q][3] * z3;
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        out[q] = wave_sum(acc[q]);
+        if (st.scale) out[q] *= (double)st.scale[js[q]];
+    }
+}
+
+template <int NA>
+__device__ __forceinline__ void dense_dots(const StageDesc& st, int N, const int (&js)[NA], const double* zs, int lane,
+                                           double (&out)[NA]) {
+    switch (st.dtype) {
+        case SL1_F64: dense_dots_t<SL1_F64, NA>(st, N, js, zs, lane, out); break;
+        case SL1_F32: dense_dots_t<SL1_F32, NA>(st, N, js, zs, lane, out); break;
+        case SL1_BF16: dense_dots_t<SL1_BF16, NA>(st, N, js, zs, lane, out); break;
+        default: dense_dots_t<SL1_FP8_E4M3, NA>(st, N, js, zs, lane, out); break;
+    }
+}
+
+template <int NA>
+__device__ __forceinline__ void dense_item(const SolveParams* P, const StageDesc& st, int N, const int* act,
+                                           const int* s_pre, int nseg, int n_act, int first, const double* zs,
+                                           double rz, double* g, int lane, double (&mx)[3]) {
+    int js[NA];
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int i = first + q;
+        js[q] = i < n_act ? list_get(act, s_pre, nseg, i) : -1;
+        cnt += i < n_act;
+    }
+    if (cnt == 0) return;
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+        if (js[q] < 0) js[q] = js[0];
+    double gv[NA];
+    dense_dots<NA>(st, N, js, zs, lane, gv);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            if (q < cnt) {
+                const int j = js[q];
+                g[j] = gv[q];
                 const double e = st.eps[j];
-                mx[0] = fmax(mx[0], fabs(gj) + e * rz);
-                mx[1] = fmax(mx[1], fabs(gj));
+                mx[0] = fmax(mx[0], fabs(gv[q]) + e * rz);
+                mx[1] = fmax(mx[1], fabs(gv[q]));
                 mx[2] = fmax(mx[2], e);
             }
         }
-    } else {
-        __syncthreads();
-        const int ntc = (st.k1 + kKronColTile - 1) / kKronColTile;
-        const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;
-        const int li = lane & 15, lk = lane >> 4;
-        const uint8_t* mask = P->mask + (size_t)b * K;
-        if (st.dtype == SL1_F64) {
-            double* Vall = (double*)extra;
-            double* red = Vall + 4 * 16 * P->n1_max;
-            f64x4 acc[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-            kron_tile_f64(st, a0, cb0, zs, Vall, acc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
+    }
+}
+
+__device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double* s_red, double& r2, double& zz,
+                                           double& yz) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < P->nrc; k += blockDim.x) {
+        const double* rp = P->res_part + ((size_t)b * P->nrc + k) * 3;
+        v[0] += rp[0];
+        v[1] += rp[1];
+        v[2] += rp[2];
+    }
+    block_sum<3>(v, s_red);
+    r2 = v[0];
+    zz = v[1];
+    yz = v[2];
+}
+
+// ---------------------------------------------------------------------------
+// correlations over the preserved set: g_j = a~_j^T z for j in A_t, and the
+// per-item maxima of the stable dual scaling (Section III-C)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock, 3) void k_adj(const SolveParams* __restrict__ P, int slot) {
+    extern __shared__ __align__(16) char smem[];
+    const int N = P->N, K = P->K, batch = P->batch;
+    const size_t zbytes = ((size_t)N * 8 + 15) & ~(size_t)15;
+    int* s_pre = (int*)(smem + zbytes);
+    int* s_wpre = s_pre + (P->nseg_max + 1);
+    char* extra = smem + zbytes + ((((size_t)(P->nseg_max + 1) + batch + 1) * 4 + 15) & ~(size_t)15);
+    __shared__ double s_red[48];
+    __shared__ int s_tmp[16];
+    const int total = build_work_map(P->cnt_adj, batch, s_wpre, s_tmp);
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int cur_b = -1;
+    Control C;
+    double rz = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const int b = find_signal(s_wpre, batch, g);
+        const int c = g - s_wpre[b];
+        const StageDesc* stp;
+        if (b != cur_b) {
+            cur_b = b;
+            C = P->ctrl[2 * b + slot];
+            double r2, zz, yz;
+            reduce_res(P, b, s_red, r2, zz, yz);
+            rz = sqrt(zz);
+            const StageDesc& st0 = P->st[C.stage];
+            const bool zf32 = st0.kind == kKron && st0.dtype != SL1_F64;
+            const double* zg = P->z + (size_t)b * N;
+            if (zf32) {
+                float* zsf = (float*)smem;
+                for (int i = threadIdx.x; i < N; i += kBlock) zsf[i] = (float)zg[i];
+            } else {
+                double* zsd = (double*)smem;
+                for (int i = threadIdx.x * 2; i < N; i += kBlock * 2) *(f64v2*)(zsd + i) = *(const f64v2*)(zg + i);
+            }
+            if (st0.kind == kDense) {
+                const int* ap = actpre(P, b, C.par);
+                for (int s = threadIdx.x; s <= C.nseg_act; s += kBlock) s_pre[s] = ap[s];
+            }
             __syncthreads();
-            for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
-                const int i = o >> 6, col = o & 63;
-                if (cb0 + col < st.k1) {
-                    const double s = ((red[(0 * 16 + i) * 64 + col] + red[(1 * 16 + i) * 64 + col]) +
-                                      red[(2 * 16 + i) * 64 + col]) + red[(3 * 16 + i) * 64 + col];
-                    const int j = (cb0 + col) * st.k2 + a0 + i;
-                    g[j] = s;
-                    if (mask[j]) {
-                        const double e = st.eps[j];
-                        mx[0] = fmax(mx[0], fabs(s) + e * rz);
-                        mx[1] = fmax(mx[1], fabs(s));
-                        mx[2] = fmax(mx[2], e);
+        }
+        stp = &P->st[C.stage];
+        const StageDesc& st = *stp;
+        const double* zs = (const double*)smem;
+        double* gvec = gbuf(P, b, C.par);
+        double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over A_t
+
+        if (st.kind == kDense) {
+            const int apw = dense_apw(N);
+            const int* act = actbuf(P, b, C.par);
+            const int first = (c * 4 + w) * apw;
+            if (apw == 4) dense_item<4>(P, st, N, act, s_pre, C.nseg_act, C.n_act, first, zs, rz, gvec, lane, mx);
+            else if (apw == 2) dense_item<2>(P, st, N, act, s_pre, C.nseg_act, C.n_act, first, zs, rz, gvec, lane, mx);
+            else dense_item<1>(P, st, N, act, s_pre, C.nseg_act, C.n_act, first, zs, rz, gvec, lane, mx);
+        } else {
+            const int ntc = (st.k1 + kKronColTile - 1) / kKronColTile;
+            const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;
+            const int li = lane & 15, lk = lane >> 4;
+            const uint8_t* mask = P->mask + (size_t)b * K;
+            if (st.dtype == SL1_F64) {
+                double* Vall = (double*)extra;
+                double* red = Vall + 4 * 16 * P->n1_max;
+                f64x4 acc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+                kron_tile_f64(st, a0, cb0, zs, Vall, acc);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
+                __syncthreads();
+                for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
+                    const int i = o >> 6, col = o & 63;
+                    if (cb0 + col < st.k1) {
+                        const double s = ((red[(0 * 16 + i) * 64 + col] + red[(1 * 16 + i) * 64 + col]) +
+                                          red[(2 * 16 + i) * 64 + col]) + red[(3 * 16 + i) * 64 + col];
+                        const int j = (cb0 + col) * st.k2 + a0 + i;
+                        gvec[j] = s;
+                        if (mask[j]) {
+                            const double e = st.eps[j];
+                            mx[0] = fmax(mx[0], fabs(s) + e * rz);
+                            mx[1] = fmax(mx[1], fabs(s));
+                            mx[2] = fmax(mx[2], e);
+                        }
                     }
                 }
-            }
-        } else {
-            float* red = (float*)extra;
-            char* vspace = extra + 4 * 16 * 64 * sizeof(float);
-            f32x4 acc[4];
+            } else {
+                float* red = (float*)extra;
+                char* vspace = extra + 4 * 16 * 64 * sizeof(float);
+                f32x4 acc[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)smem, (float*)vspace, acc);
-            else kron_tile_bf16(st, a0, cb0, (const float*)smem, (uint16_t*)vspace, acc);
+                for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)smem, (float*)vspace, acc);
+                else kron_tile_bf16(st, a0, cb0, (const float*)smem, (uint16_t*)vspace, acc);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
-            __syncthreads();
-            for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
-                const int i = o >> 6, col = o & 63;
-                if (cb0 + col < st.k1) {
-                    const double s = (((double)red[(0 * 16 + i) * 64 + col] + (double)red[(1 * 16 + i) * 64 + col]) +
-                                      (double)red[(2 * 16 + i) * 64 + col]) + (double)red[(3 * 16 + i) * 64 + col];
-                    const int j = (cb0 + col) * st.k2 + a0 + i;
-                    g[j] = s;
-                    if (mask[j]) {
-                        const double e = st.eps[j];
-                        mx[0] = fmax(mx[0], fabs(s) + e * rz);
-                        mx[1] = fmax(mx[1], fabs(s));
-                        mx[2] = fmax(mx[2], e);
+                    for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
+                __syncthreads();
+                for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
+                    const int i = o >> 6, col = o & 63;
+                    if (cb0 + col < st.k1) {
+                        const double s = (((double)red[(0 * 16 + i) * 64 + col] + (double)red[(1 * 16 + i) * 64 + col]) +
+                                          (double)red[(2 * 16 + i) * 64 + col]) + (double)red[(3 * 16 + i) * 64 + col];
+                        const int j = (cb0 + col) * st.k2 + a0 + i;
+                        gvec[j] = s;
+                        if (mask[j]) {
+                            const double e = st.eps[j];
+                            mx[0] = fmax(mx[0], fabs(s) + e * rz);
+                            mx[1] = fmax(mx[1], fabs(s));
+                            mx[2] = fmax(mx[2], e);
+                        }
                     }
                 }
             }
         }
-    }
-    block_max<3>(mx, s_red);
-    if (threadIdx.x == 0) {
-        double* ap = P->adj_part + ((size_t)b * P->nadj_max + c) * 3;
-        ap[0] = mx[0];
-        ap[1] = mx[1];
-        ap[2] = mx[2];
+        block_max<3>(mx, s_red);
+        if (threadIdx.x == 0) {
+            double* ap = P->adj_part + ((size_t)b * P->nadj_max + c) * 3;
+            ap[0] = mx[0];
+            ap[1] = mx[1];
+            ap[2] = mx[2];
+        }
     }
 }
 
@@ -852,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_adj(const SolveParams* __restrict__ 
 // ---------------------------------------------------------------------------
 __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scalars& S, double* s_red) {
     const StageDesc& st = P->st[C.stage];
-    const int nitems = adj_items(st, C.n_act);
+    const int nitems = adj_items(st, C.n_act, P->N);
     double mx[3] = {0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < nitems; k += blockDim.x) {
         const double* ap = P->adj_part + ((size_t)b * P->nadj_max + k) * 3;
@@ -862,7 +964,7 @@ __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scal
     }
     block_max<3>(mx, s_red);
     double r2, zz, yz;
-    reduce_res(P, b, r2, zz, yz);
+    reduce_res(P, b, s_red, r2, zz, yz);
     const double lam = C.lam, l1 = C.l1;
     const double mp = mx[0], mt = mx[1], E = mx[2];
     const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;     // projection of y/lam on z
@@ -896,7 +998,8 @@ __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scal
 
 // ---------------------------------------------------------------------------
 // test + FISTA update + compaction (Table I stable GAP Safe row; Algorithm 1
-// screening step; Section IV-C look-ahead count)
+// screening step; Section IV-C look-ahead count).  Item = segment of 256
+// entries of the preserved set.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int block_excl_scan_flag(bool f, int* s_w, int& total) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -913,76 +1016,89 @@ __device__ __forceinline__ int block_excl_scan_flag(bool f, int* s_w, int& total
 
 __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
-    const int b = blockIdx.y;
-    const Control C = P->ctrl[2 * b + slot];
-    if (C.done) return;
-    const int c = blockIdx.x;
-    const int K = P->K, n_act = C.n_act, par = C.par;
-    const int nblk = max(1, (n_act + kSeg - 1) / kSeg);
-    if (c >= nblk) return;
+    const int K = P->K, batch = P->batch;
+    int* s_pre = (int*)smem;
+    int* s_wpre = s_pre + (P->nseg_max + 1);
     __shared__ double s_red[48];
     __shared__ int s_w[4];
+    __shared__ int s_tmp[16];
+    const int total = build_work_map(P->cnt_upd, batch, s_wpre, s_tmp);
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
+    int cur_b = -1;
+    Control C;
     Scalars S;
-    scalar_block(P, b, C, S, s_red);
-    if (c == 0 && threadIdx.x == 0) {
-        if (S.conv == 1) S.tconv = wall_clock64();
-        P->sc[b] = S;
-    }
-    if (S.conv) return;
-
-    const StageDesc& st = P->st[C.stage];
-    int* s_pre = (int*)smem;
-    load_pre(s_pre, actpre(P, b, par), C.nseg_act);
-    const int i = c * kSeg + threadIdx.x;
-    const bool valid = i < n_act;
-    int j = 0;
-    bool keep = false, nzf = false;
-    double kt = 0.0, l1 = 0.0;
-    if (valid) {
-        j = list_get(actbuf(P, b, par), s_pre, C.nseg_act, i);
-        double* xc = xbuf(P, b, par);
-        double* xo = xbuf(P, b, 1 - par);
-        const double gt = gbuf(P, b, par)[j];
-        const double gp = gbuf(P, b, 1 - par)[j];
-        const double xt = xc[j];
-        const double xp = xo[j];
-        const double e = st.eps[j];
-        const double ag = fabs(gt);
-        // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
-        const double mu = S.c1 * ag + e * S.c2 + S.Rp * P->atom_norm[j];
-        keep = mu >= 1.0 - P->margin;
-        // look-ahead: conventional test on the approximate atom
-        kt = (S.c1 * ag + S.Rp * st.at_norm[j] >= 1.0) ? 1.0 : 0.0;
-        // FISTA step on the preserved coefficients; the gradient at the
-        // extrapolated point follows from the two correlation vectors by linearity
-        const double beta = S.beta;
-        const double zpt = xt + beta * (xt - xp);
-        const double h = (1.0 + beta) * gt - beta * gp;
-        const double v = zpt + h * st.invL;
-        const double thr = C.lam * st.invL;
-        double xn = 0.0;
-        if (keep) xn = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
-        xo[j] = xn;
-        if (!keep) {
-            xc[j] = 0.0;
-            P->mask[(size_t)b * K + j] = 0;
+    for (int g = g0; g < g1; ++g) {
+        const int b = find_signal(s_wpre, batch, g);
+        const int c = g - s_wpre[b];
+        if (b != cur_b) {
+            cur_b = b;
+            C = P->ctrl[2 * b + slot];
+            scalar_block(P, b, C, S, s_red);
+            const int* ap = actpre(P, b, C.par);
+            for (int s = threadIdx.x; s <= C.nseg_act; s += kBlock) s_pre[s] = ap[s];
+            __syncthreads();
         }
-        nzf = keep && (xn != 0.0);
-        l1 = fabs(xn);
-    }
-    int tot_keep, tot_nz;
-    const int pk = block_excl_scan_flag(keep, s_w, tot_keep);
-    if (keep) actbuf(P, b, 1 - par)[c * kSeg + pk] = j;
-    const int pz = block_excl_scan_flag(nzf, s_w, tot_nz);
-    if (nzf) nzbuf(P, b, 1 - par)[c * kSeg + pz] = j;
-    double sums[2] = {kt, l1};
-    block_sum<2>(sums, s_red);
-    if (threadIdx.x == 0) {
-        double* up = P->upd_part + ((size_t)b * P->nseg_max + c) * 4;
-        up[0] = (double)tot_keep;
-        up[1] = (double)tot_nz;
-        up[2] = sums[0];
-        up[3] = sums[1];
+        if (c == 0 && threadIdx.x == 0) {
+            Scalars T = S;
+            if (T.conv == 1) T.tconv = wall_clock64();
+            P->sc[b] = T;
+            P->cnt_fwd[(size_t)(1 - slot) * batch + b] = P->nrc;
+        }
+        if (S.conv) continue;
+        const int par = C.par, n_act = C.n_act;
+        const StageDesc& st = P->st[C.stage];
+        const int i = c * kSeg + threadIdx.x;
+        const bool valid = i < n_act;
+        int j = 0;
+        bool keep = false, nzf = false;
+        double kt = 0.0, l1 = 0.0;
+        if (valid) {
+            j = list_get(actbuf(P, b, par), s_pre, C.nseg_act, i);
+            double* xc = xbuf(P, b, par);
+            double* xo = xbuf(P, b, 1 - par);
+            const double gt = gbuf(P, b, par)[j];
+            const double gp = gbuf(P, b, 1 - par)[j];
+            const double xt = xc[j];
+            const double xp = xo[j];
+            const double e = st.eps[j];
+            const double ag = fabs(gt);
+            // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
+            const double mu = S.c1 * ag + e * S.c2 + S.Rp * P->atom_norm[j];
+            keep = mu >= 1.0 - P->margin;
+            // look-ahead: conventional test on the approximate atom
+            kt = (S.c1 * ag + S.Rp * st.at_norm[j] >= 1.0) ? 1.0 : 0.0;
+            // FISTA step on the preserved coefficients; the gradient at the
+            // extrapolated point follows from the two correlation vectors by linearity
+            const double beta = S.beta;
+            const double zpt = xt + beta * (xt - xp);
+            const double h = (1.0 + beta) * gt - beta * gp;
+            const double v = zpt + h * st.invL;
+            const double thr = C.lam * st.invL;
+            double xn = 0.0;
+            if (keep) xn = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
+            xo[j] = xn;
+            if (!keep) {
+                xc[j] = 0.0;
+                P->mask[(size_t)b * K + j] = 0;
+            }
+            nzf = keep && (xn != 0.0);
+            l1 = fabs(xn);
+        }
+        int tot_keep, tot_nz;
+        const int pk = block_excl_scan_flag(keep, s_w, tot_keep);
+        if (keep) actbuf(P, b, 1 - par)[c * kSeg + pk] = j;
+        const int pz = block_excl_scan_flag(nzf, s_w, tot_nz);
+        if (nzf) nzbuf(P, b, 1 - par)[c * kSeg + pz] = j;
+        double sums[2] = {kt, l1};
+        block_sum<2>(sums, s_red);
+        if (threadIdx.x == 0) {
+            double* up = P->upd_part + ((size_t)b * P->nseg_max + c) * 4;
+            up[0] = (double)tot_keep;
+            up[1] = (double)tot_nz;
+            up[2] = sums[0];
+            up[3] = sums[1];
+        }
     }
 }
 
@@ -1014,11 +1130,16 @@ __global__ void k_lambda_out(const SolveParams* __restrict__ P, double* out, int
     if (b >= P->batch) return;
     const Control& C = P->ctrl[2 * b];
     const StageDesc& st = P->st[0];
-    const int nitems = adj_items(st, C.n_act);
+    const int nitems = adj_items(st, C.n_act, P->N);
     double mp = 0.0;
     for (int k = 0; k < nitems; ++k) mp = fmax(mp, P->adj_part[((size_t)b * P->nadj_max + k) * 3]);
-    double r2, zz, yz;
-    reduce_res(P, b, r2, zz, yz);
+    double r2 = 0.0, zz = 0.0, yz = 0.0;
+    for (int k = 0; k < P->nrc; ++k) {
+        const double* rp = P->res_part + ((size_t)b * P->nrc + k) * 3;
+        r2 += rp[0];
+        zz += rp[1];
+        yz += rp[2];
+    }
     // when z is a rounded copy of y (BF16 Kronecker stages) add the bound
     // ||y - z|| (max ||a~_j|| + max eps_j)
     const bool rounded = st.kind == kKron && st.dtype == SL1_BF16;
@@ -1103,9 +1224,9 @@ hipError_t launch_init(const SolveParams* dP, const LaunchCfg& c, hipStream_t s)
 }
 
 hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    if (which == 0) hipLaunchKernelGGL(k_fwd, dim3(c.nrc, c.batch), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
-    else if (which == 1) hipLaunchKernelGGL(k_adj, dim3(c.nadj_max, c.batch), dim3(kBlock), c.lds_adj, s, dP, slot);
-    else hipLaunchKernelGGL(k_upd, dim3(c.nseg_max, c.batch), dim3(kBlock), c.lds_upd, s, dP, slot);
+    if (which == 0) hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
+    else if (which == 1) hipLaunchKernelGGL(k_adj, dim3(c.g_adj), dim3(kBlock), c.lds_adj, s, dP, slot);
+    else hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
     return hipGetLastError();
 }
 
