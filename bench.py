@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-single", action="store_true", help="skip the single-signal block")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled oracle parity check")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -199,6 +201,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.calibrate_copy:
+        # known traffic: each copy reads and writes 2^30 bytes
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": 2 ** 30,
+                          "bytes_written_per_copy": 2 ** 30, "copies": 3}))
+        return
     import synth
     import paper_1812_06635_amd as sl1
     torch.cuda.set_device(0)
