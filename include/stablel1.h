@@ -112,7 +112,9 @@ typedef struct {
     double margin;       /* [1e-12] reject atom j iff its test value < 1 - margin */
     int32_t max_iter;    /* [100000] iteration cap per signal */
     int32_t y_dtype;     /* [SL1_F32] storage type of the signals y: SL1_F64 or SL1_F32 */
-    int32_t chunk;       /* [16] iterations enqueued between two convergence polls */
+    int32_t chunk;       /* [16] grid engine: iterations enqueued between two convergence polls
+                            (rounded up to even); whole-solve engine: at most 256*chunk
+                            iterations per launch */
     int32_t flags;       /* [0] SL1_FLAG_* */
     double* trace;       /* [NULL] optional device buffer, batch x trace_cap x SL1_TRACE_FIELDS
                             doubles: per iteration t, stage, |A_t|, |A_t+1|, K_t, G(x,theta'|A~),
@@ -123,6 +125,21 @@ typedef struct {
 
 #define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */
 #define SL1_FLAG_PROFILE 2    /* direct launches bracketed by HIP events; see sl1_last_solve_profile */
+#define SL1_FLAG_ENGINE_GRID 4  /* force the per-iteration grid engine */
+#define SL1_FLAG_ENGINE_WG 8    /* force the whole-solve engine (SL1_ELIMIT if its LDS need exceeds 159 KB) */
+
+/* Engines (sl1_last_solve_phases):
+ *   SL1_ENGINE_GRID  three persistent launches per iteration covering every live
+ *                    signal (any size within the limits; captured in hipGraph chunks);
+ *   SL1_ENGINE_WG    one 512-thread workgroup per signal runs the whole solve in one
+ *                    launch (per-signal z and the current stage's Kronecker factors in
+ *                    LDS).  Chosen by default when its LDS fits and N*K <= 2^20 (a
+ *                    dense stage is then cheap for one CU); launches are bounded and
+ *                    repeated while signals remain.
+ * Both compute every per-element quantity with the same expressions; results differ
+ * only by the order of FP64 reductions. */
+#define SL1_ENGINE_GRID 1
+#define SL1_ENGINE_WG 2
 
 int sl1_opts_default(sl1_opts* o);
 
@@ -220,6 +237,17 @@ int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, do
  * block, 2 test/update/compaction (host arrays of 3).
  */
 int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
+
+/*
+ * sl1_last_solve_phases -- engine of the most recent sl1_solve with these
+ * shapes (*engine = SL1_ENGINE_GRID or SL1_ENGINE_WG) and, for the whole-solve
+ * engine run with SL1_FLAG_PROFILE, phase_ms[4] (host, may be NULL): workgroup
+ * milliseconds summed over signals of forward/residual, dense correlations,
+ * Kronecker correlations, and test/update/compaction.  With the whole-solve
+ * engine, sl1_last_solve_profile reports the k_solve launches in ms[0] and
+ * launches[0].
+ */
+int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms);
 
 const char* sl1_status_str(int status);
 const char* sl1_version(void);

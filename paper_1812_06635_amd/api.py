@@ -113,11 +113,18 @@ def upload_stage(stage, device="cuda"):
     return Dict.kron(B, C, eps, stage.dtype)
 
 
+_ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG}
+
+
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
-          trace_cap=0, use_graph=True, profile=False, check=True):
+          trace_cap=0, use_graph=True, profile=False, check=True, engine="auto"):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
-    Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage,
-    the status code, and the trace (batch, trace_cap, 12) when requested."""
+    engine: "auto", "grid" (per-iteration launches) or "wg" (one workgroup per
+    signal for the whole solve).  Returns a dict of device tensors x, gap,
+    gap_cert, screened, iters, stage, the status code, and the trace
+    (batch, trace_cap, 12) when requested."""
+    if engine not in _ENGINES:
+        raise ValueError(f"engine must be one of {sorted(_ENGINES)}")
     if y.dtype not in (torch.float64, torch.float32):
         raise TypeError("y must be float32 or float64")
     _dev(y, None, "y")
@@ -137,7 +144,7 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.Gamma, opts.tol, opts.margin = Gamma, tol, margin
     opts.max_iter, opts.chunk = max_iter, chunk
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
-    opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0)
+    opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine]
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)
@@ -209,6 +216,17 @@ def last_solve_profile(batch, N, K):
     L.check(L.load().sl1_last_solve_profile(batch, N, K, ms, n), "sl1_last_solve_profile")
     names = ("fwd", "adj", "upd")
     return {names[k]: (ms[k], n[k]) for k in range(3)}
+
+
+def last_solve_phases(batch, N, K):
+    """(engine name, {phase: ms}) of the last solve of this shape; the phase
+    times (workgroup milliseconds summed over signals) are filled for the
+    whole-solve engine run with profile=True."""
+    eng = L.c_i32()
+    ph = (L.c_d * 4)()
+    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph), "sl1_last_solve_phases")
+    name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg"}.get(eng.value, "none")
+    return name, dict(zip(("fwd", "adj_dense", "adj_kron", "upd"), list(ph)))
 
 
 def grad(A, x, y, lam, dx):

@@ -27,6 +27,7 @@ hipError_t launch_adjoint_out(const SolveParams*, int, int, int, double*, double
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
+hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
 }  // namespace sl1
 
 using namespace sl1;
@@ -102,6 +103,9 @@ struct Workspace {
     int graph_chunk = 0;
     double prof_ms[3] = {0, 0, 0};
     long long prof_n[3] = {0, 0, 0};
+    long long* d_wgprof = nullptr;          // [batch][kWgPhases] phase clocks of the whole-solve engine
+    double phase_ms[kWgPhases] = {0, 0, 0, 0};
+    int last_engine = 0;
     std::vector<hipEvent_t> prof_ev;
     LaunchCfg graph_cfg{};
     std::mutex mu;
@@ -151,6 +155,7 @@ int make_workspace(Workspace& w) {
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
     const size_t o_times = take(B * 16);
+    const size_t o_wgprof = take(B * kWgPhases * 8);
     const size_t o_params = take(sizeof(SolveParams));
     if (hipMalloc(&w.mem, off) != hipSuccess) return SL1_ENOMEM;
     char* m = (char*)w.mem;
@@ -182,6 +187,7 @@ int make_workspace(Workspace& w) {
     w.d_active = p.active_signals;
     w.d_status = (int32_t*)(m + o_status);
     w.d_times = (long long*)(m + o_times);
+    w.d_wgprof = (long long*)(m + o_wgprof);
     w.dP = (SolveParams*)(m + o_params);
     if (hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) != hipSuccess) return SL1_EHIP;
     if (hipEventCreateWithFlags(&w.ev_in, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
@@ -281,6 +287,39 @@ int check_lds(const LaunchCfg& c) {
     return SL1_OK;
 }
 
+// Dynamic LDS of the whole-solve kernel: z (FP64 and FP32 copies), the factors
+// of the largest Kronecker stage, and a scratch shared by the forward staging /
+// row reduction (32 KB) and the Kronecker intermediate V.  0 if it does not fit.
+size_t wg_lds(SolveParams& p) {
+    auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    size_t fac = 0, scr = (size_t)(kWgWaves / 2) * 16 * 64 * 8;
+    for (int i = 0; i < p.n_stages; ++i) {
+        const StageDesc& s = p.st[i];
+        if (s.kind != kKron) continue;
+        const size_t es = s.dtype == SL1_F64 ? 8 : (s.dtype == SL1_F32 ? 4 : 2);
+        fac = std::max(fac, a16(((size_t)s.R * s.k1 * s.n1 + (size_t)s.R * s.k2 * s.n2) * es));
+        const size_t v = (size_t)s.R * s.k2 * s.n1 * (s.dtype == SL1_F64 ? 8 : 4);   // BF16: hi + lo
+        scr = std::max(scr, a16(v));
+    }
+    const size_t total = a16((size_t)p.N * 8) + a16((size_t)p.N * 4) + fac + scr;
+    const size_t lim = 160 * 1024 - 1024;   // static LDS of the kernel stays below 1 KB
+    if (total > lim || fac > (size_t)INT32_MAX || scr > (size_t)INT32_MAX) return 0;
+    p.wg_fac = (int)fac;
+    p.wg_scr = (int)scr;
+    return total;
+}
+
+// Iterations per whole-solve launch: bounded so that one launch streams at most
+// ~8 GB of dense dictionary per workgroup; the host relaunches while signals remain.
+int wg_iters_per_launch(const SolveParams& p) {
+    size_t es = 0;
+    for (int i = 0; i < p.n_stages; ++i)
+        if (p.st[i].kind == kDense) es = std::max(es, p.st[i].dtype == SL1_F64 ? (size_t)8 : (size_t)4);
+    if (es == 0) return 4096;
+    const double per = (double)p.N * (double)p.K * (double)es;
+    return (int)std::max(1.0, std::min(4096.0, 8.0e9 / per));
+}
+
 int current_device(int* dev) {
     return hipGetDevice(dev) == hipSuccess ? SL1_OK : SL1_EHIP;
 }
@@ -310,6 +349,24 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
     p.y_f64 = y_dtype == SL1_F64;
     p.n1_max = n1_max;
     return SL1_OK;
+}
+
+// outputs of a solve, per-signal statuses, hand-back to the caller's stream
+int finish_solve(Workspace* w, const LaunchCfg& cfg, int64_t batch, double* x, double* gap, double* gap_cert,
+                 uint8_t* screened, int32_t* iters, int32_t* stage, hipStream_t us) {
+    HIP_TRY(launch_finalize(w->dP, cfg, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
+    std::vector<int32_t> hs(batch);
+    HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
+    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
+    int result = SL1_OK;
+    for (int32_t v : hs) {
+        if (v < 0) return v;
+        if (v == SL1_MAXITER) result = SL1_MAXITER;
+    }
+    if (*w->h_active > 0) result = SL1_MAXITER;
+    return result;
 }
 
 }  // namespace
@@ -576,15 +633,72 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.atom_norm = atom_norm;
     p.y = y;
     p.lam = lambda;
+    const int eng = o.flags & (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG);
+    if (eng == (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG)) return SL1_EINVAL;
+    const size_t wlds = wg_lds(p);
+    bool use_wg;
+    if (eng == SL1_FLAG_ENGINE_WG) {
+        if (!wlds) return SL1_ELIMIT;
+        use_wg = true;
+    } else if (eng == SL1_FLAG_ENGINE_GRID) {
+        use_wg = false;
+    } else {
+        // one workgroup per signal pays off for small dictionaries: a dense stage is
+        // then streamed by one CU per signal at little cost; larger dense stages
+        // need the whole chip per iteration (grid engine)
+        use_wg = wlds && (int64_t)p.N * p.K <= (1 << 20);
+    }
+    const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
+    p.wg_prof = (use_wg && prof) ? w->d_wgprof : nullptr;
     LaunchCfg cfg = launch_cfg(*w, p);
-    st = check_lds(cfg);
-    if (st != SL1_OK) return st;
+    if (!use_wg) {
+        st = check_lds(cfg);
+        if (st != SL1_OK) return st;
+    }
+    w->last_engine = use_wg ? SL1_ENGINE_WG : SL1_ENGINE_GRID;
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
+    if (prof) {
+        for (int k = 0; k < 3; ++k) {
+            w->prof_ms[k] = 0.0;
+            w->prof_n[k] = 0;
+        }
+        for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] = 0.0;
+    }
+    if (use_wg) {
+        if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
+        const int per = std::min(wg_iters_per_launch(p), 256 * (o.chunk > 0 ? o.chunk : 16));
+        const long long cap = (long long)o.max_iter + 1;
+        long long launched = 0;
+        for (;;) {
+            if (prof) HIP_TRY(hipEventRecord(w->ev_a, w->stream));
+            HIP_TRY(launch_solve_wg(w->dP, (int)batch, wlds, per, w->stream));
+            if (prof) HIP_TRY(hipEventRecord(w->ev_b, w->stream));
+            launched += per;
+            HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
+            HIP_TRY(hipStreamSynchronize(w->stream));
+            if (prof) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
+                w->prof_ms[0] += ms;
+                w->prof_n[0] += 1;
+            }
+            if (*w->h_active <= 0 || launched >= cap) break;
+        }
+        if (prof) {
+            std::vector<long long> ticks((size_t)batch * kWgPhases);
+            HIP_TRY(hipMemcpy(ticks.data(), w->d_wgprof, ticks.size() * 8, hipMemcpyDeviceToHost));
+            int khz = 0;
+            HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            for (int64_t b = 0; b < batch; ++b)
+                for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] += (double)ticks[b * kWgPhases + k] / khz;
+        }
+        return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
+    }
     // iterations alternate between the two control slots: chunks have even length
     const int chunk = o.chunk > 0 ? ((o.chunk + 1) & ~1) : 16;
     const bool use_graph = !(o.flags & SL1_FLAG_NO_GRAPH);
@@ -618,17 +732,12 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     }
     long long launched = 0;
     const long long cap = (long long)o.max_iter + 2LL * chunk + 4;
-    const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
     if (prof) {
         // one event before and after every kernel of a chunk
         while ((int)w->prof_ev.size() < 6 * chunk) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             w->prof_ev.push_back(e);
-        }
-        for (int k = 0; k < 3; ++k) {
-            w->prof_ms[k] = 0.0;
-            w->prof_n[k] = 0;
         }
     }
     for (;;) {
@@ -659,19 +768,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (*w->h_active <= 0 || launched > cap) break;
     }
-    HIP_TRY(launch_finalize(w->dP, cfg, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
-    std::vector<int32_t> hs(batch);
-    HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
-    HIP_TRY(hipStreamSynchronize(w->stream));
-    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
-    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
-    int result = SL1_OK;
-    for (int32_t v : hs) {
-        if (v < 0) return v;
-        if (v == SL1_MAXITER) result = SL1_MAXITER;
-    }
-    if (*w->h_active > 0) result = SL1_MAXITER;
-    return result;
+    return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
 }
 
 static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* lam_out, double* g_out,
@@ -703,6 +800,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.trace = nullptr;
     p.trace_cap = 0;
     p.lambda_only = 1;
+    p.wg_prof = nullptr;
     p.Gamma = 0.5;
     p.tol = 0.0;
     p.margin = 0.0;
@@ -782,6 +880,7 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
         p.trace = nullptr;
         p.trace_cap = 0;
         p.lambda_only = 1;
+        p.wg_prof = nullptr;
         p.tol = 0.0;
         p.margin = 0.0;
         p.atom_norm = tmp.st[i].at_norm;
@@ -845,6 +944,19 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
         ms[k] = it->second->prof_ms[k];
         launches[k] = it->second->prof_n[k];
     }
+    return SL1_OK;
+}
+
+int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms) {
+    if (!engine) return SL1_EINVAL;
+    int dev = 0;
+    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
+    if (it == g_ws.end()) return SL1_EINVAL;
+    *engine = it->second->last_engine;
+    if (phase_ms)
+        for (int k = 0; k < kWgPhases; ++k) phase_ms[k] = it->second->phase_ms[k];
     return SL1_OK;
 }
 

@@ -1,0 +1,288 @@
+// Device functions shared by the two solve engines (per-iteration grid kernels
+// and the whole-solve workgroup kernel): workspace accessors, block
+// reductions, BF16/FP8 decoding, the forward atom generation, the dense
+// correlation streams and the FP64 scalar block.  Both engines compute every
+// per-element quantity with these same expressions.
+#pragma once
+#include "sl1_internal.hpp"
+
+namespace sl1 {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32v4 __attribute__((ext_vector_type(4)));
+typedef double f64v2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// workspace accessors (signal b, buffer parity par)
+__device__ __forceinline__ double* xbuf(const SolveParams* P, int b, int par) {
+    return P->x + ((size_t)b * 2 + par) * P->K;
+}
+// signal value y_b[i] (FP32 or FP64 input)
+__device__ __forceinline__ double yval(const SolveParams* P, int b, int i) {
+    const size_t k = (size_t)b * P->N + i;
+    return P->y_f64 ? ((const double*)P->y)[k] : (double)((const float*)P->y)[k];
+}
+__device__ __forceinline__ double* gbuf(const SolveParams* P, int b, int par) {
+    return P->g + ((size_t)b * 2 + par) * P->K;
+}
+__device__ __forceinline__ int* actbuf(const SolveParams* P, int b, int par) {
+    return P->act + ((size_t)b * 2 + par) * P->K;
+}
+__device__ __forceinline__ int* nzbuf(const SolveParams* P, int b, int par) {
+    return P->nz + ((size_t)b * 2 + par) * P->K;
+}
+__device__ __forceinline__ int* actpre(const SolveParams* P, int b, int par) {
+    return P->act_pre + ((size_t)b * 2 + par) * (P->nseg_max + 1);
+}
+__device__ __forceinline__ int* nzpre(const SolveParams* P, int b, int par) {
+    return P->nz_pre + ((size_t)b * 2 + par) * (P->nseg_max + 1);
+}
+
+// block-wide sums / maxima of NV values, fixed order (red: LDS, NV*16 doubles)
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[k * 16 + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = 0.0;
+        for (int q = 0; q < nw; ++q) a += red[k * 16 + q];
+        v[k] = a;
+    }
+    __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void block_max(double (&v)[NV], double* red) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_max(v[k]);
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[k * 16 + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = red[k * 16];
+        for (int q = 1; q < nw; ++q) a = fmax(a, red[k * 16 + q]);
+        v[k] = a;
+    }
+    __syncthreads();
+}
+
+// exclusive block-wide prefix of per-thread integer counts; returns the total
+__device__ __forceinline__ int block_excl_scan(int v, int& excl, int* s_tmp /* LDS, 16 ints */) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) s_tmp[w] = incl;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int q = 0; q < nw; ++q) {
+        if (q < w) base += s_tmp[q];
+        total += s_tmp[q];
+    }
+    excl = base + incl - v;
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ float bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+__device__ __forceinline__ uint16_t bf16_bits(float f) {  // f already bf16-exact
+    return (uint16_t)(__float_as_uint(f) >> 16);
+}
+
+// Algorithm 2 (SwitchDictionary): speed criterion first, then gap saturation.
+__device__ __forceinline__ int switch_dictionary(int i, int I, double gamma, double Gamma, double K_t, double rc,
+                                                 double K) {
+    if (i >= I) return I;
+    if (K_t <= rc * K) return I;
+    if (gamma <= Gamma) return i + 1;
+    return i;
+}
+
+// dense correlation items: atoms per wave so that a wave keeps ~16 loads in flight
+__device__ __forceinline__ int dense_apw(int N) { return N <= 1024 ? 4 : (N <= 2048 ? 2 : 1); }
+
+// forward product: adds x_j a~_j[r0..r0+3] (4 rows per lane); a Kronecker atom
+// is generated from its factors, sum_r B_r[i1, j1] C_r[i2, j2] in storage precision
+__device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j, double xj, int r0,
+                                               double (&acc)[4]) {
+    if (st.kind == kDense) {
+        const size_t off = (size_t)j * N + r0;
+        if (st.dtype == SL1_F64) {
+            const f64v2* p = (const f64v2*)((const double*)st.A + off);
+            f64v2 a = p[0], c = p[1];
+            acc[0] += xj * a[0]; acc[1] += xj * a[1]; acc[2] += xj * c[0]; acc[3] += xj * c[1];
+        } else if (st.dtype == SL1_F32) {
+            f32v4 a = *(const f32v4*)((const float*)st.A + off);
+            acc[0] += xj * (double)a[0]; acc[1] += xj * (double)a[1];
+            acc[2] += xj * (double)a[2]; acc[3] += xj * (double)a[3];
+        } else if (st.dtype == SL1_BF16) {
+            u16x4 a = *(const u16x4*)((const uint16_t*)st.A + off);
+            const double s = st.scale ? (double)st.scale[j] : 1.0;
+            const double xs = xj * s;
+            acc[0] += xs * (double)bf16_to_f(a[0]); acc[1] += xs * (double)bf16_to_f(a[1]);
+            acc[2] += xs * (double)bf16_to_f(a[2]); acc[3] += xs * (double)bf16_to_f(a[3]);
+        } else {
+            const uint32_t q = *(const uint32_t*)((const uint8_t*)st.A + off);
+            const double s = st.scale ? (double)st.scale[j] : 1.0;
+            const double xs = xj * s;
+            auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
+            auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+            acc[0] += xs * (double)lo[0]; acc[1] += xs * (double)lo[1];
+            acc[2] += xs * (double)hi[0]; acc[3] += xs * (double)hi[1];
+        }
+    } else {
+        // Kronecker atom generated on the fly: a~_j[i] = sum_r B_r[i1,j1] C_r[i2,j2]
+        const int n1 = st.n1, k1 = st.k1, n2 = st.n2, k2 = st.k2;
+        const int i1 = r0 / n2, i2 = r0 - i1 * n2;
+        const int j1 = j / k2, j2 = j - j1 * k2;
+        if (st.dtype == SL1_F64) {
+            double a[4] = {0, 0, 0, 0};
+            for (int r = 0; r < st.R; ++r) {
+                const double bv = ((const double*)st.B)[((size_t)r * k1 + j1) * n1 + i1];
+                const f64v2* cp = (const f64v2*)((const double*)st.C + ((size_t)r * k2 + j2) * n2 + i2);
+                f64v2 c0 = cp[0], c1 = cp[1];
+                a[0] += bv * c0[0]; a[1] += bv * c0[1]; a[2] += bv * c1[0]; a[3] += bv * c1[1];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += xj * a[v];
+        } else if (st.dtype == SL1_F32) {
+            float a[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int r = 0; r < st.R; ++r) {
+                const float bv = ((const float*)st.B)[((size_t)r * k1 + j1) * n1 + i1];
+                f32v4 c = *(const f32v4*)((const float*)st.C + ((size_t)r * k2 + j2) * n2 + i2);
+                a[0] = fmaf(bv, c[0], a[0]); a[1] = fmaf(bv, c[1], a[1]);
+                a[2] = fmaf(bv, c[2], a[2]); a[3] = fmaf(bv, c[3], a[3]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += xj * (double)a[v];
+        } else {
+            float a[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int r = 0; r < st.R; ++r) {
+                const float bv = bf16_to_f(((const uint16_t*)st.B)[((size_t)r * k1 + j1) * n1 + i1]);
+                u16x4 c = *(const u16x4*)((const uint16_t*)st.C + ((size_t)r * k2 + j2) * n2 + i2);
+                a[0] = fmaf(bv, bf16_to_f(c[0]), a[0]); a[1] = fmaf(bv, bf16_to_f(c[1]), a[1]);
+                a[2] = fmaf(bv, bf16_to_f(c[2]), a[2]); a[3] = fmaf(bv, bf16_to_f(c[3]), a[3]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += xj * (double)a[v];
+        }
+    }
+}
+
+__device__ __forceinline__ double clip_scale(double s0, double m) {
+    if (!(m > 0.0)) return s0;
+    return fmin(fmax(s0, -1.0 / m), 1.0 / m);
+}
+
+// dense correlations: NA atoms per wave streamed together (their loads are in
+// flight at once), FP64 accumulation of the decoded storage values
+template <int DT>
+__device__ __forceinline__ void load4(const void* A, size_t idx, double (&v)[4]) {
+    if constexpr (DT == SL1_F64) {
+        const f64v2* p = (const f64v2*)((const double*)A + idx);
+        const f64v2 a = p[0], c = p[1];
+        v[0] = a[0]; v[1] = a[1]; v[2] = c[0]; v[3] = c[1];
+    } else if constexpr (DT == SL1_F32) {
+        const f32v4 a = *(const f32v4*)((const float*)A + idx);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+    } else if constexpr (DT == SL1_BF16) {
+        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
+        v[0] = bf16_to_f(a[0]); v[1] = bf16_to_f(a[1]); v[2] = bf16_to_f(a[2]); v[3] = bf16_to_f(a[3]);
+    } else {
+        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+        v[0] = lo[0]; v[1] = lo[1]; v[2] = hi[0]; v[3] = hi[1];
+    }
+}
+
+template <int DT, int NA>
+__device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const int (&js)[NA], const double* zs,
+                                             int lane, double (&out)[NA]) {
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    for (int k = lane * 4; k < N; k += 256) {
+        double a[NA][4];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) load4<DT>(st.A, (size_t)js[q] * N + k, a[q]);
+        const double z0 = zs[k], z1 = zs[k + 1], z2 = zs[k + 2], z3 = zs[k + 3];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) acc[q] += a[q][0] * z0 + a[q][1] * z1 + a[q][2] * z2 + a[q][3] * z3;
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        out[q] = wave_sum(acc[q]);
+        if (st.scale) out[q] *= (double)st.scale[js[q]];
+    }
+}
+
+template <int NA>
+__device__ __forceinline__ void dense_dots(const StageDesc& st, int N, const int (&js)[NA], const double* zs, int lane,
+                                           double (&out)[NA]) {
+    switch (st.dtype) {
+        case SL1_F64: dense_dots_t<SL1_F64, NA>(st, N, js, zs, lane, out); break;
+        case SL1_F32: dense_dots_t<SL1_F32, NA>(st, N, js, zs, lane, out); break;
+        case SL1_BF16: dense_dots_t<SL1_BF16, NA>(st, N, js, zs, lane, out); break;
+        default: dense_dots_t<SL1_FP8_E4M3, NA>(st, N, js, zs, lane, out); break;
+    }
+}
+
+// FP64 scalar block of iteration t from the residual sums and the maxima over A_t
+__device__ __forceinline__ void scalars_from(const SolveParams* P, const Control& C, double r2, double zz, double yz,
+                                             double mp, double mt, double E, Scalars& S) {
+    const double lam = C.lam, l1 = C.l1;
+    const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;     // projection of y/lam on z
+    const double sp = clip_scale(s0, mp);                  // stable dual point theta' (Lemma 2)
+    const double stc = clip_scale(s0, mt);                 // conventional point on A~
+    const double Pv = 0.5 * r2 + lam * l1;                 // P(x_t | A~)
+    const double Gp = Pv - (lam * sp * yz - 0.5 * lam * lam * sp * sp * zz);
+    const double Gt = Pv - (lam * stc * yz - 0.5 * lam * lam * stc * stc * zz);
+    const double delta = sqrt(r2) * E * l1 + 0.5 * E * E * l1 * l1;     // Theorem 1, r = 1
+    S.r2 = r2; S.zz = zz; S.yz = yz;
+    S.mp = mp; S.mt = mt; S.E = E;
+    S.sp = sp; S.st = stc;
+    S.P = Pv; S.Gp = Gp; S.Gt = Gt; S.delta = delta;
+    S.Rp = sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam;
+    S.gamma = Gp > 0.0 ? Gt / Gp : 1.0;
+    S.c1 = fabs(sp);
+    S.c2 = fabs(sp) * sqrt(zz);
+    if (C.ksince == 0) {
+        S.beta = 0.0;
+        S.tau_next = C.tau;
+    } else {
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * C.tau * C.tau));
+        S.beta = (C.tau - 1.0) / tn;
+        S.tau_next = tn;
+    }
+    const bool on_exact = C.stage == P->n_stages - 1;
+    S.conv = (on_exact && Gt < P->tol) ? 1 : (C.iter >= P->max_iter ? 2 : 0);
+    S.pad0 = 0;
+    S.tconv = 0;
+}
+
+}  // namespace sl1

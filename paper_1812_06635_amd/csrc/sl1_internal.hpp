@@ -17,6 +17,11 @@ constexpr int kFwdWaves = kFwdBlock / 64;
 constexpr int kMaxSeg = 1024;       // segments of a compacted list (K <= 262144)
 constexpr int kKronColTile = 64;    // atoms (j1) per Kronecker-adjoint block (16 per wave)
 constexpr int kMaxN = 8192;
+constexpr int kWgBlock = 512;       // whole-solve engine: one 8-wave workgroup per signal
+constexpr int kWgWaves = kWgBlock / 64;
+constexpr int kWgRows = 1024;       // rows per forward pass of that engine (16 per lane of a wave)
+constexpr int kWgStage = 512;       // nonzeros of x staged in LDS per forward step
+constexpr int kWgPhases = 4;        // profiled phases: forward, dense correlations, Kronecker correlations, update
 
 enum Kind { kDense = 0, kKron = 1 };
 
@@ -95,6 +100,10 @@ struct SolveParams {
     int* cnt_upd;             // [batch] work items of the update launch (current iteration)
     int* active_signals;      // one int: signals not yet done
     int nseg_max, nrc, nadj_max, n1_max;
+    // whole-solve engine: LDS bytes of the factor copy and of the shared scratch,
+    // optional per-signal phase clocks [batch][kWgPhases] (wall-clock ticks)
+    int wg_fac, wg_scr;
+    long long* wg_prof;
 };
 
 struct LaunchCfg {

@@ -1,0 +1,761 @@
+// Whole-solve engine (gfx950): one workgroup of 8 waves runs Algorithm 1
+// (FastL1) for one signal from the first iteration to the stop, with no host
+// round trip and no kernel boundary between iterations.  Meant for batches of
+// small problems (the per-signal vectors fit in LDS and the Kronecker factors of
+// the current stage are copied into LDS once per stage switch).
+//
+// Iteration t, inside the workgroup (every barrier is block-wide):
+//   forward    u = A~ x_t over the nonzeros of x_t (Kronecker atoms generated
+//              from the LDS factors; dense columns streamed from HBM), the 8
+//              waves split the nonzeros and their row partials are summed in a
+//              fixed tree; residual rho = y - u, its norms, stored direction z.
+//   correlate  g = A~^T z: dense stages over the preserved list (8 waves x 4
+//              atoms in flight); Kronecker stages as two MFMA products
+//              V_r = C_r^T Z then G = sum_r V_r B_r with every operand in LDS.
+//   scalars    maxima over A_t, then the FP64 scalar block (shared expressions
+//              with the per-iteration grid kernels): dual points, gaps, delta,
+//              stable radius, gap ratio, stop decision.
+//   update     stable GAP Safe test, look-ahead count, FISTA step, in-place
+//              compaction of the preserved list and rebuild of the nonzero list.
+//   switch     Algorithm 2 and the momentum sequence.
+// Per-element arithmetic is the same as in the grid kernels; only the order of
+// the FP64 reductions differs.  A launch runs at most a given number of
+// iterations and stores its state, so every launch has bounded duration; the
+// host relaunches while signals remain.
+#include "sl1_device.hpp"
+
+namespace sl1 {
+
+namespace {
+
+__device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// block-uniform values read from LDS, moved to scalar registers
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xFFFFFFFFll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// exclusive prefix of a per-thread flag over the 8-wave block; total returned in `total`
+__device__ __forceinline__ int wg_scan_flag(bool f, int* s_w, int& total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long bal = __ballot(f);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) s_w[w] = __popcll(bal);
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWgWaves; ++k) {
+        base += k < w ? s_w[k] : 0;
+        tot += s_w[k];
+    }
+    total = tot;
+    __syncthreads();
+    return base + pre;
+}
+
+// ---------------------------------------------------------------------------
+// forward product.  A lane holds 16 rows row(e) = rbase + (e / 4) rstride +
+// e % 4: dense stages rbase = chunk 1024 + 4 lane, rstride = 256; Kronecker
+// stages the 4 x 4 block i1 = 4 ba + e / 4, i2 = 4 bc + e % 4 of block
+// chunk 64 + lane (rbase = 4 ba n2 + 4 bc, rstride = n2), so that one LDS
+// vector of B_r and one of C_r serve 16 products.  Staged nonzeros carry j for
+// dense stages and (j1 << 16) | j2 for Kronecker stages.
+// ---------------------------------------------------------------------------
+template <int DT>
+__device__ __forceinline__ void wg_kron_fwd(const char* fac, const StageDesc& st, int jp, double xj, int ba, int bc,
+                                            double (&acc)[16]) {
+    const int R = st.R, n1 = st.n1, k1 = st.k1, n2 = st.n2, k2 = st.k2;
+    const int j1 = jp >> 16, j2 = jp & 0xFFFF;
+    if constexpr (DT == SL1_F64) {
+        // two passes of 8 rows keep the FP64 partial products within budget
+        const double* Bl = (const double*)fac;
+        const double* Cl = Bl + (size_t)R * k1 * n1;
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            double a[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] = 0.0;
+            for (int r = 0; r < R; ++r) {
+                const f64v2 b2 = *(const f64v2*)(Bl + ((size_t)r * k1 + j1) * n1 + 4 * ba + 2 * ph);
+                const double* cp = Cl + ((size_t)r * k2 + j2) * n2 + 4 * bc;
+                const f64v2 c01 = *(const f64v2*)cp, c23 = *(const f64v2*)(cp + 2);
+                const double cv[4] = {c01[0], c01[1], c23[0], c23[1]};
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a[p * 4 + q] += b2[p] * cv[q];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[8 * ph + e] += xj * a[e];
+        }
+    } else {
+        float a[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = 0.f;
+        for (int r = 0; r < R; ++r) {
+            float bv[4], cv[4];
+            if constexpr (DT == SL1_F32) {
+                const float* Bl = (const float*)fac;
+                const float* Cl = Bl + (size_t)R * k1 * n1;
+                const f32v4 b4 = *(const f32v4*)(Bl + ((size_t)r * k1 + j1) * n1 + 4 * ba);
+                const f32v4 c4 = *(const f32v4*)(Cl + ((size_t)r * k2 + j2) * n2 + 4 * bc);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    bv[v] = b4[v];
+                    cv[v] = c4[v];
+                }
+            } else {
+                const uint16_t* Bl = (const uint16_t*)fac;
+                const uint16_t* Cl = Bl + (size_t)R * k1 * n1;
+                const u16x4 b4 = *(const u16x4*)(Bl + ((size_t)r * k1 + j1) * n1 + 4 * ba);
+                const u16x4 c4 = *(const u16x4*)(Cl + ((size_t)r * k2 + j2) * n2 + 4 * bc);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    bv[v] = bf16_to_f(b4[v]);
+                    cv[v] = bf16_to_f(c4[v]);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[p * 4 + q] = fmaf(bv[p], cv[q], a[p * 4 + q]);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] += xj * (double)a[e];
+    }
+}
+
+// four consecutive elements of a dense column in FP32/BF16/FP8 storage, decoded
+// to float (exact); the column scale is applied in FP64 by the caller
+__device__ __forceinline__ f32v4 dense4_f(int dtype, const void* A, size_t idx) {
+    f32v4 r;
+    if (dtype == SL1_F32) {
+        r = *(const f32v4*)((const float*)A + idx);
+    } else if (dtype == SL1_BF16) {
+        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
+        r = f32v4{bf16_to_f(a[0]), bf16_to_f(a[1]), bf16_to_f(a[2]), bf16_to_f(a[3])};
+    } else {
+        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+        r = f32v4{lo[0], lo[1], hi[0], hi[1]};
+    }
+    return r;
+}
+
+// accumulate this wave's share [k0, k1) of the staged nonzeros.  D64: FP64
+// storage (dense or Kronecker); otherwise FP32/BF16/FP8 dense or FP32/BF16
+// Kronecker, the storage type decoded per load.
+template <bool D64>
+__device__ __forceinline__ void wg_fwd_range(const StageDesc& st, const char* fac, int N, int rbase, int nq, int ba,
+                                             int bc, bool kvalid, const int* s_j, const double* s_x, int k0, int k1,
+                                             double (&acc)[16]) {
+    if (st.kind == kDense) {
+        if constexpr (D64) {
+#pragma unroll 1
+            for (int k = k0; k < k1; ++k) {
+                const int j = s_j[k];
+                const double xj = s_x[k];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q < nq) {
+                        const f64v2* p = (const f64v2*)((const double*)st.A + (size_t)j * N + rbase + 256 * q);
+                        const f64v2 u = p[0], v = p[1];
+                        acc[4 * q + 0] += xj * u[0];
+                        acc[4 * q + 1] += xj * u[1];
+                        acc[4 * q + 2] += xj * v[0];
+                        acc[4 * q + 3] += xj * v[1];
+                    }
+                }
+            }
+        } else {
+            const int dt = st.dtype;
+            const bool scaled = st.scale != nullptr && dt != SL1_F32;
+#pragma unroll 1
+            for (int k = k0; k < k1; k += 2) {
+                const bool two = k + 1 < k1;
+                const int ja = s_j[k], jb = two ? s_j[k + 1] : ja;
+                double sa = s_x[k], sb = two ? s_x[k + 1] : 0.0;
+                f32v4 va[4], vb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q < nq) {
+                        va[q] = dense4_f(dt, st.A, (size_t)ja * N + rbase + 256 * q);
+                        vb[q] = dense4_f(dt, st.A, (size_t)jb * N + rbase + 256 * q);
+                    } else {
+                        va[q] = vb[q] = f32v4{0.f, 0.f, 0.f, 0.f};
+                    }
+                }
+                if (scaled) {
+                    sa *= (double)st.scale[ja];
+                    sb *= (double)st.scale[jb];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[4 * q + v] += sa * (double)va[q][v];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[4 * q + v] += sb * (double)vb[q][v];
+            }
+        }
+    } else {
+        if (!kvalid) return;
+        if constexpr (D64) {
+#pragma unroll 1
+            for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_F64>(fac, st, s_j[k], s_x[k], ba, bc, acc);
+        } else if (st.dtype == SL1_F32) {
+#pragma unroll 1
+            for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_F32>(fac, st, s_j[k], s_x[k], ba, bc, acc);
+        } else {
+#pragma unroll 1
+            for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_BF16>(fac, st, s_j[k], s_x[k], ba, bc, acc);
+        }
+    }
+}
+
+// sum of the 8 waves' row partials into wave 0, fixed order; scr: 32 KB
+__device__ __forceinline__ void wg_reduce_rows(double (&acc)[16], double* scr) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int half = kWgWaves / 2; half >= 1; half >>= 1) {
+        if (w >= half && w < 2 * half) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) scr[((w - half) * 16 + e) * 64 + lane] = acc[e];
+        }
+        __syncthreads();
+        if (w < half) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[e] += scr[(w * 16 + e) * 64 + lane];
+        }
+        __syncthreads();
+    }
+}
+
+// forward product, residual, stored direction z (into LDS) and the three FP64
+// sums ||rho||^2, ||z||^2, y^T z (into s_sum, by wave 0)
+template <bool D64>
+__device__ __forceinline__ void wg_forward(const SolveParams* P, int b, const StageDesc& st, const char* fac,
+                                           const double* x, const int* nzl, int n_nz, int zround, double* zd,
+                                           float* zf, char* scr, double* s_sum) {
+    const int N = P->N, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int nchunk = (N + kWgRows - 1) / kWgRows;
+    const bool dense = st.kind == kDense;
+    const int k2 = st.k2;
+    double* s_x = (double*)scr;                                   // staging shares the scratch
+    int* s_j = (int*)(scr + kWgStage * 8);
+    const double* y64 = (const double*)P->y + (size_t)b * N;
+    const float* y32 = (const float*)P->y + (size_t)b * N;
+    const bool yd = P->y_f64;
+    double sums[3] = {0.0, 0.0, 0.0};
+    for (int chunk = 0; chunk < nchunk; ++chunk) {
+        // this lane's rows
+        int rbase, rstride, nq, ba = 0, bc = 0;
+        bool kvalid = false;
+        if (dense) {
+            rbase = chunk * kWgRows + 4 * lane;
+            rstride = 256;
+            nq = rbase < N ? min(4, (N - rbase + 255) / 256) : 0;
+        } else {
+            const int q = chunk * 64 + lane, nb2 = st.n2 >> 2;
+            kvalid = q < (N >> 4);
+            ba = kvalid ? q / nb2 : 0;
+            bc = kvalid ? q - ba * nb2 : 0;
+            rbase = 4 * ba * st.n2 + 4 * bc;
+            rstride = st.n2;
+            nq = kvalid ? 4 : 0;
+        }
+        double acc[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+        for (int base = 0; base < n_nz; base += kWgStage) {
+            const int cnt = min(kWgStage, n_nz - base);
+            if (tid < cnt) {
+                const int j = nzl[base + tid];
+                if (dense) {
+                    s_j[tid] = j;
+                } else {
+                    const int j1 = j / k2;
+                    s_j[tid] = (j1 << 16) | (j - j1 * k2);
+                }
+                s_x[tid] = x[j];
+            }
+            __syncthreads();
+            const int pw = (cnt + kWgWaves - 1) / kWgWaves;
+            const int k0 = min(cnt, w * pw), k1 = min(cnt, k0 + pw);
+            wg_fwd_range<D64>(st, fac, N, rbase, nq, ba, bc, kvalid, s_j, s_x, k0, k1, acc);
+            __syncthreads();
+        }
+        wg_reduce_rows(acc, (double*)scr);
+        if (w == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < nq) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rbase + q * rstride + v;
+                        const double yv = yd ? y64[row] : (double)y32[row];
+                        const double rho = yv - acc[4 * q + v];
+                        double zv = rho;
+                        if (zround == 1) zv = (double)(float)rho;
+                        else if (zround == 2) zv = (double)bf16_rne((float)rho);
+                        zd[row] = zv;
+                        zf[row] = (float)zv;
+                        sums[0] += rho * rho;
+                        sums[1] += zv * zv;
+                        sums[2] += yv * zv;
+                    }
+                }
+            }
+        }
+    }
+    if (w == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sums[k] = wave_sum(sums[k]);
+        if (lane == 0) {
+            s_sum[0] = sums[0];
+            s_sum[1] = sums[1];
+            s_sum[2] = sums[2];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kronecker correlations with LDS operands: G[a][j1] = sum_r (C_r^T Z B_r)[a][j1],
+// g_j for j = j1 k2 + a.  MFMA 16x16 operand layout (wave64): lane l holds
+// A[l%16][k], B[k][l%16] with k = l/16 (x4 shapes) or 4(l/16)+v (x16 shapes);
+// D[4(l/16)+v][l%16].
+// ---------------------------------------------------------------------------
+template <int DT>
+__device__ void wg_kron_adj(const StageDesc& st, const char* fac, const double* zd, const float* zf, char* scr,
+                            const uint8_t* mask, double rz, double* g, double (&mx)[3]) {
+    const int R = st.R, n1 = st.n1, k1 = st.k1, n2 = st.n2, k2 = st.k2;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int nA = k2 >> 4, nI = n1 >> 4, nJ = k1 >> 4;
+    // phase 1: V_r = C_r^T Z (k2 x n1 per term) into scr
+    const int t1 = R * nA * nI;
+    for (int t = w; t < t1; t += kWgWaves) {
+        const int r = t / (nA * nI), rem = t - r * nA * nI;
+        const int a0 = (rem / nI) * 16, i0 = (rem % nI) * 16;
+        if constexpr (DT == SL1_F64) {
+            const double* Cl = (const double*)fac + (size_t)R * k1 * n1;
+            const double* cp = Cl + ((size_t)r * k2 + a0 + li) * n2 + lk;
+            const double* zp = zd + (size_t)(i0 + li) * n2 + lk;
+            f64x4 d = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < n2; k0 += 4) d = __builtin_amdgcn_mfma_f64_16x16x4f64(cp[k0], zp[k0], d, 0, 0, 0);
+            double* V = (double*)scr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) V[((size_t)r * k2 + a0 + 4 * lk + v) * n1 + i0 + li] = d[v];
+        } else if constexpr (DT == SL1_F32) {
+            const float* Cl = (const float*)fac + (size_t)R * k1 * n1;
+            const float* cp = Cl + ((size_t)r * k2 + a0 + li) * n2 + lk;
+            const float* zp = zf + (size_t)(i0 + li) * n2 + lk;
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < n2; k0 += 4) d = __builtin_amdgcn_mfma_f32_16x16x4f32(cp[k0], zp[k0], d, 0, 0, 0);
+            float* V = (float*)scr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) V[((size_t)r * k2 + a0 + 4 * lk + v) * n1 + i0 + li] = d[v];
+        } else {
+            const uint16_t* Cl = (const uint16_t*)fac + (size_t)R * k1 * n1;
+            const uint16_t* cp = Cl + ((size_t)r * k2 + a0 + li) * n2 + 4 * lk;
+            const float* zp = zf + (size_t)(i0 + li) * n2 + 4 * lk;
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < n2; k0 += 16) {
+                const u16x4 av = *(const u16x4*)(cp + k0);
+                const f32v4 zv = *(const f32v4*)(zp + k0);
+                s16x4 a, bb;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    a[v] = (short)av[v];
+                    bb[v] = (short)bf16_bits(zv[v]);
+                }
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, d, 0, 0, 0);
+            }
+            uint16_t* Vh = (uint16_t*)scr;
+            uint16_t* Vl = Vh + (size_t)R * k2 * n1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float hi = bf16_rne(d[v]);
+                const float lo = bf16_rne(d[v] - hi);
+                const size_t o = ((size_t)r * k2 + a0 + 4 * lk + v) * n1 + i0 + li;
+                Vh[o] = bf16_bits(hi);
+                Vl[o] = bf16_bits(lo);
+            }
+        }
+    }
+    __syncthreads();
+    // phase 2: G = sum_r V_r B_r, one 16 x 16 output tile per wave at a time
+    const int t2 = nA * nJ;
+    for (int t = w; t < t2; t += kWgWaves) {
+        const int a0 = (t / nJ) * 16, j0 = (t % nJ) * 16;
+        double gv[4];
+        if constexpr (DT == SL1_F64) {
+            const double* Bl = (const double*)fac;
+            const double* V = (const double*)scr;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int r = 0; r < R; ++r) {
+                const double* vp = V + ((size_t)r * k2 + a0 + li) * n1 + lk;
+                const double* bp = Bl + ((size_t)r * k1 + j0 + li) * n1 + lk;
+                for (int k0 = 0; k0 < n1; k0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vp[k0], bp[k0], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gv[v] = acc[v];
+        } else if constexpr (DT == SL1_F32) {
+            const float* Bl = (const float*)fac;
+            const float* V = (const float*)scr;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int r = 0; r < R; ++r) {
+                const float* vp = V + ((size_t)r * k2 + a0 + li) * n1 + lk;
+                const float* bp = Bl + ((size_t)r * k1 + j0 + li) * n1 + lk;
+                for (int k0 = 0; k0 < n1; k0 += 4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(vp[k0], bp[k0], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gv[v] = (double)acc[v];
+        } else {
+            const uint16_t* Bl = (const uint16_t*)fac;
+            const uint16_t* Vh = (const uint16_t*)scr;
+            const uint16_t* Vl = Vh + (size_t)R * k2 * n1;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int r = 0; r < R; ++r) {
+                const size_t vo = ((size_t)r * k2 + a0 + li) * n1 + 4 * lk;
+                const uint16_t* bp = Bl + ((size_t)r * k1 + j0 + li) * n1 + 4 * lk;
+                for (int k0 = 0; k0 < n1; k0 += 16) {
+                    const u16x4 hv = *(const u16x4*)(Vh + vo + k0);
+                    const u16x4 lv = *(const u16x4*)(Vl + vo + k0);
+                    const u16x4 bv = *(const u16x4*)(bp + k0);
+                    s16x4 h, lo, bb;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        h[v] = (short)hv[v];
+                        lo[v] = (short)lv[v];
+                        bb[v] = (short)bv[v];
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, bb, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo, bb, acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gv[v] = (double)acc[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = (j0 + li) * k2 + a0 + 4 * lk + v;
+            g[j] = gv[v];
+            if (mask[j]) {
+                const double e = st.eps[j];
+                mx[0] = fmax(mx[0], fabs(gv[v]) + e * rz);
+                mx[1] = fmax(mx[1], fabs(gv[v]));
+                mx[2] = fmax(mx[2], e);
+            }
+        }
+    }
+}
+
+// dense correlations over the preserved list: wave w takes NA atoms at a time
+template <int NA>
+__device__ void wg_dense_adj(const StageDesc& st, int N, const int* act, int n_act, const double* zd, double rz,
+                             double* g, double (&mx)[3]) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int first = w * NA; first < n_act; first += kWgWaves * NA) {
+        int js[NA];
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const bool ok = first + q < n_act;
+            js[q] = ok ? act[first + q] : -1;
+            cnt += ok;
+        }
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+            if (js[q] < 0) js[q] = js[0];
+        double gv[NA];
+        dense_dots<NA>(st, N, js, zd, lane, gv);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                if (q < cnt) {
+                    const int j = js[q];
+                    g[j] = gv[q];
+                    const double e = st.eps[j];
+                    mx[0] = fmax(mx[0], fabs(gv[q]) + e * rz);
+                    mx[1] = fmax(mx[1], fabs(gv[q]));
+                    mx[2] = fmax(mx[2], e);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void wg_copy_factors(const StageDesc& st, char* fac) {
+    const size_t es = st.dtype == SL1_F64 ? 8 : (st.dtype == SL1_F32 ? 4 : 2);
+    const size_t nb = (size_t)st.R * st.k1 * st.n1 * es, nc = (size_t)st.R * st.k2 * st.n2 * es;
+    const u32x4* B = (const u32x4*)st.B;
+    const u32x4* Cg = (const u32x4*)st.C;
+    u32x4* dst = (u32x4*)fac;
+    for (size_t i = threadIdx.x; i < nb / 16; i += kWgBlock) dst[i] = B[i];
+    u32x4* dc = (u32x4*)(fac + nb);
+    for (size_t i = threadIdx.x; i < nc / 16; i += kWgBlock) dc[i] = Cg[i];
+}
+
+// phase clock (thread 0, after the phase's closing barrier)
+__device__ __forceinline__ void wg_stamp(const SolveParams* P, int b, int phase, long long& t) {
+    if (P->wg_prof && threadIdx.x == 0) {
+        const long long now = wall_clock64();
+        P->wg_prof[(size_t)b * kWgPhases + phase] += now - t;
+        t = now;
+    }
+}
+
+}  // namespace
+
+// The parameter block re-read through an opaque copy at the start of each phase:
+// pointers and sizes then live only within the phase instead of being held in
+// registers across the whole iteration loop.
+__device__ __forceinline__ const SolveParams* phase_params(const SolveParams* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// the whole-solve kernel: grid = batch, block = 512; state in P->ctrl[2 b]
+// (written by the initialisation kernel and stored back when a launch ends
+// before the signal stops); at most max_it iterations per launch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __restrict__ P0, int max_it) {
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    // iteration state of the signal, written by thread 0 between barriers
+    __shared__ Control sC;
+    __shared__ Scalars sS;
+    __shared__ double s_red[48];
+    __shared__ double s_sum[4];
+    __shared__ double s_kt[2];
+    __shared__ int s_cnt[2];
+    __shared__ int s_w[kWgWaves];
+    __shared__ int s_loaded;
+    __shared__ long long s_clk;
+
+    if (tid == 0) {
+        sC = P0->ctrl[2 * b];
+        s_loaded = -1;
+        s_clk = P0->wg_prof ? wall_clock64() : 0;
+    }
+    __syncthreads();
+    if (sC.done) return;
+
+    for (int it = 0; it < max_it; ++it) {
+        const int stage = uni(sC.stage), par = uni(sC.par);
+        // ---- factors of a new Kronecker stage into LDS ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const StageDesc& st = P->st[stage];
+            char* fac = smem + al16((size_t)P->N * 8) + al16((size_t)P->N * 4);
+            if (st.kind == kKron && uni(s_loaded) != stage) {
+                wg_copy_factors(st, fac);
+                __syncthreads();
+                if (tid == 0) s_loaded = stage;
+                __syncthreads();
+            }
+        }
+        // ---- forward product and residual ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const int N = P->N;
+            const StageDesc& st = P->st[stage];
+            double* zd = (double*)smem;
+            float* zf = (float*)(smem + al16((size_t)N * 8));
+            char* fac = (char*)zf + al16((size_t)N * 4);
+            char* scr = fac + P->wg_fac;
+            const double* x = xbuf(P, b, par);
+            const int* nzl = nzbuf(P, b, 0);
+            const int zround = st.kind == kKron ? (st.dtype == SL1_BF16 ? 2 : (st.dtype == SL1_F32 ? 1 : 0)) : 0;
+            const int n_nz = uni(sC.n_nz);
+            if (st.dtype == SL1_F64) wg_forward<true>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, scr, s_sum);
+            else wg_forward<false>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, scr, s_sum);
+            __syncthreads();
+            wg_stamp(P, b, 0, s_clk);
+        }
+        // ---- correlations over A_t, maxima of the stable dual scaling, scalars ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const int N = P->N, K = P->K;
+            const StageDesc& st = P->st[stage];
+            double* zd = (double*)smem;
+            float* zf = (float*)(smem + al16((size_t)N * 8));
+            char* fac = (char*)zf + al16((size_t)N * 4);
+            char* scr = fac + P->wg_fac;
+            const double rz = uni(sqrt(s_sum[1]));
+            double* gvec = gbuf(P, b, par);
+            double mx[3] = {0.0, 0.0, 0.0};
+            if (st.kind == kDense) {
+                const int apw = dense_apw(N), n_act = uni(sC.n_act);
+                const int* act = actbuf(P, b, 0);
+                if (apw == 4) wg_dense_adj<4>(st, N, act, n_act, zd, rz, gvec, mx);
+                else if (apw == 2) wg_dense_adj<2>(st, N, act, n_act, zd, rz, gvec, mx);
+                else wg_dense_adj<1>(st, N, act, n_act, zd, rz, gvec, mx);
+            } else {
+                const uint8_t* mask = P->mask + (size_t)b * K;
+                if (st.dtype == SL1_F64) wg_kron_adj<SL1_F64>(st, fac, zd, zf, scr, mask, rz, gvec, mx);
+                else if (st.dtype == SL1_F32) wg_kron_adj<SL1_F32>(st, fac, zd, zf, scr, mask, rz, gvec, mx);
+                else wg_kron_adj<SL1_BF16>(st, fac, zd, zf, scr, mask, rz, gvec, mx);
+            }
+            block_max<3>(mx, s_red);
+            if (tid == 0) {
+                Scalars S;
+                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], S);
+                if (S.conv == 1) S.tconv = wall_clock64();
+                sS = S;
+            }
+            __syncthreads();
+            wg_stamp(P, b, st.kind == kDense ? 1 : 2, s_clk);
+        }
+        if (uni(sS.conv)) {
+            if (tid == 0) {
+                const SolveParams* P = phase_params(P0);
+                Final F;
+                F.gap = sS.Gt;
+                F.gap_cert = sS.Gp + sS.delta;
+                F.iters = sC.iter;
+                F.stage = sC.stage;
+                F.status = sS.conv == 2 ? SL1_MAXITER : SL1_OK;
+                F.par = sC.par;
+                F.t0 = sC.t0;
+                F.tconv = sS.tconv;
+                P->fin[b] = F;
+                sC.done = 1;
+                P->ctrl[2 * b] = sC;
+                atomicSub(P->active_signals, 1);
+            }
+            return;
+        }
+        // ---- stable GAP test, look-ahead count, FISTA step, compaction ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const int K = P->K;
+            const StageDesc& st = P->st[stage];
+            const int n_act = uni(sC.n_act);
+            int* act = actbuf(P, b, 0);
+            int* nzl = nzbuf(P, b, 0);
+            uint8_t* mask = P->mask + (size_t)b * K;
+            double* xc = xbuf(P, b, par);
+            double* xo = xbuf(P, b, 1 - par);
+            const double* gcur = gbuf(P, b, par);
+            const double* gprev = gbuf(P, b, 1 - par);
+            const double* eps = st.eps;
+            const double* atn = st.at_norm;
+            const double* an = P->atom_norm;
+            const double c1 = uni(sS.c1), c2 = uni(sS.c2), Rp = uni(sS.Rp), beta = uni(sS.beta);
+            const double invL = st.invL, thr = uni(sC.lam) * st.invL, keep_min = 1.0 - P->margin;
+            int wpos = 0, zpos = 0;
+            double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
+            for (int base = 0; base < n_act; base += 2 * kWgBlock) {
+                int jj[2];
+                bool keep[2], nzf[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = base + h * kWgBlock + tid;
+                    keep[h] = nzf[h] = false;
+                    jj[h] = 0;
+                    if (i < n_act) {
+                        const int j = act[i];
+                        jj[h] = j;
+                        const double gt = gcur[j];
+                        const double gp = gprev[j];
+                        const double xt = xc[j];
+                        const double xp = xo[j];
+                        const double e = eps[j];
+                        const double ag = fabs(gt);
+                        // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
+                        const double mu = c1 * ag + e * c2 + Rp * an[j];
+                        keep[h] = mu >= keep_min;
+                        // look-ahead: conventional test on the approximate atom
+                        sv[0] += (c1 * ag + Rp * atn[j] >= 1.0) ? 1.0 : 0.0;
+                        // FISTA step from the two correlation vectors (gradient by linearity)
+                        const double zpt = xt + beta * (xt - xp);
+                        const double hh = (1.0 + beta) * gt - beta * gp;
+                        const double v = zpt + hh * invL;
+                        double xn = 0.0;
+                        if (keep[h]) xn = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
+                        xo[j] = xn;
+                        if (!keep[h]) {
+                            xc[j] = 0.0;
+                            mask[j] = 0;
+                        }
+                        nzf[h] = keep[h] && (xn != 0.0);
+                        sv[1] += fabs(xn);
+                    }
+                }
+                // every read of this part of the list precedes the in-place writes
+                __syncthreads();
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    int tk, tz;
+                    const int pk = wg_scan_flag(keep[h], s_w, tk);
+                    if (keep[h]) act[wpos + pk] = jj[h];
+                    const int pz = wg_scan_flag(nzf[h], s_w, tz);
+                    if (nzf[h]) nzl[zpos + pz] = jj[h];
+                    wpos += tk;
+                    zpos += tz;
+                }
+            }
+            block_sum<2>(sv, s_red);
+            if (tid == 0) {
+                s_kt[0] = sv[0];
+                s_kt[1] = sv[1];
+                s_cnt[0] = wpos;
+                s_cnt[1] = zpos;
+            }
+            __syncthreads();
+            wg_stamp(P, b, 3, s_clk);
+        }
+        // ---- trace row, Algorithm 2, momentum (thread 0) ----
+        if (tid == 0) {
+            const SolveParams* P = phase_params(P0);
+            const StageDesc& st = P->st[stage];
+            Control C = sC;
+            const double kt = s_kt[0];
+            if (P->trace && C.iter < P->trace_cap) {
+                double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
+                tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
+                tr[4] = kt;
+                tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = sS.Rp; tr[9] = sS.gamma;
+                tr[10] = C.l1; tr[11] = sS.P;
+            }
+            const int i_new = switch_dictionary(C.stage, P->n_stages - 1, sS.gamma, P->Gamma, kt, st.rc, (double)P->K);
+            if (i_new != C.stage) {
+                C.stage = i_new;
+                C.ksince = 0;
+                C.tau = 1.0;
+            } else {
+                C.ksince += 1;
+                C.tau = sS.tau_next;
+            }
+            C.iter += 1;
+            C.par = 1 - C.par;
+            C.n_act = s_cnt[0];
+            C.n_nz = s_cnt[1];
+            C.l1 = s_kt[1];
+            sC = C;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) P0->ctrl[2 * b] = sC;
+}
+
+hipError_t launch_solve_wg(const SolveParams* dP, int batch, size_t lds, int max_it, hipStream_t s) {
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_solve_wg, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_solve_wg, dim3(batch), dim3(kWgBlock), lds, s, dP, max_it);
+    return hipGetLastError();
+}
+
+}  // namespace sl1

@@ -96,11 +96,15 @@ def test_adjoint_kernels_match_oracle_products(sl1, name, maker, rtol):
 # ---------------------------------------------------------------------------
 # the method: per-iteration trace against the FP64 method reference (C1)
 # ---------------------------------------------------------------------------
+ENGINES = ["grid", "wg"]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("real,frac", [(0, 0.5), (1, 0.2), (2, 0.8)])
-def test_fp64_trace_matches_method_reference(sl1, real, frac):
-    _say(f"trace C1 real={real} frac={frac}")
+def test_fp64_trace_matches_method_reference(sl1, real, frac, engine):
+    _say(f"trace C1 real={real} frac={frac} engine={engine}")
     p = synth.config1(realization=real, lam_frac=frac)
-    out = _run(sl1, p, tol=1e-10, trace_cap=5000)
+    out = _run(sl1, p, tol=1e-10, trace_cap=5000, engine=engine)
     ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
                       [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10)
     n = int(out["iters"][0])
@@ -146,36 +150,40 @@ def _check_solution(p, out, b, obj_tol=1e-5, x_tol=1e-4):
     return rel_obj, rel_x
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("frac", [0.3, 0.5, 0.8])
-def test_fp32_kronecker_method(sl1, frac):
-    _say(f"C2-small f32 kron frac={frac}")
+def test_fp32_kronecker_method(sl1, frac, engine):
+    _say(f"C2-small f32 kron frac={frac} engine={engine}")
     p = synth.config2(n=(16, 32), lam_frac=frac)
-    out = _run(sl1, p, tol=1e-10)
+    out = _run(sl1, p, tol=1e-10, engine=engine)
     assert out["status"] == 0 and out["stage"][0] == len(p.stages) - 1
     _check_solution(p, out, 0)
 
 
-def test_low_precision_dense_method(sl1):
-    _say("C3-small fp8/bf16/f32 dense")
+@pytest.mark.parametrize("engine", ENGINES)
+def test_low_precision_dense_method(sl1, engine):
+    _say(f"C3-small fp8/bf16/f32 dense engine={engine}")
     p = synth.config3(N=256, K=1024, s=20, batch=4)
-    out = _run(sl1, p, tol=1e-10)
+    out = _run(sl1, p, tol=1e-10, engine=engine)
     assert out["status"] == 0
     for b in range(p.batch):
         _check_solution(p, out, b)
 
 
-def test_low_precision_dense_ragged(sl1):
-    _say("C3 ragged N=2500 K=600")
+@pytest.mark.parametrize("engine", ENGINES)
+def test_low_precision_dense_ragged(sl1, engine):
+    _say(f"C3 ragged N=2500 K=600 engine={engine}")
     p = synth.config3(N=2500, K=600, s=20, batch=2)
-    out = _run(sl1, p, tol=1e-10)
+    out = _run(sl1, p, tol=1e-10, engine=engine)
     for b in range(p.batch):
         _check_solution(p, out, b)
 
 
-def test_batched_bf16_kronecker_method(sl1):
-    _say("C4-small batch 24 bf16 kron")
+@pytest.mark.parametrize("engine", ENGINES)
+def test_batched_bf16_kronecker_method(sl1, engine):
+    _say(f"C4-small batch 24 bf16 kron engine={engine}")
     p = synth.config4(batch=24, n=(16, 32))
-    out = _run(sl1, p, tol=1e-10)
+    out = _run(sl1, p, tol=1e-10, engine=engine)
     assert out["status"] == 0
     assert len(set(out["iters"].tolist())) > 1           # uneven convergence inside one launch
     for b in range(p.batch):
@@ -185,11 +193,12 @@ def test_batched_bf16_kronecker_method(sl1):
 # ---------------------------------------------------------------------------
 # edge cases and error paths
 # ---------------------------------------------------------------------------
-def test_lambda_above_lambda_max_returns_zero(sl1):
-    _say("lambda >= lambda_max")
+@pytest.mark.parametrize("engine", ENGINES)
+def test_lambda_above_lambda_max_returns_zero(sl1, engine):
+    _say(f"lambda >= lambda_max engine={engine}")
     p = synth.config1()
     p.lam = p.lam_max * 1.01
-    out = _run(sl1, p, tol=1e-12)
+    out = _run(sl1, p, tol=1e-12, engine=engine)
     assert out["status"] == 0
     assert np.all(out["x"] == 0) and out["gap"][0] <= 1e-12
     # x = 0 is optimal at once on A: the solve stops there (Section I-A), without
@@ -197,25 +206,27 @@ def test_lambda_above_lambda_max_returns_zero(sl1):
     assert out["stage"][0] == len(p.stages) - 1
 
 
-def test_max_iter_zero_and_cap(sl1):
-    _say("max_iter 0 and 5")
+@pytest.mark.parametrize("engine", ENGINES)
+def test_max_iter_zero_and_cap(sl1, engine):
+    _say(f"max_iter 0 and 5 engine={engine}")
     p = synth.config1()
-    out = _run(sl1, p, tol=1e-12, max_iter=0, check=False)
+    out = _run(sl1, p, tol=1e-12, max_iter=0, check=False, engine=engine)
     assert out["status"] == 1 and out["iters"][0] == 0 and np.all(out["x"] == 0)
-    out = _run(sl1, p, tol=1e-14, max_iter=5, check=False)
+    out = _run(sl1, p, tol=1e-14, max_iter=5, check=False, engine=engine)
     assert out["status"] == 1 and out["iters"][0] == 5
 
 
-def test_invalid_lambda_is_reported(sl1):
-    _say("invalid lambda")
+@pytest.mark.parametrize("engine", ENGINES)
+def test_invalid_lambda_is_reported(sl1, engine):
+    _say(f"invalid lambda engine={engine}")
     from paper_1812_06635_amd._lib import Stablel1Error
     p = synth.config1()
     p.lam = np.array([-1.0])
     with pytest.raises(Stablel1Error):
-        _run(sl1, p, tol=1e-8)
+        _run(sl1, p, tol=1e-8, engine=engine)
     p.lam = np.array([np.nan])
     with pytest.raises(Stablel1Error):
-        _run(sl1, p, tol=1e-8)
+        _run(sl1, p, tol=1e-8, engine=engine)
 
 
 def test_graph_replay_equals_direct_launches(sl1):
@@ -228,12 +239,45 @@ def test_graph_replay_equals_direct_launches(sl1):
     np.testing.assert_array_equal(a["screened"], b["screened"])
 
 
-def test_exact_only_sequence_is_gap_safe(sl1):
+def test_engines_agree_and_relaunch_is_exact(sl1):
+    # both engines take the same decisions; the whole-solve engine split over
+    # many bounded launches (256 iterations each) gives bit-identical results
+    _say("engines agree; whole-solve relaunch")
+    import paper_1812_06635_amd as m
+    p = synth.config4(batch=12, n=(16, 32))
+    g = _run(sl1, p, tol=1e-9, engine="grid")
+    w = _run(sl1, p, tol=1e-9, engine="wg")
+    w1 = _run(sl1, p, tol=1e-9, engine="wg", chunk=1)
+    assert m.last_solve_phases(p.batch, p.N, p.K)[0] == "wg"
+    np.testing.assert_array_equal(w["x"], w1["x"])
+    np.testing.assert_array_equal(w["iters"], w1["iters"])
+    np.testing.assert_array_equal(w["screened"], w1["screened"])
+    assert int(w["iters"].max()) > 256                 # the relaunch path was taken
+    np.testing.assert_array_equal(g["stage"], w["stage"])
+    assert np.all(np.abs(g["iters"] - w["iters"]) <= 2)
+    for b in range(p.batch):
+        rel = np.linalg.norm(g["x"][b] - w["x"][b]) / max(np.linalg.norm(g["x"][b]), 1e-300)
+        assert rel <= 1e-4, f"signal {b}: engines differ by {rel:.2e}"
+
+
+def test_auto_engine_choice(sl1):
+    _say("auto engine choice")
+    import paper_1812_06635_amd as m
+    p = synth.config4(batch=40, n=(16, 32))
+    _run(sl1, p, tol=1e-6)
+    assert m.last_solve_phases(p.batch, p.N, p.K)[0] == "wg"
+    q = synth.config2(n=(32, 64), R_A=4, Rs=(1, 4))        # one signal, N*K = 2^21
+    _run(sl1, q, tol=1e-6)
+    assert m.last_solve_phases(1, q.N, q.K)[0] == "grid"
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_exact_only_sequence_is_gap_safe(sl1, engine):
     # one stage (the exact A): the stable test is GAP Safe, gamma = 1
-    _say("exact-only sequence")
+    _say(f"exact-only sequence engine={engine}")
     p = synth.config1()
     st = [p.stages[-1]]
-    out = _run(sl1, p, tol=1e-10, stages=st, trace_cap=3000)
+    out = _run(sl1, p, tol=1e-10, stages=st, trace_cap=3000, engine=engine)
     ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in st], p.atom_norm, p.Y[0], float(p.lam[0]), [1.0],
                       tol=1e-10)
     n = int(out["iters"][0])
