@@ -125,21 +125,25 @@ typedef struct {
 
 #define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */
 #define SL1_FLAG_PROFILE 2    /* direct launches bracketed by HIP events; see sl1_last_solve_profile */
-#define SL1_FLAG_ENGINE_GRID 4  /* force the per-iteration grid engine */
-#define SL1_FLAG_ENGINE_WG 8    /* force the whole-solve engine (SL1_ELIMIT if its LDS need exceeds 159 KB) */
+#define SL1_FLAG_ENGINE_GRID 4    /* force the per-iteration grid engine throughout */
+#define SL1_FLAG_ENGINE_WG 8      /* force the whole-solve engine (SL1_ELIMIT if its LDS need exceeds 159 KB) */
+#define SL1_FLAG_ENGINE_HYBRID 16 /* grid engine, then the whole-solve engine for the tail (SL1_ELIMIT as above) */
 
-/* Engines (sl1_last_solve_phases):
- *   SL1_ENGINE_GRID  three persistent launches per iteration covering every live
- *                    signal (any size within the limits; captured in hipGraph chunks);
- *   SL1_ENGINE_WG    one 512-thread workgroup per signal runs the whole solve in one
- *                    launch (per-signal z and the current stage's Kronecker factors in
- *                    LDS).  Chosen by default when its LDS fits and N*K <= 2^20 (a
- *                    dense stage is then cheap for one CU); launches are bounded and
- *                    repeated while signals remain.
- * Both compute every per-element quantity with the same expressions; results differ
- * only by the order of FP64 reductions. */
+/* Engines (at most one SL1_FLAG_ENGINE_* flag; none = automatic):
+ *   SL1_ENGINE_GRID    three persistent launches per iteration covering every live
+ *                      signal (any size within the limits; captured in hipGraph chunks);
+ *   SL1_ENGINE_WG      one 512-thread workgroup per signal runs the whole solve in one
+ *                      launch (per-signal z and the current stage's Kronecker factors in
+ *                      LDS); launches are bounded and repeated while signals remain;
+ *   SL1_ENGINE_HYBRID  the grid engine until, after a chunk, every live signal's
+ *                      preserved set holds at most ~1 MiB of dense columns; the
+ *                      remaining iterations then run in the whole-solve engine.
+ * Automatic choice: whole-solve when its LDS need fits and N*K <= 2^20, hybrid when it
+ * fits and N*K is larger, grid otherwise.  All compute every per-element quantity with
+ * the same expressions; results differ only by the order of FP64 reductions. */
 #define SL1_ENGINE_GRID 1
 #define SL1_ENGINE_WG 2
+#define SL1_ENGINE_HYBRID 3
 
 int sl1_opts_default(sl1_opts* o);
 
@@ -239,15 +243,17 @@ int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, do
 int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
 
 /*
- * sl1_last_solve_phases -- engine of the most recent sl1_solve with these
- * shapes (*engine = SL1_ENGINE_GRID or SL1_ENGINE_WG) and, for the whole-solve
- * engine run with SL1_FLAG_PROFILE, phase_ms[4] (host, may be NULL): workgroup
- * milliseconds summed over signals of forward/residual, dense correlations,
- * Kronecker correlations, and test/update/compaction.  With the whole-solve
- * engine, sl1_last_solve_profile reports the k_solve launches in ms[0] and
- * launches[0].
+ * sl1_last_solve_phases -- engine that ran the most recent sl1_solve with these
+ * shapes (*engine = SL1_ENGINE_GRID, _WG or _HYBRID) and, when it was run with
+ * SL1_FLAG_PROFILE, for its whole-solve part: phase_ms[0..3] (host, 5 doubles,
+ * may be NULL) workgroup milliseconds summed over signals of forward/residual,
+ * dense correlations, Kronecker correlations and test/update/compaction,
+ * phase_ms[4] the elapsed milliseconds of the whole-solve launches and
+ * *wg_launches (may be NULL) their number.  sl1_last_solve_profile covers the
+ * grid kernels.
  */
-int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms);
+int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms,
+                          long long* wg_launches);
 
 const char* sl1_status_str(int status);
 const char* sl1_version(void);

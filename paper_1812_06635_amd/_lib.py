@@ -18,7 +18,8 @@ FLAG_NO_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_ENGINE_GRID = 4
 FLAG_ENGINE_WG = 8
-ENGINE_GRID, ENGINE_WG = 1, 2
+FLAG_ENGINE_HYBRID = 16
+ENGINE_GRID, ENGINE_WG, ENGINE_HYBRID = 1, 2, 3
 
 c_dict = ctypes.c_void_p
 c_p = ctypes.c_void_p
@@ -48,7 +49,8 @@ SIGNATURES = [
     ("sl1_measure_rc", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, ctypes.POINTER(c_d), c_p]),
     ("sl1_last_solve_clock", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_d)]),
     ("sl1_last_solve_profile", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_longlong)]),
-    ("sl1_last_solve_phases", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_d)]),
+    ("sl1_last_solve_phases", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_d),
+                                      ctypes.POINTER(ctypes.c_longlong)]),
     ("sl1_status_str", ctypes.c_char_p, [c_i32]),
     ("sl1_version", ctypes.c_char_p, []),
 ]

@@ -113,14 +113,14 @@ def upload_stage(stage, device="cuda"):
     return Dict.kron(B, C, eps, stage.dtype)
 
 
-_ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG}
+_ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybrid": L.FLAG_ENGINE_HYBRID}
 
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto"):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
-    engine: "auto", "grid" (per-iteration launches) or "wg" (one workgroup per
-    signal for the whole solve).  Returns a dict of device tensors x, gap,
+    engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
+    signal for the whole solve) or "hybrid" (grid, then whole-solve for the tail).  Returns a dict of device tensors x, gap,
     gap_cert, screened, iters, stage, the status code, and the trace
     (batch, trace_cap, 12) when requested."""
     if engine not in _ENGINES:
@@ -219,14 +219,18 @@ def last_solve_profile(batch, N, K):
 
 
 def last_solve_phases(batch, N, K):
-    """(engine name, {phase: ms}) of the last solve of this shape; the phase
-    times (workgroup milliseconds summed over signals) are filled for the
-    whole-solve engine run with profile=True."""
+    """(engine name, {phase: ms}) of the last solve of this shape.  With
+    profile=True the whole-solve part fills the phase times (workgroup ms summed
+    over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches"."""
     eng = L.c_i32()
-    ph = (L.c_d * 4)()
-    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph), "sl1_last_solve_phases")
-    name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg"}.get(eng.value, "none")
-    return name, dict(zip(("fwd", "adj_dense", "adj_kron", "upd"), list(ph)))
+    ph = (L.c_d * 5)()
+    n = ctypes.c_longlong()
+    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph, ctypes.byref(n)),
+            "sl1_last_solve_phases")
+    name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg", L.ENGINE_HYBRID: "hybrid"}.get(eng.value, "none")
+    out = dict(zip(("fwd", "adj_dense", "adj_kron", "upd", "wg_ms"), list(ph)))
+    out["wg_launches"] = n.value
+    return name, out
 
 
 def grad(A, x, y, lam, dx):

@@ -28,6 +28,7 @@ hipError_t launch_dense_norms(int, const void*, const float*, int, int, const do
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
 hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
+hipError_t launch_to_wg(const SolveParams*, int, hipStream_t);
 }  // namespace sl1
 
 using namespace sl1;
@@ -105,6 +106,8 @@ struct Workspace {
     long long prof_n[3] = {0, 0, 0};
     long long* d_wgprof = nullptr;          // [batch][kWgPhases] phase clocks of the whole-solve engine
     double phase_ms[kWgPhases] = {0, 0, 0, 0};
+    double wg_ms = 0.0;                     // whole-solve launches of the last profiled solve
+    long long wg_n = 0;
     int last_engine = 0;
     std::vector<hipEvent_t> prof_ev;
     LaunchCfg graph_cfg{};
@@ -181,6 +184,7 @@ int make_workspace(Workspace& w) {
     p.cnt_adj = p.cnt_fwd + 2 * B;
     p.cnt_upd = p.cnt_adj + B;
     p.active_signals = (int*)(m + o_act_sig);
+    p.stat = p.active_signals + 4;
     p.nseg_max = w.nseg_max;
     p.nrc = w.nrc;
     p.nadj_max = w.nadj_max;
@@ -287,26 +291,63 @@ int check_lds(const LaunchCfg& c) {
     return SL1_OK;
 }
 
-// Dynamic LDS of the whole-solve kernel: z (FP64 and FP32 copies), the factors
-// of the largest Kronecker stage, and a scratch shared by the forward staging /
-// row reduction (32 KB) and the Kronecker intermediate V.  0 if it does not fit.
-size_t wg_lds(SolveParams& p) {
+// LDS layout of the whole-solve kernel; sets the region offsets in p and
+// returns the dynamic LDS bytes (0: does not fit).
+//   full: z (FP64 and FP32), the largest Kronecker stage's factors, a scratch
+//         (forward staging; with Kronecker stages also the cross-wave sums and
+//         the intermediate V), then y and the two lists when two workgroups per
+//         CU can still share the LDS;
+//   tail: every live signal on the last, dense, stage with at most max_act
+//         preserved atoms: z (FP64), y and both lists of max_act entries.
+size_t wg_layout(SolveParams& p, bool tail, int max_act) {
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
-    size_t fac = 0, scr = (size_t)(kWgWaves / 2) * 16 * 64 * 8;
+    const size_t lim = 160 * 1024 - 1024;       // static LDS of the kernel stays below 1 KB
+    const size_t two_per_cu = 79 * 1024;
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        const size_t o = off;
+        off += a16(bytes);
+        return (int)std::min<size_t>(o, (size_t)INT32_MAX);
+    };
+    const size_t N = (size_t)p.N;
+    p.wo_zd = put(N * 8);
+    if (tail) {
+        const int cap = std::max(64, (max_act + 63) & ~63);
+        p.wo_zf = p.wo_fac = p.wo_scr = -1;
+        p.wo_y = put(N * 8);
+        p.wg_cap_nz = p.wg_cap_act = cap;
+        p.wo_lnj = put((size_t)cap * 4);
+        p.wo_lnx = put((size_t)cap * 8);
+        p.wo_lact = put((size_t)cap * 4);
+        return off <= lim ? off : 0;
+    }
+    size_t fac = 0, scr = (size_t)kWgStage * 12;
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
         if (s.kind != kKron) continue;
         const size_t es = s.dtype == SL1_F64 ? 8 : (s.dtype == SL1_F32 ? 4 : 2);
         fac = std::max(fac, a16(((size_t)s.R * s.k1 * s.n1 + (size_t)s.R * s.k2 * s.n2) * es));
         const size_t v = (size_t)s.R * s.k2 * s.n1 * (s.dtype == SL1_F64 ? 8 : 4);   // BF16: hi + lo
-        scr = std::max(scr, a16(v));
+        scr = std::max(scr, std::max(a16(v), (size_t)(kWgWaves / 2) * 16 * 64 * 8));
     }
-    const size_t total = a16((size_t)p.N * 8) + a16((size_t)p.N * 4) + fac + scr;
-    const size_t lim = 160 * 1024 - 1024;   // static LDS of the kernel stays below 1 KB
-    if (total > lim || fac > (size_t)INT32_MAX || scr > (size_t)INT32_MAX) return 0;
-    p.wg_fac = (int)fac;
-    p.wg_scr = (int)scr;
-    return total;
+    p.wo_zf = put(N * 4);
+    p.wo_fac = fac ? put(fac) : -1;
+    p.wo_scr = put(scr);
+    const int cap_nz = 256, cap_act = 512;
+    const size_t extra = a16(N * 8) + a16((size_t)cap_nz * 12) + a16((size_t)cap_act * 4);
+    if (off + extra <= two_per_cu) {
+        p.wo_y = put(N * 8);
+        p.wg_cap_nz = cap_nz;
+        p.wg_cap_act = cap_act;
+        p.wo_lnj = put((size_t)cap_nz * 4);
+        p.wo_lnx = put((size_t)cap_nz * 8);
+        p.wo_lact = put((size_t)cap_act * 4);
+    } else {
+        p.wo_y = -1;
+        p.wg_cap_nz = p.wg_cap_act = 0;
+        p.wo_lnj = p.wo_lnx = p.wo_lact = 0;     // never dereferenced with capacity 0
+    }
+    return off <= lim ? off : 0;
 }
 
 // Iterations per whole-solve launch: bounded so that one launch streams at most
@@ -348,6 +389,53 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
     p.K = (int)d0->K;
     p.y_f64 = y_dtype == SL1_F64;
     p.n1_max = n1_max;
+    return SL1_OK;
+}
+
+#ifndef SL1_HYBRID_BYTES
+#define SL1_HYBRID_BYTES (1 << 20)
+#endif
+// Largest preserved set (atoms) at which the hybrid solve moves to the whole-solve
+// kernel: one CU then streams at most SL1_HYBRID_BYTES of dense columns per iteration.
+int hybrid_atoms(const SolveParams& p) {
+    size_t es = 0;
+    for (int i = 0; i < p.n_stages; ++i)
+        if (p.st[i].kind == kDense) es = std::max(es, p.st[i].dtype == SL1_F64 ? (size_t)8 : (size_t)4);
+    if (es == 0) return p.K;
+    return (int)std::max<size_t>(16, (size_t)SL1_HYBRID_BYTES / ((size_t)p.N * es));
+}
+
+// Whole-solve launches until every signal stopped (or the iteration cap, counting
+// the `done` iterations already run by the grid kernels); profile: launch times
+// and per-signal phase clocks.
+int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch, size_t wlds, bool prof, int dev,
+           long long done) {
+    const int per = std::min(wg_iters_per_launch(p), 256 * (o.chunk > 0 ? o.chunk : 16));
+    const long long cap = (long long)o.max_iter + 1;
+    long long launched = done;
+    for (;;) {
+        if (prof) HIP_TRY(hipEventRecord(w->ev_a, w->stream));
+        HIP_TRY(launch_solve_wg(w->dP, (int)batch, wlds, per, w->stream));
+        if (prof) HIP_TRY(hipEventRecord(w->ev_b, w->stream));
+        launched += per;
+        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        if (prof) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
+            w->wg_ms += ms;
+            w->wg_n += 1;
+        }
+        if (*w->h_active <= 0 || launched >= cap) break;
+    }
+    if (prof) {
+        std::vector<long long> ticks((size_t)batch * kWgPhases);
+        HIP_TRY(hipMemcpy(ticks.data(), w->d_wgprof, ticks.size() * 8, hipMemcpyDeviceToHost));
+        int khz = 0;
+        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        for (int64_t b = 0; b < batch; ++b)
+            for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] += (double)ticks[b * kWgPhases + k] / khz;
+    }
     return SL1_OK;
 }
 
@@ -633,23 +721,25 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.atom_norm = atom_norm;
     p.y = y;
     p.lam = lambda;
-    const int eng = o.flags & (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG);
-    if (eng == (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG)) return SL1_EINVAL;
-    const size_t wlds = wg_lds(p);
-    bool use_wg;
-    if (eng == SL1_FLAG_ENGINE_WG) {
+    const int eng = o.flags & (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG | SL1_FLAG_ENGINE_HYBRID);
+    if (eng & (eng - 1)) return SL1_EINVAL;   // at most one engine flag
+    const size_t wlds = wg_layout(p, false, 0);
+    bool use_wg = false, hybrid = false;
+    if (eng == SL1_FLAG_ENGINE_WG || eng == SL1_FLAG_ENGINE_HYBRID) {
         if (!wlds) return SL1_ELIMIT;
-        use_wg = true;
-    } else if (eng == SL1_FLAG_ENGINE_GRID) {
-        use_wg = false;
-    } else {
-        // one workgroup per signal pays off for small dictionaries: a dense stage is
-        // then streamed by one CU per signal at little cost; larger dense stages
-        // need the whole chip per iteration (grid engine)
-        use_wg = wlds && (int64_t)p.N * p.K <= (1 << 20);
+        use_wg = eng == SL1_FLAG_ENGINE_WG;
+        hybrid = !use_wg;
+    } else if (eng == 0 && wlds) {
+        // small dictionaries: one workgroup per signal throughout (a dense stage is
+        // cheap for one CU); larger ones: the grid kernels while the preserved sets
+        // are large, then the whole-solve kernel for the tail
+        use_wg = (int64_t)p.N * p.K <= (1 << 20);
+        hybrid = !use_wg;
     }
+    // the tail hand-over needs a dense last stage
+    if (p.st[p.n_stages - 1].kind != kDense) hybrid = false;
     const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
-    p.wg_prof = (use_wg && prof) ? w->d_wgprof : nullptr;
+    p.wg_prof = ((use_wg || hybrid) && prof) ? w->d_wgprof : nullptr;
     LaunchCfg cfg = launch_cfg(*w, p);
     if (!use_wg) {
         st = check_lds(cfg);
@@ -660,7 +750,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+    HIP_TRY(hipMemsetAsync(w->d_active, 0, 48, w->stream));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
     if (prof) {
         for (int k = 0; k < 3; ++k) {
@@ -668,40 +758,19 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
             w->prof_n[k] = 0;
         }
         for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] = 0.0;
+        w->wg_ms = 0.0;
+        w->wg_n = 0;
     }
     if (use_wg) {
         if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
-        const int per = std::min(wg_iters_per_launch(p), 256 * (o.chunk > 0 ? o.chunk : 16));
-        const long long cap = (long long)o.max_iter + 1;
-        long long launched = 0;
-        for (;;) {
-            if (prof) HIP_TRY(hipEventRecord(w->ev_a, w->stream));
-            HIP_TRY(launch_solve_wg(w->dP, (int)batch, wlds, per, w->stream));
-            if (prof) HIP_TRY(hipEventRecord(w->ev_b, w->stream));
-            launched += per;
-            HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
-            HIP_TRY(hipStreamSynchronize(w->stream));
-            if (prof) {
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
-                w->prof_ms[0] += ms;
-                w->prof_n[0] += 1;
-            }
-            if (*w->h_active <= 0 || launched >= cap) break;
-        }
-        if (prof) {
-            std::vector<long long> ticks((size_t)batch * kWgPhases);
-            HIP_TRY(hipMemcpy(ticks.data(), w->d_wgprof, ticks.size() * 8, hipMemcpyDeviceToHost));
-            int khz = 0;
-            HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-            for (int64_t b = 0; b < batch; ++b)
-                for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] += (double)ticks[b * kWgPhases + k] / khz;
-        }
+        st = run_wg(w, p, o, batch, wlds, prof, dev, 0);
+        if (st != SL1_OK) return st;
         return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
     }
     // iterations alternate between the two control slots: chunks have even length
     const int chunk = o.chunk > 0 ? ((o.chunk + 1) & ~1) : 16;
     const bool use_graph = !(o.flags & SL1_FLAG_NO_GRAPH);
+    const int hyb_atoms = hybrid_atoms(p);
     if (use_graph && (!w->graph || w->graph_chunk != chunk || !cfg_equal(cfg, w->graph_cfg))) {
         if (w->graph) {
             HIP_TRY(hipGraphExecDestroy(w->graph));
@@ -764,9 +833,26 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
                     w->prof_n[k] += 1;
                 }
         }
-        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 48, hipMemcpyDeviceToHost, w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (*w->h_active <= 0 || launched > cap) break;
+        // hand the remaining iterations to the whole-solve kernel once every live
+        // signal is on the last stage with a small preserved set (statistics of
+        // the chunk's last launch, slot 1)
+        const int* stat1 = w->h_active + 4 + 4;
+        if (hybrid && stat1[0] <= hyb_atoms && stat1[2] == 0) {
+            const size_t tlds = wg_layout(p, true, stat1[0]);
+            if (tlds) {
+                HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+                HIP_TRY(launch_one(0, 0, w->dP, cfg, w->stream));
+                HIP_TRY(launch_to_wg(w->dP, (int)batch, w->stream));
+                w->last_engine = SL1_ENGINE_HYBRID;
+                if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
+                st = run_wg(w, p, o, batch, tlds, prof, dev, launched);
+                if (st != SL1_OK) return st;
+                break;
+            }
+        }
     }
     return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
 }
@@ -947,16 +1033,21 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
     return SL1_OK;
 }
 
-int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms) {
+int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms,
+                          long long* wg_launches) {
     if (!engine) return SL1_EINVAL;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
     if (it == g_ws.end()) return SL1_EINVAL;
-    *engine = it->second->last_engine;
-    if (phase_ms)
-        for (int k = 0; k < kWgPhases; ++k) phase_ms[k] = it->second->phase_ms[k];
+    const Workspace& w = *it->second;
+    *engine = w.last_engine;
+    if (phase_ms) {
+        for (int k = 0; k < kWgPhases; ++k) phase_ms[k] = w.phase_ms[k];
+        phase_ms[kWgPhases] = w.wg_ms;
+    }
+    if (wg_launches) *wg_launches = w.wg_n;
     return SL1_OK;
 }
 

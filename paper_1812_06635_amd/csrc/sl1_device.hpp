@@ -17,6 +17,16 @@ typedef float f32v4 __attribute__((ext_vector_type(4)));
 typedef double f64v2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// block-uniform values (read from LDS or computed identically by every lane)
+// moved to scalar registers, so that addresses derived from them are scalar
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xFFFFFFFFll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // workspace accessors (signal b, buffer parity par)
 __device__ __forceinline__ double* xbuf(const SolveParams* P, int b, int par) {
     return P->x + ((size_t)b * 2 + par) * P->K;
@@ -198,41 +208,79 @@ __device__ __forceinline__ double clip_scale(double s0, double m) {
     return fmin(fmax(s0, -1.0 / m), 1.0 / m);
 }
 
-// dense correlations: NA atoms per wave streamed together (their loads are in
-// flight at once), FP64 accumulation of the decoded storage values
+// four consecutive stored elements of a dense column, kept in storage form
+// until use so that many loads fit in registers at once
+template <int DT> struct Raw4;
+template <> struct Raw4<SL1_F64> { f64v2 a, b; };
+template <> struct Raw4<SL1_F32> { f32v4 a; };
+template <> struct Raw4<SL1_BF16> { u16x4 a; };
+template <> struct Raw4<SL1_FP8_E4M3> { uint32_t a; };
+
 template <int DT>
-__device__ __forceinline__ void load4(const void* A, size_t idx, double (&v)[4]) {
+__device__ __forceinline__ Raw4<DT> raw_load(const void* A, size_t idx) {
+    Raw4<DT> r;
     if constexpr (DT == SL1_F64) {
         const f64v2* p = (const f64v2*)((const double*)A + idx);
-        const f64v2 a = p[0], c = p[1];
-        v[0] = a[0]; v[1] = a[1]; v[2] = c[0]; v[3] = c[1];
+        r.a = p[0];
+        r.b = p[1];
     } else if constexpr (DT == SL1_F32) {
-        const f32v4 a = *(const f32v4*)((const float*)A + idx);
-        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+        r.a = *(const f32v4*)((const float*)A + idx);
     } else if constexpr (DT == SL1_BF16) {
-        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
-        v[0] = bf16_to_f(a[0]); v[1] = bf16_to_f(a[1]); v[2] = bf16_to_f(a[2]); v[3] = bf16_to_f(a[3]);
+        r.a = *(const u16x4*)((const uint16_t*)A + idx);
     } else {
-        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
-        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
-        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+        r.a = *(const uint32_t*)((const uint8_t*)A + idx);
+    }
+    return r;
+}
+
+// decoded values (exact in FP64)
+template <int DT>
+__device__ __forceinline__ void raw_get(const Raw4<DT>& r, double (&v)[4]) {
+    if constexpr (DT == SL1_F64) {
+        v[0] = r.a[0]; v[1] = r.a[1]; v[2] = r.b[0]; v[3] = r.b[1];
+    } else if constexpr (DT == SL1_F32) {
+        v[0] = r.a[0]; v[1] = r.a[1]; v[2] = r.a[2]; v[3] = r.a[3];
+    } else if constexpr (DT == SL1_BF16) {
+        v[0] = bf16_to_f(r.a[0]); v[1] = bf16_to_f(r.a[1]); v[2] = bf16_to_f(r.a[2]); v[3] = bf16_to_f(r.a[3]);
+    } else {
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.a, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.a, true);
         v[0] = lo[0]; v[1] = lo[1]; v[2] = hi[0]; v[3] = hi[1];
     }
 }
 
+// NA atoms per wave; each pass issues the loads of NK 256-element steps of all
+// NA atoms before the first product (loads past N are clamped to a valid
+// address and discarded).  Per lane the products are accumulated in increasing k.
 template <int DT, int NA>
 __device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const int (&js)[NA], const double* zs,
                                              int lane, double (&out)[NA]) {
+    constexpr int NK = (DT == SL1_F64 ? 4 : 8) / NA > 0 ? (DT == SL1_F64 ? 4 : 8) / NA : 1;
     double acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-    for (int k = lane * 4; k < N; k += 256) {
-        double a[NA][4];
+    for (int kb = 0; kb < N; kb += 256 * NK) {
+        Raw4<DT> r[NA][NK];
 #pragma unroll
-        for (int q = 0; q < NA; ++q) load4<DT>(st.A, (size_t)js[q] * N + k, a[q]);
-        const double z0 = zs[k], z1 = zs[k + 1], z2 = zs[k + 2], z3 = zs[k + 3];
+        for (int s = 0; s < NK; ++s) {
+            const int k = kb + 256 * s + 4 * lane;
+            const int kc = k < N ? k : 0;
 #pragma unroll
-        for (int q = 0; q < NA; ++q) acc[q] += a[q][0] * z0 + a[q][1] * z1 + a[q][2] * z2 + a[q][3] * z3;
+            for (int q = 0; q < NA; ++q) r[q][s] = raw_load<DT>(st.A, (size_t)js[q] * N + kc);
+        }
+#pragma unroll
+        for (int s = 0; s < NK; ++s) {
+            const int k = kb + 256 * s + 4 * lane;
+            if (k < N) {
+                const double z0 = zs[k], z1 = zs[k + 1], z2 = zs[k + 2], z3 = zs[k + 3];
+#pragma unroll
+                for (int q = 0; q < NA; ++q) {
+                    double a[4];
+                    raw_get<DT>(r[q][s], a);
+                    acc[q] += a[0] * z0 + a[1] * z1 + a[2] * z2 + a[3] * z3;
+                }
+            }
+        }
     }
 #pragma unroll
     for (int q = 0; q < NA; ++q) {

@@ -99,10 +99,16 @@ struct SolveParams {
     int* cnt_adj;             // [batch] work items of the correlation launch (current iteration)
     int* cnt_upd;             // [batch] work items of the update launch (current iteration)
     int* active_signals;      // one int: signals not yet done
+    int* stat;                // [2][4] per forward-launch slot: max and sum of |A_t| over live
+                              // signals, live signals not yet on the last stage, unused
     int nseg_max, nrc, nadj_max, n1_max;
-    // whole-solve engine: LDS bytes of the factor copy and of the shared scratch,
+    // whole-solve engine: byte offsets of its dynamic LDS regions (-1: absent):
+    // z in FP64 and FP32, y, the current stage's Kronecker factors, the scratch
+    // (staging, cross-wave sums, Kronecker intermediate), the nonzero list (index
+    // and value) and the preserved list, with the two list capacities (entries);
     // optional per-signal phase clocks [batch][kWgPhases] (wall-clock ticks)
-    int wg_fac, wg_scr;
+    int wo_zd, wo_zf, wo_y, wo_fac, wo_scr, wo_lnj, wo_lnx, wo_lact;
+    int wg_cap_nz, wg_cap_act;
     long long* wg_prof;
 };
 

@@ -121,6 +121,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         P->cnt_adj[b] = 0;
         P->cnt_upd[b] = 0;
         if (ok) atomicAdd(P->active_signals, 1);
+        if (b == 0) {
+            for (int k = 0; k < 8; ++k) P->stat[k] = 0;
+        }
     }
 }
 
@@ -197,11 +200,116 @@ __device__ int advance_control(const SolveParams* P, int b, const Control& Cp, C
 }
 
 // ---------------------------------------------------------------------------
+// forward gathers for one lane's rows r0..r0+3 over the staged nonzeros [k0, k1)
+// (same per-element arithmetic as fwd_accumulate).  Dense: G columns per step,
+// every load issued before the first product.  Kronecker: staged entries are
+// (j1 << 16) | j2; four atoms generated together, term by term.
+// ---------------------------------------------------------------------------
+template <int DT>
+__device__ __forceinline__ void fwd_dense_gather(const StageDesc& st, int N, int r0, const int* s_j, const double* s_x,
+                                                 int k0, int k1, double (&acc)[4]) {
+    constexpr int G = DT == SL1_F64 ? 2 : 4;
+    constexpr bool kScaled = DT == SL1_BF16 || DT == SL1_FP8_E4M3;
+    const float* scale = kScaled ? st.scale : nullptr;
+    for (int k = k0; k < k1; k += G) {
+        Raw4<DT> r[G];
+        double xs[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int kk = min(k + g, k1 - 1);
+            const int j = s_j[kk];
+            r[g] = raw_load<DT>(st.A, (size_t)j * N + r0);
+            xs[g] = k + g < k1 ? s_x[kk] : 0.0;
+            if (scale) xs[g] *= (double)scale[j];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (k + g < k1) {
+                double a[4];
+                raw_get<DT>(r[g], a);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += xs[g] * a[v];
+            }
+        }
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, int r0, const int* s_j, const double* s_x,
+                                                int k0, int k1, double (&acc)[4]) {
+    constexpr int G = DT == SL1_F64 ? 2 : 4;
+    const int n1 = st.n1, k1d = st.k1, n2 = st.n2, k2 = st.k2, R = st.R;
+    const int i1 = r0 / n2, i2 = r0 - i1 * n2;
+    for (int k = k0; k < k1; k += G) {
+        int j1[G], j2[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int jp = s_j[min(k + g, k1 - 1)];
+            j1[g] = jp >> 16;
+            j2[g] = jp & 0xFFFF;
+        }
+        if constexpr (DT == SL1_F64) {
+            const double* Bf = (const double*)st.B;
+            const double* Cf = (const double*)st.C;
+            double a[G][4];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a[g][v] = 0.0;
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const double bv = Bf[((size_t)r * k1d + j1[g]) * n1 + i1];
+                    const f64v2* cp = (const f64v2*)(Cf + ((size_t)r * k2 + j2[g]) * n2 + i2);
+                    const f64v2 c0 = cp[0], c1 = cp[1];
+                    a[g][0] += bv * c0[0]; a[g][1] += bv * c0[1]; a[g][2] += bv * c1[0]; a[g][3] += bv * c1[1];
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (k + g < k1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[v] += s_x[k + g] * a[g][v];
+                }
+        } else {
+            float a[G][4];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a[g][v] = 0.f;
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    float bv, cv[4];
+                    if constexpr (DT == SL1_F32) {
+                        bv = ((const float*)st.B)[((size_t)r * k1d + j1[g]) * n1 + i1];
+                        const f32v4 c = *(const f32v4*)((const float*)st.C + ((size_t)r * k2 + j2[g]) * n2 + i2);
+                        cv[0] = c[0]; cv[1] = c[1]; cv[2] = c[2]; cv[3] = c[3];
+                    } else {
+                        bv = bf16_to_f(((const uint16_t*)st.B)[((size_t)r * k1d + j1[g]) * n1 + i1]);
+                        const u16x4 c = *(const u16x4*)((const uint16_t*)st.C + ((size_t)r * k2 + j2[g]) * n2 + i2);
+                        cv[0] = bf16_to_f(c[0]); cv[1] = bf16_to_f(c[1]); cv[2] = bf16_to_f(c[2]); cv[3] = bf16_to_f(c[3]);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) a[g][v] = fmaf(bv, cv[v], a[g][v]);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (k + g < k1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[v] += s_x[k + g] * (double)a[g][v];
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // forward product and residual (Section III-C: rho~_t = y - A~ x_t)
 // items: row chunks of 256 rows; the 8 waves of a block share the nonzeros of
 // x_t for the same rows and reduce in LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict__ P, int slot) {
+__global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int prev = 1 - slot;
     const int N = P->N, batch = P->batch;
@@ -223,6 +331,12 @@ __global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict
     if (blockIdx.x == 0) {
         for (int b = threadIdx.x; b < batch; b += blockDim.x)
             if (s_wpre[b + 1] == s_wpre[b]) P->cnt_fwd[(size_t)prev * batch + b] = 0;
+        // the other slot's statistics are gathered afresh by the next forward launch
+        if (threadIdx.x == 0) {
+            P->stat[4 * prev] = 0;
+            P->stat[4 * prev + 1] = 0;
+            P->stat[4 * prev + 2] = 0;
+        }
     }
     const int per = (total + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
@@ -230,8 +344,8 @@ __global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict
     int cur_b = -1, finished = 0;
     Control C;
     for (int g = g0; g < g1; ++g) {
-        const int b = find_signal(s_wpre, batch, g);
-        const int item = g - s_wpre[b];
+        const int b = uni(find_signal(s_wpre, batch, g));
+        const int item = uni(g - s_wpre[b]);
         if (b != cur_b) {
             cur_b = b;
             const Control Cp = P->ctrl[2 * b + prev];
@@ -283,6 +397,9 @@ __global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict
                         Control D = C;
                         D.advance = 1;
                         P->ctrl[2 * b + slot] = D;
+                        atomicMax(P->stat + 4 * slot, C.n_act);
+                        atomicAdd(P->stat + 4 * slot + 1, C.n_act);
+                        if (C.stage < P->n_stages - 1) atomicAdd(P->stat + 4 * slot + 2, 1);
                         P->cnt_adj[b] = adj_items(P->st[C.stage], C.n_act, N);
                         P->cnt_upd[b] = max(1, (C.n_act + kSeg - 1) / kSeg);
                         if (Cp.advance && P->trace && Cp.iter < P->trace_cap) {
@@ -298,24 +415,38 @@ __global__ __launch_bounds__(kFwdBlock) void k_fwd(const SolveParams* __restrict
         }
         if (finished) continue;
 
-        const StageDesc& st = P->st[C.stage];
+        const int stg = uni(C.stage), par = uni(C.par), nnz = uni(C.n_nz), nseg_nz = uni(C.nseg_nz);
+        const StageDesc& st = P->st[stg];
+        const bool kron = st.kind == kKron;
         const int r0 = item * kFwdRows + lane * 4;
-        const int* nzi = nzbuf(P, b, C.par);
-        const double* x = xbuf(P, b, C.par);
-        const int nnz = C.n_nz;
+        const int* nzi = nzbuf(P, b, par);
+        const double* x = xbuf(P, b, par);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int base = 0; base < nnz; base += kFwdBlock) {
             const int cnt = min(kFwdBlock, nnz - base);
             if ((int)threadIdx.x < cnt) {
-                const int j = list_get(nzi, s_zpre, C.nseg_nz, base + threadIdx.x);
-                s_j[threadIdx.x] = j;
+                const int j = list_get(nzi, s_zpre, nseg_nz, base + threadIdx.x);
+                if (kron) {
+                    const int j1 = j / st.k2;
+                    s_j[threadIdx.x] = (j1 << 16) | (j - j1 * st.k2);
+                } else {
+                    s_j[threadIdx.x] = j;
+                }
                 s_x[threadIdx.x] = x[j];
             }
             __syncthreads();
             const int pw = (cnt + kFwdWaves - 1) / kFwdWaves;
-            const int k0 = w * pw, k1 = min(cnt, k0 + pw);
-            if (r0 < N) {
-                for (int k = k0; k < k1; ++k) fwd_accumulate(st, N, s_j[k], s_x[k], r0, acc);
+            const int k0 = min(cnt, w * pw), k1 = min(cnt, k0 + pw);
+            if (r0 < N && k0 < k1) {
+                switch (st.kind * 4 + st.dtype) {
+                    case kDense * 4 + SL1_F64: fwd_dense_gather<SL1_F64>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case kDense * 4 + SL1_F32: fwd_dense_gather<SL1_F32>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case kDense * 4 + SL1_BF16: fwd_dense_gather<SL1_BF16>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case kDense * 4 + SL1_FP8_E4M3: fwd_dense_gather<SL1_FP8_E4M3>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case kKron * 4 + SL1_F64: fwd_kron_gather<SL1_F64>(st, r0, s_j, s_x, k0, k1, acc); break;
+                    case kKron * 4 + SL1_F32: fwd_kron_gather<SL1_F32>(st, r0, s_j, s_x, k0, k1, acc); break;
+                    default: fwd_kron_gather<SL1_BF16>(st, r0, s_j, s_x, k0, k1, acc); break;
+                }
             }
             __syncthreads();
         }
@@ -583,8 +714,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj(const SolveParams* __restrict
     Control C;
     double rz = 0.0;
     for (int g = g0; g < g1; ++g) {
-        const int b = find_signal(s_wpre, batch, g);
-        const int c = g - s_wpre[b];
+        const int b = uni(find_signal(s_wpre, batch, g));
+        const int c = uni(g - s_wpre[b]);
         const StageDesc* stp;
         if (b != cur_b) {
             cur_b = b;
@@ -744,8 +875,8 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
     Control C;
     Scalars S;
     for (int g = g0; g < g1; ++g) {
-        const int b = find_signal(s_wpre, batch, g);
-        const int c = g - s_wpre[b];
+        const int b = uni(find_signal(s_wpre, batch, g));
+        const int c = uni(g - s_wpre[b]);
         if (b != cur_b) {
             cur_b = b;
             C = P->ctrl[2 * b + slot];

@@ -30,14 +30,6 @@ namespace {
 
 __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// block-uniform values read from LDS, moved to scalar registers
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ double uni(double v) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xFFFFFFFFll));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // exclusive prefix of a per-thread flag over the 8-wave block; total returned in `total`
 __device__ __forceinline__ int wg_scan_flag(bool f, int* s_w, int& total) {
@@ -58,12 +50,9 @@ __device__ __forceinline__ int wg_scan_flag(bool f, int* s_w, int& total) {
 }
 
 // ---------------------------------------------------------------------------
-// forward product.  A lane holds 16 rows row(e) = rbase + (e / 4) rstride +
-// e % 4: dense stages rbase = chunk 1024 + 4 lane, rstride = 256; Kronecker
-// stages the 4 x 4 block i1 = 4 ba + e / 4, i2 = 4 bc + e % 4 of block
-// chunk 64 + lane (rbase = 4 ba n2 + 4 bc, rstride = n2), so that one LDS
-// vector of B_r and one of C_r serve 16 products.  Staged nonzeros carry j for
-// dense stages and (j1 << 16) | j2 for Kronecker stages.
+// Kronecker forward product: a lane holds the 4 x 4 block of rows i1 = 4 ba + e / 4,
+// i2 = 4 bc + e % 4 (block chunk 64 + lane), so that one LDS vector of B_r and
+// one of C_r serve 16 products; staged nonzeros carry (j1 << 16) | j2.
 // ---------------------------------------------------------------------------
 template <int DT>
 __device__ __forceinline__ void wg_kron_fwd(const char* fac, const StageDesc& st, int jp, double xj, int ba, int bc,
@@ -129,93 +118,21 @@ __device__ __forceinline__ void wg_kron_fwd(const char* fac, const StageDesc& st
     }
 }
 
-// four consecutive elements of a dense column in FP32/BF16/FP8 storage, decoded
-// to float (exact); the column scale is applied in FP64 by the caller
-__device__ __forceinline__ f32v4 dense4_f(int dtype, const void* A, size_t idx) {
-    f32v4 r;
-    if (dtype == SL1_F32) {
-        r = *(const f32v4*)((const float*)A + idx);
-    } else if (dtype == SL1_BF16) {
-        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
-        r = f32v4{bf16_to_f(a[0]), bf16_to_f(a[1]), bf16_to_f(a[2]), bf16_to_f(a[3])};
-    } else {
-        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
-        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
-        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
-        r = f32v4{lo[0], lo[1], hi[0], hi[1]};
-    }
-    return r;
-}
-
-// accumulate this wave's share [k0, k1) of the staged nonzeros.  D64: FP64
-// storage (dense or Kronecker); otherwise FP32/BF16/FP8 dense or FP32/BF16
-// Kronecker, the storage type decoded per load.
+// accumulate this wave's share [k0, k1) of the staged nonzeros of a Kronecker
+// stage (entries (j1 << 16) | j2); D64: FP64 factors, else FP32 or BF16
 template <bool D64>
-__device__ __forceinline__ void wg_fwd_range(const StageDesc& st, const char* fac, int N, int rbase, int nq, int ba,
-                                             int bc, bool kvalid, const int* s_j, const double* s_x, int k0, int k1,
-                                             double (&acc)[16]) {
-    if (st.kind == kDense) {
-        if constexpr (D64) {
+__device__ __forceinline__ void wg_kron_range(const StageDesc& st, const char* fac, int ba, int bc, bool kvalid,
+                                              const int* s_j, const double* s_x, int k0, int k1, double (&acc)[16]) {
+    if (!kvalid) return;
+    if constexpr (D64) {
 #pragma unroll 1
-            for (int k = k0; k < k1; ++k) {
-                const int j = s_j[k];
-                const double xj = s_x[k];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (q < nq) {
-                        const f64v2* p = (const f64v2*)((const double*)st.A + (size_t)j * N + rbase + 256 * q);
-                        const f64v2 u = p[0], v = p[1];
-                        acc[4 * q + 0] += xj * u[0];
-                        acc[4 * q + 1] += xj * u[1];
-                        acc[4 * q + 2] += xj * v[0];
-                        acc[4 * q + 3] += xj * v[1];
-                    }
-                }
-            }
-        } else {
-            const int dt = st.dtype;
-            const bool scaled = st.scale != nullptr && dt != SL1_F32;
+        for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_F64>(fac, st, s_j[k], s_x[k], ba, bc, acc);
+    } else if (st.dtype == SL1_F32) {
 #pragma unroll 1
-            for (int k = k0; k < k1; k += 2) {
-                const bool two = k + 1 < k1;
-                const int ja = s_j[k], jb = two ? s_j[k + 1] : ja;
-                double sa = s_x[k], sb = two ? s_x[k + 1] : 0.0;
-                f32v4 va[4], vb[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (q < nq) {
-                        va[q] = dense4_f(dt, st.A, (size_t)ja * N + rbase + 256 * q);
-                        vb[q] = dense4_f(dt, st.A, (size_t)jb * N + rbase + 256 * q);
-                    } else {
-                        va[q] = vb[q] = f32v4{0.f, 0.f, 0.f, 0.f};
-                    }
-                }
-                if (scaled) {
-                    sa *= (double)st.scale[ja];
-                    sb *= (double)st.scale[jb];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[4 * q + v] += sa * (double)va[q][v];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[4 * q + v] += sb * (double)vb[q][v];
-            }
-        }
+        for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_F32>(fac, st, s_j[k], s_x[k], ba, bc, acc);
     } else {
-        if (!kvalid) return;
-        if constexpr (D64) {
 #pragma unroll 1
-            for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_F64>(fac, st, s_j[k], s_x[k], ba, bc, acc);
-        } else if (st.dtype == SL1_F32) {
-#pragma unroll 1
-            for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_F32>(fac, st, s_j[k], s_x[k], ba, bc, acc);
-        } else {
-#pragma unroll 1
-            for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_BF16>(fac, st, s_j[k], s_x[k], ba, bc, acc);
-        }
+        for (int k = k0; k < k1; ++k) wg_kron_fwd<SL1_BF16>(fac, st, s_j[k], s_x[k], ba, bc, acc);
     }
 }
 
@@ -237,39 +154,32 @@ __device__ __forceinline__ void wg_reduce_rows(double (&acc)[16], double* scr) {
     }
 }
 
-// forward product, residual, stored direction z (into LDS) and the three FP64
-// sums ||rho||^2, ||z||^2, y^T z (into s_sum, by wave 0)
+// signal value y[row] (from LDS when it is held there)
+__device__ __forceinline__ double wg_y(const SolveParams* P, int b, const double* yl, int row) {
+    return yl ? yl[row] : yval(P, b, row);
+}
+
+// Kronecker forward product, residual, stored direction z (LDS) and the FP64
+// sums ||rho||^2, ||z||^2, y^T z (into s_sum).  The 8 waves split the staged
+// nonzeros; a lane holds a 4 x 4 block of rows (one LDS vector of B_r and one of
+// C_r serve 16 products) and the partials meet in a fixed tree.
 template <bool D64>
-__device__ __forceinline__ void wg_forward(const SolveParams* P, int b, const StageDesc& st, const char* fac,
-                                           const double* x, const int* nzl, int n_nz, int zround, double* zd,
-                                           float* zf, char* scr, double* s_sum) {
+__device__ __forceinline__ void wg_kron_forward(const SolveParams* P, int b, const StageDesc& st, const char* fac,
+                                                const double* x, const int* nzl, int n_nz, int zround, double* zd,
+                                                float* zf, const double* yl, char* scr, double* s_red,
+                                                double* s_sum) {
     const int N = P->N, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int nchunk = (N + kWgRows - 1) / kWgRows;
-    const bool dense = st.kind == kDense;
     const int k2 = st.k2;
     double* s_x = (double*)scr;                                   // staging shares the scratch
     int* s_j = (int*)(scr + kWgStage * 8);
-    const double* y64 = (const double*)P->y + (size_t)b * N;
-    const float* y32 = (const float*)P->y + (size_t)b * N;
-    const bool yd = P->y_f64;
     double sums[3] = {0.0, 0.0, 0.0};
     for (int chunk = 0; chunk < nchunk; ++chunk) {
-        // this lane's rows
-        int rbase, rstride, nq, ba = 0, bc = 0;
-        bool kvalid = false;
-        if (dense) {
-            rbase = chunk * kWgRows + 4 * lane;
-            rstride = 256;
-            nq = rbase < N ? min(4, (N - rbase + 255) / 256) : 0;
-        } else {
-            const int q = chunk * 64 + lane, nb2 = st.n2 >> 2;
-            kvalid = q < (N >> 4);
-            ba = kvalid ? q / nb2 : 0;
-            bc = kvalid ? q - ba * nb2 : 0;
-            rbase = 4 * ba * st.n2 + 4 * bc;
-            rstride = st.n2;
-            nq = kvalid ? 4 : 0;
-        }
+        const int q = chunk * 64 + lane, nb2 = st.n2 >> 2;
+        const bool kvalid = q < (N >> 4);
+        const int ba = kvalid ? q / nb2 : 0;
+        const int bc = kvalid ? q - ba * nb2 : 0;
+        const int rbase = 4 * ba * st.n2 + 4 * bc;
         double acc[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] = 0.0;
@@ -277,51 +187,158 @@ __device__ __forceinline__ void wg_forward(const SolveParams* P, int b, const St
             const int cnt = min(kWgStage, n_nz - base);
             if (tid < cnt) {
                 const int j = nzl[base + tid];
-                if (dense) {
-                    s_j[tid] = j;
-                } else {
-                    const int j1 = j / k2;
-                    s_j[tid] = (j1 << 16) | (j - j1 * k2);
-                }
+                const int j1 = j / k2;
+                s_j[tid] = (j1 << 16) | (j - j1 * k2);
                 s_x[tid] = x[j];
             }
             __syncthreads();
             const int pw = (cnt + kWgWaves - 1) / kWgWaves;
             const int k0 = min(cnt, w * pw), k1 = min(cnt, k0 + pw);
-            wg_fwd_range<D64>(st, fac, N, rbase, nq, ba, bc, kvalid, s_j, s_x, k0, k1, acc);
+            wg_kron_range<D64>(st, fac, ba, bc, kvalid, s_j, s_x, k0, k1, acc);
             __syncthreads();
         }
         wg_reduce_rows(acc, (double*)scr);
-        if (w == 0) {
+        if (w == 0 && kvalid) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q < nq) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = rbase + q * rstride + v;
-                        const double yv = yd ? y64[row] : (double)y32[row];
-                        const double rho = yv - acc[4 * q + v];
-                        double zv = rho;
-                        if (zround == 1) zv = (double)(float)rho;
-                        else if (zround == 2) zv = (double)bf16_rne((float)rho);
-                        zd[row] = zv;
-                        zf[row] = (float)zv;
-                        sums[0] += rho * rho;
-                        sums[1] += zv * zv;
-                        sums[2] += yv * zv;
-                    }
-                }
+            for (int e = 0; e < 16; ++e) {
+                const int row = rbase + (e >> 2) * st.n2 + (e & 3);
+                const double yv = wg_y(P, b, yl, row);
+                const double rho = yv - acc[e];
+                double zv = rho;
+                if (zround == 1) zv = (double)(float)rho;
+                else if (zround == 2) zv = (double)bf16_rne((float)rho);
+                zd[row] = zv;
+                zf[row] = (float)zv;
+                sums[0] += rho * rho;
+                sums[1] += zv * zv;
+                sums[2] += yv * zv;
             }
         }
     }
-    if (w == 0) {
+    block_sum<3>(sums, s_red);
+    if (tid == 0) {
+        s_sum[0] = sums[0];
+        s_sum[1] = sums[1];
+        s_sum[2] = sums[2];
+    }
+}
+
+// two consecutive stored elements (rows 2q, 2q + 1) of a dense column, decoded
+// to float (exact; FP64 storage handled separately)
+__device__ __forceinline__ void dense2_f(int dtype, const void* A, size_t idx, float& a0, float& a1) {
+    if (dtype == SL1_F32) {
+        typedef float f32v2 __attribute__((ext_vector_type(2)));
+        const f32v2 v = *(const f32v2*)((const float*)A + idx);
+        a0 = v[0];
+        a1 = v[1];
+    } else if (dtype == SL1_BF16) {
+        const uint32_t v = *(const uint32_t*)((const uint16_t*)A + idx);
+        a0 = bf16_to_f((uint16_t)(v & 0xFFFFu));
+        a1 = bf16_to_f((uint16_t)(v >> 16));
+    } else {
+        const uint32_t v = *(const uint16_t*)((const uint8_t*)A + idx);
+        const auto f = __builtin_amdgcn_cvt_pk_f32_fp8((int)v, false);
+        a0 = f[0];
+        a1 = f[1];
+    }
+}
+
+// u[row0], u[row0 + 1] over cnt nonzeros (lj, lx): G columns per step, every
+// load issued before the first product; same per-element arithmetic as the
+// grid forward kernel
+template <bool D64>
+__device__ __forceinline__ void wg_dense_rows(const StageDesc& st, int N, int row0, const int* lj, const double* lx,
+                                              int cnt, double& u0, double& u1) {
+    constexpr int G = D64 ? 4 : 8;
+    const int dt = st.dtype;
+    const float* scale = (!D64 && dt != SL1_F32) ? st.scale : nullptr;
+    for (int k = 0; k < cnt; k += G) {
+        double xs[G];
+        if constexpr (D64) {
+            f64v2 v[G];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sums[k] = wave_sum(sums[k]);
-        if (lane == 0) {
-            s_sum[0] = sums[0];
-            s_sum[1] = sums[1];
-            s_sum[2] = sums[2];
+            for (int g = 0; g < G; ++g) {
+                const int kk = min(k + g, cnt - 1);
+                v[g] = *(const f64v2*)((const double*)st.A + (size_t)lj[kk] * N + row0);
+                xs[g] = k + g < cnt ? lx[kk] : 0.0;
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (k + g < cnt) {
+                    u0 += xs[g] * v[g][0];
+                    u1 += xs[g] * v[g][1];
+                }
+        } else {
+            float a0[G], a1[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int kk = min(k + g, cnt - 1);
+                const int j = lj[kk];
+                dense2_f(dt, st.A, (size_t)j * N + row0, a0[g], a1[g]);
+                xs[g] = k + g < cnt ? lx[kk] : 0.0;
+                if (scale) xs[g] *= (double)scale[j];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (k + g < cnt) {
+                    u0 += xs[g] * (double)a0[g];
+                    u1 += xs[g] * (double)a1[g];
+                }
         }
+    }
+}
+
+// dense forward product, residual and sums: every thread owns row pairs
+// (2q, 2q + 1), q = tid + 512 c, over all nonzeros, so no cross-wave sum is
+// needed.  Nonzeros from the LDS list when it holds them, else staged from the
+// global list through the scratch.
+template <bool D64>
+__device__ __forceinline__ void wg_dense_forward(const SolveParams* P, int b, const StageDesc& st, const double* x,
+                                                 const int* nzl, int n_nz, const int* lj, const double* lx,
+                                                 bool in_lds, double* zd, float* zf, const double* yl, char* scr,
+                                                 double* s_red, double* s_sum) {
+    const int N = P->N, tid = threadIdx.x;
+    double* s_x = (double*)scr;
+    int* s_j = (int*)(scr + kWgStage * 8);
+    double sums[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c * 2 * kWgBlock < N; ++c) {
+        const int row0 = 2 * (tid + kWgBlock * c);
+        const bool valid = row0 < N;
+        double u0 = 0.0, u1 = 0.0;
+        if (in_lds) {
+            if (valid) wg_dense_rows<D64>(st, N, row0, lj, lx, n_nz, u0, u1);
+        } else {
+            for (int base = 0; base < n_nz; base += kWgStage) {
+                const int cnt = min(kWgStage, n_nz - base);
+                if (tid < cnt) {
+                    const int j = nzl[base + tid];
+                    s_j[tid] = j;
+                    s_x[tid] = x[j];
+                }
+                __syncthreads();
+                if (valid) wg_dense_rows<D64>(st, N, row0, s_j, s_x, cnt, u0, u1);
+                __syncthreads();
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int row = row0 + v;
+                const double yv = wg_y(P, b, yl, row);
+                const double rho = yv - (v ? u1 : u0);
+                zd[row] = rho;
+                if (zf) zf[row] = (float)rho;
+                sums[0] += rho * rho;
+                sums[1] += rho * rho;
+                sums[2] += yv * rho;
+            }
+        }
+    }
+    block_sum<3>(sums, s_red);
+    if (tid == 0) {
+        s_sum[0] = sums[0];
+        s_sum[1] = sums[1];
+        s_sum[2] = sums[2];
     }
 }
 
@@ -456,7 +473,8 @@ __device__ void wg_kron_adj(const StageDesc& st, const char* fac, const double* 
     }
 }
 
-// dense correlations over the preserved list: wave w takes NA atoms at a time
+// dense correlations over the preserved list (LDS or global): wave w takes NA
+// atoms at a time; eps_j is fetched together with the columns
 template <int NA>
 __device__ void wg_dense_adj(const StageDesc& st, int N, const int* act, int n_act, const double* zd, double rz,
                              double* g, double (&mx)[3]) {
@@ -473,18 +491,19 @@ __device__ void wg_dense_adj(const StageDesc& st, int N, const int* act, int n_a
 #pragma unroll
         for (int q = 0; q < NA; ++q)
             if (js[q] < 0) js[q] = js[0];
+        double e[NA];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) e[q] = st.eps[js[q]];
         double gv[NA];
         dense_dots<NA>(st, N, js, zd, lane, gv);
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
                 if (q < cnt) {
-                    const int j = js[q];
-                    g[j] = gv[q];
-                    const double e = st.eps[j];
-                    mx[0] = fmax(mx[0], fabs(gv[q]) + e * rz);
+                    g[js[q]] = gv[q];
+                    mx[0] = fmax(mx[0], fabs(gv[q]) + e[q] * rz);
                     mx[1] = fmax(mx[1], fabs(gv[q]));
-                    mx[2] = fmax(mx[2], e);
+                    mx[2] = fmax(mx[2], e[q]);
                 }
             }
         }
@@ -538,46 +557,106 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
     __shared__ double s_kt[2];
     __shared__ int s_cnt[2];
     __shared__ int s_w[kWgWaves];
-    __shared__ int s_loaded;
+    __shared__ int s_loaded, s_nz_ok, s_act_ok;
     __shared__ long long s_clk;
 
     if (tid == 0) {
         sC = P0->ctrl[2 * b];
         s_loaded = -1;
+        s_nz_ok = 0;
+        s_act_ok = 0;
         s_clk = P0->wg_prof ? wall_clock64() : 0;
     }
     __syncthreads();
     if (sC.done) return;
+    {
+        const SolveParams* P = phase_params(P0);
+        if (P->wo_y >= 0) {
+            double* yl = (double*)(smem + P->wo_y);
+            for (int i = tid; i < P->N; i += kWgBlock) yl[i] = yval(P, b, i);
+        }
+    }
 
     for (int it = 0; it < max_it; ++it) {
         const int stage = uni(sC.stage), par = uni(sC.par);
-        // ---- factors of a new Kronecker stage into LDS ----
+        const int n_nz = uni(sC.n_nz), n_act = uni(sC.n_act);
+        // ---- factors of a new Kronecker stage, and the two lists, into LDS ----
         {
             const SolveParams* P = phase_params(P0);
             const StageDesc& st = P->st[stage];
-            char* fac = smem + al16((size_t)P->N * 8) + al16((size_t)P->N * 4);
-            if (st.kind == kKron && uni(s_loaded) != stage) {
-                wg_copy_factors(st, fac);
-                __syncthreads();
-                if (tid == 0) s_loaded = stage;
-                __syncthreads();
+            // a layout without factor space serves dense stages only (the host
+            // chooses it when every live signal is on the last, dense, stage)
+            const bool bad = st.kind == kKron ? (P->wo_fac < 0 || P->wo_scr < 0)
+                                              : (n_nz > P->wg_cap_nz && P->wo_scr < 0);
+            if (bad) {
+                if (tid == 0) {
+                    Final F;
+                    F.gap = 0.0;
+                    F.gap_cert = 0.0;
+                    F.iters = sC.iter;
+                    F.stage = sC.stage;
+                    F.status = SL1_ELIMIT;
+                    F.par = sC.par;
+                    F.t0 = sC.t0;
+                    F.tconv = 0;
+                    P->fin[b] = F;
+                    sC.done = 1;
+                    P->ctrl[2 * b] = sC;
+                    atomicSub(P->active_signals, 1);
+                }
+                return;
             }
+            if (st.kind == kKron && uni(s_loaded) != stage) {
+                wg_copy_factors(st, smem + P->wo_fac);
+                if (tid == 0) s_loaded = stage;
+            }
+            const bool fill_nz = !uni(s_nz_ok) && n_nz <= P->wg_cap_nz;
+            const bool fill_act = !uni(s_act_ok) && n_act <= P->wg_cap_act;
+            if (fill_nz) {
+                const int* nzl = nzbuf(P, b, 0);
+                const double* x = xbuf(P, b, par);
+                int* lj = (int*)(smem + P->wo_lnj);
+                double* lx = (double*)(smem + P->wo_lnx);
+                for (int i = tid; i < n_nz; i += kWgBlock) {
+                    const int j = nzl[i];
+                    lj[i] = j;
+                    lx[i] = x[j];
+                }
+            }
+            if (fill_act) {
+                const int* act = actbuf(P, b, 0);
+                int* la = (int*)(smem + P->wo_lact);
+                for (int i = tid; i < n_act; i += kWgBlock) la[i] = act[i];
+            }
+            __syncthreads();
+            if (tid == 0) {
+                if (fill_nz) s_nz_ok = 1;
+                if (fill_act) s_act_ok = 1;
+            }
+            __syncthreads();
         }
         // ---- forward product and residual ----
         {
             const SolveParams* P = phase_params(P0);
-            const int N = P->N;
             const StageDesc& st = P->st[stage];
-            double* zd = (double*)smem;
-            float* zf = (float*)(smem + al16((size_t)N * 8));
-            char* fac = (char*)zf + al16((size_t)N * 4);
-            char* scr = fac + P->wg_fac;
+            double* zd = (double*)(smem + P->wo_zd);
+            float* zf = P->wo_zf >= 0 ? (float*)(smem + P->wo_zf) : nullptr;
+            const double* yl = P->wo_y >= 0 ? (const double*)(smem + P->wo_y) : nullptr;
+            char* scr = P->wo_scr >= 0 ? smem + P->wo_scr : nullptr;
             const double* x = xbuf(P, b, par);
             const int* nzl = nzbuf(P, b, 0);
-            const int zround = st.kind == kKron ? (st.dtype == SL1_BF16 ? 2 : (st.dtype == SL1_F32 ? 1 : 0)) : 0;
-            const int n_nz = uni(sC.n_nz);
-            if (st.dtype == SL1_F64) wg_forward<true>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, scr, s_sum);
-            else wg_forward<false>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, scr, s_sum);
+            if (st.kind == kKron) {
+                const char* fac = smem + P->wo_fac;
+                const int zround = st.dtype == SL1_BF16 ? 2 : (st.dtype == SL1_F32 ? 1 : 0);
+                if (st.dtype == SL1_F64) wg_kron_forward<true>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, yl, scr, s_red, s_sum);
+                else wg_kron_forward<false>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, yl, scr, s_red, s_sum);
+            } else {
+                const bool in_lds = uni(s_nz_ok) != 0;
+                const int* lj = (const int*)(smem + P->wo_lnj);
+                const double* lx = (const double*)(smem + P->wo_lnx);
+                if (st.dtype == SL1_F64) wg_dense_forward<true>(P, b, st, x, nzl, n_nz, lj, lx, in_lds, zd, zf, yl, scr, s_red, s_sum);
+                else wg_dense_forward<false>(P, b, st, x, nzl, n_nz, lj, lx, in_lds, zd, zf, yl, scr, s_red, s_sum);
+            }
             __syncthreads();
             wg_stamp(P, b, 0, s_clk);
         }
@@ -586,20 +665,20 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const SolveParams* P = phase_params(P0);
             const int N = P->N, K = P->K;
             const StageDesc& st = P->st[stage];
-            double* zd = (double*)smem;
-            float* zf = (float*)(smem + al16((size_t)N * 8));
-            char* fac = (char*)zf + al16((size_t)N * 4);
-            char* scr = fac + P->wg_fac;
+            const double* zd = (const double*)(smem + P->wo_zd);
             const double rz = uni(sqrt(s_sum[1]));
             double* gvec = gbuf(P, b, par);
             double mx[3] = {0.0, 0.0, 0.0};
             if (st.kind == kDense) {
-                const int apw = dense_apw(N), n_act = uni(sC.n_act);
-                const int* act = actbuf(P, b, 0);
+                const int apw = dense_apw(N);
+                const int* act = uni(s_act_ok) ? (const int*)(smem + P->wo_lact) : actbuf(P, b, 0);
                 if (apw == 4) wg_dense_adj<4>(st, N, act, n_act, zd, rz, gvec, mx);
                 else if (apw == 2) wg_dense_adj<2>(st, N, act, n_act, zd, rz, gvec, mx);
                 else wg_dense_adj<1>(st, N, act, n_act, zd, rz, gvec, mx);
             } else {
+                const char* fac = smem + P->wo_fac;
+                char* scr = smem + P->wo_scr;
+                const float* zf = (const float*)(smem + P->wo_zf);
                 const uint8_t* mask = P->mask + (size_t)b * K;
                 if (st.dtype == SL1_F64) wg_kron_adj<SL1_F64>(st, fac, zd, zf, scr, mask, rz, gvec, mx);
                 else if (st.dtype == SL1_F32) wg_kron_adj<SL1_F32>(st, fac, zd, zf, scr, mask, rz, gvec, mx);
@@ -639,9 +718,13 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const SolveParams* P = phase_params(P0);
             const int K = P->K;
             const StageDesc& st = P->st[stage];
-            const int n_act = uni(sC.n_act);
+            const int cap_nz = P->wg_cap_nz, cap_act = P->wg_cap_act;
             int* act = actbuf(P, b, 0);
             int* nzl = nzbuf(P, b, 0);
+            int* la = (int*)(smem + P->wo_lact);
+            int* lj = (int*)(smem + P->wo_lnj);
+            double* lx = (double*)(smem + P->wo_lnx);
+            const bool act_lds = uni(s_act_ok) != 0;
             uint8_t* mask = P->mask + (size_t)b * K;
             double* xc = xbuf(P, b, par);
             double* xo = xbuf(P, b, 1 - par);
@@ -657,13 +740,15 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             for (int base = 0; base < n_act; base += 2 * kWgBlock) {
                 int jj[2];
                 bool keep[2], nzf[2];
+                double xnv[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int i = base + h * kWgBlock + tid;
                     keep[h] = nzf[h] = false;
                     jj[h] = 0;
+                    xnv[h] = 0.0;
                     if (i < n_act) {
-                        const int j = act[i];
+                        const int j = act_lds ? la[i] : act[i];
                         jj[h] = j;
                         const double gt = gcur[j];
                         const double gp = gprev[j];
@@ -688,6 +773,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                             mask[j] = 0;
                         }
                         nzf[h] = keep[h] && (xn != 0.0);
+                        xnv[h] = xn;
                         sv[1] += fabs(xn);
                     }
                 }
@@ -697,9 +783,18 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                 for (int h = 0; h < 2; ++h) {
                     int tk, tz;
                     const int pk = wg_scan_flag(keep[h], s_w, tk);
-                    if (keep[h]) act[wpos + pk] = jj[h];
+                    if (keep[h]) {
+                        act[wpos + pk] = jj[h];
+                        if (wpos + pk < cap_act) la[wpos + pk] = jj[h];
+                    }
                     const int pz = wg_scan_flag(nzf[h], s_w, tz);
-                    if (nzf[h]) nzl[zpos + pz] = jj[h];
+                    if (nzf[h]) {
+                        nzl[zpos + pz] = jj[h];
+                        if (zpos + pz < cap_nz) {
+                            lj[zpos + pz] = jj[h];
+                            lx[zpos + pz] = xnv[h];
+                        }
+                    }
                     wpos += tk;
                     zpos += tz;
                 }
@@ -710,6 +805,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                 s_kt[1] = sv[1];
                 s_cnt[0] = wpos;
                 s_cnt[1] = zpos;
+                s_act_ok = wpos <= cap_act;
+                s_nz_ok = zpos <= cap_nz;
             }
             __syncthreads();
             wg_stamp(P, b, 3, s_clk);
@@ -746,6 +843,40 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
         __syncthreads();
     }
     if (tid == 0) P0->ctrl[2 * b] = sC;
+}
+
+// ---------------------------------------------------------------------------
+// hand-over from the per-iteration grid kernels: after a forward launch of slot
+// 0 has formed C_{t+1} (ctrl[2 b]) and the segment prefixes of its two lists,
+// copy the segmented lists of buffer C.par into contiguous lists in buffer 0,
+// the layout of the whole-solve kernel.  Segments go in increasing order, each
+// read completely before it is written, so the in-place case (par = 0) is safe:
+// a segment's destination never reaches a later segment's source.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSeg) void k_to_wg(const SolveParams* __restrict__ P) {
+    const int b = blockIdx.x;
+    const Control C = P->ctrl[2 * b];
+    if (C.done) return;
+    const int par = uni(C.par);
+    for (int which = 0; which < 2; ++which) {
+        const int nseg = uni(which ? C.nseg_nz : C.nseg_act);
+        const int* pre = which ? nzpre(P, b, par) : actpre(P, b, par);
+        const int* src = which ? nzbuf(P, b, par) : actbuf(P, b, par);
+        int* dst = which ? nzbuf(P, b, 0) : actbuf(P, b, 0);
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int p0 = pre[sg], cnt = pre[sg + 1] - p0;
+            int v = 0;
+            if ((int)threadIdx.x < cnt) v = src[(size_t)sg * kSeg + threadIdx.x];
+            __syncthreads();
+            if ((int)threadIdx.x < cnt) dst[p0 + threadIdx.x] = v;
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_to_wg(const SolveParams* dP, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_wg, dim3(batch), dim3(kSeg), 0, s, dP);
+    return hipGetLastError();
 }
 
 hipError_t launch_solve_wg(const SolveParams* dP, int batch, size_t lds, int max_it, hipStream_t s) {

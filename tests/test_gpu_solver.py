@@ -263,12 +263,37 @@ def test_engines_agree_and_relaunch_is_exact(sl1):
 def test_auto_engine_choice(sl1):
     _say("auto engine choice")
     import paper_1812_06635_amd as m
-    p = synth.config4(batch=40, n=(16, 32))
+    p = synth.config4(batch=40, n=(16, 32))                 # N*K = 2^18: whole-solve engine
     _run(sl1, p, tol=1e-6)
     assert m.last_solve_phases(p.batch, p.N, p.K)[0] == "wg"
-    q = synth.config2(n=(32, 64), R_A=4, Rs=(1, 4))        # one signal, N*K = 2^21
+    q = synth.config2(n=(32, 64), R_A=4, Rs=(1, 4))        # one signal, N*K = 2^22: grid, then the tail
     _run(sl1, q, tol=1e-6)
+    assert m.last_solve_phases(1, q.N, q.K)[0] in ("grid", "hybrid")
+    _run(sl1, q, tol=1e-6, engine="grid")
     assert m.last_solve_phases(1, q.N, q.K)[0] == "grid"
+
+
+def test_hybrid_hand_over_matches_grid(sl1):
+    # the full batched dictionary (N=1024, K=4096) on 12 signals: the grid kernels
+    # hand the tail to the whole-solve kernel; decisions and solutions agree
+    _say("hybrid hand-over, batched dictionary, 12 signals")
+    import paper_1812_06635_amd as m
+    p = synth.config4(batch=12)
+    g = _run(sl1, p, tol=1e-9, engine="grid")
+    h = _run(sl1, p, tol=1e-9, engine="hybrid", trace_cap=4000)
+    assert m.last_solve_phases(p.batch, p.N, p.K)[0] == "hybrid"
+    assert g["status"] == 0 and h["status"] == 0
+    np.testing.assert_array_equal(g["stage"], h["stage"])
+    assert np.all(np.abs(g["iters"] - h["iters"]) <= 2)
+    for b in range(p.batch):
+        rel = np.linalg.norm(g["x"][b] - h["x"][b]) / max(np.linalg.norm(g["x"][b]), 1e-300)
+        assert rel <= 1e-4, f"signal {b}: engines differ by {rel:.2e}"
+        n = int(h["iters"][b])
+        tr = h["trace"][b][:n]
+        assert np.array_equal(tr[:, 0], np.arange(n))                  # one trace row per iteration
+        assert np.all(tr[1:, 2] == tr[:-1, 3])                          # |A_t+1| carried over
+    for b in (0, 7):
+        _check_solution(p, h, b)
 
 
 @pytest.mark.parametrize("engine", ENGINES)
