@@ -152,9 +152,9 @@ int make_workspace(Workspace& w) {
     const size_t o_zp = take(B * 2 * np * 4);
     const size_t o_z = take(B * N * ws);
     const size_t o_rp = take(B * w.nrc * 3 * 8);
-    const size_t o_adp = take(B * w.nadj_max * 3 * 8);
+    const size_t o_adp = take(B * w.nadj_max * 4 * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
-    const size_t o_cnt = take(B * 4 * 4);
+    const size_t o_cnt = take(B * 5 * 4);
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
     const size_t o_times = take(B * 16);
@@ -182,7 +182,8 @@ int make_workspace(Workspace& w) {
     p.upd_part = (double*)(m + o_up);
     p.cnt_fwd = (int*)(m + o_cnt);
     p.cnt_adj = p.cnt_fwd + 2 * B;
-    p.cnt_upd = p.cnt_adj + B;
+    p.cnt_adjk = p.cnt_adj + B;
+    p.cnt_upd = p.cnt_adjk + B;
     p.active_signals = (int*)(m + o_act_sig);
     p.stat = p.active_signals + 4;
     p.nseg_max = w.nseg_max;
@@ -261,33 +262,42 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     const size_t nseg1 = (size_t)w.nseg_max + 1, nb1 = (size_t)w.batch + 1;
     c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + kFwdWaves * kFwdRows * 8;
     c.lds_upd = 4 * (nseg1 + nb1);
-    const size_t pre = (4 * (nseg1 + nb1) + 15) & ~(size_t)15;
-    // persistent grids: enough blocks to fill the chip, never more than the work
-    c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
-    c.g_adj = (int)std::min<long long>((long long)w.batch * w.nadj_max, 2048);
-    c.g_upd = (int)std::min<long long>((long long)w.batch * w.nseg_max, 1024);
+    // persistent grids: enough blocks to fill the chip, never more than the work;
+    // a correlation kernel whose stage kind is absent is not launched
+    bool dense = false;
+    int kron_items = 0;
     size_t extra = 0;
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
-        if (s.kind != kKron) continue;
+        if (s.kind != kKron) {
+            dense = true;
+            continue;
+        }
+        kron_items = std::max(kron_items, (s.k2 / 16) * ((s.k1 + kKronColTile - 1) / kKronColTile));
         size_t need;
         if (s.dtype == SL1_F64) need = 4 * 16 * (size_t)p.n1_max * 8 + 4 * 16 * 64 * 8;
         else need = 4 * 16 * 64 * 4 + 4 * 16 * (size_t)p.n1_max * 4;
         extra = std::max(extra, need);
     }
-    c.lds_adj = (((size_t)w.N * ws + 15) & ~(size_t)15) + pre + extra;
+    c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
+    c.g_adj = dense ? (int)std::min<long long>((long long)w.batch * w.nadj_max, 2048) : 0;
+    c.g_adjk = kron_items ? (int)std::min<long long>((long long)w.batch * kron_items, 1024) : 0;
+    c.g_upd = (int)std::min<long long>((long long)w.batch * w.nseg_max, 1024);
+    const size_t zb = ((size_t)w.N * ws + 15) & ~(size_t)15;
+    c.lds_adj = zb + 4 * (nseg1 + nb1);
+    c.lds_adjk = zb + ((4 * nb1 + 15) & ~(size_t)15) + extra;
     return c;
 }
 
 bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
-           a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_upd == b.g_upd && a.lds_fwd == b.lds_fwd &&
-           a.lds_adj == b.lds_adj && a.lds_upd == b.lds_upd;
+           a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_adjk == b.g_adjk && a.g_upd == b.g_upd &&
+           a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj && a.lds_adjk == b.lds_adjk && a.lds_upd == b.lds_upd;
 }
 
 int check_lds(const LaunchCfg& c) {
     const size_t lim = 160 * 1024;
-    if (c.lds_adj > lim || c.lds_fwd > lim) return SL1_ELIMIT;
+    if (c.lds_adj > lim || c.lds_adjk > lim || c.lds_fwd > lim) return SL1_ELIMIT;
     return SL1_OK;
 }
 

@@ -132,8 +132,9 @@ __device__ __forceinline__ int switch_dictionary(int i, int I, double gamma, dou
     return i;
 }
 
-// dense correlation items: atoms per wave so that a wave keeps ~16 loads in flight
-__device__ __forceinline__ int dense_apw(int N) { return N <= 1024 ? 4 : (N <= 2048 ? 2 : 1); }
+// dense correlation items: atoms per wave (a wave then has 8 column loads in
+// flight per pass at N <= 1024 and N <= 2048)
+__device__ __forceinline__ int dense_apw(int N) { return N <= 1024 ? 2 : 1; }
 
 // forward product: adds x_j a~_j[r0..r0+3] (4 rows per lane); a Kronecker atom
 // is generated from its factors, sum_r B_r[i1, j1] C_r[i2, j2] in storage precision

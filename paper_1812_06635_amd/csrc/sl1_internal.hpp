@@ -93,10 +93,11 @@ struct SolveParams {
     int* nz_pre;              // [batch][2][nseg_max+1]
     double* z;                // [batch][N]
     double* res_part;         // [batch][nrc][3]
-    double* adj_part;         // [batch][nadj_max][3]
+    double* adj_part;         // [batch][nadj_max][4 waves][3] per-wave maxima of the correlation items
     double* upd_part;         // [batch][nseg_max][4]
     int* cnt_fwd;             // [2][batch] work items of the forward launch of the iteration with parity s
-    int* cnt_adj;             // [batch] work items of the correlation launch (current iteration)
+    int* cnt_adj;             // [batch] work items of the dense correlation launch (current iteration)
+    int* cnt_adjk;            // [batch] work items of the Kronecker correlation launch
     int* cnt_upd;             // [batch] work items of the update launch (current iteration)
     int* active_signals;      // one int: signals not yet done
     int* stat;                // [2][4] per forward-launch slot: max and sum of |A_t| over live
@@ -114,8 +115,8 @@ struct SolveParams {
 
 struct LaunchCfg {
     int batch, nseg_max, nrc, nadj_max;
-    int g_fwd, g_adj, g_upd;          // persistent grid sizes (blocks)
-    size_t lds_fwd, lds_adj, lds_upd;
+    int g_fwd, g_adj, g_adjk, g_upd;  // persistent grid sizes (blocks; 0: launch skipped)
+    size_t lds_fwd, lds_adj, lds_adjk, lds_upd;
 };
 
 constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS

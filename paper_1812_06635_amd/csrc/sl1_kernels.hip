@@ -1,17 +1,19 @@
 // Per-iteration kernels of the stable-screening FISTA solver (gfx950).
 //
-// One iteration t of Algorithm 1 (FastL1) for every signal of a batch is three
-// launches, each covering all signals (grid.y = signal):
-//   k_fwd  forward product u = A~ x_t as a gather over the nonzeros of x_t,
-//          residual rho = y - u and its norms (FP64), stored direction z.
-//   k_adj  correlations g = A~^T z over the preserved set A_t (dense: one
-//          wavefront streams one atom; Kronecker: MFMA tiles of
-//          sum_r C_r^T P B_r), the maxima of the stable dual scaling, then the
-//          scalar block: dual points, gaps, delta, the stable GAP radius, the
-//          gap ratio and the stop decision (FP64).
-//   k_upd  per-atom stable GAP test, look-ahead count, FISTA step with soft
-//          thresholding, compaction of the preserved set and of the nonzeros
-//          (wavefront ballot + prefix), then Algorithm 2 and momentum update.
+// One iteration t of Algorithm 1 (FastL1) for every live signal of a batch is
+// three steps, each a persistent launch over a work list of (signal, item) pairs:
+//   k_fwd        forward product u = A~ x_t as a gather over the nonzeros of x_t,
+//                residual rho = y - u and its norms (FP64), stored direction z;
+//                also folds the previous iteration's partials into C_t
+//                (Algorithm 2, momentum, list prefixes).
+//   k_adj_dense  correlations g = A~^T z over the preserved set A_t on dense
+//   k_adj_kron   stages (each wavefront streams a few atoms) or Kronecker stages
+//                (MFMA tiles of sum_r C_r^T P B_r), and per-wave maxima of the
+//                stable dual scaling.
+//   k_upd        FP64 scalar block (dual points, gaps, delta, stable GAP radius,
+//                gap ratio, stop decision), per-atom stable GAP test, look-ahead
+//                count, FISTA step with soft thresholding, compaction of the
+//                preserved set and of the nonzeros (wavefront ballot + prefix).
 // No block communicates with another block of the same launch: every block
 // writes its partial results, and the consumers in the NEXT launch reduce them
 // in a fixed order (deterministic; the kernel boundary makes them visible
@@ -119,6 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         P->cnt_fwd[b] = ok ? P->nrc : 0;                 // slot 0
         P->cnt_fwd[P->batch + b] = 0;                    // slot 1
         P->cnt_adj[b] = 0;
+        P->cnt_adjk[b] = 0;
         P->cnt_upd[b] = 0;
         if (ok) atomicAdd(P->active_signals, 1);
         if (b == 0) {
@@ -374,6 +377,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     P->ctrl[2 * b + slot] = D;
                     P->ctrl[2 * b + prev] = D;   // other blocks read Cp here: done or not, they write nothing
                     P->cnt_adj[b] = 0;
+                    P->cnt_adjk[b] = 0;
                     P->cnt_upd[b] = 0;
                     P->cnt_fwd[(size_t)prev * batch + b] = 0;
                     atomicSub(P->active_signals, 1);
@@ -400,7 +404,10 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                         atomicMax(P->stat + 4 * slot, C.n_act);
                         atomicAdd(P->stat + 4 * slot + 1, C.n_act);
                         if (C.stage < P->n_stages - 1) atomicAdd(P->stat + 4 * slot + 2, 1);
-                        P->cnt_adj[b] = adj_items(P->st[C.stage], C.n_act, N);
+                        const StageDesc& stn = P->st[C.stage];
+                        const int items = adj_items(stn, C.n_act, N);
+                        P->cnt_adj[b] = stn.kind == kDense ? items : 0;
+                        P->cnt_adjk[b] = stn.kind == kKron ? items : 0;
                         P->cnt_upd[b] = max(1, (C.n_act + kSeg - 1) / kSeg);
                         if (Cp.advance && P->trace && Cp.iter < P->trace_cap) {
                             double* tr = P->trace + ((size_t)b * P->trace_cap + Cp.iter) * SL1_TRACE_FIELDS;
@@ -644,11 +651,12 @@ __device__ __forceinline__ void kron_tile_bf16(const StageDesc& st, int a0, int 
     }
 }
 
-// dense correlation item: NA atoms per wave (first = first list position)
-template <int NA>
-__device__ __forceinline__ void dense_item(const SolveParams* P, const StageDesc& st, int N, const int* act,
-                                           const int* s_pre, int nseg, int n_act, int first, const double* zs,
-                                           double rz, double* g, int lane, double (&mx)[3]) {
+// dense correlation item: NA atoms of one wave (first = first list position);
+// eps_j is fetched together with the columns
+template <int DT, int NA>
+__device__ __forceinline__ void dense_item(const StageDesc& st, int N, const int* act, const int* s_pre, int nseg,
+                                           int n_act, int first, const double* zs, double rz, double* g, int lane,
+                                           double (&mx)[3]) {
     int js[NA];
     int cnt = 0;
 #pragma unroll
@@ -661,20 +669,37 @@ __device__ __forceinline__ void dense_item(const SolveParams* P, const StageDesc
 #pragma unroll
     for (int q = 0; q < NA; ++q)
         if (js[q] < 0) js[q] = js[0];
+    double e[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) e[q] = st.eps[js[q]];
     double gv[NA];
-    dense_dots<NA>(st, N, js, zs, lane, gv);
+    dense_dots_t<DT, NA>(st, N, js, zs, lane, gv);
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             if (q < cnt) {
-                const int j = js[q];
-                g[j] = gv[q];
-                const double e = st.eps[j];
-                mx[0] = fmax(mx[0], fabs(gv[q]) + e * rz);
+                g[js[q]] = gv[q];
+                mx[0] = fmax(mx[0], fabs(gv[q]) + e[q] * rz);
                 mx[1] = fmax(mx[1], fabs(gv[q]));
-                mx[2] = fmax(mx[2], e);
+                mx[2] = fmax(mx[2], e[q]);
             }
         }
+    }
+}
+
+// per-wave maxima of one correlation item into its slot (lane 0 holds them
+// already for dense items; Kronecker items reduce over the wave first)
+__device__ __forceinline__ void put_wave_max(const SolveParams* P, int b, int item, double (&mx)[3], bool reduce) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (reduce) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) mx[k] = wave_max(mx[k]);
+    }
+    if (lane == 0) {
+        double* ap = P->adj_part + (((size_t)b * P->nadj_max + item) * 4 + w) * 3;
+        ap[0] = mx[0];
+        ap[1] = mx[1];
+        ap[2] = mx[2];
     }
 }
 
@@ -695,15 +720,24 @@ __device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double* 
 
 // ---------------------------------------------------------------------------
 // correlations over the preserved set: g_j = a~_j^T z for j in A_t, and the
-// per-item maxima of the stable dual scaling (Section III-C)
+// per-wave maxima of the stable dual scaling (Section III-C).  Dense stages and
+// Kronecker stages have kernels of their own (the dense one needs few registers
+// and runs at high occupancy; the Kronecker one holds MFMA tiles).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock, 3) void k_adj(const SolveParams* __restrict__ P, int slot) {
+template <int DT>
+__device__ __forceinline__ void dense_item_any(const StageDesc& st, int N, const int* act, const int* s_pre, int nseg,
+                                               int n_act, int first, const double* zs, double rz, double* g,
+                                               int lane, double (&mx)[3]) {
+    if (dense_apw(N) == 2) dense_item<DT, 2>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
+    else dense_item<DT, 1>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
+}
+
+__global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
-    const int N = P->N, K = P->K, batch = P->batch;
+    const int N = P->N, batch = P->batch;
     const size_t zbytes = ((size_t)N * 8 + 15) & ~(size_t)15;
     int* s_pre = (int*)(smem + zbytes);
     int* s_wpre = s_pre + (P->nseg_max + 1);
-    char* extra = smem + zbytes + ((((size_t)(P->nseg_max + 1) + batch + 1) * 4 + 15) & ~(size_t)15);
     __shared__ double s_red[48];
     __shared__ int s_tmp[16];
     const int total = build_work_map(P->cnt_adj, batch, s_wpre, s_tmp);
@@ -716,111 +750,136 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj(const SolveParams* __restrict
     for (int g = g0; g < g1; ++g) {
         const int b = uni(find_signal(s_wpre, batch, g));
         const int c = uni(g - s_wpre[b]);
-        const StageDesc* stp;
         if (b != cur_b) {
             cur_b = b;
             C = P->ctrl[2 * b + slot];
             double r2, zz, yz;
             reduce_res(P, b, s_red, r2, zz, yz);
             rz = sqrt(zz);
-            const StageDesc& st0 = P->st[C.stage];
-            const bool zf32 = st0.kind == kKron && st0.dtype != SL1_F64;
             const double* zg = P->z + (size_t)b * N;
-            if (zf32) {
+            double* zsd = (double*)smem;
+            for (int i = threadIdx.x * 2; i < N; i += kBlock * 2) *(f64v2*)(zsd + i) = *(const f64v2*)(zg + i);
+            const int* ap = actpre(P, b, C.par);
+            for (int s = threadIdx.x; s <= C.nseg_act; s += kBlock) s_pre[s] = ap[s];
+            __syncthreads();
+        }
+        const int stg = uni(C.stage), par = uni(C.par), nseg = uni(C.nseg_act), n_act = uni(C.n_act);
+        const StageDesc& st = P->st[stg];
+        const double* zs = (const double*)smem;
+        double* gvec = gbuf(P, b, par);
+        const int* act = actbuf(P, b, par);
+        const int first = (c * 4 + w) * dense_apw(N);
+        double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over the item
+        switch (st.dtype) {
+            case SL1_F64: dense_item_any<SL1_F64>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
+            case SL1_F32: dense_item_any<SL1_F32>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
+            case SL1_BF16: dense_item_any<SL1_BF16>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
+            default: dense_item_any<SL1_FP8_E4M3>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
+        }
+        put_wave_max(P, b, c, mx, false);
+    }
+}
+
+__global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __restrict__ P, int slot) {
+    extern __shared__ __align__(16) char smem[];
+    const int N = P->N, K = P->K, batch = P->batch;
+    const size_t zbytes = ((size_t)N * 8 + 15) & ~(size_t)15;
+    int* s_wpre = (int*)(smem + zbytes);
+    char* extra = smem + zbytes + ((((size_t)batch + 1) * 4 + 15) & ~(size_t)15);
+    __shared__ double s_red[48];
+    __shared__ int s_tmp[16];
+    const int total = build_work_map(P->cnt_adjk, batch, s_wpre, s_tmp);
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int cur_b = -1;
+    Control C;
+    double rz = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const int b = uni(find_signal(s_wpre, batch, g));
+        const int c = uni(g - s_wpre[b]);
+        if (b != cur_b) {
+            cur_b = b;
+            C = P->ctrl[2 * b + slot];
+            double r2, zz, yz;
+            reduce_res(P, b, s_red, r2, zz, yz);
+            rz = sqrt(zz);
+            const StageDesc& st0 = P->st[uni(C.stage)];
+            const double* zg = P->z + (size_t)b * N;
+            if (st0.dtype != SL1_F64) {
                 float* zsf = (float*)smem;
                 for (int i = threadIdx.x; i < N; i += kBlock) zsf[i] = (float)zg[i];
             } else {
                 double* zsd = (double*)smem;
                 for (int i = threadIdx.x * 2; i < N; i += kBlock * 2) *(f64v2*)(zsd + i) = *(const f64v2*)(zg + i);
             }
-            if (st0.kind == kDense) {
-                const int* ap = actpre(P, b, C.par);
-                for (int s = threadIdx.x; s <= C.nseg_act; s += kBlock) s_pre[s] = ap[s];
-            }
             __syncthreads();
         }
-        stp = &P->st[C.stage];
-        const StageDesc& st = *stp;
+        const StageDesc& st = P->st[uni(C.stage)];
         const double* zs = (const double*)smem;
-        double* gvec = gbuf(P, b, C.par);
-        double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over A_t
-
-        if (st.kind == kDense) {
-            const int apw = dense_apw(N);
-            const int* act = actbuf(P, b, C.par);
-            const int first = (c * 4 + w) * apw;
-            if (apw == 4) dense_item<4>(P, st, N, act, s_pre, C.nseg_act, C.n_act, first, zs, rz, gvec, lane, mx);
-            else if (apw == 2) dense_item<2>(P, st, N, act, s_pre, C.nseg_act, C.n_act, first, zs, rz, gvec, lane, mx);
-            else dense_item<1>(P, st, N, act, s_pre, C.nseg_act, C.n_act, first, zs, rz, gvec, lane, mx);
-        } else {
-            const int ntc = (st.k1 + kKronColTile - 1) / kKronColTile;
-            const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;
-            const int li = lane & 15, lk = lane >> 4;
-            const uint8_t* mask = P->mask + (size_t)b * K;
-            if (st.dtype == SL1_F64) {
-                double* Vall = (double*)extra;
-                double* red = Vall + 4 * 16 * P->n1_max;
-                f64x4 acc[4];
+        double* gvec = gbuf(P, b, uni(C.par));
+        double mx[3] = {0.0, 0.0, 0.0};
+        const int ntc = (st.k1 + kKronColTile - 1) / kKronColTile;
+        const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;
+        const int li = lane & 15, lk = lane >> 4;
+        const uint8_t* mask = P->mask + (size_t)b * K;
+        if (st.dtype == SL1_F64) {
+            double* Vall = (double*)extra;
+            double* red = Vall + 4 * 16 * P->n1_max;
+            f64x4 acc[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-                kron_tile_f64(st, a0, cb0, zs, Vall, acc);
+            for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+            kron_tile_f64(st, a0, cb0, zs, Vall, acc);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
-                __syncthreads();
-                for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
-                    const int i = o >> 6, col = o & 63;
-                    if (cb0 + col < st.k1) {
-                        const double s = ((red[(0 * 16 + i) * 64 + col] + red[(1 * 16 + i) * 64 + col]) +
-                                          red[(2 * 16 + i) * 64 + col]) + red[(3 * 16 + i) * 64 + col];
-                        const int j = (cb0 + col) * st.k2 + a0 + i;
-                        gvec[j] = s;
-                        if (mask[j]) {
-                            const double e = st.eps[j];
-                            mx[0] = fmax(mx[0], fabs(s) + e * rz);
-                            mx[1] = fmax(mx[1], fabs(s));
-                            mx[2] = fmax(mx[2], e);
-                        }
+                for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
+            __syncthreads();
+            for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
+                const int i = o >> 6, col = o & 63;
+                if (cb0 + col < st.k1) {
+                    const double s = ((red[(0 * 16 + i) * 64 + col] + red[(1 * 16 + i) * 64 + col]) +
+                                      red[(2 * 16 + i) * 64 + col]) + red[(3 * 16 + i) * 64 + col];
+                    const int j = (cb0 + col) * st.k2 + a0 + i;
+                    gvec[j] = s;
+                    if (mask[j]) {
+                        const double e = st.eps[j];
+                        mx[0] = fmax(mx[0], fabs(s) + e * rz);
+                        mx[1] = fmax(mx[1], fabs(s));
+                        mx[2] = fmax(mx[2], e);
                     }
                 }
-            } else {
-                float* red = (float*)extra;
-                char* vspace = extra + 4 * 16 * 64 * sizeof(float);
-                f32x4 acc[4];
+            }
+        } else {
+            float* red = (float*)extra;
+            char* vspace = extra + 4 * 16 * 64 * sizeof(float);
+            f32x4 acc[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-                if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)smem, (float*)vspace, acc);
-                else kron_tile_bf16(st, a0, cb0, (const float*)smem, (uint16_t*)vspace, acc);
+            for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)smem, (float*)vspace, acc);
+            else kron_tile_bf16(st, a0, cb0, (const float*)smem, (uint16_t*)vspace, acc);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
-                __syncthreads();
-                for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
-                    const int i = o >> 6, col = o & 63;
-                    if (cb0 + col < st.k1) {
-                        const double s = (((double)red[(0 * 16 + i) * 64 + col] + (double)red[(1 * 16 + i) * 64 + col]) +
-                                          (double)red[(2 * 16 + i) * 64 + col]) + (double)red[(3 * 16 + i) * 64 + col];
-                        const int j = (cb0 + col) * st.k2 + a0 + i;
-                        gvec[j] = s;
-                        if (mask[j]) {
-                            const double e = st.eps[j];
-                            mx[0] = fmax(mx[0], fabs(s) + e * rz);
-                            mx[1] = fmax(mx[1], fabs(s));
-                            mx[2] = fmax(mx[2], e);
-                        }
+                for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
+            __syncthreads();
+            for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
+                const int i = o >> 6, col = o & 63;
+                if (cb0 + col < st.k1) {
+                    const double s = (((double)red[(0 * 16 + i) * 64 + col] + (double)red[(1 * 16 + i) * 64 + col]) +
+                                      (double)red[(2 * 16 + i) * 64 + col]) + (double)red[(3 * 16 + i) * 64 + col];
+                    const int j = (cb0 + col) * st.k2 + a0 + i;
+                    gvec[j] = s;
+                    if (mask[j]) {
+                        const double e = st.eps[j];
+                        mx[0] = fmax(mx[0], fabs(s) + e * rz);
+                        mx[1] = fmax(mx[1], fabs(s));
+                        mx[2] = fmax(mx[2], e);
                     }
                 }
             }
         }
-        block_max<3>(mx, s_red);
-        if (threadIdx.x == 0) {
-            double* ap = P->adj_part + ((size_t)b * P->nadj_max + c) * 3;
-            ap[0] = mx[0];
-            ap[1] = mx[1];
-            ap[2] = mx[2];
-        }
+        put_wave_max(P, b, c, mx, true);
     }
 }
 
@@ -828,10 +887,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj(const SolveParams* __restrict
 // and correlation launches; computed identically by every block that needs it.
 __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scalars& S, double* s_red) {
     const StageDesc& st = P->st[C.stage];
-    const int nitems = adj_items(st, C.n_act, P->N);
+    const int nslots = 4 * adj_items(st, C.n_act, P->N);
     double mx[3] = {0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < nitems; k += blockDim.x) {
-        const double* ap = P->adj_part + ((size_t)b * P->nadj_max + k) * 3;
+    for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
+        const double* ap = P->adj_part + ((size_t)b * P->nadj_max * 4 + k) * 3;
         mx[0] = fmax(mx[0], ap[0]);
         mx[1] = fmax(mx[1], ap[1]);
         mx[2] = fmax(mx[2], ap[2]);
@@ -976,9 +1035,9 @@ __global__ void k_lambda_out(const SolveParams* __restrict__ P, double* out, int
     if (b >= P->batch) return;
     const Control& C = P->ctrl[2 * b];
     const StageDesc& st = P->st[0];
-    const int nitems = adj_items(st, C.n_act, P->N);
+    const int nslots = 4 * adj_items(st, C.n_act, P->N);
     double mp = 0.0;
-    for (int k = 0; k < nitems; ++k) mp = fmax(mp, P->adj_part[((size_t)b * P->nadj_max + k) * 3]);
+    for (int k = 0; k < nslots; ++k) mp = fmax(mp, P->adj_part[((size_t)b * P->nadj_max * 4 + k) * 3]);
     double r2 = 0.0, zz = 0.0, yz = 0.0;
     for (int k = 0; k < P->nrc; ++k) {
         const double* rp = P->res_part + ((size_t)b * P->nrc + k) * 3;
@@ -1071,7 +1130,10 @@ hipError_t launch_init(const SolveParams* dP, const LaunchCfg& c, hipStream_t s)
 
 hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
     if (which == 0) hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
-    else if (which == 1) hipLaunchKernelGGL(k_adj, dim3(c.g_adj), dim3(kBlock), c.lds_adj, s, dP, slot);
+    else if (which == 1) {
+        if (c.g_adj > 0) hipLaunchKernelGGL(k_adj_dense, dim3(c.g_adj), dim3(kBlock), c.lds_adj, s, dP, slot);
+        if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
+    }
     else hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
     return hipGetLastError();
 }
