@@ -308,7 +308,8 @@ int check_lds(const LaunchCfg& c) {
 //         the intermediate V), then y and the two lists when two workgroups per
 //         CU can still share the LDS;
 //   tail: every live signal on the last, dense, stage with at most max_act
-//         preserved atoms: z (FP64), y and both lists of max_act entries.
+//         preserved atoms: z (FP64), an 8 KB scratch, y and both lists of
+//         max_act entries.
 size_t wg_layout(SolveParams& p, bool tail, int max_act) {
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     const size_t lim = 160 * 1024 - 1024;       // static LDS of the kernel stays below 1 KB
@@ -323,7 +324,8 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act) {
     p.wo_zd = put(N * 8);
     if (tail) {
         const int cap = std::max(64, (max_act + 63) & ~63);
-        p.wo_zf = p.wo_fac = p.wo_scr = -1;
+        p.wo_zf = p.wo_fac = -1;
+        p.wo_scr = put(8192);                    // the dense forward's cross-group sums
         p.wo_y = put(N * 8);
         p.wg_cap_nz = p.wg_cap_act = cap;
         p.wo_lnj = put((size_t)cap * 4);
@@ -331,7 +333,7 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act) {
         p.wo_lact = put((size_t)cap * 4);
         return off <= lim ? off : 0;
     }
-    size_t fac = 0, scr = (size_t)kWgStage * 12;
+    size_t fac = 0, scr = 8192;                 // forward staging (6 KB) or cross-group sums (8 KB)
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
         if (s.kind != kKron) continue;

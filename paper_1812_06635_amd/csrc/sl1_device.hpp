@@ -254,9 +254,11 @@ __device__ __forceinline__ void raw_get(const Raw4<DT>& r, double (&v)[4]) {
 // NA atoms before the first product (loads past N are clamped to a valid
 // address and discarded).  Per lane the products are accumulated in increasing k.
 template <int DT, int NA>
+constexpr int dense_nk() { return (DT == SL1_F64 ? 4 : 8) / NA > 0 ? (DT == SL1_F64 ? 4 : 8) / NA : 1; }
+
+template <int DT, int NA, int NK = dense_nk<DT, NA>()>
 __device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const int (&js)[NA], const double* zs,
                                              int lane, double (&out)[NA]) {
-    constexpr int NK = (DT == SL1_F64 ? 4 : 8) / NA > 0 ? (DT == SL1_F64 ? 4 : 8) / NA : 1;
     double acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;

@@ -330,10 +330,15 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
     const int total = build_work_map(cnt_cur, batch, s_wpre, s_tmp);
     // a signal without work in this slot is finished: clear its count in the
     // other slot too, so no later forward launch visits it (the other slot is
-    // read only by the next forward launch; live signals have work here)
+    // read only by the next forward launch; live signals have work here), and
+    // mark this slot's control state done (no block of this launch reads it:
+    // blocks read the other slot, and only live signals' blocks write this one)
     if (blockIdx.x == 0) {
         for (int b = threadIdx.x; b < batch; b += blockDim.x)
-            if (s_wpre[b + 1] == s_wpre[b]) P->cnt_fwd[(size_t)prev * batch + b] = 0;
+            if (s_wpre[b + 1] == s_wpre[b]) {
+                P->cnt_fwd[(size_t)prev * batch + b] = 0;
+                P->ctrl[2 * b + slot].done = 1;
+            }
         // the other slot's statistics are gathered afresh by the next forward launch
         if (threadIdx.x == 0) {
             P->stat[4 * prev] = 0;
@@ -346,12 +351,18 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int cur_b = -1, finished = 0;
     Control C;
+    __shared__ Control s_cp;
     for (int g = g0; g < g1; ++g) {
         const int b = uni(find_signal(s_wpre, batch, g));
         const int item = uni(g - s_wpre[b]);
         if (b != cur_b) {
             cur_b = b;
-            const Control Cp = P->ctrl[2 * b + prev];
+            // C_{t-1} read once for the whole block, so that every thread takes
+            // the same path through the barriers below
+            __syncthreads();
+            if (threadIdx.x == 0) s_cp = P->ctrl[2 * b + prev];
+            __syncthreads();
+            const Control Cp = s_cp;
             if (Cp.done) {           // finished in an earlier launch: nothing to do
                 finished = 1;
                 continue;
@@ -371,11 +382,12 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     F.t0 = Cp.t0;
                     F.tconv = S.tconv;
                     P->fin[b] = F;
+                    // the other slot is read by this launch's other blocks of the
+                    // signal: it is marked done by the next forward launch
                     Control D = Cp;
                     D.done = 1;
                     D.advance = 0;
                     P->ctrl[2 * b + slot] = D;
-                    P->ctrl[2 * b + prev] = D;   // other blocks read Cp here: done or not, they write nothing
                     P->cnt_adj[b] = 0;
                     P->cnt_adjk[b] = 0;
                     P->cnt_upd[b] = 0;

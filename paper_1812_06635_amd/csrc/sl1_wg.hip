@@ -223,90 +223,105 @@ __device__ __forceinline__ void wg_kron_forward(const SolveParams* P, int b, con
     }
 }
 
-// two consecutive stored elements (rows 2q, 2q + 1) of a dense column, decoded
-// to float (exact; FP64 storage handled separately)
-__device__ __forceinline__ void dense2_f(int dtype, const void* A, size_t idx, float& a0, float& a1) {
+// four consecutive elements of a dense column in FP32/BF16/FP8 storage, decoded
+// to float (exact); FP64 storage is handled separately
+__device__ __forceinline__ f32v4 dense4_f(int dtype, const void* A, size_t idx) {
+    f32v4 r;
     if (dtype == SL1_F32) {
-        typedef float f32v2 __attribute__((ext_vector_type(2)));
-        const f32v2 v = *(const f32v2*)((const float*)A + idx);
-        a0 = v[0];
-        a1 = v[1];
+        r = *(const f32v4*)((const float*)A + idx);
     } else if (dtype == SL1_BF16) {
-        const uint32_t v = *(const uint32_t*)((const uint16_t*)A + idx);
-        a0 = bf16_to_f((uint16_t)(v & 0xFFFFu));
-        a1 = bf16_to_f((uint16_t)(v >> 16));
+        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
+        r = f32v4{bf16_to_f(a[0]), bf16_to_f(a[1]), bf16_to_f(a[2]), bf16_to_f(a[3])};
     } else {
-        const uint32_t v = *(const uint16_t*)((const uint8_t*)A + idx);
-        const auto f = __builtin_amdgcn_cvt_pk_f32_fp8((int)v, false);
-        a0 = f[0];
-        a1 = f[1];
+        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+        r = f32v4{lo[0], lo[1], hi[0], hi[1]};
     }
+    return r;
 }
 
-// u[row0], u[row0 + 1] over cnt nonzeros (lj, lx): G columns per step, every
-// load issued before the first product; same per-element arithmetic as the
-// grid forward kernel
+// u[row0 .. row0 + 3] over the nonzeros [k0, k1) of (lj, lx): G columns per
+// step, every load issued before the first product; same per-element arithmetic
+// as the grid forward kernel.  D64: FP64 storage; otherwise the storage type is
+// decoded per load.
 template <bool D64>
-__device__ __forceinline__ void wg_dense_rows(const StageDesc& st, int N, int row0, const int* lj, const double* lx,
-                                              int cnt, double& u0, double& u1) {
+__device__ __forceinline__ void wg_dense_quad(const StageDesc& st, int N, int row0, const int* lj, const double* lx,
+                                              int k0, int k1, double (&u)[4]) {
     constexpr int G = D64 ? 4 : 8;
     const int dt = st.dtype;
     const float* scale = (!D64 && dt != SL1_F32) ? st.scale : nullptr;
-    for (int k = 0; k < cnt; k += G) {
+    for (int k = k0; k < k1; k += G) {
         double xs[G];
         if constexpr (D64) {
-            f64v2 v[G];
+            Raw4<SL1_F64> r[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int kk = min(k + g, cnt - 1);
-                v[g] = *(const f64v2*)((const double*)st.A + (size_t)lj[kk] * N + row0);
-                xs[g] = k + g < cnt ? lx[kk] : 0.0;
+                const int kk = min(k + g, k1 - 1);
+                r[g] = raw_load<SL1_F64>(st.A, (size_t)lj[kk] * N + row0);
+                xs[g] = k + g < k1 ? lx[kk] : 0.0;
             }
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                if (k + g < cnt) {
-                    u0 += xs[g] * v[g][0];
-                    u1 += xs[g] * v[g][1];
+            for (int g = 0; g < G; ++g) {
+                if (k + g < k1) {
+                    double a[4];
+                    raw_get<SL1_F64>(r[g], a);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) u[v] += xs[g] * a[v];
                 }
+            }
         } else {
-            float a0[G], a1[G];
+            f32v4 r[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int kk = min(k + g, cnt - 1);
+                const int kk = min(k + g, k1 - 1);
                 const int j = lj[kk];
-                dense2_f(dt, st.A, (size_t)j * N + row0, a0[g], a1[g]);
-                xs[g] = k + g < cnt ? lx[kk] : 0.0;
+                r[g] = dense4_f(dt, st.A, (size_t)j * N + row0);
+                xs[g] = k + g < k1 ? lx[kk] : 0.0;
                 if (scale) xs[g] *= (double)scale[j];
             }
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                if (k + g < cnt) {
-                    u0 += xs[g] * (double)a0[g];
-                    u1 += xs[g] * (double)a1[g];
+            for (int g = 0; g < G; ++g) {
+                if (k + g < k1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) u[v] += xs[g] * (double)r[g][v];
                 }
+            }
         }
     }
 }
 
-// dense forward product, residual and sums: every thread owns row pairs
-// (2q, 2q + 1), q = tid + 512 c, over all nonzeros, so no cross-wave sum is
-// needed.  Nonzeros from the LDS list when it holds them, else staged from the
-// global list through the scratch.
+// dense forward product, residual and sums.  Rows go in quads: with N <= 2048
+// the Q = N/4 quads are spread over one thread each in S = 512 / 2^ceil(log2 Q)
+// groups, the groups split the nonzeros and their partials meet in a fixed tree
+// (at most 8 KB of LDS); with larger N one group takes the quads in chunks of
+// 512.  Nonzeros come from the LDS list when it holds them, else are staged
+// from the global list through the scratch.
 template <bool D64>
 __device__ __forceinline__ void wg_dense_forward(const SolveParams* P, int b, const StageDesc& st, const double* x,
                                                  const int* nzl, int n_nz, const int* lj, const double* lx,
                                                  bool in_lds, double* zd, float* zf, const double* yl, char* scr,
                                                  double* s_red, double* s_sum) {
     const int N = P->N, tid = threadIdx.x;
-    double* s_x = (double*)scr;
+    const int Q = N >> 2;
+    int qp = 1;
+    while (qp < Q) qp <<= 1;
+    const int S = Q <= kWgBlock ? kWgBlock / qp : 1;        // groups
+    const int T = kWgBlock / S;                             // threads per group
+    const int grp = tid / T, q0 = tid - grp * T;
+    double* red = (double*)scr;
+    double* s_x = (double*)scr;                             // staging (fallback), also in the scratch
     int* s_j = (int*)(scr + kWgStage * 8);
     double sums[3] = {0.0, 0.0, 0.0};
-    for (int c = 0; c * 2 * kWgBlock < N; ++c) {
-        const int row0 = 2 * (tid + kWgBlock * c);
-        const bool valid = row0 < N;
-        double u0 = 0.0, u1 = 0.0;
+    for (int c = 0; c * T < Q; ++c) {
+        const int q = q0 + c * T;
+        const bool valid = q < Q;
+        const int row0 = 4 * q;
+        double u[4] = {0.0, 0.0, 0.0, 0.0};
         if (in_lds) {
-            if (valid) wg_dense_rows<D64>(st, N, row0, lj, lx, n_nz, u0, u1);
+            const int per = (n_nz + S - 1) / S;
+            const int k0 = min(n_nz, grp * per), k1 = min(n_nz, k0 + per);
+            if (valid) wg_dense_quad<D64>(st, N, row0, lj, lx, k0, k1, u);
         } else {
             for (int base = 0; base < n_nz; base += kWgStage) {
                 const int cnt = min(kWgStage, n_nz - base);
@@ -316,16 +331,31 @@ __device__ __forceinline__ void wg_dense_forward(const SolveParams* P, int b, co
                     s_x[tid] = x[j];
                 }
                 __syncthreads();
-                if (valid) wg_dense_rows<D64>(st, N, row0, s_j, s_x, cnt, u0, u1);
+                const int per = (cnt + S - 1) / S;
+                const int k0 = min(cnt, grp * per), k1 = min(cnt, k0 + per);
+                if (valid) wg_dense_quad<D64>(st, N, row0, s_j, s_x, k0, k1, u);
                 __syncthreads();
             }
         }
-        if (valid) {
+        // fixed-order tree over the groups
+        for (int h = S >> 1; h >= 1; h >>= 1) {
+            if (grp >= h && grp < 2 * h && valid) {
 #pragma unroll
-            for (int v = 0; v < 2; ++v) {
+                for (int v = 0; v < 4; ++v) red[(size_t)(grp - h) * N + row0 + v] = u[v];
+            }
+            __syncthreads();
+            if (grp < h && valid) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) u[v] += red[(size_t)grp * N + row0 + v];
+            }
+            __syncthreads();
+        }
+        if (grp == 0 && valid) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
                 const int row = row0 + v;
                 const double yv = wg_y(P, b, yl, row);
-                const double rho = yv - (v ? u1 : u0);
+                const double rho = yv - u[v];
                 zd[row] = rho;
                 if (zf) zf[row] = (float)rho;
                 sums[0] += rho * rho;
@@ -474,7 +504,8 @@ __device__ void wg_kron_adj(const StageDesc& st, const char* fac, const double* 
 }
 
 // dense correlations over the preserved list (LDS or global): wave w takes NA
-// atoms at a time; eps_j is fetched together with the columns
+// atoms at a time (N <= 1024: 4 atoms, all 16 column loads in flight); eps_j is
+// fetched together with the columns
 template <int NA>
 __device__ void wg_dense_adj(const StageDesc& st, int N, const int* act, int n_act, const double* zd, double rz,
                              double* g, double (&mx)[3]) {
@@ -495,7 +526,12 @@ __device__ void wg_dense_adj(const StageDesc& st, int N, const int* act, int n_a
 #pragma unroll
         for (int q = 0; q < NA; ++q) e[q] = st.eps[js[q]];
         double gv[NA];
-        dense_dots<NA>(st, N, js, zd, lane, gv);
+        switch (st.dtype) {
+            case SL1_F64: dense_dots_t<SL1_F64, NA, (NA == 4 ? 2 : 4)>(st, N, js, zd, lane, gv); break;
+            case SL1_F32: dense_dots_t<SL1_F32, NA, 4>(st, N, js, zd, lane, gv); break;
+            case SL1_BF16: dense_dots_t<SL1_BF16, NA, 4>(st, N, js, zd, lane, gv); break;
+            default: dense_dots_t<SL1_FP8_E4M3, NA, 4>(st, N, js, zd, lane, gv); break;
+        }
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
@@ -586,8 +622,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const StageDesc& st = P->st[stage];
             // a layout without factor space serves dense stages only (the host
             // chooses it when every live signal is on the last, dense, stage)
-            const bool bad = st.kind == kKron ? (P->wo_fac < 0 || P->wo_scr < 0)
-                                              : (n_nz > P->wg_cap_nz && P->wo_scr < 0);
+            const bool bad = P->wo_scr < 0 || (st.kind == kKron && P->wo_fac < 0);
             if (bad) {
                 if (tid == 0) {
                     Final F;
@@ -670,10 +705,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             double* gvec = gbuf(P, b, par);
             double mx[3] = {0.0, 0.0, 0.0};
             if (st.kind == kDense) {
-                const int apw = dense_apw(N);
                 const int* act = uni(s_act_ok) ? (const int*)(smem + P->wo_lact) : actbuf(P, b, 0);
-                if (apw == 4) wg_dense_adj<4>(st, N, act, n_act, zd, rz, gvec, mx);
-                else if (apw == 2) wg_dense_adj<2>(st, N, act, n_act, zd, rz, gvec, mx);
+                if (N <= 1024) wg_dense_adj<4>(st, N, act, n_act, zd, rz, gvec, mx);
                 else wg_dense_adj<1>(st, N, act, n_act, zd, rz, gvec, mx);
             } else {
                 const char* fac = smem + P->wo_fac;

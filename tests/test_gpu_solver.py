@@ -296,6 +296,33 @@ def test_hybrid_hand_over_matches_grid(sl1):
         _check_solution(p, h, b)
 
 
+def test_identical_signals_finishing_together(sl1):
+    # 256 copies of one signal on the batched dictionary: the forward launch then
+    # gives each block two of a signal's four row items, and every copy stops in
+    # the same launch (control state of a finishing signal vs. its other blocks)
+    _say("256 identical signals, grid engine")
+    import torch
+    p = synth.config4(batch=512)
+    sig = 203
+    ups = [sl1.upload_stage(s) for s in p.stages]
+    Ls, rc = [s.L for s in p.stages], [0.037, 0.037, 0.040, 1.0]
+    an = _t(p.atom_norm)
+    one = sl1.solve(ups, Ls, rc, an, _t(p.Y[sig:sig + 1], torch.float32), _t(p.lam[sig:sig + 1]), tol=1e-7,
+                    engine="grid")
+    many = sl1.solve(ups, Ls, rc, an, _t(np.tile(p.Y[sig], (256, 1)), torch.float32),
+                     _t(np.tile(p.lam[sig], 256)), tol=1e-7, engine="grid")
+    torch.cuda.synchronize()
+    x1 = one["x"].cpu().numpy()[0]
+    X = many["x"].cpu().numpy()
+    assert one["status"] == 0 and many["status"] == 0
+    assert np.all(many["iters"].cpu().numpy() == int(one["iters"][0]))
+    for b in range(256):
+        rel = np.linalg.norm(X[b] - x1) / np.linalg.norm(x1)
+        assert rel <= 1e-9, f"copy {b} differs from the single solve by {rel:.2e}"
+    sol = ol.solve(p.A, p.Y[sig], float(p.lam[sig]), L=p.stages[-1].L)
+    assert np.linalg.norm(x1 - sol["x"]) <= 1e-4 * np.linalg.norm(sol["x"])
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 def test_exact_only_sequence_is_gap_safe(sl1, engine):
     # one stage (the exact A): the stable test is GAP Safe, gamma = 1
