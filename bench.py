@@ -70,30 +70,73 @@ def timed(torch, fn, steps, warmup):
     return a.elapsed_time(b) / steps, out
 
 
-def adj_work(p, trace, iters):
-    """Algorithmic work of the correlation kernel over one solve, from the trace:
-    dense stage: N * bytes/element * |A_t| (+ 4 B per scaled atom);
-    Kronecker stage: 2 R k2 n1 (n2 + k1) flops (sum_r C_r^T P B_r)."""
+UPD_BYTES_PER_ATOM = 76.0   # test/update per preserved atom: index, 7 FP64 gathers, x and index writes
+
+
+def kernel_work(p, trace, iters, t_split):
+    """Algorithmic work of each kernel over one solve, from the trace (rows
+    t < t_split ran in the grid kernels, the rest in the whole-solve kernel):
+      dense correlations  |A_t| N b bytes (b: bytes per stored element, + 4 B per
+                          column scale); Kronecker correlations 2 R k2 n1 (n2 + k1)
+                          flops (sum_r C_r^T P B_r);
+      forward             ||x_t||_0 N b bytes on dense stages (gathered columns);
+      update              76 B per preserved atom."""
     import numpy as np
     N = p.N
-    byts, flops, dense_it, kron_it = 0.0, 0.0, 0, 0
+    w = dict(fwd_bytes=[0.0, 0.0], adj_bytes=[0.0, 0.0], adj_flops=[0.0, 0.0], upd_bytes=[0.0, 0.0],
+             dense_it=[0, 0], kron_it=[0, 0])
     for b in range(trace.shape[0]):
         n = int(iters[b])
         rows = trace[b, :n]
+        part = (np.arange(n) >= t_split).astype(int)
         for s_idx, st in enumerate(p.stages):
-            m = rows[:, 1] == s_idx
-            cnt = int(m.sum())
-            if not cnt:
-                continue
-            if st.kind == "dense":
-                bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
-                byts += N * bpe * float(rows[m, 2].sum())
-                dense_it += cnt
-            else:
-                n1, k1, n2, k2 = st.dims
-                flops += cnt * 2.0 * st.R * k2 * n1 * (n2 + k1)
-                kron_it += cnt
-    return byts, flops, dense_it, kron_it
+            for ph in (0, 1):
+                m = (rows[:, 1] == s_idx) & (part == ph)
+                cnt = int(m.sum())
+                if not cnt:
+                    continue
+                w["upd_bytes"][ph] += UPD_BYTES_PER_ATOM * float(rows[m, 2].sum())
+                if st.kind == "dense":
+                    bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
+                    w["adj_bytes"][ph] += N * bpe * float(rows[m, 2].sum())
+                    w["fwd_bytes"][ph] += N * bpe * float(rows[m, 12].sum())
+                    w["dense_it"][ph] += cnt
+                else:
+                    n1, k1, n2, k2 = st.dims
+                    w["adj_flops"][ph] += cnt * 2.0 * st.R * k2 * n1 * (n2 + k1)
+                    w["kron_it"][ph] += cnt
+    return w
+
+
+def roofline_entries(prof, phases, work):
+    """Roofline of every kernel of the solve: achieved = algorithmic work /
+    measured time (HIP events around each launch), against the MI355X peak of
+    its bound."""
+    out = []
+
+    def add(name, ms, launches, amount, unit_kind):
+        if ms <= 0 or launches <= 0:
+            return
+        if unit_kind == "hbm":
+            ach = amount / (ms * 1e-3) / 1e9
+            out.append(dict(kernel=name, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=ach / HBM_PEAK_GBS, traffic=None, launches=launches, total_ms=ms,
+                            avg_launch_us=ms * 1e3 / launches))
+        else:
+            ach = amount / (ms * 1e-3) / 1e12
+            out.append(dict(kernel=name, bound="mfma", achieved=ach, peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=ach / BF16_PEAK_TFLOPS, traffic=None, launches=launches, total_ms=ms,
+                            avg_launch_us=ms * 1e3 / launches))
+
+    add("k_fwd", *prof["fwd"], work["fwd_bytes"][0], "hbm")
+    add("k_adj_dense", *prof["adj_dense"], work["adj_bytes"][0], "hbm")
+    add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma")
+    add("k_upd", *prof["upd"], work["upd_bytes"][0], "hbm")
+    if phases.get("wg_launches", 0) > 0:
+        add("k_solve_wg", phases["wg_ms"], phases["wg_launches"],
+            work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1], "hbm")
+    out.sort(key=lambda e: -e["total_ms"])
+    return out
 
 
 def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
@@ -111,44 +154,40 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
         return sl1.solve([st[-1]], [L[-1]], [1.0], an, Y, lam, tol=tol)
 
     ms_m, out_m = timed(torch, method, steps, warmup)
+    engine = sl1.last_solve_phases(p.batch, p.N, p.K)[0]
     clk = sl1.last_solve_clock(p.batch, p.N, p.K)
     ttg_dev = float(np.max(clk[:, 1] - clk[:, 0])) * 1e3
     ms_p, out_p = timed(torch, plain, steps, warmup)
+    engine_p = sl1.last_solve_phases(p.batch, p.N, p.K)[0]
     it_m = int(out_m["iters"].sum().item())
     it_p = int(out_p["iters"].sum().item())
     gap_m = out_m["gap"].cpu().numpy()
     gap_p = out_p["gap"].cpu().numpy()
-    log(f"{label}: method {ms_m:.3f} ms ({it_m} iters), plain {ms_p:.3f} ms ({it_p} iters)")
-    # profiled run (not timed): per-kernel device time and the trace for algorithmic work
+    log(f"{label}: method {ms_m:.3f} ms ({it_m} iters, {engine}), plain {ms_p:.3f} ms ({it_p} iters, {engine_p})")
+    # profiled run (not timed): every kernel launched directly between HIP
+    # events on the library's stream, and the trace for the algorithmic work
     cap = int(out_m["iters"].max().item()) + 8
     outp = sl1.solve(st, L, rc, an, Y, lam, tol=tol, profile=True, trace_cap=cap)
     prof = sl1.last_solve_profile(p.batch, p.N, p.K)
+    _, phases = sl1.last_solve_phases(p.batch, p.N, p.K)
     trace = outp["trace"].cpu().numpy()
     iters = outp["iters"].cpu().numpy()
-    byts, flops, dense_it, kron_it = adj_work(p, trace, iters)
+    t_split = prof["fwd"][1] if phases.get("wg_launches", 0) > 0 else 10 ** 9
+    work = kernel_work(p, trace, iters, t_split)
     res = dict(
-        ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p,
+        ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p, engine=engine, engine_plain=engine_p,
         time_to_gap_ms_device=ttg_dev, max_gap_method=float(gap_m.max()), max_gap_plain=float(gap_p.max()),
         stage_final=sorted(set(out_m["stage"].cpu().numpy().tolist())), rc_measured=rc_meas,
-        rc_model=[s.rc_theory for s in p.stages], kernel_ms=prof,
-        adj_alg_bytes=byts, adj_alg_flops=flops, adj_dense_signal_iters=dense_it, adj_kron_signal_iters=kron_it,
+        rc_model=[s.rc_theory for s in p.stages], kernel_ms=prof, wg_phases=phases, grid_iterations=t_split,
+        roofline_kernels=roofline_entries(prof, phases, work),
         x=out_m["x"].cpu().numpy(), screened=out_m["screened"].cpu().numpy(),
     )
     return res
 
 
 def roofline(res):
-    ms_adj, n_adj = res["kernel_ms"]["adj"]
-    t = ms_adj * 1e-3
-    if res["adj_dense_signal_iters"] >= res["adj_kron_signal_iters"]:
-        ach = res["adj_alg_bytes"] / t / 1e9
-        return dict(kernel="k_adj (correlations + scalar block)", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None, launches=n_adj,
-                    avg_launch_us=ms_adj * 1e3 / max(n_adj, 1))
-    ach = res["adj_alg_flops"] / t / 1e12
-    return dict(kernel="k_adj (correlations + scalar block)", bound="mfma", achieved=ach, peak=BF16_PEAK_TFLOPS,
-                unit="TFLOP/s", frac=ach / BF16_PEAK_TFLOPS, traffic=None, launches=n_adj,
-                avg_launch_us=ms_adj * 1e3 / max(n_adj, 1))
+    """The kernel with the largest share of the solve's device time."""
+    return dict(res["roofline_kernels"][0])
 
 
 def parity_sample(np, p, res, n=2):
@@ -244,8 +283,11 @@ def main():
         "max_gap": res["max_gap_method"],
         "rc_measured": res["rc_measured"],
         "rc_model": res["rc_model"],
+        "engine": res["engine"],
         "kernel_ms": res["kernel_ms"],
+        "whole_solve_phases_ms": res["wg_phases"],
         "roofline": roofline(res),
+        "roofline_kernels": res["roofline_kernels"],
     }
     if not args.no_parity:
         log("sampled parity against the FP64 oracle")
@@ -264,7 +306,9 @@ def main():
             "iters_per_s": r2["iters_method"] / (r2["ms_method"] * 1e-3),
             "plain_fp32_time_to_gap_ms": r2["ms_plain"], "plain_fp32_iters": r2["iters_plain"],
             "speedup_vs_plain_fp32": r2["ms_plain"] / r2["ms_method"],
-            "rc_measured": r2["rc_measured"], "kernel_ms": r2["kernel_ms"], "roofline": roofline(r2),
+            "rc_measured": r2["rc_measured"], "engine": r2["engine"], "kernel_ms": r2["kernel_ms"],
+            "whole_solve_phases_ms": r2["wg_phases"], "roofline": roofline(r2),
+            "roofline_kernels": r2["roofline_kernels"],
             "max_gap": r2["max_gap_method"],
         }
     print(json.dumps(line))

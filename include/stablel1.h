@@ -40,7 +40,7 @@ extern "C" {
 #endif
 
 #define SL1_MAX_STAGES 8
-#define SL1_TRACE_FIELDS 12
+#define SL1_TRACE_FIELDS 13
 
 enum sl1_status_code {
     SL1_OK = 0,
@@ -118,7 +118,7 @@ typedef struct {
     int32_t flags;       /* [0] SL1_FLAG_* */
     double* trace;       /* [NULL] optional device buffer, batch x trace_cap x SL1_TRACE_FIELDS
                             doubles: per iteration t, stage, |A_t|, |A_t+1|, K_t, G(x,theta'|A~),
-                            G(x,theta~|A~), delta, R', gamma, ||x_t||_1, P(x_t|A~) */
+                            G(x,theta~|A~), delta, R', gamma, ||x_t||_1, P(x_t|A~), ||x_t||_0 */
     int32_t trace_cap;   /* [0] rows per signal in `trace` */
     int32_t reserved;
 } sl1_opts;
@@ -235,10 +235,11 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
 int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, double* rate_khz);
 
 /*
- * sl1_last_solve_profile -- per-kernel device time of the most recent
- * sl1_solve with SL1_FLAG_PROFILE and these shapes: ms[k] total milliseconds and
- * launches[k] launch count of k = 0 forward/residual, 1 correlations + scalar
- * block, 2 test/update/compaction (host arrays of 3).
+ * sl1_last_solve_profile -- per-kernel device time of the grid kernels in the
+ * most recent sl1_solve with SL1_FLAG_PROFILE and these shapes: ms[k] total
+ * milliseconds and launches[k] launch count of k = 0 forward/residual, 1 dense
+ * correlations, 2 Kronecker correlations, 3 scalar block + test/update/compaction
+ * (host arrays of 4).
  */
 int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
 

@@ -13,7 +13,7 @@ from .build import lib_path
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 OK, MAXITER, EINVAL, ESHAPE, EDTYPE, EHIP, ENOMEM, ESINGULAR, ELIMIT = 0, 1, -1, -2, -3, -4, -5, -6, -7
 MAX_STAGES = 8
-TRACE_FIELDS = 12
+TRACE_FIELDS = 13
 FLAG_NO_GRAPH = 1
 FLAG_PROFILE = 2
 FLAG_ENGINE_GRID = 4

@@ -210,12 +210,13 @@ def last_solve_clock(batch, N, K):
 
 
 def last_solve_profile(batch, N, K):
-    """{kernel: (total ms, launches)} of the last solve run with profile=True."""
-    ms = (L.c_d * 3)()
-    n = (ctypes.c_longlong * 3)()
+    """{kernel: (total ms, launches)} of the grid kernels in the last solve run
+    with profile=True."""
+    ms = (L.c_d * 4)()
+    n = (ctypes.c_longlong * 4)()
     L.check(L.load().sl1_last_solve_profile(batch, N, K, ms, n), "sl1_last_solve_profile")
-    names = ("fwd", "adj", "upd")
-    return {names[k]: (ms[k], n[k]) for k in range(3)}
+    names = ("fwd", "adj_dense", "adj_kron", "upd")
+    return {names[k]: (ms[k], n[k]) for k in range(4)}
 
 
 def last_solve_phases(batch, N, K):

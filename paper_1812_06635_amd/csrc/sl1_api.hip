@@ -102,8 +102,8 @@ struct Workspace {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
-    double prof_ms[3] = {0, 0, 0};
-    long long prof_n[3] = {0, 0, 0};
+    double prof_ms[4] = {0, 0, 0, 0};       // grid kernels: forward, dense / Kronecker correlations, update
+    long long prof_n[4] = {0, 0, 0, 0};
     long long* d_wgprof = nullptr;          // [batch][kWgPhases] phase clocks of the whole-solve engine
     double phase_ms[kWgPhases] = {0, 0, 0, 0};
     double wg_ms = 0.0;                     // whole-solve launches of the last profiled solve
@@ -765,7 +765,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 48, w->stream));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
     if (prof) {
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             w->prof_ms[k] = 0.0;
             w->prof_n[k] = 0;
         }
@@ -815,7 +815,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     const long long cap = (long long)o.max_iter + 2LL * chunk + 4;
     if (prof) {
         // one event before and after every kernel of a chunk
-        while ((int)w->prof_ev.size() < 6 * chunk) {
+        while ((int)w->prof_ev.size() < 8 * chunk) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             w->prof_ev.push_back(e);
@@ -824,10 +824,10 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     for (;;) {
         if (prof) {
             for (int it = 0; it < chunk; ++it)
-                for (int k = 0; k < 3; ++k) {
-                    HIP_TRY(hipEventRecord(w->prof_ev[6 * it + 2 * k], w->stream));
+                for (int k = 0; k < 4; ++k) {
+                    HIP_TRY(hipEventRecord(w->prof_ev[8 * it + 2 * k], w->stream));
                     HIP_TRY(launch_one(k, it & 1, w->dP, cfg, w->stream));
-                    HIP_TRY(hipEventRecord(w->prof_ev[6 * it + 2 * k + 1], w->stream));
+                    HIP_TRY(hipEventRecord(w->prof_ev[8 * it + 2 * k + 1], w->stream));
                 }
         } else if (use_graph) {
             HIP_TRY(hipGraphLaunch(w->graph, w->stream));
@@ -837,10 +837,12 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         launched += chunk;
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
+            const bool run[4] = {true, cfg.g_adj > 0, cfg.g_adjk > 0, true};
             for (int it = 0; it < chunk; ++it)
-                for (int k = 0; k < 3; ++k) {
+                for (int k = 0; k < 4; ++k) {
+                    if (!run[k]) continue;
                     float ms = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&ms, w->prof_ev[6 * it + 2 * k], w->prof_ev[6 * it + 2 * k + 1]));
+                    HIP_TRY(hipEventElapsedTime(&ms, w->prof_ev[8 * it + 2 * k], w->prof_ev[8 * it + 2 * k + 1]));
                     w->prof_ms[k] += ms;
                     w->prof_n[k] += 1;
                 }
@@ -1038,7 +1040,7 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
     if (it == g_ws.end()) return SL1_EINVAL;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ms[k] = it->second->prof_ms[k];
         launches[k] = it->second->prof_n[k];
     }

@@ -426,7 +426,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                             tr[0] = Cp.iter; tr[1] = Cp.stage; tr[2] = Cp.n_act; tr[3] = C.n_act;
                             tr[4] = kt;
                             tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = S.Rp; tr[9] = S.gamma;
-                            tr[10] = Cp.l1; tr[11] = S.P;
+                            tr[10] = Cp.l1; tr[11] = S.P; tr[12] = Cp.n_nz;
                         }
                     }
                 }
@@ -1140,31 +1140,39 @@ hipError_t launch_init(const SolveParams* dP, const LaunchCfg& c, hipStream_t s)
     return hipGetLastError();
 }
 
+// kernels of one iteration: 0 forward, 1 dense correlations, 2 Kronecker
+// correlations, 3 test/update; a correlation kernel with an empty grid (its
+// stage kind is absent) is skipped
 hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    if (which == 0) hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
-    else if (which == 1) {
-        if (c.g_adj > 0) hipLaunchKernelGGL(k_adj_dense, dim3(c.g_adj), dim3(kBlock), c.lds_adj, s, dP, slot);
-        if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
+    switch (which) {
+        case 0: hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot); break;
+        case 1:
+            if (c.g_adj > 0) hipLaunchKernelGGL(k_adj_dense, dim3(c.g_adj), dim3(kBlock), c.lds_adj, s, dP, slot);
+            break;
+        case 2:
+            if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
+            break;
+        default: hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot); break;
     }
-    else hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
     return hipGetLastError();
 }
 
 hipError_t launch_iter(int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         hipError_t e = launch_one(k, slot, dP, c, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_fwd_adj(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    hipError_t e = launch_one(0, 0, dP, c, s);
-    return e != hipSuccess ? e : launch_one(1, 0, dP, c, s);
+hipError_t launch_adj_only(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    hipError_t e = launch_one(1, 0, dP, c, s);
+    return e != hipSuccess ? e : launch_one(2, 0, dP, c, s);
 }
 
-hipError_t launch_adj_only(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    return launch_one(1, 0, dP, c, s);
+hipError_t launch_fwd_adj(const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
+    hipError_t e = launch_one(0, 0, dP, c, s);
+    return e != hipSuccess ? e : launch_adj_only(dP, c, s);
 }
 
 hipError_t launch_finalize(const SolveParams* dP, const LaunchCfg& c, double* x, double* gap, double* gap_cert,

@@ -855,7 +855,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                 tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
                 tr[4] = kt;
                 tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = sS.Rp; tr[9] = sS.gamma;
-                tr[10] = C.l1; tr[11] = sS.P;
+                tr[10] = C.l1; tr[11] = sS.P; tr[12] = C.n_nz;
             }
             const int i_new = switch_dictionary(C.stage, P->n_stages - 1, sS.gamma, P->Gamma, kt, st.rc, (double)P->K);
             if (i_new != C.stage) {
