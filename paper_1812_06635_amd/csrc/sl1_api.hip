@@ -148,6 +148,7 @@ int make_workspace(Workspace& w) {
     const size_t o_mask = take(B * K);
     const size_t o_act = take(B * 2 * K * 4);
     const size_t o_nz = take(B * 2 * K * 4);
+    const size_t o_nzx = take(B * 2 * K * 8);
     const size_t o_ap = take(B * 2 * np * 4);
     const size_t o_zp = take(B * 2 * np * 4);
     const size_t o_z = take(B * N * ws);
@@ -174,6 +175,7 @@ int make_workspace(Workspace& w) {
     p.mask = (uint8_t*)(m + o_mask);
     p.act = (int*)(m + o_act);
     p.nz = (int*)(m + o_nz);
+    p.nzx = (double*)(m + o_nzx);
     p.act_pre = (int*)(m + o_ap);
     p.nz_pre = (int*)(m + o_zp);
     p.z = (double*)(m + o_z);
@@ -260,7 +262,7 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     c.nadj_max = w.nadj_max;
     const size_t ws = 8;
     const size_t nseg1 = (size_t)w.nseg_max + 1, nb1 = (size_t)w.batch + 1;
-    c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + kFwdWaves * kFwdRows * 8;
+    c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + 4 * 256 * 8;
     c.lds_upd = 4 * (nseg1 + nb1);
     // persistent grids: enough blocks to fill the chip, never more than the work;
     // a correlation kernel whose stage kind is absent is not launched

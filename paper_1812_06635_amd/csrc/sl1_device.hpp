@@ -45,6 +45,9 @@ __device__ __forceinline__ int* actbuf(const SolveParams* P, int b, int par) {
 __device__ __forceinline__ int* nzbuf(const SolveParams* P, int b, int par) {
     return P->nz + ((size_t)b * 2 + par) * P->K;
 }
+__device__ __forceinline__ double* nzxbuf(const SolveParams* P, int b, int par) {
+    return P->nzx + ((size_t)b * 2 + par) * P->K;
+}
 __device__ __forceinline__ int* actpre(const SolveParams* P, int b, int par) {
     return P->act_pre + ((size_t)b * 2 + par) * (P->nseg_max + 1);
 }

@@ -11,7 +11,7 @@ namespace sl1 {
 constexpr int kBlock = 256;         // threads per block (4 waves)
 constexpr int kWave = 64;
 constexpr int kSeg = 256;           // atoms per segment of a compacted list (one update block)
-constexpr int kFwdRows = 256;       // rows per forward block (4 per lane)
+constexpr int kFwdRows = 1024;      // rows per forward item: 4 sub-chunks of 256 (4 per lane), 2 waves each
 constexpr int kFwdBlock = 512;      // forward block: 8 waves share the nonzeros of x
 constexpr int kFwdWaves = kFwdBlock / 64;
 constexpr int kMaxSeg = 1024;       // segments of a compacted list (K <= 262144)
@@ -89,6 +89,7 @@ struct SolveParams {
     uint8_t* mask;            // [batch][K]
     int* act;                 // [batch][2][K]
     int* nz;                  // [batch][2][K]
+    double* nzx;              // [batch][2][K] values of the nonzero list (same positions)
     int* act_pre;             // [batch][2][nseg_max+1]
     int* nz_pre;              // [batch][2][nseg_max+1]
     double* z;                // [batch][N]
@@ -152,9 +153,13 @@ __device__ __forceinline__ int seg_find(const int* pre, int nseg, int i) {
     return lo;
 }
 
+__device__ __forceinline__ int list_pos(const int* pre, int nseg, int i) {
+    const int s = seg_find(pre, nseg, i);
+    return s * kSeg + (i - pre[s]);
+}
+
 __device__ __forceinline__ int list_get(const int* idx, const int* pre, int nseg, int i) {
-    int s = seg_find(pre, nseg, i);
-    return idx[s * kSeg + (i - pre[s])];
+    return idx[list_pos(pre, nseg, i)];
 }
 
 }  // namespace sl1

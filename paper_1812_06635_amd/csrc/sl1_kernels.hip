@@ -309,8 +309,10 @@ __device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, int r0, con
 
 // ---------------------------------------------------------------------------
 // forward product and residual (Section III-C: rho~_t = y - A~ x_t)
-// items: row chunks of 256 rows; the 8 waves of a block share the nonzeros of
-// x_t for the same rows and reduce in LDS.
+// items: row chunks of 1024 rows; wave pair (2s, 2s + 1) covers rows
+// 256 s .. 256 s + 255 of the chunk (4 per lane) and splits the nonzeros of x_t
+// (staged once per item with their values); the odd wave's partial meets the
+// even wave's in LDS.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
     int* s_j = s_zpre + nseg1;
     int* s_wpre = s_j + kFwdBlock;                      // work map (batch + 1)
     double* s_x = (double*)(((uintptr_t)(s_wpre + batch + 1) + 15) & ~(uintptr_t)15);
-    double* s_u = s_x + kFwdBlock;                      // [kFwdWaves][256 rows]
+    double* s_u = s_x + kFwdBlock;                      // [4 sub-chunks][256 rows]: odd waves' partials
     __shared__ double s_red[48];
     __shared__ int s_tmp[16];
 
@@ -437,26 +439,36 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
         const int stg = uni(C.stage), par = uni(C.par), nnz = uni(C.n_nz), nseg_nz = uni(C.nseg_nz);
         const StageDesc& st = P->st[stg];
         const bool kron = st.kind == kKron;
-        const int r0 = item * kFwdRows + lane * 4;
+        // wave w: 256-row sub-chunk w / 2 of this 1024-row item, half w % 2 of the nonzeros
+        const int sub = w >> 1, half = w & 1;
+        const int r0 = item * kFwdRows + sub * 256 + lane * 4;
+        const bool rows_ok = r0 < N;
+        // y of the rows this lane finishes, fetched before the gather
+        double yv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (half == 0 && rows_ok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) yv[v] = yval(P, b, r0 + v);
+        }
         const int* nzi = nzbuf(P, b, par);
-        const double* x = xbuf(P, b, par);
+        const double* nzx = nzxbuf(P, b, par);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int base = 0; base < nnz; base += kFwdBlock) {
             const int cnt = min(kFwdBlock, nnz - base);
             if ((int)threadIdx.x < cnt) {
-                const int j = list_get(nzi, s_zpre, nseg_nz, base + threadIdx.x);
+                const int pos = list_pos(s_zpre, nseg_nz, base + threadIdx.x);
+                const int j = nzi[pos];
                 if (kron) {
                     const int j1 = j / st.k2;
                     s_j[threadIdx.x] = (j1 << 16) | (j - j1 * st.k2);
                 } else {
                     s_j[threadIdx.x] = j;
                 }
-                s_x[threadIdx.x] = x[j];
+                s_x[threadIdx.x] = nzx[pos];
             }
             __syncthreads();
-            const int pw = (cnt + kFwdWaves - 1) / kFwdWaves;
-            const int k0 = min(cnt, w * pw), k1 = min(cnt, k0 + pw);
-            if (r0 < N && k0 < k1) {
+            const int ph = (cnt + 1) >> 1;
+            const int k0 = half ? ph : 0, k1 = half ? cnt : ph;
+            if (rows_ok && k0 < k1) {
                 switch (st.kind * 4 + st.dtype) {
                     case kDense * 4 + SL1_F64: fwd_dense_gather<SL1_F64>(st, N, r0, s_j, s_x, k0, k1, acc); break;
                     case kDense * 4 + SL1_F32: fwd_dense_gather<SL1_F32>(st, N, r0, s_j, s_x, k0, k1, acc); break;
@@ -469,26 +481,28 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
             }
             __syncthreads();
         }
+        if (half == 1) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) s_u[w * kFwdRows + lane * 4 + v] = acc[v];
+            for (int v = 0; v < 4; ++v) s_u[sub * 256 + lane * 4 + v] = acc[v];
+        }
         __syncthreads();
         // rho = y - u and the stored direction z (rho itself, or its FP32 / BF16
         // rounding when the stage's matrix-core product takes that input type)
         const int zround = (st.kind == kKron && st.dtype == SL1_BF16) ? 2 : ((st.kind == kKron && st.dtype == SL1_F32) ? 1 : 0);
         double sums[3] = {0.0, 0.0, 0.0};
-        const int row = item * kFwdRows + threadIdx.x;
-        if (threadIdx.x < kFwdRows && row < N) {
-            double u = 0.0;
-            for (int q = 0; q < kFwdWaves; ++q) u += s_u[q * kFwdRows + threadIdx.x];
-            const double yv = yval(P, b, row);
-            const double rho = yv - u;
-            double zd = rho;
-            if (zround == 1) zd = (double)(float)rho;
-            else if (zround == 2) zd = (double)bf16_rne((float)rho);
-            P->z[(size_t)b * N + row] = zd;
-            sums[0] = rho * rho;
-            sums[1] = zd * zd;
-            sums[2] = yv * zd;
+        if (half == 0 && rows_ok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double u = acc[v] + s_u[sub * 256 + lane * 4 + v];
+                const double rho = yv[v] - u;
+                double zd = rho;
+                if (zround == 1) zd = (double)(float)rho;
+                else if (zround == 2) zd = (double)bf16_rne((float)rho);
+                P->z[(size_t)b * N + r0 + v] = zd;
+                sums[0] += rho * rho;
+                sums[1] += zd * zd;
+                sums[2] += yv[v] * zd;
+            }
         }
         block_sum<3>(sums, s_red);
         if (threadIdx.x == 0) {
@@ -969,7 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
         const bool valid = i < n_act;
         int j = 0;
         bool keep = false, nzf = false;
-        double kt = 0.0, l1 = 0.0;
+        double kt = 0.0, l1 = 0.0, xnv = 0.0;
         if (valid) {
             j = list_get(actbuf(P, b, par), s_pre, C.nseg_act, i);
             double* xc = xbuf(P, b, par);
@@ -1001,12 +1015,16 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             }
             nzf = keep && (xn != 0.0);
             l1 = fabs(xn);
+            xnv = xn;
         }
         int tot_keep, tot_nz;
         const int pk = block_excl_scan_flag(keep, s_w, tot_keep);
         if (keep) actbuf(P, b, 1 - par)[c * kSeg + pk] = j;
         const int pz = block_excl_scan_flag(nzf, s_w, tot_nz);
-        if (nzf) nzbuf(P, b, 1 - par)[c * kSeg + pz] = j;
+        if (nzf) {
+            nzbuf(P, b, 1 - par)[c * kSeg + pz] = j;
+            nzxbuf(P, b, 1 - par)[c * kSeg + pz] = xnv;
+        }
         double sums[2] = {kt, l1};
         block_sum<2>(sums, s_red);
         if (threadIdx.x == 0) {
