@@ -28,6 +28,7 @@ hipError_t launch_dense_norms(int, const void*, const float*, int, int, const do
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
 hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
+hipError_t launch_solve_tail(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_to_wg(const SolveParams*, int, hipStream_t);
 }  // namespace sl1
 
@@ -310,8 +311,8 @@ int check_lds(const LaunchCfg& c) {
 //         the intermediate V), then y and the two lists when two workgroups per
 //         CU can still share the LDS;
 //   tail: every live signal on the last, dense, stage with at most max_act
-//         preserved atoms: z (FP64), an 8 KB scratch, y and both lists of
-//         max_act entries.
+//         preserved atoms: z (FP64), an 8 KB scratch, y, both lists of max_act
+//         entries and the per-position state of the preserved set.
 size_t wg_layout(SolveParams& p, bool tail, int max_act) {
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     const size_t lim = 160 * 1024 - 1024;       // static LDS of the kernel stays below 1 KB
@@ -333,8 +334,10 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act) {
         p.wo_lnj = put((size_t)cap * 4);
         p.wo_lnx = put((size_t)cap * 8);
         p.wo_lact = put((size_t)cap * 4);
+        p.wo_tail = put((size_t)cap * 7 * 8);
         return off <= lim ? off : 0;
     }
+    p.wo_tail = -1;
     size_t fac = 0, scr = 8192;                 // forward staging (6 KB) or cross-group sums (8 KB)
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
@@ -420,16 +423,18 @@ int hybrid_atoms(const SolveParams& p) {
 }
 
 // Whole-solve launches until every signal stopped (or the iteration cap, counting
-// the `done` iterations already run by the grid kernels); profile: launch times
-// and per-signal phase clocks.
+// the `done` iterations already run by the grid kernels); tail: the hybrid
+// solve's kernel for the last, dense, stage with LDS-resident per-atom state.
+// Profile: launch times and per-signal phase clocks.
 int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch, size_t wlds, bool prof, int dev,
-           long long done) {
+           long long done, bool tail) {
     const int per = std::min(wg_iters_per_launch(p), 256 * (o.chunk > 0 ? o.chunk : 16));
     const long long cap = (long long)o.max_iter + 1;
     long long launched = done;
     for (;;) {
         if (prof) HIP_TRY(hipEventRecord(w->ev_a, w->stream));
-        HIP_TRY(launch_solve_wg(w->dP, (int)batch, wlds, per, w->stream));
+        if (tail) HIP_TRY(launch_solve_tail(w->dP, (int)batch, wlds, per, w->stream));
+        else HIP_TRY(launch_solve_wg(w->dP, (int)batch, wlds, per, w->stream));
         if (prof) HIP_TRY(hipEventRecord(w->ev_b, w->stream));
         launched += per;
         HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
@@ -777,7 +782,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     }
     if (use_wg) {
         if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
-        st = run_wg(w, p, o, batch, wlds, prof, dev, 0);
+        st = run_wg(w, p, o, batch, wlds, prof, dev, 0, false);
         if (st != SL1_OK) return st;
         return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
     }
@@ -864,7 +869,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
                 HIP_TRY(launch_to_wg(w->dP, (int)batch, w->stream));
                 w->last_engine = SL1_ENGINE_HYBRID;
                 if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
-                st = run_wg(w, p, o, batch, tlds, prof, dev, launched);
+                st = run_wg(w, p, o, batch, tlds, prof, dev, launched, true);
                 if (st != SL1_OK) return st;
                 break;
             }

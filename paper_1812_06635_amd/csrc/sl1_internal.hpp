@@ -108,8 +108,10 @@ struct SolveParams {
     // z in FP64 and FP32, y, the current stage's Kronecker factors, the scratch
     // (staging, cross-wave sums, Kronecker intermediate), the nonzero list (index
     // and value) and the preserved list, with the two list capacities (entries);
-    // optional per-signal phase clocks [batch][kWgPhases] (wall-clock ticks)
-    int wo_zd, wo_zf, wo_y, wo_fac, wo_scr, wo_lnj, wo_lnx, wo_lact;
+    // the tail kernel's per-position state of the preserved set (7 FP64 arrays
+    // of wg_cap_act entries); optional per-signal phase clocks [batch][kWgPhases]
+    // (wall-clock ticks)
+    int wo_zd, wo_zf, wo_y, wo_fac, wo_scr, wo_lnj, wo_lnx, wo_lact, wo_tail;
     int wg_cap_nz, wg_cap_act;
     long long* wg_prof;
 };

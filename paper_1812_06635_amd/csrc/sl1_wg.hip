@@ -879,6 +879,334 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
 }
 
 // ---------------------------------------------------------------------------
+// tail kernel of the hybrid solve: every live signal is on the last, dense,
+// stage with a small preserved set.  The whole per-atom state of the preserved
+// set lives in LDS by list position (index, x_t, x_{t-1}, g_t, g_{t-1}, eps_j,
+// ||a_j||, ||a~_j||) and moves with the compaction, so an iteration touches
+// global memory only for the dense columns (forward and correlations), for
+// atoms being screened (their x and mask entries) and at exit (final x, or the
+// full state when the launch ends before the signal stops).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TailState {
+    int* la;                 // atom index
+    double *xt, *xp, *gt, *gp, *e, *an, *atn;
+};
+
+__device__ __forceinline__ TailState tail_state(char* smem, const SolveParams* P) {
+    const int cap = P->wg_cap_act;
+    TailState T;
+    T.la = (int*)(smem + P->wo_lact);
+    double* base = (double*)(smem + P->wo_tail);
+    T.xt = base;
+    T.xp = base + cap;
+    T.gt = base + 2 * (size_t)cap;
+    T.gp = base + 3 * (size_t)cap;
+    T.e = base + 4 * (size_t)cap;
+    T.an = base + 5 * (size_t)cap;
+    T.atn = base + 6 * (size_t)cap;
+    return T;
+}
+
+// correlations of the preserved positions (wave w takes NA positions at a time)
+template <int NA>
+__device__ void tail_adj(const StageDesc& st, int N, const TailState& T, int n_act, const double* zd, double rz,
+                         double (&mx)[3]) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int first = w * NA; first < n_act; first += kWgWaves * NA) {
+        int js[NA];
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const bool ok = first + q < n_act;
+            js[q] = T.la[ok ? first + q : first];
+            cnt += ok;
+        }
+        double gv[NA];
+        switch (st.dtype) {
+            case SL1_F64: dense_dots_t<SL1_F64, NA, (NA == 4 ? 2 : 4)>(st, N, js, zd, lane, gv); break;
+            case SL1_F32: dense_dots_t<SL1_F32, NA, 4>(st, N, js, zd, lane, gv); break;
+            case SL1_BF16: dense_dots_t<SL1_BF16, NA, 4>(st, N, js, zd, lane, gv); break;
+            default: dense_dots_t<SL1_FP8_E4M3, NA, 4>(st, N, js, zd, lane, gv); break;
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                if (q < cnt) {
+                    const int i = first + q;
+                    const double e = T.e[i];
+                    T.gt[i] = gv[q];
+                    mx[0] = fmax(mx[0], fabs(gv[q]) + e * rz);
+                    mx[1] = fmax(mx[1], fabs(gv[q]));
+                    mx[2] = fmax(mx[2], e);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* __restrict__ P0, int max_it) {
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    __shared__ Control sC;
+    __shared__ Scalars sS;
+    __shared__ double s_red[48];
+    __shared__ double s_sum[4];
+    __shared__ double s_kt[2];
+    __shared__ int s_cnt[2];
+    __shared__ int s_w[kWgWaves];
+    __shared__ long long s_clk;
+
+    if (tid == 0) {
+        sC = P0->ctrl[2 * b];
+        s_clk = P0->wg_prof ? wall_clock64() : 0;
+    }
+    __syncthreads();
+    if (sC.done) return;
+    // state of the preserved set into LDS
+    {
+        const SolveParams* P = phase_params(P0);
+        const int N = P->N, par = uni(sC.par), n_act = uni(sC.n_act), n_nz = uni(sC.n_nz);
+        const StageDesc& st = P->st[uni(sC.stage)];
+        const bool bad = st.kind != kDense || uni(sC.stage) != P->n_stages - 1 || P->wo_tail < 0 ||
+                         P->wg_cap_nz < P->wg_cap_act || n_act > P->wg_cap_act || n_nz > P->wg_cap_nz;
+        if (bad) {   // the host hands over only dense, small sets; anything else is refused
+            if (tid == 0) {
+                Final F;
+                F.gap = 0.0;
+                F.gap_cert = 0.0;
+                F.iters = sC.iter;
+                F.stage = sC.stage;
+                F.status = SL1_ELIMIT;
+                F.par = sC.par;
+                F.t0 = sC.t0;
+                F.tconv = 0;
+                P->fin[b] = F;
+                sC.done = 1;
+                P->ctrl[2 * b] = sC;
+                atomicSub(P->active_signals, 1);
+            }
+            return;
+        }
+        double* yl = (double*)(smem + P->wo_y);
+        for (int i = tid; i < N; i += kWgBlock) yl[i] = yval(P, b, i);
+        const TailState T = tail_state(smem, P);
+        const int* act = actbuf(P, b, 0);
+        const double* xc = xbuf(P, b, par);
+        const double* xo = xbuf(P, b, 1 - par);
+        const double* gprev = gbuf(P, b, 1 - par);
+        for (int i = tid; i < n_act; i += kWgBlock) {
+            const int j = act[i];
+            T.la[i] = j;
+            T.xt[i] = xc[j];
+            T.xp[i] = xo[j];
+            T.gp[i] = gprev[j];
+            T.e[i] = st.eps[j];
+            T.an[i] = P->atom_norm[j];
+            T.atn[i] = st.at_norm[j];
+        }
+        const int* nzl = nzbuf(P, b, 0);
+        int* lj = (int*)(smem + P->wo_lnj);
+        double* lx = (double*)(smem + P->wo_lnx);
+        for (int i = tid; i < n_nz; i += kWgBlock) {
+            const int j = nzl[i];
+            lj[i] = j;
+            lx[i] = xc[j];
+        }
+        __syncthreads();
+    }
+
+    for (int it = 0; it < max_it; ++it) {
+        const int par = uni(sC.par), n_nz = uni(sC.n_nz), n_act = uni(sC.n_act);
+        // ---- forward product and residual ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const StageDesc& st = P->st[uni(sC.stage)];
+            double* zd = (double*)(smem + P->wo_zd);
+            const double* yl = (const double*)(smem + P->wo_y);
+            char* scr = smem + P->wo_scr;
+            const int* lj = (const int*)(smem + P->wo_lnj);
+            const double* lx = (const double*)(smem + P->wo_lnx);
+            if (st.dtype == SL1_F64) wg_dense_forward<true>(P, b, st, nullptr, nullptr, n_nz, lj, lx, true, zd, nullptr, yl, scr, s_red, s_sum);
+            else wg_dense_forward<false>(P, b, st, nullptr, nullptr, n_nz, lj, lx, true, zd, nullptr, yl, scr, s_red, s_sum);
+            __syncthreads();
+            wg_stamp(P, b, 0, s_clk);
+        }
+        // ---- correlations, maxima of the stable dual scaling, scalars ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const int N = P->N;
+            const StageDesc& st = P->st[uni(sC.stage)];
+            const double* zd = (const double*)(smem + P->wo_zd);
+            const double rz = uni(sqrt(s_sum[1]));
+            const TailState T = tail_state(smem, P);
+            double mx[3] = {0.0, 0.0, 0.0};
+            if (N <= 1024) tail_adj<4>(st, N, T, n_act, zd, rz, mx);
+            else tail_adj<1>(st, N, T, n_act, zd, rz, mx);
+            block_max<3>(mx, s_red);
+            if (tid == 0) {
+                Scalars S;
+                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], S);
+                if (S.conv == 1) S.tconv = wall_clock64();
+                sS = S;
+            }
+            __syncthreads();
+            wg_stamp(P, b, 1, s_clk);
+        }
+        if (uni(sS.conv)) {
+            // the final iterate x_t of the preserved atoms to global memory
+            const SolveParams* P = phase_params(P0);
+            const TailState T = tail_state(smem, P);
+            double* xc = xbuf(P, b, par);
+            for (int i = tid; i < n_act; i += kWgBlock) xc[T.la[i]] = T.xt[i];
+            if (tid == 0) {
+                Final F;
+                F.gap = sS.Gt;
+                F.gap_cert = sS.Gp + sS.delta;
+                F.iters = sC.iter;
+                F.stage = sC.stage;
+                F.status = sS.conv == 2 ? SL1_MAXITER : SL1_OK;
+                F.par = sC.par;
+                F.t0 = sC.t0;
+                F.tconv = sS.tconv;
+                P->fin[b] = F;
+                sC.done = 1;
+                P->ctrl[2 * b] = sC;
+                atomicSub(P->active_signals, 1);
+            }
+            return;
+        }
+        // ---- stable GAP test, look-ahead count, FISTA step, compaction (LDS) ----
+        {
+            const SolveParams* P = phase_params(P0);
+            const int K = P->K;
+            const StageDesc& st = P->st[uni(sC.stage)];
+            const TailState T = tail_state(smem, P);
+            int* lj = (int*)(smem + P->wo_lnj);
+            double* lx = (double*)(smem + P->wo_lnx);
+            uint8_t* mask = P->mask + (size_t)b * K;
+            double* xc = xbuf(P, b, par);
+            double* xo = xbuf(P, b, 1 - par);
+            const double c1 = uni(sS.c1), c2 = uni(sS.c2), Rp = uni(sS.Rp), beta = uni(sS.beta);
+            const double invL = st.invL, thr = uni(sC.lam) * st.invL, keep_min = 1.0 - P->margin;
+            int wpos = 0, zpos = 0;
+            double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
+            for (int base = 0; base < n_act; base += kWgBlock) {
+                const int i = base + tid;
+                const bool valid = i < n_act;
+                bool keep = false, nzf = false;
+                int j = 0;
+                double xn = 0.0, xt = 0.0, gt = 0.0, e = 0.0, an = 0.0, atn = 0.0;
+                if (valid) {
+                    j = T.la[i];
+                    xt = T.xt[i];
+                    gt = T.gt[i];
+                    e = T.e[i];
+                    an = T.an[i];
+                    atn = T.atn[i];
+                    const double xp = T.xp[i];
+                    const double gp = T.gp[i];
+                    const double ag = fabs(gt);
+                    // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
+                    const double mu = c1 * ag + e * c2 + Rp * an;
+                    keep = mu >= keep_min;
+                    // look-ahead: conventional test on the approximate atom
+                    sv[0] += (c1 * ag + Rp * atn >= 1.0) ? 1.0 : 0.0;
+                    // FISTA step from the two correlation vectors (gradient by linearity)
+                    const double zpt = xt + beta * (xt - xp);
+                    const double hh = (1.0 + beta) * gt - beta * gp;
+                    const double v = zpt + hh * invL;
+                    if (keep) xn = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
+                    if (!keep) {         // screened: its coefficient is zero in both iterates
+                        xc[j] = 0.0;
+                        xo[j] = 0.0;
+                        mask[j] = 0;
+                    }
+                    nzf = keep && (xn != 0.0);
+                    sv[1] += fabs(xn);
+                }
+                // every read of this part of the state precedes the in-place writes
+                __syncthreads();
+                int tk, tz;
+                const int pk = wg_scan_flag(keep, s_w, tk);
+                if (keep) {
+                    const int q = wpos + pk;
+                    T.la[q] = j;
+                    T.xt[q] = xn;        // x_{t+1}
+                    T.xp[q] = xt;        // x_t
+                    T.gp[q] = gt;        // g_t
+                    T.e[q] = e;
+                    T.an[q] = an;
+                    T.atn[q] = atn;
+                }
+                const int pz = wg_scan_flag(nzf, s_w, tz);
+                if (nzf) {
+                    lj[zpos + pz] = j;
+                    lx[zpos + pz] = xn;
+                }
+                wpos += tk;
+                zpos += tz;
+            }
+            block_sum<2>(sv, s_red);
+            if (tid == 0) {
+                s_kt[0] = sv[0];
+                s_kt[1] = sv[1];
+                s_cnt[0] = wpos;
+                s_cnt[1] = zpos;
+            }
+            __syncthreads();
+            wg_stamp(P, b, 3, s_clk);
+        }
+        // ---- trace row and momentum (thread 0; the last stage stays) ----
+        if (tid == 0) {
+            const SolveParams* P = phase_params(P0);
+            Control C = sC;
+            if (P->trace && C.iter < P->trace_cap) {
+                double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
+                tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
+                tr[4] = s_kt[0];
+                tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = sS.Rp; tr[9] = sS.gamma;
+                tr[10] = C.l1; tr[11] = sS.P; tr[12] = C.n_nz;
+            }
+            C.ksince += 1;
+            C.tau = sS.tau_next;
+            C.iter += 1;
+            C.par = 1 - C.par;
+            C.n_act = s_cnt[0];
+            C.n_nz = s_cnt[1];
+            C.l1 = s_kt[1];
+            sC = C;
+        }
+        __syncthreads();
+    }
+    // the launch ends before the signal stops: state back to global memory
+    {
+        const SolveParams* P = phase_params(P0);
+        const int par = uni(sC.par), n_act = uni(sC.n_act), n_nz = uni(sC.n_nz);
+        const TailState T = tail_state(smem, P);
+        const int* lj = (const int*)(smem + P->wo_lnj);
+        int* act = actbuf(P, b, 0);
+        int* nzl = nzbuf(P, b, 0);
+        double* xc = xbuf(P, b, par);
+        double* xo = xbuf(P, b, 1 - par);
+        double* gprev = gbuf(P, b, 1 - par);
+        for (int i = tid; i < n_act; i += kWgBlock) {
+            const int j = T.la[i];
+            act[i] = j;
+            xc[j] = T.xt[i];
+            xo[j] = T.xp[i];
+            gprev[j] = T.gp[i];
+        }
+        for (int i = tid; i < n_nz; i += kWgBlock) nzl[i] = lj[i];
+        if (tid == 0) P->ctrl[2 * b] = sC;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // hand-over from the per-iteration grid kernels: after a forward launch of slot
 // 0 has formed C_{t+1} (ctrl[2 b]) and the segment prefixes of its two lists,
 // copy the segmented lists of buffer C.par into contiguous lists in buffer 0,
@@ -909,6 +1237,16 @@ __global__ __launch_bounds__(kSeg) void k_to_wg(const SolveParams* __restrict__ 
 
 hipError_t launch_to_wg(const SolveParams* dP, int batch, hipStream_t s) {
     hipLaunchKernelGGL(k_to_wg, dim3(batch), dim3(kSeg), 0, s, dP);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_tail(const SolveParams* dP, int batch, size_t lds, int max_it, hipStream_t s) {
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_solve_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_solve_tail, dim3(batch), dim3(kWgBlock), lds, s, dP, max_it);
     return hipGetLastError();
 }
 
