@@ -127,7 +127,11 @@ typedef struct {
 #define SL1_FLAG_PROFILE 2    /* direct launches bracketed by HIP events; see sl1_last_solve_profile */
 #define SL1_FLAG_ENGINE_GRID 4    /* force the per-iteration grid engine throughout */
 #define SL1_FLAG_ENGINE_WG 8      /* force the whole-solve engine (SL1_ELIMIT if its LDS need exceeds 159 KB) */
-#define SL1_FLAG_ENGINE_HYBRID 16 /* grid engine, then the whole-solve engine for the tail (SL1_ELIMIT as above) */
+#define SL1_FLAG_ENGINE_HYBRID 16 /* grid engine, then the tail kernel (SL1_ELIMIT if a dense last stage's
+                                     tail layout exceeds 159 KB; the grid engine alone when the last
+                                     stage is not dense) */
+#define SL1_FLAG_TAIL_COLUMNS 32  /* the tail kernel forms every iteration's products from the stored
+                                     columns (no Gram mode) */
 
 /* Engines (at most one SL1_FLAG_ENGINE_* flag; none = automatic):
  *   SL1_ENGINE_GRID    three persistent launches per iteration covering every live
@@ -135,12 +139,20 @@ typedef struct {
  *   SL1_ENGINE_WG      one 512-thread workgroup per signal runs the whole solve in one
  *                      launch (per-signal z and the current stage's Kronecker factors in
  *                      LDS); launches are bounded and repeated while signals remain;
- *   SL1_ENGINE_HYBRID  the grid engine until, after a chunk, every live signal's
- *                      preserved set holds at most ~1 MiB of dense columns; the
- *                      remaining iterations then run in the whole-solve engine.
- * Automatic choice: whole-solve when its LDS need fits and N*K <= 2^20, hybrid when it
- * fits and N*K is larger, grid otherwise.  All compute every per-element quantity with
- * the same expressions; results differ only by the order of FP64 reductions. */
+ *   SL1_ENGINE_HYBRID  the grid engine until, after a chunk, every live signal is on
+ *                      the last (dense) stage and its preserved set holds at most
+ *                      ~1 MiB of columns or fits the Gram capacity (up to 128 atoms);
+ *                      the remaining iterations then run in a tail kernel, one
+ *                      workgroup per signal with the preserved set's state in LDS.
+ *                      Once a signal's |A_t| fits the Gram capacity, the tail kernel
+ *                      forms G = A_t^T A_t and A_t^T y once (FP64) and iterates on
+ *                      them (g = A_t^T y - G x, ||y - Ax||^2 and y^T(y - Ax) from the
+ *                      same forms), with the FP64 rounding of these forms bounded and
+ *                      added to the test and to delta (SL1_FLAG_TAIL_COLUMNS: never).
+ * Automatic choice: whole-solve when its LDS need fits and N*K <= 2^20, hybrid when the
+ * last stage is dense and N*K is larger, grid otherwise.  All compute every per-element
+ * quantity with the same expressions; results differ only by the order of FP64
+ * reductions (and, in Gram mode, by the Gram forms of the same products). */
 #define SL1_ENGINE_GRID 1
 #define SL1_ENGINE_WG 2
 #define SL1_ENGINE_HYBRID 3
@@ -248,7 +260,8 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
  * shapes (*engine = SL1_ENGINE_GRID, _WG or _HYBRID) and, when it was run with
  * SL1_FLAG_PROFILE, for its whole-solve part: phase_ms[0..3] (host, 5 doubles,
  * may be NULL) workgroup milliseconds summed over signals of forward/residual,
- * dense correlations, Kronecker correlations and test/update/compaction,
+ * dense correlations, Kronecker correlations (hybrid tail: Gram-mode
+ * correlations and scalars) and test/update/compaction,
  * phase_ms[4] the elapsed milliseconds of the whole-solve launches and
  * *wg_launches (may be NULL) their number.  sl1_last_solve_profile covers the
  * grid kernels.

@@ -117,12 +117,14 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
-          trace_cap=0, use_graph=True, profile=False, check=True, engine="auto"):
+          trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
-    signal for the whole solve) or "hybrid" (grid, then whole-solve for the tail).  Returns a dict of device tensors x, gap,
-    gap_cert, screened, iters, stage, the status code, and the trace
-    (batch, trace_cap, 12) when requested."""
+    signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
+    signal is on the last, dense, stage with a small preserved set); tail_gram:
+    the tail iterates on G = A_t^T A_t once |A_t| fits (else it streams columns).
+    Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
+    status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
         raise ValueError(f"engine must be one of {sorted(_ENGINES)}")
     if y.dtype not in (torch.float64, torch.float32):
@@ -144,7 +146,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.Gamma, opts.tol, opts.margin = Gamma, tol, margin
     opts.max_iter, opts.chunk = max_iter, chunk
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
-    opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine]
+    opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
+        (0 if tail_gram else L.FLAG_TAIL_COLUMNS)
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)
@@ -229,7 +232,9 @@ def last_solve_phases(batch, N, K):
     L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph, ctypes.byref(n)),
             "sl1_last_solve_phases")
     name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg", L.ENGINE_HYBRID: "hybrid"}.get(eng.value, "none")
-    out = dict(zip(("fwd", "adj_dense", "adj_kron", "upd", "wg_ms"), list(ph)))
+    keys = ("fwd", "adj_dense", "gram", "upd", "wg_ms") if name == "hybrid" else \
+        ("fwd", "adj_dense", "adj_kron", "upd", "wg_ms")
+    out = dict(zip(keys, list(ph)))
     out["wg_launches"] = n.value
     return name, out
 

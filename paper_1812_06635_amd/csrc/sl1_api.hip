@@ -312,8 +312,11 @@ int check_lds(const LaunchCfg& c) {
 //         CU can still share the LDS;
 //   tail: every live signal on the last, dense, stage with at most max_act
 //         preserved atoms: z (FP64), an 8 KB scratch, y, both lists of max_act
-//         entries and the per-position state of the preserved set.
-size_t wg_layout(SolveParams& p, bool tail, int max_act) {
+//         entries and the per-position state of the preserved set; with gram,
+//         the Gram region (G, c, row atoms) overlays z, the scratch and y, its
+//         capacity the largest multiple of 16 up to 128 that keeps two
+//         workgroups per CU when the batch needs them.
+size_t wg_layout(SolveParams& p, bool tail, int max_act, bool gram) {
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     const size_t lim = 160 * 1024 - 1024;       // static LDS of the kernel stays below 1 KB
     const size_t two_per_cu = 79 * 1024;
@@ -324,17 +327,34 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act) {
         return (int)std::min<size_t>(o, (size_t)INT32_MAX);
     };
     const size_t N = (size_t)p.N;
+    p.wo_gram = -1;
+    p.wg_cap_gram = 0;
     p.wo_zd = put(N * 8);
     if (tail) {
         const int cap = std::max(64, (max_act + 63) & ~63);
         p.wo_zf = p.wo_fac = -1;
         p.wo_scr = put(8192);                    // the dense forward's cross-group sums
         p.wo_y = put(N * 8);
+        const size_t colbuf = off;
+        const size_t lists = a16((size_t)cap * 4) + a16((size_t)cap * 8) + a16((size_t)cap * 4) +
+                             a16((size_t)cap * (7 * 8 + 4));
+        auto gbytes = [&](size_t g) { return a16(g * g * 8) + a16(g * 8) + a16(g * 4); };
+        if (gram) {
+            const size_t target = (p.batch > 256 && colbuf + lists <= two_per_cu) ? two_per_cu : lim;
+            for (int g = 128; g >= 16; g -= 16) {
+                if (std::max(colbuf, gbytes((size_t)g)) + lists <= target) {
+                    p.wg_cap_gram = g;
+                    p.wo_gram = 0;
+                    off = std::max(colbuf, gbytes((size_t)g));
+                    break;
+                }
+            }
+        }
         p.wg_cap_nz = p.wg_cap_act = cap;
         p.wo_lnj = put((size_t)cap * 4);
         p.wo_lnx = put((size_t)cap * 8);
         p.wo_lact = put((size_t)cap * 4);
-        p.wo_tail = put((size_t)cap * 7 * 8);
+        p.wo_tail = put((size_t)cap * (7 * 8 + 4));
         return off <= lim ? off : 0;
     }
     p.wo_tail = -1;
@@ -742,21 +762,28 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.lam = lambda;
     const int eng = o.flags & (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG | SL1_FLAG_ENGINE_HYBRID);
     if (eng & (eng - 1)) return SL1_EINVAL;   // at most one engine flag
-    const size_t wlds = wg_layout(p, false, 0);
+    const bool gram = !(o.flags & SL1_FLAG_TAIL_COLUMNS);
+    const size_t wlds = wg_layout(p, false, 0, false);
+    // the tail hand-over needs a dense last stage whose tail layout fits
+    bool tail_fits = p.st[p.n_stages - 1].kind == kDense;
+    if (tail_fits) {
+        SolveParams probe = p;
+        tail_fits = wg_layout(probe, true, 64, gram) != 0;
+    }
     bool use_wg = false, hybrid = false;
-    if (eng == SL1_FLAG_ENGINE_WG || eng == SL1_FLAG_ENGINE_HYBRID) {
+    if (eng == SL1_FLAG_ENGINE_WG) {
         if (!wlds) return SL1_ELIMIT;
-        use_wg = eng == SL1_FLAG_ENGINE_WG;
-        hybrid = !use_wg;
-    } else if (eng == 0 && wlds) {
+        use_wg = true;
+    } else if (eng == SL1_FLAG_ENGINE_HYBRID) {
+        if (p.st[p.n_stages - 1].kind == kDense && !tail_fits) return SL1_ELIMIT;
+        hybrid = tail_fits;
+    } else if (eng == 0) {
         // small dictionaries: one workgroup per signal throughout (a dense stage is
         // cheap for one CU); larger ones: the grid kernels while the preserved sets
-        // are large, then the whole-solve kernel for the tail
-        use_wg = (int64_t)p.N * p.K <= (1 << 20);
-        hybrid = !use_wg;
+        // are large, then the tail kernel
+        use_wg = wlds && (int64_t)p.N * p.K <= (1 << 20);
+        hybrid = !use_wg && tail_fits;
     }
-    // the tail hand-over needs a dense last stage
-    if (p.st[p.n_stages - 1].kind != kDense) hybrid = false;
     const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
     p.wg_prof = ((use_wg || hybrid) && prof) ? w->d_wgprof : nullptr;
     LaunchCfg cfg = launch_cfg(*w, p);
@@ -861,9 +888,11 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         // signal is on the last stage with a small preserved set (statistics of
         // the chunk's last launch, slot 1)
         const int* stat1 = w->h_active + 4 + 4;
-        if (hybrid && stat1[0] <= hyb_atoms && stat1[2] == 0) {
-            const size_t tlds = wg_layout(p, true, stat1[0]);
-            if (tlds) {
+        if (hybrid && stat1[2] == 0) {
+            // in Gram mode an iteration costs no N-length work: hand over as soon as
+            // the largest preserved set fits the Gram capacity
+            const size_t tlds = wg_layout(p, true, stat1[0], gram);
+            if (tlds && (stat1[0] <= hyb_atoms || stat1[0] <= p.wg_cap_gram)) {
                 HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
                 HIP_TRY(launch_one(0, 0, w->dP, cfg, w->stream));
                 HIP_TRY(launch_to_wg(w->dP, (int)batch, w->stream));

@@ -109,10 +109,11 @@ struct SolveParams {
     // (staging, cross-wave sums, Kronecker intermediate), the nonzero list (index
     // and value) and the preserved list, with the two list capacities (entries);
     // the tail kernel's per-position state of the preserved set (7 FP64 arrays
-    // of wg_cap_act entries); optional per-signal phase clocks [batch][kWgPhases]
-    // (wall-clock ticks)
-    int wo_zd, wo_zf, wo_y, wo_fac, wo_scr, wo_lnj, wo_lnx, wo_lact, wo_tail;
-    int wg_cap_nz, wg_cap_act;
+    // and one int array of wg_cap_act entries) and its Gram region (G, c and the
+    // atom of each row, wg_cap_gram rows; 0: columns only); optional per-signal
+    // phase clocks [batch][kWgPhases] (wall-clock ticks)
+    int wo_zd, wo_zf, wo_y, wo_fac, wo_scr, wo_lnj, wo_lnx, wo_lact, wo_tail, wo_gram;
+    int wg_cap_nz, wg_cap_act, wg_cap_gram;
     long long* wg_prof;
 };
 

@@ -517,7 +517,10 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
 // ---------------------------------------------------------------------------
 // adjoint: Kronecker tile G[a0:a0+16, cb0:cb0+64] = sum_r C_r^T P B_r with MFMA.
 // MFMA 16x16 operand layout (wave64): lane l holds A[l%16][k], B[k][l%16] with
-// k = l/16 (x4 shapes) or 4*(l/16)+v (x16 shapes); D[4*(l/16)+v][l%16].
+// k = l/16 (x4 shapes) or 4*(l/16)+v (x16 shapes); D[4*(l/16)+v][l%16], except
+// the FP64 16x16x4 form, whose D is D[4v+l/16][l%16]: its first product stores V
+// rows in the 4*(l/16)+v order and the second reads them back as operand rows,
+// so the two within-tile row permutations cancel.
 // Wave w handles the terms r = w, w+4, ...; the four partial tiles are summed
 // in LDS in a fixed order.
 // ---------------------------------------------------------------------------

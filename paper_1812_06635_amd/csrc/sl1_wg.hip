@@ -376,7 +376,9 @@ __device__ __forceinline__ void wg_dense_forward(const SolveParams* P, int b, co
 // Kronecker correlations with LDS operands: G[a][j1] = sum_r (C_r^T Z B_r)[a][j1],
 // g_j for j = j1 k2 + a.  MFMA 16x16 operand layout (wave64): lane l holds
 // A[l%16][k], B[k][l%16] with k = l/16 (x4 shapes) or 4(l/16)+v (x16 shapes);
-// D[4(l/16)+v][l%16].
+// D[4(l/16)+v][l%16], except the FP64 16x16x4 form, whose D is D[4v+l/16][l%16]:
+// its first product stores V rows in the 4(l/16)+v order and its second reads
+// them back as operand rows, so the two within-tile row permutations cancel.
 // ---------------------------------------------------------------------------
 template <int DT>
 __device__ void wg_kron_adj(const StageDesc& st, const char* fac, const double* zd, const float* zf, char* scr,
@@ -879,19 +881,34 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
 }
 
 // ---------------------------------------------------------------------------
-// tail kernel of the hybrid solve: every live signal is on the last, dense,
+// Tail kernel of the hybrid solve: every live signal is on the last, dense,
 // stage with a small preserved set.  The whole per-atom state of the preserved
 // set lives in LDS by list position (index, x_t, x_{t-1}, g_t, g_{t-1}, eps_j,
-// ||a_j||, ||a~_j||) and moves with the compaction, so an iteration touches
-// global memory only for the dense columns (forward and correlations), for
-// atoms being screened (their x and mask entries) and at exit (final x, or the
-// full state when the launch ends before the signal stops).
+// ||a_j||, ||a~_j||) and moves with the compaction.  Two modes per signal:
+//   columns  an iteration forms the residual from the gathered columns and
+//            correlates it with the preserved columns (all 8 waves); global
+//            memory is touched only for those columns, for atoms being screened
+//            (their x and mask entries) and at exit;
+//   Gram     once |A_t| fits the Gram capacity, G = A_t^T A_t and c = A_t^T y are
+//            formed once (FP64 MFMA over the stored columns), after which an
+//            iteration has no N-length work: g = c - G x_t, y^T rho =
+//            ||y||^2 - c^T x_t and ||rho||^2 = y^T rho - x_t^T g (rho = y - A x_t).
+//            A_t only shrinks, so G stays valid; positions keep their row of G.
+//            Wave 0 runs these iterations alone, without workgroup barriers.
+// The FP64 rounding of the Gram forms is bounded a priori (standard dot-product
+// bound gamma_n = n u / (1 - n u), u = 2^-53, n doubled for slack): every |g_j|
+// is off by at most eta ||a_j||, eta = gamma_n (||y|| + X) with X = sum_k ||a_k||
+// |x_k|, so eta ||a_j|| joins the dual-scaling maximum (Lemma 2 stays exact) and
+// the sphere test; ||rho||^2 and y^T rho are off by at most 4 gamma_n (||y|| + X)^2
+// and gamma_n (||y|| + X)^2, whose effect on P(x_t) - D(theta') is added to delta
+// (Theorem 1), hence to the radius R' and to the certified gap.
 // ---------------------------------------------------------------------------
 namespace {
 
 struct TailState {
     int* la;                 // atom index
-    double *xt, *xp, *gt, *gp, *e, *an, *atn;
+    int* lg;                 // row of the atom in the Gram matrix (Gram mode)
+    double *xt, *xp, *gt, *gm, *e, *an, *atn;   // x_t, x_{t-1}, g_t, g_{t-1}, eps, norms
 };
 
 __device__ __forceinline__ TailState tail_state(char* smem, const SolveParams* P) {
@@ -902,11 +919,19 @@ __device__ __forceinline__ TailState tail_state(char* smem, const SolveParams* P
     T.xt = base;
     T.xp = base + cap;
     T.gt = base + 2 * (size_t)cap;
-    T.gp = base + 3 * (size_t)cap;
+    T.gm = base + 3 * (size_t)cap;
     T.e = base + 4 * (size_t)cap;
     T.an = base + 5 * (size_t)cap;
     T.atn = base + 6 * (size_t)cap;
+    T.lg = (int*)(base + 7 * (size_t)cap);
     return T;
+}
+
+// LDS ordering among the lanes of one wave (no other wave takes part)
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // correlations of the preserved positions (wave w takes NA positions at a time)
@@ -946,6 +971,344 @@ __device__ void tail_adj(const StageDesc& st, int N, const TailState& T, int n_a
     }
 }
 
+// c_i = a_{la[i]}^T y for positions i < m (one wave per position, FP64 sums)
+template <int DT>
+__device__ void tail_gram_c(const StageDesc& st, int N, const int* la, int m, const double* yl, double* c) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int i = w; i < m; i += kWgWaves) {
+        const int j = la[i];
+        const size_t cj = (size_t)j * N;
+        double acc = 0.0;
+        for (int r = 4 * l; r < N; r += 256) {
+            double a[4];
+            raw_get<DT>(raw_load<DT>(st.A, cj + r), a);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc = fma(a[v], yl[r + v], acc);
+        }
+        acc = wave_sum(acc);
+        if (l == 0) c[i] = st.scale ? acc * (double)st.scale[j] : acc;
+    }
+}
+
+// Gram matrix of positions 0..m-1 (column-major, leading dimension ld) with FP64
+// MFMA 16x16x4: one wave per 16 x 16 tile (I, J), I <= J.  Lane l reads rows
+// k0 + 4 (l / 16) .. + 3 of the columns at positions 16 I + l % 16 and
+// 16 J + l % 16 and feeds row k0 + 4 (l / 16) + v to the v-th MFMA of a step,
+// so the four MFMAs of a step cover 16 rows; column scales apply at the end.
+// FP64 accumulator layout: lane l holds D[4 v + l / 16][l % 16].
+template <int DT>
+__device__ void tail_gram_g(const StageDesc& st, int N, const int* la, int m, double* G, int ld) {
+    constexpr int U = DT == SL1_F64 ? 4 : 8;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int nt = (m + 15) >> 4;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t = w; t < ntiles; t += kWgWaves) {
+        int I = 0, rem = t;
+        while (rem >= nt - I) {
+            rem -= nt - I;
+            ++I;
+        }
+        const int J = I + rem;
+        const int pa = min(16 * I + li, m - 1), pb = min(16 * J + li, m - 1);
+        const size_t ca = (size_t)la[pa] * N, cb = (size_t)la[pb] * N;
+        f64x4 d = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < N; k0 += 16 * U) {
+            Raw4<DT> ra[U], rb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = k0 + 16 * u + 4 * lk;
+                const int rr = r < N ? r : 0;          // rows past N read row 0 and are zeroed
+                ra[u] = raw_load<DT>(st.A, ca + rr);
+                rb[u] = raw_load<DT>(st.A, cb + rr);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = k0 + 16 * u + 4 * lk < N;
+                double a[4], bv[4];
+                raw_get<DT>(ra[u], a);
+                raw_get<DT>(rb[u], bv);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    d = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? a[v] : 0.0, bv[v], d, 0, 0, 0);
+            }
+        }
+        const double sb = st.scale ? (double)st.scale[la[pb]] : 1.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + lk, c = 16 * J + li;
+            if (r < m && c < m) {
+                const double sa = st.scale ? (double)st.scale[la[r]] : 1.0;
+                const double val = d[v] * sa * sb;
+                G[(size_t)c * ld + r] = val;
+                if (I != J) G[(size_t)r * ld + c] = val;
+            }
+        }
+    }
+}
+
+// Gram mode set-up for positions 0..m-1 (all threads): c into T.gt, ||y||^2,
+// then (y no longer needed; the Gram region overlays z, the scratch and y) G,
+// c and the atom of each Gram row, and lg[i] = i.
+__device__ __attribute__((noinline)) void tail_gram_build(const SolveParams* P, int b, const StageDesc& st,
+                                                          char* smem, int m, double* s_red, double* s_yy) {
+    const int N = P->N, gcap = P->wg_cap_gram, tid = threadIdx.x;
+    const TailState T = tail_state(smem, P);
+    const double* yl = (const double*)(smem + P->wo_y);
+    switch (st.dtype) {
+        case SL1_F64: tail_gram_c<SL1_F64>(st, N, T.la, m, yl, T.gt); break;
+        case SL1_F32: tail_gram_c<SL1_F32>(st, N, T.la, m, yl, T.gt); break;
+        case SL1_BF16: tail_gram_c<SL1_BF16>(st, N, T.la, m, yl, T.gt); break;
+        default: tail_gram_c<SL1_FP8_E4M3>(st, N, T.la, m, yl, T.gt); break;
+    }
+    double yy[1] = {0.0};
+    for (int i = tid; i < N; i += kWgBlock) yy[0] = fma(yl[i], yl[i], yy[0]);
+    block_sum<1>(yy, s_red);              // its barriers also order every read of y before G
+    if (tid == 0) *s_yy = yy[0];
+    double* G = (double*)(smem + P->wo_gram);
+    double* cv = G + (size_t)gcap * gcap;
+    int* ga = (int*)(cv + gcap);
+    switch (st.dtype) {
+        case SL1_F64: tail_gram_g<SL1_F64>(st, N, T.la, m, G, gcap); break;
+        case SL1_F32: tail_gram_g<SL1_F32>(st, N, T.la, m, G, gcap); break;
+        case SL1_BF16: tail_gram_g<SL1_BF16>(st, N, T.la, m, G, gcap); break;
+        default: tail_gram_g<SL1_FP8_E4M3>(st, N, T.la, m, G, gcap); break;
+    }
+    for (int i = tid; i < m; i += kWgBlock) {
+        cv[i] = T.gt[i];
+        ga[i] = T.la[i];
+        T.lg[i] = i;
+    }
+    __syncthreads();
+}
+
+// Gram-mode iterations of one signal, wave 0 only; lane l holds list positions
+// l + 64 h, h < H (Gram capacity <= 64 H).  Leaves the control state in *sCp;
+// sets *s_done when the signal stopped.
+template <int H>
+__device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int it, int max_it, char* smem,
+                                               Control* sCp, int* s_done, long long* s_clk, double yy) {
+    const int l = threadIdx.x & 63;
+    const SolveParams* P = phase_params(P0);
+    Control C = *sCp;
+    const StageDesc& st = P->st[uni(C.stage)];
+    const int N = P->N, K = P->K, gcap = P->wg_cap_gram;
+    const TailState T = tail_state(smem, P);
+    const double* G = (const double*)(smem + P->wo_gram);
+    const double* cv = G + (size_t)gcap * gcap;
+    int* lj = (int*)(smem + P->wo_lnj);       // nonzero list, as Gram rows
+    double* lx = (double*)(smem + P->wo_lnx);
+    const double invL = uni(st.invL), lam = uni(C.lam), thr = uni(lam * st.invL), keep_min = uni(1.0 - P->margin);
+    const double ny = uni(sqrt(yy));
+    const unsigned long long below = (1ull << l) - 1ull;
+    int n_act = uni(C.n_act), n_nz = 0;
+    double X;
+    {
+        double xs = 0.0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int i = l + 64 * h;
+            const bool in = i < n_act;
+            const double xv = in ? T.xt[i] : 0.0;
+            const bool nzf = xv != 0.0;
+            if (in) xs += T.an[i] * fabs(xv);
+            const unsigned long long bal = __ballot(nzf);
+            if (nzf) {
+                const int q = n_nz + __popcll(bal & below);
+                lj[q] = T.lg[i];
+                lx[q] = xv;
+            }
+            n_nz += __popcll(bal);
+        }
+        X = uni(wave_sum(xs));
+    }
+    wave_sync_lds();
+    for (; it < max_it; ++it) {
+        // per-iteration copies of the parameter block and of the lane's positions
+        // keep addresses out of the loop-carried registers
+        const SolveParams* Pi = phase_params(P0);
+        int lo = l;
+        asm volatile("" : "+v"(lo));
+        const int par = uni(C.par);
+        const double nu = 2.0 * (double)(N + n_nz + 2) * 0x1p-53;
+        const double gam = uni(nu / (1.0 - nu));
+        const double YX = uni(ny + X);
+        const double eta = uni(gam * YX);
+        // ---- g = c - G x_t over the preserved positions ----
+        double xt[H], g[H];
+        double cx = 0.0, xg = 0.0, m1 = 0.0, me = 0.0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int i = lo + 64 * h;
+            xt[h] = g[h] = 0.0;
+            if (i < n_act) {
+                const int r = T.lg[i];
+                xt[h] = T.xt[i];
+                const double* Gc = G + r;
+                double gi = cv[r];
+                for (int q = 0; q < n_nz; ++q) gi = fma(-Gc[(size_t)lj[q] * gcap], lx[q], gi);
+                g[h] = gi;
+                cx = fma(cv[r], xt[h], cx);
+                xg = fma(xt[h], gi, xg);
+                m1 = fmax(m1, fabs(gi) + eta * T.an[i]);
+                me = fmax(me, T.e[i]);
+            }
+        }
+        cx = uni(wave_sum(cx));
+        xg = uni(wave_sum(xg));
+        m1 = uni(wave_max(m1));
+        me = uni(wave_max(me));
+        // ---- scalars (uniform) ----
+        const double yr = yy - cx;
+        const double r2 = fmax(yr - xg, 0.0);
+        const double e_yr = gam * YX * YX, e_r2 = 4.0 * gam * YX * YX;
+        const double rz = uni(sqrt(r2 + e_r2));
+        double c1, c2, Rp, beta, tau_next, Gp, Gt, delta, gam_t, Pv;
+        int conv;
+        {
+            Scalars S;
+            scalars_from(Pi, C, r2, r2, yr, m1 + me * rz, m1, me, S);
+            c1 = uni(S.c1);
+            beta = uni(S.beta);
+            tau_next = uni(S.tau_next);
+            Gp = uni(S.Gp);
+            Gt = uni(S.Gt);
+            gam_t = uni(S.gamma);
+            Pv = uni(S.P);
+            conv = uni(S.conv);
+            delta = uni(S.delta + 0.5 * e_r2 + lam * c1 * e_yr + 0.5 * lam * lam * c1 * c1 * e_r2 + lam * gam * C.l1);
+            Rp = uni(sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam);
+            c2 = uni(c1 * rz);
+        }
+        wg_stamp(Pi, b, 2, *s_clk);
+        if (conv) {
+            double* xc = xbuf(Pi, b, par);
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int i = lo + 64 * h;
+                if (i < n_act) xc[T.la[i]] = xt[h];
+            }
+            if (l == 0) {
+                Final F;
+                F.gap = Gt;
+                F.gap_cert = Gp + delta;
+                F.iters = C.iter;
+                F.stage = C.stage;
+                F.status = conv == 2 ? SL1_MAXITER : SL1_OK;
+                F.par = C.par;
+                F.t0 = C.t0;
+                F.tconv = conv == 1 ? wall_clock64() : 0;
+                Pi->fin[b] = F;
+                C.done = 1;
+                Pi->ctrl[2 * b] = C;
+                *sCp = C;
+                *s_done = 1;
+                atomicSub(Pi->active_signals, 1);
+            }
+            return;
+        }
+        // ---- stable GAP test (|g_j| + eta ||a_j||), look-ahead count, FISTA step ----
+        const double Rq = uni(Rp + c1 * eta);
+        bool keep[H], nzf[H];
+        double xn[H];
+        double kt = 0.0, l1 = 0.0, Xn = 0.0;
+        {
+            double* xc = xbuf(Pi, b, par);
+            double* xo = xbuf(Pi, b, 1 - par);
+            uint8_t* mask = Pi->mask + (size_t)b * K;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int i = lo + 64 * h;
+                keep[h] = nzf[h] = false;
+                xn[h] = 0.0;
+                if (i < n_act) {
+                    const double an = T.an[i], ag = fabs(g[h]);
+                    keep[h] = c1 * ag + T.e[i] * c2 + Rq * an >= keep_min;
+                    kt += (c1 * ag + Rp * T.atn[i] >= 1.0) ? 1.0 : 0.0;
+                    const double xp = T.xp[i], gm = T.gm[i];
+                    const double zpt = xt[h] + beta * (xt[h] - xp);
+                    const double hh = (1.0 + beta) * g[h] - beta * gm;
+                    const double v = zpt + hh * invL;
+                    if (keep[h]) xn[h] = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
+                    if (!keep[h]) {      // screened: its coefficient is zero in both iterates
+                        const int j = T.la[i];
+                        xc[j] = 0.0;
+                        xo[j] = 0.0;
+                        mask[j] = 0;
+                    }
+                    nzf[h] = keep[h] && (xn[h] != 0.0);
+                    l1 += fabs(xn[h]);
+                    Xn += an * fabs(xn[h]);
+                }
+            }
+        }
+        // ---- compaction (positions keep their order) ----
+        int jj[H], lgp[H];
+        double ev[H], anv[H], atv[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int i = lo + 64 * h;
+            jj[h] = lgp[h] = 0;
+            ev[h] = anv[h] = atv[h] = 0.0;
+            if (keep[h]) {
+                jj[h] = T.la[i];
+                lgp[h] = T.lg[i];
+                ev[h] = T.e[i];
+                anv[h] = T.an[i];
+                atv[h] = T.atn[i];
+            }
+        }
+        wave_sync_lds();                  // every lane's reads of the state precede the writes
+        int wpos = 0, zpos = 0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const unsigned long long bk = __ballot(keep[h]);
+            const unsigned long long bz = __ballot(nzf[h]);
+            if (keep[h]) {
+                const int q = wpos + __popcll(bk & below);
+                T.la[q] = jj[h];
+                T.lg[q] = lgp[h];
+                T.xt[q] = xn[h];
+                T.xp[q] = xt[h];
+                T.gm[q] = g[h];
+                T.e[q] = ev[h];
+                T.an[q] = anv[h];
+                T.atn[q] = atv[h];
+            }
+            if (nzf[h]) {
+                const int q = zpos + __popcll(bz & below);
+                lj[q] = lgp[h];
+                lx[q] = xn[h];
+            }
+            wpos += __popcll(bk);
+            zpos += __popcll(bz);
+        }
+        wave_sync_lds();
+        kt = wave_sum(kt);
+        l1 = uni(wave_sum(l1));
+        Xn = uni(wave_sum(Xn));
+        wg_stamp(Pi, b, 3, *s_clk);
+        // ---- trace row and momentum (the last stage stays) ----
+        if (l == 0 && Pi->trace && C.iter < Pi->trace_cap) {
+            double* tr = Pi->trace + ((size_t)b * Pi->trace_cap + C.iter) * SL1_TRACE_FIELDS;
+            tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = wpos;
+            tr[4] = kt;
+            tr[5] = Gp; tr[6] = Gt; tr[7] = delta; tr[8] = Rp; tr[9] = gam_t;
+            tr[10] = C.l1; tr[11] = Pv; tr[12] = C.n_nz;
+        }
+        C.ksince += 1;
+        C.tau = tau_next;
+        C.iter += 1;
+        C.par = 1 - par;
+        C.n_act = wpos;
+        C.n_nz = zpos;
+        C.l1 = l1;
+        n_act = wpos;
+        n_nz = zpos;
+        X = Xn;
+    }
+    if (l == 0) *sCp = C;
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* __restrict__ P0, int max_it) {
@@ -957,12 +1320,15 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
     __shared__ double s_red[48];
     __shared__ double s_sum[4];
     __shared__ double s_kt[2];
+    __shared__ double s_yy;
     __shared__ int s_cnt[2];
     __shared__ int s_w[kWgWaves];
+    __shared__ int s_done;
     __shared__ long long s_clk;
 
     if (tid == 0) {
         sC = P0->ctrl[2 * b];
+        s_done = 0;
         s_clk = P0->wg_prof ? wall_clock64() : 0;
     }
     __syncthreads();
@@ -973,7 +1339,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
         const int N = P->N, par = uni(sC.par), n_act = uni(sC.n_act), n_nz = uni(sC.n_nz);
         const StageDesc& st = P->st[uni(sC.stage)];
         const bool bad = st.kind != kDense || uni(sC.stage) != P->n_stages - 1 || P->wo_tail < 0 ||
-                         P->wg_cap_nz < P->wg_cap_act || n_act > P->wg_cap_act || n_nz > P->wg_cap_nz;
+                         P->wg_cap_nz < P->wg_cap_act || n_act > P->wg_cap_act || n_nz > P->wg_cap_nz ||
+                         P->wg_cap_gram > 64 * 2 || (P->wg_cap_gram > 0 && P->wo_gram < 0);
         if (bad) {   // the host hands over only dense, small sets; anything else is refused
             if (tid == 0) {
                 Final F;
@@ -1004,7 +1371,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             T.la[i] = j;
             T.xt[i] = xc[j];
             T.xp[i] = xo[j];
-            T.gp[i] = gprev[j];
+            T.gm[i] = gprev[j];
             T.e[i] = st.eps[j];
             T.an[i] = P->atom_norm[j];
             T.atn[i] = st.at_norm[j];
@@ -1020,8 +1387,14 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
         __syncthreads();
     }
 
-    for (int it = 0; it < max_it; ++it) {
+    int it = 0;
+    bool gram = false;
+    for (; it < max_it; ++it) {
         const int par = uni(sC.par), n_nz = uni(sC.n_nz), n_act = uni(sC.n_act);
+        if (P0->wg_cap_gram > 0 && n_act <= P0->wg_cap_gram) {
+            gram = true;
+            break;
+        }
         // ---- forward product and residual ----
         {
             const SolveParams* P = phase_params(P0);
@@ -1109,7 +1482,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                     an = T.an[i];
                     atn = T.atn[i];
                     const double xp = T.xp[i];
-                    const double gp = T.gp[i];
+                    const double gp = T.gm[i];
                     const double ag = fabs(gt);
                     // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
                     const double mu = c1 * ag + e * c2 + Rp * an;
@@ -1138,7 +1511,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                     T.la[q] = j;
                     T.xt[q] = xn;        // x_{t+1}
                     T.xp[q] = xt;        // x_t
-                    T.gp[q] = gt;        // g_t
+                    T.gm[q] = gt;        // g_t
                     T.e[q] = e;
                     T.an[q] = an;
                     T.atn[q] = atn;
@@ -1183,12 +1556,23 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
         }
         __syncthreads();
     }
+    if (gram) {
+        {
+            const SolveParams* P = phase_params(P0);
+            tail_gram_build(P, b, P->st[uni(sC.stage)], smem, uni(sC.n_act), s_red, &s_yy);
+        }
+        if (tid < 64) tail_gram_loop<2>(P0, b, it, max_it, smem, &sC, &s_done, &s_clk, s_yy);
+        __syncthreads();
+        if (s_done) return;
+    }
     // the launch ends before the signal stops: state back to global memory
     {
         const SolveParams* P = phase_params(P0);
         const int par = uni(sC.par), n_act = uni(sC.n_act), n_nz = uni(sC.n_nz);
         const TailState T = tail_state(smem, P);
         const int* lj = (const int*)(smem + P->wo_lnj);
+        const int* ga = gram ? (const int*)((const double*)(smem + P->wo_gram) + (size_t)P->wg_cap_gram *
+                                            (P->wg_cap_gram + 1)) : nullptr;
         int* act = actbuf(P, b, 0);
         int* nzl = nzbuf(P, b, 0);
         double* xc = xbuf(P, b, par);
@@ -1199,9 +1583,9 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             act[i] = j;
             xc[j] = T.xt[i];
             xo[j] = T.xp[i];
-            gprev[j] = T.gp[i];
+            gprev[j] = T.gm[i];
         }
-        for (int i = tid; i < n_nz; i += kWgBlock) nzl[i] = lj[i];
+        for (int i = tid; i < n_nz; i += kWgBlock) nzl[i] = ga ? ga[lj[i]] : lj[i];
         if (tid == 0) P->ctrl[2 * b] = sC;
     }
 }

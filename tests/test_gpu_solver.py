@@ -273,14 +273,16 @@ def test_auto_engine_choice(sl1):
     assert m.last_solve_phases(1, q.N, q.K)[0] == "grid"
 
 
-def test_hybrid_hand_over_matches_grid(sl1):
+@pytest.mark.parametrize("gram", [True, False], ids=["gram", "columns"])
+def test_hybrid_hand_over_matches_grid(sl1, gram):
     # the full batched dictionary (N=1024, K=4096) on 12 signals: the grid kernels
-    # hand the tail to the whole-solve kernel; decisions and solutions agree
-    _say("hybrid hand-over, batched dictionary, 12 signals")
+    # hand the tail to the tail kernel (Gram or column mode); decisions and
+    # solutions agree
+    _say(f"hybrid hand-over, batched dictionary, 12 signals, gram={gram}")
     import paper_1812_06635_amd as m
     p = synth.config4(batch=12)
     g = _run(sl1, p, tol=1e-9, engine="grid")
-    h = _run(sl1, p, tol=1e-9, engine="hybrid", trace_cap=4000)
+    h = _run(sl1, p, tol=1e-9, engine="hybrid", trace_cap=4000, tail_gram=gram)
     assert m.last_solve_phases(p.batch, p.N, p.K)[0] == "hybrid"
     assert g["status"] == 0 and h["status"] == 0
     np.testing.assert_array_equal(g["stage"], h["stage"])
@@ -294,6 +296,53 @@ def test_hybrid_hand_over_matches_grid(sl1):
         assert np.all(tr[1:, 2] == tr[:-1, 3])                          # |A_t+1| carried over
     for b in (0, 7):
         _check_solution(p, h, b)
+
+
+def _bf16_exact(p):
+    # the column-scaled BF16 copy taken as the exact dictionary of its own problem
+    import dataclasses
+    st = dataclasses.replace(p.stages[1], eps=np.zeros(p.K), label="bf16 (exact)")
+    A = st.values()
+    return dataclasses.replace(p, A=A, stages=[st], atom_norm=np.linalg.norm(A, axis=0))
+
+
+TAIL_CASES = [
+    ("C3-small dense fp8/bf16/f32", lambda: synth.config3(N=256, K=1024, s=20, batch=4)),
+    ("C3 ragged N=2500 (N % 16 = 4)", lambda: synth.config3(N=2500, K=600, s=20, batch=2)),
+    ("column-scaled BF16 as the exact stage", lambda: _bf16_exact(synth.config3(N=256, K=1024, s=20, batch=3))),
+]
+
+
+@pytest.mark.parametrize("name,maker", TAIL_CASES, ids=[c[0] for c in TAIL_CASES])
+def test_tail_modes_match_grid(sl1, name, maker):
+    # dense last stages: the hybrid solve hands over at once and its tail kernel
+    # switches to the Gram form when |A_t| fits; the column mode and the grid
+    # engine solve the same problem with the same decisions
+    _say(f"tail modes vs grid: {name}")
+    import paper_1812_06635_amd as m
+    p = maker()
+    stages = None
+    g = _run(sl1, p, tol=1e-10, stages=stages, engine="grid")
+    runs = {}
+    for gram in (True, False):
+        runs[gram] = _run(sl1, p, tol=1e-10, stages=stages, engine="hybrid", trace_cap=20000, tail_gram=gram)
+        assert m.last_solve_phases(p.batch, p.N, p.K)[0] == "hybrid"
+    for gram, h in runs.items():
+        assert g["status"] == 0 and h["status"] == 0
+        np.testing.assert_array_equal(g["stage"], h["stage"])
+        assert np.all(np.abs(g["iters"] - h["iters"]) <= 3), (gram, g["iters"], h["iters"])
+        for b in range(p.batch):
+            rel = np.linalg.norm(g["x"][b] - h["x"][b]) / max(np.linalg.norm(g["x"][b]), 1e-300)
+            assert rel <= 1e-6, f"gram={gram} signal {b}: differs from grid by {rel:.2e}"
+            n = int(h["iters"][b])
+            tr = h["trace"][b][:n]
+            assert np.array_equal(tr[:, 0], np.arange(n))
+            assert np.all(tr[1:, 2] == tr[:-1, 3])
+            assert np.all(tr[:, 7] >= 0.0) and np.all(tr[:, 5] >= -1e-9 * tr[:, 11])
+            # the screened sets agree up to atoms decided within rounding of the threshold
+            assert np.sum(g["screened"][b] != h["screened"][b]) <= 2
+    for b in range(p.batch):
+        _check_solution(p, runs[True], b)
 
 
 def test_identical_signals_finishing_together(sl1):
