@@ -73,31 +73,43 @@ def timed(torch, fn, steps, warmup):
 UPD_BYTES_PER_ATOM = 76.0   # test/update per preserved atom: index, 7 FP64 gathers, x and index writes
 
 
-def kernel_work(p, trace, iters, t_split):
+def kernel_work(p, trace, iters, t_split, gram_cap=0):
     """Algorithmic work of each kernel over one solve, from the trace (rows
-    t < t_split ran in the grid kernels, the rest in the whole-solve kernel):
+    t < t_split ran in the grid kernels, the rest in the tail kernel):
       dense correlations  |A_t| N b bytes (b: bytes per stored element, + 4 B per
                           column scale); Kronecker correlations 2 R k2 n1 (n2 + k1)
                           flops (sum_r C_r^T P B_r);
       forward             ||x_t||_0 N b bytes on dense stages (gathered columns);
-      update              76 B per preserved atom."""
+      update              76 B per preserved atom in the grid kernels (the tail
+                          keeps the per-atom state in LDS);
+      tail, Gram form     rows with |A_t| <= gram_cap: the |A_t| columns read once
+                          to form G and A_t^T y, then no HBM traffic per iteration."""
     import numpy as np
     N = p.N
     w = dict(fwd_bytes=[0.0, 0.0], adj_bytes=[0.0, 0.0], adj_flops=[0.0, 0.0], upd_bytes=[0.0, 0.0],
-             dense_it=[0, 0], kron_it=[0, 0])
+             gram_bytes=0.0, gram_it=0, dense_it=[0, 0], kron_it=[0, 0])
     for b in range(trace.shape[0]):
         n = int(iters[b])
         rows = trace[b, :n]
         part = (np.arange(n) >= t_split).astype(int)
+        gram = (part == 1) & (rows[:, 2] <= gram_cap) if gram_cap > 0 else np.zeros(n, dtype=bool)
         for s_idx, st in enumerate(p.stages):
+            bpe = 0.0
+            if st.kind == "dense":
+                bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
+            on = rows[:, 1] == s_idx
+            g = on & gram
+            if g.any():
+                w["gram_bytes"] += N * bpe * float(rows[np.argmax(g), 2])
+                w["gram_it"] += int(g.sum())
             for ph in (0, 1):
-                m = (rows[:, 1] == s_idx) & (part == ph)
+                m = on & (part == ph) & ~gram
                 cnt = int(m.sum())
                 if not cnt:
                     continue
-                w["upd_bytes"][ph] += UPD_BYTES_PER_ATOM * float(rows[m, 2].sum())
+                if ph == 0:
+                    w["upd_bytes"][ph] += UPD_BYTES_PER_ATOM * float(rows[m, 2].sum())
                 if st.kind == "dense":
-                    bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
                     w["adj_bytes"][ph] += N * bpe * float(rows[m, 2].sum())
                     w["fwd_bytes"][ph] += N * bpe * float(rows[m, 12].sum())
                     w["dense_it"][ph] += cnt
@@ -108,7 +120,7 @@ def kernel_work(p, trace, iters, t_split):
     return w
 
 
-def roofline_entries(prof, phases, work):
+def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
     """Roofline of every kernel of the solve: achieved = algorithmic work /
     measured time (HIP events around each launch), against the MI355X peak of
     its bound."""
@@ -133,8 +145,8 @@ def roofline_entries(prof, phases, work):
     add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma")
     add("k_upd", *prof["upd"], work["upd_bytes"][0], "hbm")
     if phases.get("wg_launches", 0) > 0:
-        add("k_solve_wg", phases["wg_ms"], phases["wg_launches"],
-            work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1], "hbm")
+        add(tail_kernel, phases["wg_ms"], phases["wg_launches"],
+            work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1] + work["gram_bytes"], "hbm")
     out.sort(key=lambda e: -e["total_ms"])
     return out
 
@@ -173,21 +185,66 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
     trace = outp["trace"].cpu().numpy()
     iters = outp["iters"].cpu().numpy()
     t_split = prof["fwd"][1] if phases.get("wg_launches", 0) > 0 else 10 ** 9
-    work = kernel_work(p, trace, iters, t_split)
+    work = kernel_work(p, trace, iters, t_split, phases.get("gram_cap", 0))
     res = dict(
         ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p, engine=engine, engine_plain=engine_p,
         time_to_gap_ms_device=ttg_dev, max_gap_method=float(gap_m.max()), max_gap_plain=float(gap_p.max()),
         stage_final=sorted(set(out_m["stage"].cpu().numpy().tolist())), rc_measured=rc_meas,
         rc_model=[s.rc_theory for s in p.stages], kernel_ms=prof, wg_phases=phases, grid_iterations=t_split,
-        roofline_kernels=roofline_entries(prof, phases, work),
+        roofline_kernels=roofline_entries(prof, phases, work,
+                                          "k_solve_tail" if engine == "hybrid" else "k_solve_wg"),
+        gram_iterations=work["gram_it"],
         x=out_m["x"].cpu().numpy(), screened=out_m["screened"].cpu().numpy(),
     )
     return res
 
 
+# sources whose change voids a recorded HBM-traffic figure of a kernel
+TRAFFIC_SOURCES = {
+    "k_adj_dense": ["paper_1812_06635_amd/csrc/sl1_kernels.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
+                    "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"],
+}
+
+
+def sources_sha256(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary under profiles/ (a 'traffic-record:' line), or None when there is
+    none or the kernel's sources changed since the counters were taken."""
+    if kernel not in TRAFFIC_SOURCES:
+        return None
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    want = sources_sha256(kernel)
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if kv.get("kernel") == kernel and kv.get("sources_sha256") == want:
+                    return float(kv["bytes_per_launch"])
+    return None
+
+
 def roofline(res):
-    """The kernel with the largest share of the solve's device time."""
-    return dict(res["roofline_kernels"][0])
+    """The kernel with the largest share of the solve's device time, with its
+    recorded HBM traffic per launch when the counters match the current code."""
+    r = dict(res["roofline_kernels"][0])
+    if r["bound"] == "hbm":
+        r["traffic"] = recorded_traffic(r["kernel"])
+    return r
 
 
 def parity_sample(np, p, res, n=2):
@@ -286,6 +343,8 @@ def main():
         "engine": res["engine"],
         "kernel_ms": res["kernel_ms"],
         "whole_solve_phases_ms": res["wg_phases"],
+        "grid_iterations": res["grid_iterations"],
+        "tail_gram_signal_iterations": res["gram_iterations"],
         "roofline": roofline(res),
         "roofline_kernels": res["roofline_kernels"],
     }

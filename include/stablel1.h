@@ -263,11 +263,13 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
  * dense correlations, Kronecker correlations (hybrid tail: Gram-mode
  * correlations and scalars) and test/update/compaction,
  * phase_ms[4] the elapsed milliseconds of the whole-solve launches and
- * *wg_launches (may be NULL) their number.  sl1_last_solve_profile covers the
- * grid kernels.
+ * *wg_launches (may be NULL) their number; *gram_cap (may be NULL) the Gram
+ * capacity (atoms) of the hybrid tail, 0 when no tail ran or it had no Gram mode:
+ * a signal's tail iterations with |A_t| <= *gram_cap ran in the Gram form.
+ * sl1_last_solve_profile covers the grid kernels.
  */
 int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms,
-                          long long* wg_launches);
+                          long long* wg_launches, int32_t* gram_cap);
 
 const char* sl1_status_str(int status);
 const char* sl1_version(void);

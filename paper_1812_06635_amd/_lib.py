@@ -51,7 +51,7 @@ SIGNATURES = [
     ("sl1_last_solve_clock", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_d)]),
     ("sl1_last_solve_profile", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_longlong)]),
     ("sl1_last_solve_phases", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_d),
-                                      ctypes.POINTER(ctypes.c_longlong)]),
+                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_i32)]),
     ("sl1_status_str", ctypes.c_char_p, [c_i32]),
     ("sl1_version", ctypes.c_char_p, []),
 ]

@@ -225,17 +225,20 @@ def last_solve_profile(batch, N, K):
 def last_solve_phases(batch, N, K):
     """(engine name, {phase: ms}) of the last solve of this shape.  With
     profile=True the whole-solve part fills the phase times (workgroup ms summed
-    over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches"."""
+    over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches";
+    "gram_cap" is the Gram capacity of a hybrid tail (0: none)."""
     eng = L.c_i32()
     ph = (L.c_d * 5)()
     n = ctypes.c_longlong()
-    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph, ctypes.byref(n)),
+    gcap = L.c_i32()
+    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph, ctypes.byref(n), ctypes.byref(gcap)),
             "sl1_last_solve_phases")
     name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg", L.ENGINE_HYBRID: "hybrid"}.get(eng.value, "none")
     keys = ("fwd", "adj_dense", "gram", "upd", "wg_ms") if name == "hybrid" else \
         ("fwd", "adj_dense", "adj_kron", "upd", "wg_ms")
     out = dict(zip(keys, list(ph)))
     out["wg_launches"] = n.value
+    out["gram_cap"] = gcap.value
     return name, out
 
 

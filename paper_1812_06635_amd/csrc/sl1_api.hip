@@ -102,6 +102,7 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
     hipGraphExec_t graph = nullptr;
+    int last_gram_cap = 0;    // Gram capacity of the last hybrid tail (0: none)
     int graph_chunk = 0;
     double prof_ms[4] = {0, 0, 0, 0};       // grid kernels: forward, dense / Kronecker correlations, update
     long long prof_n[4] = {0, 0, 0, 0};
@@ -792,6 +793,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         if (st != SL1_OK) return st;
     }
     w->last_engine = use_wg ? SL1_ENGINE_WG : SL1_ENGINE_GRID;
+    w->last_gram_cap = 0;
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
@@ -897,6 +899,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
                 HIP_TRY(launch_one(0, 0, w->dP, cfg, w->stream));
                 HIP_TRY(launch_to_wg(w->dP, (int)batch, w->stream));
                 w->last_engine = SL1_ENGINE_HYBRID;
+                w->last_gram_cap = p.wg_cap_gram;
                 if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
                 st = run_wg(w, p, o, batch, tlds, prof, dev, launched, true);
                 if (st != SL1_OK) return st;
@@ -1084,7 +1087,7 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
 }
 
 int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms,
-                          long long* wg_launches) {
+                          long long* wg_launches, int32_t* gram_cap) {
     if (!engine) return SL1_EINVAL;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
@@ -1098,6 +1101,7 @@ int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, 
         phase_ms[kWgPhases] = w.wg_ms;
     }
     if (wg_launches) *wg_launches = w.wg_n;
+    if (gram_cap) *gram_cap = w.last_gram_cap;
     return SL1_OK;
 }
 
