@@ -22,6 +22,12 @@ Readings of points the paper leaves open (each stated where it is used):
   * K_t uses the conventional sphere test on the approximate atoms with the
     same sphere (theta'_t, R'_t).
   * The stop test is the conventional duality gap once A~ = A (Section IV).
+  * Options beside FISTA + stable GAP Safe (Table II's other combinations):
+    ISTA (the update of Section I-B, no momentum), and the stable Dynamic Safe
+    sphere B(y/lambda, ||theta'_t - y/lambda||) (Table I, fourth row) tested
+    with a_j^T y given: the product with the exact A is formed once, as the
+    footnote to Table I allows, so the test needs no eps term.  Its look-ahead
+    count K_t uses the same sphere with ||a~_j|| in place of ||a_j||.
 """
 from __future__ import annotations
 
@@ -70,6 +76,12 @@ def stable_gap_radius(gap_tilde_A, res_norm, E, x_l1, lam):
     return np.sqrt(2.0 * max(gap_tilde_A, 0.0) + 2.0 * delta) / lam, delta
 
 
+def dynamic_radius(theta, y, lam):
+    """R = ||theta - y/lambda||_2: radius of the (stable) Dynamic Safe sphere
+    centred at y/lambda (Table I, third and fourth rows)."""
+    return float(np.linalg.norm(theta - y / lam))
+
+
 def stable_lambda_max(At, eps, y):
     """lambda'_max = max_j (|a~_j^T y| + eps_j ||y||_2) >= lambda_max (Section III-C,
     stable static sphere)."""
@@ -98,7 +110,7 @@ class TraceRow:
     G_stable: float        # G(x_t, theta'_t | A~)
     G_conv: float          # G(x_t, theta~_t | A~)
     delta: float
-    R_stable: float
+    R_stable: float        # radius of the rule's sphere (R' of GAP, or ||theta' - y/lambda||)
     gamma: float
     x_l1: float
     P: float
@@ -117,8 +129,9 @@ class Result:
 
 
 def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12,
-            eps_scale=1.0, keep_trace=True):
-    """Algorithm 1 (FastL1) with FISTA and the stable GAP Safe test.
+            eps_scale=1.0, keep_trace=True, update="fista", rule="gap", radius_scale=1.0):
+    """Algorithm 1 (FastL1) with FISTA (or ISTA) and the stable GAP Safe (or
+    stable Dynamic Safe) test.
 
     stages     list of (At, eps, L): At is the (N, K) FP64 matrix of the i-th
                approximation (the last one is A, with eps = 0), eps its per-atom
@@ -127,7 +140,12 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     rc         relative complexity RC(A~^i) of each stage (Section IV-B).
     eps_scale  multiplies every eps (a value below 1 plants an unsafe bound; the
                tests use it to show that the safety check can fail).
+    update     "fista" or "ista" (Section I-B: x_{t+1} = ST(x_t + A~^T rho~_t / L)).
+    rule       "gap" (stable GAP Safe) or "dst" (stable Dynamic Safe).
+    radius_scale  multiplies the sphere radius (below 1 plants an unsafe test).
     """
+    if update not in ("fista", "ista") or rule not in ("gap", "dst"):
+        raise ValueError("update must be fista|ista and rule gap|dst")
     I = len(stages) - 1
     N, K = stages[0][0].shape
     y = np.asarray(y, dtype=np.float64)
@@ -142,6 +160,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     trace = []
     At, eps, L = stages[0]
     at_norms = [np.linalg.norm(s[0], axis=0) for s in stages]
+    # stable Dynamic Safe: a_j^T y with the exact dictionary, formed once
+    aty = stages[I][0].T @ y if rule == "dst" else None
     res = None
     for t in range(max_iter + 1):
         At, eps, L = stages[i]
@@ -166,6 +186,11 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         G_conv = P - dual_value_along(s_conv, lam, y_rho, r_sq, y_sq)
         E = float(np.max(eps[act], initial=0.0))
         R_stable, delta = stable_gap_radius(G_stable, r_norm, E, x_l1, lam)
+        if rule == "dst":
+            R_test = dynamic_radius(s_stable * rho, y, lam)       # ||theta'_t - y/lambda||
+        else:
+            R_test = float(R_stable)
+        R_test *= radius_scale
         gamma = G_conv / G_stable if G_stable > 0 else 1.0
         # ---- stopping criterion: conventional gap once A~ = A (Section IV)
         if i == I and G_conv < tol:
@@ -176,8 +201,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
             res = Result(x=x.copy(), gap=G_conv, gap_cert=G_stable + delta, screened=~active,
                          iters=t, stage=i, converged=False, trace=trace)
             break
-        # ---- update of the preserved coefficients (FISTA step)
-        if k_since == 0:
+        # ---- update of the preserved coefficients (FISTA or ISTA step)
+        if k_since == 0 or update == "ista":
             beta = 0.0
         else:
             tau_next = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * tau * tau))
@@ -188,18 +213,24 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         h = (1.0 + beta) * g - beta * g_prev
         x_new = np.zeros(K)
         x_new[act] = soft_threshold(z[act] + h[act] / L, lam / L)
-        # ---- dynamic screening with the stable GAP Safe sphere (Table I)
-        c_norm = abs(s_stable) * r_norm                       # ||theta'_t||_2
-        mu = stable_sphere_test(s_stable * g, eps, c_norm, R_stable, atom_norm)
+        # ---- dynamic screening with the stable sphere of the rule (Table I)
+        if rule == "dst":
+            mu = sphere_test(aty / lam, R_test, atom_norm)     # centre y/lambda, a^T y given
+        else:
+            c_norm = abs(s_stable) * r_norm                   # ||theta'_t||_2
+            mu = stable_sphere_test(s_stable * g, eps, c_norm, R_test, atom_norm)
         keep = active & (mu >= 1.0 - margin)
         # ---- look-ahead estimate K_t (Section IV-C)
-        mu_conv = sphere_test(s_stable * g, R_stable, at_norms[i])
+        if rule == "dst":
+            mu_conv = sphere_test(aty / lam, R_test, at_norms[i])
+        else:
+            mu_conv = sphere_test(s_stable * g, R_test, at_norms[i])
         K_t = int(np.count_nonzero(active & (mu_conv >= 1.0)))
         x_new[~keep] = 0.0
         x[~keep] = 0.0
         if keep_trace:
             trace.append(TraceRow(t=t, stage=i, n_active=int(act.size), n_keep=int(keep.sum()), K_t=K_t,
-                                  G_stable=G_stable, G_conv=G_conv, delta=delta, R_stable=float(R_stable),
+                                  G_stable=G_stable, G_conv=G_conv, delta=delta, R_stable=float(R_test),
                                   gamma=gamma, x_l1=x_l1, P=P))
         # ---- switching criterion (Algorithm 2)
         i_next = switch_dictionary(i, I, gamma, Gamma, K_t, rc[i], K)

@@ -233,3 +233,87 @@ def test_stage_error_bounds_are_exact_column_errors():
     for st in q.stages[:-1]:
         err = np.linalg.norm(q.A - st.values(), axis=0)
         assert np.all(st.eps >= err)
+
+
+# ---------------------------------------------------------------------------
+# ISTA and the stable Dynamic Safe sphere (Table I, fourth row; Table II)
+# ---------------------------------------------------------------------------
+def test_dual_solution_is_the_feasible_point_nearest_y_over_lambda():
+    # theta* = (y - A x*)/lambda is the projection of y/lambda onto the dual
+    # feasible set (Section II), so every feasible theta is at least as far from
+    # y/lambda: this is what makes B(y/lambda, ||theta - y/lambda||) safe.
+    rng = np.random.default_rng(5)
+    for real, frac in ((0, 0.5), (1, 0.2), (2, 0.8)):
+        p = synth.config1(realization=real, lam_frac=frac)
+        A, y, lam = p.A, p.Y[0], float(p.lam[0])
+        sol = ol.solve(A, y, lam, L=p.stages[-1].L)
+        th = (y - A @ sol["x"]) / lam
+        assert np.max(np.abs(A.T @ th)) <= 1 + 1e-9
+        d_star = np.linalg.norm(th - y / lam)
+        for _ in range(200):
+            z = rng.standard_normal(y.shape) + rng.uniform(0, 3) * y
+            t = z / max(1.0, np.max(np.abs(A.T @ z)))      # feasible: ||A^T t||_inf <= 1
+            assert d_star <= np.linalg.norm(t - y / lam) * (1 + 1e-12)
+
+
+VARIANTS = [("fista", "dst"), ("ista", "gap"), ("ista", "dst")]
+
+
+@pytest.mark.parametrize("update,rule", VARIANTS, ids=[f"{u}-{r}" for u, r in VARIANTS])
+@pytest.mark.parametrize("maker", [
+    lambda: synth.config1(),
+    lambda: synth.config1(realization=1, lam_frac=0.2),
+    lambda: synth.config1(realization=2, lam_frac=0.8),
+    lambda: synth.config3(N=256, K=1024),
+])
+def test_method_variants_are_safe_and_reach_the_lasso_solution(maker, update, rule):
+    p = maker()
+    sol, res = _check_method(p, update=update, rule=rule)
+    assert res.converged
+    assert not np.any(res.screened & (sol["x"] != 0))
+    P = ol.primal(p.A, p.Y[0], float(p.lam[0]), res.x)
+    assert (P - sol["P"]) / sol["P"] <= 1e-7
+    assert np.linalg.norm(res.x - sol["x"]) <= 1e-4 * np.linalg.norm(sol["x"])
+    na = [r.n_active for r in res.trace]
+    assert all(a >= b for a, b in zip(na, na[1:]))
+    for r in res.trace:
+        assert r.K_t <= r.n_active and -1e-12 <= r.gamma <= 1 + 1e-9
+    if rule == "dst":
+        # every traced radius covers the dual solution (centre y/lambda)
+        y, lam = p.Y[0], float(p.lam[0])
+        d_star = np.linalg.norm((y - p.A @ sol["x"]) / lam - y / lam)
+        assert all(r.R_stable >= d_star * (1 - 1e-9) for r in res.trace)
+
+
+def test_ista_objective_decreases_on_a_fixed_preserved_set():
+    # ISTA is a descent method for the problem restricted to the preserved set: on
+    # the exact stage, between iterations that screen nothing, P(x_t) never rises.
+    p = synth.config1()
+    _, r = _check_method(p, update="ista", rule="gap")
+    I = len(p.stages) - 1
+    rows = r.trace
+    for a, b in zip(rows, rows[1:]):
+        if a.stage == I and b.stage == I and a.n_keep == a.n_active:
+            assert b.P <= a.P * (1 + 1e-13)
+
+
+def test_dynamic_safe_screens_less_than_gap_safe_at_the_end():
+    # Table I: the GAP sphere shrinks to theta* while the Dynamic Safe radius stays
+    # at least ||theta* - y/lambda||, so at convergence GAP preserves fewer atoms.
+    p = synth.config1(lam_frac=0.5)
+    _, rg = _check_method(p)
+    _, rd = _check_method(p, rule="dst")
+    assert rg.trace[-1].n_keep <= rd.trace[-1].n_keep
+
+
+def test_planted_unsafe_dynamic_radius_is_caught():
+    # A radius scaled to zero (a mistake planted in the oracle) must break safety
+    # or exactness on at least one case.
+    caught = 0
+    for real, frac in itertools.product(range(3), (0.2, 0.5)):
+        p = synth.config1(realization=real, lam_frac=frac)
+        sol, res = _check_method(p, rule="dst", radius_scale=0.0)
+        unsafe = np.any(res.screened & (sol["x"] != 0))
+        wrong = np.linalg.norm(res.x - sol["x"]) > 1e-4 * np.linalg.norm(sol["x"])
+        caught += bool(unsafe or wrong)
+    assert caught > 0
