@@ -132,6 +132,13 @@ typedef struct {
                                      stage is not dense) */
 #define SL1_FLAG_TAIL_COLUMNS 32  /* the tail kernel forms every iteration's products from the stored
                                      columns (no Gram mode) */
+#define SL1_FLAG_ISTA 64          /* ISTA update x_{t+1} = ST(x_t + A~^T rho~_t / L) (Section I-B)
+                                     instead of FISTA */
+#define SL1_FLAG_RULE_DST 128     /* stable Dynamic Safe test (Table I, fourth row) instead of stable
+                                     GAP Safe: sphere B(y/lambda, ||theta'_t - y/lambda||) tested with
+                                     a_j^T y formed once on the exact dictionary (footnote to Table I;
+                                     the solve first runs one correlation pass of seq[n_stages-1] over
+                                     all atoms, which must be dense: SL1_ELIMIT otherwise) */
 
 /* Engines (at most one SL1_FLAG_ENGINE_* flag; none = automatic):
  *   SL1_ENGINE_GRID    three persistent launches per iteration covering every live

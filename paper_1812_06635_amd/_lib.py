@@ -20,6 +20,8 @@ FLAG_ENGINE_GRID = 4
 FLAG_ENGINE_WG = 8
 FLAG_ENGINE_HYBRID = 16
 FLAG_TAIL_COLUMNS = 32
+FLAG_ISTA = 64
+FLAG_RULE_DST = 128
 ENGINE_GRID, ENGINE_WG, ENGINE_HYBRID = 1, 2, 3
 
 c_dict = ctypes.c_void_p

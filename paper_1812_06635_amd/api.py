@@ -117,16 +117,21 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
-          trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True):
+          trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
+          update="fista", rule="gap"):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
     signal is on the last, dense, stage with a small preserved set); tail_gram:
-    the tail iterates on G = A_t^T A_t once |A_t| fits (else it streams columns).
+    the tail iterates on G = A_t^T A_t once |A_t| fits (else it streams columns);
+    update: "fista" or "ista"; rule: "gap" (stable GAP Safe) or "dst" (stable
+    Dynamic Safe, Table I).
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
         raise ValueError(f"engine must be one of {sorted(_ENGINES)}")
+    if update not in ("fista", "ista") or rule not in ("gap", "dst"):
+        raise ValueError("update must be 'fista' or 'ista', rule 'gap' or 'dst'")
     if y.dtype not in (torch.float64, torch.float32):
         raise TypeError("y must be float32 or float64")
     _dev(y, None, "y")
@@ -147,7 +152,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.max_iter, opts.chunk = max_iter, chunk
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
     opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
-        (0 if tail_gram else L.FLAG_TAIL_COLUMNS)
+        (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \
+        (L.FLAG_RULE_DST if rule == "dst" else 0)
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)

@@ -24,6 +24,7 @@ hipError_t launch_finalize(const SolveParams*, const LaunchCfg&, double*, double
 hipError_t launch_lambda_out(const SolveParams*, int, double*, int32_t*, hipStream_t);
 hipError_t launch_time_out(const SolveParams*, int, long long*, hipStream_t);
 hipError_t launch_adjoint_out(const SolveParams*, int, int, int, double*, double*, hipStream_t);
+hipError_t launch_ysq(const SolveParams*, int, double*, hipStream_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
@@ -103,6 +104,8 @@ struct Workspace {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
     hipGraphExec_t graph = nullptr;
     int last_gram_cap = 0;    // Gram capacity of the last hybrid tail (0: none)
+    double* d_cy = nullptr;   // stable Dynamic Safe: [batch][K] a^T y on the exact dictionary (lazy)
+    double* d_yy = nullptr;   // [batch] ||y||^2
     int graph_chunk = 0;
     double prof_ms[4] = {0, 0, 0, 0};       // grid kernels: forward, dense / Kronecker correlations, update
     long long prof_n[4] = {0, 0, 0, 0};
@@ -117,6 +120,8 @@ struct Workspace {
     ~Workspace() {
         if (graph) (void)hipGraphExecDestroy(graph);
         if (mem) (void)hipFree(mem);
+        if (d_cy) (void)hipFree(d_cy);
+        if (d_yy) (void)hipFree(d_yy);
         if (hP) (void)hipHostFree(hP);
         if (h_active) (void)hipHostFree(h_active);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -338,7 +343,7 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act, bool gram) {
         p.wo_y = put(N * 8);
         const size_t colbuf = off;
         const size_t lists = a16((size_t)cap * 4) + a16((size_t)cap * 8) + a16((size_t)cap * 4) +
-                             a16((size_t)cap * (7 * 8 + 4));
+                             a16((size_t)cap * (8 * 8 + 4));
         auto gbytes = [&](size_t g) { return a16(g * g * 8) + a16(g * 8) + a16(g * 4); };
         if (gram) {
             const size_t target = (p.batch > 256 && colbuf + lists <= two_per_cu) ? two_per_cu : lim;
@@ -355,7 +360,7 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act, bool gram) {
         p.wo_lnj = put((size_t)cap * 4);
         p.wo_lnx = put((size_t)cap * 8);
         p.wo_lact = put((size_t)cap * 4);
-        p.wo_tail = put((size_t)cap * (7 * 8 + 4));
+        p.wo_tail = put((size_t)cap * (8 * 8 + 4));
         return off <= lim ? off : 0;
     }
     p.wo_tail = -1;
@@ -721,6 +726,57 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     return SL1_OK;
 }
 
+// Stable Dynamic Safe set-up (the caller holds w->mu): a_j^T y with the exact
+// dictionary for every atom and signal -- the product the footnote to Table I
+// allows to form once -- and ||y||^2, both in FP64 into the workspace.  Ends with
+// the library stream synchronised, so the pinned parameter block may be rewritten.
+int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtype, hipStream_t us) {
+    sl1_dict seq[1] = {d};
+    double L = 1.0;
+    SolveParams tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    int st = prepare(seq, 1, &L, nullptr, y_dtype, tmp);
+    if (st != SL1_OK) return st;
+    if (!w->d_cy) {
+        if (hipMalloc(&w->d_cy, (size_t)batch * tmp.K * sizeof(double)) != hipSuccess) return SL1_ENOMEM;
+        if (hipMalloc(&w->d_yy, (size_t)batch * sizeof(double)) != hipSuccess) return SL1_ENOMEM;
+    }
+    SolveParams& p = *w->hP;
+    std::memcpy(p.st, tmp.st, sizeof(tmp.st));
+    p.n_stages = 1;
+    p.N = tmp.N;
+    p.K = tmp.K;
+    p.batch = (int)batch;
+    p.y_f64 = tmp.y_f64;
+    p.n1_max = tmp.n1_max;
+    p.max_iter = 0;
+    p.trace = nullptr;
+    p.trace_cap = 0;
+    p.lambda_only = 1;
+    p.ista = p.rule = 0;
+    p.cy = p.yy = nullptr;
+    p.wg_prof = nullptr;
+    p.Gamma = 0.5;
+    p.tol = 0.0;
+    p.margin = 0.0;
+    p.atom_norm = d->at_norm;
+    p.y = y;
+    p.lam = nullptr;
+    LaunchCfg cfg = launch_cfg(*w, p);
+    st = check_lds(cfg);
+    if (st != SL1_OK) return st;
+    HIP_TRY(hipEventRecord(w->ev_in, us));
+    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+    HIP_TRY(launch_init(w->dP, cfg, w->stream));
+    HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));
+    HIP_TRY(launch_adjoint_out(w->dP, (int)batch, tmp.K, tmp.N, w->d_cy, nullptr, w->stream));
+    HIP_TRY(launch_ysq(w->dP, (int)batch, w->d_yy, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return SL1_OK;
+}
+
 int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc, const double* atom_norm,
               int64_t batch, const void* y, const double* lambda, const sl1_opts* opt, double* x, double* gap,
               double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage, void* stream) {
@@ -743,6 +799,13 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
     if (st != SL1_OK) return st;
     std::lock_guard<std::mutex> lk(w->mu);
+    const bool dst = (o.flags & SL1_FLAG_RULE_DST) != 0;
+    if (dst) {
+        // a^T y is formed with the exact dictionary's dense correlation kernel
+        if (seq[n_stages - 1]->kind != kDense) return SL1_ELIMIT;
+        st = dst_setup(w, seq[n_stages - 1], batch, y, o.y_dtype, (hipStream_t)stream);
+        if (st != SL1_OK) return st;
+    }
     SolveParams& p = *w->hP;
     std::memcpy(p.st, tmp.st, sizeof(tmp.st));
     p.n_stages = tmp.n_stages;
@@ -755,6 +818,10 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.trace = o.trace;
     p.trace_cap = o.trace ? o.trace_cap : 0;
     p.lambda_only = 0;
+    p.ista = (o.flags & SL1_FLAG_ISTA) ? 1 : 0;
+    p.rule = dst ? 1 : 0;
+    p.cy = dst ? w->d_cy : nullptr;
+    p.yy = dst ? w->d_yy : nullptr;
     p.Gamma = o.Gamma;
     p.tol = o.tol;
     p.margin = o.margin;
@@ -939,6 +1006,8 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.trace = nullptr;
     p.trace_cap = 0;
     p.lambda_only = 1;
+    p.ista = p.rule = 0;
+    p.cy = p.yy = nullptr;
     p.wg_prof = nullptr;
     p.Gamma = 0.5;
     p.tol = 0.0;
@@ -1019,6 +1088,8 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
         p.trace = nullptr;
         p.trace_cap = 0;
         p.lambda_only = 1;
+        p.ista = p.rule = 0;
+        p.cy = p.yy = nullptr;
         p.wg_prof = nullptr;
         p.tol = 0.0;
         p.margin = 0.0;

@@ -307,8 +307,15 @@ __device__ __forceinline__ void dense_dots(const StageDesc& st, int N, const int
 }
 
 // FP64 scalar block of iteration t from the residual sums and the maxima over A_t
+// Rounding slack of an FP64 quantity formed from N-term sums: gamma_n with
+// n = 2 (N + 8) (the dot-product bound n u / (1 - n u), u = 2^-53, doubled).
+__device__ __forceinline__ double fp64_slack(int N) {
+    const double nu = 2.0 * (double)(N + 8) * 0x1p-53;
+    return nu / (1.0 - nu);
+}
+
 __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control& C, double r2, double zz, double yz,
-                                             double mp, double mt, double E, Scalars& S) {
+                                             double mp, double mt, double E, double yy, Scalars& S) {
     const double lam = C.lam, l1 = C.l1;
     const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;     // projection of y/lam on z
     const double sp = clip_scale(s0, mp);                  // stable dual point theta' (Lemma 2)
@@ -325,7 +332,16 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     S.gamma = Gp > 0.0 ? Gt / Gp : 1.0;
     S.c1 = fabs(sp);
     S.c2 = fabs(sp) * sqrt(zz);
-    if (C.ksince == 0) {
+    // stable Dynamic Safe sphere B(y/lambda, ||theta' - y/lambda||) (Table I): the
+    // squared radius s'^2 ||z||^2 - 2 s' y^T z / lambda + ||y||^2 / lambda^2, widened by
+    // the FP64 rounding of its sums, gamma (|s'| ||z|| + ||y|| / lambda)^2
+    S.ny = sqrt(yy);
+    {
+        const double q = sp * sp * zz - 2.0 * sp * yz / lam + yy / (lam * lam);
+        const double a = fabs(sp) * sqrt(zz) + S.ny / lam;
+        S.Rd = sqrt(fmax(q, 0.0) + fp64_slack(P->N) * a * a);
+    }
+    if (C.ksince == 0 || P->ista) {      // ISTA: no momentum (Section I-B)
         S.beta = 0.0;
         S.tau_next = C.tau;
     } else {
@@ -337,6 +353,24 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     S.conv = (on_exact && Gt < P->tol) ? 1 : (C.iter >= P->max_iter ? 2 : 0);
     S.pad0 = 0;
     S.tconv = 0;
+}
+
+// Sphere test of one preserved atom (Table I) and its look-ahead flag (Section IV-C):
+//   stable GAP Safe     |a~^T theta'| + eps ||theta'|| + R' ||a||     (rule 0)
+//   stable Dynamic Safe |a^T y| / lambda + ||theta' - y/lambda|| ||a|| (rule 1), with
+//                       a^T y formed once on the exact dictionary and widened by its
+//                       rounding allowance eI ||y||
+// ag = |a~^T z|, Rg = the GAP radius to use, acy = |a^T y|, eI the exact stage's eps.
+__device__ __forceinline__ bool atom_test(int rule, const Scalars& S, double invlam, double Rg, double ag, double e,
+                                          double an, double atn, double acy, double eI, double keep_min,
+                                          double& kt) {
+    if (rule) {
+        const double c = acy * invlam;
+        kt = (c + S.Rd * atn >= 1.0) ? 1.0 : 0.0;
+        return c + eI * S.ny * invlam + S.Rd * an >= keep_min;
+    }
+    kt = (S.c1 * ag + S.Rp * atn >= 1.0) ? 1.0 : 0.0;
+    return S.c1 * ag + e * S.c2 + Rg * an >= keep_min;
 }
 
 }  // namespace sl1

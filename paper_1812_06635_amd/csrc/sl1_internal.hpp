@@ -60,6 +60,7 @@ struct Scalars {
     double P, Gp, Gt, delta, Rp, gamma;
     double c1, c2;                    // |s'| and |s'| ||z||
     double beta, tau_next;
+    double Rd, ny;                    // stable Dynamic Safe radius ||theta' - y/lambda|| (bounded), ||y||
     int conv, pad0;                   // 1 converged on A, 2 iteration cap
     long long tconv;
 };
@@ -74,11 +75,14 @@ struct Final {
 struct SolveParams {
     int n_stages, N, K, batch;
     int max_iter, trace_cap, y_f64, lambda_only;
+    int ista, rule;           // update: 0 FISTA, 1 ISTA; test: 0 stable GAP Safe, 1 stable Dynamic Safe
     double Gamma, tol, margin;
     StageDesc st[SL1_MAX_STAGES];
     const double* atom_norm;
     const void* y;            // batch x N, FP32 or FP64 (y_f64)
     const double* lam;        // batch
+    const double* cy;         // stable Dynamic Safe: [batch][K] a_j^T y with the exact dictionary
+    const double* yy;         // [batch] ||y||^2 (FP64)
     double* trace;
     // workspace (per signal b)
     Control* ctrl;            // [batch][2]
@@ -108,7 +112,7 @@ struct SolveParams {
     // z in FP64 and FP32, y, the current stage's Kronecker factors, the scratch
     // (staging, cross-wave sums, Kronecker intermediate), the nonzero list (index
     // and value) and the preserved list, with the two list capacities (entries);
-    // the tail kernel's per-position state of the preserved set (7 FP64 arrays
+    // the tail kernel's per-position state of the preserved set (8 FP64 arrays
     // and one int array of wg_cap_act entries) and its Gram region (G, c and the
     // atom of each row, wg_cap_gram rows; 0: columns only); optional per-signal
     // phase clocks [batch][kWgPhases] (wall-clock ticks)

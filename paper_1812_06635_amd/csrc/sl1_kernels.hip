@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                             double* tr = P->trace + ((size_t)b * P->trace_cap + Cp.iter) * SL1_TRACE_FIELDS;
                             tr[0] = Cp.iter; tr[1] = Cp.stage; tr[2] = Cp.n_act; tr[3] = C.n_act;
                             tr[4] = kt;
-                            tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = S.Rp; tr[9] = S.gamma;
+                            tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = P->rule ? S.Rd : S.Rp; tr[9] = S.gamma;
                             tr[10] = Cp.l1; tr[11] = S.P; tr[12] = Cp.n_nz;
                         }
                     }
@@ -927,7 +927,7 @@ __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scal
     block_max<3>(mx, s_red);
     double r2, zz, yz;
     reduce_res(P, b, s_red, r2, zz, yz);
-    scalars_from(P, C, r2, zz, yz, mx[0], mx[1], mx[2], S);
+    scalars_from(P, C, r2, zz, yz, mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -997,13 +997,14 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             const double xp = xo[j];
             const double e = st.eps[j];
             const double ag = fabs(gt);
-            // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
-            const double mu = S.c1 * ag + e * S.c2 + S.Rp * P->atom_norm[j];
-            keep = mu >= 1.0 - P->margin;
-            // look-ahead: conventional test on the approximate atom
-            kt = (S.c1 * ag + S.Rp * st.at_norm[j] >= 1.0) ? 1.0 : 0.0;
-            // FISTA step on the preserved coefficients; the gradient at the
-            // extrapolated point follows from the two correlation vectors by linearity
+            // sphere test of the rule and the look-ahead flag on the approximate atom
+            const int rule = P->rule;
+            const double acy = rule ? fabs(P->cy[(size_t)b * K + j]) : 0.0;
+            const double eI = rule ? P->st[P->n_stages - 1].eps[j] : 0.0;
+            keep = atom_test(rule, S, 1.0 / C.lam, S.Rp, ag, e, P->atom_norm[j], st.at_norm[j], acy, eI,
+                             1.0 - P->margin, kt);
+            // FISTA (or ISTA: beta = 0) step on the preserved coefficients; the gradient at
+            // the extrapolated point follows from the two correlation vectors by linearity
             const double beta = S.beta;
             const double zpt = xt + beta * (xt - xp);
             const double h = (1.0 + beta) * gt - beta * gp;
@@ -1038,6 +1039,19 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             up[3] = sums[1];
         }
     }
+}
+
+// ||y||^2 of every signal in FP64 (the stable Dynamic Safe radius)
+__global__ __launch_bounds__(kBlock) void k_ysq(const SolveParams* __restrict__ P, double* yy) {
+    __shared__ double s_red[48];
+    const int b = blockIdx.x;
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < P->N; i += kBlock) {
+        const double t = yval(P, b, i);
+        v[0] = fma(t, t, v[0]);
+    }
+    block_sum<1>(v, s_red);
+    if (threadIdx.x == 0) yy[b] = v[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1205,6 +1219,11 @@ hipError_t launch_finalize(const SolveParams* dP, const LaunchCfg& c, double* x,
 
 hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int32_t* status, hipStream_t s) {
     hipLaunchKernelGGL(k_lambda_out, dim3((batch + 255) / 256), dim3(256), 0, s, dP, out, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ysq(const SolveParams* dP, int batch, double* yy, hipStream_t s) {
+    hipLaunchKernelGGL(k_ysq, dim3(batch), dim3(kBlock), 0, s, dP, yy);
     return hipGetLastError();
 }
 

@@ -722,7 +722,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             block_max<3>(mx, s_red);
             if (tid == 0) {
                 Scalars S;
-                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], S);
+                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
                 if (S.conv == 1) S.tconv = wall_clock64();
                 sS = S;
             }
@@ -770,6 +770,10 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const double* an = P->atom_norm;
             const double c1 = uni(sS.c1), c2 = uni(sS.c2), Rp = uni(sS.Rp), beta = uni(sS.beta);
             const double invL = st.invL, thr = uni(sC.lam) * st.invL, keep_min = 1.0 - P->margin;
+            const int rule = P->rule;
+            const double Rd = uni(sS.Rd), invlam = uni(1.0 / sC.lam), eyl = uni(sS.ny / sC.lam);
+            const double* cyb = rule ? P->cy + (size_t)b * K : nullptr;
+            const double* eI = P->st[P->n_stages - 1].eps;
             int wpos = 0, zpos = 0;
             double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
             for (int base = 0; base < n_act; base += 2 * kWgBlock) {
@@ -791,12 +795,18 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                         const double xp = xo[j];
                         const double e = eps[j];
                         const double ag = fabs(gt);
-                        // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
-                        const double mu = c1 * ag + e * c2 + Rp * an[j];
-                        keep[h] = mu >= keep_min;
-                        // look-ahead: conventional test on the approximate atom
-                        sv[0] += (c1 * ag + Rp * atn[j] >= 1.0) ? 1.0 : 0.0;
-                        // FISTA step from the two correlation vectors (gradient by linearity)
+                        if (rule) {
+                            // stable Dynamic Safe: |a^T y| / lambda + ||theta' - y/lambda|| ||a||
+                            const double c = fabs(cyb[j]) * invlam;
+                            keep[h] = c + eI[j] * eyl + Rd * an[j] >= keep_min;
+                            sv[0] += (c + Rd * atn[j] >= 1.0) ? 1.0 : 0.0;
+                        } else {
+                            // stable GAP Safe: |a~^T theta'| + eps ||theta'|| + R' ||a||
+                            keep[h] = c1 * ag + e * c2 + Rp * an[j] >= keep_min;
+                            // look-ahead: conventional test on the approximate atom
+                            sv[0] += (c1 * ag + Rp * atn[j] >= 1.0) ? 1.0 : 0.0;
+                        }
+                        // FISTA (ISTA: beta = 0) step from the two correlation vectors
                         const double zpt = xt + beta * (xt - xp);
                         const double hh = (1.0 + beta) * gt - beta * gp;
                         const double v = zpt + hh * invL;
@@ -856,7 +866,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                 double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
                 tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
                 tr[4] = kt;
-                tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = sS.Rp; tr[9] = sS.gamma;
+                tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = P->rule ? sS.Rd : sS.Rp; tr[9] = sS.gamma;
                 tr[10] = C.l1; tr[11] = sS.P; tr[12] = C.n_nz;
             }
             const int i_new = switch_dictionary(C.stage, P->n_stages - 1, sS.gamma, P->Gamma, kt, st.rc, (double)P->K);
@@ -909,6 +919,7 @@ struct TailState {
     int* la;                 // atom index
     int* lg;                 // row of the atom in the Gram matrix (Gram mode)
     double *xt, *xp, *gt, *gm, *e, *an, *atn;   // x_t, x_{t-1}, g_t, g_{t-1}, eps, norms
+    double* cy;              // a^T y on the exact dictionary (stable Dynamic Safe)
 };
 
 __device__ __forceinline__ TailState tail_state(char* smem, const SolveParams* P) {
@@ -923,7 +934,8 @@ __device__ __forceinline__ TailState tail_state(char* smem, const SolveParams* P
     T.e = base + 4 * (size_t)cap;
     T.an = base + 5 * (size_t)cap;
     T.atn = base + 6 * (size_t)cap;
-    T.lg = (int*)(base + 7 * (size_t)cap);
+    T.cy = base + 7 * (size_t)cap;
+    T.lg = (int*)(base + 8 * (size_t)cap);
     return T;
 }
 
@@ -1126,6 +1138,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         // per-iteration copies of the parameter block and of the lane's positions
         // keep addresses out of the loop-carried registers
         const SolveParams* Pi = phase_params(P0);
+        const int rule = Pi->rule;
         int lo = l;
         asm volatile("" : "+v"(lo));
         const int par = uni(C.par);
@@ -1162,11 +1175,11 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         const double r2 = fmax(yr - xg, 0.0);
         const double e_yr = gam * YX * YX, e_r2 = 4.0 * gam * YX * YX;
         const double rz = uni(sqrt(r2 + e_r2));
-        double c1, c2, Rp, beta, tau_next, Gp, Gt, delta, gam_t, Pv;
+        double c1, c2, Rp, Rd, ny, beta, tau_next, Gp, Gt, delta, gam_t, Pv;
         int conv;
         {
             Scalars S;
-            scalars_from(Pi, C, r2, r2, yr, m1 + me * rz, m1, me, S);
+            scalars_from(Pi, C, r2, r2, yr, m1 + me * rz, m1, me, rule ? Pi->yy[b] : 0.0, S);
             c1 = uni(S.c1);
             beta = uni(S.beta);
             tau_next = uni(S.tau_next);
@@ -1178,6 +1191,9 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             delta = uni(S.delta + 0.5 * e_r2 + lam * c1 * e_yr + 0.5 * lam * lam * c1 * c1 * e_r2 + lam * gam * C.l1);
             Rp = uni(sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam);
             c2 = uni(c1 * rz);
+            // the Dynamic Safe radius also carries the Gram errors of ||rho||^2 and y^T rho
+            Rd = uni(sqrt(S.Rd * S.Rd + c1 * c1 * e_r2 + 2.0 * c1 * e_yr / lam));
+            ny = uni(S.ny);
         }
         wg_stamp(Pi, b, 2, *s_clk);
         if (conv) {
@@ -1208,6 +1224,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         }
         // ---- stable GAP test (|g_j| + eta ||a_j||), look-ahead count, FISTA step ----
         const double Rq = uni(Rp + c1 * eta);
+        const double invlam = uni(1.0 / lam);
         bool keep[H], nzf[H];
         double xn[H];
         double kt = 0.0, l1 = 0.0, Xn = 0.0;
@@ -1222,8 +1239,14 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 xn[h] = 0.0;
                 if (i < n_act) {
                     const double an = T.an[i], ag = fabs(g[h]);
-                    keep[h] = c1 * ag + T.e[i] * c2 + Rq * an >= keep_min;
-                    kt += (c1 * ag + Rp * T.atn[i] >= 1.0) ? 1.0 : 0.0;
+                    if (rule) {          // stable Dynamic Safe with a^T y given
+                        const double c = fabs(T.cy[i]) * invlam;
+                        keep[h] = c + T.e[i] * ny * invlam + Rd * an >= keep_min;
+                        kt += (c + Rd * T.atn[i] >= 1.0) ? 1.0 : 0.0;
+                    } else {
+                        keep[h] = c1 * ag + T.e[i] * c2 + Rq * an >= keep_min;
+                        kt += (c1 * ag + Rp * T.atn[i] >= 1.0) ? 1.0 : 0.0;
+                    }
                     const double xp = T.xp[i], gm = T.gm[i];
                     const double zpt = xt[h] + beta * (xt[h] - xp);
                     const double hh = (1.0 + beta) * g[h] - beta * gm;
@@ -1243,18 +1266,19 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         }
         // ---- compaction (positions keep their order) ----
         int jj[H], lgp[H];
-        double ev[H], anv[H], atv[H];
+        double ev[H], anv[H], atv[H], cyv[H];
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const int i = lo + 64 * h;
             jj[h] = lgp[h] = 0;
-            ev[h] = anv[h] = atv[h] = 0.0;
+            ev[h] = anv[h] = atv[h] = cyv[h] = 0.0;
             if (keep[h]) {
                 jj[h] = T.la[i];
                 lgp[h] = T.lg[i];
                 ev[h] = T.e[i];
                 anv[h] = T.an[i];
                 atv[h] = T.atn[i];
+                cyv[h] = T.cy[i];
             }
         }
         wave_sync_lds();                  // every lane's reads of the state precede the writes
@@ -1273,6 +1297,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 T.e[q] = ev[h];
                 T.an[q] = anv[h];
                 T.atn[q] = atv[h];
+                T.cy[q] = cyv[h];
             }
             if (nzf[h]) {
                 const int q = zpos + __popcll(bz & below);
@@ -1292,7 +1317,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             double* tr = Pi->trace + ((size_t)b * Pi->trace_cap + C.iter) * SL1_TRACE_FIELDS;
             tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = wpos;
             tr[4] = kt;
-            tr[5] = Gp; tr[6] = Gt; tr[7] = delta; tr[8] = Rp; tr[9] = gam_t;
+            tr[5] = Gp; tr[6] = Gt; tr[7] = delta; tr[8] = rule ? Rd : Rp; tr[9] = gam_t;
             tr[10] = C.l1; tr[11] = Pv; tr[12] = C.n_nz;
         }
         C.ksince += 1;
@@ -1375,6 +1400,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             T.e[i] = st.eps[j];
             T.an[i] = P->atom_norm[j];
             T.atn[i] = st.at_norm[j];
+            T.cy[i] = P->rule ? P->cy[(size_t)b * P->K + j] : 0.0;
         }
         const int* nzl = nzbuf(P, b, 0);
         int* lj = (int*)(smem + P->wo_lnj);
@@ -1423,7 +1449,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             block_max<3>(mx, s_red);
             if (tid == 0) {
                 Scalars S;
-                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], S);
+                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
                 if (S.conv == 1) S.tconv = wall_clock64();
                 sS = S;
             }
@@ -1466,6 +1492,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             double* xo = xbuf(P, b, 1 - par);
             const double c1 = uni(sS.c1), c2 = uni(sS.c2), Rp = uni(sS.Rp), beta = uni(sS.beta);
             const double invL = st.invL, thr = uni(sC.lam) * st.invL, keep_min = 1.0 - P->margin;
+            const int rule = P->rule;
+            const double Rd = uni(sS.Rd), invlam = uni(1.0 / sC.lam), eyl = uni(sS.ny / sC.lam);
             int wpos = 0, zpos = 0;
             double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
             for (int base = 0; base < n_act; base += kWgBlock) {
@@ -1473,7 +1501,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                 const bool valid = i < n_act;
                 bool keep = false, nzf = false;
                 int j = 0;
-                double xn = 0.0, xt = 0.0, gt = 0.0, e = 0.0, an = 0.0, atn = 0.0;
+                double xn = 0.0, xt = 0.0, gt = 0.0, e = 0.0, an = 0.0, atn = 0.0, cy = 0.0;
                 if (valid) {
                     j = T.la[i];
                     xt = T.xt[i];
@@ -1481,14 +1509,21 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                     e = T.e[i];
                     an = T.an[i];
                     atn = T.atn[i];
+                    cy = T.cy[i];
                     const double xp = T.xp[i];
                     const double gp = T.gm[i];
                     const double ag = fabs(gt);
-                    // stable GAP Safe test: |a~^T theta'| + eps ||theta'|| + R' ||a||
-                    const double mu = c1 * ag + e * c2 + Rp * an;
-                    keep = mu >= keep_min;
-                    // look-ahead: conventional test on the approximate atom
-                    sv[0] += (c1 * ag + Rp * atn >= 1.0) ? 1.0 : 0.0;
+                    if (rule) {
+                        // stable Dynamic Safe: |a^T y| / lambda + ||theta' - y/lambda|| ||a||
+                        const double c = fabs(cy) * invlam;
+                        keep = c + e * eyl + Rd * an >= keep_min;
+                        sv[0] += (c + Rd * atn >= 1.0) ? 1.0 : 0.0;
+                    } else {
+                        // stable GAP Safe: |a~^T theta'| + eps ||theta'|| + R' ||a||
+                        keep = c1 * ag + e * c2 + Rp * an >= keep_min;
+                        // look-ahead: conventional test on the approximate atom
+                        sv[0] += (c1 * ag + Rp * atn >= 1.0) ? 1.0 : 0.0;
+                    }
                     // FISTA step from the two correlation vectors (gradient by linearity)
                     const double zpt = xt + beta * (xt - xp);
                     const double hh = (1.0 + beta) * gt - beta * gp;
@@ -1515,6 +1550,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                     T.e[q] = e;
                     T.an[q] = an;
                     T.atn[q] = atn;
+                    T.cy[q] = cy;
                 }
                 const int pz = wg_scan_flag(nzf, s_w, tz);
                 if (nzf) {
@@ -1542,7 +1578,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                 double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
                 tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
                 tr[4] = s_kt[0];
-                tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = sS.Rp; tr[9] = sS.gamma;
+                tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = P->rule ? sS.Rd : sS.Rp; tr[9] = sS.gamma;
                 tr[10] = C.l1; tr[11] = sS.P; tr[12] = C.n_nz;
             }
             C.ksince += 1;

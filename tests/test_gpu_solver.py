@@ -444,3 +444,72 @@ def test_autograd_function_backward(sl1):
     loss.backward()
     assert y.grad is not None and lam.grad is not None
     assert torch.isfinite(y.grad).all() and torch.isfinite(lam.grad).all()
+
+
+# ---------------------------------------------------------------------------
+# ISTA and the stable Dynamic Safe test (Table I, fourth row; Table II)
+# ---------------------------------------------------------------------------
+RULE_VARIANTS = [("fista", "dst"), ("ista", "gap"), ("ista", "dst")]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("update,rule", RULE_VARIANTS, ids=[f"{u}-{r}" for u, r in RULE_VARIANTS])
+@pytest.mark.parametrize("real,frac", [(0, 0.5), (1, 0.2)])
+def test_variant_trace_matches_method_reference(sl1, real, frac, update, rule, engine):
+    _say(f"trace C1 {update}/{rule} real={real} frac={frac} engine={engine}")
+    p = synth.config1(realization=real, lam_frac=frac)
+    out = _run(sl1, p, tol=1e-10, trace_cap=20000, engine=engine, update=update, rule=rule)
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
+                      [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10, update=update, rule=rule)
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0
+    assert n == ref.iters
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+    np.testing.assert_allclose(tr[:, 6], np.array([r.G_conv for r in ref.trace]), rtol=1e-7, atol=1e-12)
+    # the sphere radius of the rule, squared (the GAP radius is sqrt(2 (G' + delta)) / lambda,
+    # so compare R^2 with the absolute gap accuracy; the GPU's Dynamic Safe radius also
+    # carries its rounding widening)
+    lam = float(p.lam[0])
+    np.testing.assert_allclose(tr[:, 8] ** 2, np.array([r.R_stable for r in ref.trace]) ** 2, rtol=1e-6,
+                               atol=2e-10 / lam ** 2)
+    sol = ol.solve(p.A, p.Y[0], float(p.lam[0]), L=p.stages[-1].L)
+    x = out["x"][0]
+    assert not np.any((out["screened"][0] == 1) & (sol["x"] != 0))
+    assert (ol.primal(p.A, p.Y[0], float(p.lam[0]), x) - sol["P"]) / sol["P"] <= 1e-7
+    assert np.linalg.norm(x - sol["x"]) <= 1e-4 * np.linalg.norm(sol["x"])
+
+
+@pytest.mark.parametrize("update,rule", RULE_VARIANTS, ids=[f"{u}-{r}" for u, r in RULE_VARIANTS])
+def test_variants_hybrid_tail_match_grid(sl1, update, rule):
+    # the batched dictionary (12 signals) and a dense low-precision sequence: the
+    # hybrid solve's tail (Gram and column modes) agrees with the grid engine
+    _say(f"variants {update}/{rule}: hybrid tail vs grid")
+    for p in (synth.config4(batch=12), synth.config3(N=256, K=1024, s=20, batch=3)):
+        g = _run(sl1, p, tol=1e-9, engine="grid", update=update, rule=rule)
+        assert g["status"] == 0
+        for gram in (True, False):
+            h = _run(sl1, p, tol=1e-9, engine="hybrid", tail_gram=gram, update=update, rule=rule)
+            assert h["status"] == 0
+            np.testing.assert_array_equal(g["stage"], h["stage"])
+            assert np.all(np.abs(g["iters"] - h["iters"]) <= 3), (gram, g["iters"], h["iters"])
+            for b in range(p.batch):
+                rel = np.linalg.norm(g["x"][b] - h["x"][b]) / max(np.linalg.norm(g["x"][b]), 1e-300)
+                assert rel <= 1e-6, f"{p.name} gram={gram} signal {b}: {rel:.2e}"
+        for b in (0, p.batch - 1):
+            _check_solution(p, g, b)
+
+
+def test_dst_requires_a_dense_exact_stage(sl1):
+    # a^T y is formed with the dense correlation kernel; a Kronecker exact stage is refused
+    import torch
+    p = synth.config2(n=(16, 32))
+    kr = [s for s in p.stages if s.kind == "kron"][-1]
+    import dataclasses
+    ex = dataclasses.replace(kr, eps=np.zeros(p.K))
+    with pytest.raises(Exception):
+        _run(sl1, p, tol=1e-6, stages=[ex], rule="dst")
+    torch.cuda.synchronize()
