@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-single", action="store_true", help="skip the single-signal block")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled oracle parity check")
+    ap.add_argument("--no-variants", action="store_true", help="skip the ISTA / Dynamic Safe variants")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
@@ -238,6 +239,33 @@ def recorded_traffic(kernel):
     return None
 
 
+VARIANTS = (("fista", "dst"), ("ista", "gap"), ("ista", "dst"))
+
+
+def variants_block(sl1, torch, np, p, rc, tol, steps, warmup):
+    """The other update / test combinations of Table II (FISTA or ISTA, stable GAP
+    Safe or stable Dynamic Safe) on the same batch: time-to-gap of the method and
+    of plain FP32 (the single stage [A]) with the same update and test."""
+    st, Y, lam, an = upload(sl1, torch, p)
+    L = [s.L for s in p.stages]
+    out = []
+    for update, rule in VARIANTS:
+        def method():
+            return sl1.solve(st, L, rc, an, Y, lam, tol=tol, update=update, rule=rule)
+
+        def plain():
+            return sl1.solve([st[-1]], [L[-1]], [1.0], an, Y, lam, tol=tol, update=update, rule=rule)
+
+        ms_m, o_m = timed(torch, method, steps, warmup)
+        ms_p, o_p = timed(torch, plain, steps, warmup)
+        it_m, it_p = int(o_m["iters"].sum().item()), int(o_p["iters"].sum().item())
+        log(f"variant {update}/{rule}: method {ms_m:.3f} ms ({it_m} iters), plain {ms_p:.3f} ms ({it_p} iters)")
+        out.append(dict(update=update, rule=rule, time_to_gap_ms=ms_m, iters=it_m,
+                        iters_per_s=it_m / (ms_m * 1e-3), plain_fp32_time_to_gap_ms=ms_p, plain_fp32_iters=it_p,
+                        speedup_vs_plain_fp32=ms_p / ms_m, max_gap=float(o_m["gap"].max().item())))
+    return out
+
+
 def roofline(res):
     """The kernel with the largest share of the solve's device time, with its
     recorded HBM traffic per launch when the counters match the current code."""
@@ -351,6 +379,9 @@ def main():
     if not args.no_parity:
         log("sampled parity against the FP64 oracle")
         line["parity"] = parity_sample(np, p, res)
+    if not args.no_variants:
+        log("update / test variants on the batched workload (1 timed solve each)")
+        line["variants"] = variants_block(sl1, torch, np, p, res["rc_measured"], args.tol, 1, 1)
     if not args.no_cpu:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(np, p, args.cpu_seconds)
