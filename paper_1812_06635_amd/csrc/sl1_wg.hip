@@ -1157,8 +1157,17 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 const int r = T.lg[i];
                 xt[h] = T.xt[i];
                 const double* Gc = G + r;
-                double gi = cv[r];
-                for (int q = 0; q < n_nz; ++q) gi = fma(-Gc[(size_t)lj[q] * gcap], lx[q], gi);
+                // four independent chains over the nonzeros (any order is within the bound)
+                double g0 = cv[r], g1 = 0.0, g2 = 0.0, g3 = 0.0;
+                int q = 0;
+                for (; q + 4 <= n_nz; q += 4) {
+                    g0 = fma(-Gc[(size_t)lj[q] * gcap], lx[q], g0);
+                    g1 = fma(-Gc[(size_t)lj[q + 1] * gcap], lx[q + 1], g1);
+                    g2 = fma(-Gc[(size_t)lj[q + 2] * gcap], lx[q + 2], g2);
+                    g3 = fma(-Gc[(size_t)lj[q + 3] * gcap], lx[q + 3], g3);
+                }
+                for (; q < n_nz; ++q) g0 = fma(-Gc[(size_t)lj[q] * gcap], lx[q], g0);
+                const double gi = (g0 + g1) + (g2 + g3);
                 g[h] = gi;
                 cx = fma(cv[r], xt[h], cx);
                 xg = fma(xt[h], gi, xg);
@@ -1166,10 +1175,20 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 me = fmax(me, T.e[i]);
             }
         }
-        cx = uni(wave_sum(cx));
-        xg = uni(wave_sum(xg));
-        m1 = uni(wave_max(m1));
-        me = uni(wave_max(me));
+        // the four wave reductions interleaved (xor butterfly: every lane ends with the same bits)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double a0 = __shfl_xor(cx, off, 64), a1 = __shfl_xor(xg, off, 64);
+            const double a2 = __shfl_xor(m1, off, 64), a3 = __shfl_xor(me, off, 64);
+            cx += a0;
+            xg += a1;
+            m1 = fmax(m1, a2);
+            me = fmax(me, a3);
+        }
+        cx = uni(cx);
+        xg = uni(xg);
+        m1 = uni(m1);
+        me = uni(me);
         // ---- scalars (uniform) ----
         const double yr = yy - cx;
         const double r2 = fmax(yr - xg, 0.0);
@@ -1308,9 +1327,15 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             zpos += __popcll(bz);
         }
         wave_sync_lds();
-        kt = wave_sum(kt);
-        l1 = uni(wave_sum(l1));
-        Xn = uni(wave_sum(Xn));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double a0 = __shfl_xor(kt, off, 64), a1 = __shfl_xor(l1, off, 64), a2 = __shfl_xor(Xn, off, 64);
+            kt += a0;
+            l1 += a1;
+            Xn += a2;
+        }
+        l1 = uni(l1);
+        Xn = uni(Xn);
         wg_stamp(Pi, b, 3, *s_clk);
         // ---- trace row and momentum (the last stage stays) ----
         if (l == 0 && Pi->trace && C.iter < Pi->trace_cap) {
