@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -74,7 +75,7 @@ def timed(torch, fn, steps, warmup):
 UPD_BYTES_PER_ATOM = 76.0   # test/update per preserved atom: index, 7 FP64 gathers, x and index writes
 
 
-def kernel_work(p, trace, iters, t_split, gram_cap=0):
+def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
     """Algorithmic work of each kernel over one solve, from the trace (rows
     t < t_split ran in the grid kernels, the rest in the tail kernel):
       dense correlations  |A_t| N b bytes (b: bytes per stored element, + 4 B per
@@ -84,11 +85,16 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0):
       update              76 B per preserved atom in the grid kernels (the tail
                           keeps the per-atom state in LDS);
       tail, Gram form     rows with |A_t| <= gram_cap: the |A_t| columns read once
-                          to form G and A_t^T y, then no HBM traffic per iteration."""
+                          to form G and A_t^T y, then no HBM traffic per iteration;
+      batched product     grid rows on the exact dense stage with |A_t| >= gemm_min:
+                          2 N |A_t| FP64 flops (the needed entries; the product also
+                          forms the discarded ones, 2 N K per signal)."""
     import numpy as np
     N = p.N
     w = dict(fwd_bytes=[0.0, 0.0], adj_bytes=[0.0, 0.0], adj_flops=[0.0, 0.0], upd_bytes=[0.0, 0.0],
-             gram_bytes=0.0, gram_it=0, dense_it=[0, 0], kron_it=[0, 0])
+             gram_bytes=0.0, gram_it=0, gemm_flops=0.0, gemm_exec_flops=0.0, gemm_it=0,
+             dense_it=[0, 0], kron_it=[0, 0])
+    I = len(p.stages) - 1
     for b in range(trace.shape[0]):
         n = int(iters[b])
         rows = trace[b, :n]
@@ -100,6 +106,15 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0):
                 bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
             on = rows[:, 1] == s_idx
             g = on & gram
+            if s_idx == I and st.kind == "dense" and gemm_min > 0:
+                gm = on & (part == 0) & (rows[:, 2] >= gemm_min)
+                if gm.any():
+                    w["gemm_flops"] += 2.0 * N * float(rows[gm, 2].sum())
+                    w["gemm_exec_flops"] += 2.0 * N * p.K * int(gm.sum())
+                    w["gemm_it"] += int(gm.sum())
+                    w["fwd_bytes"][0] += N * bpe * float(rows[gm, 12].sum())
+                    w["upd_bytes"][0] += UPD_BYTES_PER_ATOM * float(rows[gm, 2].sum())
+                on = on & ~gm
             if g.any():
                 w["gram_bytes"] += N * bpe * float(rows[np.argmax(g), 2])
                 w["gram_it"] += int(g.sum())
@@ -127,7 +142,7 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
     its bound."""
     out = []
 
-    def add(name, ms, launches, amount, unit_kind):
+    def add(name, ms, launches, amount, unit_kind, peak=BF16_PEAK_TFLOPS):
         if ms <= 0 or launches <= 0:
             return
         if unit_kind == "hbm":
@@ -137,14 +152,18 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
                             avg_launch_us=ms * 1e3 / launches))
         else:
             ach = amount / (ms * 1e-3) / 1e12
-            out.append(dict(kernel=name, bound="mfma", achieved=ach, peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
-                            frac=ach / BF16_PEAK_TFLOPS, traffic=None, launches=launches, total_ms=ms,
+            out.append(dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                            frac=ach / peak, traffic=None, launches=launches, total_ms=ms,
                             avg_launch_us=ms * 1e3 / launches))
 
     add("k_fwd", *prof["fwd"], work["fwd_bytes"][0], "hbm")
     add("k_adj_dense", *prof["adj_dense"], work["adj_bytes"][0], "hbm")
     add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma")
     add("k_upd", *prof["upd"], work["upd_bytes"][0], "hbm")
+    if "adj_gemm" in prof:
+        add("k_adj_gemm", *prof["adj_gemm"], work["gemm_flops"], "mfma", FP64_PEAK_TFLOPS)
+        if out and out[-1]["kernel"] == "k_adj_gemm" and prof["adj_gemm"][0] > 0:
+            out[-1]["executed_tflops"] = work["gemm_exec_flops"] / (prof["adj_gemm"][0] * 1e-3) / 1e12
     if phases.get("wg_launches", 0) > 0:
         add(tail_kernel, phases["wg_ms"], phases["wg_launches"],
             work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1] + work["gram_bytes"], "hbm")
@@ -186,7 +205,7 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
     trace = outp["trace"].cpu().numpy()
     iters = outp["iters"].cpu().numpy()
     t_split = prof["fwd"][1] if phases.get("wg_launches", 0) > 0 else 10 ** 9
-    work = kernel_work(p, trace, iters, t_split, phases.get("gram_cap", 0))
+    work = kernel_work(p, trace, iters, t_split, phases.get("gram_cap", 0), phases.get("gemm_min", 0))
     res = dict(
         ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p, engine=engine, engine_plain=engine_p,
         time_to_gap_ms_device=ttg_dev, max_gap_method=float(gap_m.max()), max_gap_plain=float(gap_p.max()),
@@ -194,7 +213,7 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
         rc_model=[s.rc_theory for s in p.stages], kernel_ms=prof, wg_phases=phases, grid_iterations=t_split,
         roofline_kernels=roofline_entries(prof, phases, work,
                                           "k_solve_tail" if engine == "hybrid" else "k_solve_wg"),
-        gram_iterations=work["gram_it"],
+        gram_iterations=work["gram_it"], gemm_iterations=work["gemm_it"],
         x=out_m["x"].cpu().numpy(), screened=out_m["screened"].cpu().numpy(),
     )
     return res
@@ -373,6 +392,7 @@ def main():
         "whole_solve_phases_ms": res["wg_phases"],
         "grid_iterations": res["grid_iterations"],
         "tail_gram_signal_iterations": res["gram_iterations"],
+        "batched_product_signal_iterations": res["gemm_iterations"],
         "roofline": roofline(res),
         "roofline_kernels": res["roofline_kernels"],
     }

@@ -134,6 +134,11 @@ typedef struct {
                                      columns (no Gram mode) */
 #define SL1_FLAG_ISTA 64          /* ISTA update x_{t+1} = ST(x_t + A~^T rho~_t / L) (Section I-B)
                                      instead of FISTA */
+#define SL1_FLAG_NO_GEMM 256      /* grid engine: correlations of every signal stream its own preserved
+                                     columns (by default, signals on the exact dense stage with
+                                     |A_t| >= max(4 a ceil(K/64), K/8), a = 2 for N <= 1024 else 1,
+                                     share one FP64 matrix-core product A^T Z over tiles of 64 atoms
+                                     x 32 signals) */
 #define SL1_FLAG_RULE_DST 128     /* stable Dynamic Safe test (Table I, fourth row) instead of stable
                                      GAP Safe: sphere B(y/lambda, ||theta'_t - y/lambda||) tested with
                                      a_j^T y formed once on the exact dictionary (footnote to Table I;
@@ -257,8 +262,8 @@ int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, do
  * sl1_last_solve_profile -- per-kernel device time of the grid kernels in the
  * most recent sl1_solve with SL1_FLAG_PROFILE and these shapes: ms[k] total
  * milliseconds and launches[k] launch count of k = 0 forward/residual, 1 dense
- * correlations, 2 Kronecker correlations, 3 scalar block + test/update/compaction
- * (host arrays of 4).
+ * correlations, 2 Kronecker correlations, 3 scalar block + test/update/compaction,
+ * 4 batched dense correlations (host arrays of 5).
  */
 int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
 
@@ -272,11 +277,13 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
  * phase_ms[4] the elapsed milliseconds of the whole-solve launches and
  * *wg_launches (may be NULL) their number; *gram_cap (may be NULL) the Gram
  * capacity (atoms) of the hybrid tail, 0 when no tail ran or it had no Gram mode:
- * a signal's tail iterations with |A_t| <= *gram_cap ran in the Gram form.
+ * a signal's tail iterations with |A_t| <= *gram_cap ran in the Gram form;
+ * *gemm_min (may be NULL) the |A_t| from which a grid iteration of a signal on the
+ * exact dense stage went through the batched correlation product (0: never).
  * sl1_last_solve_profile covers the grid kernels.
  */
 int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms,
-                          long long* wg_launches, int32_t* gram_cap);
+                          long long* wg_launches, int32_t* gram_cap, int32_t* gemm_min);
 
 const char* sl1_status_str(int status);
 const char* sl1_version(void);

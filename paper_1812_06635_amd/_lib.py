@@ -22,6 +22,8 @@ FLAG_ENGINE_HYBRID = 16
 FLAG_TAIL_COLUMNS = 32
 FLAG_ISTA = 64
 FLAG_RULE_DST = 128
+FLAG_NO_GEMM = 256
+GRID_KERNELS = 5
 ENGINE_GRID, ENGINE_WG, ENGINE_HYBRID = 1, 2, 3
 
 c_dict = ctypes.c_void_p
@@ -53,7 +55,8 @@ SIGNATURES = [
     ("sl1_last_solve_clock", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_d)]),
     ("sl1_last_solve_profile", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_longlong)]),
     ("sl1_last_solve_phases", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_d),
-                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_i32)]),
+                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_i32),
+                                      ctypes.POINTER(c_i32)]),
     ("sl1_status_str", ctypes.c_char_p, [c_i32]),
     ("sl1_version", ctypes.c_char_p, []),
 ]

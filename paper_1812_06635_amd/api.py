@@ -118,14 +118,15 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
-          update="fista", rule="gap"):
+          update="fista", rule="gap", batched_gemm=True):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
     signal is on the last, dense, stage with a small preserved set); tail_gram:
     the tail iterates on G = A_t^T A_t once |A_t| fits (else it streams columns);
     update: "fista" or "ista"; rule: "gap" (stable GAP Safe) or "dst" (stable
-    Dynamic Safe, Table I).
+    Dynamic Safe, Table I); batched_gemm: signals with large preserved sets on
+    the exact dense stage share one matrix-core correlation product.
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
@@ -153,7 +154,7 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
     opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
         (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \
-        (L.FLAG_RULE_DST if rule == "dst" else 0)
+        (L.FLAG_RULE_DST if rule == "dst" else 0) | (0 if batched_gemm else L.FLAG_NO_GEMM)
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)
@@ -221,30 +222,33 @@ def last_solve_clock(batch, N, K):
 def last_solve_profile(batch, N, K):
     """{kernel: (total ms, launches)} of the grid kernels in the last solve run
     with profile=True."""
-    ms = (L.c_d * 4)()
-    n = (ctypes.c_longlong * 4)()
+    ms = (L.c_d * L.GRID_KERNELS)()
+    n = (ctypes.c_longlong * L.GRID_KERNELS)()
     L.check(L.load().sl1_last_solve_profile(batch, N, K, ms, n), "sl1_last_solve_profile")
-    names = ("fwd", "adj_dense", "adj_kron", "upd")
-    return {names[k]: (ms[k], n[k]) for k in range(4)}
+    names = ("fwd", "adj_dense", "adj_kron", "upd", "adj_gemm")
+    return {names[k]: (ms[k], n[k]) for k in range(L.GRID_KERNELS)}
 
 
 def last_solve_phases(batch, N, K):
     """(engine name, {phase: ms}) of the last solve of this shape.  With
     profile=True the whole-solve part fills the phase times (workgroup ms summed
     over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches";
-    "gram_cap" is the Gram capacity of a hybrid tail (0: none)."""
+    "gram_cap" is the Gram capacity of a hybrid tail (0: none), "gemm_min" the
+    |A_t| from which signals joined the batched correlation product (0: off)."""
     eng = L.c_i32()
     ph = (L.c_d * 5)()
     n = ctypes.c_longlong()
     gcap = L.c_i32()
-    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph, ctypes.byref(n), ctypes.byref(gcap)),
-            "sl1_last_solve_phases")
+    gmin = L.c_i32()
+    L.check(L.load().sl1_last_solve_phases(batch, N, K, ctypes.byref(eng), ph, ctypes.byref(n), ctypes.byref(gcap),
+                                           ctypes.byref(gmin)), "sl1_last_solve_phases")
     name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg", L.ENGINE_HYBRID: "hybrid"}.get(eng.value, "none")
     keys = ("fwd", "adj_dense", "gram", "upd", "wg_ms") if name == "hybrid" else \
         ("fwd", "adj_dense", "adj_kron", "upd", "wg_ms")
     out = dict(zip(keys, list(ph)))
     out["wg_launches"] = n.value
     out["gram_cap"] = gcap.value
+    out["gemm_min"] = gmin.value
     return name, out
 
 

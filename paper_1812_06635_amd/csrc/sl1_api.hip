@@ -25,6 +25,7 @@ hipError_t launch_lambda_out(const SolveParams*, int, double*, int32_t*, hipStre
 hipError_t launch_time_out(const SolveParams*, int, long long*, hipStream_t);
 hipError_t launch_adjoint_out(const SolveParams*, int, int, int, double*, double*, hipStream_t);
 hipError_t launch_ysq(const SolveParams*, int, double*, hipStream_t);
+hipError_t gemm_lds_attr(size_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
@@ -107,8 +108,9 @@ struct Workspace {
     double* d_cy = nullptr;   // stable Dynamic Safe: [batch][K] a^T y on the exact dictionary (lazy)
     double* d_yy = nullptr;   // [batch] ||y||^2
     int graph_chunk = 0;
-    double prof_ms[4] = {0, 0, 0, 0};       // grid kernels: forward, dense / Kronecker correlations, update
-    long long prof_n[4] = {0, 0, 0, 0};
+    double prof_ms[kGridKernels] = {};      // grid kernels: forward, dense / Kronecker correlations, update,
+    long long prof_n[kGridKernels] = {};    // batched correlations
+    int last_gemm_min = 0;                  // |A_t| threshold of the batched correlations (0: off)
     long long* d_wgprof = nullptr;          // [batch][kWgPhases] phase clocks of the whole-solve engine
     double phase_ms[kWgPhases] = {0, 0, 0, 0};
     double wg_ms = 0.0;                     // whole-solve launches of the last profiled solve
@@ -162,7 +164,7 @@ int make_workspace(Workspace& w) {
     const size_t o_rp = take(B * w.nrc * 3 * 8);
     const size_t o_adp = take(B * w.nadj_max * 4 * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
-    const size_t o_cnt = take(B * 5 * 4);
+    const size_t o_cnt = take(B * 6 * 4);
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
     const size_t o_times = take(B * 16);
@@ -193,6 +195,7 @@ int make_workspace(Workspace& w) {
     p.cnt_adj = p.cnt_fwd + 2 * B;
     p.cnt_adjk = p.cnt_adj + B;
     p.cnt_upd = p.cnt_adjk + B;
+    p.cnt_gemm = p.cnt_upd + B;
     p.active_signals = (int*)(m + o_act_sig);
     p.stat = p.active_signals + 4;
     p.nseg_max = w.nseg_max;
@@ -295,13 +298,30 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     const size_t zb = ((size_t)w.N * ws + 15) & ~(size_t)15;
     c.lds_adj = zb + 4 * (nseg1 + nb1);
     c.lds_adjk = zb + ((4 * nb1 + 15) & ~(size_t)15) + extra;
+    // batched correlations on a dense exact stage: one block per (32-signal, 64-atom)
+    // tile at most; z tile + the flag prefix and signal list in LDS (<= 64 KB)
+    c.lds_gemm = 2 * ((size_t)kGemmAtoms * 33 * 2 * 4 + (size_t)kGemmSig * 33 * 8) + 4 * (2 * (size_t)w.batch + 1);
+    const bool last_dense = p.n_stages > 0 && p.st[p.n_stages - 1].kind == kDense;
+    c.g_gemm = (last_dense && c.lds_gemm <= 159 * 1024)
+                   ? (int)std::min<long long>((long long)((w.batch + kGemmSig - 1) / kGemmSig) *
+                                                  ((w.K + kGemmAtoms - 1) / kGemmAtoms), 1024)
+                   : 0;
     return c;
+}
+
+// |A_t| from which a signal on the exact dense stage joins the batched correlation
+// product: its update launch must read at least the 4 slots per 64-atom tile the
+// product writes, and the product must beat streaming (|A_t| >= K/8).
+int gemm_min_atoms(const SolveParams& p) {
+    const int per = 4 * (p.N <= 1024 ? 2 : 1);
+    return std::max(per * ((p.K + kGemmAtoms - 1) / kGemmAtoms), std::max(1, p.K / 8));
 }
 
 bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
            a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_adjk == b.g_adjk && a.g_upd == b.g_upd &&
-           a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj && a.lds_adjk == b.lds_adjk && a.lds_upd == b.lds_upd;
+           a.g_gemm == b.g_gemm && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj && a.lds_adjk == b.lds_adjk &&
+           a.lds_upd == b.lds_upd && a.lds_gemm == b.lds_gemm;
 }
 
 int check_lds(const LaunchCfg& c) {
@@ -755,6 +775,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     p.lambda_only = 1;
     p.ista = p.rule = 0;
     p.cy = p.yy = nullptr;
+    p.gemm_min = 0;
     p.wg_prof = nullptr;
     p.Gamma = 0.5;
     p.tol = 0.0;
@@ -859,6 +880,11 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         st = check_lds(cfg);
         if (st != SL1_OK) return st;
     }
+    if (o.flags & SL1_FLAG_NO_GEMM) cfg.g_gemm = 0;
+    if (cfg.g_gemm > 0) HIP_TRY(gemm_lds_attr(cfg.lds_gemm));
+    p.gemm_min = cfg.g_gemm > 0 ? gemm_min_atoms(p) : 0;
+    p.gemm_on = p.gemm_min > 0 && batch >= kGemmMinSignals;
+    w->last_gemm_min = p.gemm_min;
     w->last_engine = use_wg ? SL1_ENGINE_WG : SL1_ENGINE_GRID;
     w->last_gram_cap = 0;
     hipStream_t us = (hipStream_t)stream;
@@ -868,7 +894,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 48, w->stream));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
     if (prof) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kGridKernels; ++k) {
             w->prof_ms[k] = 0.0;
             w->prof_n[k] = 0;
         }
@@ -918,7 +944,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     const long long cap = (long long)o.max_iter + 2LL * chunk + 4;
     if (prof) {
         // one event before and after every kernel of a chunk
-        while ((int)w->prof_ev.size() < 8 * chunk) {
+        while ((int)w->prof_ev.size() < 2 * kGridKernels * chunk) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             w->prof_ev.push_back(e);
@@ -927,10 +953,12 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     for (;;) {
         if (prof) {
             for (int it = 0; it < chunk; ++it)
-                for (int k = 0; k < 4; ++k) {
-                    HIP_TRY(hipEventRecord(w->prof_ev[8 * it + 2 * k], w->stream));
+                for (int q = 0; q < kGridKernels; ++q) {
+                    const int k = kIterOrder[q];
+                    const int e0 = 2 * (kGridKernels * it + k);
+                    HIP_TRY(hipEventRecord(w->prof_ev[e0], w->stream));
                     HIP_TRY(launch_one(k, it & 1, w->dP, cfg, w->stream));
-                    HIP_TRY(hipEventRecord(w->prof_ev[8 * it + 2 * k + 1], w->stream));
+                    HIP_TRY(hipEventRecord(w->prof_ev[e0 + 1], w->stream));
                 }
         } else if (use_graph) {
             HIP_TRY(hipGraphLaunch(w->graph, w->stream));
@@ -940,12 +968,13 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         launched += chunk;
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
-            const bool run[4] = {true, cfg.g_adj > 0, cfg.g_adjk > 0, true};
+            const bool run[kGridKernels] = {true, cfg.g_adj > 0, cfg.g_adjk > 0, true, cfg.g_gemm > 0};
             for (int it = 0; it < chunk; ++it)
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < kGridKernels; ++k) {
                     if (!run[k]) continue;
                     float ms = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&ms, w->prof_ev[8 * it + 2 * k], w->prof_ev[8 * it + 2 * k + 1]));
+                    const int e0 = 2 * (kGridKernels * it + k);
+                    HIP_TRY(hipEventElapsedTime(&ms, w->prof_ev[e0], w->prof_ev[e0 + 1]));
                     w->prof_ms[k] += ms;
                     w->prof_n[k] += 1;
                 }
@@ -953,6 +982,15 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 48, hipMemcpyDeviceToHost, w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (*w->h_active <= 0 || launched > cap) break;
+        // the batched correlation product runs in the next chunk only if enough
+        // signals qualified in this chunk's last iteration
+        if (p.gemm_min > 0) {
+            const int on = w->h_active[4 + 4 + 3] >= kGemmMinSignals ? 1 : 0;
+            if (on != p.gemm_on) {
+                p.gemm_on = on;
+                HIP_TRY(hipMemcpyAsync(&w->dP->gemm_on, &p.gemm_on, sizeof(int), hipMemcpyHostToDevice, w->stream));
+            }
+        }
         // hand the remaining iterations to the whole-solve kernel once every live
         // signal is on the last stage with a small preserved set (statistics of
         // the chunk's last launch, slot 1)
@@ -1008,6 +1046,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.lambda_only = 1;
     p.ista = p.rule = 0;
     p.cy = p.yy = nullptr;
+    p.gemm_min = 0;
     p.wg_prof = nullptr;
     p.Gamma = 0.5;
     p.tol = 0.0;
@@ -1090,6 +1129,7 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
         p.lambda_only = 1;
         p.ista = p.rule = 0;
         p.cy = p.yy = nullptr;
+        p.gemm_min = 0;
         p.wg_prof = nullptr;
         p.tol = 0.0;
         p.margin = 0.0;
@@ -1150,7 +1190,7 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
     if (it == g_ws.end()) return SL1_EINVAL;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kGridKernels; ++k) {
         ms[k] = it->second->prof_ms[k];
         launches[k] = it->second->prof_n[k];
     }
@@ -1158,7 +1198,7 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
 }
 
 int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, double* phase_ms,
-                          long long* wg_launches, int32_t* gram_cap) {
+                          long long* wg_launches, int32_t* gram_cap, int32_t* gemm_min) {
     if (!engine) return SL1_EINVAL;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
@@ -1173,6 +1213,7 @@ int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, 
     }
     if (wg_launches) *wg_launches = w.wg_n;
     if (gram_cap) *gram_cap = w.last_gram_cap;
+    if (gemm_min) *gemm_min = w.last_gemm_min;
     return SL1_OK;
 }
 

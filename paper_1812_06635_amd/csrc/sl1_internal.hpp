@@ -104,9 +104,13 @@ struct SolveParams {
     int* cnt_adj;             // [batch] work items of the dense correlation launch (current iteration)
     int* cnt_adjk;            // [batch] work items of the Kronecker correlation launch
     int* cnt_upd;             // [batch] work items of the update launch (current iteration)
+    int* cnt_gemm;            // [batch] 1: the signal's correlations go through the batched product
+    int gemm_min;             // |A_t| from which a signal on the exact dense stage qualifies (0: never)
+    int gemm_on;              // the batched product runs (set by the host between chunks)
     int* active_signals;      // one int: signals not yet done
     int* stat;                // [2][4] per forward-launch slot: max and sum of |A_t| over live
-                              // signals, live signals not yet on the last stage, unused
+                              // signals, live signals not yet on the last stage, signals that
+                              // qualify for the batched correlation product
     int nseg_max, nrc, nadj_max, n1_max;
     // whole-solve engine: byte offsets of its dynamic LDS regions (-1: absent):
     // z in FP64 and FP32, y, the current stage's Kronecker factors, the scratch
@@ -123,9 +127,19 @@ struct SolveParams {
 
 struct LaunchCfg {
     int batch, nseg_max, nrc, nadj_max;
-    int g_fwd, g_adj, g_adjk, g_upd;  // persistent grid sizes (blocks; 0: launch skipped)
-    size_t lds_fwd, lds_adj, lds_adjk, lds_upd;
+    int g_fwd, g_adj, g_adjk, g_upd, g_gemm;  // persistent grid sizes (blocks; 0: launch skipped)
+    size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm;
 };
+
+// grid kernels (profile order): forward, dense correlations, Kronecker correlations,
+// update, batched correlations; launch order within an iteration
+constexpr int kGridKernels = 5;
+constexpr int kIterOrder[kGridKernels] = {0, 1, 4, 2, 3};
+
+// batched correlation tiles: 64 atoms x 64 signals per block
+constexpr int kGemmAtoms = 64;
+constexpr int kGemmSig = 64;
+constexpr int kGemmMinSignals = 64;         // fewer qualifying signals: streaming is faster
 
 constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS
 

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         P->cnt_adj[b] = 0;
         P->cnt_adjk[b] = 0;
         P->cnt_upd[b] = 0;
+        P->cnt_gemm[b] = 0;
         if (ok) atomicAdd(P->active_signals, 1);
         if (b == 0) {
             for (int k = 0; k < 8; ++k) P->stat[k] = 0;
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
             P->stat[4 * prev] = 0;
             P->stat[4 * prev + 1] = 0;
             P->stat[4 * prev + 2] = 0;
+            P->stat[4 * prev + 3] = 0;
         }
     }
     const int per = (total + gridDim.x - 1) / gridDim.x;
@@ -393,6 +395,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     P->cnt_adj[b] = 0;
                     P->cnt_adjk[b] = 0;
                     P->cnt_upd[b] = 0;
+                    P->cnt_gemm[b] = 0;
                     P->cnt_fwd[(size_t)prev * batch + b] = 0;
                     atomicSub(P->active_signals, 1);
                 }
@@ -420,8 +423,15 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                         if (C.stage < P->n_stages - 1) atomicAdd(P->stat + 4 * slot + 2, 1);
                         const StageDesc& stn = P->st[C.stage];
                         const int items = adj_items(stn, C.n_act, N);
-                        P->cnt_adj[b] = stn.kind == kDense ? items : 0;
+                        // large preserved sets on the exact dense stage join the batched product
+                        // while enough signals qualify (the host decides between chunks)
+                        const bool qual = P->gemm_min > 0 && C.stage == P->n_stages - 1 &&
+                                          stn.kind == kDense && C.n_act >= P->gemm_min;
+                        if (qual) atomicAdd(P->stat + 4 * slot + 3, 1);
+                        const bool gemm = qual && P->gemm_on;
+                        P->cnt_adj[b] = (stn.kind == kDense && !gemm) ? items : 0;
                         P->cnt_adjk[b] = stn.kind == kKron ? items : 0;
+                        P->cnt_gemm[b] = gemm ? 1 : 0;
                         P->cnt_upd[b] = max(1, (C.n_act + kSeg - 1) / kSeg);
                         if (Cp.advance && P->trace && Cp.iter < P->trace_cap) {
                             double* tr = P->trace + ((size_t)b * P->trace_cap + Cp.iter) * SL1_TRACE_FIELDS;
@@ -809,6 +819,248 @@ __global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __re
     }
 }
 
+// ---------------------------------------------------------------------------
+// batched correlations: the signals whose preserved set on the exact dense
+// stage is large share one product G = A^T Z, tiled 64 atoms x 64 signals per
+// block (FP64 MFMA 16x16x4; stored entries decoded to FP64 exactly, z in FP64),
+// so a column is read once per 64 signals instead of once per signal.  Entries of
+// atoms outside a signal's preserved set are discarded.  Rows go in chunks of 32:
+// the block stages the chunk's A (stored type) and z (FP64) with coalesced loads
+// into one of two LDS buffers while the waves multiply the other.  The four waves
+// form a 2 x 2 grid of 32 atoms x 32 signals (2 x 2 MFMA tiles each).  MFMA
+// operands: lane l gives A[atom l%16][row 4k + l/16] and z[signal l%16][same row];
+// the FP64 accumulator holds D[4v + l/16][l%16] (atom, signal).  Per-16-atom
+// maxima of the stable dual scaling go to the slots the update launch reduces
+// (4 per 64-atom tile); the signal's remaining slots are zeroed.
+// ---------------------------------------------------------------------------
+constexpr int kGR = 32;                 // rows per chunk
+constexpr int kGLdA = kGR + 1;          // LDS row length of a staged column (32-bit words)
+constexpr int kGLdZ = kGR + 1;          // LDS row length of a staged z (doubles)
+constexpr int kGBufA = kGemmAtoms * kGLdA;      // 32-bit words of one A buffer (F64: 2 words each)
+constexpr int kGBufZ = kGemmSig * kGLdZ;        // doubles of one z buffer
+
+template <int DT>
+__device__ __forceinline__ double gemm_dec(const uint32_t* w, int i) {
+    if constexpr (DT == SL1_F64) return __hiloint2double((int)w[2 * i + 1], (int)w[2 * i]);
+    else if constexpr (DT == SL1_F32) return (double)__uint_as_float(w[i]);
+    else if constexpr (DT == SL1_BF16) return (double)bf16_to_f((uint16_t)w[i]);
+    else {
+        const auto v = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+        return (double)v[0];
+    }
+}
+
+// rows r0..r0+kGR (zero past N) of the tile's 64 columns and 64 z vectors: the
+// global loads go to registers first (gemm_fetch) and reach LDS later (gemm_put),
+// so they are in flight while the previous chunk is multiplied
+constexpr int kGQuads = kGemmAtoms * (kGR / 4) / kBlock;     // column quads per thread
+constexpr int kGPairs = kGemmSig * (kGR / 2) / kBlock;       // z pairs per thread
+
+template <int DT>
+struct GemmRegs {
+    Raw4<DT> a[kGQuads];
+    f64v2 z[kGPairs];
+};
+
+template <int DT>
+__device__ __forceinline__ void gemm_fetch(const SolveParams* P, const StageDesc& st, int N, int K, int j0,
+                                           const int* sig, int ns, int r0, GemmRegs<DT>& g) {
+#pragma unroll
+    for (int t = 0; t < kGQuads; ++t) {
+        const int e = threadIdx.x + t * kBlock;
+        const int c = e / (kGR / 4), q = e - c * (kGR / 4);
+        const int r = r0 + 4 * q;
+        const int j = min(j0 + c, K - 1);
+        g.a[t] = raw_load<DT>(st.A, (size_t)j * N + (r < N ? r : 0));
+    }
+#pragma unroll
+    for (int t = 0; t < kGPairs; ++t) {
+        const int e = threadIdx.x + t * kBlock;
+        const int sl = e / (kGR / 2), p2 = e - sl * (kGR / 2);
+        const int r = r0 + 2 * p2;
+        f64v2 v = {0.0, 0.0};
+        if (sl < ns && r < N) v = *(const f64v2*)(P->z + (size_t)sig[sl] * N + r);
+        g.z[t] = v;
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void gemm_put(const GemmRegs<DT>& g, int N, int r0, uint32_t* sa, double* sz) {
+    constexpr int wpe = DT == SL1_F64 ? 2 : 1;     // 32-bit words per stored entry
+#pragma unroll
+    for (int t = 0; t < kGQuads; ++t) {
+        const int e = threadIdx.x + t * kBlock;
+        const int c = e / (kGR / 4), q = e - c * (kGR / 4);
+        const bool in = r0 + 4 * q < N;
+        uint32_t wv[4 * wpe];
+        if constexpr (DT == SL1_F64) {
+            double v[4];
+            raw_get<DT>(g.a[t], v);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                wv[2 * u] = (uint32_t)__double2loint(in ? v[u] : 0.0);
+                wv[2 * u + 1] = (uint32_t)__double2hiint(in ? v[u] : 0.0);
+            }
+        } else if constexpr (DT == SL1_F32) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wv[u] = in ? __float_as_uint(g.a[t].a[u]) : 0u;
+        } else if constexpr (DT == SL1_BF16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wv[u] = in ? (uint32_t)g.a[t].a[u] : 0u;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wv[u] = in ? ((g.a[t].a >> (8 * u)) & 0xFFu) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4 * wpe; ++u) sa[(c * kGLdA + 4 * q) * wpe + u] = wv[u];
+    }
+#pragma unroll
+    for (int t = 0; t < kGPairs; ++t) {
+        const int e = threadIdx.x + t * kBlock;
+        const int sl = e / (kGR / 2), p2 = e - sl * (kGR / 2);
+        sz[sl * kGLdZ + 2 * p2] = g.z[t][0];
+        sz[sl * kGLdZ + 2 * p2 + 1] = g.z[t][1];
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void gemm_mul(const uint32_t* sa, const double* sz, int wa, int wsg, int li, int lk,
+                                         f64x4 (&acc)[2][2]) {
+#pragma unroll
+    for (int k = 0; k < kGR / 4; ++k) {
+        const int row = 4 * k + lk;
+        double a[2], z[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) a[q] = gemm_dec<DT>(sa, (32 * wa + 16 * q + li) * kGLdA + row);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) z[p] = sz[(32 * wsg + 16 * p + li) * kGLdZ + row];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) acc[q][p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], z[p], acc[q][p], 0, 0, 0);
+    }
+}
+
+template <int DT>
+__device__ void gemm_block_tile(const SolveParams* P, const StageDesc& st, int N, int K, int j0, const int* sig,
+                                int ns, uint32_t* sa0, uint32_t* sa1, double* sz0, double* sz1, int wa, int wsg,
+                                int li, int lk, f64x4 (&acc)[2][2]) {
+    GemmRegs<DT> g;
+    gemm_fetch<DT>(P, st, N, K, j0, sig, ns, 0, g);
+    gemm_put<DT>(g, N, 0, sa0, sz0);
+    __syncthreads();
+    int buf = 0;
+    for (int r0 = 0; r0 < N; r0 += kGR) {
+        const bool more = r0 + kGR < N;
+        // the next chunk's loads are in flight while this one is multiplied
+        if (more) gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0 + kGR, g);
+        gemm_mul<DT>(buf ? sa1 : sa0, buf ? sz1 : sz0, wa, wsg, li, lk, acc);
+        if (more) gemm_put<DT>(g, N, r0 + kGR, buf ? sa0 : sa1, buf ? sz0 : sz1);
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock, 2) void k_adj_gemm(const SolveParams* __restrict__ P, int slot) {
+    extern __shared__ __align__(16) char smem[];
+    const int N = P->N, K = P->K, batch = P->batch;
+    const StageDesc& st = P->st[P->n_stages - 1];
+    uint32_t* sa0 = (uint32_t*)smem;
+    uint32_t* sa1 = sa0 + kGBufA * 2;                                    // room for FP64 entries
+    double* sz0 = (double*)(sa1 + kGBufA * 2);
+    double* sz1 = sz0 + kGBufZ;
+    int* s_pre = (int*)(sz1 + kGBufZ);                                   // [batch + 1]
+    int* s_sig = s_pre + batch + 1;                                      // compacted signal list
+    __shared__ int s_tmp[16];
+    const int S = build_work_map(P->cnt_gemm, batch, s_pre, s_tmp);
+    if (S == 0) return;
+    for (int b = threadIdx.x; b < batch; b += kBlock)
+        if (s_pre[b + 1] > s_pre[b]) s_sig[s_pre[b]] = b;
+    __syncthreads();
+    const int nat = (K + kGemmAtoms - 1) / kGemmAtoms, nst = (S + kGemmSig - 1) / kGemmSig;
+    const int total = nat * nst;
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int wa = w & 1, wsg = w >> 1;                 // the wave's atom half and signal half
+    for (int g = g0; g < g1; ++g) {
+        const int ts = g / nat, ta = g - ts * nat;      // signal tile outer, atom tile inner
+        const int s0 = ts * kGemmSig, j0 = ta * kGemmAtoms;
+        const int ns = min(kGemmSig, S - s0);
+        f64x4 acc[2][2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) acc[q][p] = f64x4{0.0, 0.0, 0.0, 0.0};
+        switch (st.dtype) {
+            case SL1_F64: gemm_block_tile<SL1_F64>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            case SL1_F32: gemm_block_tile<SL1_F32>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            case SL1_BF16: gemm_block_tile<SL1_BF16>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            default: gemm_block_tile<SL1_FP8_E4M3>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+        }
+        // lane: signals s0 + 32 wsg + 16 p + li, atoms j0 + 32 wa + 16 q + 4 v + lk
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int sl = 32 * wsg + 16 * p + li;
+            int b = 0, par = 0;
+            double rz = 0.0;
+            if (sl < ns) {
+                b = s_sig[s0 + sl];
+                par = P->ctrl[2 * b + slot].par;
+                double zz = 0.0;
+                for (int k = 0; k < P->nrc; ++k) zz += P->res_part[((size_t)b * P->nrc + k) * 3 + 1];
+                rz = sqrt(zz);
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double mx[3] = {0.0, 0.0, 0.0};
+                if (sl < ns) {
+                    double* gv = gbuf(P, b, par);
+                    const uint8_t* mk = P->mask + (size_t)b * K;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int j = j0 + 32 * wa + 16 * q + 4 * v + lk;
+                        if (j < K && mk[j]) {
+                            double gval = acc[q][p][v];
+                            if (st.scale) gval *= (double)st.scale[j];
+                            gv[j] = gval;
+                            const double e = st.eps[j];
+                            mx[0] = fmax(mx[0], fabs(gval) + e * rz);
+                            mx[1] = fmax(mx[1], fabs(gval));
+                            mx[2] = fmax(mx[2], e);
+                        }
+                    }
+                }
+                // the four lanes of a signal (l % 16 equal) combine their atoms
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    mx[k] = fmax(mx[k], __shfl_xor(mx[k], 16, 64));
+                    mx[k] = fmax(mx[k], __shfl_xor(mx[k], 32, 64));
+                }
+                if (lk == 0 && sl < ns) {
+                    double* ap = P->adj_part + (((size_t)b * P->nadj_max + ta) * 4 + 2 * wa + q) * 3;
+                    ap[0] = mx[0];
+                    ap[1] = mx[1];
+                    ap[2] = mx[2];
+                }
+            }
+        }
+        // slots beyond the 64-atom tiles, up to what the update launch reads, are zero
+        if (ta == 0) {
+            for (int sl = w; sl < ns; sl += kBlock / 64) {
+                const int b = s_sig[s0 + sl];
+                const int slots = 4 * adj_items(st, P->ctrl[2 * b + slot].n_act, N);
+                double* ap = P->adj_part + (size_t)b * P->nadj_max * 4 * 3;
+                for (int k = 4 * nat + l; k < slots; k += 64) {
+                    ap[(size_t)k * 3] = 0.0;
+                    ap[(size_t)k * 3 + 1] = 0.0;
+                    ap[(size_t)k * 3 + 2] = 0.0;
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int N = P->N, K = P->K, batch = P->batch;
@@ -1187,14 +1439,17 @@ hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCf
         case 2:
             if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
             break;
+        case 4:
+            if (c.g_gemm > 0) hipLaunchKernelGGL(k_adj_gemm, dim3(c.g_gemm), dim3(kBlock), c.lds_gemm, s, dP, slot);
+            break;
         default: hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_iter(int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
-    for (int k = 0; k < 4; ++k) {
-        hipError_t e = launch_one(k, slot, dP, c, s);
+    for (int q = 0; q < kGridKernels; ++q) {
+        hipError_t e = launch_one(kIterOrder[q], slot, dP, c, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1220,6 +1475,12 @@ hipError_t launch_finalize(const SolveParams* dP, const LaunchCfg& c, double* x,
 hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int32_t* status, hipStream_t s) {
     hipLaunchKernelGGL(k_lambda_out, dim3((batch + 255) / 256), dim3(256), 0, s, dP, out, status);
     return hipGetLastError();
+}
+
+// the batched correlation kernel may use more than the default 64 KB of LDS
+hipError_t gemm_lds_attr(size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)k_adj_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_ysq(const SolveParams* dP, int batch, double* yy, hipStream_t s) {

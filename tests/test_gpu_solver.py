@@ -513,3 +513,36 @@ def test_dst_requires_a_dense_exact_stage(sl1):
     with pytest.raises(Exception):
         _run(sl1, p, tol=1e-6, stages=[ex], rule="dst")
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# batched correlations (one FP64 matrix-core product for large preserved sets)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("rule", ["gap", "dst"])
+def test_batched_correlations_match_streaming(sl1, rule):
+    # grid engine with and without the batched product: same decisions, same x;
+    # the trace shows iterations that went through the product
+    import paper_1812_06635_amd as m
+    used_by = {}
+    for p in (synth.config4(batch=12), synth.config3(N=256, K=1024, s=20, batch=3),
+              synth.config3(N=2500, K=600, s=20, batch=2)):
+        _say(f"batched correlations vs streaming: {p.name} N={p.N} K={p.K} rule={rule}")
+        on = _run(sl1, p, tol=1e-9, engine="grid", rule=rule, trace_cap=20000)
+        gmin = m.last_solve_phases(p.batch, p.N, p.K)[1]["gemm_min"]
+        off = _run(sl1, p, tol=1e-9, engine="grid", rule=rule, batched_gemm=False)
+        assert on["status"] == 0 and off["status"] == 0 and gmin > 0
+        I = len(p.stages) - 1
+        used = 0
+        for b in range(p.batch):
+            tr = on["trace"][b][:int(on["iters"][b])]
+            used += int(np.sum((tr[:, 1] == I) & (tr[:, 2] >= gmin)))
+        used_by[(p.name, p.N)] = used
+        np.testing.assert_array_equal(on["stage"], off["stage"])
+        assert np.all(np.abs(on["iters"] - off["iters"]) <= 2), (on["iters"], off["iters"])
+        for b in range(p.batch):
+            rel = np.linalg.norm(on["x"][b] - off["x"][b]) / max(np.linalg.norm(off["x"][b]), 1e-300)
+            assert rel <= 1e-7, f"{p.name} signal {b}: {rel:.2e}"
+        for b in (0, p.batch - 1):
+            _check_solution(p, on, b)
+    # the batched dictionary and the small dense sequence do go through the product
+    assert used_by[("C4", 1024)] > 0 and used_by[("C3", 256)] > 0, used_by
