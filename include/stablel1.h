@@ -153,7 +153,7 @@ typedef struct {
  *                      LDS); launches are bounded and repeated while signals remain;
  *   SL1_ENGINE_HYBRID  the grid engine until, after a chunk, every live signal is on
  *                      the last (dense) stage and its preserved set holds at most
- *                      ~1 MiB of columns or fits the Gram capacity (up to 128 atoms);
+ *                      ~2 MiB of columns or fits the Gram capacity (up to 128 atoms);
  *                      the remaining iterations then run in a tail kernel, one
  *                      workgroup per signal with the preserved set's state in LDS.
  *                      Once a signal's |A_t| fits the Gram capacity, the tail kernel

@@ -456,7 +456,7 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
 }
 
 #ifndef SL1_HYBRID_BYTES
-#define SL1_HYBRID_BYTES (1 << 20)
+#define SL1_HYBRID_BYTES (2 << 20)
 #endif
 // Largest preserved set (atoms) at which the hybrid solve moves to the whole-solve
 // kernel: one CU then streams at most SL1_HYBRID_BYTES of dense columns per iteration.

@@ -139,7 +139,10 @@ constexpr int kIterOrder[kGridKernels] = {0, 1, 4, 2, 3};
 // batched correlation tiles: 64 atoms x 64 signals per block
 constexpr int kGemmAtoms = 64;
 constexpr int kGemmSig = 64;
-constexpr int kGemmMinSignals = 64;         // fewer qualifying signals: streaming is faster
+#ifndef SL1_GEMM_MIN_SIGNALS
+#define SL1_GEMM_MIN_SIGNALS 64
+#endif
+constexpr int kGemmMinSignals = SL1_GEMM_MIN_SIGNALS;   // fewer qualifying signals: streaming is faster
 
 constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS
 
