@@ -118,9 +118,13 @@ typedef struct {
     int32_t flags;       /* [0] SL1_FLAG_* */
     double* trace;       /* [NULL] optional device buffer, batch x trace_cap x SL1_TRACE_FIELDS
                             doubles: per iteration t, stage, |A_t|, |A_t+1|, K_t, G(x,theta'|A~),
-                            G(x,theta~|A~), delta, R', gamma, ||x_t||_1, P(x_t|A~), ||x_t||_0 */
+                            G(x,theta~|A~), delta, radius of the test's sphere (R' for stable GAP
+                            Safe, ||theta'-y/lambda|| for stable Dynamic Safe), gamma, ||x_t||_1,
+                            P(x_t|A~), ||x_t||_0 */
     int32_t trace_cap;   /* [0] rows per signal in `trace` */
-    int32_t reserved;
+    int32_t screen_every;/* [1] reject atoms only at iterations t with t % screen_every == 0 (the
+                            variation of Algorithm 1 that screens at regular intervals); dual
+                            points, gaps and K_t are still formed every iteration; 0 = 1 */
 } sl1_opts;
 
 #define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */

@@ -22,6 +22,9 @@ Readings of points the paper leaves open (each stated where it is used):
   * K_t uses the conventional sphere test on the approximate atoms with the
     same sphere (theta'_t, R'_t).
   * The stop test is the conventional duality gap once A~ = A (Section IV).
+  * Screening at regular intervals (Algorithm 1's stated variation): atoms are
+    rejected only every screen_every iterations; K_t and the switch are
+    evaluated at every iteration.
   * Options beside FISTA + stable GAP Safe (Table II's other combinations):
     ISTA (the update of Section I-B, no momentum), and the stable Dynamic Safe
     sphere B(y/lambda, ||theta'_t - y/lambda||) (Table I, fourth row) tested
@@ -129,7 +132,7 @@ class Result:
 
 
 def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12,
-            eps_scale=1.0, keep_trace=True, update="fista", rule="gap", radius_scale=1.0):
+            eps_scale=1.0, keep_trace=True, update="fista", rule="gap", radius_scale=1.0, screen_every=1):
     """Algorithm 1 (FastL1) with FISTA (or ISTA) and the stable GAP Safe (or
     stable Dynamic Safe) test.
 
@@ -143,6 +146,9 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     update     "fista" or "ista" (Section I-B: x_{t+1} = ST(x_t + A~^T rho~_t / L)).
     rule       "gap" (stable GAP Safe) or "dst" (stable Dynamic Safe).
     radius_scale  multiplies the sphere radius (below 1 plants an unsafe test).
+    screen_every  atoms are rejected only at iterations t with t % screen_every == 0
+               (the variation of Algorithm 1 that screens at regular intervals); the
+               dual points, gaps and K_t are formed at every iteration.
     """
     if update not in ("fista", "ista") or rule not in ("gap", "dst"):
         raise ValueError("update must be fista|ista and rule gap|dst")
@@ -220,6 +226,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
             c_norm = abs(s_stable) * r_norm                   # ||theta'_t||_2
             mu = stable_sphere_test(s_stable * g, eps, c_norm, R_test, atom_norm)
         keep = active & (mu >= 1.0 - margin)
+        if t % max(1, screen_every) != 0:
+            keep = active.copy()
         # ---- look-ahead estimate K_t (Section IV-C)
         if rule == "dst":
             mu_conv = sphere_test(aty / lam, R_test, at_norms[i])

@@ -118,7 +118,7 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
-          update="fista", rule="gap", batched_gemm=True):
+          update="fista", rule="gap", batched_gemm=True, screen_every=1):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
@@ -126,7 +126,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     the tail iterates on G = A_t^T A_t once |A_t| fits (else it streams columns);
     update: "fista" or "ista"; rule: "gap" (stable GAP Safe) or "dst" (stable
     Dynamic Safe, Table I); batched_gemm: signals with large preserved sets on
-    the exact dense stage share one matrix-core correlation product.
+    the exact dense stage share one matrix-core correlation product;
+    screen_every: atoms are rejected only every screen_every iterations.
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
@@ -151,6 +152,7 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     L.load().sl1_opts_default(ctypes.byref(opts))
     opts.Gamma, opts.tol, opts.margin = Gamma, tol, margin
     opts.max_iter, opts.chunk = max_iter, chunk
+    opts.screen_every = int(screen_every)
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
     opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
         (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \

@@ -555,6 +555,7 @@ int sl1_opts_default(sl1_opts* o) {
     o->flags = 0;
     o->trace = nullptr;
     o->trace_cap = 0;
+    o->screen_every = 1;
     return SL1_OK;
 }
 
@@ -774,6 +775,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     p.trace_cap = 0;
     p.lambda_only = 1;
     p.ista = p.rule = 0;
+    p.screen_every = 1;
     p.cy = p.yy = nullptr;
     p.gemm_min = 0;
     p.wg_prof = nullptr;
@@ -808,6 +810,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (batch > kMaxBatch) return SL1_ELIMIT;
     if (o.max_iter < 0 || !(o.tol >= 0.0) || !std::isfinite(o.Gamma) || !(o.margin >= 0.0)) return SL1_EINVAL;
     if (o.trace && o.trace_cap < 0) return SL1_EINVAL;
+    if (o.screen_every < 0) return SL1_EINVAL;
     SolveParams tmp;
     std::memset(&tmp, 0, sizeof(tmp));
     int st = prepare(seq, n_stages, L, rc, o.y_dtype, tmp);
@@ -840,6 +843,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.trace_cap = o.trace ? o.trace_cap : 0;
     p.lambda_only = 0;
     p.ista = (o.flags & SL1_FLAG_ISTA) ? 1 : 0;
+    p.screen_every = std::max(1, o.screen_every);
     p.rule = dst ? 1 : 0;
     p.cy = dst ? w->d_cy : nullptr;
     p.yy = dst ? w->d_yy : nullptr;
@@ -1045,6 +1049,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.trace_cap = 0;
     p.lambda_only = 1;
     p.ista = p.rule = 0;
+    p.screen_every = 1;
     p.cy = p.yy = nullptr;
     p.gemm_min = 0;
     p.wg_prof = nullptr;
@@ -1128,6 +1133,7 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
         p.trace_cap = 0;
         p.lambda_only = 1;
         p.ista = p.rule = 0;
+        p.screen_every = 1;
         p.cy = p.yy = nullptr;
         p.gemm_min = 0;
         p.wg_prof = nullptr;

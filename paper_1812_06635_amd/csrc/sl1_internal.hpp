@@ -76,6 +76,7 @@ struct SolveParams {
     int n_stages, N, K, batch;
     int max_iter, trace_cap, y_f64, lambda_only;
     int ista, rule;           // update: 0 FISTA, 1 ISTA; test: 0 stable GAP Safe, 1 stable Dynamic Safe
+    int screen_every;         // rejections only at iterations t with t % screen_every == 0
     double Gamma, tol, margin;
     StageDesc st[SL1_MAX_STAGES];
     const double* atom_norm;

@@ -1104,6 +1104,20 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
         const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;
         const int li = lane & 15, lk = lane >> 4;
         const uint8_t* mask = P->mask + (size_t)b * K;
+        // tile skipping: once few atoms remain, a tile whose 16 x 64 atoms are all
+        // screened is not multiplied (its maxima are zero, its g is never read)
+        if (uni(C.n_act) * 16 <= K) {
+            int any = 0;
+            if ((int)threadIdx.x < kKronColTile && cb0 + (int)threadIdx.x < st.k1) {
+                // atoms (cb0 + col) k2 + a0 .. + 15: 16 consecutive mask bytes, 16-byte aligned
+                const uint4 mv = *(const uint4*)(mask + (size_t)(cb0 + threadIdx.x) * st.k2 + a0);
+                any = (mv.x | mv.y | mv.z | mv.w) != 0u;
+            }
+            if (!__syncthreads_or(any)) {
+                put_wave_max(P, b, c, mx, false);
+                continue;
+            }
+        }
         if (st.dtype == SL1_F64) {
             double* Vall = (double*)extra;
             double* red = Vall + 4 * 16 * P->n1_max;
@@ -1255,6 +1269,7 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             const double eI = rule ? P->st[P->n_stages - 1].eps[j] : 0.0;
             keep = atom_test(rule, S, 1.0 / C.lam, S.Rp, ag, e, P->atom_norm[j], st.at_norm[j], acy, eI,
                              1.0 - P->margin, kt);
+            if (C.iter % P->screen_every != 0) keep = true;    // rejections only every screen_every
             // FISTA (or ISTA: beta = 0) step on the preserved coefficients; the gradient at
             // the extrapolated point follows from the two correlation vectors by linearity
             const double beta = S.beta;

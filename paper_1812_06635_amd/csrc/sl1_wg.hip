@@ -774,6 +774,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const double Rd = uni(sS.Rd), invlam = uni(1.0 / sC.lam), eyl = uni(sS.ny / sC.lam);
             const double* cyb = rule ? P->cy + (size_t)b * K : nullptr;
             const double* eI = P->st[P->n_stages - 1].eps;
+            const bool no_reject = uni(sC.iter) % P->screen_every != 0;
             int wpos = 0, zpos = 0;
             double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
             for (int base = 0; base < n_act; base += 2 * kWgBlock) {
@@ -806,6 +807,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                             // look-ahead: conventional test on the approximate atom
                             sv[0] += (c1 * ag + Rp * atn[j] >= 1.0) ? 1.0 : 0.0;
                         }
+                        if (no_reject) keep[h] = true;
                         // FISTA (ISTA: beta = 0) step from the two correlation vectors
                         const double zpt = xt + beta * (xt - xp);
                         const double hh = (1.0 + beta) * gt - beta * gp;
@@ -1266,6 +1268,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                         keep[h] = c1 * ag + T.e[i] * c2 + Rq * an >= keep_min;
                         kt += (c1 * ag + Rp * T.atn[i] >= 1.0) ? 1.0 : 0.0;
                     }
+                    if (C.iter % Pi->screen_every != 0) keep[h] = true;
                     const double xp = T.xp[i], gm = T.gm[i];
                     const double zpt = xt[h] + beta * (xt[h] - xp);
                     const double hh = (1.0 + beta) * g[h] - beta * gm;
@@ -1519,6 +1522,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             const double invL = st.invL, thr = uni(sC.lam) * st.invL, keep_min = 1.0 - P->margin;
             const int rule = P->rule;
             const double Rd = uni(sS.Rd), invlam = uni(1.0 / sC.lam), eyl = uni(sS.ny / sC.lam);
+            const bool no_reject = uni(sC.iter) % P->screen_every != 0;
             int wpos = 0, zpos = 0;
             double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
             for (int base = 0; base < n_act; base += kWgBlock) {
@@ -1549,6 +1553,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                         // look-ahead: conventional test on the approximate atom
                         sv[0] += (c1 * ag + Rp * atn >= 1.0) ? 1.0 : 0.0;
                     }
+                    if (no_reject) keep = true;
                     // FISTA step from the two correlation vectors (gradient by linearity)
                     const double zpt = xt + beta * (xt - xp);
                     const double hh = (1.0 + beta) * gt - beta * gp;

@@ -546,3 +546,39 @@ def test_batched_correlations_match_streaming(sl1, rule):
             _check_solution(p, on, b)
     # the batched dictionary and the small dense sequence do go through the product
     assert used_by[("C4", 1024)] > 0 and used_by[("C3", 256)] > 0, used_by
+
+
+# ---------------------------------------------------------------------------
+# screening at regular intervals (Algorithm 1's variation)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("engine", ENGINES)
+def test_interval_screening_trace_matches_method_reference(sl1, engine):
+    _say(f"trace C1 screen_every=3 engine={engine}")
+    p = synth.config1(realization=1, lam_frac=0.3)
+    out = _run(sl1, p, tol=1e-10, trace_cap=5000, engine=engine, screen_every=3)
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
+                      [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10, screen_every=3)
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0 and n == ref.iters
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+    assert all(int(r[3]) == int(r[2]) for r in tr if int(r[0]) % 3 != 0)
+    _check_solution(p, out, 0, obj_tol=1e-7)
+
+
+def test_interval_screening_hybrid_tail_matches_grid(sl1):
+    _say("screen_every=4: hybrid tail vs grid")
+    p = synth.config4(batch=12)
+    g = _run(sl1, p, tol=1e-9, engine="grid", screen_every=4)
+    for gram in (True, False):
+        h = _run(sl1, p, tol=1e-9, engine="hybrid", tail_gram=gram, screen_every=4)
+        assert g["status"] == 0 and h["status"] == 0
+        assert np.all(np.abs(g["iters"] - h["iters"]) <= 3)
+        for b in range(p.batch):
+            rel = np.linalg.norm(g["x"][b] - h["x"][b]) / max(np.linalg.norm(g["x"][b]), 1e-300)
+            assert rel <= 1e-6
+    for b in (0, 11):
+        _check_solution(p, g, b)

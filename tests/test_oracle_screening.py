@@ -317,3 +317,17 @@ def test_planted_unsafe_dynamic_radius_is_caught():
         wrong = np.linalg.norm(res.x - sol["x"]) > 1e-4 * np.linalg.norm(sol["x"])
         caught += bool(unsafe or wrong)
     assert caught > 0
+
+
+@pytest.mark.parametrize("k", [3, 7])
+def test_screening_every_k_iterations_is_safe_and_exact(k):
+    # Algorithm 1's variation: rejections only every k iterations.  The preserved
+    # sets only shrink at those iterations and the Lasso solution is unchanged.
+    p = synth.config1(realization=1, lam_frac=0.3)
+    sol, res = _check_method(p, screen_every=k)
+    assert res.converged and not np.any(res.screened & (sol["x"] != 0))
+    assert np.linalg.norm(res.x - sol["x"]) <= 1e-4 * np.linalg.norm(sol["x"])
+    for r in res.trace:
+        if r.t % k != 0:
+            assert r.n_keep == r.n_active
+    assert any(r.n_keep < r.n_active for r in res.trace)
