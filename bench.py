@@ -220,10 +220,9 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
 
 
 # sources whose change voids a recorded HBM-traffic figure of a kernel
-TRAFFIC_SOURCES = {
-    "k_adj_dense": ["paper_1812_06635_amd/csrc/sl1_kernels.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
-                    "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"],
-}
+_GRID_SOURCES = ["paper_1812_06635_amd/csrc/sl1_kernels.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
+                 "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
+TRAFFIC_SOURCES = {k: _GRID_SOURCES for k in ("k_adj_dense", "k_adj_gemm", "k_fwd", "k_upd", "k_adj_kron")}
 
 
 def sources_sha256(kernel):
@@ -289,8 +288,7 @@ def roofline(res):
     """The kernel with the largest share of the solve's device time, with its
     recorded HBM traffic per launch when the counters match the current code."""
     r = dict(res["roofline_kernels"][0])
-    if r["bound"] == "hbm":
-        r["traffic"] = recorded_traffic(r["kernel"])
+    r["traffic"] = recorded_traffic(r["kernel"])
     return r
 
 
