@@ -261,7 +261,7 @@ VARIANTS = (("fista", "dst"), ("ista", "gap"), ("ista", "dst"))
 
 
 def variants_block(sl1, torch, np, p, rc, tol, steps, warmup):
-    """The other update / test combinations of Table II (FISTA or ISTA, stable GAP
+    """The other update / test combinations of Table III (FISTA or ISTA, stable GAP
     Safe or stable Dynamic Safe) on the same batch: time-to-gap of the method and
     of plain FP32 (the single stage [A]) with the same update and test."""
     st, Y, lam, an = upload(sl1, torch, p)

@@ -25,7 +25,7 @@ Readings of points the paper leaves open (each stated where it is used):
   * Screening at regular intervals (Algorithm 1's stated variation): atoms are
     rejected only every screen_every iterations; K_t and the switch are
     evaluated at every iteration.
-  * Options beside FISTA + stable GAP Safe (Table II's other combinations):
+  * Options beside FISTA + stable GAP Safe (Table III's other combinations):
     ISTA (the update of Section I-B, no momentum), and the stable Dynamic Safe
     sphere B(y/lambda, ||theta'_t - y/lambda||) (Table I, fourth row) tested
     with a_j^T y given: the product with the exact A is formed once, as the

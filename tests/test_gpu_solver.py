@@ -447,7 +447,7 @@ def test_autograd_function_backward(sl1):
 
 
 # ---------------------------------------------------------------------------
-# ISTA and the stable Dynamic Safe test (Table I, fourth row; Table II)
+# ISTA and the stable Dynamic Safe test (Table I, fourth row; Table III)
 # ---------------------------------------------------------------------------
 RULE_VARIANTS = [("fista", "dst"), ("ista", "gap"), ("ista", "dst")]
 

@@ -236,7 +236,7 @@ def test_stage_error_bounds_are_exact_column_errors():
 
 
 # ---------------------------------------------------------------------------
-# ISTA and the stable Dynamic Safe sphere (Table I, fourth row; Table II)
+# ISTA and the stable Dynamic Safe sphere (Table I, fourth row; Table III)
 # ---------------------------------------------------------------------------
 def test_dual_solution_is_the_feasible_point_nearest_y_over_lambda():
     # theta* = (y - A x*)/lambda is the projection of y/lambda onto the dual
