@@ -125,6 +125,10 @@ typedef struct {
     int32_t screen_every;/* [1] reject atoms only at iterations t with t % screen_every == 0 (the
                             variation of Algorithm 1 that screens at regular intervals); dual
                             points, gaps and K_t are still formed every iteration; 0 = 1 */
+    int32_t gemm_signals;/* [64] grid engine: the batched correlation product (SL1_FLAG_NO_GEMM)
+                            runs in a chunk of iterations when at least this many signals
+                            qualified at the end of the previous chunk (and in the first chunk
+                            when the batch has this many); 0 = 64 */
 } sl1_opts;
 
 #define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */
@@ -142,7 +146,7 @@ typedef struct {
                                      columns (by default, signals on the exact dense stage with
                                      |A_t| >= max(4 a ceil(K/64), K/8), a = 2 for N <= 1024 else 1,
                                      share one FP64 matrix-core product A^T Z over tiles of 64 atoms
-                                     x 32 signals) */
+                                     x 64 signals; see gemm_signals) */
 #define SL1_FLAG_RULE_DST 128     /* stable Dynamic Safe test (Table I, fourth row) instead of stable
                                      GAP Safe: sphere B(y/lambda, ||theta'_t - y/lambda||) tested with
                                      a_j^T y formed once on the exact dictionary (footnote to Table I;
@@ -150,7 +154,7 @@ typedef struct {
                                      all atoms, which must be dense: SL1_ELIMIT otherwise) */
 
 /* Engines (at most one SL1_FLAG_ENGINE_* flag; none = automatic):
- *   SL1_ENGINE_GRID    three persistent launches per iteration covering every live
+ *   SL1_ENGINE_GRID    five persistent launches per iteration covering every live
  *                      signal (any size within the limits; captured in hipGraph chunks);
  *   SL1_ENGINE_WG      one 512-thread workgroup per signal runs the whole solve in one
  *                      launch (per-signal z and the current stage's Kronecker factors in

@@ -118,7 +118,7 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
-          update="fista", rule="gap", batched_gemm=True, screen_every=1):
+          update="fista", rule="gap", batched_gemm=True, screen_every=1, gemm_signals=0):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
@@ -127,7 +127,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     update: "fista" or "ista"; rule: "gap" (stable GAP Safe) or "dst" (stable
     Dynamic Safe, Table I); batched_gemm: signals with large preserved sets on
     the exact dense stage share one matrix-core correlation product;
-    screen_every: atoms are rejected only every screen_every iterations.
+    screen_every: atoms are rejected only every screen_every iterations;
+    gemm_signals: qualifying signals from which the batched product runs (0: 64).
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
@@ -153,6 +154,7 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.Gamma, opts.tol, opts.margin = Gamma, tol, margin
     opts.max_iter, opts.chunk = max_iter, chunk
     opts.screen_every = int(screen_every)
+    opts.gemm_signals = int(gemm_signals)
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
     opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
         (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \

@@ -25,6 +25,8 @@ hipError_t launch_lambda_out(const SolveParams*, int, double*, int32_t*, hipStre
 hipError_t launch_time_out(const SolveParams*, int, long long*, hipStream_t);
 hipError_t launch_adjoint_out(const SolveParams*, int, int, int, double*, double*, hipStream_t);
 hipError_t launch_ysq(const SolveParams*, int, double*, hipStream_t);
+hipError_t launch_stat(const SolveParams*, hipStream_t);
+int upd_resident_blocks(size_t);
 hipError_t gemm_lds_attr(size_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
@@ -103,11 +105,14 @@ struct Workspace {
     long long* d_times = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
-    hipGraphExec_t graph = nullptr;
+    // captured chunks of grid iterations, one per launch set: bit 0 with the
+    // Kronecker correlation launch, bit 1 with the batched correlation product
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    int graph_chunk[4] = {0, 0, 0, 0};
+    LaunchCfg graph_cfg[4] = {};
     int last_gram_cap = 0;    // Gram capacity of the last hybrid tail (0: none)
     double* d_cy = nullptr;   // stable Dynamic Safe: [batch][K] a^T y on the exact dictionary (lazy)
     double* d_yy = nullptr;   // [batch] ||y||^2
-    int graph_chunk = 0;
     double prof_ms[kGridKernels] = {};      // grid kernels: forward, dense / Kronecker correlations, update,
     long long prof_n[kGridKernels] = {};    // batched correlations
     int last_gemm_min = 0;                  // |A_t| threshold of the batched correlations (0: off)
@@ -117,10 +122,10 @@ struct Workspace {
     long long wg_n = 0;
     int last_engine = 0;
     std::vector<hipEvent_t> prof_ev;
-    LaunchCfg graph_cfg{};
     std::mutex mu;
     ~Workspace() {
-        if (graph) (void)hipGraphExecDestroy(graph);
+        for (auto& g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
         if (mem) (void)hipFree(mem);
         if (d_cy) (void)hipFree(d_cy);
         if (d_yy) (void)hipFree(d_yy);
@@ -164,7 +169,8 @@ int make_workspace(Workspace& w) {
     const size_t o_rp = take(B * w.nrc * 3 * 8);
     const size_t o_adp = take(B * w.nadj_max * 4 * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
-    const size_t o_cnt = take(B * 6 * 4);
+    const size_t o_cnt = take(B * 10 * 4);
+    const size_t o_gpart = take((size_t)kGemmSplitUnits * kGemmAtoms * kGemmSig * 8);
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
     const size_t o_times = take(B * 16);
@@ -196,6 +202,8 @@ int make_workspace(Workspace& w) {
     p.cnt_adjk = p.cnt_adj + B;
     p.cnt_upd = p.cnt_adjk + B;
     p.cnt_gemm = p.cnt_upd + B;
+    p.sig_stat = p.cnt_gemm + B;
+    p.gemm_part = (double*)(m + o_gpart);
     p.active_signals = (int*)(m + o_act_sig);
     p.stat = p.active_signals + 4;
     p.nseg_max = w.nseg_max;
@@ -294,18 +302,26 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
     c.g_adj = dense ? (int)std::min<long long>((long long)w.batch * w.nadj_max, 2048) : 0;
     c.g_adjk = kron_items ? (int)std::min<long long>((long long)w.batch * kron_items, 1024) : 0;
-    c.g_upd = (int)std::min<long long>((long long)w.batch * w.nseg_max, 1024);
+    // update: one resident round of blocks (each block takes a contiguous range of items)
+#ifdef SL1_UPD_GRID
+    const int upd_cap = SL1_UPD_GRID;
+#else
+    const int upd_res = upd_resident_blocks(c.lds_upd);
+    const int upd_cap = upd_res > 0 ? std::min(upd_res, 4096) : 1024;
+#endif
+    c.g_upd = (int)std::min<long long>((long long)w.batch * w.nseg_max, upd_cap);
     const size_t zb = ((size_t)w.N * ws + 15) & ~(size_t)15;
     c.lds_adj = zb + 4 * (nseg1 + nb1);
     c.lds_adjk = zb + ((4 * nb1 + 15) & ~(size_t)15) + extra;
-    // batched correlations on a dense exact stage: one block per (32-signal, 64-atom)
-    // tile at most; z tile + the flag prefix and signal list in LDS (<= 64 KB)
+    // batched correlations on a dense exact stage: one block per (64-signal, 64-atom)
+    // tile, or per row split of a tile while the tiles are few (up to kGemmMaxSplit
+    // splits, kGemmSplitUnits partial tiles); two LDS buffers of a 32-row chunk of
+    // A (room for FP64) and z, + the flag prefix and signal list
     c.lds_gemm = 2 * ((size_t)kGemmAtoms * 33 * 2 * 4 + (size_t)kGemmSig * 33 * 8) + 4 * (2 * (size_t)w.batch + 1);
     const bool last_dense = p.n_stages > 0 && p.st[p.n_stages - 1].kind == kDense;
-    c.g_gemm = (last_dense && c.lds_gemm <= 159 * 1024)
-                   ? (int)std::min<long long>((long long)((w.batch + kGemmSig - 1) / kGemmSig) *
-                                                  ((w.K + kGemmAtoms - 1) / kGemmAtoms), 1024)
-                   : 0;
+    const long long tiles_max = (long long)((w.batch + kGemmSig - 1) / kGemmSig) * ((w.K + kGemmAtoms - 1) / kGemmAtoms);
+    const long long g_split = std::min<long long>(tiles_max * kGemmMaxSplit, kGemmSplitUnits);
+    c.g_gemm = (last_dense && c.lds_gemm <= 159 * 1024) ? (int)std::min<long long>(std::max(tiles_max, g_split), 1024) : 0;
     return c;
 }
 
@@ -505,6 +521,37 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
 }
 
 // outputs of a solve, per-signal statuses, hand-back to the caller's stream
+// captures `chunk` grid iterations with the launch set of ccfg into graph slot v
+int capture_chunk(Workspace* w, const LaunchCfg& ccfg, int chunk, int v) {
+    if (w->graph[v]) {
+        HIP_TRY(hipGraphExecDestroy(w->graph[v]));
+        w->graph[v] = nullptr;
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) {
+        if (launch_iter(k & 1, w->dP, ccfg, cs) != hipSuccess) {
+            (void)hipStreamEndCapture(cs, &g);
+            (void)hipStreamDestroy(cs);
+            return SL1_EHIP;
+        }
+    }
+    HIP_TRY(hipStreamEndCapture(cs, &g));
+    HIP_TRY(hipStreamDestroy(cs));
+    hipError_t e = hipGraphInstantiate(&w->graph[v], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        w->graph[v] = nullptr;
+        return SL1_EHIP;
+    }
+    w->graph_chunk[v] = chunk;
+    w->graph_cfg[v] = ccfg;
+    return SL1_OK;
+}
+
 int finish_solve(Workspace* w, const LaunchCfg& cfg, int64_t batch, double* x, double* gap, double* gap_cert,
                  uint8_t* screened, int32_t* iters, int32_t* stage, hipStream_t us) {
     HIP_TRY(launch_finalize(w->dP, cfg, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
@@ -543,6 +590,8 @@ const char* sl1_status_str(int s) {
     return "unknown status";
 }
 
+static_assert(sizeof(sl1_opts) == 64, "sl1_opts layout (mirrored by the Python binding)");
+
 int sl1_opts_default(sl1_opts* o) {
     if (!o) return SL1_EINVAL;
     std::memset(o, 0, sizeof(*o));
@@ -556,6 +605,7 @@ int sl1_opts_default(sl1_opts* o) {
     o->trace = nullptr;
     o->trace_cap = 0;
     o->screen_every = 1;
+    o->gemm_signals = kGemmMinSignals;
     return SL1_OK;
 }
 
@@ -810,7 +860,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (batch > kMaxBatch) return SL1_ELIMIT;
     if (o.max_iter < 0 || !(o.tol >= 0.0) || !std::isfinite(o.Gamma) || !(o.margin >= 0.0)) return SL1_EINVAL;
     if (o.trace && o.trace_cap < 0) return SL1_EINVAL;
-    if (o.screen_every < 0) return SL1_EINVAL;
+    if (o.screen_every < 0 || o.gemm_signals < 0) return SL1_EINVAL;
     SolveParams tmp;
     std::memset(&tmp, 0, sizeof(tmp));
     int st = prepare(seq, n_stages, L, rc, o.y_dtype, tmp);
@@ -887,7 +937,8 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (o.flags & SL1_FLAG_NO_GEMM) cfg.g_gemm = 0;
     if (cfg.g_gemm > 0) HIP_TRY(gemm_lds_attr(cfg.lds_gemm));
     p.gemm_min = cfg.g_gemm > 0 ? gemm_min_atoms(p) : 0;
-    p.gemm_on = p.gemm_min > 0 && batch >= kGemmMinSignals;
+    const int gemm_signals = o.gemm_signals > 0 ? o.gemm_signals : kGemmMinSignals;
+    p.gemm_on = p.gemm_min > 0 && batch >= gemm_signals;
     w->last_gemm_min = p.gemm_min;
     w->last_engine = use_wg ? SL1_ENGINE_WG : SL1_ENGINE_GRID;
     w->last_gram_cap = 0;
@@ -916,34 +967,6 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     const int chunk = o.chunk > 0 ? ((o.chunk + 1) & ~1) : 16;
     const bool use_graph = !(o.flags & SL1_FLAG_NO_GRAPH);
     const int hyb_atoms = hybrid_atoms(p);
-    if (use_graph && (!w->graph || w->graph_chunk != chunk || !cfg_equal(cfg, w->graph_cfg))) {
-        if (w->graph) {
-            HIP_TRY(hipGraphExecDestroy(w->graph));
-            w->graph = nullptr;
-        }
-        HIP_TRY(hipStreamSynchronize(w->stream));
-        hipStream_t cs;
-        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipGraph_t g;
-        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < chunk; ++k) {
-            if (launch_iter(k & 1, w->dP, cfg, cs) != hipSuccess) {
-                (void)hipStreamEndCapture(cs, &g);
-                (void)hipStreamDestroy(cs);
-                return SL1_EHIP;
-            }
-        }
-        HIP_TRY(hipStreamEndCapture(cs, &g));
-        HIP_TRY(hipStreamDestroy(cs));
-        hipError_t e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            w->graph = nullptr;
-            return SL1_EHIP;
-        }
-        w->graph_chunk = chunk;
-        w->graph_cfg = cfg;
-    }
     long long launched = 0;
     const long long cap = (long long)o.max_iter + 2LL * chunk + 4;
     if (prof) {
@@ -954,25 +977,38 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
             w->prof_ev.push_back(e);
         }
     }
+    // launches with no possible work are left out of a chunk: the Kronecker
+    // correlations once every live signal is on a dense last stage (stages only
+    // advance), the batched product while the host has it switched off
+    const bool last_kron = p.st[p.n_stages - 1].kind == kKron;
+    bool kron_live = cfg.g_adjk > 0;
     for (;;) {
+        LaunchCfg ccfg = cfg;
+        if (!kron_live) ccfg.g_adjk = 0;
+        if (!p.gemm_on) ccfg.g_gemm = 0;
+        const int v = (ccfg.g_adjk > 0 ? 1 : 0) | (ccfg.g_gemm > 0 ? 2 : 0);
         if (prof) {
             for (int it = 0; it < chunk; ++it)
                 for (int q = 0; q < kGridKernels; ++q) {
                     const int k = kIterOrder[q];
                     const int e0 = 2 * (kGridKernels * it + k);
                     HIP_TRY(hipEventRecord(w->prof_ev[e0], w->stream));
-                    HIP_TRY(launch_one(k, it & 1, w->dP, cfg, w->stream));
+                    HIP_TRY(launch_one(k, it & 1, w->dP, ccfg, w->stream));
                     HIP_TRY(hipEventRecord(w->prof_ev[e0 + 1], w->stream));
                 }
         } else if (use_graph) {
-            HIP_TRY(hipGraphLaunch(w->graph, w->stream));
+            if (!w->graph[v] || w->graph_chunk[v] != chunk || !cfg_equal(ccfg, w->graph_cfg[v])) {
+                st = capture_chunk(w, ccfg, chunk, v);
+                if (st != SL1_OK) return st;
+            }
+            HIP_TRY(hipGraphLaunch(w->graph[v], w->stream));
         } else {
-            for (int k = 0; k < chunk; ++k) HIP_TRY(launch_iter(k & 1, w->dP, cfg, w->stream));
+            for (int k = 0; k < chunk; ++k) HIP_TRY(launch_iter(k & 1, w->dP, ccfg, w->stream));
         }
         launched += chunk;
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
-            const bool run[kGridKernels] = {true, cfg.g_adj > 0, cfg.g_adjk > 0, true, cfg.g_gemm > 0};
+            const bool run[kGridKernels] = {true, ccfg.g_adj > 0, ccfg.g_adjk > 0, true, ccfg.g_gemm > 0};
             for (int it = 0; it < chunk; ++it)
                 for (int k = 0; k < kGridKernels; ++k) {
                     if (!run[k]) continue;
@@ -983,13 +1019,14 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
                     w->prof_n[k] += 1;
                 }
         }
-        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 48, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(launch_stat(w->dP, w->stream));
+        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 32, hipMemcpyDeviceToHost, w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (*w->h_active <= 0 || launched > cap) break;
         // the batched correlation product runs in the next chunk only if enough
         // signals qualified in this chunk's last iteration
         if (p.gemm_min > 0) {
-            const int on = w->h_active[4 + 4 + 3] >= kGemmMinSignals ? 1 : 0;
+            const int on = w->h_active[4 + 3] >= gemm_signals ? 1 : 0;
             if (on != p.gemm_on) {
                 p.gemm_on = on;
                 HIP_TRY(hipMemcpyAsync(&w->dP->gemm_on, &p.gemm_on, sizeof(int), hipMemcpyHostToDevice, w->stream));
@@ -997,8 +1034,9 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         }
         // hand the remaining iterations to the whole-solve kernel once every live
         // signal is on the last stage with a small preserved set (statistics of
-        // the chunk's last launch, slot 1)
-        const int* stat1 = w->h_active + 4 + 4;
+        // the chunk's last forward launch)
+        const int* stat1 = w->h_active + 4;
+        if (!last_kron && stat1[2] == 0) kron_live = false;
         if (hybrid && stat1[2] == 0) {
             // in Gram mode an iteration costs no N-length work: hand over as soon as
             // the largest preserved set fits the Gram capacity

@@ -361,7 +361,9 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
 //                       a^T y formed once on the exact dictionary and widened by its
 //                       rounding allowance eI ||y||
 // ag = |a~^T z|, Rg = the GAP radius to use, acy = |a^T y|, eI the exact stage's eps.
-__device__ __forceinline__ bool atom_test(int rule, const Scalars& S, double invlam, double Rg, double ag, double e,
+// SC: Scalars, or any record with the fields c1, c2, Rp, Rd, ny
+template <typename SC>
+__device__ __forceinline__ bool atom_test(int rule, const SC& S, double invlam, double Rg, double ag, double e,
                                           double an, double atn, double acy, double eI, double keep_min,
                                           double& kt) {
     if (rule) {

@@ -45,7 +45,8 @@ struct StageDesc {
 // t%2; every later kernel of iteration t reads slot t%2.
 struct Control {
     int stage, iter, done, status;
-    int ksince, par, advance, pad0;   // advance: the next iteration folds this one's results
+    int ksince, par, advance;         // advance: the next iteration folds this one's results
+    int nslot;                        // correlation-partial slots of the iteration (4 per item)
     int n_act, n_nz, nseg_act, nseg_nz;
     double lam, tau, l1;              // lambda, FISTA momentum sequence, ||x_t||_1
     long long t0;
@@ -106,12 +107,15 @@ struct SolveParams {
     int* cnt_adjk;            // [batch] work items of the Kronecker correlation launch
     int* cnt_upd;             // [batch] work items of the update launch (current iteration)
     int* cnt_gemm;            // [batch] 1: the signal's correlations go through the batched product
+    double* gemm_part;        // [kGemmSplitUnits][64 * 64] partial tiles of a split product launch
     int gemm_min;             // |A_t| from which a signal on the exact dense stage qualifies (0: never)
     int gemm_on;              // the batched product runs (set by the host between chunks)
     int* active_signals;      // one int: signals not yet done
-    int* stat;                // [2][4] per forward-launch slot: max and sum of |A_t| over live
-                              // signals, live signals not yet on the last stage, signals that
-                              // qualify for the batched correlation product
+    int* sig_stat;            // [batch][4] per live signal, written by each forward launch (zero
+                              // once done): |A_t|, |A_t|, not yet on the last stage, qualifies
+                              // for the batched correlation product
+    int* stat;                // [4] reduction of sig_stat after a chunk: max and sum of |A_t|,
+                              // count of signals not on the last stage, count that qualify
     int nseg_max, nrc, nadj_max, n1_max;
     // whole-solve engine: byte offsets of its dynamic LDS regions (-1: absent):
     // z in FP64 and FP32, y, the current stage's Kronecker factors, the scratch
@@ -140,6 +144,8 @@ constexpr int kIterOrder[kGridKernels] = {0, 1, 4, 2, 3};
 // batched correlation tiles: 64 atoms x 64 signals per block
 constexpr int kGemmAtoms = 64;
 constexpr int kGemmSig = 64;
+constexpr int kGemmMaxSplit = 8;     // row splits of one product tile
+constexpr int kGemmSplitUnits = 512; // partial tiles of one split launch at most
 #ifndef SL1_GEMM_MIN_SIGNALS
 #define SL1_GEMM_MIN_SIGNALS 64
 #endif

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         C.ksince = 0;
         C.par = 0;
         C.advance = 0;
-        C.pad0 = 0;
+        C.nslot = 0;
         C.n_act = K;
         C.n_nz = 0;
         C.nseg_act = nseg;
@@ -124,9 +124,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         P->cnt_adjk[b] = 0;
         P->cnt_upd[b] = 0;
         P->cnt_gemm[b] = 0;
+        for (int k = 0; k < 4; ++k) P->sig_stat[4 * b + k] = 0;
         if (ok) atomicAdd(P->active_signals, 1);
         if (b == 0) {
-            for (int k = 0; k < 8; ++k) P->stat[k] = 0;
+            for (int k = 0; k < 4; ++k) P->stat[k] = 0;
         }
     }
 }
@@ -142,11 +143,14 @@ __device__ __forceinline__ int adj_items(const StageDesc& st, int n_act, int N) 
 // C_t from C_{t-1}, the scalars of iteration t-1 and the update launch's
 // per-block partials; also the prefix counts of the two new compacted lists
 // (into LDS).  Identical in every block; returns 1 when the signal finished.
-__device__ int advance_control(const SolveParams* P, int b, const Control& Cp, Control& C, int* s_apre,
-                               int* s_zpre, double* s_red, int* s_tmp, Scalars& S, double& kt_out) {
+// Sp and up0 were fetched together with C_{t-1}: the signal's scalars and this
+// thread's first update partial (valid for threadIdx.x < min(nseg_max, blockDim)).
+__device__ int advance_control(const SolveParams* P, int b, const Control& Cp, const Scalars& Sp,
+                               const double (&up0)[4], Control& C, int* s_apre, int* s_zpre, double* s_red,
+                               int* s_tmp, Scalars& S, double& kt_out) {
     C = Cp;
     if (!Cp.advance) return 0;
-    S = P->sc[b];
+    S = Sp;
     if (S.conv) return 1;
     const int nblk = max(1, (Cp.n_act + kSeg - 1) / kSeg);
     int ak_tot = 0, az_tot = 0;
@@ -156,11 +160,18 @@ __device__ int advance_control(const SolveParams* P, int b, const Control& Cp, C
         int ck = 0, cz = 0;
         double a = 0.0, d = 0.0;
         if (k < nblk) {
-            const double* up = P->upd_part + ((size_t)b * P->nseg_max + k) * 4;
-            ck = (int)up[0];
-            cz = (int)up[1];
-            a = up[2];
-            d = up[3];
+            if (base == 0) {
+                ck = (int)up0[0];
+                cz = (int)up0[1];
+                a = up0[2];
+                d = up0[3];
+            } else {
+                const double* up = P->upd_part + ((size_t)b * P->nseg_max + k) * 4;
+                ck = (int)up[0];
+                cz = (int)up[1];
+                a = up[2];
+                d = up[3];
+            }
         }
         int ek, ez;
         const int tk = block_excl_scan(ck, ek, s_tmp);
@@ -342,13 +353,6 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                 P->cnt_fwd[(size_t)prev * batch + b] = 0;
                 P->ctrl[2 * b + slot].done = 1;
             }
-        // the other slot's statistics are gathered afresh by the next forward launch
-        if (threadIdx.x == 0) {
-            P->stat[4 * prev] = 0;
-            P->stat[4 * prev + 1] = 0;
-            P->stat[4 * prev + 2] = 0;
-            P->stat[4 * prev + 3] = 0;
-        }
     }
     const int per = (total + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
@@ -362,9 +366,20 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
         if (b != cur_b) {
             cur_b = b;
             // C_{t-1} read once for the whole block, so that every thread takes
-            // the same path through the barriers below
+            // the same path through the barriers below; the scalars of t-1 and the
+            // update partials are fetched in the same round trip (they are only
+            // used when C_{t-1} says so)
             __syncthreads();
             if (threadIdx.x == 0) s_cp = P->ctrl[2 * b + prev];
+            double up0[4] = {0.0, 0.0, 0.0, 0.0};
+            if ((int)threadIdx.x < P->nseg_max) {
+                const double* up = P->upd_part + ((size_t)b * P->nseg_max + threadIdx.x) * 4;
+                up0[0] = up[0];
+                up0[1] = up[1];
+                up0[2] = up[2];
+                up0[3] = up[3];
+            }
+            const Scalars Sp = P->sc[b];
             __syncthreads();
             const Control Cp = s_cp;
             if (Cp.done) {           // finished in an earlier launch: nothing to do
@@ -373,7 +388,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
             }
             Scalars S;
             double kt = 0.0;
-            finished = advance_control(P, b, Cp, C, s_apre, s_zpre, s_red, s_tmp, S, kt);
+            finished = advance_control(P, b, Cp, Sp, up0, C, s_apre, s_zpre, s_red, s_tmp, S, kt);
             if (finished) {
                 if (item == 0 && threadIdx.x == 0) {
                     Final F;
@@ -397,6 +412,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     P->cnt_upd[b] = 0;
                     P->cnt_gemm[b] = 0;
                     P->cnt_fwd[(size_t)prev * batch + b] = 0;
+                    *(int4*)(P->sig_stat + 4 * b) = make_int4(0, 0, 0, 0);
                     atomicSub(P->active_signals, 1);
                 }
             } else {
@@ -415,19 +431,19 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                         }
                     }
                     if (threadIdx.x == 0) {
-                        Control D = C;
-                        D.advance = 1;
-                        P->ctrl[2 * b + slot] = D;
-                        atomicMax(P->stat + 4 * slot, C.n_act);
-                        atomicAdd(P->stat + 4 * slot + 1, C.n_act);
-                        if (C.stage < P->n_stages - 1) atomicAdd(P->stat + 4 * slot + 2, 1);
                         const StageDesc& stn = P->st[C.stage];
                         const int items = adj_items(stn, C.n_act, N);
+                        Control D = C;
+                        D.advance = 1;
+                        D.nslot = 4 * items;
+                        P->ctrl[2 * b + slot] = D;
                         // large preserved sets on the exact dense stage join the batched product
                         // while enough signals qualify (the host decides between chunks)
                         const bool qual = P->gemm_min > 0 && C.stage == P->n_stages - 1 &&
                                           stn.kind == kDense && C.n_act >= P->gemm_min;
-                        if (qual) atomicAdd(P->stat + 4 * slot + 3, 1);
+                        // per-signal statistics, plain stores (reduced once per chunk)
+                        *(int4*)(P->sig_stat + 4 * b) =
+                            make_int4(C.n_act, C.n_act, C.stage < P->n_stages - 1 ? 1 : 0, qual ? 1 : 0);
                         const bool gemm = qual && P->gemm_on;
                         P->cnt_adj[b] = (stn.kind == kDense && !gemm) ? items : 0;
                         P->cnt_adjk[b] = stn.kind == kKron ? items : 0;
@@ -757,6 +773,46 @@ __device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double* 
     yz = v[2];
 }
 
+// the residual sums together with three maxima already loaded by the caller:
+// one pass of barriers (sums in the same fixed order as block_sum; red: 96 doubles)
+__device__ __forceinline__ void reduce_res_max(const SolveParams* P, int b, double* red, double (&mx)[3], double& r2,
+                                               double& zz, double& yz) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < P->nrc; k += blockDim.x) {
+        const double* rp = P->res_part + ((size_t)b * P->nrc + k) * 3;
+        v[0] += rp[0];
+        v[1] += rp[1];
+        v[2] += rp[2];
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = wave_sum(v[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            red[k * 16 + w] = v[k];
+            red[48 + k * 16 + w] = mx[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double a = 0.0, m = red[48 + k * 16];
+        for (int q = 0; q < nw; ++q) a += red[k * 16 + q];
+        for (int q = 1; q < nw; ++q) m = fmax(m, red[48 + k * 16 + q]);
+        v[k] = a;
+        mx[k] = m;
+    }
+    __syncthreads();
+    r2 = v[0];
+    zz = v[1];
+    yz = v[2];
+}
+
 // ---------------------------------------------------------------------------
 // correlations over the preserved set: g_j = a~_j^T z for j in A_t, and the
 // per-wave maxima of the stable dual scaling (Section III-C).  Dense stages and
@@ -832,6 +888,10 @@ __global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __re
 // the FP64 accumulator holds D[4v + l/16][l%16] (atom, signal).  Per-16-atom
 // maxima of the stable dual scaling go to the slots the update launch reduces
 // (4 per 64-atom tile); the signal's remaining slots are zeroed.
+// One block's tile is bound by its waves' MFMA rate, so while the tiles are
+// fewer than half the blocks each tile's rows are split over up to
+// kGemmMaxSplit blocks: they store partial tiles, and k_gemm_fin, launched
+// right after, sums each tile's partials in split order and finishes it.
 // ---------------------------------------------------------------------------
 constexpr int kGR = 32;                 // rows per chunk
 constexpr int kGLdA = kGR + 1;          // LDS row length of a staged column (32-bit words)
@@ -941,23 +1001,117 @@ __device__ __forceinline__ void gemm_mul(const uint32_t* sa, const double* sz, i
     }
 }
 
+// the tile's rows, chunk by chunk: while chunk c is multiplied from one LDS
+// buffer, chunk c + 1 (already in registers) goes to the other and chunk c + 2
+// is loaded, so every chunk's loads have two chunk periods to arrive
+// chunks c0 .. c0 + nch - 1 of the tile (rows from 32 c0)
 template <int DT>
 __device__ void gemm_block_tile(const SolveParams* P, const StageDesc& st, int N, int K, int j0, const int* sig,
-                                int ns, uint32_t* sa0, uint32_t* sa1, double* sz0, double* sz1, int wa, int wsg,
-                                int li, int lk, f64x4 (&acc)[2][2]) {
-    GemmRegs<DT> g;
-    gemm_fetch<DT>(P, st, N, K, j0, sig, ns, 0, g);
-    gemm_put<DT>(g, N, 0, sa0, sz0);
+                                int ns, int c0, int nch, uint32_t* sa0, uint32_t* sa1, double* sz0, double* sz1,
+                                int wa, int wsg, int li, int lk, f64x4 (&acc)[2][2]) {
+    const int r0 = c0 * kGR;
+    GemmRegs<DT> g0, g1;
+    gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0, g0);
+    if (nch > 1) gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0 + kGR, g1);
+    gemm_put<DT>(g0, N, r0, sa0, sz0);
     __syncthreads();
-    int buf = 0;
-    for (int r0 = 0; r0 < N; r0 += kGR) {
-        const bool more = r0 + kGR < N;
-        // the next chunk's loads are in flight while this one is multiplied
-        if (more) gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0 + kGR, g);
-        gemm_mul<DT>(buf ? sa1 : sa0, buf ? sz1 : sz0, wa, wsg, li, lk, acc);
-        if (more) gemm_put<DT>(g, N, r0 + kGR, buf ? sa0 : sa1, buf ? sz0 : sz1);
+    if (nch > 2) gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0 + 2 * kGR, g0);
+    for (int c = 0; c < nch; ++c) {
+        const bool odd = c & 1;
+        gemm_mul<DT>(odd ? sa1 : sa0, odd ? sz1 : sz0, wa, wsg, li, lk, acc);
+        if (c + 1 < nch) {
+            // chunk c + 1 sits in g1 when c is even, in g0 when c is odd
+            if (!odd) gemm_put<DT>(g1, N, r0 + (c + 1) * kGR, sa1, sz1);
+            else gemm_put<DT>(g0, N, r0 + (c + 1) * kGR, sa0, sz0);
+        }
         __syncthreads();
-        buf ^= 1;
+        if (c + 3 < nch) {
+            if (!odd) gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0 + (c + 3) * kGR, g1);
+            else gemm_fetch<DT>(P, st, N, K, j0, sig, ns, r0 + (c + 3) * kGR, g0);
+        }
+    }
+}
+
+// tiles and row splits of one product launch (identical in k_adj_gemm and k_gemm_fin)
+struct GemmPlan {
+    int nat, tiles, ks, cps, nch;
+};
+__device__ __forceinline__ GemmPlan gemm_plan(int S, int N, int K, int grid) {
+    GemmPlan g;
+    g.nat = (K + kGemmAtoms - 1) / kGemmAtoms;
+    g.tiles = g.nat * ((S + kGemmSig - 1) / kGemmSig);
+    g.nch = (N + kGR - 1) / kGR;
+    int ks = 1;
+    if (2 * g.tiles <= grid) ks = max(1, min(min(kGemmMaxSplit, g.nch), min(grid, kGemmSplitUnits) / g.tiles));
+    g.cps = (g.nch + ks - 1) / ks;                      // chunks per split
+    g.ks = (g.nch + g.cps - 1) / g.cps;                 // no empty split
+    return g;
+}
+
+// g, the per-16-atom maxima and the zeroed extra slots of one finished tile
+__device__ void gemm_epilogue(const SolveParams* P, const StageDesc& st, int slot, const int* s_sig, int s0, int ns,
+                              int j0, int ta, int nat, int wa, int wsg, int li, int lk, const f64x4 (&acc)[2][2]) {
+    const int N = P->N, K = P->K;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // lane: signals s0 + 32 wsg + 16 p + li, atoms j0 + 32 wa + 16 q + 4 v + lk
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int sl = 32 * wsg + 16 * p + li;
+        int b = 0, par = 0;
+        double rz = 0.0;
+        if (sl < ns) {
+            b = s_sig[s0 + sl];
+            par = P->ctrl[2 * b + slot].par;
+            double zz = 0.0;
+            for (int k = 0; k < P->nrc; ++k) zz += P->res_part[((size_t)b * P->nrc + k) * 3 + 1];
+            rz = sqrt(zz);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            double mx[3] = {0.0, 0.0, 0.0};
+            if (sl < ns) {
+                double* gv = gbuf(P, b, par);
+                const uint8_t* mk = P->mask + (size_t)b * K;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = j0 + 32 * wa + 16 * q + 4 * v + lk;
+                    if (j < K && mk[j]) {
+                        double gval = acc[q][p][v];
+                        if (st.scale) gval *= (double)st.scale[j];
+                        gv[j] = gval;
+                        const double e = st.eps[j];
+                        mx[0] = fmax(mx[0], fabs(gval) + e * rz);
+                        mx[1] = fmax(mx[1], fabs(gval));
+                        mx[2] = fmax(mx[2], e);
+                    }
+                }
+            }
+            // the four lanes of a signal (l % 16 equal) combine their atoms
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                mx[k] = fmax(mx[k], __shfl_xor(mx[k], 16, 64));
+                mx[k] = fmax(mx[k], __shfl_xor(mx[k], 32, 64));
+            }
+            if (lk == 0 && sl < ns) {
+                double* ap = P->adj_part + (((size_t)b * P->nadj_max + ta) * 4 + 2 * wa + q) * 3;
+                ap[0] = mx[0];
+                ap[1] = mx[1];
+                ap[2] = mx[2];
+            }
+        }
+    }
+    // slots beyond the 64-atom tiles, up to what the update launch reads, are zero
+    if (ta == 0) {
+        for (int sl = w; sl < ns; sl += kBlock / 64) {
+            const int b = s_sig[s0 + sl];
+            const int slots = 4 * adj_items(st, P->ctrl[2 * b + slot].n_act, N);
+            double* ap = P->adj_part + (size_t)b * P->nadj_max * 4 * 3;
+            for (int k = 4 * nat + l; k < slots; k += 64) {
+                ap[(size_t)k * 3] = 0.0;
+                ap[(size_t)k * 3 + 1] = 0.0;
+                ap[(size_t)k * 3 + 2] = 0.0;
+            }
+        }
     }
 }
 
@@ -977,87 +1131,97 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_gemm(const SolveParams* __res
     for (int b = threadIdx.x; b < batch; b += kBlock)
         if (s_pre[b + 1] > s_pre[b]) s_sig[s_pre[b]] = b;
     __syncthreads();
-    const int nat = (K + kGemmAtoms - 1) / kGemmAtoms, nst = (S + kGemmSig - 1) / kGemmSig;
-    const int total = nat * nst;
+    const GemmPlan pl = gemm_plan(S, N, K, gridDim.x);
+    const int nat = pl.nat, total = pl.tiles * pl.ks;
     const int per = (total + gridDim.x - 1) / gridDim.x;
     const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     const int wa = w & 1, wsg = w >> 1;                 // the wave's atom half and signal half
-    for (int g = g0; g < g1; ++g) {
+    for (int u = g0; u < g1; ++u) {
+        const int g = u / pl.ks, ks = u - g * pl.ks;
         const int ts = g / nat, ta = g - ts * nat;      // signal tile outer, atom tile inner
         const int s0 = ts * kGemmSig, j0 = ta * kGemmAtoms;
         const int ns = min(kGemmSig, S - s0);
+        const int c0 = ks * pl.cps, nc = min(pl.nch, c0 + pl.cps) - c0;
         f64x4 acc[2][2];
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int p = 0; p < 2; ++p) acc[q][p] = f64x4{0.0, 0.0, 0.0, 0.0};
         switch (st.dtype) {
-            case SL1_F64: gemm_block_tile<SL1_F64>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
-            case SL1_F32: gemm_block_tile<SL1_F32>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
-            case SL1_BF16: gemm_block_tile<SL1_BF16>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
-            default: gemm_block_tile<SL1_FP8_E4M3>(P, st, N, K, j0, s_sig + s0, ns, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            case SL1_F64: gemm_block_tile<SL1_F64>(P, st, N, K, j0, s_sig + s0, ns, c0, nc, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            case SL1_F32: gemm_block_tile<SL1_F32>(P, st, N, K, j0, s_sig + s0, ns, c0, nc, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            case SL1_BF16: gemm_block_tile<SL1_BF16>(P, st, N, K, j0, s_sig + s0, ns, c0, nc, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
+            default: gemm_block_tile<SL1_FP8_E4M3>(P, st, N, K, j0, s_sig + s0, ns, c0, nc, sa0, sa1, sz0, sz1, wa, wsg, li, lk, acc); break;
         }
-        // lane: signals s0 + 32 wsg + 16 p + li, atoms j0 + 32 wa + 16 q + 4 v + lk
+        if (pl.ks > 1) {
+            // partial tile, element-major (coalesced): [unit][16 accumulator entries][256 threads];
+            // k_gemm_fin reads it after this launch
+            double* part = P->gemm_part + (size_t)u * (kGemmAtoms * kGemmSig);
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int sl = 32 * wsg + 16 * p + li;
-            int b = 0, par = 0;
-            double rz = 0.0;
-            if (sl < ns) {
-                b = s_sig[s0 + sl];
-                par = P->ctrl[2 * b + slot].par;
-                double zz = 0.0;
-                for (int k = 0; k < P->nrc; ++k) zz += P->res_part[((size_t)b * P->nrc + k) * 3 + 1];
-                rz = sqrt(zz);
-            }
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                double mx[3] = {0.0, 0.0, 0.0};
-                if (sl < ns) {
-                    double* gv = gbuf(P, b, par);
-                    const uint8_t* mk = P->mask + (size_t)b * K;
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int j = j0 + 32 * wa + 16 * q + 4 * v + lk;
-                        if (j < K && mk[j]) {
-                            double gval = acc[q][p][v];
-                            if (st.scale) gval *= (double)st.scale[j];
-                            gv[j] = gval;
-                            const double e = st.eps[j];
-                            mx[0] = fmax(mx[0], fabs(gval) + e * rz);
-                            mx[1] = fmax(mx[1], fabs(gval));
-                            mx[2] = fmax(mx[2], e);
-                        }
-                    }
-                }
-                // the four lanes of a signal (l % 16 equal) combine their atoms
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    mx[k] = fmax(mx[k], __shfl_xor(mx[k], 16, 64));
-                    mx[k] = fmax(mx[k], __shfl_xor(mx[k], 32, 64));
-                }
-                if (lk == 0 && sl < ns) {
-                    double* ap = P->adj_part + (((size_t)b * P->nadj_max + ta) * 4 + 2 * wa + q) * 3;
-                    ap[0] = mx[0];
-                    ap[1] = mx[1];
-                    ap[2] = mx[2];
-                }
-            }
+                    for (int v = 0; v < 4; ++v) part[((q * 2 + p) * 4 + v) * kBlock + threadIdx.x] = acc[q][p][v];
+            continue;
         }
-        // slots beyond the 64-atom tiles, up to what the update launch reads, are zero
-        if (ta == 0) {
-            for (int sl = w; sl < ns; sl += kBlock / 64) {
-                const int b = s_sig[s0 + sl];
-                const int slots = 4 * adj_items(st, P->ctrl[2 * b + slot].n_act, N);
-                double* ap = P->adj_part + (size_t)b * P->nadj_max * 4 * 3;
-                for (int k = 4 * nat + l; k < slots; k += 64) {
-                    ap[(size_t)k * 3] = 0.0;
-                    ap[(size_t)k * 3 + 1] = 0.0;
-                    ap[(size_t)k * 3 + 2] = 0.0;
+        gemm_epilogue(P, st, slot, s_sig, s0, ns, j0, ta, nat, wa, wsg, li, lk, acc);
+    }
+}
+
+// split product tiles: the partials summed in split order, then the tile's
+// epilogue (one block per tile; nothing to do when the launch did not split)
+__global__ __launch_bounds__(kBlock, 2) void k_gemm_fin(const SolveParams* __restrict__ P, int slot, int gemm_grid) {
+    extern __shared__ __align__(16) char smem[];
+    const int N = P->N, K = P->K, batch = P->batch;
+    const StageDesc& st = P->st[P->n_stages - 1];
+    int* s_pre = (int*)smem;                                              // [batch + 1]
+    int* s_sig = s_pre + batch + 1;
+    __shared__ int s_tmp[16];
+    const int S = build_work_map(P->cnt_gemm, batch, s_pre, s_tmp);
+    if (S == 0) return;
+    const GemmPlan pl = gemm_plan(S, N, K, gemm_grid);
+    if (pl.ks == 1) return;
+    for (int b = threadIdx.x; b < batch; b += kBlock)
+        if (s_pre[b + 1] > s_pre[b]) s_sig[s_pre[b]] = b;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int wa = w & 1, wsg = w >> 1;
+    for (int g = blockIdx.x; g < pl.tiles; g += gridDim.x) {
+        const int ts = g / pl.nat, ta = g - ts * pl.nat;
+        const int s0 = ts * kGemmSig, j0 = ta * kGemmAtoms;
+        const int ns = min(kGemmSig, S - s0);
+        const double* pt = P->gemm_part + (size_t)g * pl.ks * (kGemmAtoms * kGemmSig);
+        f64x4 acc[2][2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) acc[q][p] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // four splits' partials are loaded together, then added in split order
+        constexpr int kStep = 4;
+#pragma unroll 1
+        for (int k0 = 0; k0 < pl.ks; k0 += kStep) {
+            double part[kStep][16];
+#pragma unroll
+            for (int k = 0; k < kStep; ++k)
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    part[k][e] = k0 + k < pl.ks
+                                     ? pt[(size_t)(k0 + k) * (kGemmAtoms * kGemmSig) + e * kBlock + threadIdx.x]
+                                     : 0.0;
+#pragma unroll
+            for (int k = 0; k < kStep; ++k)
+                if (k0 + k < pl.ks) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+#pragma unroll
+                        for (int p = 0; p < 2; ++p)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc[q][p][v] += part[k][(q * 2 + p) * 4 + v];
                 }
-            }
         }
+        gemm_epilogue(P, st, slot, s_sig, s0, ns, j0, ta, pl.nat, wa, wsg, li, lk, acc);
     }
 }
 
@@ -1181,8 +1345,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
 // FP64 scalar block of iteration t from the per-block partials of the forward
 // and correlation launches; computed identically by every block that needs it.
 __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scalars& S, double* s_red) {
-    const StageDesc& st = P->st[C.stage];
-    const int nslots = 4 * adj_items(st, C.n_act, P->N);
+    const int nslots = C.nslot;
     double mx[3] = {0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
         const double* ap = P->adj_part + ((size_t)b * P->nadj_max * 4 + k) * 3;
@@ -1190,9 +1353,8 @@ __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scal
         mx[1] = fmax(mx[1], ap[1]);
         mx[2] = fmax(mx[2], ap[2]);
     }
-    block_max<3>(mx, s_red);
     double r2, zz, yz;
-    reduce_res(P, b, s_red, r2, zz, yz);
+    reduce_res_max(P, b, s_red, mx, r2, zz, yz);
     scalars_from(P, C, r2, zz, yz, mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
 }
 
@@ -1219,7 +1381,7 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
     const int K = P->K, batch = P->batch;
     int* s_pre = (int*)smem;
     int* s_wpre = s_pre + (P->nseg_max + 1);
-    __shared__ double s_red[48];
+    __shared__ double s_red[96];
     __shared__ int s_w[4];
     __shared__ int s_tmp[16];
     const int total = build_work_map(P->cnt_upd, batch, s_wpre, s_tmp);
@@ -1227,25 +1389,43 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
     const int g0 = blockIdx.x * per, g1 = min(total, g0 + per);
     int cur_b = -1;
     Control C;
-    Scalars S;
+    // the scalars the per-atom test and step use, block-uniform (scalar registers)
+    struct {
+        double c1, c2, Rp, Rd, ny, beta;
+        int conv;
+    } U;
     for (int g = g0; g < g1; ++g) {
         const int b = uni(find_signal(s_wpre, batch, g));
         const int c = uni(g - s_wpre[b]);
         if (b != cur_b) {
             cur_b = b;
             C = P->ctrl[2 * b + slot];
-            scalar_block(P, b, C, S, s_red);
+            // the list prefixes are fetched before the scalar block, so that both
+            // wait on the same memory round trip
             const int* ap = actpre(P, b, C.par);
-            for (int s = threadIdx.x; s <= C.nseg_act; s += kBlock) s_pre[s] = ap[s];
+            const int pv0 = (int)threadIdx.x <= C.nseg_act ? ap[threadIdx.x] : 0;
+            Scalars S;
+            scalar_block(P, b, C, S, s_red);
+            // the block holding the signal's first item stores them (items of a
+            // signal are consecutive, so item 0 is the first one a block meets)
+            if (c == 0 && threadIdx.x == 0) {
+                Scalars T = S;
+                if (T.conv == 1) T.tconv = wall_clock64();
+                P->sc[b] = T;
+                P->cnt_fwd[(size_t)(1 - slot) * batch + b] = P->nrc;
+            }
+            U.c1 = uni(S.c1);
+            U.c2 = uni(S.c2);
+            U.Rp = uni(S.Rp);
+            U.Rd = uni(S.Rd);
+            U.ny = uni(S.ny);
+            U.beta = uni(S.beta);
+            U.conv = uni(S.conv);
+            if ((int)threadIdx.x <= C.nseg_act) s_pre[threadIdx.x] = pv0;
+            for (int s = threadIdx.x + kBlock; s <= C.nseg_act; s += kBlock) s_pre[s] = ap[s];
             __syncthreads();
         }
-        if (c == 0 && threadIdx.x == 0) {
-            Scalars T = S;
-            if (T.conv == 1) T.tconv = wall_clock64();
-            P->sc[b] = T;
-            P->cnt_fwd[(size_t)(1 - slot) * batch + b] = P->nrc;
-        }
-        if (S.conv) continue;
+        if (U.conv) continue;
         const int par = C.par, n_act = C.n_act;
         const StageDesc& st = P->st[C.stage];
         const int i = c * kSeg + threadIdx.x;
@@ -1267,12 +1447,12 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             const int rule = P->rule;
             const double acy = rule ? fabs(P->cy[(size_t)b * K + j]) : 0.0;
             const double eI = rule ? P->st[P->n_stages - 1].eps[j] : 0.0;
-            keep = atom_test(rule, S, 1.0 / C.lam, S.Rp, ag, e, P->atom_norm[j], st.at_norm[j], acy, eI,
+            keep = atom_test(rule, U, 1.0 / C.lam, U.Rp, ag, e, P->atom_norm[j], st.at_norm[j], acy, eI,
                              1.0 - P->margin, kt);
             if (C.iter % P->screen_every != 0) keep = true;    // rejections only every screen_every
             // FISTA (or ISTA: beta = 0) step on the preserved coefficients; the gradient at
             // the extrapolated point follows from the two correlation vectors by linearity
-            const double beta = S.beta;
+            const double beta = U.beta;
             const double zpt = xt + beta * (xt - xp);
             const double h = (1.0 + beta) * gt - beta * gp;
             const double v = zpt + h * st.invL;
@@ -1305,6 +1485,37 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             up[2] = sums[0];
             up[3] = sums[1];
         }
+    }
+}
+
+// statistics of the last forward launch, reduced over the batch once per chunk
+// (max and sum of |A_t|, signals not on the last stage, signals qualifying for
+// the batched correlation product); one block
+__global__ __launch_bounds__(kBlock) void k_stat(const SolveParams* __restrict__ P) {
+    __shared__ int s_v[4][kBlock / 64];
+    int v[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < P->batch; b += kBlock) {
+        const int4 q = *(const int4*)(P->sig_stat + 4 * b);
+        v[0] = max(v[0], q.x);
+        v[1] += q.y;
+        v[2] += q.z;
+        v[3] += q.w;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = max(v[0], __shfl_xor(v[0], o));
+        v[1] += __shfl_xor(v[1], o);
+        v[2] += __shfl_xor(v[2], o);
+        v[3] += __shfl_xor(v[3], o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; ++k) s_v[k][w] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        int a = s_v[k][0];
+        for (int q = 1; q < kBlock / 64; ++q) a = k == 0 ? max(a, s_v[k][q]) : a + s_v[k][q];
+        P->stat[k] = a;
     }
 }
 
@@ -1455,7 +1666,13 @@ hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCf
             if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
             break;
         case 4:
-            if (c.g_gemm > 0) hipLaunchKernelGGL(k_adj_gemm, dim3(c.g_gemm), dim3(kBlock), c.lds_gemm, s, dP, slot);
+            // the batched product and, right behind it, the pass that finishes split tiles
+            if (c.g_gemm > 0) {
+                hipLaunchKernelGGL(k_adj_gemm, dim3(c.g_gemm), dim3(kBlock), c.lds_gemm, s, dP, slot);
+                const int gf = std::max(1, std::min(c.g_gemm / 2, kGemmSplitUnits));
+                hipLaunchKernelGGL(k_gemm_fin, dim3(gf), dim3(kBlock), 4 * (2 * (size_t)c.batch + 1), s, dP, slot,
+                                   c.g_gemm);
+            }
             break;
         default: hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot); break;
     }
@@ -1496,6 +1713,20 @@ hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int3
 hipError_t gemm_lds_attr(size_t lds) {
     if (lds <= 64 * 1024) return hipSuccess;
     return hipFuncSetAttribute((const void*)k_adj_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// blocks of the update kernel resident at once on the current device (0 on error)
+int upd_resident_blocks(size_t lds) {
+    int n = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_upd, kBlock, lds) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return n * cus;
+}
+
+hipError_t launch_stat(const SolveParams* dP, hipStream_t s) {
+    hipLaunchKernelGGL(k_stat, dim3(1), dim3(kBlock), 0, s, dP);
+    return hipGetLastError();
 }
 
 hipError_t launch_ysq(const SolveParams* dP, int batch, double* yy, hipStream_t s) {

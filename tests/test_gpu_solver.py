@@ -518,25 +518,43 @@ def test_dst_requires_a_dense_exact_stage(sl1):
 # ---------------------------------------------------------------------------
 # batched correlations (one FP64 matrix-core product for large preserved sets)
 # ---------------------------------------------------------------------------
+def _product_iterations(on, p, gmin, gemm_signals, chunk=16):
+    """Per iteration t, the number of signals whose correlations went through the
+    batched product: signals qualifying at t (exact dense stage, |A_t| >= gmin),
+    counted when the product ran in t's chunk (the first chunk: batch >=
+    gemm_signals; a later one: at least gemm_signals signals qualified at the
+    previous chunk's last iteration)."""
+    I = len(p.stages) - 1
+    n = int(np.max(on["iters"]))
+    q = np.zeros((p.batch, n + 1), dtype=bool)
+    for b in range(p.batch):
+        k = int(on["iters"][b])
+        tr = on["trace"][b][:k]
+        q[b, :k] = (tr[:, 1] == I) & (tr[:, 2] >= gmin)
+    cnt = q.sum(axis=0)
+    used = np.zeros(n + 1, dtype=np.int64)
+    for t in range(n + 1):
+        c = t // chunk
+        gate = p.batch >= gemm_signals if c == 0 else cnt[c * chunk - 1] >= gemm_signals
+        used[t] = cnt[t] if gate else 0
+    return used
+
+
 @pytest.mark.parametrize("rule", ["gap", "dst"])
 def test_batched_correlations_match_streaming(sl1, rule):
-    # grid engine with and without the batched product: same decisions, same x;
-    # the trace shows iterations that went through the product
+    # grid engine with the batched product forced on for any qualifying signal
+    # (gemm_signals=1) and without it: same decisions, same x.  With a handful of
+    # signals the product tiles are few, so their rows are split over blocks.
     import paper_1812_06635_amd as m
     used_by = {}
     for p in (synth.config4(batch=12), synth.config3(N=256, K=1024, s=20, batch=3),
               synth.config3(N=2500, K=600, s=20, batch=2)):
         _say(f"batched correlations vs streaming: {p.name} N={p.N} K={p.K} rule={rule}")
-        on = _run(sl1, p, tol=1e-9, engine="grid", rule=rule, trace_cap=20000)
+        on = _run(sl1, p, tol=1e-9, engine="grid", rule=rule, trace_cap=20000, gemm_signals=1)
         gmin = m.last_solve_phases(p.batch, p.N, p.K)[1]["gemm_min"]
         off = _run(sl1, p, tol=1e-9, engine="grid", rule=rule, batched_gemm=False)
         assert on["status"] == 0 and off["status"] == 0 and gmin > 0
-        I = len(p.stages) - 1
-        used = 0
-        for b in range(p.batch):
-            tr = on["trace"][b][:int(on["iters"][b])]
-            used += int(np.sum((tr[:, 1] == I) & (tr[:, 2] >= gmin)))
-        used_by[(p.name, p.N)] = used
+        used_by[(p.name, p.N)] = int(_product_iterations(on, p, gmin, 1).sum())
         np.testing.assert_array_equal(on["stage"], off["stage"])
         assert np.all(np.abs(on["iters"] - off["iters"]) <= 2), (on["iters"], off["iters"])
         for b in range(p.batch):
@@ -546,6 +564,43 @@ def test_batched_correlations_match_streaming(sl1, rule):
             _check_solution(p, on, b)
     # the batched dictionary and the small dense sequence do go through the product
     assert used_by[("C4", 1024)] > 0 and used_by[("C3", 256)] > 0, used_by
+
+
+def test_batched_product_many_and_few_signals_match_streaming(sl1):
+    # 320 signals: 300 copies of one signal, which qualify together (five signal
+    # tiles, one of them partial), and 20 distinct ones, which qualify a few at a
+    # time (one partial signal tile)
+    import dataclasses
+    import paper_1812_06635_amd as m
+    q = synth.config4(batch=21)
+    # the copied signal: the one qualifying at the most iterations
+    pre = _run(sl1, q, tol=1e-9, engine="grid", trace_cap=20000, gemm_signals=1)
+    gmin = m.last_solve_phases(q.batch, q.N, q.K)[1]["gemm_min"]
+    nq = [int(np.sum((pre["trace"][b][:int(pre["iters"][b]), 1] == len(q.stages) - 1) &
+                     (pre["trace"][b][:int(pre["iters"][b]), 2] >= gmin))) for b in range(q.batch)]
+    c = int(np.argmax(nq))
+    assert nq[c] > 0, nq
+    sel = np.array([c] * 300 + [b for b in range(q.batch) if b != c])
+    p = dataclasses.replace(q, Y=q.Y[sel].copy(), lam=q.lam[sel].copy(), X0=q.X0[sel].copy(),
+                            lam_max=q.lam_max[sel].copy())
+    _say(f"batched product, many and few signals: {p.name} batch={p.batch}")
+    on = _run(sl1, p, tol=1e-9, engine="grid", trace_cap=20000, gemm_signals=1)
+    gmin = m.last_solve_phases(p.batch, p.N, p.K)[1]["gemm_min"]
+    off = _run(sl1, p, tol=1e-9, engine="grid", batched_gemm=False)
+    assert on["status"] == 0 and off["status"] == 0 and gmin > 0
+    used = _product_iterations(on, p, gmin, 1)
+    assert used.max() > 256, used.max()                   # many signals at once
+    assert np.any((used > 0) & (used <= 64)), used        # one partial signal tile
+    np.testing.assert_array_equal(on["stage"], off["stage"])
+    assert np.all(np.abs(on["iters"] - off["iters"]) <= 2)
+    for b in range(p.batch):
+        rel = np.linalg.norm(on["x"][b] - off["x"][b]) / max(np.linalg.norm(off["x"][b]), 1e-300)
+        assert rel <= 1e-7, f"signal {b}: {rel:.2e}"
+    for b in (0, p.batch - 1):
+        _check_solution(p, on, b)
+    # the copies of one signal end identical
+    assert np.all(on["iters"][:300] == on["iters"][0])
+    np.testing.assert_array_equal(on["x"][:300], np.broadcast_to(on["x"][0], (300, p.K)))
 
 
 # ---------------------------------------------------------------------------
