@@ -75,6 +75,44 @@ def timed(torch, fn, steps, warmup):
 UPD_BYTES_PER_ATOM = 76.0   # test/update per preserved atom: index, 7 FP64 gathers, x and index writes
 
 
+def gemm_plan(S, N, K, batch):
+    """Tiles and row splits of one batched-product launch over S signals (the
+    rule the product kernel applies): (tiles, splits)."""
+    nat = -(-K // 64)
+    tiles = nat * -(-S // 64)
+    tiles_max = nat * -(-batch // 64)
+    grid = min(max(tiles_max, min(tiles_max * 8, 512)), 1024)
+    nch = -(-N // 32)
+    ks = 1
+    if 2 * tiles <= grid:
+        ks = max(1, min(8, nch, min(grid, 512) // tiles))
+    cps = -(-nch // ks)
+    return tiles, -(-nch // cps)
+
+
+def product_rows(p, trace, iters, t_split, gemm_min, gemm_signals=64, chunk=16):
+    """(batch, T) mask of the grid rows whose correlations went through the batched
+    product: the signal qualifies (exact dense stage, |A_t| >= gemm_min) and the
+    product ran in that chunk (the first chunk: batch >= gemm_signals; a later one:
+    at least gemm_signals signals qualified at the previous chunk's last row)."""
+    import numpy as np
+    T = int(min(t_split, int(iters.max())))
+    I = len(p.stages) - 1
+    q = np.zeros((trace.shape[0], T), dtype=bool)
+    if gemm_min <= 0 or p.stages[I].kind != "dense":
+        return q
+    for b in range(trace.shape[0]):
+        n = min(int(iters[b]), T)
+        q[b, :n] = (trace[b, :n, 1] == I) & (trace[b, :n, 2] >= gemm_min)
+    cnt = q.sum(axis=0)
+    for t in range(T):
+        c = t // chunk
+        on = p.batch >= gemm_signals if c == 0 else cnt[c * chunk - 1] >= gemm_signals
+        if not on:
+            q[:, t] = False
+    return q
+
+
 def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
     """Algorithmic work of each kernel over one solve, from the trace (rows
     t < t_split ran in the grid kernels, the rest in the tail kernel):
@@ -86,15 +124,23 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
                           keeps the per-atom state in LDS);
       tail, Gram form     rows with |A_t| <= gram_cap: the |A_t| columns read once
                           to form G and A_t^T y, then no HBM traffic per iteration;
-      batched product     grid rows on the exact dense stage with |A_t| >= gemm_min:
-                          2 N |A_t| FP64 flops (the needed entries; the product also
-                          forms the discarded ones, 2 N K per signal)."""
+      batched product     grid rows that went through it (product_rows): 2 N |A_t|
+                          FP64 flops (the needed entries; the product also forms
+                          the discarded ones, 2 N K per signal);
+      finishing pass      the partial tiles of row-split product launches, read
+                          once (64 x 64 doubles per tile and split)."""
     import numpy as np
     N = p.N
     w = dict(fwd_bytes=[0.0, 0.0], adj_bytes=[0.0, 0.0], adj_flops=[0.0, 0.0], upd_bytes=[0.0, 0.0],
-             gram_bytes=0.0, gram_it=0, gemm_flops=0.0, gemm_exec_flops=0.0, gemm_it=0,
+             gram_bytes=0.0, gram_it=0, gemm_flops=0.0, gemm_exec_flops=0.0, gemm_it=0, fin_bytes=0.0,
              dense_it=[0, 0], kron_it=[0, 0])
     I = len(p.stages) - 1
+    prod = product_rows(p, trace, iters, t_split, gemm_min)
+    for S in prod.sum(axis=0):
+        if S > 0:
+            tiles, ks = gemm_plan(int(S), N, p.K, p.batch)
+            if ks > 1:
+                w["fin_bytes"] += tiles * ks * 64 * 64 * 8.0
     for b in range(trace.shape[0]):
         n = int(iters[b])
         rows = trace[b, :n]
@@ -107,7 +153,9 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
             on = rows[:, 1] == s_idx
             g = on & gram
             if s_idx == I and st.kind == "dense" and gemm_min > 0:
-                gm = on & (part == 0) & (rows[:, 2] >= gemm_min)
+                gm = np.zeros(n, dtype=bool)
+                gm[:prod.shape[1]] = prod[b, :min(n, prod.shape[1])]
+                gm &= on
                 if gm.any():
                     w["gemm_flops"] += 2.0 * N * float(rows[gm, 2].sum())
                     w["gemm_exec_flops"] += 2.0 * N * p.K * int(gm.sum())
@@ -164,6 +212,8 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
         add("k_adj_gemm", *prof["adj_gemm"], work["gemm_flops"], "mfma", FP64_PEAK_TFLOPS)
         if out and out[-1]["kernel"] == "k_adj_gemm" and prof["adj_gemm"][0] > 0:
             out[-1]["executed_tflops"] = work["gemm_exec_flops"] / (prof["adj_gemm"][0] * 1e-3) / 1e12
+    if "gemm_fin" in prof:
+        add("k_gemm_fin", *prof["gemm_fin"], work["fin_bytes"], "hbm")
     if phases.get("wg_launches", 0) > 0:
         add(tail_kernel, phases["wg_ms"], phases["wg_launches"],
             work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1] + work["gram_bytes"], "hbm")
@@ -222,7 +272,8 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
 # sources whose change voids a recorded HBM-traffic figure of a kernel
 _GRID_SOURCES = ["paper_1812_06635_amd/csrc/sl1_kernels.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
                  "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
-TRAFFIC_SOURCES = {k: _GRID_SOURCES for k in ("k_adj_dense", "k_adj_gemm", "k_fwd", "k_upd", "k_adj_kron")}
+TRAFFIC_SOURCES = {k: _GRID_SOURCES for k in ("k_adj_dense", "k_adj_gemm", "k_gemm_fin", "k_fwd", "k_upd",
+                                               "k_adj_kron")}
 
 
 def sources_sha256(kernel):

@@ -271,7 +271,8 @@ int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, do
  * most recent sl1_solve with SL1_FLAG_PROFILE and these shapes: ms[k] total
  * milliseconds and launches[k] launch count of k = 0 forward/residual, 1 dense
  * correlations, 2 Kronecker correlations, 3 scalar block + test/update/compaction,
- * 4 batched dense correlations (host arrays of 5).
+ * 4 batched dense correlations, 5 the pass that finishes row-split product tiles
+ * (host arrays of 6).
  */
 int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
 

@@ -229,7 +229,7 @@ def last_solve_profile(batch, N, K):
     ms = (L.c_d * L.GRID_KERNELS)()
     n = (ctypes.c_longlong * L.GRID_KERNELS)()
     L.check(L.load().sl1_last_solve_profile(batch, N, K, ms, n), "sl1_last_solve_profile")
-    names = ("fwd", "adj_dense", "adj_kron", "upd", "adj_gemm")
+    names = ("fwd", "adj_dense", "adj_kron", "upd", "adj_gemm", "gemm_fin")
     return {names[k]: (ms[k], n[k]) for k in range(L.GRID_KERNELS)}
 
 

@@ -114,7 +114,7 @@ struct Workspace {
     double* d_cy = nullptr;   // stable Dynamic Safe: [batch][K] a^T y on the exact dictionary (lazy)
     double* d_yy = nullptr;   // [batch] ||y||^2
     double prof_ms[kGridKernels] = {};      // grid kernels: forward, dense / Kronecker correlations, update,
-    long long prof_n[kGridKernels] = {};    // batched correlations
+    long long prof_n[kGridKernels] = {};    // batched correlations and their finishing pass
     int last_gemm_min = 0;                  // |A_t| threshold of the batched correlations (0: off)
     long long* d_wgprof = nullptr;          // [batch][kWgPhases] phase clocks of the whole-solve engine
     double phase_ms[kWgPhases] = {0, 0, 0, 0};
@@ -326,8 +326,8 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
 }
 
 // |A_t| from which a signal on the exact dense stage joins the batched correlation
-// product: its update launch must read at least the 4 slots per 64-atom tile the
-// product writes, and the product must beat streaming (|A_t| >= K/8).
+// product, which forms all K correlations: at least K/8 preserved atoms and 4a per
+// 64-atom tile (a = atoms per wave of the streaming kernel).
 int gemm_min_atoms(const SolveParams& p) {
     const int per = 4 * (p.N <= 1024 ? 2 : 1);
     return std::max(per * ((p.K + kGemmAtoms - 1) / kGemmAtoms), std::max(1, p.K / 8));
@@ -1008,7 +1008,8 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         launched += chunk;
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
-            const bool run[kGridKernels] = {true, ccfg.g_adj > 0, ccfg.g_adjk > 0, true, ccfg.g_gemm > 0};
+            const bool run[kGridKernels] = {true, ccfg.g_adj > 0, ccfg.g_adjk > 0, true, ccfg.g_gemm > 0,
+                                            ccfg.g_gemm > 0};
             for (int it = 0; it < chunk; ++it)
                 for (int k = 0; k < kGridKernels; ++k) {
                     if (!run[k]) continue;

@@ -138,8 +138,8 @@ struct LaunchCfg {
 
 // grid kernels (profile order): forward, dense correlations, Kronecker correlations,
 // update, batched correlations; launch order within an iteration
-constexpr int kGridKernels = 5;
-constexpr int kIterOrder[kGridKernels] = {0, 1, 4, 2, 3};
+constexpr int kGridKernels = 6;
+constexpr int kIterOrder[kGridKernels] = {0, 1, 4, 5, 2, 3};
 
 // batched correlation tiles: 64 atoms x 64 signals per block
 constexpr int kGemmAtoms = 64;

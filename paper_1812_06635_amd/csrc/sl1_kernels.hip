@@ -433,18 +433,20 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     if (threadIdx.x == 0) {
                         const StageDesc& stn = P->st[C.stage];
                         const int items = adj_items(stn, C.n_act, N);
-                        Control D = C;
-                        D.advance = 1;
-                        D.nslot = 4 * items;
-                        P->ctrl[2 * b + slot] = D;
                         // large preserved sets on the exact dense stage join the batched product
                         // while enough signals qualify (the host decides between chunks)
                         const bool qual = P->gemm_min > 0 && C.stage == P->n_stages - 1 &&
                                           stn.kind == kDense && C.n_act >= P->gemm_min;
+                        const bool gemm = qual && P->gemm_on;
+                        Control D = C;
+                        D.advance = 1;
+                        // correlation-partial slots the update launch reduces: 4 per item, or
+                        // the product's 4 per 64-atom tile
+                        D.nslot = gemm ? 4 * ((P->K + kGemmAtoms - 1) / kGemmAtoms) : 4 * items;
+                        P->ctrl[2 * b + slot] = D;
                         // per-signal statistics, plain stores (reduced once per chunk)
                         *(int4*)(P->sig_stat + 4 * b) =
                             make_int4(C.n_act, C.n_act, C.stage < P->n_stages - 1 ? 1 : 0, qual ? 1 : 0);
-                        const bool gemm = qual && P->gemm_on;
                         P->cnt_adj[b] = (stn.kind == kDense && !gemm) ? items : 0;
                         P->cnt_adjk[b] = stn.kind == kKron ? items : 0;
                         P->cnt_gemm[b] = gemm ? 1 : 0;
@@ -887,7 +889,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __re
 // operands: lane l gives A[atom l%16][row 4k + l/16] and z[signal l%16][same row];
 // the FP64 accumulator holds D[4v + l/16][l%16] (atom, signal).  Per-16-atom
 // maxima of the stable dual scaling go to the slots the update launch reduces
-// (4 per 64-atom tile); the signal's remaining slots are zeroed.
+// (4 per 64-atom tile).
 // One block's tile is bound by its waves' MFMA rate, so while the tiles are
 // fewer than half the blocks each tile's rows are split over up to
 // kGemmMaxSplit blocks: they store partial tiles, and k_gemm_fin, launched
@@ -1048,38 +1050,58 @@ __device__ __forceinline__ GemmPlan gemm_plan(int S, int N, int K, int grid) {
     return g;
 }
 
-// g, the per-16-atom maxima and the zeroed extra slots of one finished tile
+// g and the per-16-atom maxima of one finished tile (the update launch reduces
+// exactly the 4 slots per 64-atom tile written here).  Everything the epilogue
+// reads is loaded first (one memory round trip).
 __device__ void gemm_epilogue(const SolveParams* P, const StageDesc& st, int slot, const int* s_sig, int s0, int ns,
                               int j0, int ta, int nat, int wa, int wsg, int li, int lk, const f64x4 (&acc)[2][2]) {
-    const int N = P->N, K = P->K;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int K = P->K, nrc = P->nrc;
     // lane: signals s0 + 32 wsg + 16 p + li, atoms j0 + 32 wa + 16 q + 4 v + lk
+    int bp[2], par[2];
+    bool sv[2];
+    double zz[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const int sl = 32 * wsg + 16 * p + li;
-        int b = 0, par = 0;
-        double rz = 0.0;
-        if (sl < ns) {
-            b = s_sig[s0 + sl];
-            par = P->ctrl[2 * b + slot].par;
-            double zz = 0.0;
-            for (int k = 0; k < P->nrc; ++k) zz += P->res_part[((size_t)b * P->nrc + k) * 3 + 1];
-            rz = sqrt(zz);
+        sv[p] = sl < ns;
+        bp[p] = sv[p] ? s_sig[s0 + sl] : 0;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        par[p] = P->ctrl[2 * bp[p] + slot].par;
+        zz[p] = 0.0;
+        for (int k = 0; k < nrc; ++k) zz[p] += P->res_part[((size_t)bp[p] * nrc + k) * 3 + 1];
+    }
+    double ev[2][4], scv[2][4];
+    uint8_t mkv[2][2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = j0 + 32 * wa + 16 * q + 4 * v + lk;
+            const bool jin = j < K;
+            ev[q][v] = jin ? st.eps[j] : 0.0;
+            scv[q][v] = (jin && st.scale) ? (double)st.scale[j] : 1.0;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) mkv[p][q][v] = (sv[p] && jin) ? P->mask[(size_t)bp[p] * K + j] : (uint8_t)0;
         }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int b = bp[p];
+        const double rz = sqrt(zz[p]);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             double mx[3] = {0.0, 0.0, 0.0};
-            if (sl < ns) {
-                double* gv = gbuf(P, b, par);
-                const uint8_t* mk = P->mask + (size_t)b * K;
+            if (sv[p]) {
+                double* gv = gbuf(P, b, par[p]);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int j = j0 + 32 * wa + 16 * q + 4 * v + lk;
-                    if (j < K && mk[j]) {
+                    if (mkv[p][q][v]) {
                         double gval = acc[q][p][v];
-                        if (st.scale) gval *= (double)st.scale[j];
+                        if (st.scale) gval *= scv[q][v];
                         gv[j] = gval;
-                        const double e = st.eps[j];
+                        const double e = ev[q][v];
                         mx[0] = fmax(mx[0], fabs(gval) + e * rz);
                         mx[1] = fmax(mx[1], fabs(gval));
                         mx[2] = fmax(mx[2], e);
@@ -1092,24 +1114,11 @@ __device__ void gemm_epilogue(const SolveParams* P, const StageDesc& st, int slo
                 mx[k] = fmax(mx[k], __shfl_xor(mx[k], 16, 64));
                 mx[k] = fmax(mx[k], __shfl_xor(mx[k], 32, 64));
             }
-            if (lk == 0 && sl < ns) {
+            if (lk == 0 && sv[p]) {
                 double* ap = P->adj_part + (((size_t)b * P->nadj_max + ta) * 4 + 2 * wa + q) * 3;
                 ap[0] = mx[0];
                 ap[1] = mx[1];
                 ap[2] = mx[2];
-            }
-        }
-    }
-    // slots beyond the 64-atom tiles, up to what the update launch reads, are zero
-    if (ta == 0) {
-        for (int sl = w; sl < ns; sl += kBlock / 64) {
-            const int b = s_sig[s0 + sl];
-            const int slots = 4 * adj_items(st, P->ctrl[2 * b + slot].n_act, N);
-            double* ap = P->adj_part + (size_t)b * P->nadj_max * 4 * 3;
-            for (int k = 4 * nat + l; k < slots; k += 64) {
-                ap[(size_t)k * 3] = 0.0;
-                ap[(size_t)k * 3 + 1] = 0.0;
-                ap[(size_t)k * 3 + 2] = 0.0;
             }
         }
     }
@@ -1666,9 +1675,10 @@ hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCf
             if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
             break;
         case 4:
-            // the batched product and, right behind it, the pass that finishes split tiles
+            if (c.g_gemm > 0) hipLaunchKernelGGL(k_adj_gemm, dim3(c.g_gemm), dim3(kBlock), c.lds_gemm, s, dP, slot);
+            break;
+        case 5:     // finishes the tiles of a row-split product launch (right after it)
             if (c.g_gemm > 0) {
-                hipLaunchKernelGGL(k_adj_gemm, dim3(c.g_gemm), dim3(kBlock), c.lds_gemm, s, dP, slot);
                 const int gf = std::max(1, std::min(c.g_gemm / 2, kGemmSplitUnits));
                 hipLaunchKernelGGL(k_gemm_fin, dim3(gf), dim3(kBlock), 4 * (2 * (size_t)c.batch + 1), s, dP, slot,
                                    c.g_gemm);
