@@ -28,6 +28,7 @@ hipError_t launch_ysq(const SolveParams*, int, double*, hipStream_t);
 hipError_t launch_stat(const SolveParams*, hipStream_t);
 int upd_resident_blocks(size_t);
 hipError_t gemm_lds_attr(size_t);
+hipError_t fwd_lds_attr(size_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
@@ -280,7 +281,7 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     c.nadj_max = w.nadj_max;
     const size_t ws = 8;
     const size_t nseg1 = (size_t)w.nseg_max + 1, nb1 = (size_t)w.batch + 1;
-    c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + 4 * 256 * 8;
+    c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + 4 * 256 * 8 + (size_t)p.fwd_fac_lds;
     c.lds_upd = 4 * (nseg1 + nb1);
     // persistent grids: enough blocks to fill the chip, never more than the work;
     // a correlation kernel whose stage kind is absent is not launched
@@ -452,6 +453,7 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
     const sl1_dict_s* d0 = seq[0];
     if (!d0) return SL1_EINVAL;
     int n1_max = 0;
+    size_t fac = 0;
     for (int i = 0; i < n_stages; ++i) {
         const sl1_dict_s* d = seq[i];
         if (!d) return SL1_EINVAL;
@@ -461,8 +463,15 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
         const double rci = rc ? rc[i] : d->rc_model;
         if (!std::isfinite(rci)) return SL1_EINVAL;
         fill_stage(p.st[i], *d, Li, rci);
-        if (d->kind == kKron) n1_max = std::max(n1_max, d->n1);
+        if (d->kind == kKron) {
+            n1_max = std::max(n1_max, d->n1);
+            // the forward kernel stages a Kronecker stage's factors in LDS when they fit
+            const size_t es = d->dtype == SL1_F64 ? 8 : (d->dtype == SL1_F32 ? 4 : 2);
+            const size_t fb = (size_t)d->R * ((size_t)d->n1 * d->k1 + (size_t)d->n2 * d->k2) * es;
+            if (fb <= (size_t)kFwdFacLds) fac = std::max(fac, fb);
+        }
     }
+    p.fwd_fac_lds = (int)fac;
     p.n_stages = n_stages;
     p.N = (int)d0->N;
     p.K = (int)d0->K;
@@ -820,6 +829,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     p.batch = (int)batch;
     p.y_f64 = tmp.y_f64;
     p.n1_max = tmp.n1_max;
+    p.fwd_fac_lds = tmp.fwd_fac_lds;
     p.max_iter = 0;
     p.trace = nullptr;
     p.trace_cap = 0;
@@ -888,6 +898,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.batch = (int)batch;
     p.y_f64 = tmp.y_f64;
     p.n1_max = tmp.n1_max;
+    p.fwd_fac_lds = tmp.fwd_fac_lds;
     p.max_iter = o.max_iter;
     p.trace = o.trace;
     p.trace_cap = o.trace ? o.trace_cap : 0;
@@ -936,6 +947,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     }
     if (o.flags & SL1_FLAG_NO_GEMM) cfg.g_gemm = 0;
     if (cfg.g_gemm > 0) HIP_TRY(gemm_lds_attr(cfg.lds_gemm));
+    if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     p.gemm_min = cfg.g_gemm > 0 ? gemm_min_atoms(p) : 0;
     const int gemm_signals = o.gemm_signals > 0 ? o.gemm_signals : kGemmMinSignals;
     p.gemm_on = p.gemm_min > 0 && batch >= gemm_signals;
@@ -1083,6 +1095,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.batch = (int)batch;
     p.y_f64 = tmp.y_f64;
     p.n1_max = tmp.n1_max;
+    p.fwd_fac_lds = tmp.fwd_fac_lds;
     p.max_iter = 0;
     p.trace = nullptr;
     p.trace_cap = 0;
@@ -1167,6 +1180,7 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
         p.batch = (int)batch;
         p.y_f64 = tmp.y_f64;
         p.n1_max = tmp.n1_max;
+        p.fwd_fac_lds = tmp.fwd_fac_lds;
         p.max_iter = 0;
         p.trace = nullptr;
         p.trace_cap = 0;

@@ -13,6 +13,8 @@ constexpr int kWave = 64;
 constexpr int kSeg = 256;           // atoms per segment of a compacted list (one update block)
 constexpr int kFwdRows = 1024;      // rows per forward item: 4 sub-chunks of 256 (4 per lane), 2 waves each
 constexpr int kFwdBlock = 512;      // forward block: 8 waves share the nonzeros of x
+constexpr int kFwdFacLds = 48 * 1024;   // largest Kronecker factor set staged in the forward LDS
+constexpr int kFwdFacNnz = 32;          // nonzeros from which a block stages the factors
 constexpr int kFwdWaves = kFwdBlock / 64;
 constexpr int kMaxSeg = 1024;       // segments of a compacted list (K <= 262144)
 constexpr int kKronColTile = 64;    // atoms (j1) per Kronecker-adjoint block (16 per wave)
@@ -117,6 +119,9 @@ struct SolveParams {
     int* stat;                // [4] reduction of sig_stat after a chunk: max and sum of |A_t|,
                               // count of signals not on the last stage, count that qualify
     int nseg_max, nrc, nadj_max, n1_max;
+    int fwd_fac_lds;          // bytes of the forward kernel's LDS region for a Kronecker stage's
+                              // factors (0: none); a stage whose factors fit is staged there
+                              // for signals with many nonzeros
     // whole-solve engine: byte offsets of its dynamic LDS regions (-1: absent):
     // z in FP64 and FP32, y, the current stage's Kronecker factors, the scratch
     // (staging, cross-wave sums, Kronecker intermediate), the nonzero list (index

@@ -249,9 +249,11 @@ __device__ __forceinline__ void fwd_dense_gather(const StageDesc& st, int N, int
     }
 }
 
+// Bsrc / Csrc: the stage's factors, in global memory or staged in LDS (same layout)
 template <int DT>
-__device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, int r0, const int* s_j, const double* s_x,
-                                                int k0, int k1, double (&acc)[4]) {
+__device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, const void* Bsrc, const void* Csrc, int r0,
+                                                const int* s_j, const double* s_x, int k0, int k1,
+                                                double (&acc)[4]) {
     constexpr int G = DT == SL1_F64 ? 2 : 4;
     const int n1 = st.n1, k1d = st.k1, n2 = st.n2, k2 = st.k2, R = st.R;
     const int i1 = r0 / n2, i2 = r0 - i1 * n2;
@@ -264,8 +266,8 @@ __device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, int r0, con
             j2[g] = jp & 0xFFFF;
         }
         if constexpr (DT == SL1_F64) {
-            const double* Bf = (const double*)st.B;
-            const double* Cf = (const double*)st.C;
+            const double* Bf = (const double*)Bsrc;
+            const double* Cf = (const double*)Csrc;
             double a[G][4];
 #pragma unroll
             for (int g = 0; g < G; ++g)
@@ -297,12 +299,12 @@ __device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, int r0, con
                 for (int g = 0; g < G; ++g) {
                     float bv, cv[4];
                     if constexpr (DT == SL1_F32) {
-                        bv = ((const float*)st.B)[((size_t)r * k1d + j1[g]) * n1 + i1];
-                        const f32v4 c = *(const f32v4*)((const float*)st.C + ((size_t)r * k2 + j2[g]) * n2 + i2);
+                        bv = ((const float*)Bsrc)[((size_t)r * k1d + j1[g]) * n1 + i1];
+                        const f32v4 c = *(const f32v4*)((const float*)Csrc + ((size_t)r * k2 + j2[g]) * n2 + i2);
                         cv[0] = c[0]; cv[1] = c[1]; cv[2] = c[2]; cv[3] = c[3];
                     } else {
-                        bv = bf16_to_f(((const uint16_t*)st.B)[((size_t)r * k1d + j1[g]) * n1 + i1]);
-                        const u16x4 c = *(const u16x4*)((const uint16_t*)st.C + ((size_t)r * k2 + j2[g]) * n2 + i2);
+                        bv = bf16_to_f(((const uint16_t*)Bsrc)[((size_t)r * k1d + j1[g]) * n1 + i1]);
+                        const u16x4 c = *(const u16x4*)((const uint16_t*)Csrc + ((size_t)r * k2 + j2[g]) * n2 + i2);
                         cv[0] = bf16_to_f(c[0]); cv[1] = bf16_to_f(c[1]); cv[2] = bf16_to_f(c[2]); cv[3] = bf16_to_f(c[3]);
                     }
 #pragma unroll
@@ -337,6 +339,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
     int* s_wpre = s_j + kFwdBlock;                      // work map (batch + 1)
     double* s_x = (double*)(((uintptr_t)(s_wpre + batch + 1) + 15) & ~(uintptr_t)15);
     double* s_u = s_x + kFwdBlock;                      // [4 sub-chunks][256 rows]: odd waves' partials
+    char* s_fac = (char*)(s_u + 4 * 256);               // a Kronecker stage's factors (fwd_fac_lds bytes)
     __shared__ double s_red[48];
     __shared__ int s_tmp[16];
 
@@ -479,6 +482,25 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
         }
         const int* nzi = nzbuf(P, b, par);
         const double* nzx = nzxbuf(P, b, par);
+        // with many nonzeros, a Kronecker stage's factors are read from LDS: the
+        // block stages all R pairs (B_r, C_r) once (16-byte copies, same layout)
+        const void* Bsrc = st.B;
+        const void* Csrc = st.C;
+        if (kron && nnz >= kFwdFacNnz) {
+            const int es = st.dtype == SL1_F64 ? 8 : (st.dtype == SL1_F32 ? 4 : 2);
+            const size_t bb = (size_t)st.R * st.n1 * st.k1 * es, cb = (size_t)st.R * st.n2 * st.k2 * es;
+            if (bb + cb <= (size_t)P->fwd_fac_lds) {
+                // sizes are multiples of 16 bytes: factor dimensions are multiples of 16
+                const uint4* gb = (const uint4*)st.B;
+                const uint4* gc = (const uint4*)st.C;
+                uint4* lb = (uint4*)s_fac;
+                uint4* lc = (uint4*)(s_fac + bb);
+                for (size_t q = threadIdx.x; q < bb / 16; q += kFwdBlock) lb[q] = gb[q];
+                for (size_t q = threadIdx.x; q < cb / 16; q += kFwdBlock) lc[q] = gc[q];
+                Bsrc = s_fac;
+                Csrc = s_fac + bb;
+            }
+        }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int base = 0; base < nnz; base += kFwdBlock) {
             const int cnt = min(kFwdBlock, nnz - base);
@@ -502,9 +524,9 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     case kDense * 4 + SL1_F32: fwd_dense_gather<SL1_F32>(st, N, r0, s_j, s_x, k0, k1, acc); break;
                     case kDense * 4 + SL1_BF16: fwd_dense_gather<SL1_BF16>(st, N, r0, s_j, s_x, k0, k1, acc); break;
                     case kDense * 4 + SL1_FP8_E4M3: fwd_dense_gather<SL1_FP8_E4M3>(st, N, r0, s_j, s_x, k0, k1, acc); break;
-                    case kKron * 4 + SL1_F64: fwd_kron_gather<SL1_F64>(st, r0, s_j, s_x, k0, k1, acc); break;
-                    case kKron * 4 + SL1_F32: fwd_kron_gather<SL1_F32>(st, r0, s_j, s_x, k0, k1, acc); break;
-                    default: fwd_kron_gather<SL1_BF16>(st, r0, s_j, s_x, k0, k1, acc); break;
+                    case kKron * 4 + SL1_F64: fwd_kron_gather<SL1_F64>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc); break;
+                    case kKron * 4 + SL1_F32: fwd_kron_gather<SL1_F32>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc); break;
+                    default: fwd_kron_gather<SL1_BF16>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc); break;
                 }
             }
             __syncthreads();
@@ -1720,6 +1742,10 @@ hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int3
 }
 
 // the batched correlation kernel may use more than the default 64 KB of LDS
+hipError_t fwd_lds_attr(size_t lds) {
+    return hipFuncSetAttribute((const void*)k_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t gemm_lds_attr(size_t lds) {
     if (lds <= 64 * 1024) return hipSuccess;
     return hipFuncSetAttribute((const void*)k_adj_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
