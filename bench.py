@@ -274,6 +274,8 @@ _GRID_SOURCES = ["paper_1812_06635_amd/csrc/sl1_kernels.hip", "paper_1812_06635_
                  "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
 TRAFFIC_SOURCES = {k: _GRID_SOURCES for k in ("k_adj_dense", "k_adj_gemm", "k_gemm_fin", "k_fwd", "k_upd",
                                                "k_adj_kron")}
+TRAFFIC_SOURCES["k_solve_tail"] = ["paper_1812_06635_amd/csrc/sl1_wg.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
+                                   "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
 
 
 def sources_sha256(kernel):
