@@ -18,6 +18,10 @@ Conventions
   N x K with leading dimension N).  Kronecker factors are stored as
   ``B[r, j1, i1]`` (each term column-major n1 x k1) and ``C[r, j2, i2]``.
 * BF16 and FP8 storage arrays hold raw bit patterns (uint16 / uint8).
+* FAuST stages (products of sparse factors A~ = S_1 S_2 ... S_J, Section I-B's
+  cited model, used for the paper's MEG operator in Section V-D) keep each
+  factor in CSR form: (row_ptr int32, col_idx int32, values) with S_l of shape
+  (dims[l-1], dims[l]), dims[0] = N and dims[J] = K.
 """
 from __future__ import annotations
 
@@ -102,7 +106,7 @@ def fp8_e4m3_round(v: np.ndarray) -> np.ndarray:
 @dataclass
 class Stage:
     """One dictionary of the sequence A~^0 .. A~^I (the last one is exact)."""
-    kind: str                  # "dense" | "kron"
+    kind: str                  # "dense" | "kron" | "faust"
     dtype: str                 # storage: "f64" | "f32" | "bf16" | "fp8"
     N: int
     K: int
@@ -110,7 +114,8 @@ class Stage:
     scale: np.ndarray | None = None    # dense low precision: (K,) float32 power-of-two scales
     B: np.ndarray | None = None        # kron: (R, k1, n1) storage array
     C: np.ndarray | None = None        # kron: (R, k2, n2) storage array
-    dims: tuple | None = None          # kron: (n1, k1, n2, k2)
+    dims: tuple | None = None          # kron: (n1, k1, n2, k2); faust: (d_0 = N, d_1, ..., d_J = K)
+    factors: list | None = None        # faust: [(row_ptr, col_idx, values)] per factor, CSR
     eps: np.ndarray | None = None      # (K,) exact bound on ||a_j - a~_j||_2
     L: float = 0.0                     # ||A~||_2^2 (FP64)
     rc_theory: float = 1.0             # relative complexity model of the products
@@ -125,8 +130,24 @@ class Stage:
         dec = _decoder(self.dtype)
         return (dec(self.B).transpose(0, 2, 1), dec(self.C).transpose(0, 2, 1))
 
+    def factor_matrices(self):
+        """FAuST factors as dense float64 arrays S_1 .. S_J."""
+        out = []
+        dec = _decoder(self.dtype)
+        for l, (rp, ci, v) in enumerate(self.factors):
+            M = np.zeros((self.dims[l], self.dims[l + 1]))
+            rows = np.repeat(np.arange(self.dims[l]), np.diff(rp))
+            M[rows, ci] = dec(v)
+            out.append(M)
+        return out
+
     def values(self) -> np.ndarray:
         """Exact float64 values of the stored dictionary, shape (N, K)."""
+        if self.kind == "faust":
+            out = None
+            for M in self.factor_matrices():
+                out = M if out is None else out @ M
+            return out
         if self.kind == "dense":
             v = _decoder(self.dtype)(self.data)
             if self.scale is not None:
@@ -336,6 +357,68 @@ def quantized_stage(A, dtype, seed=0) -> Stage:
     return st
 
 
+def _csr(M: np.ndarray, dtype: str):
+    """CSR (row_ptr, col_idx, values) of a dense matrix, values encoded in dtype."""
+    rows, cols = np.nonzero(M)
+    rp = np.zeros(M.shape[0] + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    return rp, cols.astype(np.int32), _encode(M[rows, cols], dtype)
+
+
+def faust_chain(rng, dims, col_nnz):
+    """Sparse factors S_l of shape (dims[l-1], dims[l]) with col_nnz[l-1] nonzeros
+    per column at distinct uniform rows, N(0,1) values."""
+    out = []
+    for l in range(1, len(dims)):
+        r, c = dims[l - 1], dims[l]
+        M = np.zeros((r, c))
+        for j in range(c):
+            idx = rng.choice(r, size=col_nnz[l - 1], replace=False)
+            M[idx, j] = rng.standard_normal(col_nnz[l - 1])
+        out.append(M)
+    return out
+
+
+def faust_dictionary(rng, dims, col_nnz, noise, work):
+    """A = (S_1 ... S_J + noise G) D with unit-norm columns (D diagonal); returns A
+    and the factors with the column scaling folded into the last one."""
+    S = faust_chain(rng, dims, col_nnz)
+    F = S[0]
+    for M in S[1:]:
+        F = F @ M
+    F = F + noise * rng.standard_normal(F.shape)
+    d = 1.0 / np.linalg.norm(F, axis=0)
+    S[-1] = S[-1] * d[None, :]
+    return _round_work(F * d[None, :], work), S
+
+
+def faust_stage(A, S, keep, dtype, seed=0) -> Stage:
+    """FAuST approximation S_1 ... S_{J-1} S_J' where S_J' keeps the `keep` entries
+    of largest magnitude of each column of S_J; factors rounded to dtype; exact
+    per-atom bounds against A.  The relative-complexity model is the nonzero count
+    of the factors over N K (the cost of the chain of sparse products against a
+    dense product)."""
+    S = [np.array(M) for M in S]
+    last = S[-1]
+    order = np.argsort(-np.abs(last), axis=0, kind="stable")
+    pruned = np.zeros_like(last)
+    cols = np.arange(last.shape[1])
+    for q in range(min(keep, last.shape[0])):
+        pruned[order[q], cols] = last[order[q], cols]
+    S[-1] = pruned
+    dims = tuple([S[0].shape[0]] + [M.shape[1] for M in S])
+    N, K = dims[0], dims[-1]
+    st = Stage(kind="faust", dtype=dtype, N=N, K=K, dims=dims, factors=[_csr(M, dtype) for M in S],
+               label=f"faust keep={keep} ({dtype})")
+    nnz = sum(len(f[1]) for f in st.factors)
+    st.rc_theory = nnz / float(N * K)
+    At = st.values()
+    st.eps = _bound(np.linalg.norm(A - At, axis=0), np.linalg.norm(A, axis=0), np.linalg.norm(At, axis=0))
+    st.L = lipschitz_dense(At, seed)
+    return st
+
+
 # ----------------------------------------------------------------------------
 # Signals
 # ----------------------------------------------------------------------------
@@ -457,3 +540,29 @@ def config5(batch=64, realization=0, n=(64, 128), R_A=8, Rs=(1, 2, 4, 8), s=40, 
                       [s] * batch, sigma, lam_frac)
     p.name = "C5"
     return p
+
+
+@functools.lru_cache(maxsize=2)
+def _faust_cached(cid, realization, dims, col_nnz, keeps, noise, dtype):
+    A, S = faust_dictionary(rng_for(cid, realization, 0), dims, col_nnz, noise, "f32")
+    A.setflags(write=False)
+    stages = tuple([faust_stage(A, S, k, dtype, seed=cid) for k in keeps] + [exact_stage(A, "f32", cid)])
+    return A, stages
+
+
+def config6(batch=1, realization=0, N=204, K=8193, depth=4, col_nnz=(32, 32, 32, 64), keeps=(40, 48, 52, 56),
+            s=8, lam_frac=0.1, noise=0.01, dtype="f32"):
+    """FAuST approximations (Section V-D, MEG shape): A of size 204 x 8193 is a
+    product of `depth` sparse factors (N x N, ..., N x K; col_nnz nonzeros per
+    column) plus noise, unit columns, FP32; the approximations keep the `keeps`
+    largest entries of each column of the last factor (four levels, like the
+    paper's four FAuST approximations); 8-sparse x0 with N(0, 1) weights at
+    uniform positions, lambda = 0.1 lambda_max.  The MEG gain matrix itself is not
+    available: this is a synthetic operator of the same shape."""
+    dims = tuple([N] * depth + [K])
+    A, stages = _faust_cached(6, realization, dims, tuple(col_nnz), tuple(keeps), noise, dtype)
+    rng = rng_for(6, realization, 1 + 10 * batch)
+    Y, lam, X0, lmax = signals(rng, A, [s] * batch, 0.0, lam_frac, "f32")
+    return Problem(name="C6", A=A, stages=list(stages), Y=Y, lam=lam, X0=X0, work="f32",
+                   atom_norm=np.linalg.norm(A, axis=0), lam_max=lmax,
+                   meta=dict(dims=dims, col_nnz=tuple(col_nnz), keeps=tuple(keeps)))

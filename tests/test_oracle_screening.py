@@ -143,6 +143,7 @@ def _check_method(p, b=0, Gamma=0.5, tol=1e-10, **kw):
     lambda: synth.config2(n=(16, 32), lam_frac=0.3),
     lambda: synth.config3(N=256, K=1024),
     lambda: synth.config4(batch=1, n=(16, 32)),
+    lambda: synth.config6(N=64, K=512, depth=3, col_nnz=(16, 16, 32), keeps=(16, 20, 24), lam_frac=0.2),
 ])
 def test_method_is_safe_and_reaches_the_lasso_solution(maker):
     p = maker()
