@@ -94,6 +94,31 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
 int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k2,
                   const void* B, const void* C, const double* eps, void* stream);
 
+/*
+ * sl1_dict_faust -- a structured stage A~ = S_1 S_2 ... S_J, a product of sparse
+ * factors (the FAuST model cited in Section I-D, used for the MEG operator of
+ * Section V-G and Table V).  S_l has dims[l-1] x dims[l] entries (0-based: S_l
+ * is factor l-1 below), dims[0] = N, dims[J] = K.
+ *   dtype      SL1_F64 or SL1_F32 (factor values; products accumulate in FP64).
+ *   J          number of factors, 1 .. 8.
+ *   dims       host, J+1 sizes: N (multiple of 4, <= 1024), inner sizes <= 1024, K.
+ *   nnz        host, J entry counts.
+ *   row_ptr    host, CSR row pointers of every factor, concatenated (dims[l] + 1
+ *              entries for factor l, starting at 0 and ending at nnz[l]).
+ *   col_idx    host, CSR column indices, concatenated (nnz[l] for factor l;
+ *              strictly increasing within a row).
+ *   val        host, values in dtype, concatenated like col_idx.
+ *   eps        K doubles, device, as for sl1_dict_dense.
+ * Everything is copied; the transposed factors, ||a~_j|| and the rounding allowance
+ * of the chain's FP64 sums are formed here.  FAuST stages run in the grid engine
+ * (SL1_ENGINE_WG refuses them with SL1_ELIMIT).
+ * Errors: SL1_EINVAL (malformed CSR, non-finite values, bad eps), SL1_EDTYPE,
+ * SL1_ELIMIT, SL1_EHIP, SL1_ENOMEM.
+ */
+int sl1_dict_faust(sl1_dict* out, int dtype, int J, const int64_t* dims, const int64_t* nnz,
+                   const int32_t* row_ptr, const int32_t* col_idx, const void* val, const double* eps,
+                   void* stream);
+
 /* Releases a handle; NULL is accepted and ignored. */
 int sl1_dict_free(sl1_dict d);
 
@@ -101,7 +126,8 @@ int sl1_dict_free(sl1_dict d);
  * sl1_dict_info -- host outputs (any may be NULL): sizes, the largest bound
  * max_j eps_j as given, and the relative-complexity model of the stage
  * (1 for dense full precision, bytes per element / 4 for BF16 and FP8 storage,
- * R (1/n1 + 1/k2) for Kronecker sums; Section IV-B and Table IV).
+ * R (1/n1 + 1/k2) for Kronecker sums, nonzeros / (N K) for FAuST chains;
+ * Section IV-B and Table IV).
  */
 int sl1_dict_info(sl1_dict d, int64_t* N, int64_t* K, double* eps_max, double* rc_model);
 

@@ -78,6 +78,27 @@ class Dict:
                                        _ptr(eps), _stream()), "sl1_dict_kron")
         return cls(h, None, n1 * n2, k1 * k2, "kron", dtype)
 
+    @classmethod
+    def faust(cls, dims, factors, eps, dtype):
+        """A~ = S_1 ... S_J from host CSR factors [(row_ptr int32, col_idx int32,
+        values float64/float32)], S_l of dims[l-1] x dims[l]; eps (K,) device FP64."""
+        if dtype not in ("f64", "f32"):
+            raise ValueError("FAuST factors are f64 or f32")
+        _dev(eps, torch.float64, "eps")
+        J = len(factors)
+        if len(dims) != J + 1:
+            raise ValueError("dims must hold J + 1 sizes")
+        vt = np.float64 if dtype == "f64" else np.float32
+        rp = np.ascontiguousarray(np.concatenate([np.asarray(f[0], dtype=np.int32) for f in factors]))
+        ci = np.ascontiguousarray(np.concatenate([np.asarray(f[1], dtype=np.int32) for f in factors]))
+        va = np.ascontiguousarray(np.concatenate([np.asarray(f[2], dtype=vt) for f in factors]))
+        dd = (L.c_i64 * (J + 1))(*[int(v) for v in dims])
+        nz = (L.c_i64 * J)(*[len(f[1]) for f in factors])
+        h = L.c_dict()
+        L.check(L.load().sl1_dict_faust(ctypes.byref(h), DTYPES[dtype], J, dd, nz, rp.ctypes.data, ci.ctypes.data,
+                                        va.ctypes.data, _ptr(eps), _stream()), "sl1_dict_faust")
+        return cls(h, None, int(dims[0]), int(dims[-1]), "faust", dtype)
+
     def info(self):
         N, K = L.c_i64(), L.c_i64()
         em, rc = L.c_d(), L.c_d()
@@ -100,13 +121,15 @@ class Dict:
 
 def upload_stage(stage, device="cuda"):
     """Device copy of a host stage description with attributes kind, dtype,
-    data/scale (dense) or B/C (kron), eps (numpy arrays)."""
+    data/scale (dense), B/C (kron) or dims/factors (faust), eps (numpy arrays)."""
     eps = torch.from_numpy(np.ascontiguousarray(stage.eps, dtype=np.float64)).to(device)
     if stage.kind == "dense":
         arr = stage.data.view(np.int16) if stage.dtype == "bf16" else stage.data
         A = torch.from_numpy(np.ascontiguousarray(arr)).to(device)
         sc = None if stage.scale is None else torch.from_numpy(np.ascontiguousarray(stage.scale)).to(device)
         return Dict.dense(A, eps, stage.dtype, sc)
+    if stage.kind == "faust":
+        return Dict.faust(stage.dims, stage.factors, eps, stage.dtype)
     conv = (lambda a: a.view(np.int16)) if stage.dtype == "bf16" else (lambda a: a)
     B = torch.from_numpy(np.ascontiguousarray(conv(stage.B))).to(device)
     C = torch.from_numpy(np.ascontiguousarray(conv(stage.C))).to(device)

@@ -49,6 +49,16 @@ struct sl1_dict_s {
     void* C = nullptr;         // owned (kron)
     double* eps_eff = nullptr; // owned
     double* at_norm = nullptr; // owned
+    // FAuST (owned): device descriptor and the concatenated CSR arrays of the
+    // factors and of their transposes
+    FaustDesc* fa = nullptr;
+    int* fa_ptr = nullptr;
+    int* fa_idx = nullptr;
+    void* fa_val = nullptr;
+    int* fa_tptr = nullptr;
+    int* fa_tidx = nullptr;
+    void* fa_tval = nullptr;
+    int fa_maxd = 0, fa_q = 0, fa_dlast = 0;
     double eps_max_in = 0.0, eps_max_eff = 0.0, at_norm_max = 0.0, rc_model = 1.0;
 };
 
@@ -266,6 +276,9 @@ void fill_stage(StageDesc& s, const sl1_dict_s& d, double L, double rc) {
     s.C = d.C;
     s.eps = d.eps_eff;
     s.at_norm = d.at_norm;
+    s.fa = d.fa;
+    s.fa_items = d.kind == kFaust ? (int)((d.K + kFaustAtoms - 1) / kFaustAtoms) : 0;
+    s.fa_maxd = d.fa_maxd;
     s.L = L;
     s.invL = 1.0 / L;
     s.rc = rc;
@@ -290,8 +303,13 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     size_t extra = 0;
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
-        if (s.kind != kKron) {
+        if (s.kind == kDense) {
             dense = true;
+            continue;
+        }
+        if (s.kind == kFaust) {      // FAuST items share the structured-correlation launch
+            kron_items = std::max(kron_items, s.fa_items);
+            extra = std::max(extra, 2 * (size_t)s.fa_maxd * 8);
             continue;
         }
         kron_items = std::max(kron_items, (s.k2 / 16) * ((s.k1 + kKronColTile - 1) / kKronColTile));
@@ -404,6 +422,7 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act, bool gram) {
     size_t fac = 0, scr = 8192;                 // forward staging (6 KB) or cross-group sums (8 KB)
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
+        if (s.kind == kFaust) return 0;         // FAuST stages run in the grid kernels only
         if (s.kind != kKron) continue;
         const size_t es = s.dtype == SL1_F64 ? 8 : (s.dtype == SL1_F32 ? 4 : 2);
         fac = std::max(fac, a16(((size_t)s.R * s.k1 * s.n1 + (size_t)s.R * s.k2 * s.n2) * es));
@@ -470,6 +489,8 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
             const size_t fb = (size_t)d->R * ((size_t)d->n1 * d->k1 + (size_t)d->n2 * d->k2) * es;
             if (fb <= (size_t)kFwdFacLds) fac = std::max(fac, fb);
         }
+        if (d->kind == kFaust)      // the forward chain's vectors, scatter block and column bounds
+            fac = std::max(fac, (2 * (size_t)d->fa_maxd + (size_t)d->fa_dlast * d->fa_q) * 8 + 2 * (size_t)kFwdBlock * 4);
     }
     p.fwd_fac_lds = (int)fac;
     p.n_stages = n_stages;
@@ -625,6 +646,9 @@ int sl1_dict_free(sl1_dict d) {
     if (d->C) (void)hipFree(d->C);
     if (d->eps_eff) (void)hipFree(d->eps_eff);
     if (d->at_norm) (void)hipFree(d->at_norm);
+    for (void* q : {(void*)d->fa, (void*)d->fa_ptr, (void*)d->fa_idx, d->fa_val, (void*)d->fa_tptr,
+                    (void*)d->fa_tidx, d->fa_tval})
+        if (q) (void)hipFree(q);
     delete d;
     return SL1_OK;
 }
@@ -806,6 +830,195 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     return SL1_OK;
 }
 
+int sl1_dict_faust(sl1_dict* out, int dtype, int J, const int64_t* dims, const int64_t* nnz, const int32_t* row_ptr,
+                   const int32_t* col_idx, const void* val, const double* eps, void* stream) {
+    if (!out || !dims || !nnz || !row_ptr || !col_idx || !val || !eps || J < 1) return SL1_EINVAL;
+    *out = nullptr;
+    if (dtype != SL1_F64 && dtype != SL1_F32) return SL1_EDTYPE;
+    if (J > kFaustMax) return SL1_ELIMIT;
+    const int64_t N = dims[0], K = dims[J];
+    if (N < 4 || N % 4 || N > kFaustMaxDim || K < 1 || K > (int64_t)kMaxSeg * kSeg) return SL1_ELIMIT;
+    for (int l = 1; l < J; ++l)
+        if (dims[l] < 1 || dims[l] > kFaustMaxDim) return SL1_ELIMIT;
+    // the factors' CSR arrays (host), validated: row pointers from 0 to nnz, column
+    // indices in range and strictly increasing within a row, finite values
+    const size_t es = dtype_size(dtype);
+    std::vector<size_t> po(J + 1, 0), zo(J + 1, 0);
+    for (int l = 0; l < J; ++l) {
+        if (nnz[l] < 0 || nnz[l] > INT32_MAX) return SL1_EINVAL;
+        po[l + 1] = po[l] + (size_t)dims[l] + 1;
+        zo[l + 1] = zo[l] + (size_t)nnz[l];
+    }
+    if (zo[J] > (size_t)INT32_MAX) return SL1_ELIMIT;
+    auto hval = [&](size_t e) -> double {
+        return dtype == SL1_F64 ? ((const double*)val)[e] : (double)((const float*)val)[e];
+    };
+    for (int l = 0; l < J; ++l) {
+        const int32_t* rp = row_ptr + po[l];
+        const int32_t* ci = col_idx + zo[l];
+        if (rp[0] != 0 || rp[dims[l]] != nnz[l]) return SL1_EINVAL;
+        for (int64_t r = 0; r < dims[l]; ++r) {
+            if (rp[r + 1] < rp[r]) return SL1_EINVAL;
+            for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+                if (ci[e] < 0 || ci[e] >= dims[l + 1] || (e > rp[r] && ci[e] <= ci[e - 1])) return SL1_EINVAL;
+                if (!std::isfinite(hval(zo[l] + e))) return SL1_EINVAL;
+            }
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    auto d = std::make_unique<sl1_dict_s>();
+    HIP_TRY(hipGetDevice(&d->device));
+    d->kind = kFaust;
+    d->dtype = dtype;
+    d->N = N;
+    d->K = K;
+    int st = finish_dict_host_eps(d.get(), eps, s);
+    if (st != SL1_OK) return st;
+    // transposes (CSR of S_l^T; rows of S_l in increasing order give sorted rows)
+    std::vector<size_t> tpo(J + 1, 0);
+    for (int l = 0; l < J; ++l) tpo[l + 1] = tpo[l] + (size_t)dims[l + 1] + 1;
+    std::vector<int32_t> tptr(tpo[J], 0), tidx(zo[J]);
+    std::vector<unsigned char> tval(zo[J] * es);
+    int sum_terms = 0, maxd = 0;
+    for (int l = 0; l < J; ++l) {
+        const int32_t* rp = row_ptr + po[l];
+        const int32_t* ci = col_idx + zo[l];
+        int32_t* tp = tptr.data() + tpo[l];
+        for (int32_t e = 0; e < (int32_t)nnz[l]; ++e) tp[ci[e] + 1] += 1;
+        int rmax = 0, cmax = 0;
+        for (int64_t r = 0; r < dims[l]; ++r) rmax = std::max(rmax, rp[r + 1] - rp[r]);
+        for (int64_t c = 0; c < dims[l + 1]; ++c) {
+            cmax = std::max(cmax, tp[c + 1]);
+            tp[c + 1] += tp[c];
+        }
+        sum_terms += std::max(rmax, cmax);
+        std::vector<int32_t> fill(tp, tp + dims[l + 1]);
+        for (int64_t r = 0; r < dims[l]; ++r)
+            for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+                const int32_t q = fill[ci[e]]++;
+                tidx[zo[l] + q] = (int32_t)r;
+                std::memcpy(&tval[(zo[l] + q) * es], (const unsigned char*)val + (zo[l] + e) * es, es);
+            }
+        maxd = std::max(maxd, (int)dims[l]);
+    }
+    d->fa_maxd = maxd;
+    d->fa_dlast = (int)dims[J - 1];
+    d->fa_q = std::max(1, std::min(16, 2048 / d->fa_dlast));
+    // ||a~_j|| and ||(|S_1| ... |S_J|) e_j|| in FP64, 64 atoms at a time
+    std::vector<double> an(K), ab(K);
+    {
+        const int64_t BW = 64;
+        std::vector<double> vs, va, ws, wa;
+        for (int64_t j0 = 0; j0 < K; j0 += BW) {
+            const int64_t nb = std::min(BW, K - j0);
+            int64_t rows = dims[J - 1];
+            vs.assign((size_t)rows * nb, 0.0);
+            va.assign((size_t)rows * nb, 0.0);
+            const int32_t* tp = tptr.data() + tpo[J - 1];
+            for (int64_t q = 0; q < nb; ++q)
+                for (int32_t e = tp[j0 + q]; e < tp[j0 + q + 1]; ++e) {
+                    const size_t g = zo[J - 1] + e;
+                    const double v = dtype == SL1_F64 ? ((const double*)tval.data())[g] : (double)((const float*)tval.data())[g];
+                    vs[(size_t)tidx[g] * nb + q] = v;
+                    va[(size_t)tidx[g] * nb + q] = std::fabs(v);
+                }
+            for (int l = J - 2; l >= 0; --l) {
+                const int32_t* rp = row_ptr + po[l];
+                const int32_t* ci = col_idx + zo[l];
+                ws.assign((size_t)dims[l] * nb, 0.0);
+                wa.assign((size_t)dims[l] * nb, 0.0);
+                for (int64_t r = 0; r < dims[l]; ++r)
+                    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+                        const double v = hval(zo[l] + e), av = std::fabs(v);
+                        const double* a = &vs[(size_t)ci[e] * nb];
+                        const double* b = &va[(size_t)ci[e] * nb];
+                        for (int64_t q = 0; q < nb; ++q) {
+                            ws[(size_t)r * nb + q] += v * a[q];
+                            wa[(size_t)r * nb + q] += av * b[q];
+                        }
+                    }
+                vs.swap(ws);
+                va.swap(wa);
+                rows = dims[l];
+            }
+            for (int64_t q = 0; q < nb; ++q) {
+                double s1 = 0.0, s2 = 0.0;
+                for (int64_t r = 0; r < rows; ++r) {
+                    s1 += vs[(size_t)r * nb + q] * vs[(size_t)r * nb + q];
+                    s2 += va[(size_t)r * nb + q] * va[(size_t)r * nb + q];
+                }
+                an[j0 + q] = std::sqrt(s1);
+                ab[j0 + q] = std::sqrt(s2) * (1.0 + 1e-12);
+            }
+        }
+    }
+    // device copies
+    if (hipMalloc(&d->fa_ptr, po[J] * 4) != hipSuccess || hipMalloc(&d->fa_idx, std::max<size_t>(zo[J], 1) * 4) != hipSuccess ||
+        hipMalloc(&d->fa_val, std::max<size_t>(zo[J], 1) * es) != hipSuccess ||
+        hipMalloc(&d->fa_tptr, tpo[J] * 4) != hipSuccess || hipMalloc(&d->fa_tidx, std::max<size_t>(zo[J], 1) * 4) != hipSuccess ||
+        hipMalloc(&d->fa_tval, std::max<size_t>(zo[J], 1) * es) != hipSuccess || hipMalloc(&d->fa, sizeof(FaustDesc)) != hipSuccess ||
+        hipMalloc(&d->eps_eff, K * 8) != hipSuccess || hipMalloc(&d->at_norm, K * 8) != hipSuccess) {
+        sl1_dict_free(d.release());
+        return SL1_ENOMEM;
+    }
+    FaustDesc F;
+    std::memset(&F, 0, sizeof(F));
+    F.J = J;
+    for (int l = 0; l <= J; ++l) F.dim[l] = (int)dims[l];
+    F.maxd = maxd;
+    F.q = d->fa_q;
+    for (int l = 0; l < J; ++l) {
+        F.fp[l] = (long long)po[l];
+        F.fz[l] = (long long)zo[l];
+        F.tp[l] = (long long)tpo[l];
+        F.tz[l] = (long long)zo[l];
+    }
+    F.ptr = d->fa_ptr;
+    F.idx = d->fa_idx;
+    F.val = d->fa_val;
+    F.tptr = d->fa_tptr;
+    F.tidx = d->fa_tidx;
+    F.tval = d->fa_tval;
+    HIP_TRY(hipMemcpyAsync(d->fa_ptr, row_ptr, po[J] * 4, hipMemcpyHostToDevice, s));
+    if (zo[J]) {
+        HIP_TRY(hipMemcpyAsync(d->fa_idx, col_idx, zo[J] * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d->fa_val, val, zo[J] * es, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d->fa_tidx, tidx.data(), zo[J] * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d->fa_tval, tval.data(), zo[J] * es, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipMemcpyAsync(d->fa_tptr, tptr.data(), tpo[J] * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d->fa, &F, sizeof(F), hipMemcpyHostToDevice, s));
+    double* d_ab = nullptr;
+    int* bad = nullptr;
+    if (hipMalloc(&d_ab, K * 8) != hipSuccess || hipMalloc(&bad, 4) != hipSuccess) {
+        if (d_ab) (void)hipFree(d_ab);
+        sl1_dict_free(d.release());
+        return SL1_ENOMEM;
+    }
+    HIP_TRY(hipMemcpyAsync(d->at_norm, an.data(), K * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ab, ab.data(), K * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
+    // the chain's FP64 sums have at most sum_l max(row, column nonzeros of S_l) terms
+    const double kappa = 2.0 * ((double)sum_terms + (double)J + (double)K + 32.0) * kU64;
+    HIP_TRY(launch_eps_fold(eps, d_ab, kappa, (int)K, d->eps_eff, bad, s));
+    std::vector<double> ee(K);
+    int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(ee.data(), d->eps_eff, K * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(d_ab);
+    (void)hipFree(bad);
+    if (hbad) {
+        sl1_dict_free(d.release());
+        return SL1_EINVAL;
+    }
+    d->at_norm_max = *std::max_element(an.begin(), an.end());
+    d->eps_max_eff = *std::max_element(ee.begin(), ee.end());
+    d->rc_model = (double)zo[J] / ((double)N * (double)K);
+    *out = d.release();
+    return SL1_OK;
+}
+
 // Stable Dynamic Safe set-up (the caller holds w->mu): a_j^T y with the exact
 // dictionary for every atom and signal -- the product the footnote to Table I
 // allows to form once -- and ||y||^2, both in FP64 into the workspace.  Ends with
@@ -848,6 +1061,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     LaunchCfg cfg = launch_cfg(*w, p);
     st = check_lds(cfg);
     if (st != SL1_OK) return st;
+    if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
@@ -992,7 +1206,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     // launches with no possible work are left out of a chunk: the Kronecker
     // correlations once every live signal is on a dense last stage (stages only
     // advance), the batched product while the host has it switched off
-    const bool last_kron = p.st[p.n_stages - 1].kind == kKron;
+    const bool last_kron = p.st[p.n_stages - 1].kind != kDense;      // a structured last stage
     bool kron_live = cfg.g_adjk > 0;
     for (;;) {
         LaunchCfg ccfg = cfg;
@@ -1114,6 +1328,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     LaunchCfg cfg = launch_cfg(*w, p);
     st = check_lds(cfg);
     if (st != SL1_OK) return st;
+    if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
@@ -1197,7 +1412,8 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
         p.lam = nullptr;
         LaunchCfg cfg = launch_cfg(*w, p);
         if ((st = check_lds(cfg)) != SL1_OK) { (void)hipFree(ybuf); return st; }
-            HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+        if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
+        HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
         HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
         HIP_TRY(launch_init(w->dP, cfg, w->stream));
         HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));

@@ -25,7 +25,29 @@ constexpr int kWgRows = 1024;       // rows per forward pass of that engine (16 
 constexpr int kWgStage = 512;       // nonzeros of x staged in LDS per forward step
 constexpr int kWgPhases = 4;        // profiled phases: forward, dense correlations, Kronecker correlations, update
 
-enum Kind { kDense = 0, kKron = 1 };
+enum Kind { kDense = 0, kKron = 1, kFaust = 2 };
+
+// FAuST stage A~ = S_1 S_2 ... S_J (sparse factors, S_l of size dim[l-1] x dim[l],
+// dim[0] = N, dim[J] = K): every factor in CSR and its transpose in CSR, the
+// arrays of all factors concatenated (device).  Values in the stage's dtype
+// (FP64 or FP32), products accumulated in FP64.
+constexpr int kFaustMax = 8;          // factors
+constexpr int kFaustMaxDim = 1024;    // N and every inner dimension
+constexpr int kFaustAtoms = 1024;     // atoms per correlation item
+struct FaustDesc {
+    int J;
+    int dim[kFaustMax + 1];
+    int maxd;                          // largest of dim[0 .. J-1]
+    int q;                             // nonzeros of x per scatter chunk of the forward
+    long long fp[kFaustMax], fz[kFaustMax];   // S_l: offsets of its row pointers / entries
+    long long tp[kFaustMax], tz[kFaustMax];   // S_l^T: offsets of its row pointers / entries
+    const int* ptr;
+    const int* idx;
+    const void* val;
+    const int* tptr;
+    const int* tidx;
+    const void* tval;
+};
 
 struct StageDesc {
     int kind, dtype;
@@ -37,6 +59,9 @@ struct StageDesc {
     const void* C;
     const double* eps;        // eps_j enlarged by the library's rounding bound
     const double* at_norm;    // ||a~_j||_2 (look-ahead estimate K_t)
+    const FaustDesc* fa;      // FAuST factors (device) or nullptr
+    int fa_items;             // FAuST: correlation items (kFaustAtoms atoms each)
+    int fa_maxd;              // FAuST: largest of N and the inner dimensions
     double L, invL, rc;
     double at_norm_max, eps_max;
 };

@@ -137,6 +137,7 @@ __device__ __forceinline__ int adj_items(const StageDesc& st, int n_act, int N) 
         const int per = 4 * dense_apw(N);
         return max(1, (n_act + per - 1) / per);
     }
+    if (st.kind == kFaust) return st.fa_items;
     return (st.k2 / 16) * ((st.k1 + kKronColTile - 1) / kKronColTile);
 }
 
@@ -322,6 +323,104 @@ __device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, const void*
 }
 
 // ---------------------------------------------------------------------------
+// FAuST stages (A~ = S_1 S_2 ... S_J, sparse factors): products through the chain
+// with FP64 accumulation, every sum in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double faust_val(const void* v, long long i, int dtype) {
+    return dtype == SL1_F64 ? ((const double*)v)[i] : (double)((const float*)v)[i];
+}
+
+// out = S_l in (CSR rows of factor l, 0-based; out has dim[l] rows), one thread per row
+__device__ __forceinline__ void faust_rows(const FaustDesc& F, int dtype, int l, const double* in, double* out) {
+    const int rows = F.dim[l];
+    const int* ptr = F.ptr + F.fp[l];
+    const int* idx = F.idx + F.fz[l];
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+        const int e0 = ptr[i], e1 = ptr[i + 1];
+        double s = 0.0;
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) s += faust_val(F.val, F.fz[l] + e, dtype) * in[idx[e]];
+        out[i] = s;
+    }
+}
+
+// out = S_l^T in (CSR rows of the transpose of factor l; out has dim[l+1] rows)
+__device__ __forceinline__ void faust_trows(const FaustDesc& F, int dtype, int l, const double* in, double* out) {
+    const int rows = F.dim[l + 1];
+    const int* ptr = F.tptr + F.tp[l];
+    const int* idx = F.tidx + F.tz[l];
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+        const int e0 = ptr[i], e1 = ptr[i + 1];
+        double s = 0.0;
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) s += faust_val(F.tval, F.tz[l] + e, dtype) * in[idx[e]];
+        out[i] = s;
+    }
+}
+
+// Forward product u = A~ x_t of a FAuST stage for one signal (all N <= 1024 rows):
+// v = S_J x from the nonzeros of x -- each nonzero's column of S_J (a row of S_J^T)
+// is scattered, q nonzeros at a time, into column c of an LDS block M[row][q]
+// (distinct rows within a column), whose rows are then summed in list order --
+// then v <- S_l v for l = J-1 .. 1.  Region: two vectors of maxd doubles, M
+// (dim[J-1] x q doubles), the chunk's column bounds (2 x kFwdBlock ints).
+// Returns u in LDS.  Called by the whole block.
+__device__ const double* fwd_faust(const StageDesc& st, int nnz, const int* nzi, const double* nzx,
+                                   const int* s_zpre, int nseg_nz, int* s_j, double* s_x, char* region) {
+    const FaustDesc& F = *st.fa;
+    const int J = F.J, maxd = F.maxd, q = F.q, dl = F.dim[J - 1];
+    double* va = (double*)region;
+    double* vb = va + maxd;
+    double* M = vb + maxd;
+    int* s_e0 = (int*)(M + (size_t)dl * q);
+    int* s_e1 = s_e0 + kFwdBlock;
+    const int* tptr = F.tptr + F.tp[J - 1];
+    const int* tidx = F.tidx + F.tz[J - 1];
+    for (int i = threadIdx.x; i < dl; i += kFwdBlock) va[i] = 0.0;
+    __syncthreads();
+    for (int base = 0; base < nnz; base += kFwdBlock) {
+        const int cnt = min(kFwdBlock, nnz - base);
+        if ((int)threadIdx.x < cnt) {
+            const int pos = list_pos(s_zpre, nseg_nz, base + threadIdx.x);
+            const int j = nzi[pos];
+            s_j[threadIdx.x] = j;
+            s_x[threadIdx.x] = nzx[pos];
+            s_e0[threadIdx.x] = tptr[j];
+            s_e1[threadIdx.x] = tptr[j + 1];
+        }
+        for (int k0 = 0; k0 < cnt; k0 += q) {
+            const int cc = min(q, cnt - k0);
+            for (int i = threadIdx.x; i < dl * q; i += kFwdBlock) M[i] = 0.0;
+            __syncthreads();
+#pragma unroll 4
+            for (int c = 0; c < cc; ++c) {
+                const int e0 = s_e0[k0 + c], n = s_e1[k0 + c] - e0;
+                const double xv = s_x[k0 + c];
+                for (int e = threadIdx.x; e < n; e += kFwdBlock)
+                    M[(size_t)tidx[e0 + e] * q + c] = faust_val(F.tval, F.tz[J - 1] + e0 + e, st.dtype) * xv;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < dl; i += kFwdBlock) {
+                double s = 0.0;
+                for (int c = 0; c < cc; ++c) s += M[(size_t)i * q + c];
+                va[i] += s;
+            }
+            __syncthreads();
+        }
+    }
+    double* in = va;
+    double* out = vb;
+    for (int l = J - 2; l >= 0; --l) {
+        faust_rows(F, st.dtype, l, in, out);
+        __syncthreads();
+        double* t = in;
+        in = out;
+        out = t;
+    }
+    return in;
+}
+
+// ---------------------------------------------------------------------------
 // forward product and residual (Section III-C: rho~_t = y - A~ x_t)
 // items: row chunks of 1024 rows; wave pair (2s, 2s + 1) covers rows
 // 256 s .. 256 s + 255 of the chunk (4 per lane) and splits the nonzeros of x_t
@@ -451,7 +550,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                         *(int4*)(P->sig_stat + 4 * b) =
                             make_int4(C.n_act, C.n_act, C.stage < P->n_stages - 1 ? 1 : 0, qual ? 1 : 0);
                         P->cnt_adj[b] = (stn.kind == kDense && !gemm) ? items : 0;
-                        P->cnt_adjk[b] = stn.kind == kKron ? items : 0;
+                        P->cnt_adjk[b] = stn.kind != kDense ? items : 0;     // Kronecker and FAuST
                         P->cnt_gemm[b] = gemm ? 1 : 0;
                         P->cnt_upd[b] = max(1, (C.n_act + kSeg - 1) / kSeg);
                         if (Cp.advance && P->trace && Cp.iter < P->trace_cap) {
@@ -502,7 +601,15 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
             }
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int base = 0; base < nnz; base += kFwdBlock) {
+        if (st.kind == kFaust) {
+            // the whole chain in this block (N <= 1024: one item); the even waves take their rows
+            const double* u = fwd_faust(st, nnz, nzi, nzx, s_zpre, nseg_nz, s_j, s_x, s_fac);
+            if (half == 0 && rows_ok) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = u[r0 + v];
+            }
+        }
+        for (int base = 0; st.kind != kFaust && base < nnz; base += kFwdBlock) {
             const int cnt = min(kFwdBlock, nnz - base);
             if ((int)threadIdx.x < cnt) {
                 const int pos = list_pos(s_zpre, nseg_nz, base + threadIdx.x);
@@ -780,6 +887,42 @@ __device__ __forceinline__ void put_wave_max(const SolveParams* P, int b, int it
         ap[1] = mx[1];
         ap[2] = mx[2];
     }
+}
+
+// Correlations of one FAuST item (atoms c*kFaustAtoms ..): w = S_{J-1}^T ... S_1^T z
+// through two LDS vectors, then g_j = (S_J^T w)_j for the preserved atoms of the
+// item, with the per-wave maxima.  zs: z in LDS (FP64).  Called by the whole block.
+__device__ void adj_faust_item(const SolveParams* P, const StageDesc& st, int b, int c, const double* zs,
+                               double* region, double* gvec, double rz) {
+    const FaustDesc& F = *st.fa;
+    const int J = F.J, K = P->K;
+    const double* in = zs;
+    double* bufs[2] = {region, region + F.maxd};
+    for (int l = 0; l < J - 1; ++l) {
+        double* out = bufs[l & 1];
+        faust_trows(F, st.dtype, l, in, out);
+        __syncthreads();
+        in = out;
+    }
+    const int* ptr = F.tptr + F.tp[J - 1];
+    const int* idx = F.tidx + F.tz[J - 1];
+    const uint8_t* mask = P->mask + (size_t)b * K;
+    double mx[3] = {0.0, 0.0, 0.0};
+    const int a0 = c * kFaustAtoms, a1 = min(K, a0 + kFaustAtoms);
+    for (int j = a0 + threadIdx.x; j < a1; j += blockDim.x) {
+        if (!mask[j]) continue;
+        const int e0 = ptr[j], e1 = ptr[j + 1];
+        double s = 0.0;
+#pragma unroll 4
+        for (int e = e0; e < e1; ++e) s += faust_val(F.tval, F.tz[J - 1] + e, st.dtype) * in[idx[e]];
+        gvec[j] = s;
+        const double ej = st.eps[j];
+        mx[0] = fmax(mx[0], fabs(s) + ej * rz);
+        mx[1] = fmax(mx[1], fabs(s));
+        mx[2] = fmax(mx[2], ej);
+    }
+    put_wave_max(P, b, c, mx, true);
+    __syncthreads();                   // the chain vectors are reused by the next item
 }
 
 __device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double* s_red, double& r2, double& zz,
@@ -1282,7 +1425,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
             rz = sqrt(zz);
             const StageDesc& st0 = P->st[uni(C.stage)];
             const double* zg = P->z + (size_t)b * N;
-            if (st0.dtype != SL1_F64) {
+            if (st0.kind == kKron && st0.dtype != SL1_F64) {
                 float* zsf = (float*)smem;
                 for (int i = threadIdx.x; i < N; i += kBlock) zsf[i] = (float)zg[i];
             } else {
@@ -1294,6 +1437,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
         const StageDesc& st = P->st[uni(C.stage)];
         const double* zs = (const double*)smem;
         double* gvec = gbuf(P, b, uni(C.par));
+        if (st.kind == kFaust) {
+            adj_faust_item(P, st, b, c, zs, (double*)extra, gvec, rz);
+            continue;
+        }
         double mx[3] = {0.0, 0.0, 0.0};
         const int ntc = (st.k1 + kKronColTile - 1) / kKronColTile;
         const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;

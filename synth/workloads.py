@@ -18,8 +18,8 @@ Conventions
   N x K with leading dimension N).  Kronecker factors are stored as
   ``B[r, j1, i1]`` (each term column-major n1 x k1) and ``C[r, j2, i2]``.
 * BF16 and FP8 storage arrays hold raw bit patterns (uint16 / uint8).
-* FAuST stages (products of sparse factors A~ = S_1 S_2 ... S_J, Section I-B's
-  cited model, used for the paper's MEG operator in Section V-D) keep each
+* FAuST stages (products of sparse factors A~ = S_1 S_2 ... S_J, the model cited
+  in Section I-D and used for the paper's MEG operator in Section V-G) keep each
   factor in CSR form: (row_ptr int32, col_idx int32, values) with S_l of shape
   (dims[l-1], dims[l]), dims[0] = N and dims[J] = K.
 """
@@ -543,26 +543,27 @@ def config5(batch=64, realization=0, n=(64, 128), R_A=8, Rs=(1, 2, 4, 8), s=40, 
 
 
 @functools.lru_cache(maxsize=2)
-def _faust_cached(cid, realization, dims, col_nnz, keeps, noise, dtype):
-    A, S = faust_dictionary(rng_for(cid, realization, 0), dims, col_nnz, noise, "f32")
+def _faust_cached(cid, realization, dims, col_nnz, keeps, noise, dtype, work):
+    A, S = faust_dictionary(rng_for(cid, realization, 0), dims, col_nnz, noise, work)
     A.setflags(write=False)
-    stages = tuple([faust_stage(A, S, k, dtype, seed=cid) for k in keeps] + [exact_stage(A, "f32", cid)])
+    stages = tuple([faust_stage(A, S, k, dtype, seed=cid) for k in keeps] + [exact_stage(A, work, cid)])
     return A, stages
 
 
 def config6(batch=1, realization=0, N=204, K=8193, depth=4, col_nnz=(32, 32, 32, 64), keeps=(40, 48, 52, 56),
-            s=8, lam_frac=0.1, noise=0.01, dtype="f32"):
-    """FAuST approximations (Section V-D, MEG shape): A of size 204 x 8193 is a
+            s=8, lam_frac=0.1, noise=0.01, dtype="f32", work="f32"):
+    """FAuST approximations (Section V-G and Table V, MEG shape): A of size 204 x 8193 is a
     product of `depth` sparse factors (N x N, ..., N x K; col_nnz nonzeros per
     column) plus noise, unit columns, FP32; the approximations keep the `keeps`
     largest entries of each column of the last factor (four levels, like the
     paper's four FAuST approximations); 8-sparse x0 with N(0, 1) weights at
     uniform positions, lambda = 0.1 lambda_max.  The MEG gain matrix itself is not
-    available: this is a synthetic operator of the same shape."""
+    available: this is a synthetic operator of the same shape.  work="f64" gives
+    an FP64 exact stage and signals (with dtype="f64" factors)."""
     dims = tuple([N] * depth + [K])
-    A, stages = _faust_cached(6, realization, dims, tuple(col_nnz), tuple(keeps), noise, dtype)
+    A, stages = _faust_cached(6, realization, dims, tuple(col_nnz), tuple(keeps), noise, dtype, work)
     rng = rng_for(6, realization, 1 + 10 * batch)
-    Y, lam, X0, lmax = signals(rng, A, [s] * batch, 0.0, lam_frac, "f32")
-    return Problem(name="C6", A=A, stages=list(stages), Y=Y, lam=lam, X0=X0, work="f32",
+    Y, lam, X0, lmax = signals(rng, A, [s] * batch, 0.0, lam_frac, work)
+    return Problem(name="C6", A=A, stages=list(stages), Y=Y, lam=lam, X0=X0, work=work,
                    atom_norm=np.linalg.norm(A, axis=0), lam_max=lmax,
                    meta=dict(dims=dims, col_nnz=tuple(col_nnz), keeps=tuple(keeps)))

@@ -71,6 +71,24 @@ def test_argument_validation_without_device(lib):
     assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 1, 15, 16, 16, 16, 1, 1, 1, None) == _lib.ELIMIT
     assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 258, 16, 1, None, 1, None) == _lib.ELIMIT
     assert lib.sl1_dict_dense(ctypes.byref(h), 9, 256, 16, 1, None, 1, None) == _lib.EDTYPE
+    # FAuST: sizes, dtype and the CSR arrays are checked on the host
+    import numpy as np
+    dims = (_lib.c_i64 * 3)(8, 4, 5)
+    nnz = (_lib.c_i64 * 2)(2, 2)
+    rp = np.array([0, 1, 2, 2, 2, 2, 2, 2, 2, 0, 1, 1, 2, 2], dtype=np.int32)
+    ci = np.array([0, 3, 1, 4], dtype=np.int32)
+    va = np.ones(4, dtype=np.float32)
+    fa = lambda dt, J, d, r, c: lib.sl1_dict_faust(ctypes.byref(h), dt, J, d, nnz, r.ctypes.data, c.ctypes.data,
+                                                   va.ctypes.data, 1, None)
+    assert lib.sl1_dict_faust(ctypes.byref(h), _lib.F32, 0, dims, nnz, None, None, None, None, None) == _lib.EINVAL
+    assert fa(_lib.BF16, 2, dims, rp, ci) == _lib.EDTYPE
+    assert fa(_lib.F32, 9, dims, rp, ci) == _lib.ELIMIT
+    assert fa(_lib.F32, 2, (_lib.c_i64 * 3)(6, 4, 5), rp, ci) == _lib.ELIMIT        # N not a multiple of 4
+    assert fa(_lib.F32, 2, (_lib.c_i64 * 3)(8, 2000, 5), rp, ci) == _lib.ELIMIT     # inner size above 1024
+    bad = ci.copy(); bad[1] = 4                                                    # column out of range
+    assert fa(_lib.F32, 2, dims, rp, bad) == _lib.EINVAL
+    bad = rp.copy(); bad[8] = 1                                                    # rows do not end at nnz
+    assert fa(_lib.F32, 2, dims, bad, ci) == _lib.EINVAL
     assert lib.sl1_solve(None, 1, None, None, None, 1, None, None, None, None, None, None, None, None, None,
                          None) == _lib.EINVAL
     assert lib.sl1_lambda_max(None, 1, None, 1, None, None) == _lib.EINVAL

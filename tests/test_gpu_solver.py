@@ -56,6 +56,10 @@ ADJ_CASES = [
     ("C3 ragged N=2500", lambda: synth.config3(N=2500, K=600, s=20), 1e-12),
     ("C4-small kron bf16", lambda: synth.config4(batch=3, n=(16, 32)), 3e-5),
     ("kron f32 n=(32,64) R=4", lambda: synth.config2(n=(32, 64), R_A=4, Rs=(1, 4)), 2e-5),
+    ("C6-small faust f32 ragged K", lambda: synth.config6(N=64, K=1537, depth=3, col_nnz=(8, 8, 24),
+                                                          keeps=(8, 16), batch=3), 1e-12),
+    ("faust f64 one factor", lambda: synth.config6(N=48, K=333, depth=1, col_nnz=(12,), keeps=(6,),
+                                                   dtype="f64", work="f64", batch=2), 1e-12),
 ]
 
 
@@ -74,6 +78,10 @@ def test_adjoint_kernels_match_oracle_products(sl1, name, maker, rtol):
         if st.kind == "kron":                          # accumulation scale: sum_r |b_r| kron |c_r|
             Bv, Cv = st.factor_values()
             Aabs = synth.workloads._kron_sum(np.abs(Bv), np.abs(Cv))
+        elif st.kind == "faust":                       # |S_1| ... |S_J|
+            Aabs = None
+            for M in st.factor_matrices():
+                Aabs = np.abs(M) if Aabs is None else Aabs @ np.abs(M)
         else:
             Aabs = np.abs(At)
         scale = np.abs(z) @ Aabs + 1e-300
@@ -188,6 +196,55 @@ def test_batched_bf16_kronecker_method(sl1, engine):
     assert len(set(out["iters"].tolist())) > 1           # uneven convergence inside one launch
     for b in range(p.batch):
         _check_solution(p, out, b)
+
+
+# ---------------------------------------------------------------------------
+# FAuST approximations (products of sparse factors)
+# ---------------------------------------------------------------------------
+def test_faust_fp64_trace_matches_method_reference(sl1):
+    _say("trace C6-small faust f64 grid")
+    p = synth.config6(N=64, K=515, depth=3, col_nnz=(8, 8, 24), keeps=(8, 12, 16), lam_frac=0.2,
+                      dtype="f64", work="f64")
+    out = _run(sl1, p, tol=1e-10, trace_cap=20000, engine="grid")
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
+                      [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10)
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0 and n == ref.iters and n <= 20000
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+    assert max(int(r) for r in tr[:, 1]) >= 1              # the FAuST stages were used
+    np.testing.assert_allclose(out["x"][0], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
+    _check_solution(p, out, 0, obj_tol=1e-7)
+
+
+@pytest.mark.parametrize("engine", ["grid", "hybrid"])
+def test_faust_method_batch(sl1, engine):
+    _say(f"C6-small faust f32 batch 6 engine={engine}")
+    p = synth.config6(N=64, K=1537, depth=3, col_nnz=(8, 8, 24), keeps=(8, 12, 16), lam_frac=0.15, batch=6)
+    out = _run(sl1, p, tol=1e-10, engine=engine)
+    assert out["status"] == 0 and np.all(out["stage"] == len(p.stages) - 1)
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+def test_faust_meg_shape_method(sl1):
+    _say("C6 faust MEG shape 204 x 8193, batch 2")
+    p = synth.config6(batch=2)
+    out = _run(sl1, p, tol=1e-8)
+    assert out["status"] == 0
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+def test_faust_refused_by_the_whole_solve_engine(sl1):
+    from paper_1812_06635_amd._lib import ELIMIT, Stablel1Error
+    p = synth.config6(N=64, K=515, depth=2, col_nnz=(8, 16), keeps=(8,), lam_frac=0.3)
+    with pytest.raises(Stablel1Error) as e:
+        _run(sl1, p, tol=1e-8, engine="wg")
+    assert e.value.code == ELIMIT
 
 
 # ---------------------------------------------------------------------------

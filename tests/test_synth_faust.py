@@ -1,5 +1,5 @@
 """FAuST inputs (products of sparse factors, the structured family used for the
-MEG operator in Section V-D): the stored factors, their dense value, the per-atom
+MEG operator in Section V-G): the stored factors, their dense value, the per-atom
 error bounds and the relative-complexity model, each checked against an
 independent computation."""
 import numpy as np
