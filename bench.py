@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-single", action="store_true", help="skip the single-signal block")
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled oracle parity check")
     ap.add_argument("--no-variants", action="store_true", help="skip the ISTA / Dynamic Safe variants")
+    ap.add_argument("--no-faust", action="store_true", help="skip the FAuST (MEG-shaped) block")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
@@ -133,7 +134,7 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
     N = p.N
     w = dict(fwd_bytes=[0.0, 0.0], adj_bytes=[0.0, 0.0], adj_flops=[0.0, 0.0], upd_bytes=[0.0, 0.0],
              gram_bytes=0.0, gram_it=0, gemm_flops=0.0, gemm_exec_flops=0.0, gemm_it=0, fin_bytes=0.0,
-             dense_it=[0, 0], kron_it=[0, 0])
+             dense_it=[0, 0], kron_it=[0, 0], faust_it=[0, 0])
     I = len(p.stages) - 1
     prod = product_rows(p, trace, iters, t_split, gemm_min)
     for S in prod.sum(axis=0):
@@ -177,6 +178,11 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
                     w["adj_bytes"][ph] += N * bpe * float(rows[m, 2].sum())
                     w["fwd_bytes"][ph] += N * bpe * float(rows[m, 12].sum())
                     w["dense_it"][ph] += cnt
+                elif st.kind == "faust":
+                    # the adjoint chain: 2 flops per factor entry (FP64), per signal
+                    nnz = sum(len(f[1]) for f in st.factors)
+                    w["adj_flops"][ph] += cnt * 2.0 * nnz
+                    w["faust_it"][ph] += cnt
                 else:
                     n1, k1, n2, k2 = st.dims
                     w["adj_flops"][ph] += cnt * 2.0 * st.R * k2 * n1 * (n2 + k1)
@@ -200,13 +206,16 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
                             avg_launch_us=ms * 1e3 / launches))
         else:
             ach = amount / (ms * 1e-3) / 1e12
-            out.append(dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+            out.append(dict(kernel=name, bound=unit_kind, achieved=ach, peak=peak, unit="TFLOP/s",
                             frac=ach / peak, traffic=None, launches=launches, total_ms=ms,
                             avg_launch_us=ms * 1e3 / launches))
 
     add("k_fwd", *prof["fwd"], work["fwd_bytes"][0], "hbm")
     add("k_adj_dense", *prof["adj_dense"], work["adj_bytes"][0], "hbm")
-    add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma")
+    if work["faust_it"][0] > work["kron_it"][0]:    # structured launch running FAuST chains (FP64 vector)
+        add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "alu", FP64_PEAK_TFLOPS)
+    else:
+        add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma")
     add("k_upd", *prof["upd"], work["upd_bytes"][0], "hbm")
     if "adj_gemm" in prof:
         add("k_adj_gemm", *prof["adj_gemm"], work["gemm_flops"], "mfma", FP64_PEAK_TFLOPS)
@@ -471,6 +480,21 @@ def main():
             "whole_solve_phases_ms": r2["wg_phases"], "roofline": roofline(r2),
             "roofline_kernels": r2["roofline_kernels"],
             "max_gap": r2["max_gap_method"],
+        }
+    if not args.no_faust:
+        log("FAuST block (MEG shape 204 x 8193, 50 signals)")
+        q = synth.config6(batch=50)
+        r3 = solve_block(sl1, torch, np, q, args.tol, max(1, args.steps), args.warmup, "faust")
+        line["faust_meg_shape"] = {
+            "workload": "A (204 x 8193, FP32) = product of 4 sparse factors (204 x 204 x3 with 32 nonzeros per "
+                        "column, 204 x 8193 with 64) + 0.01 G, unit columns; stages: FAuST approximations keeping "
+                        "40, 48, 52, 56 entries per column of the last factor (FP32), then A; 50 signals, 8-sparse "
+                        "x0, lambda = 0.1 lambda_max, tol 1e-6 (synthetic stand-in for the MEG operator)",
+            "time_to_gap_ms": r3["ms_method"], "iters": r3["iters_method"],
+            "plain_fp32_time_to_gap_ms": r3["ms_plain"], "plain_fp32_iters": r3["iters_plain"],
+            "speedup_vs_plain_fp32": r3["ms_plain"] / r3["ms_method"],
+            "rc_model": r3["rc_model"], "rc_measured": r3["rc_measured"], "engine": r3["engine"],
+            "kernel_ms": r3["kernel_ms"], "max_gap": r3["max_gap_method"],
         }
     print(json.dumps(line))
 
