@@ -155,6 +155,12 @@ typedef struct {
                             runs in a chunk of iterations when at least this many signals
                             qualified at the end of the previous chunk (and in the first chunk
                             when the batch has this many); 0 = 64 */
+    const double* x0;    /* [NULL] optional device buffer, batch x K doubles: the initial iterate
+                            (warm start, e.g. the solution at the previous lambda of a path --
+                            the sequential setting of Section I-D). The preserved set still starts
+                            with every atom and the first step has no momentum, so the test stays
+                            safe for any x0; a non-finite entry makes that signal SL1_EINVAL.
+                            NULL: x_0 = 0 (Algorithm 1) */
 } sl1_opts;
 
 #define SL1_FLAG_NO_GRAPH 1   /* launch iterations directly instead of replaying a hipGraph */

@@ -132,7 +132,8 @@ class Result:
 
 
 def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12,
-            eps_scale=1.0, keep_trace=True, update="fista", rule="gap", radius_scale=1.0, screen_every=1):
+            eps_scale=1.0, keep_trace=True, update="fista", rule="gap", radius_scale=1.0, screen_every=1,
+            x0=None):
     """Algorithm 1 (FastL1) with FISTA (or ISTA) and the stable GAP Safe (or
     stable Dynamic Safe) test.
 
@@ -149,6 +150,10 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     screen_every  atoms are rejected only at iterations t with t % screen_every == 0
                (the variation of Algorithm 1 that screens at regular intervals); the
                dual points, gaps and K_t are formed at every iteration.
+    x0         initial iterate (warm start, e.g. the solution at the previous lambda
+               of a path, the sequential setting Section I-D mentions); default 0.
+               The preserved set still starts with every atom, and the first step
+               has no momentum, so screening stays safe whatever x0 is.
     """
     if update not in ("fista", "ista") or rule not in ("gap", "dst"):
         raise ValueError("update must be fista|ista and rule gap|dst")
@@ -156,8 +161,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     N, K = stages[0][0].shape
     y = np.asarray(y, dtype=np.float64)
     y_sq = float(y @ y)
-    x = np.zeros(K)
-    x_prev = np.zeros(K)
+    x = np.zeros(K) if x0 is None else np.array(x0, dtype=np.float64)
+    x_prev = x.copy()
     g_prev = np.zeros(K)
     active = np.ones(K, dtype=bool)
     i = 0

@@ -36,7 +36,7 @@ c_d = ctypes.c_double
 class Opts(ctypes.Structure):
     _fields_ = [("Gamma", c_d), ("tol", c_d), ("margin", c_d), ("max_iter", c_i32), ("y_dtype", c_i32),
                 ("chunk", c_i32), ("flags", c_i32), ("trace", c_p), ("trace_cap", c_i32), ("screen_every", c_i32),
-                ("gemm_signals", c_i32)]
+                ("gemm_signals", c_i32), ("x0", c_p)]
 
 
 # (name, restype, argtypes) of every exported entry point

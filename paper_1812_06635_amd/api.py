@@ -141,7 +141,7 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
-          update="fista", rule="gap", batched_gemm=True, screen_every=1, gemm_signals=0):
+          update="fista", rule="gap", batched_gemm=True, screen_every=1, gemm_signals=0, x0=None):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
@@ -151,7 +151,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     Dynamic Safe, Table I); batched_gemm: signals with large preserved sets on
     the exact dense stage share one matrix-core correlation product;
     screen_every: atoms are rejected only every screen_every iterations;
-    gemm_signals: qualifying signals from which the batched product runs (0: 64).
+    gemm_signals: qualifying signals from which the batched product runs (0: 64);
+    x0: optional (batch, K) float64 device tensor, the initial iterate (warm start).
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
@@ -178,6 +179,14 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.max_iter, opts.chunk = max_iter, chunk
     opts.screen_every = int(screen_every)
     opts.gemm_signals = int(gemm_signals)
+    if x0 is not None:
+        _dev(x0, torch.float64, "x0")
+        if x0.dim() == 1:
+            x0 = x0.unsqueeze(0)
+        if tuple(x0.shape) != (batch, K):
+            raise ValueError(f"x0 must have shape ({batch}, {K})")
+        x0 = x0.contiguous()
+        opts.x0 = x0.data_ptr()
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
     opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
         (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \
@@ -226,6 +235,21 @@ def adjoint(d, y):
     L.check(L.load().sl1_dict_adjoint(d.handle, y.shape[0], _ptr(y), work, _ptr(out), _ptr(z), _stream()),
             "sl1_dict_adjoint")
     return out, z
+
+
+def solve_path(stages, L_, rc, atom_norm, y, lams, warm=True, **kw):
+    """Solves along a sequence of regularization parameters: lams is a list of
+    (batch,) float64 device tensors (usually decreasing).  With warm=True each solve
+    starts from the previous solution (x0), the sequential setting Section I-D
+    mentions; the test itself is the same stable screening from the full atom set.
+    Returns the list of solve() results."""
+    outs = []
+    x0 = None
+    for lam in lams:
+        out = solve(stages, L_, rc, atom_norm, y, lam, x0=x0 if warm else None, **kw)
+        outs.append(out)
+        x0 = out["x"]
+    return outs
 
 
 def measure_rc(stages, batch=1):

@@ -26,6 +26,7 @@ hipError_t launch_time_out(const SolveParams*, int, long long*, hipStream_t);
 hipError_t launch_adjoint_out(const SolveParams*, int, int, int, double*, double*, hipStream_t);
 hipError_t launch_ysq(const SolveParams*, int, double*, hipStream_t);
 hipError_t launch_stat(const SolveParams*, hipStream_t);
+hipError_t launch_init_x0(const SolveParams*, int, const double*, hipStream_t);
 int upd_resident_blocks(size_t);
 hipError_t gemm_lds_attr(size_t);
 hipError_t fwd_lds_attr(size_t);
@@ -620,7 +621,7 @@ const char* sl1_status_str(int s) {
     return "unknown status";
 }
 
-static_assert(sizeof(sl1_opts) == 64, "sl1_opts layout (mirrored by the Python binding)");
+static_assert(sizeof(sl1_opts) == 72, "sl1_opts layout (mirrored by the Python binding)");
 
 int sl1_opts_default(sl1_opts* o) {
     if (!o) return SL1_EINVAL;
@@ -636,6 +637,7 @@ int sl1_opts_default(sl1_opts* o) {
     o->trace_cap = 0;
     o->screen_every = 1;
     o->gemm_signals = kGemmMinSignals;
+    o->x0 = nullptr;
     return SL1_OK;
 }
 
@@ -1174,6 +1176,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 48, w->stream));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
+    if (o.x0) HIP_TRY(launch_init_x0(w->dP, (int)batch, o.x0, w->stream));
     if (prof) {
         for (int k = 0; k < kGridKernels; ++k) {
             w->prof_ms[k] = 0.0;

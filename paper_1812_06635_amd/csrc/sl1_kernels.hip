@@ -1666,6 +1666,66 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
     }
 }
 
+// warm start: x_0 = x_{-1} = x0 (device, batch x K), its nonzeros compacted in atom
+// order into the nonzero list of slot 0 (contiguous, so segment s begins at
+// min(256 s, n)), ||x_0||_1 into the control record.  One block per signal, after
+// k_init; a non-finite entry makes the signal invalid.
+__global__ __launch_bounds__(kBlock) void k_init_x0(const SolveParams* __restrict__ P, const double* __restrict__ x0) {
+    const int b = blockIdx.x, K = P->K;
+    __shared__ int s_w[4];
+    __shared__ double s_red[48];
+    __shared__ Control s_c;
+    if (threadIdx.x == 0) s_c = P->ctrl[2 * b];
+    __syncthreads();
+    if (s_c.done) return;
+    int* nzl = nzbuf(P, b, 0);
+    double* nzv = nzxbuf(P, b, 0);
+    double* xa = xbuf(P, b, 0);
+    double* xb = xbuf(P, b, 1);
+    int cnt = 0;
+    double l1 = 0.0;
+    bool bad = false;
+    for (int base = 0; base < K; base += kBlock) {
+        const int j = base + threadIdx.x;
+        const double v = j < K ? x0[(size_t)b * K + j] : 0.0;
+        bad |= !isfinite(v);
+        if (j < K) {
+            xa[j] = v;
+            xb[j] = v;
+        }
+        const bool nz = v != 0.0;
+        int tot;
+        const int pos = block_excl_scan_flag(nz, s_w, tot);
+        if (nz) {
+            nzl[cnt + pos] = j;
+            nzv[cnt + pos] = v;
+        }
+        cnt += tot;
+        l1 += fabs(v);
+    }
+    double sums[2] = {l1, bad ? 1.0 : 0.0};
+    block_sum<2>(sums, s_red);
+    const int nseg = (cnt + kSeg - 1) / kSeg;
+    int* zp = nzpre(P, b, 0);
+    for (int s = threadIdx.x; s <= nseg; s += kBlock) zp[s] = min(s * kSeg, cnt);
+    if (threadIdx.x == 0) {
+        Control C = s_c;
+        if (sums[1] != 0.0) {
+            C.done = 1;
+            C.status = SL1_EINVAL;
+            P->fin[b].status = SL1_EINVAL;
+            P->cnt_fwd[b] = 0;
+            atomicSub(P->active_signals, 1);
+        } else {
+            C.n_nz = cnt;
+            C.nseg_nz = nseg;
+            C.l1 = sums[0];
+        }
+        P->ctrl[2 * b] = C;
+        P->ctrl[2 * b + 1] = C;
+    }
+}
+
 // statistics of the last forward launch, reduced over the batch once per chunk
 // (max and sum of |A_t|, signals not on the last stage, signals qualifying for
 // the batched correlation product); one block
@@ -1905,6 +1965,11 @@ int upd_resident_blocks(size_t lds) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     return n * cus;
+}
+
+hipError_t launch_init_x0(const SolveParams* dP, int batch, const double* x0, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_x0, dim3(batch), dim3(kBlock), 0, s, dP, x0);
+    return hipGetLastError();
 }
 
 hipError_t launch_stat(const SolveParams* dP, hipStream_t s) {

@@ -53,10 +53,10 @@ def test_host_only_calls(lib):
     assert lib.sl1_status_str(0).decode() == "ok"
     assert "singular" in lib.sl1_status_str(-6).decode()
     o = _lib.Opts()
-    assert ctypes.sizeof(o) == 64          # the library checks sizeof(sl1_opts) == 64 at build time
+    assert ctypes.sizeof(o) == 72          # the library checks sizeof(sl1_opts) == 72 at build time
     assert lib.sl1_opts_default(ctypes.byref(o)) == 0
     assert (o.Gamma, o.tol, o.max_iter, o.chunk, o.y_dtype) == (0.5, 1e-6, 100000, 16, _lib.F32)
-    assert (o.screen_every, o.gemm_signals) == (1, 64)
+    assert (o.screen_every, o.gemm_signals, o.x0) == (1, 64, None)
     assert lib.sl1_opts_default(None) == _lib.EINVAL
     assert lib.sl1_dict_free(None) == 0
 

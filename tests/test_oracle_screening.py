@@ -332,3 +332,66 @@ def test_screening_every_k_iterations_is_safe_and_exact(k):
         if r.t % k != 0:
             assert r.n_keep == r.n_active
     assert any(r.n_keep < r.n_active for r in res.trace)
+
+
+# ---------------------------------------------------------------------------
+# warm starts along a lambda path (the sequential setting of Section I-D)
+# ---------------------------------------------------------------------------
+def test_warm_start_at_the_solution_needs_few_iterations_on_a():
+    # on the exact dictionary alone (plain FISTA + stable GAP Safe) a start at x*
+    # stops almost at once; with approximate stages first the iterate moves toward
+    # the approximate problems' solutions, so Algorithm 1 keeps its cost
+    p = synth.config1(realization=1, lam_frac=0.4)
+    y, lam = p.Y[0], float(p.lam[0])
+    sol = ol.solve(p.A, y, lam, L=p.stages[-1].L, tol=1e-14)
+    exact = _stages(p)[-1:]
+    cold = osc.fast_l1(exact, p.atom_norm, y, lam, [1.0], tol=1e-10)
+    warm = osc.fast_l1(exact, p.atom_norm, y, lam, [1.0], tol=1e-10, x0=sol["x"])
+    assert cold.converged and warm.converged
+    assert warm.iters * 10 <= cold.iters
+    assert not np.any(warm.screened & (sol["x"] != 0))
+    assert np.linalg.norm(warm.x - sol["x"]) <= 1e-5 * np.linalg.norm(sol["x"])
+    staged = osc.fast_l1(_stages(p), p.atom_norm, y, lam, [s.rc_theory for s in p.stages], tol=1e-10,
+                         x0=sol["x"])
+    assert staged.converged and not np.any(staged.screened & (sol["x"] != 0))
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.config1(realization=2),
+                                   lambda: synth.config4(batch=1, n=(16, 32))])
+def test_warm_started_path_is_safe_and_matches_cold_solves(maker):
+    p = maker()
+    y = p.Y[0]
+    rc = [s.rc_theory for s in p.stages]
+    for stages, rcs in ((_stages(p), rc), (_stages(p)[-1:], [1.0])):
+        x0 = None
+        it_warm = it_cold = 0
+        for frac in (0.8, 0.5, 0.3):
+            lam = frac * float(p.lam_max[0])
+            sol = ol.solve(p.A, y, lam, L=p.stages[-1].L)
+            warm = osc.fast_l1(stages, p.atom_norm, y, lam, rcs, tol=1e-10, x0=x0)
+            cold = osc.fast_l1(stages, p.atom_norm, y, lam, rcs, tol=1e-10)
+            assert warm.converged and cold.converged
+            assert not np.any(warm.screened & (sol["x"] != 0))          # safe from any start
+            assert (ol.primal(p.A, y, lam, warm.x) - sol["P"]) / sol["P"] <= 1e-7
+            assert np.linalg.norm(warm.x - cold.x) <= 1e-4 * max(np.linalg.norm(cold.x), 1e-300)
+            it_warm += warm.iters
+            it_cold += cold.iters
+            x0 = warm.x
+        if len(stages) == 1:
+            assert it_warm < it_cold                 # the path pays on the exact dictionary
+
+
+def test_warm_start_from_any_point_keeps_the_first_step_plain():
+    # from an arbitrary x0 the first step has no momentum: it equals a proximal
+    # gradient step from x0 on the first stage (Section I-B)
+    p = synth.config1()
+    y, lam = p.Y[0], float(p.lam[0])
+    rng = np.random.default_rng(3)
+    x0 = np.where(rng.random(p.K) < 0.05, rng.standard_normal(p.K), 0.0)
+    At, eps, L = _stages(p)[0]
+    res = osc.fast_l1(_stages(p), p.atom_norm, y, lam, [s.rc_theory for s in p.stages], tol=1e-10,
+                      x0=x0, max_iter=1)
+    v = x0 + At.T @ (y - At @ x0) / L
+    x1 = np.sign(v) * np.maximum(np.abs(v) - lam / L, 0.0)
+    keep = ~res.screened
+    np.testing.assert_allclose(res.x[keep], x1[keep], rtol=1e-12, atol=1e-14)
