@@ -25,6 +25,11 @@ Readings of points the paper leaves open (each stated where it is used):
   * Screening at regular intervals (Algorithm 1's stated variation): atoms are
     rejected only every screen_every iterations; K_t and the switch are
     evaluated at every iteration.
+  * Error bounds in any l_q norm (Lemma 1, Lemma 2, the Appendix): eps_j bounds
+    ||a_j - a~_j||_q, q in [1, inf]; the dual scaling and the test then use the
+    dual norm ||z||_{q*} (1/q + 1/q* = 1), and Theorem 1 (an l2 statement) takes
+    E = N^((1/2 - 1/q)_+) max_j eps_j, the Hoelder constant of the Appendix with
+    p* = 2 bounding ||a_j - a~_j||_2 by the l_q bound.  q = 2 is the default.
   * Options beside FISTA + stable GAP Safe (Table III's other combinations):
     ISTA (the update of Section I-B, no momentum), and the stable Dynamic Safe
     sphere B(y/lambda, ||theta'_t - y/lambda||) (Table I, fourth row) tested
@@ -41,20 +46,49 @@ import numpy as np
 from .lasso import soft_threshold
 
 
+def dual_exponent(q):
+    """q* with 1/q + 1/q* = 1 (q = 1 gives inf, q = inf gives 1): the exponent of the
+    dual norm that the l_q zone of Lemma 1 brings into the tests (Appendix)."""
+    q = float(q)
+    if q < 1.0 or np.isnan(q):
+        raise ValueError("q must lie in [1, inf]")
+    if q == 1.0:
+        return np.inf
+    if np.isinf(q):
+        return 1.0
+    return q / (q - 1.0)
+
+
+def lq_norm(v, p):
+    """||v||_p for p in [1, inf], written as m (sum (|v_i|/m)^p)^(1/p) with m = max |v_i|
+    (the definition, by homogeneity) so that large p cannot underflow."""
+    a = np.abs(np.asarray(v, dtype=np.float64)).ravel()
+    m = float(np.max(a, initial=0.0))
+    if m == 0.0 or np.isinf(p):
+        return m
+    return m * float(np.sum((a / m) ** p)) ** (1.0 / p)
+
+
+def l2_constant(q, N):
+    """sup of ||u||_2 over the unit l_q ball of R^N, N^((1/2 - 1/q)_+): the constant C
+    of the Appendix with p* = 2 (Hoelder), so ||e||_2 <= C ||e||_q."""
+    return float(N) ** max(0.5 - 1.0 / float(q), 0.0)
+
+
 def sphere_test(at_c, radius, a_norm):
     """mu(a|B(c,R)) = |a^T c| + R ||a||_2 (closed form of Section II-B, p = 2)."""
     return np.abs(at_c) + radius * a_norm
 
 
 def stable_sphere_test(at_c, eps, c_norm, radius, a_norm):
-    """mu(S'|B(c,R)) = |a~^T c| + eps ||c||_2 + R a for the norm-restricted zone
-    (Section III-B, Lemma 1, q = p = 2)."""
+    """mu(S'|B(c,R)) = |a~^T c| + eps ||c||_{q*} + R a for the norm-restricted zone
+    (Section III-B, Lemma 1, p = 2); c_norm is ||c||_{q*} of the bounds' norm q."""
     return np.abs(at_c) + eps * c_norm + radius * a_norm
 
 
 def stable_dual_scaling(corr, eps, z_norm):
-    """max(1, max_j (|a~_j^T z| + eps_j ||z||_2)): the divisor of the stable dual
-    scaling Theta'(z|A~, eps) (Section III-C, Lemma 2)."""
+    """max(1, max_j (|a~_j^T z| + eps_j ||z||_{q*})): the divisor of the stable dual
+    scaling Theta'(z|A~, eps) (Section III-C, Lemma 2); z_norm is ||z||_{q*}."""
     m = float(np.max(np.abs(corr) + eps * z_norm, initial=0.0))
     return max(1.0, m)
 
@@ -85,10 +119,12 @@ def dynamic_radius(theta, y, lam):
     return float(np.linalg.norm(theta - y / lam))
 
 
-def stable_lambda_max(At, eps, y):
-    """lambda'_max = max_j (|a~_j^T y| + eps_j ||y||_2) >= lambda_max (Section III-C,
-    stable static sphere)."""
-    return float(np.max(np.abs(At.T @ y) + eps * np.linalg.norm(y)))
+def stable_lambda_max(At, eps, y, q=2.0):
+    """lambda'_max = max_j (|a~_j^T y| + eps_j ||y||_{q*}) >= lambda_max (Section III-C,
+    stable static sphere), eps_j bounding ||a_j - a~_j||_q."""
+    qs = dual_exponent(q)
+    y_norm = np.linalg.norm(y) if qs == 2.0 else lq_norm(y, qs)
+    return float(np.max(np.abs(At.T @ y) + eps * y_norm))
 
 
 def switch_dictionary(i, I, gamma, Gamma, K_t, rc_i, K):
@@ -133,7 +169,7 @@ class Result:
 
 def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12,
             eps_scale=1.0, keep_trace=True, update="fista", rule="gap", radius_scale=1.0, screen_every=1,
-            x0=None):
+            x0=None, q=2.0):
     """Algorithm 1 (FastL1) with FISTA (or ISTA) and the stable GAP Safe (or
     stable Dynamic Safe) test.
 
@@ -154,11 +190,16 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
                of a path, the sequential setting Section I-D mentions); default 0.
                The preserved set still starts with every atom, and the first step
                has no momentum, so screening stays safe whatever x0 is.
+    q          norm of the error bounds, one value or one per stage: eps_j of stage i
+               bounds ||a_j - a~^i_j||_{q_i}, 1 <= q_i <= inf (Lemma 1 with an l_q zone).
     """
     if update not in ("fista", "ista") or rule not in ("gap", "dst"):
         raise ValueError("update must be fista|ista and rule gap|dst")
     I = len(stages) - 1
     N, K = stages[0][0].shape
+    qs_list = [float(v) for v in (np.broadcast_to(np.asarray(q, dtype=np.float64), (I + 1,)))]
+    for v in qs_list:
+        dual_exponent(v)                                   # rejects q < 1
     y = np.asarray(y, dtype=np.float64)
     y_sq = float(y @ y)
     x = np.zeros(K) if x0 is None else np.array(x0, dtype=np.float64)
@@ -187,7 +228,10 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         r_norm = np.sqrt(r_sq)
         y_rho = float(y @ rho)
         s0 = y_rho / (lam * r_sq) if r_sq > 0 else 0.0
-        m_stable = float(np.max(np.abs(g[act]) + eps[act] * r_norm, initial=0.0))
+        # ||rho~_t||_{q*}: the norm that the l_q error bounds of this stage pair with
+        q_dual = dual_exponent(qs_list[i])
+        z_norm = r_norm if q_dual == 2.0 else lq_norm(rho, q_dual)
+        m_stable = float(np.max(np.abs(g[act]) + eps[act] * z_norm, initial=0.0))
         m_conv = float(np.max(np.abs(g[act]), initial=0.0))
         s_stable = clip_scale(s0, m_stable)
         s_conv = clip_scale(s0, m_conv)
@@ -196,6 +240,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         G_stable = P - dual_value_along(s_stable, lam, y_rho, r_sq, y_sq)
         G_conv = P - dual_value_along(s_conv, lam, y_rho, r_sq, y_sq)
         E = float(np.max(eps[act], initial=0.0))
+        if qs_list[i] != 2.0:                              # ||a_j - a~_j||_2 <= C ||a_j - a~_j||_q
+            E *= l2_constant(qs_list[i], N)
         R_stable, delta = stable_gap_radius(G_stable, r_norm, E, x_l1, lam)
         if rule == "dst":
             R_test = dynamic_radius(s_stable * rho, y, lam)       # ||theta'_t - y/lambda||
@@ -228,7 +274,7 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         if rule == "dst":
             mu = sphere_test(aty / lam, R_test, atom_norm)     # centre y/lambda, a^T y given
         else:
-            c_norm = abs(s_stable) * r_norm                   # ||theta'_t||_2
+            c_norm = abs(s_stable) * z_norm                   # ||theta'_t||_{q*}
             mu = stable_sphere_test(s_stable * g, eps, c_norm, R_test, atom_norm)
         keep = active & (mu >= 1.0 - margin)
         if t % max(1, screen_every) != 0:

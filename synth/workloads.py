@@ -116,7 +116,8 @@ class Stage:
     C: np.ndarray | None = None        # kron: (R, k2, n2) storage array
     dims: tuple | None = None          # kron: (n1, k1, n2, k2); faust: (d_0 = N, d_1, ..., d_J = K)
     factors: list | None = None        # faust: [(row_ptr, col_idx, values)] per factor, CSR
-    eps: np.ndarray | None = None      # (K,) exact bound on ||a_j - a~_j||_2
+    eps: np.ndarray | None = None      # (K,) exact bound on ||a_j - a~_j||_q
+    q: float = 2.0                     # norm of the bounds eps, 1 <= q <= inf
     L: float = 0.0                     # ||A~||_2^2 (FP64)
     rc_theory: float = 1.0             # relative complexity model of the products
     label: str = ""
@@ -220,6 +221,31 @@ def _round_work(M: np.ndarray, work: str) -> np.ndarray:
 def _bound(diff_norm: np.ndarray, a_norm: np.ndarray, at_norm: np.ndarray) -> np.ndarray:
     """Exact FP64 column-difference norm, widened by a few FP64 ulps of the operands."""
     return diff_norm + 1e-13 * (a_norm + at_norm)
+
+
+def _col_norm(M: np.ndarray, q: float) -> np.ndarray:
+    return np.linalg.norm(M, ord=q, axis=0) if np.isinf(q) or q in (1.0, 2.0) else \
+        np.sum(np.abs(M) ** q, axis=0) ** (1.0 / q)
+
+
+def with_lq_bounds(problem, q, stages=None):
+    """A copy of `problem` whose approximate stages carry l_q error bounds
+    eps_j = ||a_j - a~_j||_q (widened like the l2 ones) instead of l2 bounds: the
+    zone B_q(a~_j, eps_j) of Lemma 1 (Section III-B).  `stages` selects the stage
+    indices that switch (default: every stage but the exact one, whose eps stays 0);
+    q may be a number or np.inf."""
+    import copy
+    q = float(q)
+    out = copy.copy(problem)
+    out.stages = [copy.copy(st) for st in problem.stages]
+    sel = range(len(out.stages) - 1) if stages is None else stages
+    A = problem.A
+    for i in sel:
+        st = out.stages[i]
+        At = st.values()
+        st.eps = _bound(_col_norm(A - At, q), _col_norm(A, q), _col_norm(At, q))
+        st.q = q
+    return out
 
 
 # ----------------------------------------------------------------------------
