@@ -7,7 +7,8 @@
  *
  * Method (Algorithm 1, FastL1, with Algorithm 2, SwitchDictionary): FISTA
  * iterations run on a sequence A~^0, ..., A~^I = A of approximations whose atoms
- * are known up to l2 error bounds ||a~_j - a_j||_2 <= eps_j (Section III-B).  Each
+ * are known up to error bounds ||a~_j - a_j||_q <= eps_j (Section III-B; any l_q
+ * norm, 1 <= q <= inf, as Lemma 1 and Lemma 2 allow; q = 2 is the usual one).  Each
  * iteration applies the stable GAP Safe sphere test (Table I, last row; Theorem 1)
  * so that rejected atoms are provably inactive for the ORIGINAL problem, and
  * switches to a finer approximation on duality-gap saturation (Section IV-A) or
@@ -72,15 +73,23 @@ typedef struct sl1_dict_s* sl1_dict;
  *              alive and unchanged until sl1_dict_free.
  *   col_scale  optional (may be NULL) K floats, device: atom j is
  *              col_scale[j] * decode(A[:, j]).  Copied.
- *   eps        K doubles, device: bounds eps_j >= ||a~_j - a_j||_2 against the
+ *   eps        K doubles, device: bounds eps_j >= ||a~_j - a_j||_q against the
  *              exact dictionary (Section III-B; all zero for the exact A).  Copied.
  *              The library adds to each eps_j a bound on its own rounding in the
  *              products with this stage, so the test stays safe (Lemma 1, Lemma 2,
  *              Theorem 1 hold with the enlarged bounds).
- * Errors: SL1_EINVAL (NULL A/eps, N or K < 1), SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP, SL1_ENOMEM.
+ *   q          the norm of the bounds, 1 <= q <= inf (INFINITY accepted); 2 for l2
+ *              bounds.  The dual scaling and the test pair eps with ||z||_{q*},
+ *              1/q + 1/q* = 1 (Lemma 1 with an l_q zone, Lemma 2), and Theorem 1
+ *              uses the l2 column bound N^((1/2 - 1/q)_+) eps_j (the Hoelder
+ *              constant of the Appendix).  Stages with q != 2 run in the grid engine:
+ *              SL1_ENGINE_WG refuses them with SL1_ELIMIT, and the hybrid engine
+ *              keeps the grid kernels throughout when the last stage has q != 2.
+ * Errors: SL1_EINVAL (NULL A/eps, N or K < 1, q < 1 or NaN), SL1_EDTYPE, SL1_ELIMIT,
+ * SL1_EHIP, SL1_ENOMEM.
  */
 int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A,
-                   const float* col_scale, const double* eps, void* stream);
+                   const float* col_scale, const double* eps, double q, void* stream);
 
 /*
  * sl1_dict_kron -- a structured stage A~ = sum_{r<R} B_r kron C_r (the SuKro model
@@ -88,11 +97,11 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
  *   dtype      SL1_F64, SL1_F32 or SL1_BF16 (factor storage).
  *   B, C       R*n1*k1 and R*n2*k2 elements, device, layout in the header comment.
  *              Copied (the factors are small).
- *   eps        K doubles, device, as for sl1_dict_dense.  Copied.
+ *   eps, q     as for sl1_dict_dense (eps copied).
  * Errors: SL1_EINVAL, SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP, SL1_ENOMEM.
  */
 int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k2,
-                  const void* B, const void* C, const double* eps, void* stream);
+                  const void* B, const void* C, const double* eps, double q, void* stream);
 
 /*
  * sl1_dict_faust -- a structured stage A~ = S_1 S_2 ... S_J, a product of sparse
@@ -108,7 +117,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
  *   col_idx    host, CSR column indices, concatenated (nnz[l] for factor l;
  *              strictly increasing within a row).
  *   val        host, values in dtype, concatenated like col_idx.
- *   eps        K doubles, device, as for sl1_dict_dense.
+ *   eps, q     as for sl1_dict_dense.
  * Everything is copied; the transposed factors, ||a~_j|| and the rounding allowance
  * of the chain's FP64 sums are formed here.  FAuST stages run in the grid engine
  * (SL1_ENGINE_WG refuses them with SL1_ELIMIT).
@@ -117,7 +126,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
  */
 int sl1_dict_faust(sl1_dict* out, int dtype, int J, const int64_t* dims, const int64_t* nnz,
                    const int32_t* row_ptr, const int32_t* col_idx, const void* val, const double* eps,
-                   void* stream);
+                   double q, void* stream);
 
 /* Releases a handle; NULL is accepted and ignored. */
 int sl1_dict_free(sl1_dict d);
@@ -246,8 +255,9 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
               int32_t* iters, int32_t* stage, void* stream);
 
 /*
- * sl1_lambda_max -- out[b] = max_j (|a~_j^T y_b| + eps_j ||y_b||_2), the stable
- * lambda'_max of Section III-C (equal to lambda_max = ||A^T y_b||_inf when eps = 0).
+ * sl1_lambda_max -- out[b] = max_j (|a~_j^T y_b| + eps_j ||y_b||_{q*}), the stable
+ * lambda'_max of Section III-C for the stage's bound norm q (equal to
+ * lambda_max = ||A^T y_b||_inf when eps = 0).
  *   y    batch x N in y_dtype;  out  batch doubles.  Includes the library's own
  *        rounding allowance, so it is an upper bound.  Synchronous.
  */

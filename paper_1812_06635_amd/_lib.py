@@ -41,10 +41,11 @@ class Opts(ctypes.Structure):
 
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = [
-    ("sl1_dict_dense", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, c_i64, c_p, c_p, c_p, c_p]),
-    ("sl1_dict_kron", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_p, c_p]),
+    ("sl1_dict_dense", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, c_i64, c_p, c_p, c_p, c_d, c_p]),
+    ("sl1_dict_kron", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_p, c_d,
+                              c_p]),
     ("sl1_dict_faust", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
-                               c_p, c_p, c_p, c_p, c_p]),
+                               c_p, c_p, c_p, c_p, c_d, c_p]),
     ("sl1_dict_free", c_i32, [c_dict]),
     ("sl1_dict_info", c_i32, [c_dict, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), ctypes.POINTER(c_d),
                               ctypes.POINTER(c_d)]),

@@ -50,9 +50,10 @@ class Dict:
         return self._h
 
     @classmethod
-    def dense(cls, A, eps, dtype, scale=None):
+    def dense(cls, A, eps, dtype, scale=None, q=2.0):
         """A: (K, N) device tensor, atom-major (= column-major N x K), storage
-        dtype float64 / float32 / int16 (bf16 bits) / uint8 (fp8 E4M3 codes)."""
+        dtype float64 / float32 / int16 (bf16 bits) / uint8 (fp8 E4M3 codes);
+        eps bounds ||a_j - a~_j||_q (q in [1, inf], 2 by default)."""
         _dev(A, _STORAGE[dtype], "A")
         _dev(eps, torch.float64, "eps")
         if scale is not None:
@@ -60,12 +61,13 @@ class Dict:
         K, N = A.shape
         h = L.c_dict()
         L.check(L.load().sl1_dict_dense(ctypes.byref(h), DTYPES[dtype], N, K, _ptr(A), _ptr(scale), _ptr(eps),
-                                        _stream()), "sl1_dict_dense")
+                                        float(q), _stream()), "sl1_dict_dense")
         return cls(h, (A, scale), N, K, "dense", dtype)
 
     @classmethod
-    def kron(cls, B, C, eps, dtype):
-        """B: (R, k1, n1), C: (R, k2, n2) device tensors (each term column-major)."""
+    def kron(cls, B, C, eps, dtype, q=2.0):
+        """B: (R, k1, n1), C: (R, k2, n2) device tensors (each term column-major);
+        eps and q as for dense."""
         _dev(B, _STORAGE[dtype], "B")
         _dev(C, _STORAGE[dtype], "C")
         _dev(eps, torch.float64, "eps")
@@ -75,13 +77,14 @@ class Dict:
             raise ValueError("B and C must have the same number of terms")
         h = L.c_dict()
         L.check(L.load().sl1_dict_kron(ctypes.byref(h), DTYPES[dtype], R, n1, k1, n2, k2, _ptr(B), _ptr(C),
-                                       _ptr(eps), _stream()), "sl1_dict_kron")
+                                       _ptr(eps), float(q), _stream()), "sl1_dict_kron")
         return cls(h, None, n1 * n2, k1 * k2, "kron", dtype)
 
     @classmethod
-    def faust(cls, dims, factors, eps, dtype):
+    def faust(cls, dims, factors, eps, dtype, q=2.0):
         """A~ = S_1 ... S_J from host CSR factors [(row_ptr int32, col_idx int32,
-        values float64/float32)], S_l of dims[l-1] x dims[l]; eps (K,) device FP64."""
+        values float64/float32)], S_l of dims[l-1] x dims[l]; eps (K,) device FP64
+        and q as for dense."""
         if dtype not in ("f64", "f32"):
             raise ValueError("FAuST factors are f64 or f32")
         _dev(eps, torch.float64, "eps")
@@ -96,7 +99,7 @@ class Dict:
         nz = (L.c_i64 * J)(*[len(f[1]) for f in factors])
         h = L.c_dict()
         L.check(L.load().sl1_dict_faust(ctypes.byref(h), DTYPES[dtype], J, dd, nz, rp.ctypes.data, ci.ctypes.data,
-                                        va.ctypes.data, _ptr(eps), _stream()), "sl1_dict_faust")
+                                        va.ctypes.data, _ptr(eps), float(q), _stream()), "sl1_dict_faust")
         return cls(h, None, int(dims[0]), int(dims[-1]), "faust", dtype)
 
     def info(self):
@@ -121,19 +124,21 @@ class Dict:
 
 def upload_stage(stage, device="cuda"):
     """Device copy of a host stage description with attributes kind, dtype,
-    data/scale (dense), B/C (kron) or dims/factors (faust), eps (numpy arrays)."""
+    data/scale (dense), B/C (kron) or dims/factors (faust), eps (numpy arrays) and
+    optionally q, the norm of eps (2 when absent)."""
     eps = torch.from_numpy(np.ascontiguousarray(stage.eps, dtype=np.float64)).to(device)
+    q = float(getattr(stage, "q", 2.0))
     if stage.kind == "dense":
         arr = stage.data.view(np.int16) if stage.dtype == "bf16" else stage.data
         A = torch.from_numpy(np.ascontiguousarray(arr)).to(device)
         sc = None if stage.scale is None else torch.from_numpy(np.ascontiguousarray(stage.scale)).to(device)
-        return Dict.dense(A, eps, stage.dtype, sc)
+        return Dict.dense(A, eps, stage.dtype, sc, q=q)
     if stage.kind == "faust":
-        return Dict.faust(stage.dims, stage.factors, eps, stage.dtype)
+        return Dict.faust(stage.dims, stage.factors, eps, stage.dtype, q=q)
     conv = (lambda a: a.view(np.int16)) if stage.dtype == "bf16" else (lambda a: a)
     B = torch.from_numpy(np.ascontiguousarray(conv(stage.B))).to(device)
     C = torch.from_numpy(np.ascontiguousarray(conv(stage.C))).to(device)
-    return Dict.kron(B, C, eps, stage.dtype)
+    return Dict.kron(B, C, eps, stage.dtype, q=q)
 
 
 _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybrid": L.FLAG_ENGINE_HYBRID}

@@ -61,6 +61,7 @@ struct sl1_dict_s {
     void* fa_tval = nullptr;
     int fa_maxd = 0, fa_q = 0, fa_dlast = 0;
     double eps_max_in = 0.0, eps_max_eff = 0.0, at_norm_max = 0.0, rc_model = 1.0;
+    double q = 2.0;            // norm of the error bounds (1 <= q <= inf)
 };
 
 #define HIP_TRY(x)                                   \
@@ -94,6 +95,16 @@ double bf16_host(uint16_t b) {
 // Bound on |computed - exact| of both products with a stage, per unit
 // ||abs-atom||_2 ||vector||_2 (standard gamma_n = n u accumulation bounds, doubled
 // to cover any order or internal precision of the matrix-core accumulation).
+// The allowances bound a correlation's rounding by kappa (|a~_j|^T |z|) <= kappa ||a~_j||_2 ||z||_2;
+// against l_q bounds, which pair with ||z||_{q*}, ||z||_2 <= N^((1/q - 1/2)_+) ||z||_{q*}.
+double bound_norm_factor(const sl1_dict_s& d) {
+    const double e = std::isinf(d.q) ? -0.5 : 1.0 / d.q - 0.5;
+    return e > 0.0 ? std::pow((double)d.N, e) : 1.0;
+}
+
+// q of an l_q bound: 1 <= q <= inf (NaN rejected)
+bool valid_bound_norm(double q) { return q >= 1.0; }
+
 double rounding_allowance(const sl1_dict_s& d) {
     const double N = (double)d.N, K = (double)d.K;
     if (d.kind == kDense) return 2.0 * (N + K + 32.0) * kU64;
@@ -179,6 +190,7 @@ int make_workspace(Workspace& w) {
     const size_t o_zp = take(B * 2 * np * 4);
     const size_t o_z = take(B * N * ws);
     const size_t o_rp = take(B * w.nrc * 3 * 8);
+    const size_t o_zq = take(B * 8);
     const size_t o_adp = take(B * w.nadj_max * 4 * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
     const size_t o_cnt = take(B * 10 * 4);
@@ -207,6 +219,7 @@ int make_workspace(Workspace& w) {
     p.nz_pre = (int*)(m + o_zp);
     p.z = (double*)(m + o_z);
     p.res_part = (double*)(m + o_rp);
+    p.zq = (double*)(m + o_zq);
     p.adj_part = (double*)(m + o_adp);
     p.upd_part = (double*)(m + o_up);
     p.cnt_fwd = (int*)(m + o_cnt);
@@ -285,6 +298,10 @@ void fill_stage(StageDesc& s, const sl1_dict_s& d, double L, double rc) {
     s.rc = rc;
     s.at_norm_max = d.at_norm_max;
     s.eps_max = d.eps_max_eff;
+    // l_q bounds: the dual exponent q* and the l2 constant N^((1/2 - 1/q)_+)
+    s.qmode = d.q == 2.0 ? 0 : (d.q == 1.0 ? 2 : (std::isinf(d.q) ? 3 : 1));
+    s.qd = d.q == 1.0 ? INFINITY : (std::isinf(d.q) ? 1.0 : d.q / (d.q - 1.0));
+    s.cq = d.q > 2.0 ? std::pow((double)d.N, std::isinf(d.q) ? 0.5 : 0.5 - 1.0 / d.q) : 1.0;
 }
 
 LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
@@ -320,6 +337,9 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
         extra = std::max(extra, need);
     }
     c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
+    c.g_lq = 0;
+    for (int i = 0; i < p.n_stages; ++i)
+        if (p.st[i].qmode != 0) c.g_lq = w.batch;
     c.g_adj = dense ? (int)std::min<long long>((long long)w.batch * w.nadj_max, 2048) : 0;
     c.g_adjk = kron_items ? (int)std::min<long long>((long long)w.batch * kron_items, 1024) : 0;
     // update: one resident round of blocks (each block takes a contiguous range of items)
@@ -356,8 +376,8 @@ int gemm_min_atoms(const SolveParams& p) {
 bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
            a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_adjk == b.g_adjk && a.g_upd == b.g_upd &&
-           a.g_gemm == b.g_gemm && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj && a.lds_adjk == b.lds_adjk &&
-           a.lds_upd == b.lds_upd && a.lds_gemm == b.lds_gemm;
+           a.g_gemm == b.g_gemm && a.g_lq == b.g_lq && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj &&
+           a.lds_adjk == b.lds_adjk && a.lds_upd == b.lds_upd && a.lds_gemm == b.lds_gemm;
 }
 
 int check_lds(const LaunchCfg& c) {
@@ -424,6 +444,7 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act, bool gram) {
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
         if (s.kind == kFaust) return 0;         // FAuST stages run in the grid kernels only
+        if (s.qmode != 0) return 0;             // so do stages with l_q bounds, q != 2
         if (s.kind != kKron) continue;
         const size_t es = s.dtype == SL1_F64 ? 8 : (s.dtype == SL1_F32 ? 4 : 2);
         fac = std::max(fac, a16(((size_t)s.R * s.k1 * s.n1 + (size_t)s.R * s.k2 * s.n2) * es));
@@ -678,9 +699,10 @@ static int finish_dict_host_eps(sl1_dict_s* d, const double* eps, hipStream_t s)
 }
 
 int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A, const float* col_scale,
-                   const double* eps, void* stream) {
-    if (!out || !A || !eps || N < 1 || K < 1) return SL1_EINVAL;
+                   const double* eps, double q, void* stream) {
+    if (!out) return SL1_EINVAL;
     *out = nullptr;
+    if (!A || !eps || N < 1 || K < 1 || !valid_bound_norm(q)) return SL1_EINVAL;
     if (dtype_size(dtype) == 0) return SL1_EDTYPE;
     if (N % 4 != 0 || N > kMaxN || K > (int64_t)kMaxSeg * kSeg) return SL1_ELIMIT;
     hipStream_t s = (hipStream_t)stream;
@@ -691,6 +713,7 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
     d->N = N;
     d->K = K;
     d->A = A;
+    d->q = q;
     if (dtype == SL1_F64 || dtype == SL1_F32) d->vec = 4;
     else if (dtype == SL1_BF16) d->vec = (N % 8 == 0) ? 8 : 4;
     else d->vec = (N % 16 == 0) ? 16 : 4;
@@ -707,7 +730,7 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
     int* bad = nullptr;
     if (hipMalloc(&bad, 4) != hipSuccess) return SL1_ENOMEM;
     HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
-    const double kappa = rounding_allowance(*d);
+    const double kappa = rounding_allowance(*d) * bound_norm_factor(*d);
     HIP_TRY(launch_dense_norms(dtype, A, d->scale, (int)N, (int)K, eps, kappa, d->at_norm, d->eps_eff, bad, s));
     int hbad = 0;
     std::vector<double> an(K), ee(K);
@@ -728,9 +751,10 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
 }
 
 int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k2, const void* B, const void* C,
-                  const double* eps, void* stream) {
-    if (!out || !B || !C || !eps || R < 1 || n1 < 1 || k1 < 1 || n2 < 1 || k2 < 1) return SL1_EINVAL;
+                  const double* eps, double q, void* stream) {
+    if (!out) return SL1_EINVAL;
     *out = nullptr;
+    if (!B || !C || !eps || R < 1 || n1 < 1 || k1 < 1 || n2 < 1 || k2 < 1 || !valid_bound_norm(q)) return SL1_EINVAL;
     if (dtype != SL1_F64 && dtype != SL1_F32 && dtype != SL1_BF16) return SL1_EDTYPE;
     if (n1 % 16 || k1 % 16 || n2 % 16 || k2 % 16) return SL1_ELIMIT;
     const int64_t N = (int64_t)n1 * n2, K = (int64_t)k1 * k2;
@@ -742,6 +766,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     d->dtype = dtype;
     d->N = N;
     d->K = K;
+    d->q = q;
     d->R = R;
     d->n1 = n1;
     d->k1 = k1;
@@ -812,7 +837,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     HIP_TRY(hipMemcpyAsync(d->at_norm, an.data(), K * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_ab, ab.data(), K * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
-    const double kappa = rounding_allowance(*d);
+    const double kappa = rounding_allowance(*d) * bound_norm_factor(*d);
     HIP_TRY(launch_eps_fold(eps, d_ab, kappa, (int)K, d->eps_eff, bad, s));
     std::vector<double> ee(K);
     int hbad = 0;
@@ -833,9 +858,10 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
 }
 
 int sl1_dict_faust(sl1_dict* out, int dtype, int J, const int64_t* dims, const int64_t* nnz, const int32_t* row_ptr,
-                   const int32_t* col_idx, const void* val, const double* eps, void* stream) {
-    if (!out || !dims || !nnz || !row_ptr || !col_idx || !val || !eps || J < 1) return SL1_EINVAL;
+                   const int32_t* col_idx, const void* val, const double* eps, double q, void* stream) {
+    if (!out) return SL1_EINVAL;
     *out = nullptr;
+    if (!dims || !nnz || !row_ptr || !col_idx || !val || !eps || J < 1 || !valid_bound_norm(q)) return SL1_EINVAL;
     if (dtype != SL1_F64 && dtype != SL1_F32) return SL1_EDTYPE;
     if (J > kFaustMax) return SL1_ELIMIT;
     const int64_t N = dims[0], K = dims[J];
@@ -1001,7 +1027,7 @@ int sl1_dict_faust(sl1_dict* out, int dtype, int J, const int64_t* dims, const i
     HIP_TRY(hipMemcpyAsync(d_ab, ab.data(), K * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(bad, 0, 4, s));
     // the chain's FP64 sums have at most sum_l max(row, column nonzeros of S_l) terms
-    const double kappa = 2.0 * ((double)sum_terms + (double)J + (double)K + 32.0) * kU64;
+    const double kappa = 2.0 * ((double)sum_terms + (double)J + (double)K + 32.0) * kU64 * bound_norm_factor(*d);
     HIP_TRY(launch_eps_fold(eps, d_ab, kappa, (int)K, d->eps_eff, bad, s));
     std::vector<double> ee(K);
     int hbad = 0;
@@ -1134,8 +1160,9 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (eng & (eng - 1)) return SL1_EINVAL;   // at most one engine flag
     const bool gram = !(o.flags & SL1_FLAG_TAIL_COLUMNS);
     const size_t wlds = wg_layout(p, false, 0, false);
-    // the tail hand-over needs a dense last stage whose tail layout fits
-    bool tail_fits = p.st[p.n_stages - 1].kind == kDense;
+    // the tail hand-over needs a dense last stage with l2 bounds whose tail layout fits
+    const bool tail_kind = p.st[p.n_stages - 1].kind == kDense && p.st[p.n_stages - 1].qmode == 0;
+    bool tail_fits = tail_kind;
     if (tail_fits) {
         SolveParams probe = p;
         tail_fits = wg_layout(probe, true, 64, gram) != 0;
@@ -1145,7 +1172,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
         if (!wlds) return SL1_ELIMIT;
         use_wg = true;
     } else if (eng == SL1_FLAG_ENGINE_HYBRID) {
-        if (p.st[p.n_stages - 1].kind == kDense && !tail_fits) return SL1_ELIMIT;
+        if (tail_kind && !tail_fits) return SL1_ELIMIT;
         hybrid = tail_fits;
     } else if (eng == 0) {
         // small dictionaries: one workgroup per signal throughout (a dense stage is

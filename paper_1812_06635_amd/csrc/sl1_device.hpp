@@ -314,9 +314,19 @@ __device__ __forceinline__ double fp64_slack(int N) {
     return nu / (1.0 - nu);
 }
 
+// ||z||_{q*} of the stored direction, the norm that the stage's l_q bounds pair with
+// in the dual scaling and the test (Lemma 2, Lemma 1): sqrt(zz) for l2 bounds,
+// otherwise the value the l_q launch stored for the iteration.
+__device__ __forceinline__ double dual_norm_z(const SolveParams* P, const StageDesc& st, int b, double zz) {
+    return st.qmode == 0 ? sqrt(zz) : P->zq[b];
+}
+
+// zq = ||z||_{q*} for the stage's bound norm (sqrt(zz) for l2 bounds); E, the largest
+// eps over A_t, is turned into the l2 column bound of Theorem 1 by the stage's cq.
 __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control& C, double r2, double zz, double yz,
-                                             double mp, double mt, double E, double yy, Scalars& S) {
+                                             double zq, double mp, double mt, double E, double yy, Scalars& S) {
     const double lam = C.lam, l1 = C.l1;
+    E *= P->st[C.stage].cq;
     const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;     // projection of y/lam on z
     const double sp = clip_scale(s0, mp);                  // stable dual point theta' (Lemma 2)
     const double stc = clip_scale(s0, mt);                 // conventional point on A~
@@ -331,7 +341,7 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     S.Rp = sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam;
     S.gamma = Gp > 0.0 ? Gt / Gp : 1.0;
     S.c1 = fabs(sp);
-    S.c2 = fabs(sp) * sqrt(zz);
+    S.c2 = fabs(sp) * zq;
     // stable Dynamic Safe sphere B(y/lambda, ||theta' - y/lambda||) (Table I): the
     // squared radius s'^2 ||z||^2 - 2 s' y^T z / lambda + ||y||^2 / lambda^2, widened by
     // the FP64 rounding of its sums, gamma (|s'| ||z|| + ||y|| / lambda)^2
@@ -356,10 +366,11 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
 }
 
 // Sphere test of one preserved atom (Table I) and its look-ahead flag (Section IV-C):
-//   stable GAP Safe     |a~^T theta'| + eps ||theta'|| + R' ||a||     (rule 0)
-//   stable Dynamic Safe |a^T y| / lambda + ||theta' - y/lambda|| ||a|| (rule 1), with
+//   stable GAP Safe     |a~^T theta'| + eps ||theta'||_{q*} + R' ||a||   (rule 0)
+//   stable Dynamic Safe |a^T y| / lambda + ||theta' - y/lambda|| ||a||  (rule 1), with
 //                       a^T y formed once on the exact dictionary and widened by its
-//                       rounding allowance eI ||y||
+//                       rounding allowance eI ||y|| (eI: the exact stage's eps times its
+//                       cq, since ||y||_{q*} <= cq ||y||)
 // ag = |a~^T z|, Rg = the GAP radius to use, acy = |a^T y|, eI the exact stage's eps.
 // SC: Scalars, or any record with the fields c1, c2, Rp, Rd, ny
 template <typename SC>

@@ -64,6 +64,11 @@ struct StageDesc {
     int fa_maxd;              // FAuST: largest of N and the inner dimensions
     double L, invL, rc;
     double at_norm_max, eps_max;
+    // norm q of the bounds eps (Lemma 1 with an l_q zone): qmode 0 for q = 2, 1 for
+    // other finite q > 1, 2 for q = 1 (dual norm: max), 3 for q = inf (dual norm: sum);
+    // qd the dual exponent q*, cq = N^((1/2 - 1/q)_+), the l2 constant of the bounds
+    int qmode, qpad;
+    double qd, cq;
 };
 
 // Iteration state C_t of one signal.  Double-buffered by iteration parity:
@@ -127,6 +132,7 @@ struct SolveParams {
     int* nz_pre;              // [batch][2][nseg_max+1]
     double* z;                // [batch][N]
     double* res_part;         // [batch][nrc][3]
+    double* zq;               // [batch] ||z||_{q*} of the iteration (stages with l_q bounds)
     double* adj_part;         // [batch][nadj_max][4 waves][3] per-wave maxima of the correlation items
     double* upd_part;         // [batch][nseg_max][4]
     int* cnt_fwd;             // [2][batch] work items of the forward launch of the iteration with parity s
@@ -163,6 +169,7 @@ struct SolveParams {
 struct LaunchCfg {
     int batch, nseg_max, nrc, nadj_max;
     int g_fwd, g_adj, g_adjk, g_upd, g_gemm;  // persistent grid sizes (blocks; 0: launch skipped)
+    int g_lq;                                  // l_q dual norms: batch, or 0 when every stage has q = 2
     size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm;
 };
 

@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __re
             C = P->ctrl[2 * b + slot];
             double r2, zz, yz;
             reduce_res(P, b, s_red, r2, zz, yz);
-            rz = sqrt(zz);
+            rz = dual_norm_z(P, P->st[C.stage], b, zz);
             const double* zg = P->z + (size_t)b * N;
             double* zsd = (double*)smem;
             for (int i = threadIdx.x * 2; i < N; i += kBlock * 2) *(f64v2*)(zsd + i) = *(const f64v2*)(zg + i);
@@ -1253,7 +1253,7 @@ __device__ void gemm_epilogue(const SolveParams* P, const StageDesc& st, int slo
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const int b = bp[p];
-        const double rz = sqrt(zz[p]);
+        const double rz = dual_norm_z(P, st, b, zz[p]);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             double mx[3] = {0.0, 0.0, 0.0};
@@ -1422,7 +1422,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
             C = P->ctrl[2 * b + slot];
             double r2, zz, yz;
             reduce_res(P, b, s_red, r2, zz, yz);
-            rz = sqrt(zz);
+            rz = dual_norm_z(P, P->st[C.stage], b, zz);
             const StageDesc& st0 = P->st[uni(C.stage)];
             const double* zg = P->z + (size_t)b * N;
             if (st0.kind == kKron && st0.dtype != SL1_F64) {
@@ -1533,7 +1533,8 @@ __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scal
     }
     double r2, zz, yz;
     reduce_res_max(P, b, s_red, mx, r2, zz, yz);
-    scalars_from(P, C, r2, zz, yz, mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
+    scalars_from(P, C, r2, zz, yz, dual_norm_z(P, P->st[C.stage], b, zz), mx[0], mx[1], mx[2],
+                 P->rule ? P->yy[b] : 0.0, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1624,7 +1625,7 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             // sphere test of the rule and the look-ahead flag on the approximate atom
             const int rule = P->rule;
             const double acy = rule ? fabs(P->cy[(size_t)b * K + j]) : 0.0;
-            const double eI = rule ? P->st[P->n_stages - 1].eps[j] : 0.0;
+            const double eI = rule ? P->st[P->n_stages - 1].eps[j] * P->st[P->n_stages - 1].cq : 0.0;
             keep = atom_test(rule, U, 1.0 / C.lam, U.Rp, ag, e, P->atom_norm[j], st.at_norm[j], acy, eI,
                              1.0 - P->margin, kt);
             if (C.iter % P->screen_every != 0) keep = true;    // rejections only every screen_every
@@ -1813,7 +1814,7 @@ __global__ void k_lambda_out(const SolveParams* __restrict__ P, double* out, int
     const bool rounded = st.kind == kKron && st.dtype == SL1_BF16;
     const bool rounded32 = st.kind == kKron && st.dtype == SL1_F32;
     const double d2 = (rounded || rounded32) ? fmax(0.0, r2 - 2.0 * yz + zz) : 0.0;
-    out[b] = mp + sqrt(d2) * (st.at_norm_max + st.eps_max);
+    out[b] = mp + sqrt(d2) * (st.at_norm_max + st.eps_max * st.cq);     // ||v||_{q*} <= cq ||v||
     status[b] = P->fin[b].status;
 }
 
@@ -1894,9 +1895,40 @@ hipError_t launch_init(const SolveParams* dP, const LaunchCfg& c, hipStream_t s)
 // kernels of one iteration: 0 forward, 1 dense correlations, 2 Kronecker
 // correlations, 3 test/update; a correlation kernel with an empty grid (its
 // stage kind is absent) is skipped
+// ||z||_{q*} of each signal's stored direction for stages with l_q bounds, q != 2
+// (Lemma 2, Lemma 1), right after the forward launch: one block per signal.  The
+// largest entry M first, then M (sum_i (|z_i|/M)^{q*})^{1/q*} (q* = 1: the plain sum),
+// widened by 2 gamma_n so that it bounds the exact norm (q = 1: M itself, exact).
+__global__ __launch_bounds__(kBlock) void k_lq(const SolveParams* __restrict__ P, int slot) {
+    const int b = blockIdx.x;
+    const StageDesc& st = P->st[P->ctrl[2 * b + slot].stage];
+    if (st.qmode == 0) return;
+    __shared__ double s_red[16];
+    const int N = P->N;
+    const double* z = P->z + (size_t)b * N;
+    double m[1] = {0.0};
+    for (int i = threadIdx.x; i < N; i += kBlock) m[0] = fmax(m[0], fabs(z[i]));
+    block_max<1>(m, s_red);
+    const double M = m[0];
+    double v = M;
+    if (st.qmode != 2 && M > 0.0) {
+        double t[1] = {0.0};
+        for (int i = threadIdx.x; i < N; i += kBlock) {
+            const double a = fabs(z[i]);
+            t[0] += st.qmode == 3 ? a : pow(a / M, st.qd);
+        }
+        block_sum<1>(t, s_red);
+        v = (st.qmode == 3 ? t[0] : M * pow(t[0], 1.0 / st.qd)) * (1.0 + 2.0 * fp64_slack(N));
+    }
+    if (threadIdx.x == 0) P->zq[b] = v;
+}
+
 hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
     switch (which) {
-        case 0: hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot); break;
+        case 0:     // the forward, and the dual norms of solves with l_q bounds
+            hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
+            if (c.g_lq > 0) hipLaunchKernelGGL(k_lq, dim3(c.g_lq), dim3(kBlock), 0, s, dP, slot);
+            break;
         case 1:
             if (c.g_adj > 0) hipLaunchKernelGGL(k_adj_dense, dim3(c.g_adj), dim3(kBlock), c.lds_adj, s, dP, slot);
             break;

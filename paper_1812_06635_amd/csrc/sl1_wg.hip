@@ -722,7 +722,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             block_max<3>(mx, s_red);
             if (tid == 0) {
                 Scalars S;
-                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
+                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], sqrt(s_sum[1]), mx[0], mx[1], mx[2],
+                             P->rule ? P->yy[b] : 0.0, S);
                 if (S.conv == 1) S.tconv = wall_clock64();
                 sS = S;
             }
@@ -1200,7 +1201,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         int conv;
         {
             Scalars S;
-            scalars_from(Pi, C, r2, r2, yr, m1 + me * rz, m1, me, rule ? Pi->yy[b] : 0.0, S);
+            scalars_from(Pi, C, r2, r2, yr, sqrt(r2), m1 + me * rz, m1, me, rule ? Pi->yy[b] : 0.0, S);
             c1 = uni(S.c1);
             beta = uni(S.beta);
             tau_next = uni(S.tau_next);
@@ -1477,7 +1478,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             block_max<3>(mx, s_red);
             if (tid == 0) {
                 Scalars S;
-                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], mx[0], mx[1], mx[2], P->rule ? P->yy[b] : 0.0, S);
+                scalars_from(P, sC, s_sum[0], s_sum[1], s_sum[2], sqrt(s_sum[1]), mx[0], mx[1], mx[2],
+                             P->rule ? P->yy[b] : 0.0, S);
                 if (S.conv == 1) S.tconv = wall_clock64();
                 sS = S;
             }

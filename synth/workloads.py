@@ -232,19 +232,22 @@ def with_lq_bounds(problem, q, stages=None):
     """A copy of `problem` whose approximate stages carry l_q error bounds
     eps_j = ||a_j - a~_j||_q (widened like the l2 ones) instead of l2 bounds: the
     zone B_q(a~_j, eps_j) of Lemma 1 (Section III-B).  `stages` selects the stage
-    indices that switch (default: every stage but the exact one, whose eps stays 0);
-    q may be a number or np.inf."""
+    indices that switch (default: every stage but the exact one; selected, the exact
+    one takes the norm q and keeps eps = 0); q may be a number or np.inf."""
     import copy
     q = float(q)
     out = copy.copy(problem)
     out.stages = [copy.copy(st) for st in problem.stages]
-    sel = range(len(out.stages) - 1) if stages is None else stages
+    last = len(out.stages) - 1
+    sel = range(last) if stages is None else stages
     A = problem.A
     for i in sel:
         st = out.stages[i]
+        st.q = q
+        if i == last:                  # the exact dictionary: no error, eps = 0 in any norm
+            continue
         At = st.values()
         st.eps = _bound(_col_norm(A - At, q), _col_norm(A, q), _col_norm(At, q))
-        st.q = q
     return out
 
 

@@ -65,12 +65,20 @@ def test_argument_validation_without_device(lib):
     from paper_1812_06635_amd import _lib
     h = _lib.c_dict()
     # NULL pointers and bad sizes are refused on the host before any HIP call
-    assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 256, 1024, None, None, None, None) == _lib.EINVAL
-    assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 0, 16, 16, 16, 16, None, None, None, None) == _lib.EINVAL
-    assert lib.sl1_dict_kron(ctypes.byref(h), 7, 1, 16, 16, 16, 16, 1, 1, 1, None) == _lib.EDTYPE
-    assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 1, 15, 16, 16, 16, 1, 1, 1, None) == _lib.ELIMIT
-    assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 258, 16, 1, None, 1, None) == _lib.ELIMIT
-    assert lib.sl1_dict_dense(ctypes.byref(h), 9, 256, 16, 1, None, 1, None) == _lib.EDTYPE
+    assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 256, 1024, None, None, None, 2.0, None) == _lib.EINVAL
+    assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 0, 16, 16, 16, 16, None, None, None, 2.0, None) == _lib.EINVAL
+    assert lib.sl1_dict_kron(ctypes.byref(h), 7, 1, 16, 16, 16, 16, 1, 1, 1, 2.0, None) == _lib.EDTYPE
+    assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 1, 15, 16, 16, 16, 1, 1, 1, 2.0, None) == _lib.ELIMIT
+    assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 258, 16, 1, None, 1, 2.0, None) == _lib.ELIMIT
+    assert lib.sl1_dict_dense(ctypes.byref(h), 9, 256, 16, 1, None, 1, 2.0, None) == _lib.EDTYPE
+    # the norm q of the error bounds: 1 <= q <= inf, NaN refused (checked before the limits)
+    inf, nan = float("inf"), float("nan")
+    for q in (0.5, 0.0, -2.0, nan):
+        assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 256, 16, 1, None, 1, q, None) == _lib.EINVAL
+        assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 1, 16, 16, 16, 16, 1, 1, 1, q, None) == _lib.EINVAL
+    for q in (1.0, 1.5, 3.0, inf):
+        assert lib.sl1_dict_dense(ctypes.byref(h), _lib.F32, 258, 16, 1, None, 1, q, None) == _lib.ELIMIT
+        assert lib.sl1_dict_kron(ctypes.byref(h), _lib.F32, 1, 15, 16, 16, 16, 1, 1, 1, q, None) == _lib.ELIMIT
     # FAuST: sizes, dtype and the CSR arrays are checked on the host
     import numpy as np
     dims = (_lib.c_i64 * 3)(8, 4, 5)
@@ -79,8 +87,11 @@ def test_argument_validation_without_device(lib):
     ci = np.array([0, 3, 1, 4], dtype=np.int32)
     va = np.ones(4, dtype=np.float32)
     fa = lambda dt, J, d, r, c: lib.sl1_dict_faust(ctypes.byref(h), dt, J, d, nnz, r.ctypes.data, c.ctypes.data,
-                                                   va.ctypes.data, 1, None)
-    assert lib.sl1_dict_faust(ctypes.byref(h), _lib.F32, 0, dims, nnz, None, None, None, None, None) == _lib.EINVAL
+                                                   va.ctypes.data, 1, 2.0, None)
+    assert lib.sl1_dict_faust(ctypes.byref(h), _lib.F32, 0, dims, nnz, None, None, None, None, 2.0,
+                              None) == _lib.EINVAL
+    assert lib.sl1_dict_faust(ctypes.byref(h), _lib.F32, 2, dims, nnz, rp.ctypes.data, ci.ctypes.data,
+                              va.ctypes.data, 1, 0.9, None) == _lib.EINVAL
     assert fa(_lib.BF16, 2, dims, rp, ci) == _lib.EDTYPE
     assert fa(_lib.F32, 9, dims, rp, ci) == _lib.ELIMIT
     assert fa(_lib.F32, 2, (_lib.c_i64 * 3)(6, 4, 5), rp, ci) == _lib.ELIMIT        # N not a multiple of 4

@@ -757,3 +757,91 @@ def test_interval_screening_hybrid_tail_matches_grid(sl1):
             assert rel <= 1e-6
     for b in (0, 11):
         _check_solution(p, g, b)
+
+
+# ---------------------------------------------------------------------------
+# error bounds in other l_q norms (Lemma 1, Lemma 2, Theorem 1 with an l_q zone)
+# ---------------------------------------------------------------------------
+# (name, q, lambda fraction of C1 realization 2): cases where the approximations reject atoms
+LQ_CASES = [("q=1", 1.0, 0.8), ("q=1.5", 1.5, 0.7), ("q=3", 3.0, 0.7), ("q=inf", np.inf, 0.8),
+            ("inf then 1", "mixed", 0.8)]
+
+
+def _lq_problem(q, frac):
+    p = synth.config1(realization=2, lam_frac=frac)
+    if q == "mixed":
+        return synth.with_lq_bounds(synth.with_lq_bounds(p, np.inf, stages=[0]), 1.0, stages=[1, 2])
+    return synth.with_lq_bounds(p, q)
+
+
+@pytest.mark.parametrize("engine", ["grid", "hybrid"])
+@pytest.mark.parametrize("name,q,frac", LQ_CASES, ids=[c[0] for c in LQ_CASES])
+def test_lq_bounds_trace_matches_method_reference(sl1, name, q, frac, engine):
+    _say(f"trace C1 l_q bounds {name} engine={engine}")
+    p = _lq_problem(q, frac)
+    out = _run(sl1, p, tol=1e-10, trace_cap=5000, engine=engine)
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
+                      [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10, q=[s.q for s in p.stages])
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0 and n == ref.iters
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+    np.testing.assert_allclose(tr[:, 6], [r.G_conv for r in ref.trace], rtol=1e-7, atol=1e-12)
+    approx = tr[:, 1] < len(p.stages) - 1
+    assert approx.any()
+    np.testing.assert_allclose(tr[approx, 5], np.array([r.G_stable for r in ref.trace])[approx], rtol=1e-7, atol=1e-12)
+    np.testing.assert_allclose(tr[approx, 7], np.array([r.delta for r in ref.trace])[approx], rtol=1e-7, atol=1e-12)
+    np.testing.assert_allclose(tr[approx, 9], np.array([r.gamma for r in ref.trace])[approx], rtol=1e-6, atol=1e-9)
+    # the approximations reject atoms, none of the solution's support
+    assert sum(int(r[2]) - int(r[3]) for r in tr if r[1] < len(p.stages) - 1) > 0
+    _check_solution(p, out, 0, obj_tol=1e-7)
+
+
+@pytest.mark.parametrize("q", [1.0, 1.5, 3.0, np.inf])
+def test_lq_lambda_max_matches_oracle(sl1, q):
+    import torch
+    for name, p in (("C1 kron f64", synth.config1()), ("C3-small dense", synth.config3(N=256, K=1024, batch=3))):
+        p = synth.with_lq_bounds(p, q)
+        wt = torch.float64 if p.work == "f64" else torch.float32
+        for k, st in enumerate(p.stages[:-1]):
+            _say(f"lambda'_max {name} stage {k} q={q}")
+            d = sl1.upload_stage(st)
+            lm = sl1.lambda_max(d, _t(p.Y, wt)).cpu().numpy()
+            At = st.values()
+            for b in range(p.batch):
+                exact = osc.stable_lambda_max(At, st.eps, p.Y[b], q=q)
+                assert exact * (1 - 1e-12) <= lm[b] <= exact * (1 + 1e-9), (name, k, b)
+            d.free()
+
+
+def test_lq_engine_routing(sl1):
+    from paper_1812_06635_amd._lib import ELIMIT, Stablel1Error
+    _say("l_q bounds: whole-solve engine refused, hybrid with an l_q last stage = grid")
+    p = synth.with_lq_bounds(synth.config1(realization=1, lam_frac=0.5), np.inf)
+    with pytest.raises(Stablel1Error) as e:
+        _run(sl1, p, tol=1e-10, engine="wg")
+    assert e.value.code == ELIMIT
+    # every stage, the exact one included, with l_inf bounds (eps = 0 for A)
+    pe = synth.with_lq_bounds(p, np.inf, stages=range(len(p.stages)))
+    assert pe.stages[-1].q == np.inf and not np.any(pe.stages[-1].eps)
+    g = _run(sl1, pe, tol=1e-10, engine="grid")
+    h = _run(sl1, pe, tol=1e-10, engine="hybrid")
+    a = _run(sl1, pe, tol=1e-10)
+    for o in (h, a):
+        assert np.array_equal(o["iters"], g["iters"]) and np.array_equal(o["x"], g["x"])
+    _check_solution(pe, g, 0, obj_tol=1e-7)
+
+
+def test_lq_low_precision_dense_batch(sl1):
+    _say("C3-small fp8/bf16/f32 dense, l_inf bounds, batch 4")
+    p = synth.with_lq_bounds(synth.config3(N=256, K=1024, s=20, batch=4), np.inf)
+    out = _run(sl1, p, tol=1e-10, engine="grid")
+    assert out["status"] == 0
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+    h = _run(sl1, p, tol=1e-10, engine="hybrid")
+    for b in range(p.batch):
+        _check_solution(p, h, b)
