@@ -319,13 +319,16 @@ def recorded_traffic(kernel):
     return None
 
 
-VARIANTS = (("fista", "dst"), ("ista", "gap"), ("ista", "dst"))
+VARIANTS = (("fista", "dst"), ("ista", "gap"), ("ista", "dst"), ("fista", "dome"))
 
 
-def variants_block(sl1, torch, np, p, rc, tol, steps, warmup):
+def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None):
     """The other update / test combinations of Table III (FISTA or ISTA, stable GAP
     Safe or stable Dynamic Safe) on the same batch: time-to-gap of the method and
-    of plain FP32 (the single stage [A]) with the same update and test."""
+    of plain FP32 (the single stage [A]) with the same update and test; then the
+    method with l1 and l_inf error bounds instead of l2 (plain_ref: time and iterations
+    of the headline's plain FP32 solve, FISTA + stable GAP Safe, which has no bounds)."""
+    import synth
     st, Y, lam, an = upload(sl1, torch, p)
     L = [s.L for s in p.stages]
     out = []
@@ -343,6 +346,25 @@ def variants_block(sl1, torch, np, p, rc, tol, steps, warmup):
         out.append(dict(update=update, rule=rule, time_to_gap_ms=ms_m, iters=it_m,
                         iters_per_s=it_m / (ms_m * 1e-3), plain_fp32_time_to_gap_ms=ms_p, plain_fp32_iters=it_p,
                         speedup_vs_plain_fp32=ms_p / ms_m, max_gap=float(o_m["gap"].max().item())))
+    # FISTA + stable GAP Safe with the approximations' bounds in l1 and l_inf (Lemma 1 with an
+    # l_q zone); the plain comparator has no bounds, so it is the FISTA / GAP one above
+    for q, name in ((1.0, "l1"), (float("inf"), "l_inf")):
+        pq = synth.with_lq_bounds(p, q)
+        stq = [sl1.upload_stage(s) for s in pq.stages]
+
+        def method_q():
+            return sl1.solve(stq, L, rc, an, Y, lam, tol=tol)
+
+        ms_m, o_m = timed(torch, method_q, steps, warmup)
+        it_m = int(o_m["iters"].sum().item())
+        log(f"variant fista/gap with {name} bounds: method {ms_m:.3f} ms ({it_m} iters)")
+        entry = dict(update="fista", rule="gap", bounds=name, time_to_gap_ms=ms_m, iters=it_m,
+                     iters_per_s=it_m / (ms_m * 1e-3), max_gap=float(o_m["gap"].max().item()))
+        if plain_ref is not None:
+            entry.update(plain_fp32_time_to_gap_ms=plain_ref[0], plain_fp32_iters=plain_ref[1],
+                         speedup_vs_plain_fp32=plain_ref[0] / ms_m)
+        out.append(entry)
+        del stq
     return out
 
 
@@ -461,7 +483,8 @@ def main():
         line["parity"] = parity_sample(np, p, res)
     if not args.no_variants:
         log("update / test variants on the batched workload (1 timed solve each)")
-        line["variants"] = variants_block(sl1, torch, np, p, res["rc_measured"], args.tol, 1, 1)
+        line["variants"] = variants_block(sl1, torch, np, p, res["rc_measured"], args.tol, 1, 1,
+                                          plain_ref=(res["ms_plain"], res["iters_plain"]))
     if not args.no_cpu:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(np, p, args.cpu_seconds)

@@ -193,6 +193,17 @@ typedef struct {
                                      a_j^T y formed once on the exact dictionary (footnote to Table I;
                                      the solve first runs one correlation pass of seq[n_stages-1] over
                                      all atoms, which must be dense: SL1_ELIMIT otherwise) */
+#define SL1_FLAG_RULE_DOME 512    /* stable GAP Safe sphere intersected with the GAP dome of the same dual
+                                     point theta'_t: the ball with diameter [theta'_t, y/lambda] (theta*
+                                     is the projection of y/lambda, Section II-C) cut by the half-space
+                                     that keeps theta* at distance >= sqrt(||y||^2 - 2(P(x|A~) +
+                                     delta(x)))/lambda from y/lambda (weak duality with Theorem 1's
+                                     bound); the dome region the paper names as an extension (Section
+                                     I-E), tested over Lemma 1's zone.  An atom is kept when the smaller
+                                     of the two tests is >= 1 - margin.  Needs a_j^T y like
+                                     SL1_FLAG_RULE_DST (dense exact stage; not together with it:
+                                     SL1_EINVAL); grid engine only (SL1_FLAG_ENGINE_WG: SL1_ELIMIT;
+                                     the hybrid engine keeps the grid kernels) */
 
 /* Engines (at most one SL1_FLAG_ENGINE_* flag; none = automatic):
  *   SL1_ENGINE_GRID    five persistent launches per iteration covering every live

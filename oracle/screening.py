@@ -30,6 +30,10 @@ Readings of points the paper leaves open (each stated where it is used):
     dual norm ||z||_{q*} (1/q + 1/q* = 1), and Theorem 1 (an l2 statement) takes
     E = N^((1/2 - 1/q)_+) max_j eps_j, the Hoelder constant of the Appendix with
     p* = 2 bounding ||a_j - a~_j||_2 by the l_q bound.  q = 2 is the default.
+  * A dome region (the extension Section I-E and the conclusion point to; no formula
+    is printed): the GAP dome of theta'_t (gap_dome_cut), tested with the same zone
+    bounds as Lemma 1 and intersected with the stable GAP sphere, a^T y formed once on
+    the exact dictionary as for stable Dynamic Safe.
   * Options beside FISTA + stable GAP Safe (Table III's other combinations):
     ISTA (the update of Section I-B, no momentum), and the stable Dynamic Safe
     sphere B(y/lambda, ||theta'_t - y/lambda||) (Table I, fourth row) tested
@@ -127,6 +131,54 @@ def stable_lambda_max(At, eps, y, q=2.0):
     return float(np.max(np.abs(At.T @ y) + eps * y_norm))
 
 
+def dome_cap(delta, t):
+    """sup {u^T v : ||v||_2 <= 1, n^T v <= delta} for unit vectors u, n with n^T u = t
+    (-1 <= delta, t <= 1): 1 when the ball's own maximiser u meets the cut (t <= delta),
+    otherwise the maximum over the cut circle, delta t + sqrt(1 - delta^2) sqrt(1 - t^2).
+    Non-increasing in t and non-decreasing in delta."""
+    delta = np.clip(np.asarray(delta, dtype=np.float64), -1.0, 1.0)
+    t = np.clip(np.asarray(t, dtype=np.float64), -1.0, 1.0)
+    cut = delta * t + np.sqrt(1.0 - delta * delta) * np.sqrt(1.0 - t * t)
+    return np.where(t <= delta, 1.0, cut)
+
+
+def gap_dome_cut(Rd, rin2):
+    """Normalised cut level of the GAP dome.  theta* is the projection of y/lambda on
+    the dual feasible set (Section II-C), so for a feasible theta it lies in the ball
+    B(m, Rd/2) with diameter [theta, y/lambda] (m the midpoint, Rd = ||y/lambda - theta||);
+    weak duality with P(x|A) <= P(x|A~) + delta(x) (Theorem 1) keeps it at distance
+    >= sqrt(rin2) from y/lambda, rin2 = (||y||^2 - 2(P(x|A~) + delta(x)))_+ / lambda^2.
+    As y/lambda lies on that ball's sphere, the two give the half-space
+    n^T (theta - m) <= delta_c Rd/2 with n = (y/lambda - theta)/Rd and
+    delta_c = 1 - 2 rin2 / Rd^2 (clipped to [-1, 1]; Rd = 0 leaves the single point y/lambda)."""
+    if Rd <= 0.0:
+        return -1.0
+    return float(min(1.0, max(-1.0, 1.0 - 2.0 * rin2 / (Rd * Rd))))
+
+
+def stable_dome_test(cy, sg, e, Rd, rin2, a_norm):
+    """Upper bound of sup |a^T theta| over the atoms a of the zone (Lemma 1's restricted
+    zone, ||a||_2 = a_norm) and theta in the GAP dome of theta' = s z (gap_dome_cut):
+    with m = (y/lambda + theta')/2, a^T m lies within (cy + sg)/2 +- e/2 and
+    Rd a^T n within (cy - sg) +- e, where cy = a^T y / lambda (the exact product, given),
+    sg = s a~^T z and e = eps |s| ||z||_{q*} (the zone term); the supremum over the dome
+    is a^T m + (Rd/2) a_norm dome_cap(delta_c, a^T n / a_norm), and dome_cap falls with its
+    second argument, so its smallest value in the range bounds it.  Both signs of a."""
+    cy, sg, e, a_norm = (np.asarray(v, dtype=np.float64) for v in (cy, sg, e, a_norm))
+    dc = gap_dome_cut(Rd, rin2)
+    out = None
+    for sign in (1.0, -1.0):
+        am = sign * (cy + sg) / 2.0 + e / 2.0
+        if Rd > 0.0:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t = np.where(a_norm > 0, (sign * (cy - sg) - e) / (Rd * a_norm), -1.0)
+            val = am + 0.5 * Rd * a_norm * dome_cap(dc, t)
+        else:
+            val = am
+        out = val if out is None else np.maximum(out, val)
+    return out
+
+
 def switch_dictionary(i, I, gamma, Gamma, K_t, rc_i, K):
     """Algorithm 2: speed criterion (K_t <= RC(A~^i) K) jumps to A; otherwise the
     convergence criterion (gamma_t <= Gamma) moves to the next approximation."""
@@ -181,7 +233,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     eps_scale  multiplies every eps (a value below 1 plants an unsafe bound; the
                tests use it to show that the safety check can fail).
     update     "fista" or "ista" (Section I-B: x_{t+1} = ST(x_t + A~^T rho~_t / L)).
-    rule       "gap" (stable GAP Safe) or "dst" (stable Dynamic Safe).
+    rule       "gap" (stable GAP Safe), "dst" (stable Dynamic Safe) or "dome" (the stable
+               GAP Safe sphere intersected with the GAP dome of the same dual point).
     radius_scale  multiplies the sphere radius (below 1 plants an unsafe test).
     screen_every  atoms are rejected only at iterations t with t % screen_every == 0
                (the variation of Algorithm 1 that screens at regular intervals); the
@@ -193,8 +246,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     q          norm of the error bounds, one value or one per stage: eps_j of stage i
                bounds ||a_j - a~^i_j||_{q_i}, 1 <= q_i <= inf (Lemma 1 with an l_q zone).
     """
-    if update not in ("fista", "ista") or rule not in ("gap", "dst"):
-        raise ValueError("update must be fista|ista and rule gap|dst")
+    if update not in ("fista", "ista") or rule not in ("gap", "dst", "dome"):
+        raise ValueError("update must be fista|ista and rule gap|dst|dome")
     I = len(stages) - 1
     N, K = stages[0][0].shape
     qs_list = [float(v) for v in (np.broadcast_to(np.asarray(q, dtype=np.float64), (I + 1,)))]
@@ -212,8 +265,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
     trace = []
     At, eps, L = stages[0]
     at_norms = [np.linalg.norm(s[0], axis=0) for s in stages]
-    # stable Dynamic Safe: a_j^T y with the exact dictionary, formed once
-    aty = stages[I][0].T @ y if rule == "dst" else None
+    # stable Dynamic Safe and the GAP dome: a_j^T y with the exact dictionary, formed once
+    aty = stages[I][0].T @ y if rule in ("dst", "dome") else None
     res = None
     for t in range(max_iter + 1):
         At, eps, L = stages[i]
@@ -276,6 +329,11 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         else:
             c_norm = abs(s_stable) * z_norm                   # ||theta'_t||_{q*}
             mu = stable_sphere_test(s_stable * g, eps, c_norm, R_test, atom_norm)
+        if rule == "dome":
+            # the GAP dome of theta'_t, intersected with the GAP sphere: the smaller test
+            Rd = dynamic_radius(s_stable * rho, y, lam)
+            rin2 = max(y_sq - 2.0 * (P + delta), 0.0) / (lam * lam)
+            mu = np.minimum(mu, stable_dome_test(aty / lam, s_stable * g, eps * c_norm, Rd, rin2, atom_norm))
         keep = active & (mu >= 1.0 - margin)
         if t % max(1, screen_every) != 0:
             keep = active.copy()
@@ -284,6 +342,8 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
             mu_conv = sphere_test(aty / lam, R_test, at_norms[i])
         else:
             mu_conv = sphere_test(s_stable * g, R_test, at_norms[i])
+        if rule == "dome":
+            mu_conv = np.minimum(mu_conv, stable_dome_test(aty / lam, s_stable * g, 0.0, Rd, rin2, at_norms[i]))
         K_t = int(np.count_nonzero(active & (mu_conv >= 1.0)))
         x_new[~keep] = 0.0
         x[~keep] = 0.0

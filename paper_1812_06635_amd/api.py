@@ -152,8 +152,9 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
     signal is on the last, dense, stage with a small preserved set); tail_gram:
     the tail iterates on G = A_t^T A_t once |A_t| fits (else it streams columns);
-    update: "fista" or "ista"; rule: "gap" (stable GAP Safe) or "dst" (stable
-    Dynamic Safe, Table I); batched_gemm: signals with large preserved sets on
+    update: "fista" or "ista"; rule: "gap" (stable GAP Safe), "dst" (stable
+    Dynamic Safe, Table I) or "dome" (stable GAP Safe intersected with the GAP
+    dome of the same dual point; grid engine); batched_gemm: signals with large preserved sets on
     the exact dense stage share one matrix-core correlation product;
     screen_every: atoms are rejected only every screen_every iterations;
     gemm_signals: qualifying signals from which the batched product runs (0: 64);
@@ -162,8 +163,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
         raise ValueError(f"engine must be one of {sorted(_ENGINES)}")
-    if update not in ("fista", "ista") or rule not in ("gap", "dst"):
-        raise ValueError("update must be 'fista' or 'ista', rule 'gap' or 'dst'")
+    if update not in ("fista", "ista") or rule not in ("gap", "dst", "dome"):
+        raise ValueError("update must be 'fista' or 'ista', rule 'gap', 'dst' or 'dome'")
     if y.dtype not in (torch.float64, torch.float32):
         raise TypeError("y must be float32 or float64")
     _dev(y, None, "y")
@@ -195,7 +196,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     opts.y_dtype = L.F64 if y.dtype == torch.float64 else L.F32
     opts.flags = (0 if use_graph else L.FLAG_NO_GRAPH) | (L.FLAG_PROFILE if profile else 0) | _ENGINES[engine] | \
         (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \
-        (L.FLAG_RULE_DST if rule == "dst" else 0) | (0 if batched_gemm else L.FLAG_NO_GEMM)
+        (L.FLAG_RULE_DST if rule == "dst" else 0) | (L.FLAG_RULE_DOME if rule == "dome" else 0) | \
+        (0 if batched_gemm else L.FLAG_NO_GEMM)
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)

@@ -337,6 +337,7 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
         extra = std::max(extra, need);
     }
     c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
+    c.dome = p.rule == 2 ? 1 : 0;
     c.g_lq = 0;
     for (int i = 0; i < p.n_stages; ++i)
         if (p.st[i].qmode != 0) c.g_lq = w.batch;
@@ -376,7 +377,7 @@ int gemm_min_atoms(const SolveParams& p) {
 bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
            a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_adjk == b.g_adjk && a.g_upd == b.g_upd &&
-           a.g_gemm == b.g_gemm && a.g_lq == b.g_lq && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj &&
+           a.g_gemm == b.g_gemm && a.g_lq == b.g_lq && a.dome == b.dome && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj &&
            a.lds_adjk == b.lds_adjk && a.lds_upd == b.lds_upd && a.lds_gemm == b.lds_gemm;
 }
 
@@ -1126,7 +1127,9 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (st != SL1_OK) return st;
     std::lock_guard<std::mutex> lk(w->mu);
     const bool dst = (o.flags & SL1_FLAG_RULE_DST) != 0;
-    if (dst) {
+    const bool dome = (o.flags & SL1_FLAG_RULE_DOME) != 0;
+    if (dst && dome) return SL1_EINVAL;
+    if (dst || dome) {
         // a^T y is formed with the exact dictionary's dense correlation kernel
         if (seq[n_stages - 1]->kind != kDense) return SL1_ELIMIT;
         st = dst_setup(w, seq[n_stages - 1], batch, y, o.y_dtype, (hipStream_t)stream);
@@ -1147,9 +1150,9 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     p.lambda_only = 0;
     p.ista = (o.flags & SL1_FLAG_ISTA) ? 1 : 0;
     p.screen_every = std::max(1, o.screen_every);
-    p.rule = dst ? 1 : 0;
-    p.cy = dst ? w->d_cy : nullptr;
-    p.yy = dst ? w->d_yy : nullptr;
+    p.rule = dst ? 1 : (dome ? 2 : 0);
+    p.cy = (dst || dome) ? w->d_cy : nullptr;
+    p.yy = (dst || dome) ? w->d_yy : nullptr;
     p.Gamma = o.Gamma;
     p.tol = o.tol;
     p.margin = o.margin;
@@ -1159,9 +1162,10 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     const int eng = o.flags & (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG | SL1_FLAG_ENGINE_HYBRID);
     if (eng & (eng - 1)) return SL1_EINVAL;   // at most one engine flag
     const bool gram = !(o.flags & SL1_FLAG_TAIL_COLUMNS);
-    const size_t wlds = wg_layout(p, false, 0, false);
+    // the dome rule runs in the grid kernels only
+    const size_t wlds = dome ? 0 : wg_layout(p, false, 0, false);
     // the tail hand-over needs a dense last stage with l2 bounds whose tail layout fits
-    const bool tail_kind = p.st[p.n_stages - 1].kind == kDense && p.st[p.n_stages - 1].qmode == 0;
+    const bool tail_kind = !dome && p.st[p.n_stages - 1].kind == kDense && p.st[p.n_stages - 1].qmode == 0;
     bool tail_fits = tail_kind;
     if (tail_fits) {
         SolveParams probe = p;

@@ -350,6 +350,17 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
         const double q = sp * sp * zz - 2.0 * sp * yz / lam + yy / (lam * lam);
         const double a = fabs(sp) * sqrt(zz) + S.ny / lam;
         S.Rd = sqrt(fmax(q, 0.0) + fp64_slack(P->N) * a * a);
+        S.Rdl = sqrt(fmax(q - fp64_slack(P->N) * a * a, 0.0));
+    }
+    // GAP dome of theta' (rule 2): the ball with diameter [theta', y/lambda] keeps theta*
+    // (the projection of y/lambda), and weak duality with P(x|A) <= P(x|A~) + delta keeps
+    // ||theta* - y/lambda||^2 >= rin2; the cut level 1 - 2 rin2 / Rd^2 grows with Rd and
+    // falls with rin2, so the upper bound of Rd and a lower bound of rin2 (sums widened by
+    // their FP64 rounding) keep the dome safe
+    {
+        const double g = fp64_slack(P->N);
+        const double rin2 = fmax(yy * (1.0 - g) - 2.0 * (Pv + delta) * (1.0 + g), 0.0) / (lam * lam);
+        S.dcut = S.Rd > 0.0 ? fmin(1.0, fmax(-1.0, 1.0 - 2.0 * rin2 / (S.Rd * S.Rd))) : -1.0;
     }
     if (C.ksince == 0 || P->ista) {      // ISTA: no momentum (Section I-B)
         S.beta = 0.0;
@@ -384,6 +395,37 @@ __device__ __forceinline__ bool atom_test(int rule, const SC& S, double invlam, 
     }
     kt = (S.c1 * ag + S.Rp * atn >= 1.0) ? 1.0 : 0.0;
     return S.c1 * ag + e * S.c2 + Rg * an >= keep_min;
+}
+
+// sup {u^T v : ||v|| <= 1, n^T v <= d} for unit u, n with n^T u = t: 1 when the ball's
+// maximiser meets the cut (t <= d), else the maximum on the cut circle
+__device__ __forceinline__ double dome_cap(double d, double t) {
+    t = fmin(1.0, fmax(-1.0, t));
+    if (t <= d) return 1.0;
+    return d * t + sqrt(fmax(1.0 - d * d, 0.0)) * sqrt(fmax(1.0 - t * t, 0.0));
+}
+
+// Upper bound of sup |a^T theta| over the zone's atoms (||a|| = alpha) and the GAP dome:
+// cy = a^T y / lambda, sg = s' a~^T z, u = the zone and rounding allowance of both;
+// a^T m lies within (cy + sg)/2 +- u/2 and Rd a^T n within (cy - sg) +- u, and the cap
+// falls with a^T n, so its lowest value bounds the supremum (dividing a negative lowest
+// value by the radius's lower bound, a positive one by its upper bound, errs low).
+__device__ __forceinline__ double dome_test(double cy, double sg, double u, double Rd, double Rdl, double dcut,
+                                            double alpha) {
+    double best = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double sgn = k ? -1.0 : 1.0;
+        double v = 0.5 * (sgn * (cy + sg) + u);
+        if (Rd > 0.0) {
+            const double num = sgn * (cy - sg) - u;
+            const double den = (num >= 0.0 ? Rd : Rdl) * alpha;
+            const double t = den > 0.0 ? num / den : -1.0;
+            v += 0.5 * Rd * alpha * dome_cap(dcut, t);
+        }
+        best = k ? fmax(best, v) : v;
+    }
+    return best;
 }
 
 }  // namespace sl1

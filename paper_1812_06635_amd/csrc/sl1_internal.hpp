@@ -94,6 +94,7 @@ struct Scalars {
     double c1, c2;                    // |s'| and |s'| ||z||
     double beta, tau_next;
     double Rd, ny;                    // stable Dynamic Safe radius ||theta' - y/lambda|| (bounded), ||y||
+    double Rdl, dcut;                 // GAP dome: lower bound of that radius, normalised cut level
     int conv, pad0;                   // 1 converged on A, 2 iteration cap
     long long tconv;
 };
@@ -170,6 +171,7 @@ struct LaunchCfg {
     int batch, nseg_max, nrc, nadj_max;
     int g_fwd, g_adj, g_adjk, g_upd, g_gemm;  // persistent grid sizes (blocks; 0: launch skipped)
     int g_lq;                                  // l_q dual norms: batch, or 0 when every stage has q = 2
+    int dome;                                  // the update kernel of the dome rule
     size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm;
 };
 

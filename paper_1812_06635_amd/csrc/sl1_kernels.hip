@@ -1555,7 +1555,10 @@ __device__ __forceinline__ int block_excl_scan_flag(bool f, int* s_w, int& total
     return base + pre;
 }
 
-__global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ P, int slot) {
+// one body, two kernels: the dome rule's test lives in its own instantiation, so the
+// other rules' update keeps its registers and occupancy
+template <bool kDome>
+__device__ __forceinline__ void upd_body(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int K = P->K, batch = P->batch;
     int* s_pre = (int*)smem;
@@ -1571,6 +1574,7 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
     // the scalars the per-atom test and step use, block-uniform (scalar registers)
     struct {
         double c1, c2, Rp, Rd, ny, beta;
+        double sp, Rdl, dcut;         // GAP dome (rule 2)
         int conv;
     } U;
     for (int g = g0; g < g1; ++g) {
@@ -1598,6 +1602,9 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             U.Rp = uni(S.Rp);
             U.Rd = uni(S.Rd);
             U.ny = uni(S.ny);
+            U.sp = uni(S.sp);
+            U.Rdl = uni(S.Rdl);
+            U.dcut = uni(S.dcut);
             U.beta = uni(S.beta);
             U.conv = uni(S.conv);
             if ((int)threadIdx.x <= C.nseg_act) s_pre[threadIdx.x] = pv0;
@@ -1624,10 +1631,21 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             const double ag = fabs(gt);
             // sphere test of the rule and the look-ahead flag on the approximate atom
             const int rule = P->rule;
-            const double acy = rule ? fabs(P->cy[(size_t)b * K + j]) : 0.0;
+            const double cyj = rule ? P->cy[(size_t)b * K + j] : 0.0;
             const double eI = rule ? P->st[P->n_stages - 1].eps[j] * P->st[P->n_stages - 1].cq : 0.0;
-            keep = atom_test(rule, U, 1.0 / C.lam, U.Rp, ag, e, P->atom_norm[j], st.at_norm[j], acy, eI,
-                             1.0 - P->margin, kt);
+            const double an = P->atom_norm[j], atn = st.at_norm[j];
+            if (kDome) {
+                // the stable GAP sphere and the GAP dome of theta'; the smaller test decides
+                const double il = 1.0 / C.lam;
+                const double cyv = cyj * il, sg = U.sp * gt;
+                const double u = e * U.c2 + eI * U.ny * il;
+                const double mu = fmin(U.c1 * ag + e * U.c2 + U.Rp * an, dome_test(cyv, sg, u, U.Rd, U.Rdl, U.dcut, an));
+                const double mc = fmin(U.c1 * ag + U.Rp * atn, dome_test(cyv, sg, 0.0, U.Rd, U.Rdl, U.dcut, atn));
+                kt = mc >= 1.0 ? 1.0 : 0.0;
+                keep = mu >= 1.0 - P->margin;
+            } else {
+                keep = atom_test(rule, U, 1.0 / C.lam, U.Rp, ag, e, an, atn, fabs(cyj), eI, 1.0 - P->margin, kt);
+            }
             if (C.iter % P->screen_every != 0) keep = true;    // rejections only every screen_every
             // FISTA (or ISTA: beta = 0) step on the preserved coefficients; the gradient at
             // the extrapolated point follows from the two correlation vectors by linearity
@@ -1665,6 +1683,15 @@ __global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ 
             up[3] = sums[1];
         }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_upd(const SolveParams* __restrict__ P, int slot) {
+    upd_body<false>(P, slot);
+}
+
+// the update of solves with the dome rule (SolveParams::rule == 2)
+__global__ __launch_bounds__(kBlock, 5) void k_upd_dome(const SolveParams* __restrict__ P, int slot) {
+    upd_body<true>(P, slot);
 }
 
 // warm start: x_0 = x_{-1} = x0 (device, batch x K), its nonzeros compacted in atom
@@ -1945,7 +1972,10 @@ hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCf
                                    c.g_gemm);
             }
             break;
-        default: hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot); break;
+        default:
+            if (c.dome) hipLaunchKernelGGL(k_upd_dome, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
+            else hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
+            break;
     }
     return hipGetLastError();
 }
