@@ -209,7 +209,8 @@ __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j
 
 __device__ __forceinline__ double clip_scale(double s0, double m) {
     if (!(m > 0.0)) return s0;
-    return fmin(fmax(s0, -1.0 / m), 1.0 / m);
+    const double im = 1.0 / m;
+    return fmin(fmax(s0, -im), im);
 }
 
 // four consecutive stored elements of a dense column, kept in storage form
@@ -326,8 +327,9 @@ __device__ __forceinline__ double dual_norm_z(const SolveParams* P, const StageD
 __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control& C, double r2, double zz, double yz,
                                              double zq, double mp, double mt, double E, double yy, Scalars& S) {
     const double lam = C.lam, l1 = C.l1;
+    const double il = 1.0 / lam;                           // the one division by lambda
     E *= P->st[C.stage].cq;
-    const double s0 = zz > 0.0 ? yz / (lam * zz) : 0.0;     // projection of y/lam on z
+    const double s0 = zz > 0.0 ? (yz / zz) * il : 0.0;     // projection of y/lam on z
     const double sp = clip_scale(s0, mp);                  // stable dual point theta' (Lemma 2)
     const double stc = clip_scale(s0, mt);                 // conventional point on A~
     const double Pv = 0.5 * r2 + lam * l1;                 // P(x_t | A~)
@@ -338,7 +340,7 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     S.mp = mp; S.mt = mt; S.E = E;
     S.sp = sp; S.st = stc;
     S.P = Pv; S.Gp = Gp; S.Gt = Gt; S.delta = delta;
-    S.Rp = sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam;
+    S.Rp = sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) * il;
     S.gamma = Gp > 0.0 ? Gt / Gp : 1.0;
     S.c1 = fabs(sp);
     S.c2 = fabs(sp) * zq;
@@ -347,19 +349,20 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     // the FP64 rounding of its sums, gamma (|s'| ||z|| + ||y|| / lambda)^2
     S.ny = sqrt(yy);
     {
-        const double q = sp * sp * zz - 2.0 * sp * yz / lam + yy / (lam * lam);
-        const double a = fabs(sp) * sqrt(zz) + S.ny / lam;
+        const double q = sp * sp * zz - 2.0 * sp * yz * il + yy * (il * il);
+        const double a = fabs(sp) * sqrt(zz) + S.ny * il;
         S.Rd = sqrt(fmax(q, 0.0) + fp64_slack(P->N) * a * a);
-        S.Rdl = sqrt(fmax(q - fp64_slack(P->N) * a * a, 0.0));
+        S.Rdl = P->rule == 2 ? sqrt(fmax(q - fp64_slack(P->N) * a * a, 0.0)) : 0.0;
     }
     // GAP dome of theta' (rule 2): the ball with diameter [theta', y/lambda] keeps theta*
     // (the projection of y/lambda), and weak duality with P(x|A) <= P(x|A~) + delta keeps
     // ||theta* - y/lambda||^2 >= rin2; the cut level 1 - 2 rin2 / Rd^2 grows with Rd and
     // falls with rin2, so the upper bound of Rd and a lower bound of rin2 (sums widened by
     // their FP64 rounding) keep the dome safe
-    {
+    S.dcut = -1.0;
+    if (P->rule == 2) {
         const double g = fp64_slack(P->N);
-        const double rin2 = fmax(yy * (1.0 - g) - 2.0 * (Pv + delta) * (1.0 + g), 0.0) / (lam * lam);
+        const double rin2 = fmax(yy * (1.0 - g) - 2.0 * (Pv + delta) * (1.0 + g), 0.0) * (il * il);
         S.dcut = S.Rd > 0.0 ? fmin(1.0, fmax(-1.0, 1.0 - 2.0 * rin2 / (S.Rd * S.Rd))) : -1.0;
     }
     if (C.ksince == 0 || P->ista) {      // ISTA: no momentum (Section I-B)

@@ -1113,6 +1113,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
     int* lj = (int*)(smem + P->wo_lnj);       // nonzero list, as Gram rows
     double* lx = (double*)(smem + P->wo_lnx);
     const double invL = uni(st.invL), lam = uni(C.lam), thr = uni(lam * st.invL), keep_min = uni(1.0 - P->margin);
+    const double invlam = uni(1.0 / lam);
     const double ny = uni(sqrt(yy));
     const unsigned long long below = (1ull << l) - 1ull;
     int n_act = uni(C.n_act), n_nz = 0;
@@ -1211,10 +1212,10 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             Pv = uni(S.P);
             conv = uni(S.conv);
             delta = uni(S.delta + 0.5 * e_r2 + lam * c1 * e_yr + 0.5 * lam * lam * c1 * c1 * e_r2 + lam * gam * C.l1);
-            Rp = uni(sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) / lam);
+            Rp = uni(sqrt(2.0 * fmax(Gp, 0.0) + 2.0 * delta) * invlam);
             c2 = uni(c1 * rz);
             // the Dynamic Safe radius also carries the Gram errors of ||rho||^2 and y^T rho
-            Rd = uni(sqrt(S.Rd * S.Rd + c1 * c1 * e_r2 + 2.0 * c1 * e_yr / lam));
+            Rd = uni(sqrt(S.Rd * S.Rd + c1 * c1 * e_r2 + 2.0 * c1 * e_yr * invlam));
             ny = uni(S.ny);
         }
         wg_stamp(Pi, b, 2, *s_clk);
@@ -1246,7 +1247,6 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         }
         // ---- stable GAP test (|g_j| + eta ||a_j||), look-ahead count, FISTA step ----
         const double Rq = uni(Rp + c1 * eta);
-        const double invlam = uni(1.0 / lam);
         bool keep[H], nzf[H];
         double xn[H];
         double kt = 0.0, l1 = 0.0, Xn = 0.0;
