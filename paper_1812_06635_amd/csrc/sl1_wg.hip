@@ -560,10 +560,12 @@ __device__ __forceinline__ void wg_copy_factors(const StageDesc& st, char* fac) 
 }
 
 // phase clock (thread 0, after the phase's closing barrier)
+// (an atomic add whose result is unused: the wave does not wait for the memory round
+// trip, so profiling barely slows the phases it measures; one block per signal)
 __device__ __forceinline__ void wg_stamp(const SolveParams* P, int b, int phase, long long& t) {
     if (P->wg_prof && threadIdx.x == 0) {
         const long long now = wall_clock64();
-        P->wg_prof[(size_t)b * kWgPhases + phase] += now - t;
+        atomicAdd((unsigned long long*)(P->wg_prof + (size_t)b * kWgPhases + phase), (unsigned long long)(now - t));
         t = now;
     }
 }
