@@ -227,7 +227,7 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
 
     stages     list of (At, eps, L): At is the (N, K) FP64 matrix of the i-th
                approximation (the last one is A, with eps = 0), eps its per-atom
-               l2 error bounds and L its Lipschitz constant.
+               error bounds (l2 unless q says otherwise) and L its Lipschitz constant.
     atom_norm  ||a_j||_2 of the exact atoms (the restricted zone of Lemma 1).
     rc         relative complexity RC(A~^i) of each stage (Section IV-B).
     eps_scale  multiplies every eps (a value below 1 plants an unsafe bound; the
