@@ -901,6 +901,7 @@ int sl1_dict_faust(sl1_dict* out, int dtype, int J, const int64_t* dims, const i
     d->dtype = dtype;
     d->N = N;
     d->K = K;
+    d->q = q;
     int st = finish_dict_host_eps(d.get(), eps, s);
     if (st != SL1_OK) return st;
     // transposes (CSR of S_l^T; rows of S_l in increasing order give sorted rows)

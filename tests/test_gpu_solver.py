@@ -906,3 +906,48 @@ def test_dome_engines_lq_bounds_and_batch(sl1):
     assert ob["status"] == 0
     for b in range(pb.batch):
         _check_solution(pb, ob, b)
+
+
+# ---------------------------------------------------------------------------
+# the newer options together with the older ones, against the method reference
+# ---------------------------------------------------------------------------
+def _combo(name):
+    if name == "dst l_inf":
+        return synth.with_lq_bounds(synth.config1(realization=2, lam_frac=0.8), np.inf), dict(rule="dst"), None
+    if name == "dome every 3":
+        return synth.config1(realization=1, lam_frac=0.5), dict(rule="dome", screen_every=3), None
+    if name == "faust q=3":            # the FAuST trace case above, bounds in l3
+        p = synth.config6(N=64, K=515, depth=3, col_nnz=(8, 8, 24), keeps=(8, 12, 16), lam_frac=0.2,
+                          dtype="f64", work="f64")
+        return synth.with_lq_bounds(p, 3.0), dict(), None
+    if name == "warm l1":
+        p = synth.with_lq_bounds(synth.config1(realization=0, lam_frac=0.5), 1.0)
+        sol = ol.solve(p.A, p.Y[0], 0.6 * float(p.lam_max[0]), L=p.stages[-1].L)
+        return p, dict(), sol["x"]
+    raise ValueError(name)
+
+
+COMBOS = ["dst l_inf", "dome every 3", "faust q=3", "warm l1"]
+
+
+@pytest.mark.parametrize("name", COMBOS)
+def test_option_combinations_trace_matches_method_reference(sl1, name):
+    import torch
+    _say(f"trace combination {name}")
+    p, kw, x0 = _combo(name)
+    gkw = dict(kw)
+    if x0 is not None:
+        gkw["x0"] = torch.from_numpy(np.ascontiguousarray(x0[None, :])).cuda()
+    out = _run(sl1, p, tol=1e-10, trace_cap=20000, engine="grid", **gkw)
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
+                      [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10, q=[s.q for s in p.stages],
+                      x0=x0, **kw)
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0 and n == ref.iters
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+    np.testing.assert_allclose(tr[:, 6], [r.G_conv for r in ref.trace], rtol=1e-7, atol=1e-12)
+    _check_solution(p, out, 0, obj_tol=1e-7)
