@@ -951,3 +951,40 @@ def test_option_combinations_trace_matches_method_reference(sl1, name):
     assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
     np.testing.assert_allclose(tr[:, 6], [r.G_conv for r in ref.trace], rtol=1e-7, atol=1e-12)
     _check_solution(p, out, 0, obj_tol=1e-7)
+
+
+@pytest.mark.parametrize("engine", ["grid", "hybrid"])
+def test_lq_bounds_on_bf16_kronecker_batch(sl1, engine):
+    # z is the BF16-rounded residual on these stages; its l1 norm comes from that same z
+    _say(f"C4-small bf16 kron, l_inf bounds, batch 24, engine={engine}")
+    p = synth.with_lq_bounds(synth.config4(batch=24, n=(16, 32)), np.inf)
+    out = _run(sl1, p, tol=1e-10, engine=engine)
+    assert out["status"] == 0
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+def test_lq_bounds_through_the_batched_product(sl1):
+    # every stage (the exact one too) with l_inf bounds: the batched product's epilogue
+    # reads the stored dual norms; against the streaming correlations
+    _say("C4-small, all stages l_inf, batched product vs streaming")
+    p = synth.config4(batch=24, n=(16, 32))
+    p = synth.with_lq_bounds(p, np.inf, stages=range(len(p.stages)))
+    prod = _run(sl1, p, tol=1e-10, engine="grid", gemm_signals=1, profile=True)
+    assert sl1.last_solve_profile(p.batch, p.N, p.K)["adj_gemm"][1] > 0      # the product ran
+    strm = _run(sl1, p, tol=1e-10, engine="grid", batched_gemm=False)
+    assert prod["status"] == 0 and strm["status"] == 0
+    assert np.all(np.abs(prod["iters"] - strm["iters"]) <= 3)
+    for b in range(p.batch):
+        _check_solution(p, prod, b)
+        rel = np.linalg.norm(prod["x"][b] - strm["x"][b]) / max(np.linalg.norm(strm["x"][b]), 1e-300)
+        assert rel <= 1e-6
+
+
+def test_dome_on_fp32_kronecker(sl1):
+    _say("C2-small f32 kron, dome rule")
+    for frac in (0.3, 0.8):
+        p = synth.config2(n=(16, 32), lam_frac=frac)
+        out = _run(sl1, p, tol=1e-10, rule="dome")
+        assert out["status"] == 0
+        _check_solution(p, out, 0)
