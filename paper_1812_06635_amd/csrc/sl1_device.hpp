@@ -20,6 +20,13 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // block-uniform values (read from LDS or computed identically by every lane)
 // moved to scalar registers, so that addresses derived from them are scalar
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+    const unsigned long long u = (unsigned long long)p;
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(u & 0xFFFFFFFFull));
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(u >> 32));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+}
 __device__ __forceinline__ double uni(double v) {
     const long long u = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xFFFFFFFFll));
@@ -322,13 +329,31 @@ __device__ __forceinline__ double dual_norm_z(const SolveParams* P, const StageD
     return st.qmode == 0 ? sqrt(zz) : P->zq[b];
 }
 
+// The parameters the scalar block reads (a loop over many iterations loads them once).
+struct ScalarConsts {
+    double tol, slack;                // stop tolerance, fp64_slack(N)
+    int rule, ista, last_stage, max_iter;
+};
+
+__device__ __forceinline__ ScalarConsts scalar_consts(const SolveParams* P) {
+    ScalarConsts k;
+    k.tol = P->tol;
+    k.slack = fp64_slack(P->N);
+    k.rule = P->rule;
+    k.ista = P->ista;
+    k.last_stage = P->n_stages - 1;
+    k.max_iter = P->max_iter;
+    return k;
+}
+
 // zq = ||z||_{q*} for the stage's bound norm (sqrt(zz) for l2 bounds); E, the largest
 // eps over A_t, is turned into the l2 column bound of Theorem 1 by the stage's cq.
-__device__ __forceinline__ void scalars_from(const SolveParams* P, const Control& C, double r2, double zz, double yz,
-                                             double zq, double mp, double mt, double E, double yy, Scalars& S) {
+__device__ __forceinline__ void scalars_core(const ScalarConsts& K, double cq, const Control& C, double r2, double zz,
+                                             double yz, double zq, double mp, double mt, double E, double yy,
+                                             Scalars& S) {
     const double lam = C.lam, l1 = C.l1;
     const double il = 1.0 / lam;                           // the one division by lambda
-    E *= P->st[C.stage].cq;
+    E *= cq;
     const double s0 = zz > 0.0 ? (yz / zz) * il : 0.0;     // projection of y/lam on z
     const double sp = clip_scale(s0, mp);                  // stable dual point theta' (Lemma 2)
     const double stc = clip_scale(s0, mt);                 // conventional point on A~
@@ -351,8 +376,8 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     {
         const double q = sp * sp * zz - 2.0 * sp * yz * il + yy * (il * il);
         const double a = fabs(sp) * sqrt(zz) + S.ny * il;
-        S.Rd = sqrt(fmax(q, 0.0) + fp64_slack(P->N) * a * a);
-        S.Rdl = P->rule == 2 ? sqrt(fmax(q - fp64_slack(P->N) * a * a, 0.0)) : 0.0;
+        S.Rd = sqrt(fmax(q, 0.0) + K.slack * a * a);
+        S.Rdl = K.rule == 2 ? sqrt(fmax(q - K.slack * a * a, 0.0)) : 0.0;
     }
     // GAP dome of theta' (rule 2): the ball with diameter [theta', y/lambda] keeps theta*
     // (the projection of y/lambda), and weak duality with P(x|A) <= P(x|A~) + delta keeps
@@ -360,12 +385,12 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
     // falls with rin2, so the upper bound of Rd and a lower bound of rin2 (sums widened by
     // their FP64 rounding) keep the dome safe
     S.dcut = -1.0;
-    if (P->rule == 2) {
-        const double g = fp64_slack(P->N);
+    if (K.rule == 2) {
+        const double g = K.slack;
         const double rin2 = fmax(yy * (1.0 - g) - 2.0 * (Pv + delta) * (1.0 + g), 0.0) * (il * il);
         S.dcut = S.Rd > 0.0 ? fmin(1.0, fmax(-1.0, 1.0 - 2.0 * rin2 / (S.Rd * S.Rd))) : -1.0;
     }
-    if (C.ksince == 0 || P->ista) {      // ISTA: no momentum (Section I-B)
+    if (C.ksince == 0 || K.ista) {       // ISTA: no momentum (Section I-B)
         S.beta = 0.0;
         S.tau_next = C.tau;
     } else {
@@ -373,10 +398,15 @@ __device__ __forceinline__ void scalars_from(const SolveParams* P, const Control
         S.beta = (C.tau - 1.0) / tn;
         S.tau_next = tn;
     }
-    const bool on_exact = C.stage == P->n_stages - 1;
-    S.conv = (on_exact && Gt < P->tol) ? 1 : (C.iter >= P->max_iter ? 2 : 0);
+    const bool on_exact = C.stage == K.last_stage;
+    S.conv = (on_exact && Gt < K.tol) ? 1 : (C.iter >= K.max_iter ? 2 : 0);
     S.pad0 = 0;
     S.tconv = 0;
+}
+
+__device__ __forceinline__ void scalars_from(const SolveParams* P, const Control& C, double r2, double zz, double yz,
+                                             double zq, double mp, double mt, double E, double yy, Scalars& S) {
+    scalars_core(scalar_consts(P), P->st[C.stage].cq, C, r2, zz, yz, zq, mp, mt, E, yy, S);
 }
 
 // Sphere test of one preserved atom (Table I) and its look-ahead flag (Section IV-C):

@@ -562,12 +562,15 @@ __device__ __forceinline__ void wg_copy_factors(const StageDesc& st, char* fac) 
 // phase clock (thread 0, after the phase's closing barrier)
 // (an atomic add whose result is unused: the wave does not wait for the memory round
 // trip, so profiling barely slows the phases it measures; one block per signal)
-__device__ __forceinline__ void wg_stamp(const SolveParams* P, int b, int phase, long long& t) {
-    if (P->wg_prof && threadIdx.x == 0) {
+__device__ __forceinline__ void wg_stamp_p(long long* prof, int b, int phase, long long& t) {
+    if (prof && threadIdx.x == 0) {
         const long long now = wall_clock64();
-        atomicAdd((unsigned long long*)(P->wg_prof + (size_t)b * kWgPhases + phase), (unsigned long long)(now - t));
+        atomicAdd((unsigned long long*)(prof + (size_t)b * kWgPhases + phase), (unsigned long long)(now - t));
         t = now;
     }
+}
+__device__ __forceinline__ void wg_stamp(const SolveParams* P, int b, int phase, long long& t) {
+    wg_stamp_p(P->wg_prof, b, phase, t);
 }
 
 }  // namespace
@@ -1117,6 +1120,23 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
     const double invL = uni(st.invL), lam = uni(C.lam), thr = uni(lam * st.invL), keep_min = uni(1.0 - P->margin);
     const double invlam = uni(1.0 / lam);
     const double ny = uni(sqrt(yy));
+    // what the iterations read of the parameter block, loaded once (block-uniform)
+    ScalarConsts SK = scalar_consts(P);
+    SK.tol = uni(SK.tol);
+    SK.slack = uni(SK.slack);
+    SK.rule = uni(SK.rule);
+    SK.ista = uni(SK.ista);
+    SK.last_stage = uni(SK.last_stage);
+    SK.max_iter = uni(SK.max_iter);
+    const double cq = uni(st.cq);
+    const int rule = SK.rule, screen_every = uni(P->screen_every);
+    const int trace_cap = P->trace ? uni(P->trace_cap) : 0;
+    double* const trace = uni_ptr(P->trace);
+    double* const xb0 = uni_ptr(xbuf(P, b, 0));
+    double* const xb1 = uni_ptr(xbuf(P, b, 1));
+    uint8_t* const maskb = uni_ptr(P->mask + (size_t)b * K);
+    long long* const prof = uni_ptr(P->wg_prof);
+    const double yyb = rule ? uni(P->yy[b]) : 0.0;
     const unsigned long long below = (1ull << l) - 1ull;
     int n_act = uni(C.n_act), n_nz = 0;
     double X;
@@ -1144,7 +1164,6 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         // per-iteration copies of the parameter block and of the lane's positions
         // keep addresses out of the loop-carried registers
         const SolveParams* Pi = phase_params(P0);
-        const int rule = Pi->rule;
         int lo = l;
         asm volatile("" : "+v"(lo));
         const int par = uni(C.par);
@@ -1204,7 +1223,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         int conv;
         {
             Scalars S;
-            scalars_from(Pi, C, r2, r2, yr, sqrt(r2), m1 + me * rz, m1, me, rule ? Pi->yy[b] : 0.0, S);
+            scalars_core(SK, cq, C, r2, r2, yr, sqrt(r2), m1 + me * rz, m1, me, yyb, S);
             c1 = uni(S.c1);
             beta = uni(S.beta);
             tau_next = uni(S.tau_next);
@@ -1220,7 +1239,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             Rd = uni(sqrt(S.Rd * S.Rd + c1 * c1 * e_r2 + 2.0 * c1 * e_yr * invlam));
             ny = uni(S.ny);
         }
-        wg_stamp(Pi, b, 2, *s_clk);
+        wg_stamp_p(prof, b, 2, *s_clk);
         if (conv) {
             double* xc = xbuf(Pi, b, par);
 #pragma unroll
@@ -1252,10 +1271,11 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         bool keep[H], nzf[H];
         double xn[H];
         double kt = 0.0, l1 = 0.0, Xn = 0.0;
+        const bool screen_now = C.iter % screen_every == 0;   // rejections only every screen_every
         {
-            double* xc = xbuf(Pi, b, par);
-            double* xo = xbuf(Pi, b, 1 - par);
-            uint8_t* mask = Pi->mask + (size_t)b * K;
+            double* xc = par ? xb1 : xb0;
+            double* xo = par ? xb0 : xb1;
+            uint8_t* mask = maskb;
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int i = lo + 64 * h;
@@ -1271,7 +1291,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                         keep[h] = c1 * ag + T.e[i] * c2 + Rq * an >= keep_min;
                         kt += (c1 * ag + Rp * T.atn[i] >= 1.0) ? 1.0 : 0.0;
                     }
-                    if (C.iter % Pi->screen_every != 0) keep[h] = true;
+                    if (!screen_now) keep[h] = true;
                     const double xp = T.xp[i], gm = T.gm[i];
                     const double zpt = xt[h] + beta * (xt[h] - xp);
                     const double hh = (1.0 + beta) * g[h] - beta * gm;
@@ -1342,10 +1362,10 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         }
         l1 = uni(l1);
         Xn = uni(Xn);
-        wg_stamp(Pi, b, 3, *s_clk);
+        wg_stamp_p(prof, b, 3, *s_clk);
         // ---- trace row and momentum (the last stage stays) ----
-        if (l == 0 && Pi->trace && C.iter < Pi->trace_cap) {
-            double* tr = Pi->trace + ((size_t)b * Pi->trace_cap + C.iter) * SL1_TRACE_FIELDS;
+        if (l == 0 && trace && C.iter < trace_cap) {
+            double* tr = trace + ((size_t)b * trace_cap + C.iter) * SL1_TRACE_FIELDS;
             tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = wpos;
             tr[4] = kt;
             tr[5] = Gp; tr[6] = Gt; tr[7] = delta; tr[8] = rule ? Rd : Rp; tr[9] = gam_t;
