@@ -422,7 +422,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solver has no multi-GPU path "
-                                   "(batches shard by signal across GPUs, see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "(a batch would shard by signal, one process per GPU)", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -104,3 +104,16 @@ def test_argument_validation_without_device(lib):
                          None) == _lib.EINVAL
     assert lib.sl1_lambda_max(None, 1, None, 1, None, None) == _lib.EINVAL
     assert lib.sl1_grad(None, 1, None, None, None, None, None, None, 1, None) == _lib.EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; asked for more it says so and exits with status 2
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
