@@ -27,6 +27,42 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
     const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(u >> 32));
     return (T*)(((unsigned long long)hi << 32) | lo);
 }
+// Full-wave reductions with DPP row operations, for code where all 64 lanes are active:
+// prefix operations within each 16-lane row (shifts by 1, 2, 4, 8), then the row
+// broadcasts of lanes 15 and 31, which leave the result in lane 63; every lane then
+// reads it (uniform).  Lanes without a source contribute 0, so the max form is for
+// non-negative values.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xFFFFFFFFll), CTRL, ROW_MASK, 0xF, BOUND);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROW_MASK, 0xF, BOUND);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane63(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xFFFFFFFFll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_full(double v) {
+    v += dpp_move<0x111, 0xF, true>(v);     // row_shr:1
+    v += dpp_move<0x112, 0xF, true>(v);     // row_shr:2
+    v += dpp_move<0x114, 0xF, true>(v);     // row_shr:4
+    v += dpp_move<0x118, 0xF, true>(v);     // row_shr:8
+    v += dpp_move<0x142, 0xA, false>(v);    // row_bcast:15 into rows 1, 3
+    v += dpp_move<0x143, 0xC, false>(v);    // row_bcast:31 into rows 2, 3
+    return lane63(v);
+}
+__device__ __forceinline__ double wave_max_nonneg_full(double v) {
+    v = fmax(v, dpp_move<0x111, 0xF, true>(v));
+    v = fmax(v, dpp_move<0x112, 0xF, true>(v));
+    v = fmax(v, dpp_move<0x114, 0xF, true>(v));
+    v = fmax(v, dpp_move<0x118, 0xF, true>(v));
+    v = fmax(v, dpp_move<0x142, 0xA, false>(v));
+    v = fmax(v, dpp_move<0x143, 0xC, false>(v));
+    return lane63(v);
+}
 __device__ __forceinline__ double uni(double v) {
     const long long u = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xFFFFFFFFll));

@@ -1200,20 +1200,11 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 me = fmax(me, T.e[i]);
             }
         }
-        // the four wave reductions interleaved (xor butterfly: every lane ends with the same bits)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double a0 = __shfl_xor(cx, off, 64), a1 = __shfl_xor(xg, off, 64);
-            const double a2 = __shfl_xor(m1, off, 64), a3 = __shfl_xor(me, off, 64);
-            cx += a0;
-            xg += a1;
-            m1 = fmax(m1, a2);
-            me = fmax(me, a3);
-        }
-        cx = uni(cx);
-        xg = uni(xg);
-        m1 = uni(m1);
-        me = uni(me);
+        // the four wave reductions (all 64 lanes of wave 0 take part; m1, me >= 0)
+        cx = uni(wave_sum_full(cx));
+        xg = uni(wave_sum_full(xg));
+        m1 = uni(wave_max_nonneg_full(m1));
+        me = uni(wave_max_nonneg_full(me));
         // ---- scalars (uniform) ----
         const double yr = yy - cx;
         const double r2 = fmax(yr - xg, 0.0);
@@ -1353,15 +1344,9 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             zpos += __popcll(bz);
         }
         wave_sync_lds();
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double a0 = __shfl_xor(kt, off, 64), a1 = __shfl_xor(l1, off, 64), a2 = __shfl_xor(Xn, off, 64);
-            kt += a0;
-            l1 += a1;
-            Xn += a2;
-        }
-        l1 = uni(l1);
-        Xn = uni(Xn);
+        kt = uni(wave_sum_full(kt));
+        l1 = uni(wave_sum_full(l1));
+        Xn = uni(wave_sum_full(Xn));
         wg_stamp_p(prof, b, 3, *s_clk);
         // ---- trace row and momentum (the last stage stays) ----
         if (l == 0 && trace && C.iter < trace_cap) {
