@@ -190,3 +190,17 @@ def test_method_with_the_dome_is_safe_and_solves(real, frac):
     res = osc.fast_l1([(s.values(), s.eps, s.L) for s in pq.stages], p.atom_norm, y, lam, rc, tol=1e-10,
                       rule="dome", q=[s.q for s in pq.stages])
     assert res.converged and not np.any(res.screened & (sol["x"] != 0))
+
+
+def test_dome_without_a_cut_is_the_ball_with_diameter_theta_to_y_over_lambda():
+    # rin2 = 0 leaves the cut at the far side of the ball (delta_c = 1): the dome test is
+    # then the closed-form sphere test of B((y/lambda + theta)/2, ||y/lambda - theta||/2)
+    rng = np.random.default_rng(41)
+    N, K, lam = 9, 25, 0.8
+    for _ in range(20):
+        y, theta, A = rng.standard_normal(N), rng.standard_normal(N), rng.standard_normal((N, K))
+        Rd = float(np.linalg.norm(y / lam - theta))
+        assert osc.gap_dome_cut(Rd, 0.0) == 1.0
+        mu = osc.stable_dome_test(A.T @ y / lam, A.T @ theta, 0.0, Rd, 0.0, np.linalg.norm(A, axis=0))
+        ref = osc.sphere_test(A.T @ (0.5 * (y / lam + theta)), 0.5 * Rd, np.linalg.norm(A, axis=0))
+        np.testing.assert_allclose(mu, ref, rtol=1e-13, atol=1e-13)
