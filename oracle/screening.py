@@ -14,7 +14,10 @@ Readings of points the paper leaves open (each stated where it is used):
     1/L_i, L_i = ||A~^i||_2^2, and its momentum restarts on a dictionary switch.
   * Screening uses the prox output x_t and rho~_t = y - A~ x_t (Section III-C).
     The gradient at the extrapolated point is obtained by linearity from the
-    two correlation vectors A~^T rho~_t and A~^T rho~_{t-1}.
+    two correlation vectors A~^T rho~_t and A~^T rho~_{t-1}.  That identity
+    needs x_{t-1} as it was when A~^T rho~_{t-1} was formed; when a rejection
+    zeroes a nonzero coefficient it would not hold, so the momentum restarts
+    after such a rejection, as after a switch (the step is then exact).
   * The maxima defining alpha'_t, and the error scale of Theorem 1 with
     r = 1 (E = max_j eps_j, the largest column error), run over the preserved
     set A_t, as Algorithm 1 restricts the dictionary to A_t before each update.
@@ -345,6 +348,10 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
         if rule == "dome":
             mu_conv = np.minimum(mu_conv, stable_dome_test(aty / lam, s_stable * g, 0.0, Rd, rin2, at_norms[i]))
         K_t = int(np.count_nonzero(active & (mu_conv >= 1.0)))
+        # a rejection that zeroes a nonzero coefficient of x_t: the next step's gradient
+        # by linearity, (1+beta) g_{t+1} - beta g_t, would take g_t at x_t before the
+        # zeroing, so the momentum restarts there (beta = 0: the step is exact)
+        rejected_nonzero = bool(np.any(x[active & ~keep] != 0.0))
         x_new[~keep] = 0.0
         x[~keep] = 0.0
         if keep_trace:
@@ -353,7 +360,7 @@ def fast_l1(stages, atom_norm, y, lam, rc, Gamma=0.5, tol=1e-6, max_iter=100000,
                                   gamma=gamma, x_l1=x_l1, P=P))
         # ---- switching criterion (Algorithm 2)
         i_next = switch_dictionary(i, I, gamma, Gamma, K_t, rc[i], K)
-        if i_next != i:
+        if i_next != i or rejected_nonzero:
             k_since = 0
             tau = 1.0
         x_prev = x

@@ -192,6 +192,13 @@ constexpr int kGemmMinSignals = SL1_GEMM_MIN_SIGNALS;   // fewer qualifying sign
 
 constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS
 
+// Rejections that zero a nonzero coefficient of x_t are counted in the same FP64
+// sum as the look-ahead count K_t, scaled by 2^20 > K (the two stay separable):
+// after such a rejection the FISTA momentum restarts, because the gradient at the
+// extrapolated point is formed by linearity from g_t, which was taken at x_t before
+// the zeroing.
+constexpr double kRejNz = 1048576.0;
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

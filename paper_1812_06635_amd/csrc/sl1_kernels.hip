@@ -193,10 +193,13 @@ __device__ int advance_control(const SolveParams* P, int b, const Control& Cp, c
         s_zpre[nblk] = az_tot;
     }
     __syncthreads();
+    // rejected nonzero coefficients travel above the look-ahead count
+    const double rnz = floor(kt / kRejNz);
+    kt -= rnz * kRejNz;
     const int I = P->n_stages - 1;
     const StageDesc& st = P->st[Cp.stage];
     const int i_new = switch_dictionary(Cp.stage, I, S.gamma, P->Gamma, kt, st.rc, (double)P->K);
-    if (i_new != Cp.stage) {
+    if (i_new != Cp.stage || rnz > 0.0) {   // a switch, or a rejection that zeroed x_t[j]: restart
         C.stage = i_new;
         C.ksince = 0;
         C.tau = 1.0;
@@ -1660,6 +1663,7 @@ __device__ __forceinline__ void upd_body(const SolveParams* __restrict__ P, int 
             if (!keep) {
                 xc[j] = 0.0;
                 P->mask[(size_t)b * K + j] = 0;
+                if (xt != 0.0) kt += kRejNz;
             }
             nzf = keep && (xn != 0.0);
             l1 = fabs(xn);

@@ -824,6 +824,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                         if (!keep[h]) {
                             xc[j] = 0.0;
                             mask[j] = 0;
+                            if (xt != 0.0) sv[0] += kRejNz;
                         }
                         nzf[h] = keep[h] && (xn != 0.0);
                         xnv[h] = xn;
@@ -869,7 +870,9 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const SolveParams* P = phase_params(P0);
             const StageDesc& st = P->st[stage];
             Control C = sC;
-            const double kt = s_kt[0];
+            // rejected nonzero coefficients travel above the look-ahead count
+            const double rnz = floor(s_kt[0] / kRejNz);
+            const double kt = s_kt[0] - rnz * kRejNz;
             if (P->trace && C.iter < P->trace_cap) {
                 double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
                 tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
@@ -878,7 +881,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                 tr[10] = C.l1; tr[11] = sS.P; tr[12] = C.n_nz;
             }
             const int i_new = switch_dictionary(C.stage, P->n_stages - 1, sS.gamma, P->Gamma, kt, st.rc, (double)P->K);
-            if (i_new != C.stage) {
+            if (i_new != C.stage || rnz > 0.0) {   // a switch, or a rejection that zeroed x_t[j]: restart
                 C.stage = i_new;
                 C.ksince = 0;
                 C.tau = 1.0;
@@ -1293,6 +1296,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                         xc[j] = 0.0;
                         xo[j] = 0.0;
                         mask[j] = 0;
+                        if (xt[h] != 0.0) kt += kRejNz;
                     }
                     nzf[h] = keep[h] && (xn[h] != 0.0);
                     l1 += fabs(xn[h]);
@@ -1347,6 +1351,9 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         kt = uni(wave_sum_full(kt));
         l1 = uni(wave_sum_full(l1));
         Xn = uni(wave_sum_full(Xn));
+        // rejected nonzero coefficients travel above the look-ahead count
+        const double rnz = uni(floor(kt / kRejNz));
+        kt -= rnz * kRejNz;
         wg_stamp_p(prof, b, 3, *s_clk);
         // ---- trace row and momentum (the last stage stays) ----
         if (l == 0 && trace && C.iter < trace_cap) {
@@ -1356,8 +1363,13 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             tr[5] = Gp; tr[6] = Gt; tr[7] = delta; tr[8] = rule ? Rd : Rp; tr[9] = gam_t;
             tr[10] = C.l1; tr[11] = Pv; tr[12] = C.n_nz;
         }
-        C.ksince += 1;
-        C.tau = tau_next;
+        if (rnz > 0.0) {                  // a rejection that zeroed x_t[j]: momentum restarts
+            C.ksince = 0;
+            C.tau = 1.0;
+        } else {
+            C.ksince += 1;
+            C.tau = tau_next;
+        }
         C.iter += 1;
         C.par = 1 - par;
         C.n_act = wpos;
@@ -1572,6 +1584,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                         xc[j] = 0.0;
                         xo[j] = 0.0;
                         mask[j] = 0;
+                        if (xt != 0.0) sv[0] += kRejNz;
                     }
                     nzf = keep && (xn != 0.0);
                     sv[1] += fabs(xn);
@@ -1613,15 +1626,22 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
         if (tid == 0) {
             const SolveParams* P = phase_params(P0);
             Control C = sC;
+            // rejected nonzero coefficients travel above the look-ahead count
+            const double rnz = floor(s_kt[0] / kRejNz);
             if (P->trace && C.iter < P->trace_cap) {
                 double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
                 tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = s_cnt[0];
-                tr[4] = s_kt[0];
+                tr[4] = s_kt[0] - rnz * kRejNz;
                 tr[5] = sS.Gp; tr[6] = sS.Gt; tr[7] = sS.delta; tr[8] = P->rule ? sS.Rd : sS.Rp; tr[9] = sS.gamma;
                 tr[10] = C.l1; tr[11] = sS.P; tr[12] = C.n_nz;
             }
-            C.ksince += 1;
-            C.tau = sS.tau_next;
+            if (rnz > 0.0) {               // a rejection that zeroed x_t[j]: momentum restarts
+                C.ksince = 0;
+                C.tau = 1.0;
+            } else {
+                C.ksince += 1;
+                C.tau = sS.tau_next;
+            }
             C.iter += 1;
             C.par = 1 - C.par;
             C.n_act = s_cnt[0];

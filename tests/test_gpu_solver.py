@@ -271,6 +271,39 @@ def test_warm_start_trace_matches_method_reference(sl1, engine):
     _check_solution(p, out, 0, obj_tol=1e-7)
 
 
+@pytest.mark.parametrize("engine,gram", [("grid", True), ("wg", True), ("hybrid", True), ("hybrid", False)],
+                         ids=["grid", "wg", "hybrid-gram", "hybrid-columns"])
+def test_rejected_nonzero_restarts_momentum_like_the_method_reference(sl1, engine, gram):
+    # a warm start with spurious coefficients on atoms near the dual constraint: the test
+    # rejects one of them at t = 5 while x_t[j] != 0 (preserved set of 6 atoms), after
+    # which the momentum restarts; the hybrid engine hands over after 2 iterations, so
+    # its tail (Gram or column mode) meets the rejection
+    _say(f"restart after a rejected nonzero, C1 exact stage, engine={engine} gram={gram}")
+    p = synth.config1(realization=0, lam_frac=0.5)
+    y, lam = p.Y[0], float(p.lam[0])
+    sol = ol.solve(p.A, y, lam, L=p.stages[-1].L)
+    corr = p.A.T @ sol["theta"]
+    cand = np.flatnonzero((sol["x"] == 0) & (np.abs(corr) > 0.8) & (np.abs(corr) < 0.95))
+    x0 = sol["x"].copy()
+    x0[cand] = 0.1 * np.sign(corr[cand])
+    ex = p.stages[-1:]
+    out = _run(sl1, p, tol=1e-10, stages=ex, trace_cap=5000, engine=engine, tail_gram=gram, chunk=2,
+               x0=_t(x0[None, :]))
+    ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in ex], p.atom_norm, y, lam, [1.0], tol=1e-10, x0=x0)
+    n = int(out["iters"][0])
+    assert ref.converged and out["status"] == 0 and n == ref.iters
+    tr = out["trace"][0][:n]
+    assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+    assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+    assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+    np.testing.assert_allclose(tr[:, 6], np.array([r.G_conv for r in ref.trace]), rtol=1e-7, atol=1e-12)
+    np.testing.assert_allclose(tr[:, 10], np.array([r.x_l1 for r in ref.trace]), rtol=1e-9)
+    np.testing.assert_allclose(out["x"][0], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
+    _check_solution(p, out, 0, obj_tol=1e-7)
+    if engine == "hybrid":
+        assert sl1.last_solve_phases(1, p.N, p.K)[0] == "hybrid"
+
+
 @pytest.mark.parametrize("engine", ["grid", "hybrid"])
 def test_warm_started_path_matches_cold_solves(sl1, engine):
     _say(f"lambda path C4-small batch 8 engine={engine}")

@@ -179,6 +179,10 @@ def test_eps_zero_reduces_to_gap_safe():
     for r in r2.trace:
         assert r.gamma == 1.0 and r.delta == 0.0
         assert r.R_stable == pytest.approx(np.sqrt(2 * max(r.G_conv, 0)) / lam, rel=1e-14)
+        # Section IV-C: with eps = 0 on A the look-ahead test (same sphere, atoms of A,
+        # no eps term) is the screening test itself, so K_t counts exactly the atoms the
+        # test keeps (the 1e-12 margin band holds none of them here)
+        assert r.K_t == r.n_keep
     assert np.linalg.norm(r2.x - sol["x"]) <= 1e-6 * np.linalg.norm(sol["x"])
     assert not np.any(r2.screened & (sol["x"] != 0))
 
@@ -395,3 +399,81 @@ def test_warm_start_from_any_point_keeps_the_first_step_plain():
     x1 = np.sign(v) * np.maximum(np.abs(v) - lam / L, 0.0)
     keep = ~res.screened
     np.testing.assert_allclose(res.x[keep], x1[keep], rtol=1e-12, atol=1e-14)
+
+
+def test_look_ahead_count_on_a_hand_built_case():
+    # K_t of Section IV-C worked out by hand at t = 0 (x_0 = 0, so rho~_0 = y).
+    # y = (1, 0), lambda = 1/2; approximate atoms a~_A = (0.1, 0.3), a~_B = (0.2, 0.3),
+    # a~_C = (0.6, 0), a~_D = (0.05, 1); exact atoms a_j = a~_j / ||a~_j|| except
+    # a_C = (1, 0); bounds eps = (0.7, 0.64, 0.4, 0.00125) >= ||a_j - a~_j||.
+    #   g = A~^T y = (0.1, 0.2, 0.6, 0.05); stable scaling max_j (|g_j| + eps_j ||y||) = 1
+    #   (atom C), so s' = min(1/lambda, 1) = 1 and theta' = y;
+    #   G' = 1/2 - (lambda - lambda^2/2) = 1/8, delta = 0 (x = 0), R' = sqrt(2 G')/lambda = 1;
+    #   conventional: s~ = 1/0.6 = 5/3, G~ = 1/2 - (5/6 - 25/72) = 1/72, gamma = 1/9.
+    #   K_0 counts |s' g_j| + R' ||a~_j|| >= 1:  A 0.1 + 0.316 = 0.42, B 0.2 + 0.361 = 0.56,
+    #   C 0.6 + 0.6 = 1.2, D 0.05 + 1.001 = 1.05  ->  K_0 = 2 (C and D).
+    #   Readings that would differ: adding eps_j |s'| ||y|| (A 1.12, B 1.20: K_0 = 4); ||a_j||
+    #   for ||a~_j|| (A 1.1, B 1.2: K_0 = 4); the conventional sphere (theta~, sqrt(2G~)/lambda
+    #   = 1/3: only C, K_0 = 1).  The screening test itself keeps all four at t = 0
+    #   (|g_j| + eps_j + 1 >= 1).
+    At = np.array([[0.1, 0.2, 0.6, 0.05], [0.3, 0.3, 0.0, 1.0]])
+    A = At / np.linalg.norm(At, axis=0)
+    A[:, 2] = (1.0, 0.0)
+    eps = np.array([0.7, 0.64, 0.4, 0.00125])
+    assert np.all(np.linalg.norm(A - At, axis=0) <= eps)
+    y, lam = np.array([1.0, 0.0]), 0.5
+    L0, L1 = np.linalg.norm(At, 2) ** 2, np.linalg.norm(A, 2) ** 2
+    res = osc.fast_l1([(At, eps, L0), (A, np.zeros(4), L1)], np.ones(4), y, lam, [0.0, 1.0],
+                      Gamma=0.0, tol=1e-12, max_iter=1)
+    r = res.trace[0]
+    assert r.t == 0 and r.stage == 0 and r.n_active == 4 and r.n_keep == 4
+    assert r.K_t == 2
+    assert r.G_stable == pytest.approx(1 / 8, rel=1e-14)
+    assert r.R_stable == pytest.approx(1.0, rel=1e-14)
+    assert r.G_conv == pytest.approx(1 / 72, rel=1e-12)
+    assert r.gamma == pytest.approx(1 / 9, rel=1e-12)
+    assert r.delta == 0.0
+
+
+def _iterate(stages, atom_norm, y, lam, x0, t):
+    """x_t and the preserved set A_t of the method (the result returned at max_iter = t)."""
+    res = osc.fast_l1(stages, atom_norm, y, lam, [1.0] * len(stages), tol=0.0, max_iter=t, x0=x0,
+                      keep_trace=False)
+    return res.x, ~res.screened
+
+
+def test_rejecting_a_nonzero_coefficient_restarts_the_momentum():
+    # A warm start with spurious coefficients on atoms near the dual constraint makes the
+    # test reject an atom at some t >= 1 while x_t[j] != 0.  FISTA's gradient at the
+    # extrapolated point, taken by linearity from g_{t+1} and g_t, would then mix x_t
+    # before and after the zeroing; the method restarts the momentum instead, so the
+    # step from x_{t+1} is the plain proximal step on the preserved set (Section I-B).
+    p = synth.config1(realization=0, lam_frac=0.5)
+    y, lam = p.Y[0], float(p.lam[0])
+    sol = ol.solve(p.A, y, lam)
+    corr = p.A.T @ sol["theta"]
+    cand = np.flatnonzero((sol["x"] == 0) & (np.abs(corr) > 0.8) & (np.abs(corr) < 0.95))
+    x0 = sol["x"].copy()
+    x0[cand] = 0.1 * np.sign(corr[cand])
+    ex = p.stages[-1]
+    stages = [(ex.values(), ex.eps, ex.L)]
+    A, L = stages[0][0], stages[0][2]
+    hit = None
+    x_prev, act_prev = _iterate(stages, p.atom_norm, y, lam, x0, 1)
+    for t in range(1, 40):
+        x_next, act_next = _iterate(stages, p.atom_norm, y, lam, x0, t + 1)
+        if np.any(x_prev[act_prev & ~act_next] != 0.0):
+            hit = t
+            break
+        x_prev, act_prev = x_next, act_next
+    assert hit is not None, "the case must reject a nonzero coefficient at some t >= 1"
+    x1, _ = _iterate(stages, p.atom_norm, y, lam, x0, hit + 1)
+    x2, act2 = _iterate(stages, p.atom_norm, y, lam, x0, hit + 2)
+    v = x1 + A.T @ (y - A @ x1) / L
+    plain = np.sign(v) * np.maximum(np.abs(v) - lam / L, 0.0)
+    np.testing.assert_allclose(x2[act2], plain[act2], rtol=1e-12, atol=1e-14)
+    assert not np.any(x2[~act2])
+    # and the solve stays safe and exact
+    res = osc.fast_l1(stages, p.atom_norm, y, lam, [1.0], tol=1e-10, x0=x0)
+    assert not np.any(res.screened & (sol["x"] != 0))
+    assert np.linalg.norm(res.x - sol["x"]) <= 1e-6 * np.linalg.norm(sol["x"])
