@@ -256,7 +256,8 @@ int sl1_opts_default(sl1_opts* o);
  * The call orders itself after prior work on `stream`, polls convergence and
  * returns once every signal has converged or reached max_iter; the outputs are
  * then complete.  Concurrent calls with identical shapes on one device are
- * serialised internally.
+ * serialised internally; calls with other shapes use other workspaces and may run
+ * concurrently (a cached workspace is released only when no call holds it).
  * Returns SL1_OK, SL1_MAXITER, SL1_EINVAL (bad lambda / non-finite y detected on
  * the device), SL1_ESHAPE, SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP or SL1_ENOMEM.
  */

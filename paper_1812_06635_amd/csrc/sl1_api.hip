@@ -164,7 +164,9 @@ struct Workspace {
 };
 
 std::mutex g_ws_mu;
-std::map<std::tuple<int, int, int, int>, std::unique_ptr<Workspace>> g_ws;
+// Workspaces are shared: every call holds its own reference for its whole duration,
+// so dropping a cached entry never frees memory, a stream or a mutex still in use.
+std::map<std::tuple<int, int, int, int>, std::shared_ptr<Workspace>> g_ws;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -249,27 +251,29 @@ int make_workspace(Workspace& w) {
     return SL1_OK;
 }
 
-int get_workspace(int device, int batch, int N, int K, Workspace** out) {
+int get_workspace(int device, int batch, int N, int K, std::shared_ptr<Workspace>* out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto key = std::make_tuple(device, batch, N, K);
     auto it = g_ws.find(key);
     if (it != g_ws.end()) {
-        *out = it->second.get();
+        *out = it->second;
         return SL1_OK;
     }
-    // keep the cache small: drop idle workspaces of other shapes on this device
+    // keep the cache small: drop idle workspaces of other shapes on this device.  An
+    // entry is idle when the cache holds its only reference (new references are made
+    // only here, under g_ws_mu); one in use by a concurrent call stays.
     for (auto i = g_ws.begin(); i != g_ws.end();) {
-        if (std::get<0>(i->first) == device && g_ws.size() >= 4) i = g_ws.erase(i);
+        if (std::get<0>(i->first) == device && g_ws.size() >= 4 && i->second.use_count() == 1) i = g_ws.erase(i);
         else ++i;
     }
-    auto w = std::make_unique<Workspace>();
+    auto w = std::make_shared<Workspace>();
     w->device = device;
     w->batch = batch;
     w->N = N;
     w->K = K;
     int st = make_workspace(*w);
     if (st != SL1_OK) return st;
-    *out = w.get();
+    *out = w;
     g_ws[key] = std::move(w);
     return SL1_OK;
 }
@@ -1123,9 +1127,10 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     if (dev != seq[0]->device) return SL1_EINVAL;
-    Workspace* w = nullptr;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
+    std::shared_ptr<Workspace> ws;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &ws);
     if (st != SL1_OK) return st;
+    Workspace* w = ws.get();
     std::lock_guard<std::mutex> lk(w->mu);
     const bool dst = (o.flags & SL1_FLAG_RULE_DST) != 0;
     const bool dome = (o.flags & SL1_FLAG_RULE_DOME) != 0;
@@ -1332,9 +1337,10 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
     if (dev != d->device) return SL1_EINVAL;
-    Workspace* w = nullptr;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
+    std::shared_ptr<Workspace> ws;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &ws);
     if (st != SL1_OK) return st;
+    Workspace* w = ws.get();
     std::lock_guard<std::mutex> lk(w->mu);
     SolveParams& p = *w->hP;
     std::memcpy(p.st, tmp.st, sizeof(tmp.st));
@@ -1406,9 +1412,10 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
     if (st != SL1_OK) return st;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
-    Workspace* w = nullptr;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &w);
+    std::shared_ptr<Workspace> ws;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &ws);
     if (st != SL1_OK) return st;
+    Workspace* w = ws.get();
     std::lock_guard<std::mutex> lk(w->mu);
     // synthetic signals: y = 1 (any direction works, the cost does not depend on it)
     void* ybuf = nullptr;
@@ -1476,13 +1483,14 @@ int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_
 int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, double* rate_khz) {
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
-    Workspace* w = nullptr;
+    std::shared_ptr<Workspace> ws;
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         auto it = g_ws.find(std::make_tuple(dev, (int)batch, (int)N, (int)K));
         if (it == g_ws.end()) return SL1_EINVAL;
-        w = it->second.get();
+        ws = it->second;
     }
+    Workspace* w = ws.get();
     std::lock_guard<std::mutex> lk(w->mu);
     HIP_TRY(launch_time_out(w->dP, (int)batch, w->d_times, w->stream));
     HIP_TRY(hipMemcpyAsync(out, w->d_times, batch * 16, hipMemcpyDeviceToHost, w->stream));
