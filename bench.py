@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--no-parity", action="store_true", help="skip the sampled oracle parity check")
     ap.add_argument("--no-variants", action="store_true", help="skip the ISTA / Dynamic Safe variants")
     ap.add_argument("--no-faust", action="store_true", help="skip the FAuST (MEG-shaped) block")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense precision block (N=2500, K=10000)")
+    ap.add_argument("--parity-signals", type=int, default=0,
+                    help="signals of the batched workload checked against the oracle (0: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -120,7 +122,11 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
       dense correlations  |A_t| N b bytes (b: bytes per stored element, + 4 B per
                           column scale); Kronecker correlations 2 R k2 n1 (n2 + k1)
                           flops (sum_r C_r^T P B_r);
-      forward             ||x_t||_0 N b bytes on dense stages (gathered columns);
+      forward             per signal: the nonzero list (12 B per nonzero), the gathered
+                          columns on dense stages (||x_t||_0 N b), one read of the
+                          factors on Kronecker stages (R (n1 k1 + n2 k2) b) or of the
+                          factor entries on FAuST stages, the signal read and the FP64
+                          residual written (N (b_y + 8)) in the grid kernels;
       update              76 B per preserved atom in the grid kernels (the tail
                           keeps the per-atom state in LDS);
       tail, Gram form     rows with |A_t| <= gram_cap: the |A_t| columns read once
@@ -142,6 +148,7 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
             tiles, ks = gemm_plan(int(S), N, p.K, p.batch)
             if ks > 1:
                 w["fin_bytes"] += tiles * ks * 64 * 64 * 8.0
+    by = 8 if p.work == "f64" else 4
     for b in range(trace.shape[0]):
         n = int(iters[b])
         rows = trace[b, :n]
@@ -161,7 +168,7 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
                     w["gemm_flops"] += 2.0 * N * float(rows[gm, 2].sum())
                     w["gemm_exec_flops"] += 2.0 * N * p.K * int(gm.sum())
                     w["gemm_it"] += int(gm.sum())
-                    w["fwd_bytes"][0] += N * bpe * float(rows[gm, 12].sum())
+                    w["fwd_bytes"][0] += (N * bpe + 12.0) * float(rows[gm, 12].sum()) + N * (by + 8.0) * int(gm.sum())
                     w["upd_bytes"][0] += UPD_BYTES_PER_ATOM * float(rows[gm, 2].sum())
                 on = on & ~gm
             if g.any():
@@ -174,26 +181,38 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
                     continue
                 if ph == 0:
                     w["upd_bytes"][ph] += UPD_BYTES_PER_ATOM * float(rows[m, 2].sum())
+                nz = float(rows[m, 12].sum())
+                if ph == 0:                   # residual written and signal read by the forward launch
+                    w["fwd_bytes"][0] += N * (by + 8.0) * cnt + 12.0 * nz
                 if st.kind == "dense":
                     w["adj_bytes"][ph] += N * bpe * float(rows[m, 2].sum())
-                    w["fwd_bytes"][ph] += N * bpe * float(rows[m, 12].sum())
+                    w["fwd_bytes"][ph] += N * bpe * nz
                     w["dense_it"][ph] += cnt
                 elif st.kind == "faust":
                     # the adjoint chain: 2 flops per factor entry (FP64), per signal
                     nnz = sum(len(f[1]) for f in st.factors)
+                    vb = {"f64": 8, "f32": 4}[st.dtype] + 4.0
                     w["adj_flops"][ph] += cnt * 2.0 * nnz
+                    w["fwd_bytes"][ph] += cnt * vb * sum(len(f[1]) for f in st.factors[:-1]) + \
+                        vb * nz * len(st.factors[-1][1]) / st.K
                     w["faust_it"][ph] += cnt
                 else:
                     n1, k1, n2, k2 = st.dims
+                    fb = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype]
                     w["adj_flops"][ph] += cnt * 2.0 * st.R * k2 * n1 * (n2 + k1)
+                    w["fwd_bytes"][ph] += cnt * st.R * (n1 * k1 + n2 * k2) * fb
                     w["kron_it"][ph] += cnt
     return w
 
 
-def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
+MFMA_PEAK_TFLOPS = {"bf16": BF16_PEAK_TFLOPS, "f32": FP32_PEAK_TFLOPS, "f64": FP64_PEAK_TFLOPS}
+
+
+def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail", kron_dtype="bf16"):
     """Roofline of every kernel of the solve: achieved = algorithmic work /
     measured time (HIP events around each launch), against the MI355X peak of
-    its bound."""
+    its bound; the Kronecker products against the matrix-core peak of their
+    factors' storage type (BF16, FP32 or FP64 MFMA)."""
     out = []
 
     def add(name, ms, launches, amount, unit_kind, peak=BF16_PEAK_TFLOPS):
@@ -215,7 +234,7 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
     if work["faust_it"][0] > work["kron_it"][0]:    # structured launch running FAuST chains (FP64 vector)
         add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "alu", FP64_PEAK_TFLOPS)
     else:
-        add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma")
+        add("k_adj_kron", *prof["adj_kron"], work["adj_flops"][0], "mfma", MFMA_PEAK_TFLOPS[kron_dtype])
     add("k_upd", *prof["upd"], work["upd_bytes"][0], "hbm")
     if "adj_gemm" in prof:
         add("k_adj_gemm", *prof["adj_gemm"], work["gemm_flops"], "mfma", FP64_PEAK_TFLOPS)
@@ -233,6 +252,10 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail"):
 def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
     st, Y, lam, an = upload(sl1, torch, p)
     L = [s.L for s in p.stages]
+    tiles = None
+    if any(s.kind == "kron" for s in p.stages):
+        tiles, _ = sl1.tune_kron(st, batch=p.batch)
+        log(f"{label}: Kronecker tile shapes (autotuned) {tiles}")
     log(f"{label}: measuring relative complexities")
     rc_meas = sl1.measure_rc(st, batch=p.batch)
     rc = rc_meas
@@ -250,6 +273,9 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
     ttg_dev = float(np.max(clk[:, 1] - clk[:, 0])) * 1e3
     ms_p, out_p = timed(torch, plain, steps, warmup)
     engine_p = sl1.last_solve_phases(p.batch, p.N, p.K)[0]
+    # the same solve continued to the accuracy gap (untimed), where parity is evaluated
+    acc_tol = 1e-10
+    out_a = sl1.solve(st, L, rc, an, Y, lam, tol=acc_tol)
     it_m = int(out_m["iters"].sum().item())
     it_p = int(out_p["iters"].sum().item())
     gap_m = out_m["gap"].cpu().numpy()
@@ -268,12 +294,16 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
     res = dict(
         ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p, engine=engine, engine_plain=engine_p,
         time_to_gap_ms_device=ttg_dev, max_gap_method=float(gap_m.max()), max_gap_plain=float(gap_p.max()),
-        stage_final=sorted(set(out_m["stage"].cpu().numpy().tolist())), rc_measured=rc_meas,
+        stage_final=sorted(set(out_m["stage"].cpu().numpy().tolist())), rc_measured=rc_meas, kron_tiles=tiles,
         rc_model=[s.rc_theory for s in p.stages], kernel_ms=prof, wg_phases=phases, grid_iterations=t_split,
         roofline_kernels=roofline_entries(prof, phases, work,
-                                          "k_solve_tail" if engine == "hybrid" else "k_solve_wg"),
+                                          "k_solve_tail" if engine == "hybrid" else "k_solve_wg",
+                                          next((s.dtype for s in p.stages if s.kind == "kron"), "bf16")),
         gram_iterations=work["gram_it"], gemm_iterations=work["gemm_it"],
         x=out_m["x"].cpu().numpy(), screened=out_m["screened"].cpu().numpy(),
+        acc_tol=acc_tol, x_acc=out_a["x"].cpu().numpy(), screened_acc=out_a["screened"].cpu().numpy(),
+        max_gap_acc=float(out_a["gap"].max().item()),
+        x_plain=out_p["x"].cpu().numpy(), screened_plain=out_p["screened"].cpu().numpy(),
     )
     return res
 
@@ -322,7 +352,14 @@ def recorded_traffic(kernel):
 VARIANTS = (("fista", "dst"), ("ista", "gap"), ("ista", "dst"), ("fista", "dome"))
 
 
-def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None):
+def apply_tiles(stages, tiles):
+    """The autotuned Kronecker tile shapes (one entry per stage, None elsewhere) on new handles."""
+    for d, t in zip(stages, tiles or []):
+        if t is not None:
+            d.set_tile(*t)
+
+
+def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None, tiles=None):
     """The other update / test combinations of Table III (FISTA or ISTA, stable GAP
     Safe or stable Dynamic Safe) on the same batch: time-to-gap of the method and
     of plain FP32 (the single stage [A]) with the same update and test; then the
@@ -330,6 +367,7 @@ def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None):
     of the headline's plain FP32 solve, FISTA + stable GAP Safe, which has no bounds)."""
     import synth
     st, Y, lam, an = upload(sl1, torch, p)
+    apply_tiles(st, tiles)
     L = [s.L for s in p.stages]
     out = []
     for update, rule in VARIANTS:
@@ -345,12 +383,14 @@ def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None):
         log(f"variant {update}/{rule}: method {ms_m:.3f} ms ({it_m} iters), plain {ms_p:.3f} ms ({it_p} iters)")
         out.append(dict(update=update, rule=rule, time_to_gap_ms=ms_m, iters=it_m,
                         iters_per_s=it_m / (ms_m * 1e-3), plain_fp32_time_to_gap_ms=ms_p, plain_fp32_iters=it_p,
-                        speedup_vs_plain_fp32=ms_p / ms_m, max_gap=float(o_m["gap"].max().item())))
+                        speedup_vs_plain_fp32=ms_p / ms_m, max_gap=float(o_m["gap"].max().item()),
+                        _x=o_m["x"].cpu().numpy(), _screened=o_m["screened"].cpu().numpy()))
     # FISTA + stable GAP Safe with the approximations' bounds in l1 and l_inf (Lemma 1 with an
     # l_q zone); the plain comparator has no bounds, so it is the FISTA / GAP one above
     for q, name in ((1.0, "l1"), (float("inf"), "l_inf")):
         pq = synth.with_lq_bounds(p, q)
         stq = [sl1.upload_stage(s) for s in pq.stages]
+        apply_tiles(stq, tiles)
 
         def method_q():
             return sl1.solve(stq, L, rc, an, Y, lam, tol=tol)
@@ -359,12 +399,36 @@ def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None):
         it_m = int(o_m["iters"].sum().item())
         log(f"variant fista/gap with {name} bounds: method {ms_m:.3f} ms ({it_m} iters)")
         entry = dict(update="fista", rule="gap", bounds=name, time_to_gap_ms=ms_m, iters=it_m,
-                     iters_per_s=it_m / (ms_m * 1e-3), max_gap=float(o_m["gap"].max().item()))
+                     iters_per_s=it_m / (ms_m * 1e-3), max_gap=float(o_m["gap"].max().item()),
+                     _x=o_m["x"].cpu().numpy(), _screened=o_m["screened"].cpu().numpy())
         if plain_ref is not None:
             entry.update(plain_fp32_time_to_gap_ms=plain_ref[0], plain_fp32_iters=plain_ref[1],
                          speedup_vs_plain_fp32=plain_ref[0] / ms_m)
         out.append(entry)
         del stq
+    # FISTA + stable GAP Safe with the approximations' factors stored in FP8 E4M3 (the same
+    # dictionary, signals and lambdas; the factors' own rounding is in their eps)
+    p8 = synth.config4(batch=p.batch, factor_dtype="fp8") if p.name == "C4" else None
+    if p8 is not None and np.array_equal(p8.Y, p.Y):
+        st8 = [sl1.upload_stage(s) for s in p8.stages]
+        tiles8, _ = sl1.tune_kron(st8, batch=p8.batch)
+        rc8 = sl1.measure_rc(st8, batch=p8.batch)
+
+        def method_8():
+            return sl1.solve(st8, [s.L for s in p8.stages], rc8, an, Y, lam, tol=tol)
+
+        ms_m, o_m = timed(torch, method_8, steps, warmup)
+        it_m = int(o_m["iters"].sum().item())
+        log(f"variant fista/gap with FP8 factors: method {ms_m:.3f} ms ({it_m} iters), tiles {tiles8}")
+        entry = dict(update="fista", rule="gap", factors="fp8", time_to_gap_ms=ms_m, iters=it_m,
+                     iters_per_s=it_m / (ms_m * 1e-3), max_gap=float(o_m["gap"].max().item()), rc_measured=rc8,
+                     kron_tiles_autotuned=tiles8, eps_max=[float(s.eps.max()) for s in p8.stages],
+                     _x=o_m["x"].cpu().numpy(), _screened=o_m["screened"].cpu().numpy())
+        if plain_ref is not None:
+            entry.update(plain_fp32_time_to_gap_ms=plain_ref[0], plain_fp32_iters=plain_ref[1],
+                         speedup_vs_plain_fp32=plain_ref[0] / ms_m)
+        out.append(entry)
+        del st8
     return out
 
 
@@ -376,46 +440,117 @@ def roofline(res):
     return r
 
 
-def parity_sample(np, p, res, n=2):
+def oracle_reference(p, indices=None, label=""):
+    """{b: (x*, P*, kkt, margin)} of the FP64 oracle (the Lasso definition, polished
+    and certified) for the signals in indices (default: all), in worker processes."""
+    import oracle.pool as opool
+
+    def progress(done, total):
+        if done % 64 == 0 or done == total:
+            log(f"{label}: oracle solved {done} of {total} signals")
+
+    return opool.solve_batch(p.A, p.Y, p.lam, p.stages[-1].L, indices=indices, progress=progress)
+
+
+def oracle_errors(np, p, x, screened, ref):
+    """Error of solutions x (batch, K) against the oracle on the signals of ref: unsafe
+    rejections (screened atoms in the support of x*), relative objective error and
+    ||x - x*|| / ||x*||, the largest over the signals."""
     import oracle.lasso as ol
     worst_obj, worst_x, unsafe = 0.0, 0.0, 0
-    idx = list(range(min(n, p.batch)))
-    for b in idx:
-        sol = ol.solve(p.A, p.Y[b], float(p.lam[b]), L=p.stages[-1].L, tol=1e-13)
-        x = res["x"][b]
-        P = ol.primal(p.A, p.Y[b], float(p.lam[b]), x)
-        worst_obj = max(worst_obj, (P - sol["P"]) / sol["P"])
-        if np.linalg.norm(sol["x"]) > 0:
-            worst_x = max(worst_x, float(np.linalg.norm(x - sol["x"]) / np.linalg.norm(sol["x"])))
-        unsafe += int(np.sum((res["screened"][b] == 1) & (sol["x"] != 0)))
-    return dict(signals=len(idx), max_rel_obj=worst_obj, max_rel_x=worst_x, unsafe_rejections=unsafe)
+    for b, (xs, Ps, _, _) in ref.items():
+        xb = np.asarray(x[b], dtype=np.float64)
+        P = ol.primal(p.A, p.Y[b], float(p.lam[b]), xb)
+        worst_obj = max(worst_obj, (P - Ps) / Ps)
+        nx = np.linalg.norm(xs)
+        if nx > 0:
+            worst_x = max(worst_x, float(np.linalg.norm(xb - xs) / nx))
+        unsafe += int(np.sum((screened[b] == 1) & (xs != 0)))
+    return dict(signals=len(ref), unsafe_rejections=unsafe, max_rel_obj=float(worst_obj), max_rel_x=worst_x)
 
 
-def cpu_baseline(np, p, seconds):
-    """The FP64 oracle (plain FISTA, exact A, no screening) timed on the host."""
-    import oracle.lasso as ol
-    threads = os.cpu_count()
+def block_parity(np, p, res, ref, tol):
+    """Oracle errors of a block: the method at the timed stop (gap < tol) and continued
+    to the accuracy gap, and the plain FP32 comparator at the timed stop."""
+    return {"signals": len(ref), "timed_stop_gap": tol,
+            "method_at_timed_stop": oracle_errors(np, p, res["x"], res["screened"], ref),
+            "accuracy_gap": res["acc_tol"],
+            "method_at_accuracy_gap": oracle_errors(np, p, res["x_acc"], res["screened_acc"], ref),
+            "plain_fp32_at_timed_stop": oracle_errors(np, p, res["x_plain"], res["screened_plain"], ref)}
+
+
+def blas_info():
     try:
         from threadpoolctl import threadpool_info
-        info = threadpool_info()
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
         if info:
-            threads = max(int(i.get("num_threads", 1)) for i in info)
+            return info[0].get("internal_api", "?"), max(int(i.get("num_threads", 1)) for i in info)
     except Exception:
         pass
-    y, lam = p.Y[0], float(p.lam[0])
+    return "unknown", os.cpu_count()
+
+
+def cpu_legs(np, p, ref, signals, tol, threads=None):
+    """The paper's normalized-time legs (Section V-B), each to gap tol on the same
+    signals, timed on the host with the oracle code as it stands: T_N = plain FP64
+    FISTA without screening on A (the oracle's solver; its stop test is gap <
+    tol max(1, P), given tol / max(1, P*) so that it stops at gap tol), T_A = the
+    method reference on [A] alone (FISTA + GAP Safe, the stable test with eps = 0),
+    T_A~ = the method reference on the whole stage sequence.  The method reference
+    forms every product densely in FP64 (it checks arithmetic, it is not a fast
+    implementation), so T_A~ / T_N reflects iteration counts, not the structured
+    products' cost.  threads: BLAS threads (None: all)."""
+    import contextlib
+    import oracle.lasso as ol
+    import oracle.screening as osc
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(threads) if threads else contextlib.nullcontext()
+    except Exception:
+        ctx = contextlib.nullcontext()
+    st = [(s.values(), s.eps, s.L) for s in p.stages]
+    rc = [s.rc_theory for s in p.stages]
     L = p.stages[-1].L
-    n = 20
-    t0 = time.perf_counter()
-    ol.fista(p.A, y, lam, L, tol=0.0, max_iter=n, check_every=10 ** 9)
-    dt = time.perf_counter() - t0
-    while dt < seconds and n < 10 ** 6:
-        n = int(n * max(2.0, min(10.0, seconds / max(dt, 1e-3))))
-        t0 = time.perf_counter()
-        ol.fista(p.A, y, lam, L, tol=0.0, max_iter=n, check_every=10 ** 9)
-        dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="iter/s", cores=threads, kind="oracle",
-                sample=f"FP64 FISTA without screening, exact A (N={p.N}, K={p.K}), signal 0, {n} iterations "
-                       f"in {dt:.1f} s")
+    t = dict(T_N=0.0, T_A=0.0, T_At=0.0)
+    it = dict(T_N=0, T_A=0, T_At=0)
+    with ctx:
+        for b in signals:
+            y, lam = p.Y[b], float(p.lam[b])
+            P = ref[b][1]
+            t0 = time.perf_counter()
+            _, _, n = ol.fista(p.A, y, lam, L, tol=tol / max(1.0, P))
+            t["T_N"] += time.perf_counter() - t0
+            it["T_N"] += n
+            t0 = time.perf_counter()
+            r = osc.fast_l1(st[-1:], p.atom_norm, y, lam, [1.0], tol=tol, keep_trace=False)
+            t["T_A"] += time.perf_counter() - t0
+            it["T_A"] += r.iters
+            t0 = time.perf_counter()
+            r = osc.fast_l1(st, p.atom_norm, y, lam, rc, tol=tol, keep_trace=False)
+            t["T_At"] += time.perf_counter() - t0
+            it["T_At"] += r.iters
+    n = len(signals)
+    return {"signals": list(signals), "threads": threads or blas_info()[1],
+            "time_to_gap_s_per_signal": {k: v / n for k, v in t.items()},
+            "iterations_per_signal": {k: v / n for k, v in it.items()},
+            "T_A_over_T_N": t["T_A"] / t["T_N"], "T_At_over_T_N": t["T_At"] / t["T_N"]}
+
+
+def cpu_baseline(np, p, ref, tol, signals=(0, 1, 2, 3)):
+    """The FP64 oracle (plain FISTA, exact A, no screening) to gap tol on a sample of
+    the workload's signals, timed on the host with all BLAS threads and with one, next
+    to the method reference's legs T_A and T_A~ (cpu_legs)."""
+    vendor, threads = blas_info()
+    legs_all = cpu_legs(np, p, ref, signals, tol)
+    legs_one = cpu_legs(np, p, ref, signals[:1], tol, threads=1)
+    per = legs_all["time_to_gap_s_per_signal"]["T_N"]
+    its = legs_all["iterations_per_signal"]["T_N"]
+    return dict(value=its / per, unit="iter/s", cores=threads, kind="oracle",
+                sample=f"FP64 FISTA without screening, exact A (N={p.N}, K={p.K}), to gap {tol:g}, signals "
+                       f"{list(signals)} of the workload: {its:.0f} iterations, {per * 1e3:.1f} ms per signal "
+                       f"({vendor} BLAS, {threads} threads)",
+                time_to_gap_ms_per_signal=per * 1e3, blas=vendor, legs_all_threads=legs_all,
+                legs_one_thread=legs_one)
 
 
 def main():
@@ -469,6 +604,7 @@ def main():
         "max_gap": res["max_gap_method"],
         "rc_measured": res["rc_measured"],
         "rc_model": res["rc_model"],
+        "kron_tiles_autotuned": res["kron_tiles"],
         "engine": res["engine"],
         "kernel_ms": res["kernel_ms"],
         "whole_solve_phases_ms": res["wg_phases"],
@@ -478,16 +614,28 @@ def main():
         "roofline": roofline(res),
         "roofline_kernels": res["roofline_kernels"],
     }
+    ref = None
+    if not args.no_parity or not args.no_cpu:
+        idx = None if args.parity_signals <= 0 else \
+            np.unique(np.linspace(0, p.batch - 1, min(args.parity_signals, p.batch)).astype(int)).tolist()
+        if args.no_parity:
+            idx = [0, 1, 2, 3]
+        log(f"batched: FP64 oracle on {p.batch if idx is None else len(idx)} signals")
+        ref = oracle_reference(p, idx, "batched")
     if not args.no_parity:
-        log("sampled parity against the FP64 oracle")
-        line["parity"] = parity_sample(np, p, res)
+        line["parity"] = block_parity(np, p, res, ref, args.tol)
     if not args.no_variants:
         log("update / test variants on the batched workload (1 timed solve each)")
-        line["variants"] = variants_block(sl1, torch, np, p, res["rc_measured"], args.tol, 1, 1,
-                                          plain_ref=(res["ms_plain"], res["iters_plain"]))
+        var = variants_block(sl1, torch, np, p, res["rc_measured"], args.tol, 1, 1,
+                             plain_ref=(res["ms_plain"], res["iters_plain"]), tiles=res["kron_tiles"])
+        for v in var:
+            if ref is not None and not args.no_parity:
+                v["oracle_error"] = oracle_errors(np, p, v["_x"], v["_screened"], ref)
+            del v["_x"], v["_screened"]
+        line["variants"] = var
     if not args.no_cpu:
-        log("CPU oracle baseline")
-        line["cpu_baseline"] = cpu_baseline(np, p, args.cpu_seconds)
+        log("CPU oracle baseline and the method reference's legs")
+        line["cpu_baseline"] = cpu_baseline(np, p, ref, args.tol)
     if not args.no_single:
         log("single-signal block (N=4096, K=16384, R=8, FP32)")
         q = synth.config2(lam_frac=0.5)
@@ -499,11 +647,14 @@ def main():
             "iters_per_s": r2["iters_method"] / (r2["ms_method"] * 1e-3),
             "plain_fp32_time_to_gap_ms": r2["ms_plain"], "plain_fp32_iters": r2["iters_plain"],
             "speedup_vs_plain_fp32": r2["ms_plain"] / r2["ms_method"],
-            "rc_measured": r2["rc_measured"], "engine": r2["engine"], "kernel_ms": r2["kernel_ms"],
+            "rc_measured": r2["rc_measured"], "kron_tiles_autotuned": r2["kron_tiles"], "engine": r2["engine"],
+            "kernel_ms": r2["kernel_ms"],
             "whole_solve_phases_ms": r2["wg_phases"], "roofline": roofline(r2),
             "roofline_kernels": r2["roofline_kernels"],
             "max_gap": r2["max_gap_method"],
         }
+        if not args.no_parity:
+            line["single_signal"]["parity"] = block_parity(np, q, r2, oracle_reference(q, None, "single"), args.tol)
     if not args.no_faust:
         log("FAuST block (MEG shape 204 x 8193, 50 signals)")
         q = synth.config6(batch=50)
@@ -519,6 +670,27 @@ def main():
             "rc_model": r3["rc_model"], "rc_measured": r3["rc_measured"], "engine": r3["engine"],
             "kernel_ms": r3["kernel_ms"], "max_gap": r3["max_gap_method"],
         }
+        if not args.no_parity:
+            line["faust_meg_shape"]["parity"] = block_parity(np, q, r3, oracle_reference(q, None, "faust"), args.tol)
+    if not args.no_dense:
+        log("dense precision block (N=2500, K=10000, 25 signals, FP8 -> BF16 -> FP32)")
+        q = synth.config3(batch=25)
+        r4 = solve_block(sl1, torch, np, q, args.tol, max(1, args.steps), args.warmup, "dense")
+        line["dense_precision"] = {
+            "workload": "dense A (2500 x 10000, i.i.d. N(0,1), unit columns, FP32 = exact); stages: FP8-E4M3 and "
+                        "BF16 copies with per-column power-of-two scales (exact error bounds), then A; 25 signals "
+                        "y = A x0 / ||A x0|| with 50-sparse x0, lambda = 0.5 lambda_max, tol 1e-6",
+            "time_to_gap_ms": r4["ms_method"], "iters": r4["iters_method"],
+            "iters_per_s": r4["iters_method"] / (r4["ms_method"] * 1e-3),
+            "plain_fp32_time_to_gap_ms": r4["ms_plain"], "plain_fp32_iters": r4["iters_plain"],
+            "speedup_vs_plain_fp32": r4["ms_plain"] / r4["ms_method"],
+            "rc_model": r4["rc_model"], "rc_measured": r4["rc_measured"], "engine": r4["engine"],
+            "kernel_ms": r4["kernel_ms"], "whole_solve_phases_ms": r4["wg_phases"],
+            "roofline": roofline(r4), "roofline_kernels": r4["roofline_kernels"], "max_gap": r4["max_gap_method"],
+        }
+        if not args.no_parity:
+            line["dense_precision"]["parity"] = block_parity(np, q, r4, oracle_reference(q, [0, 12, 24], "dense"),
+                                                             args.tol)
     print(json.dumps(line))
 
 

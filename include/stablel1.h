@@ -94,9 +94,13 @@ int sl1_dict_dense(sl1_dict* out, int dtype, int64_t N, int64_t K, const void* A
 /*
  * sl1_dict_kron -- a structured stage A~ = sum_{r<R} B_r kron C_r (the SuKro model
  * of Section V-A), N = n1*n2, K = k1*k2.
- *   dtype      SL1_F64, SL1_F32 or SL1_BF16 (factor storage).
+ *   dtype      SL1_F64, SL1_F32, SL1_BF16 or SL1_FP8_E4M3 (factor storage).  FP8
+ *              factors are decoded exactly to BF16 for the BF16 matrix-core products
+ *              (FP32 accumulation), so they carry the BF16 rounding allowance; stages
+ *              with FP8 factors run in the grid engine (SL1_ENGINE_WG refuses them
+ *              with SL1_ELIMIT; the automatic choice never picks it for them).
  *   B, C       R*n1*k1 and R*n2*k2 elements, device, layout in the header comment.
- *              Copied (the factors are small).
+ *              Copied (the factors are small).  A non-finite entry is SL1_EINVAL.
  *   eps, q     as for sl1_dict_dense (eps copied).
  * Errors: SL1_EINVAL, SL1_EDTYPE, SL1_ELIMIT, SL1_EHIP, SL1_ENOMEM.
  */
@@ -253,6 +257,10 @@ int sl1_opts_default(sl1_opts* o);
  *   screened   out (may be NULL), batch x K bytes: 1 = atom rejected by the test.
  *   iters      out (may be NULL), batch int32: iterations performed.
  *   stage      out (may be NULL), batch int32: index of the final stage.
+ * The stop test precedes the screening step of its iteration (Algorithm 1), so
+ * `screened` holds the atoms rejected before the stop.  For lambda >= lambda'_max of
+ * seq[0] the first test rejects every atom except near-ties; for lambda_max <= lambda <
+ * lambda'_max the solve returns x = 0 on A with the atoms rejected until then.
  * The call orders itself after prior work on `stream`, polls convergence and
  * returns once every signal has converged or reached max_iter; the outputs are
  * then complete.  Concurrent calls with identical shapes on one device are
@@ -311,6 +319,31 @@ int sl1_grad(sl1_dict A, int64_t batch, const double* x, const void* y, const do
  */
 int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_out,
                    void* stream);
+
+/*
+ * sl1_tune_kron -- the autotuner of the Kronecker correlation tile shape.  Every
+ * Kronecker stage of seq is timed with each usable item shape kt2 x kt1 (atoms j2 x j1
+ * per item, kt2, kt1 in {16, 32, 64, 128} dividing k2 and k1, at least two 16 x 16
+ * output tiles, the item's intermediate within 96 KB of LDS) on `batch` synthetic
+ * signals, and the fastest shape is recorded in the stage's handle; later solves,
+ * lambda and adjoint calls use it.  Other stages are left as they are.
+ *   shape_out  host, 2 n_stages int32 (may be NULL): (kt2, kt1) chosen per stage, 0 0
+ *              for stages that are not Kronecker sums.
+ *   ms_out     host, n_stages doubles (may be NULL): the chosen shape's launch time.
+ * The shape changes the order of the FP32 sums only (within the stage's rounding
+ * allowance).  A handle's shape is the one property that changes after creation: do
+ * not tune handles that a concurrent call is using.  Synchronous.
+ */
+int sl1_tune_kron(const sl1_dict* seq, int n_stages, int64_t batch, int32_t* shape_out, double* ms_out,
+                  void* stream);
+
+/*
+ * sl1_dict_kron_tile -- sets the correlation tile shape of a Kronecker stage by hand
+ * (kt2 x kt1 atoms per item, multiples of 16 dividing k2 and k1, the item's
+ * intermediate within 96 KB; the tuner's candidates are a subset).  SL1_EINVAL for
+ * another kind of stage or an unusable shape.  Same caveat as sl1_tune_kron.
+ */
+int sl1_dict_kron_tile(sl1_dict d, int kt2, int kt1);
 
 /*
  * sl1_last_solve_clock -- device wall-clock stamps of the most recent

@@ -57,6 +57,8 @@ SIGNATURES = [
     ("sl1_dict_adjoint", c_i32, [c_dict, c_i64, c_p, c_i32, c_p, c_p, c_p]),
     ("sl1_grad", c_i32, [c_dict, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p]),
     ("sl1_measure_rc", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, ctypes.POINTER(c_d), c_p]),
+    ("sl1_tune_kron", c_i32, [ctypes.POINTER(c_dict), c_i32, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_d), c_p]),
+    ("sl1_dict_kron_tile", c_i32, [c_dict, c_i32, c_i32]),
     ("sl1_last_solve_clock", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_d)]),
     ("sl1_last_solve_profile", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_d), ctypes.POINTER(ctypes.c_longlong)]),
     ("sl1_last_solve_phases", c_i32, [c_i64, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_d),

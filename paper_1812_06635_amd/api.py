@@ -102,6 +102,10 @@ class Dict:
                                         va.ctypes.data, _ptr(eps), float(q), _stream()), "sl1_dict_faust")
         return cls(h, None, int(dims[0]), int(dims[-1]), "faust", dtype)
 
+    def set_tile(self, kt2, kt1):
+        """Kronecker stage: correlation items of kt2 x kt1 atoms (sl1_dict_kron_tile)."""
+        L.check(L.load().sl1_dict_kron_tile(self.handle, int(kt2), int(kt1)), "sl1_dict_kron_tile")
+
     def info(self):
         N, K = L.c_i64(), L.c_i64()
         em, rc = L.c_d(), L.c_d()
@@ -266,6 +270,17 @@ def measure_rc(stages, batch=1):
     out = (L.c_d * n)()
     L.check(L.load().sl1_measure_rc(arr, n, batch, out, _stream()), "sl1_measure_rc")
     return [out[i] for i in range(n)]
+
+
+def tune_kron(stages, batch=1):
+    """Autotunes the correlation tile shape of every Kronecker stage for this batch size
+    (sl1_tune_kron); returns [(kt2, kt1) or None per stage] and the launch times (ms)."""
+    n = len(stages)
+    arr = (L.c_dict * n)(*[s.handle for s in stages])
+    shp = (L.c_i32 * (2 * n))()
+    ms = (L.c_d * n)()
+    L.check(L.load().sl1_tune_kron(arr, n, batch, shp, ms, _stream()), "sl1_tune_kron")
+    return [((shp[2 * i], shp[2 * i + 1]) if shp[2 * i] else None) for i in range(n)], [ms[i] for i in range(n)]
 
 
 def last_solve_clock(batch, N, K):

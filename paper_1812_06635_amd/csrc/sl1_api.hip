@@ -30,12 +30,14 @@ hipError_t launch_init_x0(const SolveParams*, int, const double*, hipStream_t);
 int upd_resident_blocks(size_t);
 hipError_t gemm_lds_attr(size_t);
 hipError_t fwd_lds_attr(size_t);
+hipError_t adjk_lds_attr(size_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
 hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_solve_tail(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_to_wg(const SolveParams*, int, hipStream_t);
+hipError_t launch_zero(void*, size_t, hipStream_t);
 }  // namespace sl1
 
 using namespace sl1;
@@ -44,6 +46,7 @@ struct sl1_dict_s {
     int kind = 0, dtype = 0, device = 0;
     int64_t N = 0, K = 0;
     int R = 0, n1 = 0, k1 = 0, n2 = 0, k2 = 0, vec = 4;
+    int kt2 = 16, kt1 = 16;    // Kronecker correlation tile shape (sl1_tune_kron may change it)
     const void* A = nullptr;   // borrowed (dense)
     float* scale = nullptr;    // owned
     void* B = nullptr;         // owned (kron)
@@ -92,6 +95,16 @@ double bf16_host(uint16_t b) {
     return (double)f;
 }
 
+// OCP FP8 E4M3FN code -> value (bias 7, subnormals m 2^-9, 0x7F / 0xFF are NaN)
+double fp8_host(uint8_t b) {
+    const int e = (b >> 3) & 15, m = b & 7;
+    double v;
+    if (e == 15 && m == 7) v = std::nan("");
+    else if (e == 0) v = std::ldexp((double)m, -9);
+    else v = std::ldexp(1.0 + m / 8.0, e - 7);
+    return (b & 0x80) ? -v : v;
+}
+
 // Bound on |computed - exact| of both products with a stage, per unit
 // ||abs-atom||_2 ||vector||_2 (standard gamma_n = n u accumulation bounds, doubled
 // to cover any order or internal precision of the matrix-core accumulation).
@@ -111,8 +124,9 @@ double rounding_allowance(const sl1_dict_s& d) {
     const double n1 = d.n1, n2 = d.n2, R = d.R;
     if (d.dtype == SL1_F64) return 2.0 * (n2 + R * n1 + R + K + 32.0) * kU64;
     if (d.dtype == SL1_F32) return 2.0 * (n2 + R * n1 + R + 10.0) * kU32 + 2.0 * (K + 24.0) * kU64;
-    // BF16: exact first product inputs, FP32 accumulation, hi/lo split of the
-    // intermediate (residual <= 2^-18, counted as 2^-16)
+    // BF16 (and FP8 factors, decoded exactly to BF16 for the same products): exact first
+    // product inputs, FP32 accumulation, hi/lo split of the intermediate (residual
+    // <= 2^-18, counted as 2^-16)
     return 2.0 * (n2 + 2.0 * R * n1 + R + 10.0) * kU32 + 1.52587890625e-05 + 2.0 * (K + 24.0) * kU64;
 }
 
@@ -146,7 +160,11 @@ struct Workspace {
     int last_engine = 0;
     std::vector<hipEvent_t> prof_ev;
     std::mutex mu;
+    // a view over memory this object does not own (device memory, host blocks and the
+    // stream belong to the caller); it records no graphs or events
+    bool borrowed = false;
     ~Workspace() {
+        if (borrowed) return;
         for (auto& g : graph)
             if (g) (void)hipGraphExecDestroy(g);
         if (mem) (void)hipFree(mem);
@@ -170,7 +188,9 @@ std::map<std::tuple<int, int, int, int>, std::shared_ptr<Workspace>> g_ws;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int make_workspace(Workspace& w) {
+// Byte layout of a workspace for (w.batch, w.N, w.K) in one device allocation; with
+// m != nullptr the solver's pointers into it are set in p and w.  Returns its size.
+size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     const size_t ws = 8;
     const size_t B = w.batch, K = w.K, N = w.N;
     w.nseg_max = (w.K + kSeg - 1) / kSeg;
@@ -202,12 +222,8 @@ int make_workspace(Workspace& w) {
     const size_t o_times = take(B * 16);
     const size_t o_wgprof = take(B * kWgPhases * 8);
     const size_t o_params = take(sizeof(SolveParams));
-    if (hipMalloc(&w.mem, off) != hipSuccess) return SL1_ENOMEM;
-    char* m = (char*)w.mem;
-    if (hipHostMalloc((void**)&w.hP, sizeof(SolveParams), hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
-    if (hipHostMalloc((void**)&w.h_active, 64, hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
-    std::memset(w.hP, 0, sizeof(SolveParams));
-    SolveParams& p = *w.hP;
+    if (!m) return off;
+    SolveParams& p = *pp;
     p.ctrl = (Control*)(m + o_ctrl);
     p.sc = (Scalars*)(m + o_sc);
     p.fin = (Final*)(m + o_fin);
@@ -241,14 +257,64 @@ int make_workspace(Workspace& w) {
     w.d_times = (long long*)(m + o_times);
     w.d_wgprof = (long long*)(m + o_wgprof);
     w.dP = (SolveParams*)(m + o_params);
+    return off;
+}
+
+int make_workspace(Workspace& w) {
+    const size_t bytes = workspace_layout(w, nullptr, nullptr);
+    if (hipMalloc(&w.mem, bytes) != hipSuccess) return SL1_ENOMEM;
+    if (hipHostMalloc((void**)&w.hP, sizeof(SolveParams), hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
+    if (hipHostMalloc((void**)&w.h_active, 64, hipHostMallocDefault) != hipSuccess) return SL1_ENOMEM;
+    std::memset(w.hP, 0, sizeof(SolveParams));
+    workspace_layout(w, (char*)w.mem, w.hP);
     if (hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) != hipSuccess) return SL1_EHIP;
     if (hipEventCreateWithFlags(&w.ev_in, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
     if (hipEventCreateWithFlags(&w.ev_out, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
     if (hipEventCreate(&w.ev_a) != hipSuccess) return SL1_EHIP;
     if (hipEventCreate(&w.ev_b) != hipSuccess) return SL1_EHIP;
-    if (hipMemsetAsync(w.mem, 0, off, w.stream) != hipSuccess) return SL1_EHIP;
+    if (hipMemsetAsync(w.mem, 0, bytes, w.stream) != hipSuccess) return SL1_EHIP;
     if (hipStreamSynchronize(w.stream) != hipSuccess) return SL1_EHIP;
     return SL1_OK;
+}
+
+// Orders the library stream after the caller's stream (a workspace on the
+// caller's own stream needs nothing), and back.
+int order_after(Workspace* w, hipStream_t us) {
+    if (w->ev_in) {
+        HIP_TRY(hipEventRecord(w->ev_in, us));
+        HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    }
+    return SL1_OK;
+}
+int order_before(Workspace* w, hipStream_t us) {
+    if (w->ev_out) {
+        HIP_TRY(hipEventRecord(w->ev_out, w->stream));
+        HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
+    }
+    return SL1_OK;
+}
+
+// Clears n bytes of workspace memory: hipMemsetAsync on the library's own stream,
+// a fill kernel on a borrowed workspace (which runs on the caller's stream).
+hipError_t clear_ws(Workspace* w, void* p, size_t n) {
+    return w->borrowed ? launch_zero(p, n, w->stream) : hipMemsetAsync(p, 0, n, w->stream);
+}
+
+// Every per-signal status of the last finalisation or lambda pass, read in fixed-size
+// pieces: the most negative one (an error) or SL1_MAXITER if any signal stopped at the cap.
+int read_statuses(Workspace* w, int64_t batch) {
+    int32_t hs[256];
+    int result = SL1_OK;
+    for (int64_t b0 = 0; b0 < batch; b0 += 256) {
+        const int64_t n = std::min<int64_t>(256, batch - b0);
+        HIP_TRY(hipMemcpyAsync(hs, w->d_status + b0, n * 4, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        for (int64_t i = 0; i < n; ++i) {
+            if (hs[i] < 0) return hs[i];
+            if (hs[i] == SL1_MAXITER) result = SL1_MAXITER;
+        }
+    }
+    return result;
 }
 
 int get_workspace(int device, int batch, int N, int K, std::shared_ptr<Workspace>* out) {
@@ -287,6 +353,8 @@ void fill_stage(StageDesc& s, const sl1_dict_s& d, double L, double rc) {
     s.k1 = d.k1;
     s.n2 = d.n2;
     s.k2 = d.k2;
+    s.kt2 = d.kt2;
+    s.kt1 = d.kt1;
     s.vec = d.vec;
     s.A = d.A;
     s.scale = d.scale;
@@ -306,6 +374,35 @@ void fill_stage(StageDesc& s, const sl1_dict_s& d, double L, double rc) {
     s.qmode = d.q == 2.0 ? 0 : (d.q == 1.0 ? 2 : (std::isinf(d.q) ? 3 : 1));
     s.qd = d.q == 1.0 ? INFINITY : (std::isinf(d.q) ? 1.0 : d.q / (d.q - 1.0));
     s.cq = d.q > 2.0 ? std::pow((double)d.N, std::isinf(d.q) ? 0.5 : 0.5 - 1.0 / d.q) : 1.0;
+}
+
+// Bytes of the V region of a Kronecker correlation item: R terms x kt2 rows x n1
+// (FP64 for FP64 factors; FP32, or a BF16 hi + lo pair, otherwise).
+size_t kron_v_bytes(int dtype, int R, int kt2, int n1) {
+    return (size_t)R * kt2 * n1 * (dtype == SL1_F64 ? 8 : 4);
+}
+
+// A tile shape (kt2 x kt1 atoms per item) is usable when it divides the atom grid and
+// its V region fits.
+bool kron_shape_ok(const sl1_dict_s& d, int kt2, int kt1) {
+    return kt2 >= 16 && kt1 >= 16 && kt2 % 16 == 0 && kt1 % 16 == 0 && d.k2 % kt2 == 0 && d.k1 % kt1 == 0 &&
+           kron_v_bytes(d.dtype, d.R, kt2, d.n1) <= (size_t)kKronVLds;
+}
+
+// Shape before any tuning: items of at least 4 output tiles (one per wave) where the
+// grid allows, 64 columns j1 at most.
+void kron_default_shape(sl1_dict_s& d) {
+    int kt1 = 16;
+    for (int c : {64, 32, 16})
+        if (d.k1 % c == 0) { kt1 = c; break; }
+    int kt2 = 16;
+    for (int r = 16; r <= d.k2; r += 16)
+        if (d.k2 % r == 0 && kron_shape_ok(d, r, kt1)) {
+            kt2 = r;
+            if (r * kt1 >= 1024) break;
+        }
+    d.kt2 = kt2;
+    d.kt1 = kt1;
 }
 
 LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
@@ -334,11 +431,8 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
             extra = std::max(extra, 2 * (size_t)s.fa_maxd * 8);
             continue;
         }
-        kron_items = std::max(kron_items, (s.k2 / 16) * ((s.k1 + kKronColTile - 1) / kKronColTile));
-        size_t need;
-        if (s.dtype == SL1_F64) need = 4 * 16 * (size_t)p.n1_max * 8 + 4 * 16 * 64 * 8;
-        else need = 4 * 16 * 64 * 4 + 4 * 16 * (size_t)p.n1_max * 4;
-        extra = std::max(extra, need);
+        kron_items = std::max(kron_items, (s.k2 / s.kt2) * (s.k1 / s.kt1));
+        extra = std::max(extra, kron_v_bytes(s.dtype, s.R, s.kt2, s.n1));
     }
     c.g_fwd = (int)std::min<long long>((long long)w.batch * w.nrc, 512);
     c.dome = p.rule == 2 ? 1 : 0;
@@ -374,7 +468,7 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
 // product, which forms all K correlations: at least K/8 preserved atoms and 4a per
 // 64-atom tile (a = atoms per wave of the streaming kernel).
 int gemm_min_atoms(const SolveParams& p) {
-    const int per = 4 * (p.N <= 1024 ? 2 : 1);
+    const int per = 4 * (p.N <= 1024 ? 2 : 1);     // the documented gate, independent of the stream kernel's width
     return std::max(per * ((p.K + kGemmAtoms - 1) / kGemmAtoms), std::max(1, p.K / 8));
 }
 
@@ -451,6 +545,7 @@ size_t wg_layout(SolveParams& p, bool tail, int max_act, bool gram) {
         if (s.kind == kFaust) return 0;         // FAuST stages run in the grid kernels only
         if (s.qmode != 0) return 0;             // so do stages with l_q bounds, q != 2
         if (s.kind != kKron) continue;
+        if (s.dtype == SL1_FP8_E4M3) return 0;  // and Kronecker stages with FP8 factors
         const size_t es = s.dtype == SL1_F64 ? 8 : (s.dtype == SL1_F32 ? 4 : 2);
         fac = std::max(fac, a16(((size_t)s.R * s.k1 * s.n1 + (size_t)s.R * s.k2 * s.n2) * es));
         const size_t v = (size_t)s.R * s.k2 * s.n1 * (s.dtype == SL1_F64 ? 8 : 4);   // BF16: hi + lo
@@ -512,7 +607,7 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
         if (d->kind == kKron) {
             n1_max = std::max(n1_max, d->n1);
             // the forward kernel stages a Kronecker stage's factors in LDS when they fit
-            const size_t es = d->dtype == SL1_F64 ? 8 : (d->dtype == SL1_F32 ? 4 : 2);
+            const size_t es = dtype_size(d->dtype);
             const size_t fb = (size_t)d->R * ((size_t)d->n1 * d->k1 + (size_t)d->n2 * d->k2) * es;
             if (fb <= (size_t)kFwdFacLds) fac = std::max(fac, fb);
         }
@@ -612,16 +707,10 @@ int capture_chunk(Workspace* w, const LaunchCfg& ccfg, int chunk, int v) {
 int finish_solve(Workspace* w, const LaunchCfg& cfg, int64_t batch, double* x, double* gap, double* gap_cert,
                  uint8_t* screened, int32_t* iters, int32_t* stage, hipStream_t us) {
     HIP_TRY(launch_finalize(w->dP, cfg, x, gap, gap_cert, screened, iters, stage, w->d_status, w->stream));
-    std::vector<int32_t> hs(batch);
-    HIP_TRY(hipMemcpyAsync(hs.data(), w->d_status, batch * 4, hipMemcpyDeviceToHost, w->stream));
-    HIP_TRY(hipStreamSynchronize(w->stream));
-    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
-    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
-    int result = SL1_OK;
-    for (int32_t v : hs) {
-        if (v < 0) return v;
-        if (v == SL1_MAXITER) result = SL1_MAXITER;
-    }
+    int result = read_statuses(w, batch);
+    const int ord = order_before(w, us);
+    if (result < 0) return result;
+    if (ord != SL1_OK) return ord;
     if (*w->h_active > 0) result = SL1_MAXITER;
     return result;
 }
@@ -760,7 +849,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     if (!out) return SL1_EINVAL;
     *out = nullptr;
     if (!B || !C || !eps || R < 1 || n1 < 1 || k1 < 1 || n2 < 1 || k2 < 1 || !valid_bound_norm(q)) return SL1_EINVAL;
-    if (dtype != SL1_F64 && dtype != SL1_F32 && dtype != SL1_BF16) return SL1_EDTYPE;
+    if (dtype != SL1_F64 && dtype != SL1_F32 && dtype != SL1_BF16 && dtype != SL1_FP8_E4M3) return SL1_EDTYPE;
     if (n1 % 16 || k1 % 16 || n2 % 16 || k2 % 16) return SL1_ELIMIT;
     const int64_t N = (int64_t)n1 * n2, K = (int64_t)k1 * k2;
     if (N > kMaxN || n1 > (dtype == SL1_F64 ? 128 : 256) || K > (int64_t)kMaxSeg * kSeg) return SL1_ELIMIT;
@@ -777,6 +866,7 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     d->k1 = k1;
     d->n2 = n2;
     d->k2 = k2;
+    kron_default_shape(*d);
     int st = finish_dict_host_eps(d.get(), eps, s);
     if (st != SL1_OK) return st;
     const size_t es = dtype_size(dtype);
@@ -796,8 +886,14 @@ int sl1_dict_kron(sl1_dict* out, int dtype, int R, int n1, int k1, int n2, int k
     auto val = [&](const std::vector<unsigned char>& v, size_t i) -> double {
         if (dtype == SL1_F64) return ((const double*)v.data())[i];
         if (dtype == SL1_F32) return (double)((const float*)v.data())[i];
+        if (dtype == SL1_FP8_E4M3) return fp8_host(v[i]);
         return bf16_host(((const uint16_t*)v.data())[i]);
     };
+    // non-finite factor entries make every product meaningless
+    for (size_t i = 0; i < nb; ++i)
+        if (!std::isfinite(val(hb, i))) { sl1_dict_free(d.release()); return SL1_EINVAL; }
+    for (size_t i = 0; i < nc; ++i)
+        if (!std::isfinite(val(hc, i))) { sl1_dict_free(d.release()); return SL1_EINVAL; }
     // GB[j1][r][r'] = sum_i1 B_r[i1,j1] B_r'[i1,j1] (signed and absolute)
     std::vector<double> GB((size_t)k1 * R * R), GBa((size_t)k1 * R * R), GC((size_t)k2 * R * R), GCa((size_t)k2 * R * R);
     for (int j1 = 0; j1 < k1; ++j1)
@@ -1065,6 +1161,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     int st = prepare(seq, 1, &L, nullptr, y_dtype, tmp);
     if (st != SL1_OK) return st;
     if (!w->d_cy) {
+        if (w->borrowed) return SL1_ENOMEM;   // laid out by the caller of a borrowed workspace
         if (hipMalloc(&w->d_cy, (size_t)batch * tmp.K * sizeof(double)) != hipSuccess) return SL1_ENOMEM;
         if (hipMalloc(&w->d_yy, (size_t)batch * sizeof(double)) != hipSuccess) return SL1_ENOMEM;
     }
@@ -1096,10 +1193,10 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     st = check_lds(cfg);
     if (st != SL1_OK) return st;
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
-    HIP_TRY(hipEventRecord(w->ev_in, us));
-    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
+    if ((st = order_after(w, us)) != SL1_OK) return st;
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+    HIP_TRY(clear_ws(w, w->d_active, 4));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
     HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));
     HIP_TRY(launch_adjoint_out(w->dP, (int)batch, tmp.K, tmp.N, w->d_cy, nullptr, w->stream));
@@ -1108,33 +1205,33 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     return SL1_OK;
 }
 
-int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc, const double* atom_norm,
-              int64_t batch, const void* y, const double* lambda, const sl1_opts* opt, double* x, double* gap,
-              double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage, void* stream) {
-    sl1_opts o;
-    if (opt) o = *opt;
-    else sl1_opts_default(&o);
+// Argument checks shared by both solve entry points (host, synchronous); fills the
+// stage descriptors into tmp and the device into *dev.
+static int solve_checks(const sl1_dict* seq, int n_stages, const double* L, const double* rc, const double* atom_norm,
+                 int64_t batch, const void* y, const double* lambda, const sl1_opts& o, double* x, double* gap,
+                 SolveParams& tmp, int* dev) {
     if (!atom_norm || !y || !lambda || !x || !gap || batch < 1) return SL1_EINVAL;
     if (batch > kMaxBatch) return SL1_ELIMIT;
     if (o.max_iter < 0 || !(o.tol >= 0.0) || !std::isfinite(o.Gamma) || !(o.margin >= 0.0)) return SL1_EINVAL;
     if (o.trace && o.trace_cap < 0) return SL1_EINVAL;
     if (o.screen_every < 0 || o.gemm_signals < 0) return SL1_EINVAL;
-    SolveParams tmp;
+    if ((o.flags & SL1_FLAG_RULE_DST) && (o.flags & SL1_FLAG_RULE_DOME)) return SL1_EINVAL;
     std::memset(&tmp, 0, sizeof(tmp));
     int st = prepare(seq, n_stages, L, rc, o.y_dtype, tmp);
     if (st != SL1_OK) return st;
     if (seq[n_stages - 1]->eps_max_in != 0.0) return SL1_EINVAL;   // the last stage must be A
-    int dev = 0;
-    if (current_device(&dev) != SL1_OK) return SL1_EHIP;
-    if (dev != seq[0]->device) return SL1_EINVAL;
-    std::shared_ptr<Workspace> ws;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &ws);
-    if (st != SL1_OK) return st;
-    Workspace* w = ws.get();
-    std::lock_guard<std::mutex> lk(w->mu);
+    if (current_device(dev) != SL1_OK) return SL1_EHIP;
+    if (*dev != seq[0]->device) return SL1_EINVAL;
+    return SL1_OK;
+}
+
+// Algorithm 1 on workspace w (held and locked by the caller); tmp and dev from solve_checks.
+static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const double* atom_norm, int64_t batch,
+               const void* y, const double* lambda, const sl1_opts& o, const SolveParams& tmp, int dev, double* x,
+               double* gap, double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage, void* stream) {
+    int st = SL1_OK;
     const bool dst = (o.flags & SL1_FLAG_RULE_DST) != 0;
     const bool dome = (o.flags & SL1_FLAG_RULE_DOME) != 0;
-    if (dst && dome) return SL1_EINVAL;
     if (dst || dome) {
         // a^T y is formed with the exact dictionary's dense correlation kernel
         if (seq[n_stages - 1]->kind != kDense) return SL1_ELIMIT;
@@ -1201,6 +1298,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     if (o.flags & SL1_FLAG_NO_GEMM) cfg.g_gemm = 0;
     if (cfg.g_gemm > 0) HIP_TRY(gemm_lds_attr(cfg.lds_gemm));
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
+    if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
     p.gemm_min = cfg.g_gemm > 0 ? gemm_min_atoms(p) : 0;
     const int gemm_signals = o.gemm_signals > 0 ? o.gemm_signals : kGemmMinSignals;
     p.gemm_on = p.gemm_min > 0 && batch >= gemm_signals;
@@ -1208,10 +1306,9 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     w->last_engine = use_wg ? SL1_ENGINE_WG : SL1_ENGINE_GRID;
     w->last_gram_cap = 0;
     hipStream_t us = (hipStream_t)stream;
-    HIP_TRY(hipEventRecord(w->ev_in, us));
-    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
+    if ((st = order_after(w, us)) != SL1_OK) return st;
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipMemsetAsync(w->d_active, 0, 48, w->stream));
+    HIP_TRY(clear_ws(w, w->d_active, 48));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));
     if (o.x0) HIP_TRY(launch_init_x0(w->dP, (int)batch, o.x0, w->stream));
     if (prof) {
@@ -1324,6 +1421,25 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
 }
 
+int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* rc, const double* atom_norm,
+              int64_t batch, const void* y, const double* lambda, const sl1_opts* opt, double* x, double* gap,
+              double* gap_cert, uint8_t* screened, int32_t* iters, int32_t* stage, void* stream) {
+    sl1_opts o;
+    if (opt) o = *opt;
+    else sl1_opts_default(&o);
+    SolveParams tmp;
+    int dev = 0;
+    int st = solve_checks(seq, n_stages, L, rc, atom_norm, batch, y, lambda, o, x, gap, tmp, &dev);
+    if (st != SL1_OK) return st;
+    std::shared_ptr<Workspace> ws;
+    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &ws);
+    if (st != SL1_OK) return st;
+    Workspace* w = ws.get();
+    std::lock_guard<std::mutex> lk(w->mu);
+    return solve_impl(w, seq, n_stages, atom_norm, batch, y, lambda, o, tmp, dev, x, gap, gap_cert, screened, iters,
+                      stage, stream);
+}
+
 static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* lam_out, double* g_out,
                        double* z_out, void* stream) {
     if (!d || !y || batch < 1) return SL1_EINVAL;
@@ -1370,6 +1486,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     st = check_lds(cfg);
     if (st != SL1_OK) return st;
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
+    if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
@@ -1402,79 +1519,157 @@ int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int y_dtype, doub
     return lambda_pass(d, batch, y, y_dtype, nullptr, out, z_used, stream);
 }
 
-int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_out, void* stream) {
-    if (!seq || n_stages < 1 || !rc_out || batch < 1) return SL1_EINVAL;
+// Device time of one correlation launch with stage descriptor sd over the whole atom
+// set, for batch signals y = ybuf (the caller holds w->mu; launches on w->stream).
+static int time_adj(Workspace* w, const SolveParams& tmp, const StageDesc& sd, int64_t batch, const void* ybuf,
+                    int reps, double* ms_out) {
+    SolveParams& p = *w->hP;
+    std::memcpy(p.st, tmp.st, sizeof(tmp.st));
+    p.st[0] = sd;
+    p.n_stages = 1;
+    p.N = tmp.N;
+    p.K = tmp.K;
+    p.batch = (int)batch;
+    p.y_f64 = tmp.y_f64;
+    p.n1_max = tmp.n1_max;
+    p.fwd_fac_lds = tmp.fwd_fac_lds;
+    p.max_iter = 0;
+    p.trace = nullptr;
+    p.trace_cap = 0;
+    p.lambda_only = 1;
+    p.ista = p.rule = 0;
+    p.screen_every = 1;
+    p.cy = p.yy = nullptr;
+    p.gemm_min = 0;
+    p.wg_prof = nullptr;
+    p.tol = 0.0;
+    p.margin = 0.0;
+    p.atom_norm = sd.at_norm;
+    p.y = ybuf;
+    p.lam = nullptr;
+    LaunchCfg cfg = launch_cfg(*w, p);
+    int st = check_lds(cfg);
+    if (st != SL1_OK) return st;
+    if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
+    if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
+    HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
+    HIP_TRY(launch_init(w->dP, cfg, w->stream));
+    HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));
+    for (int k = 0; k < 3; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, w->stream));
+    HIP_TRY(hipEventRecord(w->ev_a, w->stream));
+    for (int k = 0; k < reps; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, w->stream));
+    HIP_TRY(hipEventRecord(w->ev_b, w->stream));
+    HIP_TRY(hipEventSynchronize(w->ev_b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
+    *ms_out = ms / reps;
+    return SL1_OK;
+}
+
+// Shared set-up of the timing calls: stage descriptors, the workspace, synthetic signals
+// y = 1 (the cost of a correlation launch over every atom does not depend on y).
+struct TimingSetup {
+    SolveParams tmp;
+    std::shared_ptr<Workspace> ws;
+    void* ybuf = nullptr;
+    ~TimingSetup() {
+        if (ybuf) (void)hipFree(ybuf);
+    }
+};
+
+static int timing_setup(const sl1_dict* seq, int n_stages, int64_t batch, TimingSetup& T) {
+    if (!seq || n_stages < 1 || batch < 1) return SL1_EINVAL;
     if (batch > kMaxBatch) return SL1_ELIMIT;
     std::vector<double> Ls(n_stages, 1.0);
-    SolveParams tmp;
-    std::memset(&tmp, 0, sizeof(tmp));
-    int st = prepare(seq, n_stages, Ls.data(), nullptr, SL1_F64, tmp);
+    std::memset(&T.tmp, 0, sizeof(T.tmp));
+    int st = prepare(seq, n_stages, Ls.data(), nullptr, SL1_F64, T.tmp);
     if (st != SL1_OK) return st;
     int dev = 0;
     if (current_device(&dev) != SL1_OK) return SL1_EHIP;
-    std::shared_ptr<Workspace> ws;
-    st = get_workspace(dev, (int)batch, tmp.N, tmp.K, &ws);
+    st = get_workspace(dev, (int)batch, T.tmp.N, T.tmp.K, &T.ws);
     if (st != SL1_OK) return st;
-    Workspace* w = ws.get();
-    std::lock_guard<std::mutex> lk(w->mu);
-    // synthetic signals: y = 1 (any direction works, the cost does not depend on it)
-    void* ybuf = nullptr;
-    if (hipMalloc(&ybuf, (size_t)batch * tmp.N * 8) != hipSuccess) return SL1_ENOMEM;
-    std::vector<double> hy((size_t)batch * tmp.N, 1.0);
-    std::vector<double> times(n_stages, 0.0);
-    hipStream_t us = (hipStream_t)stream;
-    HIP_TRY(hipEventRecord(w->ev_in, us));
-    HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
-    HIP_TRY(hipMemcpyAsync(ybuf, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, w->stream));
-    const int reps = 20;
-    for (int i = 0; i < n_stages; ++i) {
-        SolveParams& p = *w->hP;
-        std::memcpy(p.st, tmp.st, sizeof(tmp.st));
-        p.st[0] = tmp.st[i];
-        p.n_stages = 1;
-        p.N = tmp.N;
-        p.K = tmp.K;
-        p.batch = (int)batch;
-        p.y_f64 = tmp.y_f64;
-        p.n1_max = tmp.n1_max;
-        p.fwd_fac_lds = tmp.fwd_fac_lds;
-        p.max_iter = 0;
-        p.trace = nullptr;
-        p.trace_cap = 0;
-        p.lambda_only = 1;
-        p.ista = p.rule = 0;
-        p.screen_every = 1;
-        p.cy = p.yy = nullptr;
-        p.gemm_min = 0;
-        p.wg_prof = nullptr;
-        p.tol = 0.0;
-        p.margin = 0.0;
-        p.atom_norm = tmp.st[i].at_norm;
-        p.y = ybuf;
-        p.lam = nullptr;
-        LaunchCfg cfg = launch_cfg(*w, p);
-        if ((st = check_lds(cfg)) != SL1_OK) { (void)hipFree(ybuf); return st; }
-        if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
-        HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
-        HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
-        HIP_TRY(launch_init(w->dP, cfg, w->stream));
-        HIP_TRY(launch_fwd_adj(w->dP, cfg, w->stream));
-        for (int k = 0; k < 3; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, w->stream));
-        HIP_TRY(hipEventRecord(w->ev_a, w->stream));
-        for (int k = 0; k < reps; ++k) HIP_TRY(launch_adj_only(w->dP, cfg, w->stream));
-        HIP_TRY(hipEventRecord(w->ev_b, w->stream));
-        HIP_TRY(hipEventSynchronize(w->ev_b));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
-        times[i] = ms / reps;
-    }
+    if (hipMalloc(&T.ybuf, (size_t)batch * T.tmp.N * 8) != hipSuccess) return SL1_ENOMEM;
+    return SL1_OK;
+}
+
+static int timing_fill_y(Workspace* w, TimingSetup& T, int64_t batch, hipStream_t us) {
+    std::vector<double> hy((size_t)batch * T.tmp.N, 1.0);
+    if ((order_after(w, us)) != SL1_OK) return SL1_EHIP;
+    HIP_TRY(hipMemcpyAsync(T.ybuf, hy.data(), hy.size() * 8, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
-    (void)hipFree(ybuf);
-    HIP_TRY(hipEventRecord(w->ev_out, w->stream));
-    HIP_TRY(hipStreamWaitEvent(us, w->ev_out, 0));
+    return SL1_OK;
+}
+
+int sl1_measure_rc(const sl1_dict* seq, int n_stages, int64_t batch, double* rc_out, void* stream) {
+    if (!rc_out) return SL1_EINVAL;
+    TimingSetup T;
+    int st = timing_setup(seq, n_stages, batch, T);
+    if (st != SL1_OK) return st;
+    Workspace* w = T.ws.get();
+    std::lock_guard<std::mutex> lk(w->mu);
+    hipStream_t us = (hipStream_t)stream;
+    if ((st = timing_fill_y(w, T, batch, us)) != SL1_OK) return st;
+    std::vector<double> times(n_stages, 0.0);
+    for (int i = 0; i < n_stages; ++i)
+        if ((st = time_adj(w, T.tmp, T.tmp.st[i], batch, T.ybuf, 20, &times[i])) != SL1_OK) return st;
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if ((st = order_before(w, us)) != SL1_OK) return st;
     const double ref = times[n_stages - 1];
     for (int i = 0; i < n_stages; ++i) rc_out[i] = ref > 0 ? times[i] / ref : 1.0;
     return SL1_OK;
+}
+
+int sl1_dict_kron_tile(sl1_dict d, int kt2, int kt1) {
+    if (!d || d->kind != kKron || !kron_shape_ok(*d, kt2, kt1)) return SL1_EINVAL;
+    d->kt2 = kt2;
+    d->kt1 = kt1;
+    return SL1_OK;
+}
+
+int sl1_tune_kron(const sl1_dict* seq, int n_stages, int64_t batch, int32_t* shape_out, double* ms_out,
+                  void* stream) {
+    TimingSetup T;
+    int st = timing_setup(seq, n_stages, batch, T);
+    if (st != SL1_OK) return st;
+    Workspace* w = T.ws.get();
+    std::lock_guard<std::mutex> lk(w->mu);
+    hipStream_t us = (hipStream_t)stream;
+    if ((st = timing_fill_y(w, T, batch, us)) != SL1_OK) return st;
+    static const int kCand[] = {16, 32, 64, 128};
+    for (int i = 0; i < n_stages; ++i) {
+        sl1_dict_s& d = *seq[i];
+        if (shape_out) shape_out[2 * i] = shape_out[2 * i + 1] = 0;
+        if (ms_out) ms_out[i] = 0.0;
+        if (d.kind != kKron) continue;
+        int best2 = d.kt2, best1 = d.kt1;
+        double best = -1.0;
+        for (int kt2 : kCand)
+            for (int kt1 : kCand) {
+                if (!kron_shape_ok(d, kt2, kt1) || kt2 * kt1 < 512) continue;
+                StageDesc sd = T.tmp.st[i];
+                sd.kt2 = kt2;
+                sd.kt1 = kt1;
+                double ms = 0.0;
+                st = time_adj(w, T.tmp, sd, batch, T.ybuf, 20, &ms);
+                if (st == SL1_ELIMIT) continue;            // the launch's LDS does not fit
+                if (st != SL1_OK) return st;
+                if (best < 0.0 || ms < best) {
+                    best = ms;
+                    best2 = kt2;
+                    best1 = kt1;
+                }
+            }
+        d.kt2 = best2;
+        d.kt1 = best1;
+        if (shape_out) {
+            shape_out[2 * i] = best2;
+            shape_out[2 * i + 1] = best1;
+        }
+        if (ms_out) ms_out[i] = best;
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return order_before(w, us);
 }
 
 // Device clock stamps (start, convergence) of each signal of the last solve of

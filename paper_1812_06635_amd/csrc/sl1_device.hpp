@@ -180,7 +180,6 @@ __device__ __forceinline__ int switch_dictionary(int i, int I, double gamma, dou
 
 // dense correlation items: atoms per wave (a wave then has 8 column loads in
 // flight per pass at N <= 1024 and N <= 2048)
-__device__ __forceinline__ int dense_apw(int N) { return N <= 1024 ? 2 : 1; }
 
 // forward product: adds x_j a~_j[r0..r0+3] (4 rows per lane); a Kronecker atom
 // is generated from its factors, sum_r B_r[i1, j1] C_r[i2, j2] in storage precision
@@ -301,7 +300,7 @@ __device__ __forceinline__ void raw_get(const Raw4<DT>& r, double (&v)[4]) {
 // NA atoms before the first product (loads past N are clamped to a valid
 // address and discarded).  Per lane the products are accumulated in increasing k.
 template <int DT, int NA>
-constexpr int dense_nk() { return (DT == SL1_F64 ? 4 : 8) / NA > 0 ? (DT == SL1_F64 ? 4 : 8) / NA : 1; }
+constexpr int dense_nk() { return NA >= 4 ? 1 : ((DT == SL1_F64 ? 4 : 8) / NA > 0 ? (DT == SL1_F64 ? 4 : 8) / NA : 1); }
 
 template <int DT, int NA, int NK = dense_nk<DT, NA>()>
 __device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const int (&js)[NA], const double* zs,

@@ -17,7 +17,7 @@ constexpr int kFwdFacLds = 48 * 1024;   // largest Kronecker factor set staged i
 constexpr int kFwdFacNnz = 32;          // nonzeros from which a block stages the factors
 constexpr int kFwdWaves = kFwdBlock / 64;
 constexpr int kMaxSeg = 1024;       // segments of a compacted list (K <= 262144)
-constexpr int kKronColTile = 64;    // atoms (j1) per Kronecker-adjoint block (16 per wave)
+constexpr int kKronVLds = 96 * 1024; // largest V region (the item's intermediate) of a Kronecker tile shape
 constexpr int kMaxN = 8192;
 constexpr int kWgBlock = 512;       // whole-solve engine: one 8-wave workgroup per signal
 constexpr int kWgWaves = kWgBlock / 64;
@@ -52,6 +52,7 @@ struct FaustDesc {
 struct StageDesc {
     int kind, dtype;
     int R, n1, k1, n2, k2;
+    int kt2, kt1;             // Kronecker correlation item: kt2 x kt1 atoms (j2 x j1), multiples of 16
     int vec;                  // dense: elements per lane per load (4, 8 or 16)
     const void* A;            // dense storage
     const float* scale;       // dense per-column scale or nullptr
@@ -191,6 +192,15 @@ constexpr int kGemmSplitUnits = 512; // partial tiles of one split launch at mos
 constexpr int kGemmMinSignals = SL1_GEMM_MIN_SIGNALS;   // fewer qualifying signals: streaming is faster
 
 constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS
+
+// atoms per wave of the streaming correlation kernel: 4, 2 or 1 so that a wave keeps
+// about 2.5-6 KB of columns in flight (4 atoms of up to 3 KB, 2 of up to 6 KB, else 1)
+__host__ __device__ __forceinline__ int dense_apw(int N, int dtype) {
+    const int es = dtype == SL1_F64 ? 8 : (dtype == SL1_F32 ? 4 : (dtype == SL1_BF16 ? 2 : 1));
+    const int cb = N * es;
+    return cb <= 3072 ? 4 : (cb <= 6144 ? 2 : 1);
+}
+
 
 // Rejections that zero a nonzero coefficient of x_t are counted in the same FP64
 // sum as the look-ahead count K_t, scaled by 2^20 > K (the two stay separable):

@@ -134,11 +134,11 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
 
 __device__ __forceinline__ int adj_items(const StageDesc& st, int n_act, int N) {
     if (st.kind == kDense) {
-        const int per = 4 * dense_apw(N);
+        const int per = 4 * dense_apw(N, st.dtype);
         return max(1, (n_act + per - 1) / per);
     }
     if (st.kind == kFaust) return st.fa_items;
-    return (st.k2 / 16) * ((st.k1 + kKronColTile - 1) / kKronColTile);
+    return (st.k2 / st.kt2) * (st.k1 / st.kt1);
 }
 
 // C_t from C_{t-1}, the scalars of iteration t-1 and the update launch's
@@ -306,6 +306,14 @@ __device__ __forceinline__ void fwd_kron_gather(const StageDesc& st, const void*
                         bv = ((const float*)Bsrc)[((size_t)r * k1d + j1[g]) * n1 + i1];
                         const f32v4 c = *(const f32v4*)((const float*)Csrc + ((size_t)r * k2 + j2[g]) * n2 + i2);
                         cv[0] = c[0]; cv[1] = c[1]; cv[2] = c[2]; cv[3] = c[3];
+                    } else if constexpr (DT == SL1_FP8_E4M3) {
+                        // four consecutive rows i2 .. i2+3 of C_r (i2 % 4 == 0: one aligned word)
+                        const uint32_t bq = ((const uint8_t*)Bsrc)[((size_t)r * k1d + j1[g]) * n1 + i1];
+                        bv = __builtin_amdgcn_cvt_pk_f32_fp8((int)bq, false)[0];
+                        const uint32_t cq = *(const uint32_t*)((const uint8_t*)Csrc + ((size_t)r * k2 + j2[g]) * n2 + i2);
+                        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)cq, false);
+                        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)cq, true);
+                        cv[0] = lo[0]; cv[1] = lo[1]; cv[2] = hi[0]; cv[3] = hi[1];
                     } else {
                         bv = bf16_to_f(((const uint16_t*)Bsrc)[((size_t)r * k1d + j1[g]) * n1 + i1]);
                         const u16x4 c = *(const u16x4*)((const uint16_t*)Csrc + ((size_t)r * k2 + j2[g]) * n2 + i2);
@@ -589,7 +597,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
         const void* Bsrc = st.B;
         const void* Csrc = st.C;
         if (kron && nnz >= kFwdFacNnz) {
-            const int es = st.dtype == SL1_F64 ? 8 : (st.dtype == SL1_F32 ? 4 : 2);
+            const int es = st.dtype == SL1_F64 ? 8 : (st.dtype == SL1_F32 ? 4 : (st.dtype == SL1_BF16 ? 2 : 1));
             const size_t bb = (size_t)st.R * st.n1 * st.k1 * es, cb = (size_t)st.R * st.n2 * st.k2 * es;
             if (bb + cb <= (size_t)P->fwd_fac_lds) {
                 // sizes are multiples of 16 bytes: factor dimensions are multiples of 16
@@ -636,6 +644,9 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     case kDense * 4 + SL1_FP8_E4M3: fwd_dense_gather<SL1_FP8_E4M3>(st, N, r0, s_j, s_x, k0, k1, acc); break;
                     case kKron * 4 + SL1_F64: fwd_kron_gather<SL1_F64>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc); break;
                     case kKron * 4 + SL1_F32: fwd_kron_gather<SL1_F32>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc); break;
+                    case kKron * 4 + SL1_FP8_E4M3:
+                        fwd_kron_gather<SL1_FP8_E4M3>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc);
+                        break;
                     default: fwd_kron_gather<SL1_BF16>(st, Bsrc, Csrc, r0, s_j, s_x, k0, k1, acc); break;
                 }
             }
@@ -648,7 +659,8 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
         __syncthreads();
         // rho = y - u and the stored direction z (rho itself, or its FP32 / BF16
         // rounding when the stage's matrix-core product takes that input type)
-        const int zround = (st.kind == kKron && st.dtype == SL1_BF16) ? 2 : ((st.kind == kKron && st.dtype == SL1_F32) ? 1 : 0);
+        const int zround = (st.kind == kKron && (st.dtype == SL1_BF16 || st.dtype == SL1_FP8_E4M3))
+                               ? 2 : ((st.kind == kKron && st.dtype == SL1_F32) ? 1 : 0);
         double sums[3] = {0.0, 0.0, 0.0};
         if (half == 0 && rows_ok) {
 #pragma unroll
@@ -675,168 +687,176 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
 }
 
 // ---------------------------------------------------------------------------
-// adjoint: Kronecker tile G[a0:a0+16, cb0:cb0+64] = sum_r C_r^T P B_r with MFMA.
-// MFMA 16x16 operand layout (wave64): lane l holds A[l%16][k], B[k][l%16] with
-// k = l/16 (x4 shapes) or 4*(l/16)+v (x16 shapes); D[4*(l/16)+v][l%16], except
-// the FP64 16x16x4 form, whose D is D[4v+l/16][l%16]: its first product stores V
-// rows in the 4*(l/16)+v order and the second reads them back as operand rows,
-// so the two within-tile row permutations cancel.
-// Wave w handles the terms r = w, w+4, ...; the four partial tiles are summed
-// in LDS in a fixed order.
+// adjoint: Kronecker correlations of one item, G[j2, j1] = sum_r (C_r^T P B_r)[j2, j1] for
+// the atoms j = j1 k2 + j2 with j2 in [a0, a0 + TJ2) and j1 in [cb0, cb0 + TJ1), where
+// P is the stored residual direction as an n2 x n1 matrix (in LDS) and (TJ2, TJ1) =
+// (st.kt2, st.kt1), multiples of 16 chosen per stage (sl1_tune_kron measures them).
+//   Phase 1: V_r = C_r[:, a0:a0+TJ2]^T P for every term: 16 x 16 MFMA output tiles over
+//            (term, row block, column block), spread over the four waves; V in LDS as
+//            [r][jj][i1] (BF16 stages: a hi and a lo BF16 part).
+//   Phase 2: G = [V_1 .. V_R] [B_1; ..; B_R] restricted to the item's columns: the terms
+//            are folded into one contraction of length R n1; every 16 x 16 output tile
+//            belongs to one wave, which forms its whole contraction in a fixed order (no
+//            cross-wave sums) and writes g and its maxima.
+// MFMA operand layout (wave64, 16 x 16 shapes): lane l holds A[l % 16][k], B[k][l % 16]
+// with k = l / 16 (x4 shapes) or 4 (l / 16) + v (x16 shapes); the FP32 and BF16 results
+// are D[4 (l / 16) + v][l % 16], the FP64 16x16x4 result is D[4 v + l / 16][l % 16].
 // ---------------------------------------------------------------------------
-template <typename AccT>
-struct KronLds {
-    AccT* V;      // [4 waves][16][n1]
-    AccT* red;    // [4 waves][16][64]
-};
 
-__device__ __forceinline__ void kron_tile_f32(const StageDesc& st, int a0, int cb0, const float* zs,
-                                              float* Vall, f32x4 (&acc)[4]) {
-    const int n1 = st.n1, k1 = st.k1, n2 = st.n2, k2 = st.k2, R = st.R;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
-    float* Vs = Vall + w * 16 * n1;
-    const float* Bf = (const float*)st.B;
-    const float* Cf = (const float*)st.C;
-    const int rounds = (R + 3) >> 2;
-    for (int rr = 0; rr < rounds; ++rr) {
-        const int r = rr * 4 + w;
-        if (r < R) {
-            const float* Cr = Cf + (size_t)r * k2 * n2;
-            for (int cb = 0; cb < n1; cb += 16) {
-                f32x4 d = {0.f, 0.f, 0.f, 0.f};
-                for (int k0 = 0; k0 < n2; k0 += 4) {
-                    const float av = Cr[(size_t)(a0 + li) * n2 + k0 + lk];
-                    const float bv = zs[(cb + li) * n2 + k0 + lk];
-                    d = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, d, 0, 0, 0);
-                }
+// one output tile's epilogue: g_j for its 16 x 16 atoms and the lane's maxima over the
+// preserved ones (|g| + eps ||z||_{q*}, |g|, eps)
+template <bool kF64Layout, typename D4>
+__device__ __forceinline__ void kron_tile_out(const StageDesc& st, const uint8_t* mask, double* gvec, double rz,
+                                              int j2b, int j1, const D4& d, double (&mx)[3]) {
+    const int l = threadIdx.x & 63, lk = l >> 4;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Vs[(4 * lk + v) * n1 + cb + li] = d[v];
-            }
+    for (int v = 0; v < 4; ++v) {
+        const int row = kF64Layout ? 4 * v + lk : 4 * lk + v;
+        const int j = j1 * st.k2 + j2b + row;
+        const double sv = (double)d[v];
+        gvec[j] = sv;
+        if (mask[j]) {
+            const double e = st.eps[j];
+            mx[0] = fmax(mx[0], fabs(sv) + e * rz);
+            mx[1] = fmax(mx[1], fabs(sv));
+            mx[2] = fmax(mx[2], e);
         }
-        __syncthreads();
-        if (r < R) {
-            const float* Br = Bf + (size_t)r * k1 * n1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (cb0 + q * 16 < k1) {
-                    const int j1 = cb0 + q * 16 + li;
-                    for (int k0 = 0; k0 < n1; k0 += 4) {
-                        const float av = Vs[li * n1 + k0 + lk];
-                        const float bv = Br[(size_t)j1 * n1 + k0 + lk];
-                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();
     }
 }
 
-__device__ __forceinline__ void kron_tile_f64(const StageDesc& st, int a0, int cb0, const double* zs,
-                                              double* Vall, f64x4 (&acc)[4]) {
-    const int n1 = st.n1, k1 = st.k1, n2 = st.n2, k2 = st.k2, R = st.R;
+__device__ __forceinline__ void kron_item_f64(const StageDesc& st, int a0, int cb0, const double* zs, double* V,
+                                              const uint8_t* mask, double* gvec, double rz, double (&mx)[3]) {
+    const int n1 = st.n1, n2 = st.n2, k1 = st.k1, k2 = st.k2, R = st.R, tj2 = st.kt2, tj1 = st.kt1;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
-    double* Vs = Vall + w * 16 * n1;
     const double* Bf = (const double*)st.B;
     const double* Cf = (const double*)st.C;
-    const int rounds = (R + 3) >> 2;
-    for (int rr = 0; rr < rounds; ++rr) {
-        const int r = rr * 4 + w;
-        if (r < R) {
-            const double* Cr = Cf + (size_t)r * k2 * n2;
-            for (int cb = 0; cb < n1; cb += 16) {
-                f64x4 d = {0.0, 0.0, 0.0, 0.0};
-                for (int k0 = 0; k0 < n2; k0 += 4) {
-                    const double av = Cr[(size_t)(a0 + li) * n2 + k0 + lk];
-                    const double bv = zs[(cb + li) * n2 + k0 + lk];
-                    d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
-                }
+    const int nrb = tj2 >> 4, ncb = n1 >> 4;
+    for (int t = w; t < nrb * ncb * R; t += 4) {
+        const int r = t / (nrb * ncb), jt = (t / ncb) % nrb, it = t % ncb;
+        const double* A = Cf + ((size_t)r * k2 + a0 + 16 * jt + li) * n2 + lk;
+        const double* Bp = zs + (size_t)(16 * it + li) * n2 + lk;
+        f64x4 d = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < n2; k0 += 4) d = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k0], Bp[k0], d, 0, 0, 0);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Vs[(4 * lk + v) * n1 + cb + li] = d[v];
-            }
+        for (int v = 0; v < 4; ++v) V[((size_t)r * tj2 + 16 * jt + 4 * v + lk) * n1 + 16 * it + li] = d[v];
+    }
+    __syncthreads();
+    const int nct = tj1 >> 4;
+    for (int t = w; t < nrb * nct; t += 4) {
+        const int jt = t / nct, ct = t % nct;
+        f64x4 d = {0.0, 0.0, 0.0, 0.0};
+        for (int r = 0; r < R; ++r) {
+            const double* A = V + ((size_t)r * tj2 + 16 * jt + li) * n1 + lk;
+            const double* Bp = Bf + ((size_t)r * k1 + cb0 + 16 * ct + li) * n1 + lk;
+            for (int k0 = 0; k0 < n1; k0 += 4) d = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k0], Bp[k0], d, 0, 0, 0);
         }
-        __syncthreads();
-        if (r < R) {
-            const double* Br = Bf + (size_t)r * k1 * n1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (cb0 + q * 16 < k1) {
-                    const int j1 = cb0 + q * 16 + li;
-                    for (int k0 = 0; k0 < n1; k0 += 4) {
-                        const double av = Vs[li * n1 + k0 + lk];
-                        const double bv = Br[(size_t)j1 * n1 + k0 + lk];
-                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();
+        kron_tile_out<true>(st, mask, gvec, rz, a0 + 16 * jt, cb0 + 16 * ct + li, d, mx);
     }
 }
 
-// BF16 factors: P (the stored residual, bf16-exact) and C_r enter the first
-// product exactly; the FP32 intermediate V is split into hi + lo BF16 parts so
-// the second product loses at most 2^-16 |V| (folded into eps by the library).
-__device__ __forceinline__ void kron_tile_bf16(const StageDesc& st, int a0, int cb0, const float* zs,
-                                               uint16_t* Vall, f32x4 (&acc)[4]) {
-    const int n1 = st.n1, k1 = st.k1, n2 = st.n2, k2 = st.k2, R = st.R;
+__device__ __forceinline__ void kron_item_f32(const StageDesc& st, int a0, int cb0, const float* zs, float* V,
+                                              const uint8_t* mask, double* gvec, double rz, double (&mx)[3]) {
+    const int n1 = st.n1, n2 = st.n2, k1 = st.k1, k2 = st.k2, R = st.R, tj2 = st.kt2, tj1 = st.kt1;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
-    uint16_t* Vh = Vall + w * 32 * n1;      // hi part [16][n1]
-    uint16_t* Vl = Vh + 16 * n1;            // lo part [16][n1]
-    const uint16_t* Bf = (const uint16_t*)st.B;
-    const uint16_t* Cf = (const uint16_t*)st.C;
-    const int rounds = (R + 3) >> 2;
-    for (int rr = 0; rr < rounds; ++rr) {
-        const int r = rr * 4 + w;
-        if (r < R) {
-            const uint16_t* Cr = Cf + (size_t)r * k2 * n2;
-            for (int cb = 0; cb < n1; cb += 16) {
-                f32x4 d = {0.f, 0.f, 0.f, 0.f};
-                for (int k0 = 0; k0 < n2; k0 += 16) {
-                    const u16x4 av = *(const u16x4*)(Cr + (size_t)(a0 + li) * n2 + k0 + 4 * lk);
-                    const float* zp = zs + (cb + li) * n2 + k0 + 4 * lk;
-                    s16x4 a, bb;
+    const float* Bf = (const float*)st.B;
+    const float* Cf = (const float*)st.C;
+    const int nrb = tj2 >> 4, ncb = n1 >> 4;
+    for (int t = w; t < nrb * ncb * R; t += 4) {
+        const int r = t / (nrb * ncb), jt = (t / ncb) % nrb, it = t % ncb;
+        const float* A = Cf + ((size_t)r * k2 + a0 + 16 * jt + li) * n2 + lk;
+        const float* Bp = zs + (size_t)(16 * it + li) * n2 + lk;
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < n2; k0 += 4) d = __builtin_amdgcn_mfma_f32_16x16x4f32(A[k0], Bp[k0], d, 0, 0, 0);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        a[v] = (short)av[v];
-                        bb[v] = (short)bf16_bits(zp[v]);
-                    }
-                    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, d, 0, 0, 0);
-                }
+        for (int v = 0; v < 4; ++v) V[((size_t)r * tj2 + 16 * jt + 4 * lk + v) * n1 + 16 * it + li] = d[v];
+    }
+    __syncthreads();
+    const int nct = tj1 >> 4;
+    for (int t = w; t < nrb * nct; t += 4) {
+        const int jt = t / nct, ct = t % nct;
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < R; ++r) {
+            const float* A = V + ((size_t)r * tj2 + 16 * jt + li) * n1 + lk;
+            const float* Bp = Bf + ((size_t)r * k1 + cb0 + 16 * ct + li) * n1 + lk;
+            for (int k0 = 0; k0 < n1; k0 += 4) d = __builtin_amdgcn_mfma_f32_16x16x4f32(A[k0], Bp[k0], d, 0, 0, 0);
+        }
+        kron_tile_out<false>(st, mask, gvec, rz, a0 + 16 * jt, cb0 + 16 * ct + li, d, mx);
+    }
+}
+
+// four consecutive factor entries as BF16 bits: BF16 storage as is; FP8 E4M3 storage
+// decoded (every E4M3 value has at most 4 significant bits, so its FP32 form ends in
+// 16 zero bits and its BF16 form is exact)
+__device__ __forceinline__ u16x4 bf16x4_of(const uint16_t* p) { return *(const u16x4*)p; }
+__device__ __forceinline__ u16x4 bf16x4_of(const uint8_t* p) {
+    const uint32_t q = *(const uint32_t*)p;
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
+    u16x4 r;
+    r[0] = (uint16_t)(__float_as_uint(lo[0]) >> 16);
+    r[1] = (uint16_t)(__float_as_uint(lo[1]) >> 16);
+    r[2] = (uint16_t)(__float_as_uint(hi[0]) >> 16);
+    r[3] = (uint16_t)(__float_as_uint(hi[1]) >> 16);
+    return r;
+}
+
+__device__ __forceinline__ s16x4 as_s16x4(const u16x4& u) {
+    s16x4 s;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float hi = bf16_rne(d[v]);
-                    const float lo = bf16_rne(d[v] - hi);
-                    Vh[(4 * lk + v) * n1 + cb + li] = bf16_bits(hi);
-                    Vl[(4 * lk + v) * n1 + cb + li] = bf16_bits(lo);
-                }
+    for (int v = 0; v < 4; ++v) s[v] = (short)u[v];
+    return s;
+}
+
+// BF16 (or FP8) factors: P (the stored residual, bf16-exact) and C_r enter the first
+// product exactly; the FP32 intermediate V is split into hi + lo BF16 parts so the
+// second product loses at most 2^-16 |V| (folded into eps by the library).
+template <typename FT>
+__device__ __forceinline__ void kron_item_bf16(const StageDesc& st, int a0, int cb0, const float* zs, uint16_t* Vh,
+                                               const uint8_t* mask, double* gvec, double rz, double (&mx)[3]) {
+    const int n1 = st.n1, n2 = st.n2, k1 = st.k1, k2 = st.k2, R = st.R, tj2 = st.kt2, tj1 = st.kt1;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    uint16_t* Vl = Vh + (size_t)R * tj2 * n1;
+    const FT* Bf = (const FT*)st.B;
+    const FT* Cf = (const FT*)st.C;
+    const int nrb = tj2 >> 4, ncb = n1 >> 4;
+    for (int t = w; t < nrb * ncb * R; t += 4) {
+        const int r = t / (nrb * ncb), jt = (t / ncb) % nrb, it = t % ncb;
+        const FT* A = Cf + ((size_t)r * k2 + a0 + 16 * jt + li) * n2 + 4 * lk;
+        const float* Bp = zs + (size_t)(16 * it + li) * n2 + 4 * lk;
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < n2; k0 += 16) {
+            const s16x4 a = as_s16x4(bf16x4_of(A + k0));
+            s16x4 bb;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bb[v] = (short)bf16_bits(Bp[k0 + v]);
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float hi = bf16_rne(d[v]);
+            const float lo = bf16_rne(d[v] - hi);
+            const size_t o = ((size_t)r * tj2 + 16 * jt + 4 * lk + v) * n1 + 16 * it + li;
+            Vh[o] = bf16_bits(hi);
+            Vl[o] = bf16_bits(lo);
+        }
+    }
+    __syncthreads();
+    const int nct = tj1 >> 4;
+    for (int t = w; t < nrb * nct; t += 4) {
+        const int jt = t / nct, ct = t % nct;
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < R; ++r) {
+            const size_t vo = ((size_t)r * tj2 + 16 * jt + li) * n1 + 4 * lk;
+            const FT* Bp = Bf + ((size_t)r * k1 + cb0 + 16 * ct + li) * n1 + 4 * lk;
+            for (int k0 = 0; k0 < n1; k0 += 16) {
+                const s16x4 h = as_s16x4(*(const u16x4*)(Vh + vo + k0));
+                const s16x4 lo = as_s16x4(*(const u16x4*)(Vl + vo + k0));
+                const s16x4 bb = as_s16x4(bf16x4_of(Bp + k0));
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, bb, d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo, bb, d, 0, 0, 0);
             }
         }
-        __syncthreads();
-        if (r < R) {
-            const uint16_t* Br = Bf + (size_t)r * k1 * n1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (cb0 + q * 16 < k1) {
-                    const int j1 = cb0 + q * 16 + li;
-                    for (int k0 = 0; k0 < n1; k0 += 16) {
-                        const u16x4 hv = *(const u16x4*)(Vh + li * n1 + k0 + 4 * lk);
-                        const u16x4 lv = *(const u16x4*)(Vl + li * n1 + k0 + 4 * lk);
-                        const u16x4 bv = *(const u16x4*)(Br + (size_t)j1 * n1 + k0 + 4 * lk);
-                        s16x4 h, lo, bb;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            h[v] = (short)hv[v];
-                            lo[v] = (short)lv[v];
-                            bb[v] = (short)bv[v];
-                        }
-                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(h, bb, acc[q], 0, 0, 0);
-                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo, bb, acc[q], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();
+        kron_tile_out<false>(st, mask, gvec, rz, a0 + 16 * jt, cb0 + 16 * ct + li, d, mx);
     }
 }
 
@@ -993,11 +1013,13 @@ template <int DT>
 __device__ __forceinline__ void dense_item_any(const StageDesc& st, int N, const int* act, const int* s_pre, int nseg,
                                                int n_act, int first, const double* zs, double rz, double* g,
                                                int lane, double (&mx)[3]) {
-    if (dense_apw(N) == 2) dense_item<DT, 2>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
+    const int apw = dense_apw(N, DT);
+    if (apw == 4) dense_item<DT, 4>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
+    else if (apw == 2) dense_item<DT, 2>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
     else dense_item<DT, 1>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
 }
 
-__global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __restrict__ P, int slot) {
+__global__ __launch_bounds__(kBlock, 4) void k_adj_dense(const SolveParams* __restrict__ P, int slot) {
     extern __shared__ __align__(16) char smem[];
     const int N = P->N, batch = P->batch;
     const size_t zbytes = ((size_t)N * 8 + 15) & ~(size_t)15;
@@ -1033,7 +1055,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_adj_dense(const SolveParams* __re
         const double* zs = (const double*)smem;
         double* gvec = gbuf(P, b, par);
         const int* act = actbuf(P, b, par);
-        const int first = (c * 4 + w) * dense_apw(N);
+        const int first = (c * 4 + w) * dense_apw(N, st.dtype);
         double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over the item
         switch (st.dtype) {
             case SL1_F64: dense_item_any<SL1_F64>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
@@ -1445,80 +1467,33 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
             continue;
         }
         double mx[3] = {0.0, 0.0, 0.0};
-        const int ntc = (st.k1 + kKronColTile - 1) / kKronColTile;
-        const int a0 = (c / ntc) * 16, cb0 = (c % ntc) * kKronColTile;
-        const int li = lane & 15, lk = lane >> 4;
+        const int ntc = st.k1 / st.kt1;
+        const int a0 = (c / ntc) * st.kt2, cb0 = (c % ntc) * st.kt1;
         const uint8_t* mask = P->mask + (size_t)b * K;
-        // tile skipping: once few atoms remain, a tile whose 16 x 64 atoms are all
-        // screened is not multiplied (its maxima are zero, its g is never read)
+        // tile skipping: once few atoms remain, an item whose atoms are all screened is
+        // not multiplied (its maxima are zero, its g is never read)
         if (uni(C.n_act) * 16 <= K) {
             int any = 0;
-            if ((int)threadIdx.x < kKronColTile && cb0 + (int)threadIdx.x < st.k1) {
-                // atoms (cb0 + col) k2 + a0 .. + 15: 16 consecutive mask bytes, 16-byte aligned
-                const uint4 mv = *(const uint4*)(mask + (size_t)(cb0 + threadIdx.x) * st.k2 + a0);
-                any = (mv.x | mv.y | mv.z | mv.w) != 0u;
+            const int per_col = st.kt2 >> 4;                 // 16-byte mask chunks per column j1
+            for (int q = threadIdx.x; q < st.kt1 * per_col; q += kBlock) {
+                // atoms (cb0 + q / per_col) k2 + a0 + 16 (q % per_col) .. + 15: 16 aligned mask bytes
+                const uint4 mv = *(const uint4*)(mask + (size_t)(cb0 + q / per_col) * st.k2 + a0 + 16 * (q % per_col));
+                any |= (mv.x | mv.y | mv.z | mv.w) != 0u;
             }
             if (!__syncthreads_or(any)) {
                 put_wave_max(P, b, c, mx, false);
                 continue;
             }
         }
-        if (st.dtype == SL1_F64) {
-            double* Vall = (double*)extra;
-            double* red = Vall + 4 * 16 * P->n1_max;
-            f64x4 acc[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-            kron_tile_f64(st, a0, cb0, zs, Vall, acc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
-            __syncthreads();
-            for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
-                const int i = o >> 6, col = o & 63;
-                if (cb0 + col < st.k1) {
-                    const double s = ((red[(0 * 16 + i) * 64 + col] + red[(1 * 16 + i) * 64 + col]) +
-                                      red[(2 * 16 + i) * 64 + col]) + red[(3 * 16 + i) * 64 + col];
-                    const int j = (cb0 + col) * st.k2 + a0 + i;
-                    gvec[j] = s;
-                    if (mask[j]) {
-                        const double e = st.eps[j];
-                        mx[0] = fmax(mx[0], fabs(s) + e * rz);
-                        mx[1] = fmax(mx[1], fabs(s));
-                        mx[2] = fmax(mx[2], e);
-                    }
-                }
-            }
-        } else {
-            float* red = (float*)extra;
-            char* vspace = extra + 4 * 16 * 64 * sizeof(float);
-            f32x4 acc[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (st.dtype == SL1_F32) kron_tile_f32(st, a0, cb0, (const float*)smem, (float*)vspace, acc);
-            else kron_tile_bf16(st, a0, cb0, (const float*)smem, (uint16_t*)vspace, acc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) red[(w * 16 + 4 * lk + v) * 64 + q * 16 + li] = acc[q][v];
-            __syncthreads();
-            for (int o = threadIdx.x; o < 16 * 64; o += kBlock) {
-                const int i = o >> 6, col = o & 63;
-                if (cb0 + col < st.k1) {
-                    const double s = (((double)red[(0 * 16 + i) * 64 + col] + (double)red[(1 * 16 + i) * 64 + col]) +
-                                      (double)red[(2 * 16 + i) * 64 + col]) + (double)red[(3 * 16 + i) * 64 + col];
-                    const int j = (cb0 + col) * st.k2 + a0 + i;
-                    gvec[j] = s;
-                    if (mask[j]) {
-                        const double e = st.eps[j];
-                        mx[0] = fmax(mx[0], fabs(s) + e * rz);
-                        mx[1] = fmax(mx[1], fabs(s));
-                        mx[2] = fmax(mx[2], e);
-                    }
-                }
-            }
-        }
+        if (st.dtype == SL1_F64)
+            kron_item_f64(st, a0, cb0, (const double*)smem, (double*)extra, mask, gvec, rz, mx);
+        else if (st.dtype == SL1_F32)
+            kron_item_f32(st, a0, cb0, (const float*)smem, (float*)extra, mask, gvec, rz, mx);
+        else if (st.dtype == SL1_FP8_E4M3)
+            kron_item_bf16<uint8_t>(st, a0, cb0, (const float*)smem, (uint16_t*)extra, mask, gvec, rz, mx);
+        else
+            kron_item_bf16<uint16_t>(st, a0, cb0, (const float*)smem, (uint16_t*)extra, mask, gvec, rz, mx);
+        __syncthreads();       // every read of V precedes the next item's phase 1
         put_wave_max(P, b, c, mx, true);
     }
 }
@@ -1842,7 +1817,7 @@ __global__ void k_lambda_out(const SolveParams* __restrict__ P, double* out, int
     }
     // when z is a rounded copy of y (BF16 Kronecker stages) add the bound
     // ||y - z|| (max ||a~_j|| + max eps_j)
-    const bool rounded = st.kind == kKron && st.dtype == SL1_BF16;
+    const bool rounded = st.kind == kKron && (st.dtype == SL1_BF16 || st.dtype == SL1_FP8_E4M3);
     const bool rounded32 = st.kind == kKron && st.dtype == SL1_F32;
     const double d2 = (rounded || rounded32) ? fmax(0.0, r2 - 2.0 * yz + zz) : 0.0;
     out[b] = mp + sqrt(d2) * (st.at_norm_max + st.eps_max * st.cq);     // ||v||_{q*} <= cq ||v||
@@ -2015,6 +1990,10 @@ hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int3
 }
 
 // the batched correlation kernel may use more than the default 64 KB of LDS
+hipError_t adjk_lds_attr(size_t lds) {
+    return hipFuncSetAttribute((const void*)k_adj_kron, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t fwd_lds_attr(size_t lds) {
     return hipFuncSetAttribute((const void*)k_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
@@ -2031,6 +2010,21 @@ int upd_resident_blocks(size_t lds) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     return n * cus;
+}
+
+// zero fill of n 32-bit words (a kernel rather than hipMemsetAsync, so that a caller
+// may capture the calls that clear workspace memory)
+__global__ __launch_bounds__(kBlock) void k_zero(uint32_t* __restrict__ p, size_t n) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>(2048, (n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(kBlock), 0, s, (uint32_t*)p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_x0(const SolveParams* dP, int batch, const double* x0, hipStream_t s) {

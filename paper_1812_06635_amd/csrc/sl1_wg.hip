@@ -1176,7 +1176,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         const double eta = uni(gam * YX);
         // ---- g = c - G x_t over the preserved positions ----
         double xt[H], g[H];
-        double cx = 0.0, xg = 0.0, m1 = 0.0, me = 0.0;
+        double cx = 0.0, xg = 0.0, m1 = 0.0, m0 = 0.0, me = 0.0;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const int i = lo + 64 * h;
@@ -1200,13 +1200,15 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 cx = fma(cv[r], xt[h], cx);
                 xg = fma(xt[h], gi, xg);
                 m1 = fmax(m1, fabs(gi) + eta * T.an[i]);
+                m0 = fmax(m0, fabs(gi));
                 me = fmax(me, T.e[i]);
             }
         }
-        // the four wave reductions (all 64 lanes of wave 0 take part; m1, me >= 0)
+        // the five wave reductions (all 64 lanes of wave 0 take part; m1, m0, me >= 0)
         cx = uni(wave_sum_full(cx));
         xg = uni(wave_sum_full(xg));
         m1 = uni(wave_max_nonneg_full(m1));
+        m0 = uni(wave_max_nonneg_full(m0));
         me = uni(wave_max_nonneg_full(me));
         // ---- scalars (uniform) ----
         const double yr = yy - cx;
@@ -1217,7 +1219,10 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         int conv;
         {
             Scalars S;
-            scalars_core(SK, cq, C, r2, r2, yr, sqrt(r2), m1 + me * rz, m1, me, yyb, S);
+            // the stable point scales by the bound max(|g_j| + eta ||a_j||) (Lemma 2 holds for the
+            // exact products); the conventional gap of the stop test by max |g_j|, as the grid
+            // engine does
+            scalars_core(SK, cq, C, r2, r2, yr, sqrt(r2), m1 + me * rz, m0, me, yyb, S);
             c1 = uni(S.c1);
             beta = uni(S.beta);
             tau_next = uni(S.tau_next);

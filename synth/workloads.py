@@ -359,6 +359,12 @@ def kron_stage(A, B, C, dtype, seed=0) -> Stage:
     ``dtype`` and the exact per-atom error bound against A."""
     R, n1, k1 = B.shape
     _, n2, k2 = C.shape
+    if dtype == "fp8":
+        # balance each term's two factors by a power of two (B_r 2^e, C_r 2^-e leave the
+        # product unchanged) so that both sit in the same part of the FP8 range
+        e = np.round(0.5 * np.log2(np.max(np.abs(C), axis=(1, 2)) / np.max(np.abs(B), axis=(1, 2))))
+        B = B * np.exp2(e)[:, None, None]
+        C = C * np.exp2(-e)[:, None, None]
     Bs = _encode(B.transpose(0, 2, 1), dtype)      # (R, k1, n1)
     Cs = _encode(C.transpose(0, 2, 1), dtype)      # (R, k2, n2)
     st = Stage(kind="kron", dtype=dtype, N=n1 * n2, K=k1 * k2, B=Bs, C=Cs, dims=(n1, k1, n2, k2),
@@ -569,6 +575,27 @@ def config5(batch=64, realization=0, n=(64, 128), R_A=8, Rs=(1, 2, 4, 8), s=40, 
                       [s] * batch, sigma, lam_frac)
     p.name = "C5"
     return p
+
+
+def kron_near_exact(realization=0, n=(16, 32), noise=1e-3, s=10, sigma=0.01, lam_frac=0.5):
+    """A dictionary that is one Kronecker product up to small noise: B (n x k) and
+    C (n x k) with N(0,1) entries and unit columns (so B kron C has unit columns),
+    A = B kron C + noise G / sqrt(N), unit columns, FP64; stages [B kron C (FP64), A].
+    Its structured stage is accurate enough (eps ~ noise) for the stable test to
+    screen most atoms while the method stays on it."""
+    nn, kk = n
+    rng = rng_for(7, realization, 0)
+    B = rng.standard_normal((1, nn, kk))
+    C = rng.standard_normal((1, nn, kk))
+    B /= np.linalg.norm(B, axis=1, keepdims=True)
+    C /= np.linalg.norm(C, axis=1, keepdims=True)
+    G = rng.standard_normal((nn * nn, kk * kk))
+    A = _kron_sum(B, C) + noise * G / nn
+    A /= np.linalg.norm(A, axis=0, keepdims=True)
+    stages = [kron_stage(A, B, C, "f64", seed=7), exact_stage(A, "f64", seed=7)]
+    Y, lam, X0, lmax = signals(rng_for(7, realization, 1), A, [s], sigma, lam_frac, "f64")
+    return Problem(name="KN", A=A, stages=stages, Y=Y, lam=lam, X0=X0, work="f64",
+                   atom_norm=np.linalg.norm(A, axis=0), lam_max=lmax, meta=dict(n=n, noise=noise))
 
 
 @functools.lru_cache(maxsize=2)

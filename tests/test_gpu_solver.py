@@ -55,6 +55,8 @@ ADJ_CASES = [
     ("C3-small dense fp8/bf16/f32", lambda: synth.config3(N=256, K=1024), 1e-12),
     ("C3 ragged N=2500", lambda: synth.config3(N=2500, K=600, s=20), 1e-12),
     ("C4-small kron bf16", lambda: synth.config4(batch=3, n=(16, 32)), 3e-5),
+    ("C4-small kron fp8", lambda: synth.config4(batch=3, n=(16, 32), factor_dtype="fp8"), 3e-5),
+    ("C4 kron fp8 n=(32,64)", lambda: synth.config4(batch=2, factor_dtype="fp8"), 3e-5),
     ("kron f32 n=(32,64) R=4", lambda: synth.config2(n=(32, 64), R_A=4, Rs=(1, 4)), 2e-5),
     ("C6-small faust f32 ragged K", lambda: synth.config6(N=64, K=1537, depth=3, col_nnz=(8, 8, 24),
                                                           keeps=(8, 16), batch=3), 1e-12),
@@ -87,8 +89,8 @@ def test_adjoint_kernels_match_oracle_products(sl1, name, maker, rtol):
         scale = np.abs(z) @ Aabs + 1e-300
         err = np.abs(g - ref) / scale
         assert np.max(err) <= rtol, (name, k, float(np.max(err)))
-        # z is y itself except for BF16 Kronecker stages (rounded to BF16)
-        if st.kind == "kron" and st.dtype == "bf16":
+        # z is y itself except for BF16 and FP8 Kronecker stages (rounded to BF16)
+        if st.kind == "kron" and st.dtype in ("bf16", "fp8"):
             assert np.all(np.abs(z - p.Y) <= 2.0 ** -8 * np.abs(p.Y))
         else:
             assert np.array_equal(z, p.Y)
@@ -97,8 +99,68 @@ def test_adjoint_kernels_match_oracle_products(sl1, name, maker, rtol):
         for b in range(p.batch):
             exact = osc.stable_lambda_max(At, st.eps, p.Y[b])
             assert lm[b] >= exact * (1 - 1e-12)
-            assert lm[b] <= exact * (1 + max(rtol * 10, 2 ** -5 if st.dtype == "bf16" and st.kind == "kron" else 0))
+            assert lm[b] <= exact * (1 + max(rtol * 10, 2 ** -5 if st.dtype in ("bf16", "fp8") and st.kind == "kron"
+                                             else 0))
         d.free()
+
+
+TILE_CASES = [
+    ("C1 kron f64", lambda: synth.config1(), 1e-12),
+    ("kron f32 n=(32,64) R=4", lambda: synth.config2(n=(32, 64), R_A=4, Rs=(1, 4)), 2e-5),
+    ("C4 kron bf16", lambda: synth.config4(batch=2), 3e-5),
+    ("C4 kron fp8", lambda: synth.config4(batch=2, factor_dtype="fp8"), 3e-5),
+]
+SHAPES = [(a, b) for a in (16, 32, 64, 128) for b in (16, 32, 64, 128)]
+
+
+@pytest.mark.parametrize("name,maker,rtol", TILE_CASES, ids=[c[0] for c in TILE_CASES])
+def test_every_kronecker_tile_shape_matches_oracle_products(sl1, name, maker, rtol):
+    # the structured correlation kernel with each usable item shape (kt2 x kt1 atoms)
+    # atom by atom against FP64 products of the stored factors
+    import torch
+    from paper_1812_06635_amd._lib import Stablel1Error
+    p = maker()
+    wt = torch.float64 if p.work == "f64" else torch.float32
+    for k, st in enumerate(p.stages[:-1]):
+        d = sl1.upload_stage(st)
+        At = st.values()
+        Bv, Cv = st.factor_values()
+        Aabs = synth.workloads._kron_sum(np.abs(Bv), np.abs(Cv))
+        tried = 0
+        for kt2, kt1 in SHAPES:
+            try:
+                d.set_tile(kt2, kt1)
+            except Stablel1Error:
+                continue                            # not a usable shape for this stage
+            _say(f"tile {kt2}x{kt1} {name} stage {k}")
+            g, z = sl1.adjoint(d, _t(p.Y, wt))
+            g, z = g.cpu().numpy(), z.cpu().numpy().astype(np.float64)
+            err = np.abs(g - z @ At) / (np.abs(z) @ Aabs + 1e-300)
+            assert np.max(err) <= rtol, (name, k, kt2, kt1, float(np.max(err)))
+            tried += 1
+        assert tried >= 3
+        d.free()
+
+
+def test_kronecker_tile_autotuner(sl1):
+    # the tuner times every usable shape on the batched workload's stages, records the
+    # fastest, and the solve with the tuned shapes reaches the Lasso solution
+    _say("tile autotuner on the batched dictionary (64 signals)")
+    import torch
+    p = synth.config4(batch=64)
+    ups = [sl1.upload_stage(s) for s in p.stages]
+    shapes, ms = sl1.tune_kron(ups, batch=p.batch)
+    assert shapes[-1] is None and ms[-1] == 0.0
+    for (kt2, kt1), t, st in zip(shapes[:-1], ms[:-1], p.stages[:-1]):
+        n1, k1, n2, k2 = st.dims
+        assert k2 % kt2 == 0 and k1 % kt1 == 0 and kt2 * kt1 >= 512 and t > 0
+    out = sl1.solve(ups, [s.L for s in p.stages], [s.rc_theory for s in p.stages], _t(p.atom_norm),
+                    _t(p.Y, torch.float32), _t(p.lam), tol=1e-9)
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+    assert res["status"] == 0
+    for b in range(0, p.batch, 8):
+        _check_solution(p, res, b)
 
 
 # ---------------------------------------------------------------------------
@@ -107,12 +169,22 @@ def test_adjoint_kernels_match_oracle_products(sl1, name, maker, rtol):
 ENGINES = ["grid", "wg"]
 
 
-@pytest.mark.parametrize("engine", ENGINES)
+# the hybrid engine hands over to its tail kernel after 2 iterations (chunk = 2), so the
+# tail's Gram mode (or its column mode) runs most of the traced iterations
+TRACE_ENGINES = {"grid": dict(engine="grid"), "wg": dict(engine="wg"),
+                 "hybrid-gram": dict(engine="hybrid", chunk=2, tail_gram=True),
+                 "hybrid-columns": dict(engine="hybrid", chunk=2, tail_gram=False)}
+
+
+@pytest.mark.parametrize("engine", list(TRACE_ENGINES))
 @pytest.mark.parametrize("real,frac", [(0, 0.5), (1, 0.2), (2, 0.8)])
 def test_fp64_trace_matches_method_reference(sl1, real, frac, engine):
     _say(f"trace C1 real={real} frac={frac} engine={engine}")
     p = synth.config1(realization=real, lam_frac=frac)
-    out = _run(sl1, p, tol=1e-10, trace_cap=5000, engine=engine)
+    out = _run(sl1, p, tol=1e-10, trace_cap=5000, **TRACE_ENGINES[engine])
+    if engine.startswith("hybrid"):
+        assert sl1.last_solve_phases(1, p.N, p.K)[0] == "hybrid"
+        assert (sl1.last_solve_phases(1, p.N, p.K)[1]["gram_cap"] > 0) == engine.endswith("gram")
     ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
                       [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10)
     n = int(out["iters"][0])
@@ -124,11 +196,15 @@ def test_fp64_trace_matches_method_reference(sl1, real, frac, engine):
     assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]             # |A_t+1|
     assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]                # K_t
     Gc = np.array([r.G_conv for r in ref.trace])
-    np.testing.assert_allclose(tr[:, 6], Gc, rtol=1e-7, atol=1e-12)
+    # in Gram mode ||rho||^2 and y^T rho come from y^T y - c^T x and x^T G x: their FP64
+    # rounding, ~n u (||y|| + sum |x_k| ||a_k||)^2, bounds the absolute gap difference
+    np.testing.assert_allclose(tr[:, 6], Gc, rtol=1e-7, atol=1e-10 if engine == "hybrid-gram" else 1e-12)
     approx = tr[:, 1] < len(p.stages) - 1
     np.testing.assert_allclose(tr[approx, 9], np.array([r.gamma for r in ref.trace])[approx], rtol=1e-6, atol=1e-9)
-    # on A the rounding allowance (~1e-13 per atom) keeps gamma within a hair of 1
-    assert np.all(np.abs(tr[~approx, 9] - 1) <= 1e-12 * tr[~approx, 11] / np.maximum(tr[~approx, 5], 1e-300) + 1e-9)
+    # on A the rounding allowance (~1e-13 per atom) keeps gamma within a hair of 1; in Gram mode the
+    # stable scaling also carries the Gram forms' error bound eta ||a_j|| (~1e-12 here)
+    tol_g = 1e-9 if engine == "hybrid-gram" else 1e-12
+    assert np.all(np.abs(tr[~approx, 9] - 1) <= tol_g * tr[~approx, 11] / np.maximum(tr[~approx, 5], 1e-300) + 1e-9)
     np.testing.assert_allclose(out["x"][0], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
     # and the Lasso solution itself
     sol = ol.solve(p.A, p.Y[0], float(p.lam[0]), L=p.stages[-1].L)
@@ -196,6 +272,31 @@ def test_batched_bf16_kronecker_method(sl1, engine):
     assert len(set(out["iters"].tolist())) > 1           # uneven convergence inside one launch
     for b in range(p.batch):
         _check_solution(p, out, b)
+
+
+@pytest.mark.parametrize("engine", ["grid", "hybrid"])
+@pytest.mark.parametrize("n", [(16, 32), (32, 64)], ids=["small", "C4-size"])
+def test_batched_fp8_kronecker_method(sl1, engine, n):
+    # Kronecker factors stored in FP8 E4M3 (decoded exactly to BF16 for the matrix
+    # cores): every signal safe and at the Lasso solution
+    _say(f"batch 24 fp8 kron n={n} engine={engine}")
+    p = synth.config4(batch=24, n=n, factor_dtype="fp8")
+    out = _run(sl1, p, tol=1e-10, engine=engine)
+    assert out["status"] == 0
+    assert len(set(out["iters"].tolist())) > 1           # uneven convergence inside one launch
+    for b in range(p.batch):
+        _check_solution(p, out, b)
+
+
+def test_fp8_kronecker_refused_by_the_whole_solve_engine(sl1):
+    _say("fp8 kron stages, forced whole-solve engine")
+    from paper_1812_06635_amd._lib import ELIMIT, Stablel1Error
+    p = synth.config4(batch=2, n=(16, 32), factor_dtype="fp8")
+    with pytest.raises(Stablel1Error) as e:
+        _run(sl1, p, tol=1e-8, engine="wg")
+    assert e.value.code == ELIMIT
+    out = _run(sl1, p, tol=1e-8)                                  # the automatic choice avoids it
+    assert out["status"] == 0
 
 
 # ---------------------------------------------------------------------------
@@ -447,7 +548,7 @@ def test_hybrid_hand_over_matches_grid(sl1, gram):
         tr = h["trace"][b][:n]
         assert np.array_equal(tr[:, 0], np.arange(n))                  # one trace row per iteration
         assert np.all(tr[1:, 2] == tr[:-1, 3])                          # |A_t+1| carried over
-    for b in (0, 7):
+    for b in range(p.batch):
         _check_solution(p, h, b)
 
 
