@@ -275,6 +275,35 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
               int32_t* iters, int32_t* stage, void* stream);
 
 /*
+ * sl1_solve_noalloc -- sl1_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, checks, kernels and results as sl1_solve, with
+ * the workspace laid out in a fixed device array of 64 MiB that the library holds
+ * on each device it runs on until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine: it launches on `stream` itself (no library
+ * stream, events or graphs; iterations are launched directly, which gives results
+ * bit-identical to the replayed graphs of sl1_solve) and clears the array with a
+ * fill kernel at the start of each call.  The caller still passes every input and
+ * output.  The dictionary handles are made beforehand with the sl1_dict_* calls.
+ *   Limit: the workspace of (batch, N, K) must fit 64 MiB; it takes about
+ *   batch * (89 K + 8 N + 1 KiB) bytes plus 16 MiB for the batched product's tiles,
+ *   and batch * (8 K + 8) more with SL1_FLAG_RULE_DST or SL1_FLAG_RULE_DOME (e.g.
+ *   up to ~130 signals at N = 1024, K = 4096).  Larger requests return SL1_ELIMIT
+ *   before any device work.  SL1_FLAG_PROFILE is refused (SL1_EINVAL); the
+ *   sl1_last_solve_* queries do not see these solves.
+ *   Concurrency: every call on one device shares that device's array, which keeps
+ *   the last call's contents.  Calls from host threads are serialised by the
+ *   library; calls that overlap on the device in any other way (e.g. the same
+ *   graph-captured call replayed on two streams at once) race and give undefined
+ *   results.
+ * Returns as sl1_solve, plus SL1_ELIMIT for a workspace beyond the array.
+ */
+int sl1_solve_noalloc(const sl1_dict* seq, int n_stages, const double* L, const double* rc,
+                      const double* atom_norm, int64_t batch, const void* y, const double* lambda,
+                      const sl1_opts* opt, double* x, double* gap, double* gap_cert, uint8_t* screened,
+                      int32_t* iters, int32_t* stage, void* stream);
+
+/*
  * sl1_lambda_max -- out[b] = max_j (|a~_j^T y_b| + eps_j ||y_b||_{q*}), the stable
  * lambda'_max of Section III-C for the stage's bound norm q (equal to
  * lambda_max = ||A^T y_b||_inf when eps = 0).

@@ -53,6 +53,8 @@ SIGNATURES = [
     ("sl1_opts_default", c_i32, [ctypes.POINTER(Opts)]),
     ("sl1_solve", c_i32, [ctypes.POINTER(c_dict), c_i32, ctypes.POINTER(c_d), ctypes.POINTER(c_d), c_p, c_i64,
                           c_p, c_p, ctypes.POINTER(Opts), c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+    ("sl1_solve_noalloc", c_i32, [ctypes.POINTER(c_dict), c_i32, ctypes.POINTER(c_d), ctypes.POINTER(c_d), c_p,
+                                  c_i64, c_p, c_p, ctypes.POINTER(Opts), c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     ("sl1_lambda_max", c_i32, [c_dict, c_i64, c_p, c_i32, c_p, c_p]),
     ("sl1_dict_adjoint", c_i32, [c_dict, c_i64, c_p, c_i32, c_p, c_p, c_p]),
     ("sl1_grad", c_i32, [c_dict, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_i32, c_p]),

@@ -150,7 +150,7 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
-          update="fista", rule="gap", batched_gemm=True, screen_every=1, gemm_signals=0, x0=None):
+          update="fista", rule="gap", batched_gemm=True, screen_every=1, gemm_signals=0, x0=None, noalloc=False):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
@@ -162,7 +162,9 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     the exact dense stage share one matrix-core correlation product;
     screen_every: atoms are rejected only every screen_every iterations;
     gemm_signals: qualifying signals from which the batched product runs (0: 64);
-    x0: optional (batch, K) float64 device tensor, the initial iterate (warm start).
+    x0: optional (batch, K) float64 device tensor, the initial iterate (warm start);
+    noalloc: call sl1_solve_noalloc (workspace in the library's fixed device array;
+    the outputs below are still allocated here, by torch).
     Returns a dict of device tensors x, gap, gap_cert, screened, iters, stage, the
     status code, and the trace (batch, trace_cap, 13) when requested."""
     if engine not in _ENGINES:
@@ -213,11 +215,12 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
     screened = torch.empty((batch, K), dtype=torch.uint8, device=dev)
     iters = torch.empty(batch, dtype=torch.int32, device=dev)
     stage = torch.empty(batch, dtype=torch.int32, device=dev)
-    code = L.load().sl1_solve(arr, n, Ls, rcs, _ptr(atom_norm), batch, _ptr(y), _ptr(lam), ctypes.byref(opts),
-                              _ptr(x), _ptr(gap), _ptr(gap_cert), _ptr(screened), _ptr(iters), _ptr(stage),
-                              _stream())
+    entry = "sl1_solve_noalloc" if noalloc else "sl1_solve"
+    code = getattr(L.load(), entry)(arr, n, Ls, rcs, _ptr(atom_norm), batch, _ptr(y), _ptr(lam), ctypes.byref(opts),
+                                    _ptr(x), _ptr(gap), _ptr(gap_cert), _ptr(screened), _ptr(iters), _ptr(stage),
+                                    _stream())
     if check:
-        L.check(code, "sl1_solve")
+        L.check(code, entry)
     out = dict(x=x, gap=gap, gap_cert=gap_cert, screened=screened, iters=iters, stage=stage, status=code)
     if trace is not None:
         out["trace"] = trace

@@ -67,6 +67,13 @@ struct sl1_dict_s {
     double q = 2.0;            // norm of the error bounds (1 <= q <= inf)
 };
 
+// The allocation-free solve's workspace: one fixed array per device, kept until the
+// process ends.  Host code never passes `scratch` itself to a kernel or a copy (in
+// host code it names a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 #define HIP_TRY(x)                                   \
     do {                                             \
         hipError_t e_ = (x);                         \
@@ -1438,6 +1445,71 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
     std::lock_guard<std::mutex> lk(w->mu);
     return solve_impl(w, seq, n_stages, atom_norm, batch, y, lambda, o, tmp, dev, x, gap, gap_cert, screened, iters,
                       stage, stream);
+}
+
+// Device address of `scratch` on device dev (taken on the first call there, with dev
+// current), and the mutex that serialises the calls sharing it.
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_init_mu;
+std::mutex g_scratch_mu[kScratchDevices];
+void* g_scratch_ptr[kScratchDevices] = {};
+
+static int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kScratchDevices) return SL1_ELIMIT;
+    std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SL1_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SL1_OK;
+}
+
+int sl1_solve_noalloc(const sl1_dict* seq, int n_stages, const double* L, const double* rc,
+                      const double* atom_norm, int64_t batch, const void* y, const double* lambda,
+                      const sl1_opts* opt, double* x, double* gap, double* gap_cert, uint8_t* screened,
+                      int32_t* iters, int32_t* stage, void* stream) {
+    sl1_opts o;
+    if (opt) o = *opt;
+    else sl1_opts_default(&o);
+    if (o.flags & SL1_FLAG_PROFILE) return SL1_EINVAL;   // profiling records events
+    o.flags |= SL1_FLAG_NO_GRAPH;                        // direct launches: no graph to instantiate
+    SolveParams tmp;
+    int dev = 0;
+    int st = solve_checks(seq, n_stages, L, rc, atom_norm, batch, y, lambda, o, x, gap, tmp, &dev);
+    if (st != SL1_OK) return st;
+    void* base = nullptr;
+    if ((st = scratch_address(dev, &base)) != SL1_OK) return st;
+    // a view of the fixed array laid out like an allocated workspace of this shape
+    Workspace w;
+    w.borrowed = true;
+    w.device = dev;
+    w.batch = (int)batch;
+    w.N = tmp.N;
+    w.K = tmp.K;
+    SolveParams hp;
+    std::memset(&hp, 0, sizeof(hp));
+    int h_active[16] = {0};
+    size_t need = workspace_layout(w, nullptr, nullptr);
+    const bool rule_y = (o.flags & (SL1_FLAG_RULE_DST | SL1_FLAG_RULE_DOME)) != 0;
+    const size_t o_cy = need;
+    if (rule_y) need += al((size_t)batch * tmp.K * 8) + al((size_t)batch * 8);
+    if (need > kScratchBytes) return SL1_ELIMIT;
+    workspace_layout(w, (char*)base, &hp);
+    if (rule_y) {
+        w.d_cy = (double*)((char*)base + o_cy);
+        w.d_yy = (double*)((char*)base + o_cy + al((size_t)batch * tmp.K * 8));
+    }
+    w.mem = base;
+    w.hP = &hp;
+    w.h_active = h_active;
+    w.stream = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    // the array keeps the previous call's contents: start from zeros, as a new workspace does
+    HIP_TRY(launch_zero(base, need, w.stream));
+    return solve_impl(&w, seq, n_stages, atom_norm, batch, y, lambda, o, tmp, dev, x, gap, gap_cert, screened,
+                      iters, stage, stream);
 }
 
 static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, double* lam_out, double* g_out,
