@@ -185,6 +185,8 @@ typedef struct {
                                      stage is not dense) */
 #define SL1_FLAG_TAIL_COLUMNS 32  /* the tail kernel forms every iteration's products from the stored
                                      columns (no Gram mode) */
+#define SL1_FLAG_HYBRID_GRID_FIRST 1024 /* hybrid engine: run the Kronecker approximations on the grid
+                                     kernels too (by default they run in the whole-solve kernel) */
 #define SL1_FLAG_ISTA 64          /* ISTA update x_{t+1} = ST(x_t + A~^T rho~_t / L) (Section I-B)
                                      instead of FISTA */
 #define SL1_FLAG_NO_GEMM 256      /* grid engine: correlations of every signal stream its own preserved
@@ -215,11 +217,15 @@ typedef struct {
  *   SL1_ENGINE_WG      one 512-thread workgroup per signal runs the whole solve in one
  *                      launch (per-signal z and the current stage's Kronecker factors in
  *                      LDS); launches are bounded and repeated while signals remain;
- *   SL1_ENGINE_HYBRID  the grid engine until, after a chunk, every live signal is on
- *                      the last (dense) stage and its preserved set holds at most
- *                      ~2 MiB of columns or fits the Gram capacity (up to 128 atoms);
- *                      the remaining iterations then run in a tail kernel, one
- *                      workgroup per signal with the preserved set's state in LDS.
+ *   SL1_ENGINE_HYBRID  when every stage before the last is a Kronecker stage (and the
+ *                      whole-solve layout fits), those stages run in the whole-solve
+ *                      kernel, each signal stopping there on reaching the last stage;
+ *                      then (or from the start, for other sequences) the grid engine
+ *                      until, after a chunk, every live signal is on the last (dense)
+ *                      stage and its preserved set holds at most ~2 MiB of columns
+ *                      or fits the Gram capacity (up to 128 atoms); the remaining
+ *                      iterations then run in a tail kernel, one workgroup per
+ *                      signal with the preserved set's state in LDS.
  *                      Once a signal's |A_t| fits the Gram capacity, the tail kernel
  *                      forms G = A_t^T A_t and A_t^T y once (FP64) and iterates on
  *                      them (g = A_t^T y - G x, ||y - Ax||^2 and y^T(y - Ax) from the

@@ -24,6 +24,7 @@ FLAG_ISTA = 64
 FLAG_RULE_DST = 128
 FLAG_NO_GEMM = 256
 FLAG_RULE_DOME = 512
+FLAG_HYBRID_GRID_FIRST = 1024
 GRID_KERNELS = 6
 ENGINE_GRID, ENGINE_WG, ENGINE_HYBRID = 1, 2, 3
 

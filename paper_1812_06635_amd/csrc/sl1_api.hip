@@ -37,6 +37,8 @@ hipError_t launch_eps_fold(const double*, const double*, double, int, double*, i
 hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_solve_tail(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_to_wg(const SolveParams*, int, hipStream_t);
+hipError_t launch_wg_stat(const SolveParams*, hipStream_t);
+hipError_t launch_wg_to_grid(const SolveParams*, int, hipStream_t);
 hipError_t launch_zero(void*, size_t, hipStream_t);
 }  // namespace sl1
 
@@ -645,20 +647,25 @@ int hybrid_atoms(const SolveParams& p) {
 
 // Whole-solve launches until every signal stopped (or the iteration cap, counting
 // the `done` iterations already run by the grid kernels); tail: the hybrid
-// solve's kernel for the last, dense, stage with LDS-resident per-atom state.
+// solve's kernel for the last, dense, stage with LDS-resident per-atom state;
+// parking (p.wg_park >= 0): whole-solve launches until every live signal has
+// reached the park stage, with the hand-over statistics in h_active[4..7].
 // Profile: launch times and per-signal phase clocks.
+enum WgMode { kWgWhole = 0, kWgTail = 1, kWgPark = 2 };
 int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch, size_t wlds, bool prof, int dev,
-           long long done, bool tail) {
+           long long done, int mode) {
     const int per = std::min(wg_iters_per_launch(p), 256 * (o.chunk > 0 ? o.chunk : 16));
     const long long cap = (long long)o.max_iter + 1;
     long long launched = done;
     for (;;) {
         if (prof) HIP_TRY(hipEventRecord(w->ev_a, w->stream));
-        if (tail) HIP_TRY(launch_solve_tail(w->dP, (int)batch, wlds, per, w->stream));
+        if (mode == kWgTail) HIP_TRY(launch_solve_tail(w->dP, (int)batch, wlds, per, w->stream));
         else HIP_TRY(launch_solve_wg(w->dP, (int)batch, wlds, per, w->stream));
         if (prof) HIP_TRY(hipEventRecord(w->ev_b, w->stream));
         launched += per;
-        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, 4, hipMemcpyDeviceToHost, w->stream));
+        if (mode == kWgPark) HIP_TRY(launch_wg_stat(w->dP, w->stream));
+        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, mode == kWgPark ? 32 : 4, hipMemcpyDeviceToHost,
+                               w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (prof) {
             float ms = 0.f;
@@ -667,6 +674,7 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
             w->wg_n += 1;
         }
         if (*w->h_active <= 0 || launched >= cap) break;
+        if (mode == kWgPark && w->h_active[4 + 2] == 0) break;
     }
     if (prof) {
         std::vector<long long> ticks((size_t)batch * kWgPhases);
@@ -1190,6 +1198,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     p.cy = p.yy = nullptr;
     p.gemm_min = 0;
     p.wg_prof = nullptr;
+    p.wg_park = -1;
     p.Gamma = 0.5;
     p.tol = 0.0;
     p.margin = 0.0;
@@ -1297,6 +1306,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     }
     const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
     p.wg_prof = ((use_wg || hybrid) && prof) ? w->d_wgprof : nullptr;
+    p.wg_park = -1;
     LaunchCfg cfg = launch_cfg(*w, p);
     if (!use_wg) {
         st = check_lds(cfg);
@@ -1329,7 +1339,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     }
     if (use_wg) {
         if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
-        st = run_wg(w, p, o, batch, wlds, prof, dev, 0, false);
+        st = run_wg(w, p, o, batch, wlds, prof, dev, 0, kWgWhole);
         if (st != SL1_OK) return st;
         return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
     }
@@ -1352,6 +1362,40 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     // advance), the batched product while the host has it switched off
     const bool last_kron = p.st[p.n_stages - 1].kind != kDense;      // a structured last stage
     bool kron_live = cfg.g_adjk > 0;
+    // hybrid: Kronecker approximations run in the whole-solve kernel (one workgroup
+    // per signal with the factors in LDS, no kernel boundary between iterations); a
+    // signal stops there at the top of its first iteration on the last stage.  The
+    // parked signals then go on in the tail kernel when every preserved set is small
+    // enough for it, else in the grid kernels (their lists converted), which hand
+    // over to the tail later.  Dense approximations stay on the grid kernels, which
+    // spread a large preserved set over the chip.
+    bool kron_first = hybrid && wlds && p.n_stages > 1 && !(o.flags & SL1_FLAG_HYBRID_GRID_FIRST);
+    for (int i = 0; i + 1 < p.n_stages; ++i) kron_first = kron_first && p.st[i].kind == kKron;
+    if (kron_first) {
+        w->last_engine = SL1_ENGINE_HYBRID;
+        p.wg_park = p.n_stages - 1;
+        HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+        if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
+        st = run_wg(w, p, o, batch, wlds, prof, dev, 0, kWgPark);
+        if (st != SL1_OK) return st;
+        p.wg_park = -1;
+        if (*w->h_active <= 0) return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
+        const int* s1 = w->h_active + 4;
+        const size_t tlds = wg_layout(p, true, s1[0], gram);
+        if (s1[2] == 0 && tlds && (s1[0] <= hyb_atoms || s1[0] <= p.wg_cap_gram)) {
+            // the parked state is the tail kernel's input format as it stands
+            HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+            w->last_gram_cap = p.wg_cap_gram;
+            if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
+            st = run_wg(w, p, o, batch, tlds, prof, dev, 0, kWgTail);
+            if (st != SL1_OK) return st;
+            return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
+        }
+        if (p.gemm_min > 0) p.gemm_on = s1[3] >= gemm_signals ? 1 : 0;
+        if (!last_kron && s1[2] == 0) kron_live = false;
+        HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+        HIP_TRY(launch_wg_to_grid(w->dP, (int)batch, w->stream));
+    }
     for (;;) {
         LaunchCfg ccfg = cfg;
         if (!kron_live) ccfg.g_adjk = 0;
@@ -1419,7 +1463,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
                 w->last_engine = SL1_ENGINE_HYBRID;
                 w->last_gram_cap = p.wg_cap_gram;
                 if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
-                st = run_wg(w, p, o, batch, tlds, prof, dev, launched, true);
+                st = run_wg(w, p, o, batch, tlds, prof, dev, launched, kWgTail);
                 if (st != SL1_OK) return st;
                 break;
             }
@@ -1548,6 +1592,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.cy = p.yy = nullptr;
     p.gemm_min = 0;
     p.wg_prof = nullptr;
+    p.wg_park = -1;
     p.Gamma = 0.5;
     p.tol = 0.0;
     p.margin = 0.0;
@@ -1614,6 +1659,7 @@ static int time_adj(Workspace* w, const SolveParams& tmp, const StageDesc& sd, i
     p.cy = p.yy = nullptr;
     p.gemm_min = 0;
     p.wg_prof = nullptr;
+    p.wg_park = -1;
     p.tol = 0.0;
     p.margin = 0.0;
     p.atom_norm = sd.at_norm;

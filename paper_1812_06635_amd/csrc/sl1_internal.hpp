@@ -166,6 +166,9 @@ struct SolveParams {
     int wo_zd, wo_zf, wo_y, wo_fac, wo_scr, wo_lnj, wo_lnx, wo_lact, wo_tail, wo_gram;
     int wg_cap_nz, wg_cap_act, wg_cap_gram;
     long long* wg_prof;
+    // whole-solve kernel: a signal whose stage reaches wg_park stops at the top of
+    // that iteration and keeps its state for another engine (-1: never)
+    int wg_park;
 };
 
 struct LaunchCfg {

@@ -611,7 +611,9 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
         s_clk = P0->wg_prof ? wall_clock64() : 0;
     }
     __syncthreads();
-    if (sC.done) return;
+    // a signal parked at an earlier launch waits for the engine that takes over
+    const int park = P0->wg_park;
+    if (sC.done || (park >= 0 && sC.stage >= park)) return;
     {
         const SolveParams* P = phase_params(P0);
         if (P->wo_y >= 0) {
@@ -623,6 +625,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
     for (int it = 0; it < max_it; ++it) {
         const int stage = uni(sC.stage), par = uni(sC.par);
         const int n_nz = uni(sC.n_nz), n_act = uni(sC.n_act);
+        if (park >= 0 && stage >= park) break;    // state stored below, lists in slot 0
         // ---- factors of a new Kronecker stage, and the two lists, into LDS ----
         {
             const SolveParams* P = phase_params(P0);
@@ -1717,6 +1720,118 @@ __global__ __launch_bounds__(kSeg) void k_to_wg(const SolveParams* __restrict__ 
             __syncthreads();
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// After a whole-solve phase that parked signals at the last stage: the
+// statistics the host's hand-over decisions read (the same four as the grid
+// kernels' per-chunk reduction: max and sum of |A_t|, signals not yet on the
+// park stage, signals that qualify for the batched correlation product).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_wg_stat(const SolveParams* __restrict__ P) {
+    __shared__ int s_v[4][kBlock / 64];
+    const int park = P->wg_park;
+    int v[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < P->batch; b += kBlock) {
+        const Control& C = P->ctrl[2 * b];
+        if (C.done) continue;
+        const bool on_last = C.stage == P->n_stages - 1;
+        v[0] = max(v[0], C.n_act);
+        v[1] += C.n_act;
+        v[2] += C.stage < park ? 1 : 0;
+        v[3] += (P->gemm_min > 0 && on_last && P->st[C.stage].kind == kDense && C.n_act >= P->gemm_min) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = max(v[0], __shfl_xor(v[0], o));
+        v[1] += __shfl_xor(v[1], o);
+        v[2] += __shfl_xor(v[2], o);
+        v[3] += __shfl_xor(v[3], o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; ++k) s_v[k][w] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        int a = s_v[k][0];
+        for (int q = 1; q < kBlock / 64; ++q) a = k == 0 ? max(a, s_v[k][q]) : a + s_v[k][q];
+        P->stat[k] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Whole-solve state -> grid state, one block per signal.  The whole-solve kernel
+// keeps contiguous lists in slot 0 and reads x from its buffers; the grid kernels
+// read segmented lists of the iterate's parity with prefix counts and the
+// nonzero values beside the nonzero list.  A contiguous list is a segmented one
+// whose segment s starts at min(kSeg s, n), so the lists only move when the
+// parity is 1.  The state enters both control slots with advance = 0: the next
+// forward launch (slot 0, reading slot 1) takes it as is, like the state of the
+// initialisation kernel.  Each block reads only its own signal's slot-0 lists
+// before writing its slot-1 lists (disjoint buffers).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSeg) void k_wg_to_grid(const SolveParams* __restrict__ P) {
+    const int b = blockIdx.x, batch = P->batch;
+    __shared__ Control s_c;
+    if (threadIdx.x == 0) s_c = P->ctrl[2 * b];
+    __syncthreads();
+    Control C = s_c;
+    if (C.done) {
+        if (threadIdx.x == 0) {
+            P->ctrl[2 * b + 1] = C;
+            P->cnt_fwd[b] = 0;
+            P->cnt_fwd[(size_t)batch + b] = 0;
+            *(int4*)(P->sig_stat + 4 * b) = make_int4(0, 0, 0, 0);
+        }
+        return;
+    }
+    const int par = uni(C.par), n_act = uni(C.n_act), n_nz = uni(C.n_nz);
+    const int nseg_act = max(1, (n_act + kSeg - 1) / kSeg);
+    const int nseg_nz = (n_nz + kSeg - 1) / kSeg;
+    const int* a0 = actbuf(P, b, 0);
+    const int* z0 = nzbuf(P, b, 0);
+    int* a1 = actbuf(P, b, par);
+    int* z1 = nzbuf(P, b, par);
+    double* zx = nzxbuf(P, b, par);
+    const double* x = xbuf(P, b, par);
+    for (int i = threadIdx.x; i < n_act; i += kSeg) {
+        const int j = a0[i];
+        if (par) a1[i] = j;
+    }
+    for (int i = threadIdx.x; i < n_nz; i += kSeg) {
+        const int j = z0[i];
+        if (par) z1[i] = j;
+        zx[i] = x[j];
+    }
+    int* ap = actpre(P, b, par);
+    int* zp = nzpre(P, b, par);
+    for (int q = threadIdx.x; q <= nseg_act; q += kSeg) ap[q] = min(q * kSeg, n_act);
+    for (int q = threadIdx.x; q <= nseg_nz; q += kSeg) zp[q] = min(q * kSeg, n_nz);
+    if (threadIdx.x == 0) {
+        C.advance = 0;
+        C.nslot = 0;
+        C.nseg_act = nseg_act;
+        C.nseg_nz = nseg_nz;
+        P->ctrl[2 * b + 0] = C;
+        P->ctrl[2 * b + 1] = C;
+        P->cnt_fwd[b] = P->nrc;                       // slot 0
+        P->cnt_fwd[(size_t)batch + b] = 0;            // slot 1
+        P->cnt_adj[b] = 0;
+        P->cnt_adjk[b] = 0;
+        P->cnt_upd[b] = 0;
+        P->cnt_gemm[b] = 0;
+        *(int4*)(P->sig_stat + 4 * b) = make_int4(n_act, n_act, C.stage < P->n_stages - 1 ? 1 : 0, 0);
+    }
+}
+
+hipError_t launch_wg_stat(const SolveParams* dP, hipStream_t s) {
+    hipLaunchKernelGGL(k_wg_stat, dim3(1), dim3(kBlock), 0, s, dP);
+    return hipGetLastError();
+}
+
+hipError_t launch_wg_to_grid(const SolveParams* dP, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_wg_to_grid, dim3(batch), dim3(kSeg), 0, s, dP);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_wg(const SolveParams* dP, int batch, hipStream_t s) {

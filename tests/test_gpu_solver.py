@@ -169,11 +169,14 @@ def test_kronecker_tile_autotuner(sl1):
 ENGINES = ["grid", "wg"]
 
 
-# the hybrid engine hands over to its tail kernel after 2 iterations (chunk = 2), so the
-# tail's Gram mode (or its column mode) runs most of the traced iterations
+# the hybrid engine runs the Kronecker approximations in the whole-solve kernel and hands
+# the signal to its tail kernel on reaching A (or, approximations on the grid kernels, after
+# 2 iterations: chunk = 2), so the tail's Gram mode (or its column mode) runs most of the
+# traced iterations
 TRACE_ENGINES = {"grid": dict(engine="grid"), "wg": dict(engine="wg"),
                  "hybrid-gram": dict(engine="hybrid", chunk=2, tail_gram=True),
-                 "hybrid-columns": dict(engine="hybrid", chunk=2, tail_gram=False)}
+                 "hybrid-columns": dict(engine="hybrid", chunk=2, tail_gram=False),
+                 "hybrid-grid-first": dict(engine="hybrid", chunk=2, tail_gram=True, kron_first=False)}
 
 
 @pytest.mark.parametrize("engine", list(TRACE_ENGINES))
@@ -184,7 +187,7 @@ def test_fp64_trace_matches_method_reference(sl1, real, frac, engine):
     out = _run(sl1, p, tol=1e-10, trace_cap=5000, **TRACE_ENGINES[engine])
     if engine.startswith("hybrid"):
         assert sl1.last_solve_phases(1, p.N, p.K)[0] == "hybrid"
-        assert (sl1.last_solve_phases(1, p.N, p.K)[1]["gram_cap"] > 0) == engine.endswith("gram")
+        assert (sl1.last_solve_phases(1, p.N, p.K)[1]["gram_cap"] > 0) == TRACE_ENGINES[engine]["tail_gram"]
     ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[0], float(p.lam[0]),
                       [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10)
     n = int(out["iters"][0])
@@ -198,12 +201,13 @@ def test_fp64_trace_matches_method_reference(sl1, real, frac, engine):
     Gc = np.array([r.G_conv for r in ref.trace])
     # in Gram mode ||rho||^2 and y^T rho come from y^T y - c^T x and x^T G x: their FP64
     # rounding, ~n u (||y|| + sum |x_k| ||a_k||)^2, bounds the absolute gap difference
-    np.testing.assert_allclose(tr[:, 6], Gc, rtol=1e-7, atol=1e-10 if engine == "hybrid-gram" else 1e-12)
+    gram = engine in ("hybrid-gram", "hybrid-grid-first")
+    np.testing.assert_allclose(tr[:, 6], Gc, rtol=1e-7, atol=1e-10 if gram else 1e-12)
     approx = tr[:, 1] < len(p.stages) - 1
     np.testing.assert_allclose(tr[approx, 9], np.array([r.gamma for r in ref.trace])[approx], rtol=1e-6, atol=1e-9)
     # on A the rounding allowance (~1e-13 per atom) keeps gamma within a hair of 1; in Gram mode the
     # stable scaling also carries the Gram forms' error bound eta ||a_j|| (~1e-12 here)
-    tol_g = 1e-9 if engine == "hybrid-gram" else 1e-12
+    tol_g = 1e-9 if gram else 1e-12
     assert np.all(np.abs(tr[~approx, 9] - 1) <= tol_g * tr[~approx, 11] / np.maximum(tr[~approx, 5], 1e-300) + 1e-9)
     np.testing.assert_allclose(out["x"][0], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
     # and the Lasso solution itself
@@ -548,6 +552,37 @@ def test_hybrid_hand_over_matches_grid(sl1, gram):
         tr = h["trace"][b][:n]
         assert np.array_equal(tr[:, 0], np.arange(n))                  # one trace row per iteration
         assert np.all(tr[1:, 2] == tr[:-1, 3])                          # |A_t+1| carried over
+    for b in range(p.batch):
+        _check_solution(p, h, b)
+
+
+def test_hybrid_kron_first_matches_grid_first(sl1):
+    # the full batched dictionary on 12 signals: the Kronecker approximations run in the
+    # whole-solve kernel; signals that reach A with large preserved sets go on in the grid
+    # kernels (their lists converted), which later hand the rest to the tail kernel.  The
+    # decisions and solutions agree with the hybrid solve that runs the approximations on
+    # the grid kernels.
+    _say("hybrid, approximations in the whole-solve kernel vs on the grid, batched dictionary, 12 signals")
+    import paper_1812_06635_amd as m
+    p = synth.config4(batch=12)
+    g = _run(sl1, p, tol=1e-9, engine="hybrid", kron_first=False)
+    h = _run(sl1, p, tol=1e-9, engine="hybrid", trace_cap=4000, profile=True)
+    ph = m.last_solve_phases(p.batch, p.N, p.K)
+    prof = m.last_solve_profile(p.batch, p.N, p.K)
+    assert ph[0] == "hybrid"
+    assert ph[1]["wg_launches"] >= 2                       # the approximations' phase, then the tail
+    assert prof["fwd"][1] > 0 and prof["adj_kron"][1] == 0  # grid kernels on A only
+    assert g["status"] == 0 and h["status"] == 0
+    np.testing.assert_array_equal(g["stage"], h["stage"])
+    assert np.all(np.abs(g["iters"] - h["iters"]) <= 2), (g["iters"], h["iters"])
+    for b in range(p.batch):
+        rel = np.linalg.norm(g["x"][b] - h["x"][b]) / max(np.linalg.norm(g["x"][b]), 1e-300)
+        assert rel <= 1e-4, f"signal {b}: paths differ by {rel:.2e}"
+        n = int(h["iters"][b])
+        tr = h["trace"][b][:n]
+        assert np.array_equal(tr[:, 0], np.arange(n))                  # one trace row per iteration
+        assert np.all(tr[1:, 2] == tr[:-1, 3])                          # |A_t+1| carried over
+        assert np.all(np.diff(tr[:, 1]) >= 0)                           # stages only advance
     for b in range(p.batch):
         _check_solution(p, h, b)
 
