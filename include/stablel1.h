@@ -187,6 +187,10 @@ typedef struct {
                                      columns (no Gram mode) */
 #define SL1_FLAG_HYBRID_GRID_FIRST 1024 /* hybrid engine: run the Kronecker approximations on the grid
                                      kernels too (by default they run in the whole-solve kernel) */
+#define SL1_FLAG_GRID_SPLIT_STEP 2048   /* grid engine: chip-wide forward and update launches throughout
+                                     (by default, while every live signal can only be on dense stages
+                                     and without l_q bounds or the dome rule, one launch per iteration
+                                     does the update and the next forward, one block per signal) */
 #define SL1_FLAG_ISTA 64          /* ISTA update x_{t+1} = ST(x_t + A~^T rho~_t / L) (Section I-B)
                                      instead of FISTA */
 #define SL1_FLAG_NO_GEMM 256      /* grid engine: correlations of every signal stream its own preserved
@@ -393,8 +397,9 @@ int sl1_last_solve_clock(int64_t batch, int64_t N, int64_t K, long long* out, do
  * most recent sl1_solve with SL1_FLAG_PROFILE and these shapes: ms[k] total
  * milliseconds and launches[k] launch count of k = 0 forward/residual, 1 dense
  * correlations, 2 Kronecker correlations, 3 scalar block + test/update/compaction,
- * 4 batched dense correlations, 5 the pass that finishes row-split product tiles
- * (host arrays of 6).
+ * 4 batched dense correlations, 5 the pass that finishes row-split product tiles,
+ * 6 the per-signal step (update of one iteration and forward of the next; see
+ * SL1_FLAG_GRID_SPLIT_STEP) (host arrays of 7).
  */
 int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long long* launches);
 

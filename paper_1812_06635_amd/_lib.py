@@ -25,7 +25,8 @@ FLAG_RULE_DST = 128
 FLAG_NO_GEMM = 256
 FLAG_RULE_DOME = 512
 FLAG_HYBRID_GRID_FIRST = 1024
-GRID_KERNELS = 6
+FLAG_GRID_SPLIT_STEP = 2048
+GRID_KERNELS = 7
 ENGINE_GRID, ENGINE_WG, ENGINE_HYBRID = 1, 2, 3
 
 c_dict = ctypes.c_void_p

@@ -36,7 +36,7 @@ hipError_t launch_dense_norms(int, const void*, const float*, int, int, const do
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
 hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_solve_tail(const SolveParams*, int, size_t, int, hipStream_t);
-hipError_t launch_to_wg(const SolveParams*, int, hipStream_t);
+hipError_t launch_to_wg(const SolveParams*, int, int, hipStream_t);
 hipError_t launch_wg_stat(const SolveParams*, hipStream_t);
 hipError_t launch_wg_to_grid(const SolveParams*, int, hipStream_t);
 hipError_t launch_zero(void*, size_t, hipStream_t);
@@ -153,9 +153,9 @@ struct Workspace {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
     // captured chunks of grid iterations, one per launch set: bit 0 with the
     // Kronecker correlation launch, bit 1 with the batched correlation product
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
-    int graph_chunk[4] = {0, 0, 0, 0};
-    LaunchCfg graph_cfg[4] = {};
+    hipGraphExec_t graph[8] = {};           // chunk graphs by launch set (Kronecker, product, step)
+    int graph_chunk[8] = {};
+    LaunchCfg graph_cfg[8] = {};
     int last_gram_cap = 0;    // Gram capacity of the last hybrid tail (0: none)
     double* d_cy = nullptr;   // stable Dynamic Safe: [batch][K] a^T y on the exact dictionary (lazy)
     double* d_yy = nullptr;   // [batch] ||y||^2
@@ -424,6 +424,7 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     const size_t nseg1 = (size_t)w.nseg_max + 1, nb1 = (size_t)w.batch + 1;
     c.lds_fwd = 4 * (2 * nseg1 + kFwdBlock + nb1) + 16 + kFwdBlock * 8 + 4 * 256 * 8 + (size_t)p.fwd_fac_lds;
     c.lds_upd = 4 * (nseg1 + nb1);
+    c.lds_step = 4 * ((nseg1 + 3) & ~(size_t)3) + 4 * kFwdBlock + 16 + 8 * kFwdBlock + 8 * 4 * 256;
     // persistent grids: enough blocks to fill the chip, never more than the work;
     // a correlation kernel whose stage kind is absent is not launched
     bool dense = false;
@@ -485,7 +486,8 @@ bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
            a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_adjk == b.g_adjk && a.g_upd == b.g_upd &&
            a.g_gemm == b.g_gemm && a.g_lq == b.g_lq && a.dome == b.dome && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj &&
-           a.lds_adjk == b.lds_adjk && a.lds_upd == b.lds_upd && a.lds_gemm == b.lds_gemm;
+           a.lds_adjk == b.lds_adjk && a.lds_upd == b.lds_upd && a.lds_gemm == b.lds_gemm && a.step == b.step &&
+           a.lds_step == b.lds_step;
 }
 
 int check_lds(const LaunchCfg& c) {
@@ -1371,6 +1373,17 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     // spread a large preserved set over the chip.
     bool kron_first = hybrid && wlds && p.n_stages > 1 && !(o.flags & SL1_FLAG_HYBRID_GRID_FIRST);
     for (int i = 0; i + 1 < p.n_stages; ++i) kron_first = kron_first && p.st[i].kind == kKron;
+    // per-signal step launches (update of t and forward of t + 1 in one block per
+    // signal) replace the chip-wide forward and update launches while every live
+    // signal can only be on dense stages: from the start when every stage is dense,
+    // after the Kronecker approximations' whole-solve phase otherwise
+    bool step_ok = !dome && !(o.flags & SL1_FLAG_GRID_SPLIT_STEP);
+    bool all_dense = true;
+    for (int i = 0; i < p.n_stages; ++i) {
+        step_ok = step_ok && p.st[i].qmode == 0;
+        all_dense = all_dense && p.st[i].kind == kDense;
+    }
+    bool step_live = step_ok && all_dense;
     if (kron_first) {
         w->last_engine = SL1_ENGINE_HYBRID;
         p.wg_park = p.n_stages - 1;
@@ -1393,14 +1406,16 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
         }
         if (p.gemm_min > 0) p.gemm_on = s1[3] >= gemm_signals ? 1 : 0;
         if (!last_kron && s1[2] == 0) kron_live = false;
+        step_live = step_ok && s1[2] == 0;
         HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
         HIP_TRY(launch_wg_to_grid(w->dP, (int)batch, w->stream));
     }
     for (;;) {
         LaunchCfg ccfg = cfg;
-        if (!kron_live) ccfg.g_adjk = 0;
+        if (!kron_live || step_live) ccfg.g_adjk = 0;
         if (!p.gemm_on) ccfg.g_gemm = 0;
-        const int v = (ccfg.g_adjk > 0 ? 1 : 0) | (ccfg.g_gemm > 0 ? 2 : 0);
+        ccfg.step = step_live ? 1 : 0;
+        const int v = (ccfg.g_adjk > 0 ? 1 : 0) | (ccfg.g_gemm > 0 ? 2 : 0) | (ccfg.step ? 4 : 0);
         if (prof) {
             for (int it = 0; it < chunk; ++it)
                 for (int q = 0; q < kGridKernels; ++q) {
@@ -1422,8 +1437,8 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
         launched += chunk;
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
-            const bool run[kGridKernels] = {true, ccfg.g_adj > 0, ccfg.g_adjk > 0, true, ccfg.g_gemm > 0,
-                                            ccfg.g_gemm > 0};
+            const bool run[kGridKernels] = {!ccfg.step, ccfg.g_adj > 0, ccfg.g_adjk > 0, !ccfg.step, ccfg.g_gemm > 0,
+                                            ccfg.g_gemm > 0, ccfg.step != 0};
             for (int it = 0; it < chunk; ++it)
                 for (int k = 0; k < kGridKernels; ++k) {
                     if (!run[k]) continue;
@@ -1458,8 +1473,11 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
             const size_t tlds = wg_layout(p, true, stat1[0], gram);
             if (tlds && (stat1[0] <= hyb_atoms || stat1[0] <= p.wg_cap_gram)) {
                 HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
-                HIP_TRY(launch_one(0, 0, w->dP, cfg, w->stream));
-                HIP_TRY(launch_to_wg(w->dP, (int)batch, w->stream));
+                // after step launches the state of iteration t (correlations formed, update
+                // pending) is the tail's input; otherwise a forward launch first folds in
+                // the last update
+                if (!step_live) HIP_TRY(launch_one(0, 0, w->dP, cfg, w->stream));
+                HIP_TRY(launch_to_wg(w->dP, (int)batch, step_live ? 1 : 0, w->stream));
                 w->last_engine = SL1_ENGINE_HYBRID;
                 w->last_gram_cap = p.wg_cap_gram;
                 if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));

@@ -176,13 +176,15 @@ struct LaunchCfg {
     int g_fwd, g_adj, g_adjk, g_upd, g_gemm;  // persistent grid sizes (blocks; 0: launch skipped)
     int g_lq;                                  // l_q dual norms: batch, or 0 when every stage has q = 2
     int dome;                                  // the update kernel of the dome rule
-    size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm;
+    int step;                                  // per-signal step launches instead of forward + update
+    size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm, lds_step;
 };
 
 // grid kernels (profile order): forward, dense correlations, Kronecker correlations,
-// update, batched correlations; launch order within an iteration
-constexpr int kGridKernels = 6;
-constexpr int kIterOrder[kGridKernels] = {0, 1, 4, 5, 2, 3};
+// update, batched correlations, their finishing pass, per-signal step; launch order
+// within an iteration (the step, or the forward, first; the update last)
+constexpr int kGridKernels = 7;
+constexpr int kIterOrder[kGridKernels] = {6, 0, 1, 4, 5, 2, 3};
 
 // batched correlation tiles: 64 atoms x 64 signals per block
 constexpr int kGemmAtoms = 64;

@@ -1673,6 +1673,282 @@ __global__ __launch_bounds__(kBlock, 5) void k_upd_dome(const SolveParams* __res
     upd_body<true>(P, slot);
 }
 
+// ---------------------------------------------------------------------------
+// Per-signal step on dense stages: the update of iteration t and the forward of
+// iteration t + 1 in one block per signal (8 waves), so an iteration is this
+// launch and the correlation launches.  The update launch's work (scalar block,
+// stable GAP test, look-ahead count, FISTA step) and the switch decision are the
+// same per-element expressions as in k_upd and the forward launch; the new lists
+// are written contiguously (segment s of a list of n entries starts at
+// min(kSeg s, n)), so their prefix counts need no cross-block pass.
+//   reads  C_t from control slot 1 - slot (advance = 0: a fresh state, whose
+//          forward alone runs), the correlation maxima and residual sums of t;
+//   writes C_{t+1} with advance = 1 to slot `slot` (read by the correlation
+//          launches of the same slot and by the next step launch), the residual
+//          direction z and its sums, the correlation launches' item counts.
+// Every stage a signal can reach here is dense (the host's condition for
+// choosing this launch); no l_q bounds and no dome rule.
+// ---------------------------------------------------------------------------
+constexpr int kStepH = 4;            // preserved atoms per thread per pass of the update
+
+__device__ __forceinline__ void step_finish(const SolveParams* P, int b, int slot, const Control& C, const Scalars& S,
+                                            int status) {
+    Final F;
+    F.gap = S.Gt;
+    F.gap_cert = S.Gp + S.delta;
+    F.iters = C.iter;
+    F.stage = C.stage;
+    F.status = status;
+    F.par = C.par;
+    F.t0 = C.t0;
+    F.tconv = S.conv == 1 ? wall_clock64() : 0;
+    P->fin[b] = F;
+    Control D = C;
+    D.done = 1;
+    D.advance = 0;
+    P->ctrl[2 * b + slot] = D;
+    P->cnt_adj[b] = 0;
+    P->cnt_adjk[b] = 0;
+    P->cnt_upd[b] = 0;
+    P->cnt_gemm[b] = 0;
+    *(int4*)(P->sig_stat + 4 * b) = make_int4(0, 0, 0, 0);
+    atomicSub(P->active_signals, 1);
+}
+
+__global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __restrict__ P, int slot) {
+    extern __shared__ __align__(16) char smem[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
+    const int N = P->N, K = P->K, I = P->n_stages - 1;
+    int* s_pre = (int*)smem;                                    // nseg_max + 1 prefix counts
+    int* s_j = s_pre + ((P->nseg_max + 1 + 3) & ~3);            // staged nonzeros
+    double* s_x = (double*)(((uintptr_t)(s_j + kFwdBlock) + 15) & ~(uintptr_t)15);
+    double* s_u = s_x + kFwdBlock;                              // odd waves' row partials
+    __shared__ Control s_c;
+    __shared__ double s_red[96];
+    __shared__ int s_tmp[16];
+    if (tid == 0) s_c = P->ctrl[2 * b + (1 - slot)];
+    __syncthreads();
+    Control C = s_c;
+    if (C.done) {                 // stopped earlier: the record reaches this slot too
+        if (tid == 0) P->ctrl[2 * b + slot] = C;
+        return;
+    }
+    if (P->st[C.stage].kind != kDense) {   // outside this kernel's domain: refused
+        if (tid == 0) {
+            Scalars S = {};
+            step_finish(P, b, slot, C, S, SL1_ELIMIT);
+        }
+        return;
+    }
+    const bool stepped = C.advance != 0;
+    if (stepped) {
+        // ---- scalar block of iteration t (the maxima of the correlation launch) ----
+        Scalars S;
+        scalar_block(P, b, C, S, s_red);
+        if (S.conv) {
+            if (tid == 0) step_finish(P, b, slot, C, S, S.conv == 2 ? SL1_MAXITER : SL1_OK);
+            return;
+        }
+        const int par = C.par, n_act = C.n_act, nseg = C.nseg_act;
+        const int* ap = actpre(P, b, par);
+        for (int q = tid; q <= nseg; q += kFwdBlock) s_pre[q] = ap[q];
+        __syncthreads();
+        // ---- stable GAP test, look-ahead count, FISTA step, compaction ----
+        const StageDesc& st = P->st[C.stage];
+        const int* act = actbuf(P, b, par);
+        int* nact = actbuf(P, b, 1 - par);
+        int* nnz = nzbuf(P, b, 1 - par);
+        double* nnx = nzxbuf(P, b, 1 - par);
+        double* xc = xbuf(P, b, par);
+        double* xo = xbuf(P, b, 1 - par);
+        const double* gcur = gbuf(P, b, par);
+        const double* gprev = gbuf(P, b, 1 - par);
+        uint8_t* mask = P->mask + (size_t)b * K;
+        const int rule = P->rule;
+        const double invlam = uni(1.0 / C.lam), keep_min = 1.0 - P->margin;
+        const double beta = uni(S.beta), invL = st.invL, thr = uni(C.lam * st.invL);
+        const bool no_reject = C.iter % P->screen_every != 0;
+        const double* eI = P->st[I].eps;
+        const double cqI = P->st[I].cq;
+        int wpos = 0, zpos = 0;
+        double sv[2] = {0.0, 0.0};           // look-ahead count (+ rejected nonzeros), ||x_{t+1}||_1
+        for (int base = 0; base < n_act; base += kStepH * kFwdBlock) {
+            int jj[kStepH];
+            bool keep[kStepH], nzf[kStepH];
+            double xn[kStepH];
+#pragma unroll
+            for (int h = 0; h < kStepH; ++h) {
+                const int i = base + h * kFwdBlock + tid;
+                jj[h] = 0;
+                keep[h] = nzf[h] = false;
+                xn[h] = 0.0;
+                if (i < n_act) jj[h] = list_get(act, s_pre, nseg, i);
+            }
+#pragma unroll
+            for (int h = 0; h < kStepH; ++h) {
+                const int i = base + h * kFwdBlock + tid;
+                if (i < n_act) {
+                    const int j = jj[h];
+                    const double gt = gcur[j], gp = gprev[j], xt = xc[j], xp = xo[j];
+                    const double e = st.eps[j], an = P->atom_norm[j], atn = st.at_norm[j];
+                    const double cyj = rule ? P->cy[(size_t)b * K + j] : 0.0;
+                    const double eIj = rule ? eI[j] * cqI : 0.0;
+                    double kt = 0.0;
+                    bool k = atom_test(rule, S, invlam, S.Rp, fabs(gt), e, an, atn, fabs(cyj), eIj, keep_min, kt);
+                    if (no_reject) k = true;
+                    const double zpt = xt + beta * (xt - xp);
+                    const double hh = (1.0 + beta) * gt - beta * gp;
+                    const double v = zpt + hh * invL;
+                    double x1 = 0.0;
+                    if (k) x1 = (v > thr) ? v - thr : ((v < -thr) ? v + thr : 0.0);
+                    xo[j] = x1;
+                    if (!k) {
+                        xc[j] = 0.0;
+                        mask[j] = 0;
+                        if (xt != 0.0) kt += kRejNz;
+                    }
+                    sv[0] += kt;
+                    sv[1] += fabs(x1);
+                    keep[h] = k;
+                    nzf[h] = k && x1 != 0.0;
+                    xn[h] = x1;
+                }
+            }
+            // positions in list order: keep and nonzero counts in one scan (each below 2^16)
+#pragma unroll
+            for (int h = 0; h < kStepH; ++h) {
+                int ex;
+                const int tot = block_excl_scan((keep[h] ? 1 : 0) | (nzf[h] ? 0x10000 : 0), ex, s_tmp);
+                if (keep[h]) nact[wpos + (ex & 0xFFFF)] = jj[h];
+                if (nzf[h]) {
+                    nnz[zpos + (ex >> 16)] = jj[h];
+                    nnx[zpos + (ex >> 16)] = xn[h];
+                }
+                wpos += tot & 0xFFFF;
+                zpos += tot >> 16;
+            }
+        }
+        block_sum<2>(sv, s_red);
+        // ---- Algorithm 2 and the momentum sequence ----
+        const double rnz = floor(sv[0] / kRejNz);     // rejected nonzero coefficients
+        const double kt = sv[0] - rnz * kRejNz;
+        const int i_new = switch_dictionary(C.stage, I, S.gamma, P->Gamma, kt, st.rc, (double)K);
+        if (tid == 0 && P->trace && C.iter < P->trace_cap) {
+            double* tr = P->trace + ((size_t)b * P->trace_cap + C.iter) * SL1_TRACE_FIELDS;
+            tr[0] = C.iter; tr[1] = C.stage; tr[2] = C.n_act; tr[3] = wpos;
+            tr[4] = kt;
+            tr[5] = S.Gp; tr[6] = S.Gt; tr[7] = S.delta; tr[8] = rule ? S.Rd : S.Rp; tr[9] = S.gamma;
+            tr[10] = C.l1; tr[11] = S.P; tr[12] = C.n_nz;
+        }
+        if (i_new != C.stage || rnz > 0.0) {   // a switch, or a rejection that zeroed x_t[j]: restart
+            C.stage = i_new;
+            C.ksince = 0;
+            C.tau = 1.0;
+        } else {
+            C.ksince += 1;
+            C.tau = S.tau_next;
+        }
+        C.iter += 1;
+        C.par = 1 - par;
+        C.n_act = wpos;
+        C.n_nz = zpos;
+        C.l1 = sv[1];
+        C.nseg_act = max(1, (wpos + kSeg - 1) / kSeg);
+        C.nseg_nz = (zpos + kSeg - 1) / kSeg;
+        int* pa = actpre(P, b, C.par);
+        int* pz = nzpre(P, b, C.par);
+        for (int q = tid; q <= C.nseg_act; q += kFwdBlock) pa[q] = min(q * kSeg, wpos);
+        for (int q = tid; q <= C.nseg_nz; q += kFwdBlock) pz[q] = min(q * kSeg, zpos);
+        if (P->st[C.stage].kind != kDense) {   // a structured later stage: not this kernel's domain
+            if (tid == 0) step_finish(P, b, slot, C, S, SL1_ELIMIT);
+            return;
+        }
+    }
+    // ---- forward of the (new) iteration: u = A~ x over the nonzero list, rho = y - u ----
+    const StageDesc& st = P->st[C.stage];
+    const int par = C.par, nnz = C.n_nz, nseg_nz = C.nseg_nz;
+    __syncthreads();                       // s_pre: the update's reads are done
+    if (stepped) {                         // the list this block just wrote is contiguous
+        for (int q = tid; q <= nseg_nz; q += kFwdBlock) s_pre[q] = min(q * kSeg, nnz);
+    } else {
+        const int* zp = nzpre(P, b, par);
+        for (int q = tid; q <= nseg_nz; q += kFwdBlock) s_pre[q] = zp[q];
+    }
+    __syncthreads();
+    const int* nzi = nzbuf(P, b, par);
+    const double* nzx = nzxbuf(P, b, par);
+    const int sub = w >> 1, half = w & 1;
+    for (int item = 0; item < P->nrc; ++item) {
+        const int r0 = item * kFwdRows + sub * 256 + lane * 4;
+        const bool rows_ok = r0 < N;
+        double yv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (half == 0 && rows_ok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) yv[v] = yval(P, b, r0 + v);
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int base = 0; base < nnz; base += kFwdBlock) {
+            const int cnt = min(kFwdBlock, nnz - base);
+            if (tid < cnt) {
+                const int pos = list_pos(s_pre, nseg_nz, base + tid);
+                s_j[tid] = nzi[pos];
+                s_x[tid] = nzx[pos];
+            }
+            __syncthreads();
+            const int ph = (cnt + 1) >> 1;
+            const int k0 = half ? ph : 0, k1 = half ? cnt : ph;
+            if (rows_ok && k0 < k1) {
+                switch (st.dtype) {
+                    case SL1_F64: fwd_dense_gather<SL1_F64>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case SL1_F32: fwd_dense_gather<SL1_F32>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case SL1_BF16: fwd_dense_gather<SL1_BF16>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    default: fwd_dense_gather<SL1_FP8_E4M3>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                }
+            }
+            __syncthreads();
+        }
+        if (half == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s_u[sub * 256 + lane * 4 + v] = acc[v];
+        }
+        __syncthreads();
+        double sums[3] = {0.0, 0.0, 0.0};
+        if (half == 0 && rows_ok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double rho = yv[v] - (acc[v] + s_u[sub * 256 + lane * 4 + v]);
+                P->z[(size_t)b * N + r0 + v] = rho;
+                sums[0] += rho * rho;
+                sums[1] += rho * rho;
+                sums[2] += yv[v] * rho;
+            }
+        }
+        block_sum<3>(sums, s_red);        // its barriers also guard s_u for the next item
+        if (tid == 0) {
+            double* rp = P->res_part + ((size_t)b * P->nrc + item) * 3;
+            rp[0] = sums[0];
+            rp[1] = sums[1];
+            rp[2] = sums[2];
+        }
+    }
+    // ---- control record and item counts of this slot's correlation launches ----
+    if (tid == 0) {
+        const int items = adj_items(st, C.n_act, N);
+        const bool qual = P->gemm_min > 0 && C.stage == I && C.n_act >= P->gemm_min;
+        const bool gemm = qual && P->gemm_on;
+        Control D = C;
+        D.advance = 1;
+        D.nslot = gemm ? 4 * ((K + kGemmAtoms - 1) / kGemmAtoms) : 4 * items;
+        P->ctrl[2 * b + slot] = D;
+        *(int4*)(P->sig_stat + 4 * b) = make_int4(C.n_act, C.n_act, C.stage < I ? 1 : 0, qual ? 1 : 0);
+        P->cnt_adj[b] = gemm ? 0 : items;
+        P->cnt_adjk[b] = 0;
+        P->cnt_gemm[b] = gemm ? 1 : 0;
+        P->cnt_upd[b] = 0;
+    }
+}
+
 // warm start: x_0 = x_{-1} = x0 (device, batch x K), its nonzeros compacted in atom
 // order into the nonzero list of slot 0 (contiguous, so segment s begins at
 // min(256 s, n)), ||x_0||_1 into the control record.  One block per signal, after
@@ -1932,6 +2208,7 @@ __global__ __launch_bounds__(kBlock) void k_lq(const SolveParams* __restrict__ P
 hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCfg& c, hipStream_t s) {
     switch (which) {
         case 0:     // the forward, and the dual norms of solves with l_q bounds
+            if (c.step) break;
             hipLaunchKernelGGL(k_fwd, dim3(c.g_fwd), dim3(kFwdBlock), c.lds_fwd, s, dP, slot);
             if (c.g_lq > 0) hipLaunchKernelGGL(k_lq, dim3(c.g_lq), dim3(kBlock), 0, s, dP, slot);
             break;
@@ -1951,7 +2228,11 @@ hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCf
                                    c.g_gemm);
             }
             break;
+        case 6:     // the update of the previous iteration and this one's forward, per signal
+            if (c.step) hipLaunchKernelGGL(k_step, dim3(c.batch), dim3(kFwdBlock), c.lds_step, s, dP, slot);
+            break;
         default:
+            if (c.step) break;
             if (c.dome) hipLaunchKernelGGL(k_upd_dome, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
             else hipLaunchKernelGGL(k_upd, dim3(c.g_upd), dim3(kBlock), c.lds_upd, s, dP, slot);
             break;

@@ -1694,16 +1694,20 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
 }
 
 // ---------------------------------------------------------------------------
-// hand-over from the per-iteration grid kernels: after a forward launch of slot
-// 0 has formed C_{t+1} (ctrl[2 b]) and the segment prefixes of its two lists,
-// copy the segmented lists of buffer C.par into contiguous lists in buffer 0,
+// hand-over from the per-iteration grid kernels: the state C_t of control slot
+// `slot` (slot 0 after a forward launch has formed it with the segment prefixes
+// of its two lists; slot 1 after a chunk of step launches, whose state of
+// iteration t waits for its update, which the tail redoes from the top of the
+// iteration) goes to slot 0, where the tail kernel reads it, and the segmented
+// lists of buffer C.par are copied into contiguous lists in buffer 0,
 // the layout of the whole-solve kernel.  Segments go in increasing order, each
 // read completely before it is written, so the in-place case (par = 0) is safe:
 // a segment's destination never reaches a later segment's source.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSeg) void k_to_wg(const SolveParams* __restrict__ P) {
+__global__ __launch_bounds__(kSeg) void k_to_wg(const SolveParams* __restrict__ P, int slot) {
     const int b = blockIdx.x;
-    const Control C = P->ctrl[2 * b];
+    const Control C = P->ctrl[2 * b + slot];
+    if (slot != 0 && threadIdx.x == 0) P->ctrl[2 * b] = C;     // the tail reads slot 0
     if (C.done) return;
     const int par = uni(C.par);
     for (int which = 0; which < 2; ++which) {
@@ -1834,8 +1838,8 @@ hipError_t launch_wg_to_grid(const SolveParams* dP, int batch, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_to_wg(const SolveParams* dP, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_wg, dim3(batch), dim3(kSeg), 0, s, dP);
+hipError_t launch_to_wg(const SolveParams* dP, int batch, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_wg, dim3(batch), dim3(kSeg), 0, s, dP, slot);
     return hipGetLastError();
 }
 

@@ -571,7 +571,7 @@ def test_hybrid_kron_first_matches_grid_first(sl1):
     prof = m.last_solve_profile(p.batch, p.N, p.K)
     assert ph[0] == "hybrid"
     assert ph[1]["wg_launches"] >= 2                       # the approximations' phase, then the tail
-    assert prof["fwd"][1] > 0 and prof["adj_kron"][1] == 0  # grid kernels on A only
+    assert prof["step"][1] > 0 and prof["adj_kron"][1] == 0  # grid kernels on A only (step launches)
     assert g["status"] == 0 and h["status"] == 0
     np.testing.assert_array_equal(g["stage"], h["stage"])
     assert np.all(np.abs(g["iters"] - h["iters"]) <= 2), (g["iters"], h["iters"])
@@ -585,6 +585,45 @@ def test_hybrid_kron_first_matches_grid_first(sl1):
         assert np.all(np.diff(tr[:, 1]) >= 0)                           # stages only advance
     for b in range(p.batch):
         _check_solution(p, h, b)
+
+
+def _exact_only(p):
+    import dataclasses
+    return dataclasses.replace(p, stages=[p.stages[-1]])
+
+
+STEP_CASES = [
+    ("C1 exact stage alone, f64", lambda: _exact_only(synth.config1(realization=1, lam_frac=0.3))),
+    ("C3-small dense fp8 -> bf16 -> f32", lambda: synth.config3(N=256, K=1024, s=20, batch=3)),
+    ("C3 ragged N=2500 (three forward items)", lambda: synth.config3(N=2500, K=600, s=20, batch=2)),
+]
+
+
+@pytest.mark.parametrize("step", [True, False], ids=["step", "split"])
+@pytest.mark.parametrize("name,maker", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_dense_trace_matches_method_reference(sl1, name, maker, step):
+    # dense stages only: the grid engine's per-signal step launch (update of t and
+    # forward of t + 1 in one block) and the separate chip-wide launches give the
+    # method reference's trace, iteration by iteration
+    _say(f"dense trace vs method reference: {name}, step={step}")
+    import paper_1812_06635_amd as m
+    p = maker()
+    out = _run(sl1, p, tol=1e-10, engine="grid", trace_cap=6000, step=step, profile=True)
+    prof = m.last_solve_profile(p.batch, p.N, p.K)
+    assert (prof["step"][1] > 0) == step and (prof["fwd"][1] > 0) == (not step)
+    assert out["status"] == 0
+    for b in range(p.batch):
+        ref = osc.fast_l1([(s.values(), s.eps, s.L) for s in p.stages], p.atom_norm, p.Y[b], float(p.lam[b]),
+                          [s.rc_theory for s in p.stages], Gamma=0.5, tol=1e-10)
+        n = int(out["iters"][b])
+        assert ref.converged and n == ref.iters, (b, n, ref.iters)
+        tr = out["trace"][b][:n]
+        assert [int(r) for r in tr[:, 1]] == [r.stage for r in ref.trace]
+        assert [int(r) for r in tr[:, 2]] == [r.n_active for r in ref.trace]
+        assert [int(r) for r in tr[:, 3]] == [r.n_keep for r in ref.trace]
+        assert [int(r) for r in tr[:, 4]] == [r.K_t for r in ref.trace]
+        np.testing.assert_allclose(tr[:, 6], [r.G_conv for r in ref.trace], rtol=1e-7, atol=1e-12)
+        np.testing.assert_allclose(out["x"][b], ref.x, rtol=0, atol=1e-9 * max(1, np.abs(ref.x).max()))
 
 
 def _bf16_exact(p):
