@@ -93,32 +93,65 @@ def gemm_plan(S, N, K, batch):
     return tiles, -(-nch // cps)
 
 
-def product_rows(p, trace, iters, t_split, gemm_min, gemm_signals=64, chunk=16):
+def row_split(p, trace, iters, engine, grid_launches, kron_first):
+    """Per signal b, the rows (iterations) of each engine part: rows < s0[b] ran in
+    the whole-solve kernel on the Kronecker approximations (hybrid solve that runs
+    them there), rows in [s0[b], s1[b]) in the grid kernels, rows >= s1[b] in the
+    tail kernel (hybrid) or the whole-solve kernel (whole-solve engine)."""
+    import numpy as np
+    I = len(p.stages) - 1
+    B = trace.shape[0]
+    s0 = np.zeros(B, dtype=int)
+    s1 = np.zeros(B, dtype=int)
+    for b in range(B):
+        n = int(iters[b])
+        if engine == "wg":
+            continue
+        if engine == "grid":
+            s1[b] = n
+            continue
+        start = 0
+        if kron_first:
+            on = np.nonzero(trace[b, :n, 1] == I)[0]
+            start = int(on[0]) if len(on) else n
+        s0[b] = start
+        s1[b] = min(n, start + grid_launches)
+    return s0, s1
+
+
+def product_rows(p, trace, iters, s0, s1, gemm_min, gemm_signals=64, chunk=16, first_by_count=False):
     """(batch, T) mask of the grid rows whose correlations went through the batched
     product: the signal qualifies (exact dense stage, |A_t| >= gemm_min) and the
-    product ran in that chunk (the first chunk: batch >= gemm_signals; a later one:
-    at least gemm_signals signals qualified at the previous chunk's last row)."""
+    product ran in that chunk of grid launches (the first chunk: batch >= gemm_signals,
+    or, after the Kronecker whole-solve phase, that many signals qualify at their first
+    grid row; a later one: at least gemm_signals signals qualified at the previous
+    chunk's last row).  Column u of a signal is its grid row s0 + u."""
     import numpy as np
-    T = int(min(t_split, int(iters.max())))
+    B = trace.shape[0]
+    T = int(max(1, (s1 - s0).max()))
     I = len(p.stages) - 1
-    q = np.zeros((trace.shape[0], T), dtype=bool)
+    q = np.zeros((B, T), dtype=bool)
     if gemm_min <= 0 or p.stages[I].kind != "dense":
         return q
-    for b in range(trace.shape[0]):
-        n = min(int(iters[b]), T)
-        q[b, :n] = (trace[b, :n, 1] == I) & (trace[b, :n, 2] >= gemm_min)
+    for b in range(B):
+        n = int(s1[b] - s0[b])
+        r = trace[b, s0[b]:s1[b]]
+        q[b, :n] = (r[:, 1] == I) & (r[:, 2] >= gemm_min)
     cnt = q.sum(axis=0)
-    for t in range(T):
-        c = t // chunk
-        on = p.batch >= gemm_signals if c == 0 else cnt[c * chunk - 1] >= gemm_signals
+    for u in range(T):
+        c = u // chunk
+        if c == 0:
+            on = cnt[0] >= gemm_signals if first_by_count else p.batch >= gemm_signals
+        else:
+            on = cnt[c * chunk - 1] >= gemm_signals
         if not on:
-            q[:, t] = False
+            q[:, u] = False
     return q
 
 
-def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
-    """Algorithmic work of each kernel over one solve, from the trace (rows
-    t < t_split ran in the grid kernels, the rest in the tail kernel):
+def kernel_work(p, trace, iters, s0, s1, step, gram_cap=0, gemm_min=0, kron_first=False):
+    """Algorithmic work of each kernel over one solve, from the trace and the row
+    split of row_split:
       dense correlations  |A_t| N b bytes (b: bytes per stored element, + 4 B per
                           column scale); Kronecker correlations 2 R k2 n1 (n2 + k1)
                           flops (sum_r C_r^T P B_r);
@@ -129,20 +162,24 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
                           residual written (N (b_y + 8)) in the grid kernels;
       update              76 B per preserved atom in the grid kernels (the tail
                           keeps the per-atom state in LDS);
+      step                forward and update of the grid rows (one launch does the
+                          update of a row and the forward of the next);
       tail, Gram form     rows with |A_t| <= gram_cap: the |A_t| columns read once
                           to form G and A_t^T y, then no HBM traffic per iteration;
-      batched product     grid rows that went through it (product_rows): 2 N |A_t|
-                          FP64 flops (the needed entries; the product also forms
-                          the discarded ones, 2 N K per signal);
+      batched product     grid rows that went through it: 2 N |A_t| FP64 flops (the
+                          needed entries; the product also forms the discarded ones,
+                          2 N K per signal);
       finishing pass      the partial tiles of row-split product launches, read
-                          once (64 x 64 doubles per tile and split)."""
+                          once (64 x 64 doubles per tile and split);
+      Kronecker phase     rows before s0 (whole-solve kernel): the Kronecker
+                          correlations' matrix-core flops."""
     import numpy as np
     N = p.N
     w = dict(fwd_bytes=[0.0, 0.0], adj_bytes=[0.0, 0.0], adj_flops=[0.0, 0.0], upd_bytes=[0.0, 0.0],
              gram_bytes=0.0, gram_it=0, gemm_flops=0.0, gemm_exec_flops=0.0, gemm_it=0, fin_bytes=0.0,
-             dense_it=[0, 0], kron_it=[0, 0], faust_it=[0, 0])
+             dense_it=[0, 0], kron_it=[0, 0], faust_it=[0, 0], kwg_flops=0.0, kwg_it=0, step_bytes=0.0)
     I = len(p.stages) - 1
-    prod = product_rows(p, trace, iters, t_split, gemm_min)
+    prod = product_rows(p, trace, iters, s0, s1, gemm_min, first_by_count=kron_first)
     for S in prod.sum(axis=0):
         if S > 0:
             tiles, ks = gemm_plan(int(S), N, p.K, p.batch)
@@ -152,17 +189,27 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
     for b in range(trace.shape[0]):
         n = int(iters[b])
         rows = trace[b, :n]
-        part = (np.arange(n) >= t_split).astype(int)
+        t = np.arange(n)
+        kwg = t < s0[b]
+        part = np.where(t < s1[b], 0, 1)          # 0: grid kernels, 1: tail / whole-solve kernel
+        part[kwg] = 2
         gram = (part == 1) & (rows[:, 2] <= gram_cap) if gram_cap > 0 else np.zeros(n, dtype=bool)
         for s_idx, st in enumerate(p.stages):
             bpe = 0.0
             if st.kind == "dense":
                 bpe = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[st.dtype] + (4.0 / N if st.scale is not None else 0)
             on = rows[:, 1] == s_idx
+            if st.kind == "kron":
+                n1, k1, n2, k2 = st.dims
+                m = on & (part == 2)
+                w["kwg_flops"] += int(m.sum()) * 2.0 * st.R * k2 * n1 * (n2 + k1)
+                w["kwg_it"] += int(m.sum())
+            on = on & (part != 2)
             g = on & gram
             if s_idx == I and st.kind == "dense" and gemm_min > 0:
                 gm = np.zeros(n, dtype=bool)
-                gm[:prod.shape[1]] = prod[b, :min(n, prod.shape[1])]
+                u0, u1 = int(s0[b]), int(min(n, s0[b] + prod.shape[1]))
+                gm[u0:u1] = prod[b, :u1 - u0]
                 gm &= on
                 if gm.any():
                     w["gemm_flops"] += 2.0 * N * float(rows[gm, 2].sum())
@@ -202,6 +249,8 @@ def kernel_work(p, trace, iters, t_split, gram_cap=0, gemm_min=0):
                     w["adj_flops"][ph] += cnt * 2.0 * st.R * k2 * n1 * (n2 + k1)
                     w["fwd_bytes"][ph] += cnt * st.R * (n1 * k1 + n2 * k2) * fb
                     w["kron_it"][ph] += cnt
+    if step:
+        w["step_bytes"] = w["fwd_bytes"][0] + w["upd_bytes"][0]
     return w
 
 
@@ -229,6 +278,7 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail", kron_dtype=
                             frac=ach / peak, traffic=None, launches=launches, total_ms=ms,
                             avg_launch_us=ms * 1e3 / launches))
 
+    add("k_step", *prof.get("step", (0.0, 0)), work["step_bytes"], "hbm")
     add("k_fwd", *prof["fwd"], work["fwd_bytes"][0], "hbm")
     add("k_adj_dense", *prof["adj_dense"], work["adj_bytes"][0], "hbm")
     if work["faust_it"][0] > work["kron_it"][0]:    # structured launch running FAuST chains (FP64 vector)
@@ -242,8 +292,11 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail", kron_dtype=
             out[-1]["executed_tflops"] = work["gemm_exec_flops"] / (prof["adj_gemm"][0] * 1e-3) / 1e12
     if "gemm_fin" in prof:
         add("k_gemm_fin", *prof["gemm_fin"], work["fin_bytes"], "hbm")
-    if phases.get("wg_launches", 0) > 0:
-        add(tail_kernel, phases["wg_ms"], phases["wg_launches"],
+    kwg_ms = phases.get("kron_wg_ms", 0.0)
+    if kwg_ms > 0:              # the Kronecker approximations' whole-solve phase (one launch)
+        add("k_solve_wg", kwg_ms, 1, work["kwg_flops"], "mfma", MFMA_PEAK_TFLOPS[kron_dtype])
+    if phases.get("wg_launches", 0) > (1 if kwg_ms > 0 else 0):
+        add(tail_kernel, phases["wg_ms"] - kwg_ms, phases["wg_launches"] - (1 if kwg_ms > 0 else 0),
             work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1] + work["gram_bytes"], "hbm")
     out.sort(key=lambda e: -e["total_ms"])
     return out
@@ -289,8 +342,13 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
     _, phases = sl1.last_solve_phases(p.batch, p.N, p.K)
     trace = outp["trace"].cpu().numpy()
     iters = outp["iters"].cpu().numpy()
-    t_split = prof["fwd"][1] if phases.get("wg_launches", 0) > 0 else 10 ** 9
-    work = kernel_work(p, trace, iters, t_split, phases.get("gram_cap", 0), phases.get("gemm_min", 0))
+    step = prof.get("step", (0.0, 0))[1] > 0
+    grid_launches = prof["step"][1] if step else prof["fwd"][1]
+    kron_first = phases.get("kron_wg_ms", 0.0) > 0
+    s0, s1 = row_split(p, trace, iters, engine, grid_launches, kron_first)
+    work = kernel_work(p, trace, iters, s0, s1, step, phases.get("gram_cap", 0), phases.get("gemm_min", 0),
+                       kron_first)
+    t_split = grid_launches
     res = dict(
         ms_method=ms_m, ms_plain=ms_p, iters_method=it_m, iters_plain=it_p, engine=engine, engine_plain=engine_p,
         time_to_gap_ms_device=ttg_dev, max_gap_method=float(gap_m.max()), max_gap_plain=float(gap_p.max()),
@@ -312,9 +370,10 @@ def solve_block(sl1, torch, np, p, tol, steps, warmup, label):
 _GRID_SOURCES = ["paper_1812_06635_amd/csrc/sl1_kernels.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
                  "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
 TRAFFIC_SOURCES = {k: _GRID_SOURCES for k in ("k_adj_dense", "k_adj_gemm", "k_gemm_fin", "k_fwd", "k_upd",
-                                               "k_adj_kron")}
-TRAFFIC_SOURCES["k_solve_tail"] = ["paper_1812_06635_amd/csrc/sl1_wg.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
-                                   "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
+                                               "k_adj_kron", "k_step")}
+for _k in ("k_solve_tail", "k_solve_wg"):
+    TRAFFIC_SOURCES[_k] = ["paper_1812_06635_amd/csrc/sl1_wg.hip", "paper_1812_06635_amd/csrc/sl1_device.hpp",
+                           "paper_1812_06635_amd/csrc/sl1_internal.hpp", "include/stablel1.h"]
 
 
 def sources_sha256(kernel):

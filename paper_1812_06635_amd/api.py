@@ -314,11 +314,13 @@ def last_solve_profile(batch, N, K):
 def last_solve_phases(batch, N, K):
     """(engine name, {phase: ms}) of the last solve of this shape.  With
     profile=True the whole-solve part fills the phase times (workgroup ms summed
-    over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches";
+    over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches"; a
+    hybrid solve's whole-solve phase on the Kronecker approximations fills
+    "kron_wg_ms" (part of "wg_ms") and "kron_wg_phases" (its own four sums);
     "gram_cap" is the Gram capacity of a hybrid tail (0: none), "gemm_min" the
     |A_t| from which signals joined the batched correlation product (0: off)."""
     eng = L.c_i32()
-    ph = (L.c_d * 5)()
+    ph = (L.c_d * 10)()
     n = ctypes.c_longlong()
     gcap = L.c_i32()
     gmin = L.c_i32()
@@ -327,7 +329,9 @@ def last_solve_phases(batch, N, K):
     name = {L.ENGINE_GRID: "grid", L.ENGINE_WG: "wg", L.ENGINE_HYBRID: "hybrid"}.get(eng.value, "none")
     keys = ("fwd", "adj_dense", "gram", "upd", "wg_ms") if name == "hybrid" else \
         ("fwd", "adj_dense", "adj_kron", "upd", "wg_ms")
-    out = dict(zip(keys, list(ph)))
+    out = dict(zip(keys, list(ph)[:5]))
+    out["kron_wg_ms"] = ph[5]
+    out["kron_wg_phases"] = dict(zip(("fwd", "adj_dense", "adj_kron", "upd"), list(ph)[6:10]))
     out["wg_launches"] = n.value
     out["gram_cap"] = gcap.value
     out["gemm_min"] = gmin.value

@@ -166,6 +166,8 @@ struct Workspace {
     double phase_ms[kWgPhases] = {0, 0, 0, 0};
     double wg_ms = 0.0;                     // whole-solve launches of the last profiled solve
     long long wg_n = 0;
+    double park_phase_ms[kWgPhases] = {0, 0, 0, 0};   // the part of those of the Kronecker phase
+    double park_ms = 0.0;
     int last_engine = 0;
     std::vector<hipEvent_t> prof_ev;
     std::mutex mu;
@@ -674,6 +676,7 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
             HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
             w->wg_ms += ms;
             w->wg_n += 1;
+            if (mode == kWgPark) w->park_ms += ms;
         }
         if (*w->h_active <= 0 || launched >= cap) break;
         if (mode == kWgPark && w->h_active[4 + 2] == 0) break;
@@ -684,7 +687,11 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
         int khz = 0;
         HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         for (int64_t b = 0; b < batch; ++b)
-            for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] += (double)ticks[b * kWgPhases + k] / khz;
+            for (int k = 0; k < kWgPhases; ++k) {
+                const double v = (double)ticks[b * kWgPhases + k] / khz;
+                if (mode == kWgPark) w->park_phase_ms[k] += v;
+                else w->phase_ms[k] += v;
+            }
     }
     return SL1_OK;
 }
@@ -1335,8 +1342,8 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
             w->prof_ms[k] = 0.0;
             w->prof_n[k] = 0;
         }
-        for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] = 0.0;
-        w->wg_ms = 0.0;
+        for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] = w->park_phase_ms[k] = 0.0;
+        w->wg_ms = w->park_ms = 0.0;
         w->wg_n = 0;
     }
     if (use_wg) {
@@ -1857,8 +1864,12 @@ int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, 
     const Workspace& w = *it->second;
     *engine = w.last_engine;
     if (phase_ms) {
-        for (int k = 0; k < kWgPhases; ++k) phase_ms[k] = w.phase_ms[k];
+        for (int k = 0; k < kWgPhases; ++k) {
+            phase_ms[k] = w.phase_ms[k];
+            phase_ms[kWgPhases + 2 + k] = w.park_phase_ms[k];
+        }
         phase_ms[kWgPhases] = w.wg_ms;
+        phase_ms[kWgPhases + 1] = w.park_ms;
     }
     if (wg_launches) *wg_launches = w.wg_n;
     if (gram_cap) *gram_cap = w.last_gram_cap;

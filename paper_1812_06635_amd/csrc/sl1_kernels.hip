@@ -224,10 +224,11 @@ __device__ int advance_control(const SolveParams* P, int b, const Control& Cp, c
 // every load issued before the first product.  Kronecker: staged entries are
 // (j1 << 16) | j2; four atoms generated together, term by term.
 // ---------------------------------------------------------------------------
-template <int DT>
+// G: column loads in flight per lane per step (the forward launch keeps 2 or 4 to
+// stay within its registers; the per-signal step, 4 or 8)
+template <int DT, int G = (DT == SL1_F64 ? 2 : 4)>
 __device__ __forceinline__ void fwd_dense_gather(const StageDesc& st, int N, int r0, const int* s_j, const double* s_x,
                                                  int k0, int k1, double (&acc)[4]) {
-    constexpr int G = DT == SL1_F64 ? 2 : 4;
     constexpr bool kScaled = DT == SL1_BF16 || DT == SL1_FP8_E4M3;
     const float* scale = kScaled ? st.scale : nullptr;
     for (int k = k0; k < k1; k += G) {
@@ -1503,11 +1504,25 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
 __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scalars& S, double* s_red) {
     const int nslots = C.nslot;
     double mx[3] = {0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
-        const double* ap = P->adj_part + ((size_t)b * P->nadj_max * 4 + k) * 3;
-        mx[0] = fmax(mx[0], ap[0]);
-        mx[1] = fmax(mx[1], ap[1]);
-        mx[2] = fmax(mx[2], ap[2]);
+    // up to 8 slots per thread loaded together (one memory round trip per 8 blockDim slots)
+    const double* a0 = P->adj_part + (size_t)b * P->nadj_max * 4 * 3;
+    for (int base = 0; base < nslots; base += 8 * (int)blockDim.x) {
+        double v[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = base + u * blockDim.x + threadIdx.x;
+            const bool ok = k < nslots;
+            const double* ap = a0 + (size_t)(ok ? k : 0) * 3;
+            v[u][0] = ok ? ap[0] : 0.0;
+            v[u][1] = ok ? ap[1] : 0.0;
+            v[u][2] = ok ? ap[2] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            mx[0] = fmax(mx[0], v[u][0]);
+            mx[1] = fmax(mx[1], v[u][1]);
+            mx[2] = fmax(mx[2], v[u][2]);
+        }
     }
     double r2, zz, yz;
     reduce_res_max(P, b, s_red, mx, r2, zz, yz);
@@ -1773,17 +1788,28 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
         const double cqI = P->st[I].cq;
         int wpos = 0, zpos = 0;
         double sv[2] = {0.0, 0.0};           // look-ahead count (+ rejected nonzeros), ||x_{t+1}||_1
+        // a list of all K atoms is the identity (compactions keep the order); the
+        // next pass's list entries are requested before this pass's atom data is used
+        int jn[kStepH];
+#pragma unroll
+        for (int h = 0; h < kStepH; ++h) {
+            const int i = h * kFwdBlock + tid;
+            jn[h] = i < n_act ? (n_act == K ? i : list_get(act, s_pre, nseg, i)) : 0;
+        }
         for (int base = 0; base < n_act; base += kStepH * kFwdBlock) {
             int jj[kStepH];
             bool keep[kStepH], nzf[kStepH];
             double xn[kStepH];
 #pragma unroll
             for (int h = 0; h < kStepH; ++h) {
-                const int i = base + h * kFwdBlock + tid;
-                jj[h] = 0;
+                jj[h] = jn[h];
                 keep[h] = nzf[h] = false;
                 xn[h] = 0.0;
-                if (i < n_act) jj[h] = list_get(act, s_pre, nseg, i);
+            }
+#pragma unroll
+            for (int h = 0; h < kStepH; ++h) {
+                const int i = base + kStepH * kFwdBlock + h * kFwdBlock + tid;
+                jn[h] = i < n_act ? (n_act == K ? i : list_get(act, s_pre, nseg, i)) : 0;
             }
 #pragma unroll
             for (int h = 0; h < kStepH; ++h) {
@@ -1822,8 +1848,13 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
                 const int tot = block_excl_scan((keep[h] ? 1 : 0) | (nzf[h] ? 0x10000 : 0), ex, s_tmp);
                 if (keep[h]) nact[wpos + (ex & 0xFFFF)] = jj[h];
                 if (nzf[h]) {
-                    nnz[zpos + (ex >> 16)] = jj[h];
-                    nnx[zpos + (ex >> 16)] = xn[h];
+                    const int q = zpos + (ex >> 16);
+                    nnz[q] = jj[h];
+                    nnx[q] = xn[h];
+                    if (q < kFwdBlock) {      // the forward's first staged chunk, kept in LDS
+                        s_j[q] = jj[h];
+                        s_x[q] = xn[h];
+                    }
                 }
                 wpos += tot & 0xFFFF;
                 zpos += tot >> 16;
@@ -1890,7 +1921,9 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int base = 0; base < nnz; base += kFwdBlock) {
             const int cnt = min(kFwdBlock, nnz - base);
-            if (tid < cnt) {
+            // after an update a list of one chunk is already staged (and stays so for
+            // every item); longer lists are staged chunk by chunk
+            if (tid < cnt && !(stepped && nnz <= kFwdBlock)) {
                 const int pos = list_pos(s_pre, nseg_nz, base + tid);
                 s_j[tid] = nzi[pos];
                 s_x[tid] = nzx[pos];
@@ -1900,10 +1933,10 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
             const int k0 = half ? ph : 0, k1 = half ? cnt : ph;
             if (rows_ok && k0 < k1) {
                 switch (st.dtype) {
-                    case SL1_F64: fwd_dense_gather<SL1_F64>(st, N, r0, s_j, s_x, k0, k1, acc); break;
-                    case SL1_F32: fwd_dense_gather<SL1_F32>(st, N, r0, s_j, s_x, k0, k1, acc); break;
-                    case SL1_BF16: fwd_dense_gather<SL1_BF16>(st, N, r0, s_j, s_x, k0, k1, acc); break;
-                    default: fwd_dense_gather<SL1_FP8_E4M3>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case SL1_F64: fwd_dense_gather<SL1_F64, 4>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case SL1_F32: fwd_dense_gather<SL1_F32, 8>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    case SL1_BF16: fwd_dense_gather<SL1_BF16, 8>(st, N, r0, s_j, s_x, k0, k1, acc); break;
+                    default: fwd_dense_gather<SL1_FP8_E4M3, 8>(st, N, r0, s_j, s_x, k0, k1, acc); break;
                 }
             }
             __syncthreads();
