@@ -188,9 +188,12 @@ typedef struct {
 #define SL1_FLAG_HYBRID_GRID_FIRST 1024 /* hybrid engine: run the Kronecker approximations on the grid
                                      kernels too (by default they run in the whole-solve kernel) */
 #define SL1_FLAG_GRID_SPLIT_STEP 2048   /* grid engine: chip-wide forward and update launches throughout
-                                     (by default, while every live signal can only be on dense stages
-                                     and without l_q bounds or the dome rule, one launch per iteration
-                                     does the update and the next forward, one block per signal) */
+                                     (by default, for batches of at least 128 signals, while every live
+                                     signal can only be on dense stages and without l_q bounds or the
+                                     dome rule, one launch per iteration does the update and the next
+                                     forward, one block per signal) */
+#define SL1_FLAG_GRID_STEP 4096         /* grid engine: those per-signal step launches for any batch size
+                                     (not together with SL1_FLAG_GRID_SPLIT_STEP: SL1_EINVAL) */
 #define SL1_FLAG_ISTA 64          /* ISTA update x_{t+1} = ST(x_t + A~^T rho~_t / L) (Section I-B)
                                      instead of FISTA */
 #define SL1_FLAG_NO_GEMM 256      /* grid engine: correlations of every signal stream its own preserved

@@ -1289,6 +1289,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     p.lam = lambda;
     const int eng = o.flags & (SL1_FLAG_ENGINE_GRID | SL1_FLAG_ENGINE_WG | SL1_FLAG_ENGINE_HYBRID);
     if (eng & (eng - 1)) return SL1_EINVAL;   // at most one engine flag
+    if ((o.flags & SL1_FLAG_GRID_STEP) && (o.flags & SL1_FLAG_GRID_SPLIT_STEP)) return SL1_EINVAL;
     const bool gram = !(o.flags & SL1_FLAG_TAIL_COLUMNS);
     // the dome rule runs in the grid kernels only
     const size_t wlds = dome ? 0 : wg_layout(p, false, 0, false);
@@ -1384,7 +1385,11 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     // signal) replace the chip-wide forward and update launches while every live
     // signal can only be on dense stages: from the start when every stage is dense,
     // after the Kronecker approximations' whole-solve phase otherwise
-    bool step_ok = !dome && !(o.flags & SL1_FLAG_GRID_SPLIT_STEP);
+    // (a batch of fewer than 128 signals would leave most CUs idle: one block per
+    // signal streams its whole preserved set, where the split launches spread every
+    // signal's segments over the chip)
+    bool step_ok = !dome && !(o.flags & SL1_FLAG_GRID_SPLIT_STEP) &&
+                   (batch >= 128 || (o.flags & SL1_FLAG_GRID_STEP));
     bool all_dense = true;
     for (int i = 0; i < p.n_stages; ++i) {
         step_ok = step_ok && p.st[i].qmode == 0;

@@ -556,22 +556,25 @@ def test_hybrid_hand_over_matches_grid(sl1, gram):
         _check_solution(p, h, b)
 
 
-def test_hybrid_kron_first_matches_grid_first(sl1):
+@pytest.mark.parametrize("step", [True, False], ids=["step", "split"])
+def test_hybrid_kron_first_matches_grid_first(sl1, step):
     # the full batched dictionary on 12 signals: the Kronecker approximations run in the
     # whole-solve kernel; signals that reach A with large preserved sets go on in the grid
     # kernels (their lists converted), which later hand the rest to the tail kernel.  The
     # decisions and solutions agree with the hybrid solve that runs the approximations on
     # the grid kernels.
-    _say("hybrid, approximations in the whole-solve kernel vs on the grid, batched dictionary, 12 signals")
+    _say(f"hybrid, approximations in the whole-solve kernel vs on the grid, batched dictionary, 12 signals, "
+         f"step={step}")
     import paper_1812_06635_amd as m
     p = synth.config4(batch=12)
     g = _run(sl1, p, tol=1e-9, engine="hybrid", kron_first=False)
-    h = _run(sl1, p, tol=1e-9, engine="hybrid", trace_cap=4000, profile=True)
+    h = _run(sl1, p, tol=1e-9, engine="hybrid", trace_cap=4000, profile=True, step=step)
     ph = m.last_solve_phases(p.batch, p.N, p.K)
     prof = m.last_solve_profile(p.batch, p.N, p.K)
     assert ph[0] == "hybrid"
-    assert ph[1]["wg_launches"] >= 2                       # the approximations' phase, then the tail
-    assert prof["step"][1] > 0 and prof["adj_kron"][1] == 0  # grid kernels on A only (step launches)
+    assert ph[1]["wg_launches"] >= 2 and ph[1]["kron_wg_ms"] > 0   # the approximations' phase, then the tail
+    assert prof["adj_kron"][1] == 0                                 # grid kernels on A only
+    assert (prof["step"][1] > 0) == step and (prof["fwd"][1] > 0) == (not step)
     assert g["status"] == 0 and h["status"] == 0
     np.testing.assert_array_equal(g["stage"], h["stage"])
     assert np.all(np.abs(g["iters"] - h["iters"]) <= 2), (g["iters"], h["iters"])
