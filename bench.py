@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense precision block (N=2500, K=10000)")
     ap.add_argument("--parity-signals", type=int, default=0,
                     help="signals of the batched workload checked against the oracle (0: all)")
+    ap.add_argument("--blocks", default="batched,single,faust,dense",
+                    help="comma-separated blocks to run (profiling runs of one block; the JSON line's headline "
+                         "fields need 'batched')")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -635,10 +638,19 @@ def main():
     torch.cuda.set_device(0)
     sl1.load_library()
 
-    log("generating the batched workload (512 signals, N=1024, K=4096)")
-    p = synth.config4(batch=512)
-    res = solve_block(sl1, torch, np, p, args.tol, args.steps, args.warmup, "batched")
-    line = {
+    blocks = set(args.blocks.split(","))
+    args.no_single = args.no_single or "single" not in blocks
+    args.no_faust = args.no_faust or "faust" not in blocks
+    args.no_dense = args.no_dense or "dense" not in blocks
+    line = {"metric": "time-to-gap 1e-6 and FISTA iters/s (batched low-prec vs plain FP32), 1 GPU", "n_gpus": 1,
+            "blocks": sorted(blocks)}
+    if "batched" not in blocks:
+        args.no_parity = args.no_cpu = args.no_variants = True
+    else:
+        log("generating the batched workload (512 signals, N=1024, K=4096)")
+        p = synth.config4(batch=512)
+        res = solve_block(sl1, torch, np, p, args.tol, args.steps, args.warmup, "batched")
+    line = line if "batched" not in blocks else {
         "metric": "time-to-gap 1e-6 and FISTA iters/s (batched low-prec vs plain FP32), 1 GPU",
         "value": res["iters_method"] / (res["ms_method"] * 1e-3),
         "unit": "iter/s",
