@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense precision block (N=2500, K=10000)")
     ap.add_argument("--parity-signals", type=int, default=0,
                     help="signals of the batched workload checked against the oracle (0: all)")
-    ap.add_argument("--blocks", default="batched,single,faust,dense",
+    ap.add_argument("--blocks", default="batched,single,faust,dense,grad",
                     help="comma-separated blocks to run (profiling runs of one block; the JSON line's headline "
                          "fields need 'batched')")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -645,7 +645,7 @@ def main():
     line = {"metric": "time-to-gap 1e-6 and FISTA iters/s (batched low-prec vs plain FP32), 1 GPU", "n_gpus": 1,
             "blocks": sorted(blocks)}
     if "batched" not in blocks:
-        args.no_parity = args.no_cpu = args.no_variants = True
+        args.no_cpu = args.no_variants = True
     else:
         log("generating the batched workload (512 signals, N=1024, K=4096)")
         p = synth.config4(batch=512)
@@ -686,14 +686,14 @@ def main():
         "roofline_kernels": res["roofline_kernels"],
     }
     ref = None
-    if not args.no_parity or not args.no_cpu:
+    if "batched" in blocks and (not args.no_parity or not args.no_cpu):
         idx = None if args.parity_signals <= 0 else \
             np.unique(np.linspace(0, p.batch - 1, min(args.parity_signals, p.batch)).astype(int)).tolist()
         if args.no_parity:
             idx = [0, 1, 2, 3]
         log(f"batched: FP64 oracle on {p.batch if idx is None else len(idx)} signals")
         ref = oracle_reference(p, idx, "batched")
-    if not args.no_parity:
+    if "batched" in blocks and not args.no_parity:
         line["parity"] = block_parity(np, p, res, ref, args.tol)
     if not args.no_variants:
         log("update / test variants on the batched workload (1 timed solve each)")
@@ -762,7 +762,57 @@ def main():
         if not args.no_parity:
             line["dense_precision"]["parity"] = block_parity(np, q, r4, oracle_reference(q, [0, 12, 24], "dense"),
                                                              args.tol)
+    if "grad" in blocks:
+        log("gradient block (implicit adjoint, N=4096, K=16384, R=8, 64 signals)")
+        line["gradient"] = grad_block(sl1, torch, np, args)
     print(json.dumps(line))
+
+
+def grad_block(sl1, torch, np, args):
+    """The implicit adjoint (sl1_grad) after the differentiation workload's solve: 64
+    signals, 40-sparse x0, lambda = 0.5 lambda_max, loss ||x - x0||^2 (dL/dx = 2 (x - x0)).
+    Work per signal with support s: the Gram matrix N s (s + 1) flops, Cholesky s^3 / 3,
+    two substitutions 2 s^2, dL/dy = A_S w 2 N s (FP64, vector units).  Error: against the
+    closed form on the FP64 oracle's support for two signals."""
+    import synth
+    q = synth.config5(batch=64)
+    st, Y, lam, an = upload(sl1, torch, q)
+    L = [s.L for s in q.stages]
+    rc = sl1.measure_rc(st, batch=q.batch)
+    out = sl1.solve(st, L, rc, an, Y, lam, tol=1e-10)
+    x = out["x"]
+    dx = 2.0 * (x - torch.from_numpy(q.X0).to(x.device))
+    exact = st[-1]
+    steps = max(3, args.steps)
+    ms, res = timed(torch, lambda: sl1.grad(exact, x, Y, lam, dx), steps, 1)
+    dy, dlam = res
+    sup = (x != 0).sum(dim=1).cpu().numpy().astype(np.int64)
+    N = q.N
+    flops = float(np.sum(N * sup * (sup + 1) + sup ** 3 / 3.0 + 2.0 * sup ** 2 + 2.0 * N * sup))
+    ach = flops / (ms * 1e-3) / 1e12
+    entry = {"workload": "N=4096 (64x64), K=16384 (128x128), A = sum_{r<=8} B_r kron C_r + 0.01 G (FP32), 64 "
+                         "signals, 40-sparse x0, lambda = 0.5 lambda_max; loss ||x - x0||^2 after the solve to gap "
+                         "1e-10; sl1_grad on the exact dictionary",
+             "ms_per_call": ms, "support": {"min": int(sup.min()), "median": float(np.median(sup)),
+                                             "max": int(sup.max())},
+             "fp64_flops_per_call": flops,
+             "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": ach / FP64_PEAK_TFLOPS}}
+    if not args.no_parity:
+        import oracle.lasso as ol
+        dyn, dln = dy.cpu().numpy().astype(np.float64), dlam.cpu().numpy()
+        worst = 0.0
+        for b in (0, 1):
+            sol = ol.solve(q.A, q.Y[b], float(q.lam[b]), L=q.stages[-1].L, tol=1e-15)
+            S = np.flatnonzero(sol["x"])
+            AS = q.A[:, S]
+            w = np.linalg.solve(AS.T @ AS, 2.0 * (sol["x"] - q.X0[b])[S])
+            g_ref, l_ref = AS @ w, -np.sign(sol["x"][S]) @ w
+            worst = max(worst, float(np.linalg.norm(dyn[b] - g_ref) / np.linalg.norm(g_ref)),
+                        abs(float(dln[b]) - l_ref) / max(abs(l_ref), 1e-300))
+        entry["parity"] = {"signals": [0, 1], "max_rel_error_vs_oracle_closed_form": worst}
+    log(f"gradient: {ms:.3f} ms per call, supports {int(sup.min())}-{int(sup.max())}, {ach:.3f} TFLOP/s FP64")
+    return entry
 
 
 if __name__ == "__main__":

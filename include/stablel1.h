@@ -348,7 +348,9 @@ int sl1_dict_adjoint(sl1_dict d, int64_t batch, const void* y, int y_dtype, doub
  *   y          batch x N in y_dtype (unused by the formula; kept for symmetry).
  *   dy         out, batch x N in y_dtype;  dlambda  out, batch doubles.
  * Returns SL1_ESINGULAR if a support Gram matrix is not positive definite,
- * SL1_ELIMIT if a support exceeds 1024 atoms or N.  Synchronous.
+ * SL1_ELIMIT if a support exceeds 1024 atoms or N.  Synchronous.  Its device
+ * memory is kept per device, grown to the largest call and held until the
+ * process ends; calls on one device are serialised.
  */
 int sl1_grad(sl1_dict A, int64_t batch, const double* x, const void* y, const double* lambda,
              const double* dx, void* dy, double* dlambda, int y_dtype, void* stream);

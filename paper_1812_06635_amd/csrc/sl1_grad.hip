@@ -5,11 +5,13 @@
 // G = A_S^T A_S, and for an incoming gradient v = dL/dx:
 //   dL/dy = A_S G^{-1} v_S,   dL/dlambda = -s^T G^{-1} v_S.
 // Steps (FP64): compact S per signal, build G (one block per row), Cholesky
-// factorisation and two triangular solves (one block per signal), then A_S w.
+// factorisation and two triangular solves (one block per signal, every thread
+// taking part), then A_S w.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
-#include "sl1_internal.hpp"
+#include "sl1_device.hpp"
 
 namespace sl1 {
 
@@ -91,6 +93,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_gram(GradDict d, const int* sid
 }
 
 // In-place Cholesky G = L L^T (lower), then L L^T w = v; one block per signal.
+// Right-looking factorisation: per column k the pivot, the column scaled, then the
+// trailing lower triangle (pairs j <= i, spread over the block); the substitutions
+// are column-oriented (per k: w_k /= L_kk, then every thread updates its w_i), the
+// right-hand side and the solution in LDS.
 __global__ __launch_bounds__(kBlock) void k_grad_solve(const int* sidx, const int* cnt, const double* sgn, double* G,
                                                       const double* dx, int K, double* wout, double* dlam, int* flag,
                                                       int ld) {
@@ -101,13 +107,16 @@ __global__ __launch_bounds__(kBlock) void k_grad_solve(const int* sidx, const in
         return;
     }
     double* Gb = G + (size_t)b * ld * ld;
-    double* w = wout + (size_t)b * ld;
-    __shared__ double s_piv;
+    __shared__ double s_w[kGradMaxSupport];
+    __shared__ double s_piv, s_red[48];
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
-    __syncthreads();
-    double gmax = 0.0;
-    for (int k = 0; k < s; ++k) gmax = fmax(gmax, fabs(Gb[(size_t)k * ld + k]));
+    for (int i = threadIdx.x; i < s; i += kBlock) s_w[i] = dx[(size_t)b * K + sidx[(size_t)b * kGradMaxSupport + i]];
+    double gm = 0.0;
+    for (int k = threadIdx.x; k < s; k += kBlock) gm = fmax(gm, fabs(Gb[(size_t)k * ld + k]));
+    double gmv[1] = {gm};
+    block_max<1>(gmv, s_red);
+    const double gmax = gmv[0];
     for (int k = 0; k < s; ++k) {
         if (threadIdx.x == 0) {
             const double d = Gb[(size_t)k * ld + k];
@@ -119,30 +128,45 @@ __global__ __launch_bounds__(kBlock) void k_grad_solve(const int* sidx, const in
         const double piv = s_piv;
         for (int i = k + 1 + threadIdx.x; i < s; i += kBlock) Gb[(size_t)i * ld + k] /= piv;
         __syncthreads();
-        // trailing update of the lower triangle: G[i][j] -= L[i][k] L[j][k], j <= i
+        // trailing update G[i][j] -= L[i][k] L[j][k] over k < j <= i < s: pair t = i' (i' + 1) / 2 + j'
         const int m = s - k - 1;
-        for (int t = threadIdx.x; t < m * m; t += kBlock) {
-            const int i = k + 1 + t / m, j = k + 1 + t % m;
-            if (j <= i) Gb[(size_t)i * ld + j] -= Gb[(size_t)i * ld + k] * Gb[(size_t)j * ld + k];
+        const long long pairs = (long long)m * (m + 1) / 2;
+        for (long long t = threadIdx.x; t < pairs; t += kBlock) {
+            int ii = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+            while ((long long)ii * (ii + 1) / 2 > t) --ii;
+            while ((long long)(ii + 1) * (ii + 2) / 2 <= t) ++ii;
+            const int jj = (int)(t - (long long)ii * (ii + 1) / 2);
+            const int i = k + 1 + ii, j = k + 1 + jj;
+            Gb[(size_t)i * ld + j] -= Gb[(size_t)i * ld + k] * Gb[(size_t)j * ld + k];
         }
         __syncthreads();
     }
+    // forward: L u = v_S
+    for (int k = 0; k < s; ++k) {
+        if (threadIdx.x == 0) s_w[k] /= Gb[(size_t)k * ld + k];
+        __syncthreads();
+        const double wk = s_w[k];
+        for (int i = k + 1 + threadIdx.x; i < s; i += kBlock) s_w[i] -= Gb[(size_t)i * ld + k] * wk;
+        __syncthreads();
+    }
+    // backward: L^T w = u
+    for (int k = s - 1; k >= 0; --k) {
+        if (threadIdx.x == 0) s_w[k] /= Gb[(size_t)k * ld + k];
+        __syncthreads();
+        const double wk = s_w[k];
+        for (int i = threadIdx.x; i < k; i += kBlock) s_w[i] -= Gb[(size_t)k * ld + i] * wk;
+        __syncthreads();
+    }
+    double* w = wout + (size_t)b * ld;
+    double dl[1] = {0.0};
+    for (int i = threadIdx.x; i < s; i += kBlock) {
+        w[i] = s_w[i];
+        dl[0] -= sgn[(size_t)b * kGradMaxSupport + i] * s_w[i];
+    }
+    block_sum<1>(dl, s_red);
     if (threadIdx.x == 0) {
         if (s_bad) atomicOr(flag, 1);
-        // forward: L u = v_S ; backward: L^T w = u
-        for (int i = 0; i < s; ++i) {
-            double acc = dx[(size_t)b * K + sidx[(size_t)b * kGradMaxSupport + i]];
-            for (int k = 0; k < i; ++k) acc -= Gb[(size_t)i * ld + k] * w[k];
-            w[i] = acc / Gb[(size_t)i * ld + i];
-        }
-        for (int i = s - 1; i >= 0; --i) {
-            double acc = w[i];
-            for (int k = i + 1; k < s; ++k) acc -= Gb[(size_t)k * ld + i] * w[k];
-            w[i] = acc / Gb[(size_t)i * ld + i];
-        }
-        double dl = 0.0;
-        for (int i = 0; i < s; ++i) dl -= sgn[(size_t)b * kGradMaxSupport + i] * w[i];
-        dlam[b] = dl;
+        dlam[b] = dl[0];
     }
 }
 
@@ -167,6 +191,33 @@ extern "C" int sl1_grad_impl_dense_info(sl1_dict_s* d, int* kind, int* dtype, in
 
 using namespace sl1;
 
+// Device memory of the gradient, per device: grown to the largest call and kept
+// until the process ends (calls on one device are serialised by its mutex).
+namespace {
+constexpr int kGradDevices = 64;
+struct GradWs {
+    std::mutex mu;
+    char* mem1 = nullptr;
+    size_t cap1 = 0;
+    char* mem2 = nullptr;
+    size_t cap2 = 0;
+};
+GradWs g_grad_ws[kGradDevices];
+
+int grad_reserve(char*& mem, size_t& cap, size_t bytes) {
+    if (bytes <= cap) return SL1_OK;
+    if (mem) (void)hipFree(mem);
+    mem = nullptr;
+    cap = 0;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        mem = nullptr;
+        return SL1_ENOMEM;
+    }
+    cap = bytes;
+    return SL1_OK;
+}
+}  // namespace
+
 extern "C" int sl1_grad(sl1_dict A, int64_t batch, const double* x, const void* y, const double* lambda,
                         const double* dx, void* dy, double* dlambda, int y_dtype, void* stream) {
     (void)y;
@@ -182,45 +233,42 @@ extern "C" int sl1_grad(sl1_dict A, int64_t batch, const double* x, const void* 
     if (kind != 0) return SL1_EDTYPE;
     if (N * 8 > 64 * 1024) return SL1_ELIMIT;
     hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kGradDevices) return SL1_EHIP;
+    GradWs& ws = g_grad_ws[dev];
+    std::lock_guard<std::mutex> lock(ws.mu);
     const size_t B = batch, M = kGradMaxSupport;
-    char* mem = nullptr;
     const size_t bytes1 = B * M * 4 + B * 4 + 16 + B * M * 8 + 64;
-    if (hipMalloc(&mem, bytes1) != hipSuccess) return SL1_ENOMEM;
+    if (grad_reserve(ws.mem1, ws.cap1, bytes1) != SL1_OK) return SL1_ENOMEM;
+    char* mem = ws.mem1;
     int* sidx = (int*)mem;
     int* cnt = (int*)(mem + B * M * 4);
     double* sgn = (double*)(((uintptr_t)(cnt + B) + 15) & ~(uintptr_t)15);
     int* flag = (int*)(sgn + B * M);
-    char* mem2 = nullptr;
-    auto fail = [&](int code) {
-        (void)hipFree(mem);
-        if (mem2) (void)hipFree(mem2);
-        return code;
-    };
     GradDict gd{dtype, (int)N, (int)K, Ap, sc};
     const bool f64 = y_dtype == SL1_F64;
-    if (hipMemsetAsync(flag, 0, 4, s) != hipSuccess) return fail(SL1_EHIP);
+    if (hipMemsetAsync(flag, 0, 4, s) != hipSuccess) return SL1_EHIP;
     hipLaunchKernelGGL(k_grad_support, dim3(B), dim3(kBlock), 0, s, x, (int)K, sidx, cnt, sgn);
     std::vector<int> hc(B);
-    if (hipMemcpyAsync(hc.data(), cnt, B * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(SL1_EHIP);
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(SL1_EHIP);
+    if (hipMemcpyAsync(hc.data(), cnt, B * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return SL1_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SL1_EHIP;
     int smax = 1;
     for (int c : hc) {
-        if (c > kGradMaxSupport || c > N) return fail(SL1_ELIMIT);
+        if (c > kGradMaxSupport || c > N) return SL1_ELIMIT;
         smax = std::max(smax, c);
     }
     const int ld = smax;
-    if (hipMalloc(&mem2, B * (size_t)ld * ld * 8 + B * (size_t)ld * 8) != hipSuccess) return fail(SL1_ENOMEM);
-    double* G = (double*)mem2;
+    if (grad_reserve(ws.mem2, ws.cap2, B * (size_t)ld * ld * 8 + B * (size_t)ld * 8) != SL1_OK) return SL1_ENOMEM;
+    double* G = (double*)ws.mem2;
     double* wv = G + B * (size_t)ld * ld;
     hipLaunchKernelGGL(k_grad_gram, dim3(smax, B), dim3(kBlock), N * 8, s, gd, sidx, cnt, G, ld);
     hipLaunchKernelGGL(k_grad_solve, dim3(B), dim3(kBlock), 0, s, sidx, cnt, sgn, G, dx, (int)K, wv, dlambda, flag, ld);
     if (f64) hipLaunchKernelGGL(k_grad_dy<double>, dim3((N + kBlock - 1) / kBlock, B), dim3(kBlock), 0, s, gd, sidx, cnt, wv, (double*)dy, ld);
     else hipLaunchKernelGGL(k_grad_dy<float>, dim3((N + kBlock - 1) / kBlock, B), dim3(kBlock), 0, s, gd, sidx, cnt, wv, (float*)dy, ld);
-    if (hipGetLastError() != hipSuccess) return fail(SL1_EHIP);
+    if (hipGetLastError() != hipSuccess) return SL1_EHIP;
     int hflag = 0;
-    if (hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(SL1_EHIP);
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(SL1_EHIP);
-    (void)fail(0);
+    if (hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return SL1_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SL1_EHIP;
     if (hflag & 2) return SL1_ELIMIT;
     if (hflag & 1) return SL1_ESINGULAR;
     return SL1_OK;
