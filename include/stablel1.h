@@ -299,7 +299,7 @@ int sl1_solve(const sl1_dict* seq, int n_stages, const double* L, const double* 
  * fill kernel at the start of each call.  The caller still passes every input and
  * output.  The dictionary handles are made beforehand with the sl1_dict_* calls.
  *   Limit: the workspace of (batch, N, K) must fit 64 MiB; it takes about
- *   batch * (89 K + 8 N + 1 KiB) bytes plus 16 MiB for the batched product's tiles,
+ *   batch * (89 K + 8 N + 9 KiB) bytes plus 16 MiB for the batched product's tiles,
  *   and batch * (8 K + 8) more with SL1_FLAG_RULE_DST or SL1_FLAG_RULE_DOME (e.g.
  *   up to ~130 signals at N = 1024, K = 4096).  Larger requests return SL1_ELIMIT
  *   before any device work.  SL1_FLAG_PROFILE is refused (SL1_EINVAL); the

@@ -31,6 +31,7 @@ int upd_resident_blocks(size_t);
 hipError_t gemm_lds_attr(size_t);
 hipError_t fwd_lds_attr(size_t);
 hipError_t adjk_lds_attr(size_t);
+hipError_t adjf_lds_attr(size_t);
 hipError_t launch_dense_norms(int, const void*, const float*, int, int, const double*, double, double*, double*,
                               int*, hipStream_t);
 hipError_t launch_eps_fold(const double*, const double*, double, int, double*, int*, hipStream_t);
@@ -226,7 +227,8 @@ size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     const size_t o_zq = take(B * 8);
     const size_t o_adp = take(B * w.nadj_max * 4 * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
-    const size_t o_cnt = take(B * 10 * 4);
+    const size_t o_cnt = take(B * 11 * 4);
+    const size_t o_fw = take(B * kFaustMaxDim * 8);
     const size_t o_gpart = take((size_t)kGemmSplitUnits * kGemmAtoms * kGemmSig * 8);
     const size_t o_act_sig = take(64);
     const size_t o_status = take(B * 4);
@@ -257,6 +259,8 @@ size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     p.cnt_upd = p.cnt_adjk + B;
     p.cnt_gemm = p.cnt_upd + B;
     p.sig_stat = p.cnt_gemm + B;
+    p.cnt_adjf = p.sig_stat + 4 * B;
+    p.fw = (double*)(m + o_fw);
     p.gemm_part = (double*)(m + o_gpart);
     p.active_signals = (int*)(m + o_act_sig);
     p.stat = p.active_signals + 4;
@@ -376,6 +380,7 @@ void fill_stage(StageDesc& s, const sl1_dict_s& d, double L, double rc) {
     s.fa = d.fa;
     s.fa_items = d.kind == kFaust ? (int)((d.K + kFaustAtoms - 1) / kFaustAtoms) : 0;
     s.fa_maxd = d.fa_maxd;
+    s.fa_dlast = d.fa_dlast;
     s.L = L;
     s.invL = 1.0 / L;
     s.rc = rc;
@@ -430,17 +435,20 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
     // persistent grids: enough blocks to fill the chip, never more than the work;
     // a correlation kernel whose stage kind is absent is not launched
     bool dense = false;
-    int kron_items = 0;
-    size_t extra = 0;
+    int kron_items = 0, faust_tiles = 0, faust_groups = 0;
+    size_t extra = 0, faust_lds = 0;
     for (int i = 0; i < p.n_stages; ++i) {
         const StageDesc& s = p.st[i];
         if (s.kind == kDense) {
             dense = true;
             continue;
         }
-        if (s.kind == kFaust) {      // FAuST items share the structured-correlation launch
-            kron_items = std::max(kron_items, s.fa_items);
-            extra = std::max(extra, 2 * (size_t)s.fa_maxd * 8);
+        if (s.kind == kFaust) {      // FAuST correlations: their own launch, all signals of a tile at once
+            faust_tiles = std::max(faust_tiles, s.fa_items);
+            const int dl = s.fa_dlast;
+            const int sg = faust_group(dl);
+            faust_groups = std::max(faust_groups, (w.batch + sg - 1) / sg);
+            faust_lds = std::max(faust_lds, faust_lds_bytes(dl, sg, w.batch));
             continue;
         }
         kron_items = std::max(kron_items, (s.k2 / s.kt2) * (s.k1 / s.kt1));
@@ -453,6 +461,10 @@ LaunchCfg launch_cfg(const Workspace& w, const SolveParams& p) {
         if (p.st[i].qmode != 0) c.g_lq = w.batch;
     c.g_adj = dense ? (int)std::min<long long>((long long)w.batch * w.nadj_max, 2048) : 0;
     c.g_adjk = kron_items ? (int)std::min<long long>((long long)w.batch * kron_items, 1024) : 0;
+    c.adjf_x = faust_tiles;
+    c.adjf_y = faust_tiles ? faust_groups : 0;
+    c.adjf_z = faust_tiles ? p.n_stages : 0;
+    c.lds_adjf = faust_lds;
     // update: one resident round of blocks (each block takes a contiguous range of items)
 #ifdef SL1_UPD_GRID
     const int upd_cap = SL1_UPD_GRID;
@@ -485,6 +497,7 @@ int gemm_min_atoms(const SolveParams& p) {
 }
 
 bool cfg_equal(const LaunchCfg& a, const LaunchCfg& b) {
+    if (a.adjf_x != b.adjf_x || a.adjf_y != b.adjf_y || a.adjf_z != b.adjf_z || a.lds_adjf != b.lds_adjf) return false;
     return a.batch == b.batch && a.nseg_max == b.nseg_max && a.nrc == b.nrc && a.nadj_max == b.nadj_max &&
            a.g_fwd == b.g_fwd && a.g_adj == b.g_adj && a.g_adjk == b.g_adjk && a.g_upd == b.g_upd &&
            a.g_gemm == b.g_gemm && a.g_lq == b.g_lq && a.dome == b.dome && a.lds_fwd == b.lds_fwd && a.lds_adj == b.lds_adj &&
@@ -624,8 +637,11 @@ int prepare(const sl1_dict* seq, int n_stages, const double* L, const double* rc
             const size_t fb = (size_t)d->R * ((size_t)d->n1 * d->k1 + (size_t)d->n2 * d->k2) * es;
             if (fb <= (size_t)kFwdFacLds) fac = std::max(fac, fb);
         }
-        if (d->kind == kFaust)      // the forward chain's vectors, scatter block and column bounds
+        if (d->kind == kFaust) {    // the forward chain's vectors, scatter block and column bounds; then
+                                    // z and the two vectors of the adjoint's chain
             fac = std::max(fac, (2 * (size_t)d->fa_maxd + (size_t)d->fa_dlast * d->fa_q) * 8 + 2 * (size_t)kFwdBlock * 4);
+            fac = std::max(fac, 3 * (size_t)d->fa_maxd * 8);
+        }
     }
     p.fwd_fac_lds = (int)fac;
     p.n_stages = n_stages;
@@ -1219,6 +1235,7 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     if (st != SL1_OK) return st;
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
+    if (cfg.lds_adjf > 64 * 1024) HIP_TRY(adjf_lds_attr(cfg.lds_adjf));
     if ((st = order_after(w, us)) != SL1_OK) return st;
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(clear_ws(w, w->d_active, 4));
@@ -1326,6 +1343,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     if (cfg.g_gemm > 0) HIP_TRY(gemm_lds_attr(cfg.lds_gemm));
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
+    if (cfg.lds_adjf > 64 * 1024) HIP_TRY(adjf_lds_attr(cfg.lds_adjf));
     p.gemm_min = cfg.g_gemm > 0 ? gemm_min_atoms(p) : 0;
     const int gemm_signals = o.gemm_signals > 0 ? o.gemm_signals : kGemmMinSignals;
     p.gemm_on = p.gemm_min > 0 && batch >= gemm_signals;
@@ -1371,7 +1389,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     // correlations once every live signal is on a dense last stage (stages only
     // advance), the batched product while the host has it switched off
     const bool last_kron = p.st[p.n_stages - 1].kind != kDense;      // a structured last stage
-    bool kron_live = cfg.g_adjk > 0;
+    bool kron_live = cfg.g_adjk > 0 || cfg.adjf_x > 0;
     // hybrid: Kronecker approximations run in the whole-solve kernel (one workgroup
     // per signal with the factors in LDS, no kernel boundary between iterations); a
     // signal stops there at the top of its first iteration on the last stage.  The
@@ -1424,10 +1442,13 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     }
     for (;;) {
         LaunchCfg ccfg = cfg;
-        if (!kron_live || step_live) ccfg.g_adjk = 0;
+        if (!kron_live || step_live) {
+            ccfg.g_adjk = 0;
+            ccfg.adjf_x = ccfg.adjf_y = ccfg.adjf_z = 0;
+        }
         if (!p.gemm_on) ccfg.g_gemm = 0;
         ccfg.step = step_live ? 1 : 0;
-        const int v = (ccfg.g_adjk > 0 ? 1 : 0) | (ccfg.g_gemm > 0 ? 2 : 0) | (ccfg.step ? 4 : 0);
+        const int v = (ccfg.g_adjk > 0 || ccfg.adjf_x > 0 ? 1 : 0) | (ccfg.g_gemm > 0 ? 2 : 0) | (ccfg.step ? 4 : 0);
         if (prof) {
             for (int it = 0; it < chunk; ++it)
                 for (int q = 0; q < kGridKernels; ++q) {
@@ -1449,8 +1470,8 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
         launched += chunk;
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
-            const bool run[kGridKernels] = {!ccfg.step, ccfg.g_adj > 0, ccfg.g_adjk > 0, !ccfg.step, ccfg.g_gemm > 0,
-                                            ccfg.g_gemm > 0, ccfg.step != 0};
+            const bool run[kGridKernels] = {!ccfg.step, ccfg.g_adj > 0, ccfg.g_adjk > 0 || ccfg.adjf_x > 0, !ccfg.step,
+                                            ccfg.g_gemm > 0, ccfg.g_gemm > 0, ccfg.step != 0};
             for (int it = 0; it < chunk; ++it)
                 for (int k = 0; k < kGridKernels; ++k) {
                     if (!run[k]) continue;
@@ -1634,6 +1655,7 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     if (st != SL1_OK) return st;
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
+    if (cfg.lds_adjf > 64 * 1024) HIP_TRY(adjf_lds_attr(cfg.lds_adjf));
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(w->ev_in, us));
     HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_in, 0));
@@ -1700,6 +1722,7 @@ static int time_adj(Workspace* w, const SolveParams& tmp, const StageDesc& sd, i
     if (st != SL1_OK) return st;
     if (cfg.lds_fwd > 64 * 1024) HIP_TRY(fwd_lds_attr(cfg.lds_fwd));
     if (cfg.lds_adjk > 64 * 1024) HIP_TRY(adjk_lds_attr(cfg.lds_adjk));
+    if (cfg.lds_adjf > 64 * 1024) HIP_TRY(adjf_lds_attr(cfg.lds_adjf));
     HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemsetAsync(w->d_active, 0, 4, w->stream));
     HIP_TRY(launch_init(w->dP, cfg, w->stream));

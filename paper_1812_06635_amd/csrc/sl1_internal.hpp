@@ -33,7 +33,7 @@ enum Kind { kDense = 0, kKron = 1, kFaust = 2 };
 // (FP64 or FP32), products accumulated in FP64.
 constexpr int kFaustMax = 8;          // factors
 constexpr int kFaustMaxDim = 1024;    // N and every inner dimension
-constexpr int kFaustAtoms = 1024;     // atoms per correlation item
+constexpr int kFaustAtoms = 64;       // atoms per correlation tile (one block: all its signals)
 struct FaustDesc {
     int J;
     int dim[kFaustMax + 1];
@@ -61,8 +61,9 @@ struct StageDesc {
     const double* eps;        // eps_j enlarged by the library's rounding bound
     const double* at_norm;    // ||a~_j||_2 (look-ahead estimate K_t)
     const FaustDesc* fa;      // FAuST factors (device) or nullptr
-    int fa_items;             // FAuST: correlation items (kFaustAtoms atoms each)
+    int fa_items;             // FAuST: correlation tiles (kFaustAtoms atoms each)
     int fa_maxd;              // FAuST: largest of N and the inner dimensions
+    int fa_dlast;             // FAuST: rows of the last factor (length of w = S_{J-1}^T ... S_1^T z)
     double L, invL, rc;
     double at_norm_max, eps_max;
     // norm q of the bounds eps (Lemma 1 with an l_q zone): qmode 0 for q = 2, 1 for
@@ -142,6 +143,8 @@ struct SolveParams {
     int* cnt_adjk;            // [batch] work items of the Kronecker correlation launch
     int* cnt_upd;             // [batch] work items of the update launch (current iteration)
     int* cnt_gemm;            // [batch] 1: the signal's correlations go through the batched product
+    int* cnt_adjf;            // [batch] stage + 1 while the signal's correlations are a FAuST stage's (0: not)
+    double* fw;               // [batch][kFaustMaxDim] FAuST stages: w = S_{J-1}^T ... S_1^T z of the iteration
     double* gemm_part;        // [kGemmSplitUnits][64 * 64] partial tiles of a split product launch
     int gemm_min;             // |A_t| from which a signal on the exact dense stage qualifies (0: never)
     int gemm_on;              // the batched product runs (set by the host between chunks)
@@ -177,7 +180,8 @@ struct LaunchCfg {
     int g_lq;                                  // l_q dual norms: batch, or 0 when every stage has q = 2
     int dome;                                  // the update kernel of the dome rule
     int step;                                  // per-signal step launches instead of forward + update
-    size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm, lds_step;
+    int adjf_x, adjf_y, adjf_z;                // FAuST correlations: tiles x signal groups x stages (0: none)
+    size_t lds_fwd, lds_adj, lds_adjk, lds_upd, lds_gemm, lds_step, lds_adjf;
 };
 
 // grid kernels (profile order): forward, dense correlations, Kronecker correlations,
@@ -197,6 +201,20 @@ constexpr int kGemmSplitUnits = 512; // partial tiles of one split launch at mos
 constexpr int kGemmMinSignals = SL1_GEMM_MIN_SIGNALS;   // fewer qualifying signals: streaming is faster
 
 constexpr int kMaxBatch = 4096;     // per-launch work map lives in LDS
+
+// FAuST correlations: signals per block (their w vectors in LDS, rows padded to dl + 1
+// doubles, at most 96 KB) and the block's LDS bytes (the vectors, the signal list, and
+// each signal's iterate parity and ||z||)
+__host__ __device__ inline int faust_group(int dl) {
+    const int sg = (64 * 1024) / ((dl + 1) * 8);
+    return sg < 1 ? 1 : (sg > 64 ? 64 : sg);
+}
+// + per wave 4 atoms x 64 staged entries (index and value)
+constexpr int kFaustStage = 4 * 64 * 12;
+__host__ __device__ inline size_t faust_lds_bytes(int dl, int sg, int batch) {
+    return (size_t)sg * (size_t)(dl + 1) * 8 + (((size_t)batch + 1) * 4 + 15) / 16 * 16 + (size_t)64 * 16 +
+           (size_t)4 * kFaustStage;
+}
 
 // atoms per wave of the streaming correlation kernel: 4, 2 or 1 so that a wave keeps
 // about 2.5-6 KB of columns in flight (4 atoms of up to 3 KB, 2 of up to 6 KB, else 1)

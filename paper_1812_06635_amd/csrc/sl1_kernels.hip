@@ -122,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         P->cnt_fwd[P->batch + b] = 0;                    // slot 1
         P->cnt_adj[b] = 0;
         P->cnt_adjk[b] = 0;
+        P->cnt_adjf[b] = 0;
         P->cnt_upd[b] = 0;
         P->cnt_gemm[b] = 0;
         for (int k = 0; k < 4; ++k) P->sig_stat[4 * b + k] = 0;
@@ -370,6 +371,24 @@ __device__ __forceinline__ void faust_trows(const FaustDesc& F, int dtype, int l
     }
 }
 
+// w = S_{J-1}^T ... S_1^T z (z in va; va, vb: the chain's LDS vectors) into wg
+// (global); called by the whole block after z is in va, ends with a barrier.
+__device__ __forceinline__ void faust_chain_w(const StageDesc& st, double* va, double* vb, double* wg) {
+    __syncthreads();
+    const FaustDesc& F = *st.fa;
+    double* in = va;
+    double* out = vb;
+    for (int l = 0; l + 1 < F.J; ++l) {
+        faust_trows(F, st.dtype, l, in, out);
+        __syncthreads();
+        double* t = in;
+        in = out;
+        out = t;
+    }
+    for (int i = threadIdx.x; i < F.dim[F.J - 1]; i += blockDim.x) wg[i] = in[i];
+    __syncthreads();       // the region is reused by the block's next signal
+}
+
 // Forward product u = A~ x_t of a FAuST stage for one signal (all N <= 1024 rows):
 // v = S_J x from the nonzeros of x -- each nonzero's column of S_J (a row of S_J^T)
 // is scattered, q nonzeros at a time, into column c of an LDS block M[row][q]
@@ -523,6 +542,7 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                     P->ctrl[2 * b + slot] = D;
                     P->cnt_adj[b] = 0;
                     P->cnt_adjk[b] = 0;
+                    P->cnt_adjf[b] = 0;
                     P->cnt_upd[b] = 0;
                     P->cnt_gemm[b] = 0;
                     P->cnt_fwd[(size_t)prev * batch + b] = 0;
@@ -562,7 +582,8 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
                         *(int4*)(P->sig_stat + 4 * b) =
                             make_int4(C.n_act, C.n_act, C.stage < P->n_stages - 1 ? 1 : 0, qual ? 1 : 0);
                         P->cnt_adj[b] = (stn.kind == kDense && !gemm) ? items : 0;
-                        P->cnt_adjk[b] = stn.kind != kDense ? items : 0;     // Kronecker and FAuST
+                        P->cnt_adjk[b] = stn.kind == kKron ? items : 0;
+                        P->cnt_adjf[b] = stn.kind == kFaust ? C.stage + 1 : 0;
                         P->cnt_gemm[b] = gemm ? 1 : 0;
                         P->cnt_upd[b] = max(1, (C.n_act + kSeg - 1) / kSeg);
                         if (Cp.advance && P->trace && Cp.iter < P->trace_cap) {
@@ -683,6 +704,19 @@ __global__ __launch_bounds__(kFwdBlock, 4) void k_fwd(const SolveParams* __restr
             rp[0] = sums[0];
             rp[1] = sums[1];
             rp[2] = sums[2];
+        }
+        if (st.kind == kFaust) {
+            // the FAuST correlations' chain w = S_{J-1}^T ... S_1^T z of this signal (one
+            // item covers all N <= 1024 rows), for the launch that applies S_J^T to the
+            // w of many signals at once; z and the two chain vectors reuse the factor region
+            const FaustDesc& F = *st.fa;
+            double* va = (double*)s_fac;
+            double* vb = va + F.maxd;
+            if (half == 0 && rows_ok) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) va[r0 + v] = yv[v] - (acc[v] + s_u[sub * 256 + lane * 4 + v]);
+            }
+            faust_chain_w(st, va, vb, P->fw + (size_t)b * kFaustMaxDim);
         }
     }
 }
@@ -911,42 +945,6 @@ __device__ __forceinline__ void put_wave_max(const SolveParams* P, int b, int it
         ap[1] = mx[1];
         ap[2] = mx[2];
     }
-}
-
-// Correlations of one FAuST item (atoms c*kFaustAtoms ..): w = S_{J-1}^T ... S_1^T z
-// through two LDS vectors, then g_j = (S_J^T w)_j for the preserved atoms of the
-// item, with the per-wave maxima.  zs: z in LDS (FP64).  Called by the whole block.
-__device__ void adj_faust_item(const SolveParams* P, const StageDesc& st, int b, int c, const double* zs,
-                               double* region, double* gvec, double rz) {
-    const FaustDesc& F = *st.fa;
-    const int J = F.J, K = P->K;
-    const double* in = zs;
-    double* bufs[2] = {region, region + F.maxd};
-    for (int l = 0; l < J - 1; ++l) {
-        double* out = bufs[l & 1];
-        faust_trows(F, st.dtype, l, in, out);
-        __syncthreads();
-        in = out;
-    }
-    const int* ptr = F.tptr + F.tp[J - 1];
-    const int* idx = F.tidx + F.tz[J - 1];
-    const uint8_t* mask = P->mask + (size_t)b * K;
-    double mx[3] = {0.0, 0.0, 0.0};
-    const int a0 = c * kFaustAtoms, a1 = min(K, a0 + kFaustAtoms);
-    for (int j = a0 + threadIdx.x; j < a1; j += blockDim.x) {
-        if (!mask[j]) continue;
-        const int e0 = ptr[j], e1 = ptr[j + 1];
-        double s = 0.0;
-#pragma unroll 4
-        for (int e = e0; e < e1; ++e) s += faust_val(F.tval, F.tz[J - 1] + e, st.dtype) * in[idx[e]];
-        gvec[j] = s;
-        const double ej = st.eps[j];
-        mx[0] = fmax(mx[0], fabs(s) + ej * rz);
-        mx[1] = fmax(mx[1], fabs(s));
-        mx[2] = fmax(mx[2], ej);
-    }
-    put_wave_max(P, b, c, mx, true);
-    __syncthreads();                   // the chain vectors are reused by the next item
 }
 
 __device__ __forceinline__ void reduce_res(const SolveParams* P, int b, double* s_red, double& r2, double& zz,
@@ -1463,10 +1461,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
         const StageDesc& st = P->st[uni(C.stage)];
         const double* zs = (const double*)smem;
         double* gvec = gbuf(P, b, uni(C.par));
-        if (st.kind == kFaust) {
-            adj_faust_item(P, st, b, c, zs, (double*)extra, gvec, rz);
-            continue;
-        }
         double mx[3] = {0.0, 0.0, 0.0};
         const int ntc = st.k1 / st.kt1;
         const int a0 = (c / ntc) * st.kt2, cb0 = (c % ntc) * st.kt1;
@@ -1496,6 +1490,164 @@ __global__ __launch_bounds__(kBlock, 3) void k_adj_kron(const SolveParams* __res
             kron_item_bf16<uint16_t>(st, a0, cb0, (const float*)smem, (uint16_t*)extra, mask, gvec, rz, mx);
         __syncthreads();       // every read of V precedes the next item's phase 1
         put_wave_max(P, b, c, mx, true);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FAuST correlations g_j = (S_J^T w)_j for every signal on a FAuST stage, w =
+// S_{J-1}^T ... S_1^T z formed by the forward launch.  Block (tile, group, stage):
+// the tile's kFaustAtoms atoms for up to faust_group(dl) signals on that stage, whose
+// w vectors sit in LDS; each wave takes a quarter of the tile, four atoms at a time,
+// lane = signal.  The four atoms' entries of S_J^T are loaded once per wave with
+// coalesced loads (one per lane per atom, the next four atoms' loads issued before
+// this group's products), staged in the wave's LDS slice, and every lane runs the
+// four sums against its w, each atom's entries in order (as one signal's chain
+// would sum them).  Atoms with more than 64 entries take a plain loop.  Only
+// preserved atoms' g are written; each wave leaves its per-signal maxima in slot
+// (tile, wave).  The factor entries are read once per tile and group of signals
+// instead of once per signal.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void faust_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_faust(const SolveParams* __restrict__ P, int slot) {
+    extern __shared__ __align__(16) char smem[];
+    const int stage = blockIdx.z, tile = blockIdx.x, grp = blockIdx.y;
+    if (stage >= P->n_stages) return;
+    const StageDesc& st = P->st[stage];
+    if (st.kind != kFaust || tile >= st.fa_items) return;
+    const int K = P->K, batch = P->batch;
+    const FaustDesc& F = *st.fa;
+    const int dl = F.dim[F.J - 1];
+    const int sg = faust_group(dl), ld = dl + 1;
+    double* W = (double*)smem;
+    int* s_sig = (int*)(smem + (size_t)sg * ld * 8);
+    char* after_sig = smem + (size_t)sg * ld * 8 + (((size_t)batch + 1) * 4 + 15) / 16 * 16;
+    int* s_par = (int*)after_sig;
+    double* s_rz = (double*)(after_sig + 64 * 4 + 256);
+    char* stage_base = after_sig + (size_t)64 * 16;
+    __shared__ int s_tmp[16];
+    // the signals on this stage, in signal order
+    int run = 0;
+    for (int base = 0; base < batch; base += kBlock) {
+        const int b = base + threadIdx.x;
+        const int f = (b < batch && P->cnt_adjf[b] == stage + 1) ? 1 : 0;
+        int ex;
+        const int tot = block_excl_scan(f, ex, s_tmp);
+        if (f) s_sig[run + ex] = b;
+        run += tot;
+    }
+    const int g0 = grp * sg, ng = min(sg, run - g0);
+    if (ng <= 0) return;                      // block-uniform
+    if ((int)threadIdx.x < ng) {
+        const int b = s_sig[g0 + threadIdx.x];
+        const Control& C = P->ctrl[2 * b + slot];
+        double zz = 0.0;
+        for (int k = 0; k < P->nrc; ++k) zz += P->res_part[((size_t)b * P->nrc + k) * 3 + 1];
+        s_par[threadIdx.x] = C.par;
+        s_rz[threadIdx.x] = dual_norm_z(P, st, b, zz);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the group's w vectors: each wave copies every fourth signal's, eight loads in flight per lane
+    for (int q0 = w; q0 < ng; q0 += 8) {
+        const double* src0 = P->fw + (size_t)s_sig[g0 + q0] * kFaustMaxDim;
+        const double* src1 = q0 + 4 < ng ? P->fw + (size_t)s_sig[g0 + q0 + 4] * kFaustMaxDim : nullptr;
+        for (int i0 = 0; i0 < dl; i0 += 256) {
+            double v0[4], v1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 64 * u + lane;
+                v0[u] = i < dl ? src0[i] : 0.0;
+                v1[u] = (src1 && i < dl) ? src1[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 64 * u + lane;
+                if (i < dl) {
+                    W[(size_t)q0 * ld + i] = v0[u];
+                    if (src1) W[(size_t)(q0 + 4) * ld + i] = v1[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const bool on = lane < ng;
+    const int b = on ? s_sig[g0 + lane] : 0;
+    const double rz = on ? s_rz[lane] : 0.0;
+    double* gvec = gbuf(P, b, on ? s_par[lane] : 0);
+    const uint8_t* mask = P->mask + (size_t)b * K;
+    const int* tptr = F.tptr + F.tp[F.J - 1];
+    const int* tidx = F.tidx + F.tz[F.J - 1];
+    const long long vz = F.tz[F.J - 1];
+    const double* wl = W + (size_t)(on ? lane : 0) * ld;
+    int* sI = (int*)(stage_base + (size_t)w * kFaustStage);          // [4 atoms][64 entries]
+    double* sV = (double*)(sI + 4 * 64);
+    double mx[3] = {0.0, 0.0, 0.0};
+    const int per = kFaustAtoms / 4;
+    const int j0 = tile * kFaustAtoms + w * per, j1 = min(K, j0 + per);
+    // entries of the first four atoms, one per lane and atom
+    int e0[4], n[4];
+    int iv[4];
+    double vv[4];
+    auto fetch = [&](int jb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = jb + q;
+            const bool ok = j < j1;
+            e0[q] = ok ? tptr[j] : 0;
+            n[q] = ok ? tptr[j + 1] - e0[q] : 0;
+            const bool le = lane < n[q];
+            iv[q] = le ? tidx[e0[q] + lane] : 0;
+            vv[q] = le ? faust_val(F.tval, vz + e0[q] + lane, st.dtype) : 0.0;
+        }
+    };
+    if (j0 < j1) fetch(j0);
+    for (int jb = j0; jb < j1; jb += 4) {
+        int cn[4], ce[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cn[q] = n[q];
+            ce[q] = e0[q];
+            sI[q * 64 + lane] = iv[q];
+            sV[q * 64 + lane] = vv[q];
+        }
+        faust_wave_sync();
+        if (jb + 4 < j1) fetch(jb + 4);       // in flight during this group's sums
+        const int nmax = max(max(cn[0], cn[1]), max(cn[2], cn[3]));
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (nmax <= 64) {
+            for (int k = 0; k < nmax; ++k) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (k < cn[q]) acc[q] = fma(sV[q * 64 + k], wl[sI[q * 64 + k]], acc[q]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                for (int k = 0; k < cn[q]; ++k)
+                    acc[q] = fma(faust_val(F.tval, vz + ce[q] + k, st.dtype), wl[tidx[ce[q] + k]], acc[q]);
+        }
+        faust_wave_sync();                    // the slice is rewritten by the next group
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = jb + q;
+            if (on && j < j1 && mask[j]) {
+                gvec[j] = acc[q];
+                const double ej = st.eps[j];
+                mx[0] = fmax(mx[0], fabs(acc[q]) + ej * rz);
+                mx[1] = fmax(mx[1], fabs(acc[q]));
+                mx[2] = fmax(mx[2], ej);
+            }
+        }
+    }
+    if (on) {
+        double* ap = P->adj_part + (((size_t)b * P->nadj_max + tile) * 4 + w) * 3;
+        ap[0] = mx[0];
+        ap[1] = mx[1];
+        ap[2] = mx[2];
     }
 }
 
@@ -1724,6 +1876,7 @@ __device__ __forceinline__ void step_finish(const SolveParams* P, int b, int slo
     P->ctrl[2 * b + slot] = D;
     P->cnt_adj[b] = 0;
     P->cnt_adjk[b] = 0;
+    P->cnt_adjf[b] = 0;
     P->cnt_upd[b] = 0;
     P->cnt_gemm[b] = 0;
     *(int4*)(P->sig_stat + 4 * b) = make_int4(0, 0, 0, 0);
@@ -1977,6 +2130,7 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
         *(int4*)(P->sig_stat + 4 * b) = make_int4(C.n_act, C.n_act, C.stage < I ? 1 : 0, qual ? 1 : 0);
         P->cnt_adj[b] = gemm ? 0 : items;
         P->cnt_adjk[b] = 0;
+        P->cnt_adjf[b] = 0;
         P->cnt_gemm[b] = gemm ? 1 : 0;
         P->cnt_upd[b] = 0;
     }
@@ -2250,6 +2404,9 @@ hipError_t launch_one(int which, int slot, const SolveParams* dP, const LaunchCf
             break;
         case 2:
             if (c.g_adjk > 0) hipLaunchKernelGGL(k_adj_kron, dim3(c.g_adjk), dim3(kBlock), c.lds_adjk, s, dP, slot);
+            if (c.adjf_x > 0)
+                hipLaunchKernelGGL(k_adj_faust, dim3(c.adjf_x, c.adjf_y, c.adjf_z), dim3(kBlock), c.lds_adjf, s, dP,
+                                   slot);
             break;
         case 4:
             if (c.g_gemm > 0) hipLaunchKernelGGL(k_adj_gemm, dim3(c.g_gemm), dim3(kBlock), c.lds_gemm, s, dP, slot);
@@ -2306,6 +2463,10 @@ hipError_t launch_lambda_out(const SolveParams* dP, int batch, double* out, int3
 // the batched correlation kernel may use more than the default 64 KB of LDS
 hipError_t adjk_lds_attr(size_t lds) {
     return hipFuncSetAttribute((const void*)k_adj_kron, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t adjf_lds_attr(size_t lds) {
+    return hipFuncSetAttribute((const void*)k_adj_faust, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t fwd_lds_attr(size_t lds) {

@@ -1822,6 +1822,7 @@ __global__ __launch_bounds__(kSeg) void k_wg_to_grid(const SolveParams* __restri
         P->cnt_fwd[(size_t)batch + b] = 0;            // slot 1
         P->cnt_adj[b] = 0;
         P->cnt_adjk[b] = 0;
+        P->cnt_adjf[b] = 0;
         P->cnt_upd[b] = 0;
         P->cnt_gemm[b] = 0;
         *(int4*)(P->sig_stat + 4 * b) = make_int4(n_act, n_act, C.stage < P->n_stages - 1 ? 1 : 0, 0);
