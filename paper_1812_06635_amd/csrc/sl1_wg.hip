@@ -1165,6 +1165,14 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         }
         X = uni(wave_sum(xs));
     }
+    // max eps over the preserved positions: it changes only when atoms are screened
+    double me_pos = 0.0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int i = l + 64 * h;
+        if (i < n_act) me_pos = fmax(me_pos, T.e[i]);
+    }
+    double me_c = uni(wave_max_nonneg_full(me_pos));
     wave_sync_lds();
     for (; it < max_it; ++it) {
         // per-iteration copies of the parameter block and of the lane's positions
@@ -1179,7 +1187,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         const double eta = uni(gam * YX);
         // ---- g = c - G x_t over the preserved positions ----
         double xt[H], g[H];
-        double cx = 0.0, xg = 0.0, m1 = 0.0, m0 = 0.0, me = 0.0;
+        double cx = 0.0, xg = 0.0, m1 = 0.0, m0 = 0.0;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             const int i = lo + 64 * h;
@@ -1204,7 +1212,6 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 xg = fma(xt[h], gi, xg);
                 m1 = fmax(m1, fabs(gi) + eta * T.an[i]);
                 m0 = fmax(m0, fabs(gi));
-                me = fmax(me, T.e[i]);
             }
         }
         // the five wave reductions (all 64 lanes of wave 0 take part; m1, m0, me >= 0)
@@ -1212,7 +1219,7 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         xg = uni(wave_sum_full(xg));
         m1 = uni(wave_max_nonneg_full(m1));
         m0 = uni(wave_max_nonneg_full(m0));
-        me = uni(wave_max_nonneg_full(me));
+        const double me = me_c;
         // ---- scalars (uniform) ----
         const double yr = yy - cx;
         const double r2 = fmax(yr - xg, 0.0);
@@ -1312,48 +1319,79 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                 }
             }
         }
-        // ---- compaction (positions keep their order) ----
-        int jj[H], lgp[H];
-        double ev[H], anv[H], atv[H], cyv[H];
+        // ---- compaction (positions keep their order); without a rejection every position
+        // stays and only the iterates, the correlations and the nonzero list change ----
+        int nkeep = 0;
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const int i = lo + 64 * h;
-            jj[h] = lgp[h] = 0;
-            ev[h] = anv[h] = atv[h] = cyv[h] = 0.0;
-            if (keep[h]) {
-                jj[h] = T.la[i];
-                lgp[h] = T.lg[i];
-                ev[h] = T.e[i];
-                anv[h] = T.an[i];
-                atv[h] = T.atn[i];
-                cyv[h] = T.cy[i];
-            }
-        }
-        wave_sync_lds();                  // every lane's reads of the state precede the writes
+        for (int h = 0; h < H; ++h) nkeep += __popcll(__ballot(keep[h]));
         int wpos = 0, zpos = 0;
+        if (uni(nkeep) == n_act) {
+            int lgn[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const unsigned long long bk = __ballot(keep[h]);
-            const unsigned long long bz = __ballot(nzf[h]);
-            if (keep[h]) {
-                const int q = wpos + __popcll(bk & below);
-                T.la[q] = jj[h];
-                T.lg[q] = lgp[h];
-                T.xt[q] = xn[h];
-                T.xp[q] = xt[h];
-                T.gm[q] = g[h];
-                T.e[q] = ev[h];
-                T.an[q] = anv[h];
-                T.atn[q] = atv[h];
-                T.cy[q] = cyv[h];
+            for (int h = 0; h < H; ++h) lgn[h] = nzf[h] ? T.lg[lo + 64 * h] : 0;
+            wave_sync_lds();              // every lane's reads of the nonzero list precede the writes
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int i = lo + 64 * h;
+                if (keep[h]) {
+                    T.xt[i] = xn[h];
+                    T.xp[i] = xt[h];
+                    T.gm[i] = g[h];
+                }
+                const unsigned long long bz = __ballot(nzf[h]);
+                if (nzf[h]) {
+                    const int q = zpos + __popcll(bz & below);
+                    lj[q] = lgn[h];
+                    lx[q] = xn[h];
+                }
+                zpos += __popcll(bz);
             }
-            if (nzf[h]) {
-                const int q = zpos + __popcll(bz & below);
-                lj[q] = lgp[h];
-                lx[q] = xn[h];
+            wpos = n_act;
+        } else {
+            int jj[H], lgp[H];
+            double ev[H], anv[H], atv[H], cyv[H];
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int i = lo + 64 * h;
+                jj[h] = lgp[h] = 0;
+                ev[h] = anv[h] = atv[h] = cyv[h] = 0.0;
+                if (keep[h]) {
+                    jj[h] = T.la[i];
+                    lgp[h] = T.lg[i];
+                    ev[h] = T.e[i];
+                    anv[h] = T.an[i];
+                    atv[h] = T.atn[i];
+                    cyv[h] = T.cy[i];
+                }
             }
-            wpos += __popcll(bk);
-            zpos += __popcll(bz);
+            wave_sync_lds();              // every lane's reads of the state precede the writes
+            double mep = 0.0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const unsigned long long bk = __ballot(keep[h]);
+                const unsigned long long bz = __ballot(nzf[h]);
+                if (keep[h]) {
+                    const int q = wpos + __popcll(bk & below);
+                    T.la[q] = jj[h];
+                    T.lg[q] = lgp[h];
+                    T.xt[q] = xn[h];
+                    T.xp[q] = xt[h];
+                    T.gm[q] = g[h];
+                    T.e[q] = ev[h];
+                    T.an[q] = anv[h];
+                    T.atn[q] = atv[h];
+                    T.cy[q] = cyv[h];
+                    mep = fmax(mep, ev[h]);
+                }
+                if (nzf[h]) {
+                    const int q = zpos + __popcll(bz & below);
+                    lj[q] = lgp[h];
+                    lx[q] = xn[h];
+                }
+                wpos += __popcll(bk);
+                zpos += __popcll(bz);
+            }
+            me_c = uni(wave_max_nonneg_full(mep));
         }
         wave_sync_lds();
         kt = uni(wave_sum_full(kt));
