@@ -298,9 +298,15 @@ __device__ __forceinline__ void raw_get(const Raw4<DT>& r, double (&v)[4]) {
 
 // NA atoms per wave; each pass issues the loads of NK 256-element steps of all
 // NA atoms before the first product (loads past N are clamped to a valid
-// address and discarded).  Per lane the products are accumulated in increasing k.
+// address and discarded).  Per lane the products are accumulated in increasing k,
+// so NK changes only how many loads are in flight: about 8 KB of stored entries
+// per wave and pass (between 1 and 8 steps), whatever the storage type.
 template <int DT, int NA>
-constexpr int dense_nk() { return NA >= 4 ? 1 : ((DT == SL1_F64 ? 4 : 8) / NA > 0 ? (DT == SL1_F64 ? 4 : 8) / NA : 1); }
+constexpr int dense_nk() {
+    constexpr int es = DT == SL1_F64 ? 8 : (DT == SL1_F32 ? 4 : (DT == SL1_BF16 ? 2 : 1));
+    constexpr int nk = 8192 / (NA * 256 * es);
+    return nk < 1 ? 1 : (nk > 8 ? 8 : nk);
+}
 
 template <int DT, int NA, int NK = dense_nk<DT, NA>()>
 __device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const int (&js)[NA], const double* zs,

@@ -896,17 +896,19 @@ __device__ __forceinline__ void kron_item_bf16(const StageDesc& st, int a0, int 
 }
 
 // dense correlation item: NA atoms of one wave (first = first list position);
-// eps_j is fetched together with the columns
+// eps_j is fetched together with the columns.  ident: the list holds all K atoms,
+// which is the identity (compactions keep the order), so positions are atoms and
+// the list is not read before the columns.
 template <int DT, int NA>
 __device__ __forceinline__ void dense_item(const StageDesc& st, int N, const int* act, const int* s_pre, int nseg,
-                                           int n_act, int first, const double* zs, double rz, double* g, int lane,
+                                           int n_act, bool ident, int first, const double* zs, double rz, double* g, int lane,
                                            double (&mx)[3]) {
     int js[NA];
     int cnt = 0;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         const int i = first + q;
-        js[q] = i < n_act ? list_get(act, s_pre, nseg, i) : -1;
+        js[q] = i < n_act ? (ident ? i : list_get(act, s_pre, nseg, i)) : -1;
         cnt += i < n_act;
     }
     if (cnt == 0) return;
@@ -1010,12 +1012,12 @@ __device__ __forceinline__ void reduce_res_max(const SolveParams* P, int b, doub
 // ---------------------------------------------------------------------------
 template <int DT>
 __device__ __forceinline__ void dense_item_any(const StageDesc& st, int N, const int* act, const int* s_pre, int nseg,
-                                               int n_act, int first, const double* zs, double rz, double* g,
+                                               int n_act, bool ident, int first, const double* zs, double rz, double* g,
                                                int lane, double (&mx)[3]) {
     const int apw = dense_apw(N, DT);
-    if (apw == 4) dense_item<DT, 4>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
-    else if (apw == 2) dense_item<DT, 2>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
-    else dense_item<DT, 1>(st, N, act, s_pre, nseg, n_act, first, zs, rz, g, lane, mx);
+    if (apw == 4) dense_item<DT, 4>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
+    else if (apw == 2) dense_item<DT, 2>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
+    else dense_item<DT, 1>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
 }
 
 __global__ __launch_bounds__(kBlock, 4) void k_adj_dense(const SolveParams* __restrict__ P, int slot) {
@@ -1057,10 +1059,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_adj_dense(const SolveParams* __re
         const int first = (c * 4 + w) * dense_apw(N, st.dtype);
         double mx[3] = {0.0, 0.0, 0.0};   // max(|g|+eps*|z|), max|g|, max eps over the item
         switch (st.dtype) {
-            case SL1_F64: dense_item_any<SL1_F64>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
-            case SL1_F32: dense_item_any<SL1_F32>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
-            case SL1_BF16: dense_item_any<SL1_BF16>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
-            default: dense_item_any<SL1_FP8_E4M3>(st, N, act, s_pre, nseg, n_act, first, zs, rz, gvec, lane, mx); break;
+            case SL1_F64: dense_item_any<SL1_F64>(st, N, act, s_pre, nseg, n_act, n_act == P->K, first, zs, rz, gvec, lane, mx); break;
+            case SL1_F32: dense_item_any<SL1_F32>(st, N, act, s_pre, nseg, n_act, n_act == P->K, first, zs, rz, gvec, lane, mx); break;
+            case SL1_BF16: dense_item_any<SL1_BF16>(st, N, act, s_pre, nseg, n_act, n_act == P->K, first, zs, rz, gvec, lane, mx); break;
+            default: dense_item_any<SL1_FP8_E4M3>(st, N, act, s_pre, nseg, n_act, n_act == P->K, first, zs, rz, gvec, lane, mx); break;
         }
         put_wave_max(P, b, c, mx, false);
     }
