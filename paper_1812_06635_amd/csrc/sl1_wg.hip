@@ -32,21 +32,31 @@ __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~(size_t)15
 
 
 // exclusive prefix of a per-thread flag over the 8-wave block; total returned in `total`
-__device__ __forceinline__ int wg_scan_flag(bool f, int* s_w, int& total) {
+// NF flags of every thread at once (one exchange of wave counts, two barriers):
+// pos[f] = the number of threads before this one (in thread order) with flag f
+// set, total[f] = the block's count of flag f.  s_w holds kWgWaves * NF ints.
+template <int NF>
+__device__ __forceinline__ void wg_scan_flags(const bool (&f)[NF], int* s_w, int (&pos)[NF], int (&total)[NF]) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const unsigned long long bal = __ballot(f);
-    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) s_w[w] = __popcll(bal);
-    __syncthreads();
-    int base = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < kWgWaves; ++k) {
-        base += k < w ? s_w[k] : 0;
-        tot += s_w[k];
+    for (int k = 0; k < NF; ++k) {
+        const unsigned long long bal = __ballot(f[k]);
+        pos[k] = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_w[w * NF + k] = __popcll(bal);
     }
-    total = tot;
     __syncthreads();
-    return base + pre;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) total[k] = 0;
+#pragma unroll
+    for (int q = 0; q < kWgWaves; ++q) {
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const int c = s_w[q * NF + k];
+            pos[k] += q < w ? c : 0;
+            total[k] += c;
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -599,7 +609,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
     __shared__ double s_sum[4];
     __shared__ double s_kt[2];
     __shared__ int s_cnt[2];
-    __shared__ int s_w[kWgWaves];
+    __shared__ int s_w[kWgWaves * 4];
     __shared__ int s_loaded, s_nz_ok, s_act_ok;
     __shared__ long long s_clk;
 
@@ -836,15 +846,17 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                 }
                 // every read of this part of the list precedes the in-place writes
                 __syncthreads();
+                // positions in list order: the kept and the nonzero atoms of both halves
+                const bool fl[4] = {keep[0], nzf[0], keep[1], nzf[1]};
+                int ps[4], ts[4];
+                wg_scan_flags<4>(fl, s_w, ps, ts);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    int tk, tz;
-                    const int pk = wg_scan_flag(keep[h], s_w, tk);
+                    const int pk = ps[2 * h], pz = ps[2 * h + 1];
                     if (keep[h]) {
                         act[wpos + pk] = jj[h];
                         if (wpos + pk < cap_act) la[wpos + pk] = jj[h];
                     }
-                    const int pz = wg_scan_flag(nzf[h], s_w, tz);
                     if (nzf[h]) {
                         nzl[zpos + pz] = jj[h];
                         if (zpos + pz < cap_nz) {
@@ -852,8 +864,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                             lx[zpos + pz] = xnv[h];
                         }
                     }
-                    wpos += tk;
-                    zpos += tz;
+                    wpos += ts[2 * h];
+                    zpos += ts[2 * h + 1];
                 }
             }
             block_sum<2>(sv, s_red);
@@ -1441,7 +1453,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
     __shared__ double s_kt[2];
     __shared__ double s_yy;
     __shared__ int s_cnt[2];
-    __shared__ int s_w[kWgWaves];
+    __shared__ int s_w[kWgWaves * 4];
     __shared__ int s_done;
     __shared__ long long s_clk;
 
@@ -1637,8 +1649,10 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                 }
                 // every read of this part of the state precedes the in-place writes
                 __syncthreads();
-                int tk, tz;
-                const int pk = wg_scan_flag(keep, s_w, tk);
+                const bool fl[2] = {keep, nzf};
+                int ps[2], ts[2];
+                wg_scan_flags<2>(fl, s_w, ps, ts);
+                const int pk = ps[0], pz = ps[1], tk = ts[0], tz = ts[1];
                 if (keep) {
                     const int q = wpos + pk;
                     T.la[q] = j;
@@ -1650,7 +1664,6 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
                     T.atn[q] = atn;
                     T.cy[q] = cy;
                 }
-                const int pz = wg_scan_flag(nzf, s_w, tz);
                 if (nzf) {
                     lj[zpos + pz] = j;
                     lx[zpos + pz] = xn;
