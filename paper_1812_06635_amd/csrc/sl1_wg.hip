@@ -175,7 +175,8 @@ __device__ __forceinline__ double wg_y(const SolveParams* P, int b, const double
 // C_r serve 16 products) and the partials meet in a fixed tree.
 template <bool D64>
 __device__ __forceinline__ void wg_kron_forward(const SolveParams* P, int b, const StageDesc& st, const char* fac,
-                                                const double* x, const int* nzl, int n_nz, int zround, double* zd,
+                                                const double* x, const int* nzl, int n_nz, const int* lj,
+                                                const double* lx, bool in_lds, int zround, double* zd,
                                                 float* zf, const double* yl, char* scr, double* s_red,
                                                 double* s_sum) {
     const int N = P->N, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -196,10 +197,11 @@ __device__ __forceinline__ void wg_kron_forward(const SolveParams* P, int b, con
         for (int base = 0; base < n_nz; base += kWgStage) {
             const int cnt = min(kWgStage, n_nz - base);
             if (tid < cnt) {
-                const int j = nzl[base + tid];
+                // the LDS copy of the nonzero list (atoms and values) when it holds them
+                const int j = in_lds ? lj[base + tid] : nzl[base + tid];
                 const int j1 = j / k2;
                 s_j[tid] = (j1 << 16) | (j - j1 * k2);
-                s_x[tid] = x[j];
+                s_x[tid] = in_lds ? lx[base + tid] : x[j];
             }
             __syncthreads();
             const int pw = (cnt + kWgWaves - 1) / kWgWaves;
@@ -703,8 +705,13 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             if (st.kind == kKron) {
                 const char* fac = smem + P->wo_fac;
                 const int zround = st.dtype == SL1_BF16 ? 2 : (st.dtype == SL1_F32 ? 1 : 0);
-                if (st.dtype == SL1_F64) wg_kron_forward<true>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, yl, scr, s_red, s_sum);
-                else wg_kron_forward<false>(P, b, st, fac, x, nzl, n_nz, zround, zd, zf, yl, scr, s_red, s_sum);
+                const bool in_lds = uni(s_nz_ok) != 0;
+                const int* lj = (const int*)(smem + P->wo_lnj);
+                const double* lx = (const double*)(smem + P->wo_lnx);
+                if (st.dtype == SL1_F64)
+                    wg_kron_forward<true>(P, b, st, fac, x, nzl, n_nz, lj, lx, in_lds, zround, zd, zf, yl, scr, s_red, s_sum);
+                else
+                    wg_kron_forward<false>(P, b, st, fac, x, nzl, n_nz, lj, lx, in_lds, zround, zd, zf, yl, scr, s_red, s_sum);
             } else {
                 const bool in_lds = uni(s_nz_ok) != 0;
                 const int* lj = (const int*)(smem + P->wo_lnj);
@@ -796,6 +803,8 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             const bool no_reject = uni(sC.iter) % P->screen_every != 0;
             int wpos = 0, zpos = 0;
             double sv[2] = {0.0, 0.0};   // look-ahead count K_t, ||x_{t+1}||_1
+            // a list of all K atoms is the identity (compactions keep the order)
+            const bool ident = n_act == K;
             for (int base = 0; base < n_act; base += 2 * kWgBlock) {
                 int jj[2];
                 bool keep[2], nzf[2];
@@ -807,7 +816,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
                     jj[h] = 0;
                     xnv[h] = 0.0;
                     if (i < n_act) {
-                        const int j = act_lds ? la[i] : act[i];
+                        const int j = ident ? i : (act_lds ? la[i] : act[i]);
                         jj[h] = j;
                         const double gt = gcur[j];
                         const double gp = gprev[j];
