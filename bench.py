@@ -388,10 +388,12 @@ def sources_sha256(kernel):
     return h.hexdigest()
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary under profiles/ (a 'traffic-record:' line), or None when there is
-    none or the kernel's sources changed since the counters were taken."""
+def recorded_traffic(kernel, workload="batched"):
+    """HBM bytes per launch of `kernel` on `workload` (a bench block: "batched",
+    "single", "dense", ...) from the rocprofv3 FETCH_SIZE/WRITE_SIZE summaries
+    under profiles/ (a 'traffic-record:' line; one without a workload key is the
+    batched block's), or None when there is none or the kernel's sources changed
+    since the counters were taken."""
     if kernel not in TRAFFIC_SOURCES:
         return None
     pdir = os.path.join(ROOT, "profiles")
@@ -406,7 +408,8 @@ def recorded_traffic(kernel):
                 if not line.startswith("traffic-record:"):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
-                if kv.get("kernel") == kernel and kv.get("sources_sha256") == want:
+                if (kv.get("kernel") == kernel and kv.get("workload", "batched") == workload
+                        and kv.get("sources_sha256") == want):
                     return float(kv["bytes_per_launch"])
     return None
 
@@ -494,11 +497,12 @@ def variants_block(sl1, torch, np, p, rc, tol, steps, warmup, plain_ref=None, ti
     return out
 
 
-def roofline(res):
+def roofline(res, workload="batched"):
     """The kernel with the largest share of the solve's device time, with its
-    recorded HBM traffic per launch when the counters match the current code."""
+    recorded HBM traffic per launch on this workload when the counters match the
+    current code."""
     r = dict(res["roofline_kernels"][0])
-    r["traffic"] = recorded_traffic(r["kernel"])
+    r["traffic"] = recorded_traffic(r["kernel"], workload)
     return r
 
 
@@ -720,7 +724,7 @@ def main():
             "speedup_vs_plain_fp32": r2["ms_plain"] / r2["ms_method"],
             "rc_measured": r2["rc_measured"], "kron_tiles_autotuned": r2["kron_tiles"], "engine": r2["engine"],
             "kernel_ms": r2["kernel_ms"],
-            "whole_solve_phases_ms": r2["wg_phases"], "roofline": roofline(r2),
+            "whole_solve_phases_ms": r2["wg_phases"], "roofline": roofline(r2, "single"),
             "roofline_kernels": r2["roofline_kernels"],
             "max_gap": r2["max_gap_method"],
         }
@@ -757,7 +761,7 @@ def main():
             "speedup_vs_plain_fp32": r4["ms_plain"] / r4["ms_method"],
             "rc_model": r4["rc_model"], "rc_measured": r4["rc_measured"], "engine": r4["engine"],
             "kernel_ms": r4["kernel_ms"], "whole_solve_phases_ms": r4["wg_phases"],
-            "roofline": roofline(r4), "roofline_kernels": r4["roofline_kernels"], "max_gap": r4["max_gap_method"],
+            "roofline": roofline(r4, "dense"), "roofline_kernels": r4["roofline_kernels"], "max_gap": r4["max_gap_method"],
         }
         if not args.no_parity:
             line["dense_precision"]["parity"] = block_parity(np, q, r4, oracle_reference(q, [0, 12, 24], "dense"),
