@@ -952,7 +952,7 @@ namespace {
 
 struct TailState {
     int* la;                 // atom index
-    int* lg;                 // row of the atom in the Gram matrix (Gram mode)
+    int* lg;                 // Gram mode: a compaction's new position of each position
     double *xt, *xp, *gt, *gm, *e, *an, *atn;   // x_t, x_{t-1}, g_t, g_{t-1}, eps, norms
     double* cy;              // a^T y on the exact dictionary (stable Dynamic Safe)
 };
@@ -1094,8 +1094,8 @@ __device__ void tail_gram_g(const StageDesc& st, int N, const int* la, int m, do
 }
 
 // Gram mode set-up for positions 0..m-1 (all threads): c into T.gt, ||y||^2,
-// then (y no longer needed; the Gram region overlays z, the scratch and y) G,
-// c and the atom of each Gram row, and lg[i] = i.
+// then (y no longer needed; the Gram region overlays z, the scratch and y) G and
+// c, row i of G and c_i belonging to position i (the Gram loop keeps it so).
 __device__ __attribute__((noinline)) void tail_gram_build(const SolveParams* P, int b, const StageDesc& st,
                                                           char* smem, int m, double* s_red, double* s_yy) {
     const int N = P->N, gcap = P->wg_cap_gram, tid = threadIdx.x;
@@ -1113,24 +1113,20 @@ __device__ __attribute__((noinline)) void tail_gram_build(const SolveParams* P, 
     if (tid == 0) *s_yy = yy[0];
     double* G = (double*)(smem + P->wo_gram);
     double* cv = G + (size_t)gcap * gcap;
-    int* ga = (int*)(cv + gcap);
     switch (st.dtype) {
         case SL1_F64: tail_gram_g<SL1_F64>(st, N, T.la, m, G, gcap); break;
         case SL1_F32: tail_gram_g<SL1_F32>(st, N, T.la, m, G, gcap); break;
         case SL1_BF16: tail_gram_g<SL1_BF16>(st, N, T.la, m, G, gcap); break;
         default: tail_gram_g<SL1_FP8_E4M3>(st, N, T.la, m, G, gcap); break;
     }
-    for (int i = tid; i < m; i += kWgBlock) {
-        cv[i] = T.gt[i];
-        ga[i] = T.la[i];
-        T.lg[i] = i;
-    }
+    for (int i = tid; i < m; i += kWgBlock) cv[i] = T.gt[i];
     __syncthreads();
 }
 
 // Gram-mode iterations of one signal, wave 0 only; lane l holds list positions
-// l + 64 h, h < H (Gram capacity <= 64 H).  Leaves the control state in *sCp;
-// sets *s_done when the signal stopped.
+// l + 64 h, h < H (Gram capacity <= 64 H).  Row and column i of G and c_i belong
+// to position i: a rejection compacts them with the positions.  Leaves the control
+// state in *sCp; sets *s_done when the signal stopped.
 template <int H>
 __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int it, int max_it, char* smem,
                                                Control* sCp, int* s_done, long long* s_clk, double yy) {
@@ -1140,10 +1136,9 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
     const StageDesc& st = P->st[uni(C.stage)];
     const int N = P->N, K = P->K, gcap = P->wg_cap_gram;
     const TailState T = tail_state(smem, P);
-    const double* G = (const double*)(smem + P->wo_gram);
-    const double* cv = G + (size_t)gcap * gcap;
-    int* lj = (int*)(smem + P->wo_lnj);       // nonzero list, as Gram rows
-    double* lx = (double*)(smem + P->wo_lnx);
+    double* G = (double*)(smem + P->wo_gram);
+    double* cv = G + (size_t)gcap * gcap;
+    int* nidx = T.lg;                          // scratch of a compaction: new position or -1
     const double invL = uni(st.invL), lam = uni(C.lam), thr = uni(lam * st.invL), keep_min = uni(1.0 - P->margin);
     const double invlam = uni(1.0 / lam);
     const double ny = uni(sqrt(yy));
@@ -1174,15 +1169,8 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             const int i = l + 64 * h;
             const bool in = i < n_act;
             const double xv = in ? T.xt[i] : 0.0;
-            const bool nzf = xv != 0.0;
             if (in) xs += T.an[i] * fabs(xv);
-            const unsigned long long bal = __ballot(nzf);
-            if (nzf) {
-                const int q = n_nz + __popcll(bal & below);
-                lj[q] = T.lg[i];
-                lx[q] = xv;
-            }
-            n_nz += __popcll(bal);
+            n_nz += __popcll(__ballot(xv != 0.0));
         }
         X = uni(wave_sum(xs));
     }
@@ -1207,6 +1195,9 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
         const double YX = uni(ny + X);
         const double eta = uni(gam * YX);
         // ---- g = c - G x_t over the preserved positions ----
+        // g_i = c_i - sum_k G[k][i] x_k in position order (G is symmetric; lanes read
+        // consecutive entries of a row, and a zero x_k adds an exact zero), four
+        // independent chains (any order is within the bound)
         double xt[H], g[H];
         double cx = 0.0, xg = 0.0, m1 = 0.0, m0 = 0.0;
 #pragma unroll
@@ -1214,22 +1205,39 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             const int i = lo + 64 * h;
             xt[h] = g[h] = 0.0;
             if (i < n_act) {
-                const int r = T.lg[i];
                 xt[h] = T.xt[i];
-                const double* Gc = G + r;
-                // four independent chains over the nonzeros (any order is within the bound)
-                double g0 = cv[r], g1 = 0.0, g2 = 0.0, g3 = 0.0;
-                int q = 0;
-                for (; q + 4 <= n_nz; q += 4) {
-                    g0 = fma(-Gc[(size_t)lj[q] * gcap], lx[q], g0);
-                    g1 = fma(-Gc[(size_t)lj[q + 1] * gcap], lx[q + 1], g1);
-                    g2 = fma(-Gc[(size_t)lj[q + 2] * gcap], lx[q + 2], g2);
-                    g3 = fma(-Gc[(size_t)lj[q + 3] * gcap], lx[q + 3], g3);
+                const double* Gc = G + i;
+                double g0 = cv[i], g1 = 0.0, g2 = 0.0, g3 = 0.0;
+                int k = 0;
+#pragma unroll 1
+                for (; k + 8 <= n_act; k += 8) {
+                    // the step's reads are issued before its products
+                    const double* Gk = Gc + (size_t)k * gcap;
+                    double a[8], x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) a[u] = Gk[(size_t)u * gcap];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = T.xt[k + u];
+                    asm volatile("" ::: "memory");
+                    g0 = fma(-a[0], x[0], g0);
+                    g1 = fma(-a[1], x[1], g1);
+                    g2 = fma(-a[2], x[2], g2);
+                    g3 = fma(-a[3], x[3], g3);
+                    g0 = fma(-a[4], x[4], g0);
+                    g1 = fma(-a[5], x[5], g1);
+                    g2 = fma(-a[6], x[6], g2);
+                    g3 = fma(-a[7], x[7], g3);
                 }
-                for (; q < n_nz; ++q) g0 = fma(-Gc[(size_t)lj[q] * gcap], lx[q], g0);
+                for (; k + 4 <= n_act; k += 4) {
+                    g0 = fma(-Gc[(size_t)k * gcap], T.xt[k], g0);
+                    g1 = fma(-Gc[(size_t)(k + 1) * gcap], T.xt[k + 1], g1);
+                    g2 = fma(-Gc[(size_t)(k + 2) * gcap], T.xt[k + 2], g2);
+                    g3 = fma(-Gc[(size_t)(k + 3) * gcap], T.xt[k + 3], g3);
+                }
+                for (; k < n_act; ++k) g0 = fma(-Gc[(size_t)k * gcap], T.xt[k], g0);
                 const double gi = (g0 + g1) + (g2 + g3);
                 g[h] = gi;
-                cx = fma(cv[r], xt[h], cx);
+                cx = fma(cv[i], xt[h], cx);
                 xg = fma(xt[h], gi, xg);
                 m1 = fmax(m1, fabs(gi) + eta * T.an[i]);
                 m0 = fmax(m0, fabs(gi));
@@ -1341,16 +1349,15 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
             }
         }
         // ---- compaction (positions keep their order); without a rejection every position
-        // stays and only the iterates, the correlations and the nonzero list change ----
+        // stays and only the iterates and the correlations change ----
         int nkeep = 0;
 #pragma unroll
         for (int h = 0; h < H; ++h) nkeep += __popcll(__ballot(keep[h]));
         int wpos = 0, zpos = 0;
-        if (uni(nkeep) == n_act) {
-            int lgn[H];
 #pragma unroll
-            for (int h = 0; h < H; ++h) lgn[h] = nzf[h] ? T.lg[lo + 64 * h] : 0;
-            wave_sync_lds();              // every lane's reads of the nonzero list precede the writes
+        for (int h = 0; h < H; ++h) zpos += __popcll(__ballot(nzf[h]));
+        wave_sync_lds();                  // every lane's reads of x_t precede the writes
+        if (uni(nkeep) == n_act) {
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int i = lo + 64 * h;
@@ -1359,58 +1366,85 @@ __device__ __forceinline__ void tail_gram_loop(const SolveParams* P0, int b, int
                     T.xp[i] = xt[h];
                     T.gm[i] = g[h];
                 }
-                const unsigned long long bz = __ballot(nzf[h]);
-                if (nzf[h]) {
-                    const int q = zpos + __popcll(bz & below);
-                    lj[q] = lgn[h];
-                    lx[q] = xn[h];
-                }
-                zpos += __popcll(bz);
             }
             wpos = n_act;
         } else {
-            int jj[H], lgp[H];
-            double ev[H], anv[H], atv[H], cyv[H];
+            // new position of each kept position (-1: rejected)
+            int np[H];
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int i = lo + 64 * h;
-                jj[h] = lgp[h] = 0;
-                ev[h] = anv[h] = atv[h] = cyv[h] = 0.0;
-                if (keep[h]) {
-                    jj[h] = T.la[i];
-                    lgp[h] = T.lg[i];
-                    ev[h] = T.e[i];
-                    anv[h] = T.an[i];
-                    atv[h] = T.atn[i];
-                    cyv[h] = T.cy[i];
+                const unsigned long long bk = __ballot(keep[h]);
+                np[h] = keep[h] ? wpos + __popcll(bk & below) : -1;
+                wpos += __popcll(bk);
+                if (i < n_act) nidx[i] = np[h];
+            }
+            // the per-position state: every lane reads its kept entries, then writes them
+            double mep = 0.0;
+            {
+                int jj[H];
+                double ev[H], anv[H], atv[H], cyv[H], cvv[H];
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const int i = lo + 64 * h;
+                    jj[h] = 0;
+                    ev[h] = anv[h] = atv[h] = cyv[h] = cvv[h] = 0.0;
+                    if (keep[h]) {
+                        jj[h] = T.la[i];
+                        ev[h] = T.e[i];
+                        anv[h] = T.an[i];
+                        atv[h] = T.atn[i];
+                        cyv[h] = T.cy[i];
+                        cvv[h] = cv[i];
+                    }
+                }
+                wave_sync_lds();
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    if (keep[h]) {
+                        const int q = np[h];
+                        T.la[q] = jj[h];
+                        T.xt[q] = xn[h];
+                        T.xp[q] = xt[h];
+                        T.gm[q] = g[h];
+                        T.e[q] = ev[h];
+                        T.an[q] = anv[h];
+                        T.atn[q] = atv[h];
+                        T.cy[q] = cyv[h];
+                        cv[q] = cvv[h];
+                        mep = fmax(mep, ev[h]);
+                    }
                 }
             }
-            wave_sync_lds();              // every lane's reads of the state precede the writes
-            double mep = 0.0;
+            wave_sync_lds();
+            // rows and columns of G follow their positions: four rows are read before any of
+            // them is written; a kept row r goes to row nidx[r] <= r, whose old content was read
+            // in this batch or an earlier one, so nothing is overwritten before it is read
+            const int n_old = n_act;
+            for (int r0 = 0; r0 < n_old; r0 += 4) {
+                double v[4][H];
+                int nr[4];
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-                const unsigned long long bk = __ballot(keep[h]);
-                const unsigned long long bz = __ballot(nzf[h]);
-                if (keep[h]) {
-                    const int q = wpos + __popcll(bk & below);
-                    T.la[q] = jj[h];
-                    T.lg[q] = lgp[h];
-                    T.xt[q] = xn[h];
-                    T.xp[q] = xt[h];
-                    T.gm[q] = g[h];
-                    T.e[q] = ev[h];
-                    T.an[q] = anv[h];
-                    T.atn[q] = atv[h];
-                    T.cy[q] = cyv[h];
-                    mep = fmax(mep, ev[h]);
+                for (int u = 0; u < 4; ++u) {
+                    const int r = r0 + u;
+                    nr[u] = r < n_old ? nidx[r] : -1;
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        const int k = lo + 64 * h;
+                        v[u][h] = (r < n_old && k < n_old) ? G[(size_t)r * gcap + k] : 0.0;
+                    }
                 }
-                if (nzf[h]) {
-                    const int q = zpos + __popcll(bz & below);
-                    lj[q] = lgp[h];
-                    lx[q] = xn[h];
+                wave_sync_lds();
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int rn = uni(nr[u]);
+                    if (rn >= 0) {
+#pragma unroll
+                        for (int h = 0; h < H; ++h)
+                            if (np[h] >= 0) G[(size_t)rn * gcap + np[h]] = v[u][h];
+                    }
                 }
-                wpos += __popcll(bk);
-                zpos += __popcll(bz);
+                wave_sync_lds();
             }
             me_c = uni(wave_max_nonneg_full(mep));
         }
@@ -1734,8 +1768,6 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
         const int par = uni(sC.par), n_act = uni(sC.n_act), n_nz = uni(sC.n_nz);
         const TailState T = tail_state(smem, P);
         const int* lj = (const int*)(smem + P->wo_lnj);
-        const int* ga = gram ? (const int*)((const double*)(smem + P->wo_gram) + (size_t)P->wg_cap_gram *
-                                            (P->wg_cap_gram + 1)) : nullptr;
         int* act = actbuf(P, b, 0);
         int* nzl = nzbuf(P, b, 0);
         double* xc = xbuf(P, b, par);
@@ -1748,7 +1780,20 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_tail(const SolveParams* _
             xo[j] = T.xp[i];
             gprev[j] = T.gm[i];
         }
-        for (int i = tid; i < n_nz; i += kWgBlock) nzl[i] = ga ? ga[lj[i]] : lj[i];
+        if (gram) {
+            // the Gram loop keeps no nonzero list: the positions with x_t != 0, in order
+            int base_nz = 0;
+            for (int base = 0; base < n_act; base += kWgBlock) {
+                const int i = base + tid;
+                const bool f[1] = {i < n_act && T.xt[i] != 0.0};
+                int pos[1], tot[1];
+                wg_scan_flags<1>(f, s_w, pos, tot);
+                if (f[0]) nzl[base_nz + pos[0]] = T.la[i];
+                base_nz += tot[0];
+            }
+        } else {
+            for (int i = tid; i < n_nz; i += kWgBlock) nzl[i] = lj[i];
+        }
         if (tid == 0) P->ctrl[2 * b] = sC;
     }
 }
