@@ -1689,6 +1689,32 @@ __device__ void scalar_block(const SolveParams* P, int b, const Control& C, Scal
 // screening step; Section IV-C look-ahead count).  Item = segment of 256
 // entries of the preserved set.
 // ---------------------------------------------------------------------------
+// NF flags of every thread of the block at once (one exchange of wave counts, two
+// barriers): pos[f] = the number of threads before this one (in thread order) with
+// flag f set, total[f] = the block's count.  s_w holds (blockDim.x / 64) * NF ints.
+template <int NF>
+__device__ __forceinline__ void block_scan_flags(const bool (&f)[NF], int* s_w, int (&pos)[NF], int (&total)[NF]) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+        const unsigned long long bal = __ballot(f[k]);
+        pos[k] = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_w[w * NF + k] = __popcll(bal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NF; ++k) total[k] = 0;
+    for (int q = 0; q < nw; ++q) {
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const int c = s_w[q * NF + k];
+            pos[k] += q < w ? c : 0;
+            total[k] += c;
+        }
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ int block_excl_scan_flag(bool f, int* s_w, int& total) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long bal = __ballot(f);
@@ -1711,7 +1737,7 @@ __device__ __forceinline__ void upd_body(const SolveParams* __restrict__ P, int 
     int* s_pre = (int*)smem;
     int* s_wpre = s_pre + (P->nseg_max + 1);
     __shared__ double s_red[96];
-    __shared__ int s_w[4];
+    __shared__ int s_w[8];           // four waves' counts of two flags
     __shared__ int s_tmp[16];
     const int total = build_work_map(P->cnt_upd, batch, s_wpre, s_tmp);
     const int per = (total + gridDim.x - 1) / gridDim.x;
@@ -1813,10 +1839,11 @@ __device__ __forceinline__ void upd_body(const SolveParams* __restrict__ P, int 
             l1 = fabs(xn);
             xnv = xn;
         }
-        int tot_keep, tot_nz;
-        const int pk = block_excl_scan_flag(keep, s_w, tot_keep);
+        const bool fl[2] = {keep, nzf};
+        int ps[2], ts[2];
+        block_scan_flags<2>(fl, s_w, ps, ts);
+        const int pk = ps[0], pz = ps[1], tot_keep = ts[0], tot_nz = ts[1];
         if (keep) actbuf(P, b, 1 - par)[c * kSeg + pk] = j;
-        const int pz = block_excl_scan_flag(nzf, s_w, tot_nz);
         if (nzf) {
             nzbuf(P, b, 1 - par)[c * kSeg + pz] = j;
             nzxbuf(P, b, 1 - par)[c * kSeg + pz] = xnv;
@@ -1860,6 +1887,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_upd_dome(const SolveParams* __res
 // ---------------------------------------------------------------------------
 constexpr int kStepH = 4;            // preserved atoms per thread per pass of the update
 
+
 __device__ __forceinline__ void step_finish(const SolveParams* P, int b, int slot, const Control& C, const Scalars& S,
                                             int status) {
     Final F;
@@ -1897,6 +1925,7 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
     __shared__ Control s_c;
     __shared__ double s_red[96];
     __shared__ int s_tmp[16];
+    __shared__ int s_flags[kFwdWaves * 2 * kStepH];
     if (tid == 0) s_c = P->ctrl[2 * b + (1 - slot)];
     __syncthreads();
     Control C = s_c;
@@ -1996,14 +2025,20 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
                     xn[h] = x1;
                 }
             }
-            // positions in list order: keep and nonzero counts in one scan (each below 2^16)
+            // positions in list order: the kept and the nonzero atoms of the pass's parts
+            bool fl[2 * kStepH];
 #pragma unroll
             for (int h = 0; h < kStepH; ++h) {
-                int ex;
-                const int tot = block_excl_scan((keep[h] ? 1 : 0) | (nzf[h] ? 0x10000 : 0), ex, s_tmp);
-                if (keep[h]) nact[wpos + (ex & 0xFFFF)] = jj[h];
+                fl[2 * h] = keep[h];
+                fl[2 * h + 1] = nzf[h];
+            }
+            int ps[2 * kStepH], ts[2 * kStepH];
+            block_scan_flags<2 * kStepH>(fl, s_flags, ps, ts);
+#pragma unroll
+            for (int h = 0; h < kStepH; ++h) {
+                if (keep[h]) nact[wpos + ps[2 * h]] = jj[h];
                 if (nzf[h]) {
-                    const int q = zpos + (ex >> 16);
+                    const int q = zpos + ps[2 * h + 1];
                     nnz[q] = jj[h];
                     nnx[q] = xn[h];
                     if (q < kFwdBlock) {      // the forward's first staged chunk, kept in LDS
@@ -2011,8 +2046,8 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
                         s_x[q] = xn[h];
                     }
                 }
-                wpos += tot & 0xFFFF;
-                zpos += tot >> 16;
+                wpos += ts[2 * h];
+                zpos += ts[2 * h + 1];
             }
         }
         block_sum<2>(sv, s_red);
