@@ -194,6 +194,12 @@ typedef struct {
                                      forward, one block per signal) */
 #define SL1_FLAG_GRID_STEP 4096         /* grid engine: those per-signal step launches for any batch size
                                      (not together with SL1_FLAG_GRID_SPLIT_STEP: SL1_EINVAL) */
+#define SL1_FLAG_PARK_ALL 8192          /* hybrid engine: the grid kernels start only once every live signal
+                                     has left the whole-solve phase on the Kronecker approximations (by
+                                     default, for batches of at least 128 signals with a dense last stage
+                                     and step launches, they start once at most batch / 128 are still on
+                                     the approximations, and those go on in a whole-solve launch on a
+                                     second stream until they reach A, then join) */
 #define SL1_FLAG_ISTA 64          /* ISTA update x_{t+1} = ST(x_t + A~^T rho~_t / L) (Section I-B)
                                      instead of FISTA */
 #define SL1_FLAG_NO_GEMM 256      /* grid engine: correlations of every signal stream its own preserved

@@ -27,6 +27,7 @@ FLAG_RULE_DOME = 512
 FLAG_HYBRID_GRID_FIRST = 1024
 FLAG_GRID_SPLIT_STEP = 2048
 FLAG_GRID_STEP = 4096
+FLAG_PARK_ALL = 8192
 GRID_KERNELS = 7
 ENGINE_GRID, ENGINE_WG, ENGINE_HYBRID = 1, 2, 3
 

@@ -151,13 +151,16 @@ _ENGINES = {"auto": 0, "grid": L.FLAG_ENGINE_GRID, "wg": L.FLAG_ENGINE_WG, "hybr
 def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=100000, margin=1e-12, chunk=16,
           trace_cap=0, use_graph=True, profile=False, check=True, engine="auto", tail_gram=True,
           update="fista", rule="gap", batched_gemm=True, screen_every=1, gemm_signals=0, x0=None, noalloc=False,
-          kron_first=True, step=None):
+          kron_first=True, step=None, park_all=False):
     """Algorithm 1 on a batch: y (batch, N) and lam (batch,) device tensors.
     engine: "auto", "grid" (per-iteration launches), "wg" (one workgroup per
     signal for the whole solve) or "hybrid" (grid, then a tail kernel once every
     signal is on the last, dense, stage with a small preserved set); kron_first:
     the hybrid engine runs Kronecker approximations in the whole-solve kernel
-    (False: on the grid kernels); step: where every live signal can only be on
+    (False: on the grid kernels); park_all: the grid kernels start only once every
+    signal has left that phase (by default, for 128 signals or more, they start when at
+    most batch / 128 are still on the approximations; those go on beside them on a
+    second stream); step: where every live signal can only be on
     dense stages, the grid engine does the update and the next forward in one
     launch with one block per signal (None: for batches of 128 signals or more;
     True: for any batch; False: separate chip-wide launches); tail_gram:
@@ -210,7 +213,8 @@ def solve(stages, L_, rc, atom_norm, y, lam, Gamma=0.5, tol=1e-6, max_iter=10000
         (0 if tail_gram else L.FLAG_TAIL_COLUMNS) | (L.FLAG_ISTA if update == "ista" else 0) | \
         (L.FLAG_RULE_DST if rule == "dst" else 0) | (L.FLAG_RULE_DOME if rule == "dome" else 0) | \
         (0 if batched_gemm else L.FLAG_NO_GEMM) | (0 if kron_first else L.FLAG_HYBRID_GRID_FIRST) | \
-        ({None: 0, True: L.FLAG_GRID_STEP, False: L.FLAG_GRID_SPLIT_STEP}[step])
+        ({None: 0, True: L.FLAG_GRID_STEP, False: L.FLAG_GRID_SPLIT_STEP}[step]) | \
+        (L.FLAG_PARK_ALL if park_all else 0)
     trace = None
     if trace_cap > 0:
         trace = torch.zeros((batch, trace_cap, L.TRACE_FIELDS), dtype=torch.float64, device=dev)

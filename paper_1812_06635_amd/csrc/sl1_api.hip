@@ -39,7 +39,7 @@ hipError_t launch_solve_wg(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_solve_tail(const SolveParams*, int, size_t, int, hipStream_t);
 hipError_t launch_to_wg(const SolveParams*, int, int, hipStream_t);
 hipError_t launch_wg_stat(const SolveParams*, hipStream_t);
-hipError_t launch_wg_to_grid(const SolveParams*, int, hipStream_t);
+hipError_t launch_wg_to_grid(const SolveParams*, int, hipStream_t, int, int);
 hipError_t launch_zero(void*, size_t, hipStream_t);
 }  // namespace sl1
 
@@ -152,6 +152,11 @@ struct Workspace {
     long long* d_times = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_a = nullptr, ev_b = nullptr;
+    // a second stream for a whole-solve launch beside the grid kernels (its params
+    // in dP2), with the events that order the two and time it
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_j = nullptr, ev_k = nullptr, ev_c = nullptr, ev_d = nullptr;
+    SolveParams* dP2 = nullptr;
     // captured chunks of grid iterations, one per launch set: bit 0 with the
     // Kronecker correlation launch, bit 1 with the batched correlation product
     hipGraphExec_t graph[8] = {};           // chunk graphs by launch set (Kronecker, product, step)
@@ -188,7 +193,10 @@ struct Workspace {
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
+        for (hipEvent_t e : {ev_j, ev_k, ev_c, ev_d})
+            if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+        if (stream2) (void)hipStreamDestroy(stream2);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -227,7 +235,7 @@ size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     const size_t o_zq = take(B * 8);
     const size_t o_adp = take(B * w.nadj_max * 4 * 3 * 8);
     const size_t o_up = take(B * w.nseg_max * 4 * 8);
-    const size_t o_cnt = take(B * 11 * 4);
+    const size_t o_cnt = take(B * 12 * 4);
     const size_t o_fw = take(B * kFaustMaxDim * 8);
     const size_t o_gpart = take((size_t)kGemmSplitUnits * kGemmAtoms * kGemmSig * 8);
     const size_t o_act_sig = take(64);
@@ -235,6 +243,7 @@ size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     const size_t o_times = take(B * 16);
     const size_t o_wgprof = take(B * kWgPhases * 8);
     const size_t o_params = take(sizeof(SolveParams));
+    const size_t o_params2 = take(sizeof(SolveParams));
     if (!m) return off;
     SolveParams& p = *pp;
     p.ctrl = (Control*)(m + o_ctrl);
@@ -260,6 +269,7 @@ size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     p.cnt_gemm = p.cnt_upd + B;
     p.sig_stat = p.cnt_gemm + B;
     p.cnt_adjf = p.sig_stat + 4 * B;
+    p.absent = p.cnt_adjf + B;
     p.fw = (double*)(m + o_fw);
     p.gemm_part = (double*)(m + o_gpart);
     p.active_signals = (int*)(m + o_act_sig);
@@ -272,6 +282,7 @@ size_t workspace_layout(Workspace& w, char* m, SolveParams* pp) {
     w.d_times = (long long*)(m + o_times);
     w.d_wgprof = (long long*)(m + o_wgprof);
     w.dP = (SolveParams*)(m + o_params);
+    w.dP2 = (SolveParams*)(m + o_params2);
     return off;
 }
 
@@ -287,6 +298,11 @@ int make_workspace(Workspace& w) {
     if (hipEventCreateWithFlags(&w.ev_out, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
     if (hipEventCreate(&w.ev_a) != hipSuccess) return SL1_EHIP;
     if (hipEventCreate(&w.ev_b) != hipSuccess) return SL1_EHIP;
+    if (hipStreamCreateWithFlags(&w.stream2, hipStreamNonBlocking) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreateWithFlags(&w.ev_j, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreateWithFlags(&w.ev_k, hipEventDisableTiming) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreate(&w.ev_c) != hipSuccess) return SL1_EHIP;
+    if (hipEventCreate(&w.ev_d) != hipSuccess) return SL1_EHIP;
     if (hipMemsetAsync(w.mem, 0, bytes, w.stream) != hipSuccess) return SL1_EHIP;
     if (hipStreamSynchronize(w.stream) != hipSuccess) return SL1_EHIP;
     return SL1_OK;
@@ -669,7 +685,8 @@ int hybrid_atoms(const SolveParams& p) {
 // the `done` iterations already run by the grid kernels); tail: the hybrid
 // solve's kernel for the last, dense, stage with LDS-resident per-atom state;
 // parking (p.wg_park >= 0): whole-solve launches until every live signal has
-// reached the park stage, with the hand-over statistics in h_active[4..7].
+// reached the park stage, or until at most p.wg_park_allow have not (they stop where
+// they are), with the hand-over statistics in h_active[4..7].
 // Profile: launch times and per-signal phase clocks.
 enum WgMode { kWgWhole = 0, kWgTail = 1, kWgPark = 2 };
 int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch, size_t wlds, bool prof, int dev,
@@ -684,7 +701,7 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
         if (prof) HIP_TRY(hipEventRecord(w->ev_b, w->stream));
         launched += per;
         if (mode == kWgPark) HIP_TRY(launch_wg_stat(w->dP, w->stream));
-        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, mode == kWgPark ? 32 : 4, hipMemcpyDeviceToHost,
+        HIP_TRY(hipMemcpyAsync(w->h_active, w->d_active, mode == kWgPark ? 36 : 4, hipMemcpyDeviceToHost,
                                w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (prof) {
@@ -695,7 +712,11 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
             if (mode == kWgPark) w->park_ms += ms;
         }
         if (*w->h_active <= 0 || launched >= cap) break;
-        if (mode == kWgPark && w->h_active[4 + 2] == 0) break;
+        // the park phase ends when every live signal has reached the park stage, or when
+        // at most wg_park_allow are short of it (those stopped where they were)
+        if (mode == kWgPark && (w->h_active[4 + 2] <= p.wg_park_allow ||
+                                w->h_active[0] - w->h_active[8] <= p.wg_park_allow))
+            break;
     }
     if (prof) {
         std::vector<long long> ticks((size_t)batch * kWgPhases);
@@ -1224,6 +1245,8 @@ int dst_setup(Workspace* w, sl1_dict d, int64_t batch, const void* y, int y_dtyp
     p.gemm_min = 0;
     p.wg_prof = nullptr;
     p.wg_park = -1;
+    p.wg_park_allow = 0;
+    p.wg_absent_only = 0;
     p.Gamma = 0.5;
     p.tol = 0.0;
     p.margin = 0.0;
@@ -1334,6 +1357,8 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
     const bool prof = (o.flags & SL1_FLAG_PROFILE) != 0;
     p.wg_prof = ((use_wg || hybrid) && prof) ? w->d_wgprof : nullptr;
     p.wg_park = -1;
+    p.wg_park_allow = 0;
+    p.wg_absent_only = 0;
     LaunchCfg cfg = launch_cfg(*w, p);
     if (!use_wg) {
         st = check_lds(cfg);
@@ -1414,14 +1439,28 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
         all_dense = all_dense && p.st[i].kind == kDense;
     }
     bool step_live = step_ok && all_dense;
+    bool beside = false;      // late signals of the Kronecker phase in a launch on the second stream
     if (kron_first) {
         w->last_engine = SL1_ENGINE_HYBRID;
         p.wg_park = p.n_stages - 1;
+        // a few late signals need not hold the phase for the whole batch: once at most
+        // batch / 128 are short of A, the grid kernels start for the others while a
+        // whole-solve launch on the second stream goes on with those few (step launches
+        // on a dense last stage only; not for a borrowed workspace, which has no stream)
+        const bool can_beside = w->stream2 && step_ok && !last_kron && batch >= 128 &&
+                                !(o.flags & SL1_FLAG_PARK_ALL);
+        p.wg_park_allow = can_beside ? (int)(batch / 128) : 0;
         HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
         if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
         st = run_wg(w, p, o, batch, wlds, prof, dev, 0, kWgPark);
         if (st != SL1_OK) return st;
+        SolveParams pw = p;                       // the whole-solve layout, for a launch beside
+        pw.wg_park_allow = 0;
+        pw.wg_absent_only = 1;
         p.wg_park = -1;
+        p.wg_park_allow = 0;
+        p.wg_park_allow = 0;
+        p.wg_absent_only = 0;
         if (*w->h_active <= 0) return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
         const int* s1 = w->h_active + 4;
         const size_t tlds = wg_layout(p, true, s1[0], gram);
@@ -1435,10 +1474,23 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
             return finish_solve(w, cfg, batch, x, gap, gap_cert, screened, iters, stage, us);
         }
         if (p.gemm_min > 0) p.gemm_on = s1[3] >= gemm_signals ? 1 : 0;
-        if (!last_kron && s1[2] == 0) kron_live = false;
-        step_live = step_ok && s1[2] == 0;
+        beside = can_beside && s1[2] > 0;
+        if (beside || (!last_kron && s1[2] == 0)) kron_live = false;
+        step_live = step_ok && (beside || s1[2] == 0);
         HIP_TRY(hipMemcpyAsync(w->dP, &p, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
-        HIP_TRY(launch_wg_to_grid(w->dP, (int)batch, w->stream));
+        HIP_TRY(launch_wg_to_grid(w->dP, (int)batch, w->stream, beside ? 1 : 0, p.n_stages - 1));
+        if (beside) {
+            // after the absent marks: the late signals' launch runs to the park stage (or
+            // their stop) on the second stream; they join at the first chunk boundary after it
+            HIP_TRY(hipMemcpyAsync(w->dP2, &pw, sizeof(SolveParams), hipMemcpyHostToDevice, w->stream));
+            HIP_TRY(hipEventRecord(w->ev_j, w->stream));
+            HIP_TRY(hipStreamWaitEvent(w->stream2, w->ev_j, 0));
+            if (prof) HIP_TRY(hipEventRecord(w->ev_c, w->stream2));
+            HIP_TRY(launch_solve_wg(w->dP2, (int)batch, wlds, (int)std::min<long long>((long long)o.max_iter + 1, INT32_MAX),
+                                    w->stream2));
+            if (prof) HIP_TRY(hipEventRecord(w->ev_d, w->stream2));
+            HIP_TRY(hipEventRecord(w->ev_k, w->stream2));
+        }
     }
     for (;;) {
         LaunchCfg ccfg = cfg;
@@ -1468,6 +1520,20 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
             for (int k = 0; k < chunk; ++k) HIP_TRY(launch_iter(k & 1, w->dP, ccfg, w->stream));
         }
         launched += chunk;
+        if (beside) {
+            // the late signals join once their launch beside has ended
+            HIP_TRY(hipStreamWaitEvent(w->stream, w->ev_k, 0));
+            HIP_TRY(launch_wg_to_grid(w->dP, (int)batch, w->stream, 2, p.n_stages - 1));
+            beside = false;
+            if (prof) {
+                HIP_TRY(hipEventSynchronize(w->ev_d));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, w->ev_c, w->ev_d));
+                w->wg_ms += ms;
+                w->wg_n += 1;
+                w->park_ms += ms;
+            }
+        }
         if (prof) {
             HIP_TRY(hipStreamSynchronize(w->stream));
             const bool run[kGridKernels] = {!ccfg.step, ccfg.g_adj > 0, ccfg.g_adjk > 0 || ccfg.adjf_x > 0, !ccfg.step,
@@ -1644,6 +1710,8 @@ static int lambda_pass(sl1_dict d, int64_t batch, const void* y, int y_dtype, do
     p.gemm_min = 0;
     p.wg_prof = nullptr;
     p.wg_park = -1;
+    p.wg_park_allow = 0;
+    p.wg_absent_only = 0;
     p.Gamma = 0.5;
     p.tol = 0.0;
     p.margin = 0.0;
@@ -1712,6 +1780,8 @@ static int time_adj(Workspace* w, const SolveParams& tmp, const StageDesc& sd, i
     p.gemm_min = 0;
     p.wg_prof = nullptr;
     p.wg_park = -1;
+    p.wg_park_allow = 0;
+    p.wg_absent_only = 0;
     p.tol = 0.0;
     p.margin = 0.0;
     p.atom_norm = sd.at_norm;

@@ -148,7 +148,8 @@ struct SolveParams {
     double* gemm_part;        // [kGemmSplitUnits][64 * 64] partial tiles of a split product launch
     int gemm_min;             // |A_t| from which a signal on the exact dense stage qualifies (0: never)
     int gemm_on;              // the batched product runs (set by the host between chunks)
-    int* active_signals;      // one int: signals not yet done
+    int* active_signals;      // [0] signals not yet done; [8] signals that reached the park stage
+                              // in the whole-solve kernel during the current solve
     int* sig_stat;            // [batch][4] per live signal, written by each forward launch (zero
                               // once done): |A_t|, |A_t|, not yet on the last stage, qualifies
                               // for the batched correlation product
@@ -170,8 +171,15 @@ struct SolveParams {
     int wg_cap_nz, wg_cap_act, wg_cap_gram;
     long long* wg_prof;
     // whole-solve kernel: a signal whose stage reaches wg_park stops at the top of
-    // that iteration and keeps its state for another engine (-1: never)
+    // that iteration and keeps its state for another engine (-1: never); once at
+    // most wg_park_allow live signals are still short of it (0: never), those stop
+    // as well
     int wg_park;
+    int wg_park_allow;
+    int wg_absent_only;       // whole-solve launch for the signals marked absent only
+    // [batch] 1 while the signal's iterations run in a whole-solve launch beside the
+    // grid kernels, which then leave its state alone
+    int* absent;
 };
 
 struct LaunchCfg {

@@ -107,6 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const SolveParams* __restrict__
         C.t0 = wall_clock64();
         P->ctrl[2 * b + 0] = C;
         P->ctrl[2 * b + 1] = C;
+        P->absent[b] = 0;
         nzpre(P, b, 0)[0] = 0;
         Final F;
         F.gap = 0.0;
@@ -1926,6 +1927,7 @@ __global__ __launch_bounds__(kFwdBlock, 2) void k_step(const SolveParams* __rest
     __shared__ double s_red[96];
     __shared__ int s_tmp[16];
     __shared__ int s_flags[kFwdWaves * 2 * kStepH];
+    if (P->absent[b]) return;     // its iterations run in a whole-solve launch meanwhile
     if (tid == 0) s_c = P->ctrl[2 * b + (1 - slot)];
     __syncthreads();
     Control C = s_c;

@@ -612,11 +612,14 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
     __shared__ double s_kt[2];
     __shared__ int s_cnt[2];
     __shared__ int s_w[kWgWaves * 4];
-    __shared__ int s_loaded, s_nz_ok, s_act_ok;
+    __shared__ int s_loaded, s_nz_ok, s_act_ok, s_leave;
     __shared__ long long s_clk;
 
+    // a launch beside the grid kernels runs only the signals they leave alone
+    if (P0->wg_absent_only && !P0->absent[b]) return;
     if (tid == 0) {
         sC = P0->ctrl[2 * b];
+        s_leave = 0;
         s_loaded = -1;
         s_nz_ok = 0;
         s_act_ok = 0;
@@ -626,6 +629,7 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
     // a signal parked at an earlier launch waits for the engine that takes over
     const int park = P0->wg_park;
     if (sC.done || (park >= 0 && sC.stage >= park)) return;
+    const int park_allow = park >= 0 ? P0->wg_park_allow : 0;
     {
         const SolveParams* P = phase_params(P0);
         if (P->wo_y >= 0) {
@@ -638,6 +642,13 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
         const int stage = uni(sC.stage), par = uni(sC.par);
         const int n_nz = uni(sC.n_nz), n_act = uni(sC.n_act);
         if (park >= 0 && stage >= park) break;    // state stored below, lists in slot 0
+        if (uni(s_leave)) break;                  // one of the last few short of the park stage
+        // the live and parked counts, requested now and compared at the end of the iteration
+        int n_live = 0, n_parked = 0;
+        if (park_allow > 0 && tid == 0) {
+            n_live = __hip_atomic_load(P0->active_signals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            n_parked = __hip_atomic_load(P0->active_signals + 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         // ---- factors of a new Kronecker stage, and the two lists, into LDS ----
         {
             const SolveParams* P = phase_params(P0);
@@ -918,6 +929,10 @@ __global__ __launch_bounds__(kWgBlock, 4) void k_solve_wg(const SolveParams* __r
             C.n_act = s_cnt[0];
             C.n_nz = s_cnt[1];
             C.l1 = s_kt[1];
+            if (park >= 0 && C.stage >= park && stage < park) atomicAdd(P->active_signals + 8, 1);
+            // when at most park_allow live signals (counts of this iteration's start) are short
+            // of the park stage, the ones still short of it stop here as well
+            if (park_allow > 0 && C.stage < park && n_live - n_parked <= park_allow) s_leave = 1;
             sC = C;
         }
         __syncthreads();
@@ -1879,12 +1894,31 @@ __global__ __launch_bounds__(kBlock) void k_wg_stat(const SolveParams* __restric
 // initialisation kernel.  Each block reads only its own signal's slot-0 lists
 // before writing its slot-1 lists (disjoint buffers).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSeg) void k_wg_to_grid(const SolveParams* __restrict__ P) {
+// mode 0: every signal; mode 1: a live signal short of stage `park` is marked absent
+// instead (the grid kernels leave it alone while a whole-solve launch beside them
+// goes on with it); mode 2: the absent signals only, which join the grid kernels.
+__global__ __launch_bounds__(kSeg) void k_wg_to_grid(const SolveParams* __restrict__ P, int mode, int park) {
     const int b = blockIdx.x, batch = P->batch;
+    if (mode == 2 && !P->absent[b]) return;
     __shared__ Control s_c;
     if (threadIdx.x == 0) s_c = P->ctrl[2 * b];
     __syncthreads();
     Control C = s_c;
+    if (mode == 1 && !C.done && C.stage < park) {
+        if (threadIdx.x == 0) {
+            P->absent[b] = 1;
+            P->cnt_fwd[b] = 0;
+            P->cnt_fwd[(size_t)batch + b] = 0;
+            P->cnt_adj[b] = 0;
+            P->cnt_adjk[b] = 0;
+            P->cnt_adjf[b] = 0;
+            P->cnt_upd[b] = 0;
+            P->cnt_gemm[b] = 0;
+            *(int4*)(P->sig_stat + 4 * b) = make_int4(0, 0, 0, 0);
+        }
+        return;
+    }
+    if (threadIdx.x == 0) P->absent[b] = 0;
     if (C.done) {
         if (threadIdx.x == 0) {
             P->ctrl[2 * b + 1] = C;
@@ -1939,8 +1973,8 @@ hipError_t launch_wg_stat(const SolveParams* dP, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_wg_to_grid(const SolveParams* dP, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(k_wg_to_grid, dim3(batch), dim3(kSeg), 0, s, dP);
+hipError_t launch_wg_to_grid(const SolveParams* dP, int batch, hipStream_t s, int mode, int park) {
+    hipLaunchKernelGGL(k_wg_to_grid, dim3(batch), dim3(kSeg), 0, s, dP, mode, park);
     return hipGetLastError();
 }
 

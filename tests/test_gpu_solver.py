@@ -590,6 +590,33 @@ def test_hybrid_kron_first_matches_grid_first(sl1, step):
         _check_solution(p, h, b)
 
 
+def test_late_kronecker_signals_run_beside_the_grid(sl1):
+    # 256 signals of the batched dictionary: the grid kernels start once at most 256 / 128
+    # live signals are still on the approximations; those go on in a whole-solve launch on
+    # a second stream and join at the next chunk boundary.  Decisions and solutions agree
+    # with the solve whose grid kernels wait for every signal.
+    _say("hybrid, late Kronecker-phase signals beside the grid vs waiting for all, batched dictionary, "
+         "256 signals")
+    import paper_1812_06635_amd as m
+    p = synth.config4(batch=256)
+    a = _run(sl1, p, tol=1e-9, engine="hybrid", park_all=True, profile=True)
+    ph_a = m.last_solve_phases(p.batch, p.N, p.K)[1]
+    h = _run(sl1, p, tol=1e-9, engine="hybrid", profile=True)
+    ph_h = m.last_solve_phases(p.batch, p.N, p.K)[1]
+    prof_h = m.last_solve_profile(p.batch, p.N, p.K)
+    _say(f"whole-solve launches: {ph_a['wg_launches']} waiting for all, {ph_h['wg_launches']} with one beside")
+    assert ph_h["wg_launches"] == ph_a["wg_launches"] + 1           # the launch beside the grid
+    assert prof_h["adj_kron"][1] == 0 and prof_h["step"][1] > 0      # step launches on A only
+    assert a["status"] == 0 and h["status"] == 0
+    np.testing.assert_array_equal(a["stage"], h["stage"])
+    assert np.all(np.abs(a["iters"] - h["iters"]) <= 2), np.flatnonzero(np.abs(a["iters"] - h["iters"]) > 2)
+    for b in range(p.batch):
+        rel = np.linalg.norm(a["x"][b] - h["x"][b]) / max(np.linalg.norm(a["x"][b]), 1e-300)
+        assert rel <= 1e-4, f"signal {b}: paths differ by {rel:.2e}"
+    for b in np.argsort(-h["iters"])[:6]:
+        _check_solution(p, h, int(b))
+
+
 def _exact_only(p):
     import dataclasses
     return dataclasses.replace(p, stages=[p.stages[-1]])
