@@ -282,7 +282,9 @@ int sl1_opts_default(sl1_opts* o);
  * lambda'_max the solve returns x = 0 on A with the atoms rejected until then.
  * The call orders itself after prior work on `stream`, polls convergence and
  * returns once every signal has converged or reached max_iter; the outputs are
- * then complete.  Concurrent calls with identical shapes on one device are
+ * then complete.  Internally it runs on the workspace's own stream and, in a hybrid
+ * solve of 128 signals or more, on a second stream of the workspace for a few late
+ * signals (see SL1_FLAG_PARK_ALL); both are joined before the call returns.  Concurrent calls with identical shapes on one device are
  * serialised internally; calls with other shapes use other workspaces and may run
  * concurrently (a cached workspace is released only when no call holds it).
  * Returns SL1_OK, SL1_MAXITER, SL1_EINVAL (bad lambda / non-finite y detected on
