@@ -296,10 +296,13 @@ def roofline_entries(prof, phases, work, tail_kernel="k_solve_tail", kron_dtype=
     if "gemm_fin" in prof:
         add("k_gemm_fin", *prof["gemm_fin"], work["fin_bytes"], "hbm")
     kwg_ms = phases.get("kron_wg_ms", 0.0)
-    if kwg_ms > 0:              # the Kronecker approximations' whole-solve phase (one launch)
-        add("k_solve_wg", kwg_ms, 1, work["kwg_flops"], "mfma", MFMA_PEAK_TFLOPS[kron_dtype])
-    if phases.get("wg_launches", 0) > (1 if kwg_ms > 0 else 0):
-        add(tail_kernel, phases["wg_ms"] - kwg_ms, phases["wg_launches"] - (1 if kwg_ms > 0 else 0),
+    # the Kronecker approximations' whole-solve phase: its launch, and the one beside the
+    # grid kernels when late signals went on there (durations summed)
+    kwg_n = phases.get("kron_wg_launches", 1) if kwg_ms > 0 else 0
+    if kwg_ms > 0:
+        add("k_solve_wg", kwg_ms, kwg_n, work["kwg_flops"], "mfma", MFMA_PEAK_TFLOPS[kron_dtype])
+    if phases.get("wg_launches", 0) > kwg_n:
+        add(tail_kernel, phases["wg_ms"] - kwg_ms, phases["wg_launches"] - kwg_n,
             work["fwd_bytes"][1] + work["adj_bytes"][1] + work["upd_bytes"][1] + work["gram_bytes"], "hbm")
     out.sort(key=lambda e: -e["total_ms"])
     return out

@@ -419,15 +419,17 @@ int sl1_last_solve_profile(int64_t batch, int64_t N, int64_t K, double* ms, long
 /*
  * sl1_last_solve_phases -- engine that ran the most recent sl1_solve with these
  * shapes (*engine = SL1_ENGINE_GRID, _WG or _HYBRID) and, when it was run with
- * SL1_FLAG_PROFILE, for its whole-solve part: phase_ms[0..3] (host, 10 doubles,
+ * SL1_FLAG_PROFILE, for its whole-solve part: phase_ms[0..3] (host, 11 doubles,
  * may be NULL) workgroup milliseconds summed over signals of forward/residual,
  * dense correlations, Kronecker correlations (hybrid tail: Gram-mode
  * correlations and scalars) and test/update/compaction,
  * phase_ms[4] the elapsed milliseconds of the whole-solve launches and
  * *wg_launches (may be NULL) their number; for a hybrid solve whose Kronecker
  * approximations ran in the whole-solve kernel, phase_ms[5] the elapsed
- * milliseconds of those launches (part of phase_ms[4]) and phase_ms[6..9] their
- * four phase sums (not part of phase_ms[0..3]); *gram_cap (may be NULL) the Gram
+ * milliseconds of those launches (part of phase_ms[4]), phase_ms[6..9] their
+ * four phase sums (not part of phase_ms[0..3]) and phase_ms[10] their number (a
+ * launch beside the grid kernels for late signals included; its time overlaps
+ * theirs); *gram_cap (may be NULL) the Gram
  * capacity (atoms) of the hybrid tail, 0 when no tail ran or it had no Gram mode:
  * a signal's tail iterations with |A_t| <= *gram_cap ran in the Gram form;
  * *gemm_min (may be NULL) the |A_t| from which a grid iteration of a signal on the

@@ -321,11 +321,12 @@ def last_solve_phases(batch, N, K):
     profile=True the whole-solve part fills the phase times (workgroup ms summed
     over signals), "wg_ms" (elapsed ms of its launches) and "wg_launches"; a
     hybrid solve's whole-solve phase on the Kronecker approximations fills
-    "kron_wg_ms" (part of "wg_ms") and "kron_wg_phases" (its own four sums);
+    "kron_wg_ms" (part of "wg_ms"), "kron_wg_phases" (its own four sums) and
+    "kron_wg_launches" (their number, a launch beside the grid kernels included);
     "gram_cap" is the Gram capacity of a hybrid tail (0: none), "gemm_min" the
     |A_t| from which signals joined the batched correlation product (0: off)."""
     eng = L.c_i32()
-    ph = (L.c_d * 10)()
+    ph = (L.c_d * 11)()
     n = ctypes.c_longlong()
     gcap = L.c_i32()
     gmin = L.c_i32()
@@ -337,6 +338,7 @@ def last_solve_phases(batch, N, K):
     out = dict(zip(keys, list(ph)[:5]))
     out["kron_wg_ms"] = ph[5]
     out["kron_wg_phases"] = dict(zip(("fwd", "adj_dense", "adj_kron", "upd"), list(ph)[6:10]))
+    out["kron_wg_launches"] = int(ph[10])
     out["wg_launches"] = n.value
     out["gram_cap"] = gcap.value
     out["gemm_min"] = gmin.value

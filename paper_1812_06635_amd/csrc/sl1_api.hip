@@ -174,6 +174,7 @@ struct Workspace {
     long long wg_n = 0;
     double park_phase_ms[kWgPhases] = {0, 0, 0, 0};   // the part of those of the Kronecker phase
     double park_ms = 0.0;
+    long long park_n = 0;                   // and their number (with a launch beside the grid kernels)
     int last_engine = 0;
     std::vector<hipEvent_t> prof_ev;
     std::mutex mu;
@@ -709,7 +710,10 @@ int run_wg(Workspace* w, const SolveParams& p, const sl1_opts& o, int64_t batch,
             HIP_TRY(hipEventElapsedTime(&ms, w->ev_a, w->ev_b));
             w->wg_ms += ms;
             w->wg_n += 1;
-            if (mode == kWgPark) w->park_ms += ms;
+            if (mode == kWgPark) {
+                w->park_ms += ms;
+                w->park_n += 1;
+            }
         }
         if (*w->h_active <= 0 || launched >= cap) break;
         // the park phase ends when every live signal has reached the park stage, or when
@@ -1388,7 +1392,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
         }
         for (int k = 0; k < kWgPhases; ++k) w->phase_ms[k] = w->park_phase_ms[k] = 0.0;
         w->wg_ms = w->park_ms = 0.0;
-        w->wg_n = 0;
+        w->wg_n = w->park_n = 0;
     }
     if (use_wg) {
         if (prof) HIP_TRY(hipMemsetAsync(w->d_wgprof, 0, (size_t)batch * kWgPhases * 8, w->stream));
@@ -1532,6 +1536,7 @@ static int solve_impl(Workspace* w, const sl1_dict* seq, int n_stages, const dou
                 w->wg_ms += ms;
                 w->wg_n += 1;
                 w->park_ms += ms;
+                w->park_n += 1;
             }
         }
         if (prof) {
@@ -1968,6 +1973,7 @@ int sl1_last_solve_phases(int64_t batch, int64_t N, int64_t K, int32_t* engine, 
         }
         phase_ms[kWgPhases] = w.wg_ms;
         phase_ms[kWgPhases + 1] = w.park_ms;
+        phase_ms[2 * kWgPhases + 2] = (double)w.park_n;
     }
     if (wg_launches) *wg_launches = w.wg_n;
     if (gram_cap) *gram_cap = w.last_gram_cap;
