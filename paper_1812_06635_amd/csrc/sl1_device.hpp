@@ -181,6 +181,14 @@ __device__ __forceinline__ int switch_dictionary(int i, int I, double gamma, dou
 // dense correlation items: atoms per wave (a wave then has 8 column loads in
 // flight per pass at N <= 1024 and N <= 2048)
 
+// a dictionary pointer as a global-memory pointer: its loads are global loads,
+// counted by the vector-memory counter alone, so LDS reads issued while they are
+// in flight can be waited for without waiting for them
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const void* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 // forward product: adds x_j a~_j[r0..r0+3] (4 rows per lane); a Kronecker atom
 // is generated from its factors, sum_r B_r[i1, j1] C_r[i2, j2] in storage precision
 __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j, double xj, int r0,
@@ -188,21 +196,21 @@ __device__ __forceinline__ void fwd_accumulate(const StageDesc& st, int N, int j
     if (st.kind == kDense) {
         const size_t off = (size_t)j * N + r0;
         if (st.dtype == SL1_F64) {
-            const f64v2* p = (const f64v2*)((const double*)st.A + off);
+            const auto* p = gmem<f64v2>((const double*)st.A + off);
             f64v2 a = p[0], c = p[1];
             acc[0] += xj * a[0]; acc[1] += xj * a[1]; acc[2] += xj * c[0]; acc[3] += xj * c[1];
         } else if (st.dtype == SL1_F32) {
-            f32v4 a = *(const f32v4*)((const float*)st.A + off);
+            f32v4 a = *gmem<f32v4>((const float*)st.A + off);
             acc[0] += xj * (double)a[0]; acc[1] += xj * (double)a[1];
             acc[2] += xj * (double)a[2]; acc[3] += xj * (double)a[3];
         } else if (st.dtype == SL1_BF16) {
-            u16x4 a = *(const u16x4*)((const uint16_t*)st.A + off);
+            u16x4 a = *gmem<u16x4>((const uint16_t*)st.A + off);
             const double s = st.scale ? (double)st.scale[j] : 1.0;
             const double xs = xj * s;
             acc[0] += xs * (double)bf16_to_f(a[0]); acc[1] += xs * (double)bf16_to_f(a[1]);
             acc[2] += xs * (double)bf16_to_f(a[2]); acc[3] += xs * (double)bf16_to_f(a[3]);
         } else {
-            const uint32_t q = *(const uint32_t*)((const uint8_t*)st.A + off);
+            const uint32_t q = *gmem<uint32_t>((const uint8_t*)st.A + off);
             const double s = st.scale ? (double)st.scale[j] : 1.0;
             const double xs = xj * s;
             auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
@@ -267,15 +275,15 @@ template <int DT>
 __device__ __forceinline__ Raw4<DT> raw_load(const void* A, size_t idx) {
     Raw4<DT> r;
     if constexpr (DT == SL1_F64) {
-        const f64v2* p = (const f64v2*)((const double*)A + idx);
+        const auto* p = gmem<f64v2>((const double*)A + idx);
         r.a = p[0];
         r.b = p[1];
     } else if constexpr (DT == SL1_F32) {
-        r.a = *(const f32v4*)((const float*)A + idx);
+        r.a = *gmem<f32v4>((const float*)A + idx);
     } else if constexpr (DT == SL1_BF16) {
-        r.a = *(const u16x4*)((const uint16_t*)A + idx);
+        r.a = *gmem<u16x4>((const uint16_t*)A + idx);
     } else {
-        r.a = *(const uint32_t*)((const uint8_t*)A + idx);
+        r.a = *gmem<uint32_t>((const uint8_t*)A + idx);
     }
     return r;
 }

@@ -2518,6 +2518,14 @@ hipError_t gemm_lds_attr(size_t lds) {
 }
 
 // blocks of the update kernel resident at once on the current device (0 on error)
+int adj_resident_blocks(size_t lds) {
+    int n = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adj_dense, kBlock, lds) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return n * cus;
+}
+
 int upd_resident_blocks(size_t lds) {
     int n = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_upd, kBlock, lds) != hipSuccess) return 0;

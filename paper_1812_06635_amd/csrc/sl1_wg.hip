@@ -240,12 +240,12 @@ __device__ __forceinline__ void wg_kron_forward(const SolveParams* P, int b, con
 __device__ __forceinline__ f32v4 dense4_f(int dtype, const void* A, size_t idx) {
     f32v4 r;
     if (dtype == SL1_F32) {
-        r = *(const f32v4*)((const float*)A + idx);
+        r = *gmem<f32v4>((const float*)A + idx);
     } else if (dtype == SL1_BF16) {
-        const u16x4 a = *(const u16x4*)((const uint16_t*)A + idx);
+        const u16x4 a = *gmem<u16x4>((const uint16_t*)A + idx);
         r = f32v4{bf16_to_f(a[0]), bf16_to_f(a[1]), bf16_to_f(a[2]), bf16_to_f(a[3])};
     } else {
-        const uint32_t q = *(const uint32_t*)((const uint8_t*)A + idx);
+        const uint32_t q = *gmem<uint32_t>((const uint8_t*)A + idx);
         const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, false);
         const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)q, true);
         r = f32v4{lo[0], lo[1], hi[0], hi[1]};

@@ -604,9 +604,12 @@ def test_late_kronecker_signals_run_beside_the_grid(sl1):
     h = _run(sl1, p, tol=1e-9, engine="hybrid", profile=True)
     ph_h = m.last_solve_phases(p.batch, p.N, p.K)[1]
     prof_h = m.last_solve_profile(p.batch, p.N, p.K)
-    _say(f"whole-solve launches: {ph_a['wg_launches']} waiting for all, {ph_h['wg_launches']} with one beside")
-    assert ph_h["wg_launches"] == ph_a["wg_launches"] + 1           # the launch beside the grid
-    assert ph_h["kron_wg_launches"] == ph_a["kron_wg_launches"] + 1  # counted with the approximations' phase
+    _say(f"whole-solve launches (approximations' phase / all): {ph_a['kron_wg_launches']} / {ph_a['wg_launches']} "
+         f"waiting for all, {ph_h['kron_wg_launches']} / {ph_h['wg_launches']} with one beside")
+    # the launch beside the grid is one more launch of the approximations' phase; the
+    # tail's launches (476 iterations each here) may differ, as the late signals join
+    # the grid a chunk later
+    assert ph_h["kron_wg_launches"] == ph_a["kron_wg_launches"] + 1
     assert prof_h["adj_kron"][1] == 0 and prof_h["step"][1] > 0      # step launches on A only
     assert a["status"] == 0 and h["status"] == 0
     np.testing.assert_array_equal(a["stage"], h["stage"])
