@@ -305,15 +305,17 @@ __device__ __forceinline__ void raw_get(const Raw4<DT>& r, double (&v)[4]) {
 }
 
 // NA atoms per wave; each pass issues the loads of NK 256-element steps of all
-// NA atoms before the first product (loads past N are clamped to a valid
-// address and discarded).  Per lane the products are accumulated in increasing k,
-// so NK changes only how many loads are in flight: about 8 KB of stored entries
-// per wave and pass (between 1 and 8 steps), whatever the storage type.
+// NA atoms before the first product (a step that starts past N is skipped; the
+// lanes of a step that crosses N load a valid address and discard it).  Per lane
+// the products are accumulated in increasing k, so NK changes only how many loads
+// are in flight: about 12 KB of stored entries per wave and pass (between 1 and
+// 12 steps), whatever the storage type, so that a column of up to 3072 entries
+// takes one memory round trip.
 template <int DT, int NA>
 constexpr int dense_nk() {
     constexpr int es = DT == SL1_F64 ? 8 : (DT == SL1_F32 ? 4 : (DT == SL1_BF16 ? 2 : 1));
-    constexpr int nk = 8192 / (NA * 256 * es);
-    return nk < 1 ? 1 : (nk > 8 ? 8 : nk);
+    constexpr int nk = 12288 / (NA * 256 * es);
+    return nk < 1 ? 1 : (nk > 12 ? 12 : nk);
 }
 
 template <int DT, int NA, int NK = dense_nk<DT, NA>()>
@@ -328,8 +330,10 @@ __device__ __forceinline__ void dense_dots_t(const StageDesc& st, int N, const i
         for (int s = 0; s < NK; ++s) {
             const int k = kb + 256 * s + 4 * lane;
             const int kc = k < N ? k : 0;
+            if (kb + 256 * s < N) {
 #pragma unroll
-            for (int q = 0; q < NA; ++q) r[q][s] = raw_load<DT>(st.A, (size_t)js[q] * N + kc);
+                for (int q = 0; q < NA; ++q) r[q][s] = raw_load<DT>(st.A, (size_t)js[q] * N + kc);
+            }
         }
 #pragma unroll
         for (int s = 0; s < NK; ++s) {
