@@ -224,12 +224,12 @@ __host__ __device__ inline size_t faust_lds_bytes(int dl, int sg, int batch) {
            (size_t)4 * kFaustStage;
 }
 
-// atoms per wave of the streaming correlation kernel: 4, 2 or 1 by the stored size of
-// a column (4 atoms of up to 3 KB, 2 of up to 6 KB, else 1)
+// atoms per wave of the streaming correlation kernel: 4, 3, 2 or 1 by the stored size
+// of a column (4 atoms of up to 3 KB, 3 of up to 4 KB, 2 of up to 6 KB, else 1)
 __host__ __device__ __forceinline__ int dense_apw(int N, int dtype) {
     const int es = dtype == SL1_F64 ? 8 : (dtype == SL1_F32 ? 4 : (dtype == SL1_BF16 ? 2 : 1));
     const int cb = N * es;
-    return cb <= 3072 ? 4 : (cb <= 6144 ? 2 : 1);
+    return cb <= 3072 ? 4 : (cb <= 4096 ? 3 : (cb <= 6144 ? 2 : 1));
 }
 
 

@@ -1017,6 +1017,7 @@ __device__ __forceinline__ void dense_item_any(const StageDesc& st, int N, const
                                                int lane, double (&mx)[3]) {
     const int apw = dense_apw(N, DT);
     if (apw == 4) dense_item<DT, 4>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
+    else if (apw == 3) dense_item<DT, 3>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
     else if (apw == 2) dense_item<DT, 2>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
     else dense_item<DT, 1>(st, N, act, s_pre, nseg, n_act, ident, first, zs, rz, g, lane, mx);
 }
